@@ -1,0 +1,210 @@
+/* eigCG on MI355X: C ABI of the HIP library libeigcg.so.
+ *
+ * Method: A. Stathopoulos and K. Orginos, "Computing and deflating eigenvalues
+ * while solving multiple right hand side linear systems with an application
+ * to Quantum Chromodynamics" (arXiv:0707.0131).
+ *
+ * The library solves A x = b with A = M^H M, where M is the Wilson-Dirac
+ * operator on a periodic 4D lattice with SU(3) links (Section 1 of the paper:
+ * M = m_q I - D is gamma5-Hermitian and CG runs on the normal equations):
+ *
+ *   (M psi)(x) = (4 + m_q) psi(x)
+ *     - 1/2 sum_mu [ (1 - g_mu) U_mu(x) psi(x+mu) + (1 + g_mu) U_mu(x-mu)^+ psi(x-mu) ]
+ *
+ * with Euclidean chiral gamma matrices g_k = [[0, -i s_k], [i s_k, 0]]
+ * (k = x, y, z; s_k Pauli), g_t = [[0, I], [I, 0]], gamma5 = diag(1,1,-1,-1).
+ *
+ * Three solve modes follow the paper:
+ *   EIGCG_MODE_CG      plain CG (Figure 3.1, left box);
+ *   EIGCG_MODE_EIGCG   one step of Incremental eigCG (Section 4): init-CG
+ *                      guess from the current bank U (eq. (2.1)), eigCG(nev, m)
+ *                      (Figure 3.1), then the nev Ritz vectors are
+ *                      orthonormalised against U and appended, H = U^H A U
+ *                      grows by nev rows and columns;
+ *   EIGCG_MODE_INITCG  init-CG (eq. (2.1)) with the bank, restarted once near
+ *                      machine precision (Section 5.3).
+ *
+ * Boundary layout (always FP64, owned by the caller, device pointers):
+ *   spinor fields: complex128 [nrhs][Lt][Lz][Ly][Lx][4 spin][3 colour]
+ *   gauge field:   complex128 [Lt][Lz][Ly][Lx][4 mu][3][3], U_mu(x)[a][b] row-major,
+ *                  mu = 0..3 is x, y, z, t.
+ * Internal precision (EIGCG_FP64 or EIGCG_MIXED_FP32) never changes the
+ * boundary layout.  All device work is enqueued on the stream given at create
+ * time; calls return when their results are final unless stated otherwise.
+ *
+ * Errors are negative return codes; eigcg_last_error() gives a message.
+ * EIGCG_EHIP is sticky: after it only eigcg_destroy is valid.  A context is
+ * not thread-safe; distinct contexts may be used from distinct threads.
+ */
+#ifndef EIGCG_H
+#define EIGCG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct eigcg_ctx eigcg_ctx;
+
+enum {
+  EIGCG_OK = 0,
+  EIGCG_EINVAL = -1,      /* bad argument (dims, nev/m, NaN/Inf in b, ...) */
+  EIGCG_ENOMEM = -2,      /* HBM budget exceeded or hipMalloc failed */
+  EIGCG_ENOTCONV = -3,    /* max_iter reached; x holds the last iterate */
+  EIGCG_EBREAKDOWN = -4,  /* p^H A p <= 0 or non-finite scalars */
+  EIGCG_EHIP = -5,        /* HIP runtime failure (sticky) */
+  EIGCG_EBUSY = -6        /* serving: ticket not finished yet */
+};
+
+enum { EIGCG_FP64 = 0, EIGCG_MIXED_FP32 = 1 };
+enum { EIGCG_MODE_CG = 0, EIGCG_MODE_EIGCG = 1, EIGCG_MODE_INITCG = 2 };
+enum { EIGCG_OP_M = 0, EIGCG_OP_MDAG = 1, EIGCG_OP_A = 2 };
+
+typedef struct {
+  int32_t dims[4];        /* Lx, Ly, Lz, Lt; each >= 2, periodic */
+  double mass;            /* m_q */
+  int32_t nev, m;         /* eigCG(nev, m); requires m > 2 nev >= 2 (Figure 3.1) */
+  int32_t max_bank;       /* most columns of U (<= 256) */
+  int32_t precision;      /* EIGCG_FP64 or EIGCG_MIXED_FP32 */
+  int32_t max_batch;      /* right-hand sides per batched launch, 1..12 */
+  int32_t reliable_every; /* mixed precision: FP64 reliable update period */
+  int32_t max_iter;       /* per right-hand side */
+  double restart_tol;     /* init-CG restart threshold on ||r||/||b||:
+                             0 -> 10 eps ||A|| (Section 5.3), < 0 -> never */
+  uint64_t hbm_budget;    /* bytes this context may allocate, 0 = no cap */
+  int32_t compress_links; /* 1: store links as two rows when they are SU(3) */
+  int32_t check_every;    /* iterations between host convergence polls */
+  int32_t use_graphs;     /* 1: replay CG iterations from a captured HIP graph */
+  int32_t reserved;
+} eigcg_params;
+
+typedef struct {
+  int32_t iters;          /* CG iterations (inner iterations in mixed mode) */
+  int32_t restarts;       /* eigCG window restarts */
+  int32_t outer_steps;    /* init-CG restarts / reliable updates / refinements */
+  int32_t status;         /* EIGCG_OK, EIGCG_ENOTCONV or EIGCG_EBREAKDOWN */
+  double true_rel_res;    /* ||b - A x|| / ||b|| recomputed in FP64 */
+  double seconds;         /* wall time of this right-hand side's batch */
+  int32_t bank_added;     /* vectors appended to U (EIGCG mode) */
+  int32_t nritz;          /* Ritz pairs produced by eigCG (EIGCG mode) */
+} eigcg_stats;
+
+/* Fill *p with defaults (nev 10, m 100, bank 240, FP64, batch 1, ...). */
+int eigcg_default_params(eigcg_params* p);
+
+/* Create a context for one gauge field and mass.  gauge_dev: device pointer to
+ * the boundary gauge layout (deep-copied and converted; the caller may free it
+ * afterwards).  hip_stream: hipStream_t or NULL for the default stream.
+ * Errors: EINVAL (dims, nev/m, sizes), ENOMEM, EHIP. */
+int eigcg_create(const eigcg_params* p, const void* gauge_dev, void* hip_stream,
+                 eigcg_ctx** out);
+
+/* Solve A x_i = b_i for nrhs right-hand sides (batched by max_batch).
+ * b_dev, x_dev: boundary spinor layout; x_dev holds the initial guess on entry
+ * (zero it for a cold start) and the solution on exit.  Success means the FP64
+ * true residual ||b - A x|| / ||b|| <= tol.  stats: nrhs entries or NULL.
+ * b = 0 gives x = 0 after 0 iterations.  Returns the worst per-RHS status. */
+int eigcg_solve(eigcg_ctx* ctx, int32_t nrhs, const void* b_dev, void* x_dev, double tol,
+                int32_t mode, eigcg_stats* stats);
+
+/* init-CG guess of eq. (2.1): x <- x + U H^{-1} U^H (b - A x) for nrhs columns
+ * (x_dev: in x~0, out x0).  With an empty bank x is unchanged. */
+int eigcg_deflate_init(eigcg_ctx* ctx, int32_t nrhs, const void* b_dev, void* x_dev);
+
+/* Free everything the context owns. */
+int eigcg_destroy(eigcg_ctx* ctx);
+
+/* out = op(in) for op = M, M^H or A = M^H M in FP64 (test support). */
+int eigcg_apply(eigcg_ctx* ctx, int32_t op, int32_t nrhs, const void* in_dev, void* out_dev);
+
+/* Rayleigh-Ritz on the bank (Section 5.2): *l = columns of U; ritz_vals
+ * (l doubles, ascending) = eigenvalues of H = U^H A U; ritz_res (l doubles or
+ * NULL) = ||A u - theta u|| of each Ritz vector (l extra applications of A). */
+int eigcg_bank_info(eigcg_ctx* ctx, int32_t* l, double* ritz_vals, double* ritz_res);
+
+/* Copy bank columns [first, first+count) to out_dev in the boundary spinor
+ * layout (count fields). */
+int eigcg_bank_vectors(eigcg_ctx* ctx, int32_t first, int32_t count, void* out_dev);
+
+/* Append count given fields (boundary layout) to the bank: each group of nev
+ * is orthonormalised against U and within itself (classical Gram-Schmidt
+ * twice, columns whose norm drops below 1e-10 of their input norm are
+ * skipped) and H grows by U^H A Vbar, as in the Section 4 update.  *added
+ * (may be NULL) receives the number of vectors kept.  Serves checkpoint /
+ * restore of a bank and tests with prescribed deflation spaces. */
+int eigcg_bank_load(eigcg_ctx* ctx, int32_t count, const void* vecs_dev, int32_t* added);
+
+/* Copy H = U^H A U (l x l, column-major complex128) to host memory h_host. */
+int eigcg_bank_matrix(eigcg_ctx* ctx, double* h_host);
+
+/* Ritz values (ascending, nev per column) produced by the last EIGCG-mode
+ * solve; *count = values written (<= cap). */
+int eigcg_last_ritz(eigcg_ctx* ctx, double* vals, int32_t cap, int32_t* count);
+
+/* Drop every bank vector (l = 0). */
+int eigcg_bank_reset(eigcg_ctx* ctx);
+
+/* Bytes of device memory the context holds. */
+int eigcg_memory(eigcg_ctx* ctx, uint64_t* bytes);
+
+const char* eigcg_last_error(const eigcg_ctx* ctx);
+
+/* ---- serving: continuous batching over several contexts --------------------
+ * A server admits solve requests for any registered context (gauge field) as
+ * long as the per-request working set fits the HBM budget, runs all admitted
+ * requests of one context as columns of a shared batched iteration (new
+ * requests join and finished ones leave between iteration segments), deflates
+ * each request with the context's resident bank (init-CG, eq. (2.1)) and
+ * reports completion per ticket.  Requests that arrive while others run are
+ * admitted as slots free up; the server thread owns the device work.
+ * Results do not depend on which other requests share a batch. */
+typedef struct eigcg_server eigcg_server;
+
+int eigcg_server_create(uint64_t hbm_budget, eigcg_server** out);
+/* Register a context; *field_id receives its index.  The context must stay
+ * alive until the server is destroyed and must not be used directly meanwhile. */
+int eigcg_server_add(eigcg_server* srv, eigcg_ctx* ctx, int32_t* field_id);
+/* Enqueue one solve (mode EIGCG_MODE_INITCG semantics, cold start).  b_dev and
+ * x_dev (one field each, boundary layout) must stay valid until done. */
+int eigcg_submit(eigcg_server* srv, int32_t field_id, const void* b_dev, void* x_dev, double tol,
+                 uint64_t* ticket);
+/* EIGCG_EBUSY while running; otherwise the solve status with *st filled
+ * (st->seconds = submit-to-completion latency). */
+int eigcg_poll(eigcg_server* srv, uint64_t ticket, eigcg_stats* st);
+/* Block until every submitted request has completed. */
+int eigcg_server_drain(eigcg_server* srv);
+int eigcg_server_destroy(eigcg_server* srv);
+
+/* ---- device probes (test support) -------------------------------------------
+ * eigcg_debug_mfma_probe: runs the FP64 and FP32 16x16x4 matrix-core
+ * instructions on index-encoding inputs; out_dev (device, 1024 doubles)
+ * receives, per lane and accumulator register, the (row + 1, column + 1) of
+ * the product entry it holds (FP64 first, then FP32).
+ * eigcg_debug_gemm: the library's complex tall-skinny products on contiguous
+ * device columns of n complex entries (prec 0: complex128, 1: complex64):
+ * kind 0: out (n x N) = in (n x K) s (K x N, complex128 column-major);
+ * kind 1: out (K x N, complex128 column-major) = in^H r (r: n x N), using
+ * scratch_dev (scratch_elems doubles) for chunk partials.  K <= 256,
+ * N <= 24 (kind 0) or 16 (kind 1).  Both synchronise the device. */
+int eigcg_debug_mfma_probe(double* out_dev);
+int eigcg_debug_gemm(int32_t prec, int32_t kind, uint64_t n, int32_t K, int32_t N,
+                     const void* in_dev, const void* r_dev, const double* s_dev, void* out_dev,
+                     double* scratch_dev, uint64_t scratch_elems);
+
+/* ---- host linear algebra (test support; no GPU needed) ---------------------- */
+/* Ascending eigenvalues w (n) and eigenvectors of the k lowest (z, n x k
+ * column-major complex128) of the Hermitian n x n matrix a (column-major
+ * complex128, upper triangle read). */
+int eigcg_host_eig_lowest(int32_t n, const double* a, int32_t k, double* w, double* z);
+/* Thin QR of the m x n complex matrix a: q (m x n) and r (n x n). */
+int eigcg_host_qr(int32_t m, int32_t n, const double* a, double* q, double* r);
+/* Solve H X = B (H n x n HPD, B n x nrhs; complex128 column-major). */
+int eigcg_host_chol_solve(int32_t n, const double* h, int32_t nrhs, double* b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EIGCG_H */

@@ -1,0 +1,364 @@
+"""ctypes binding of libeigcg.so: argument marshalling only.
+
+Every function mirrors an ``extern "C"`` entry point of ``include/eigcg.h``
+with the same name.  Device buffers are PyTorch tensors (complex128 on a HIP
+device, boundary layout ``[nrhs][Lt][Lz][Ly][Lx][4][3]`` for spinors and
+``[Lt][Lz][Ly][Lx][4][3][3]`` for links); the binding passes their data
+pointers and torch's current stream.  No computation happens here: if the
+library is missing the import of the binding fails loudly.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libeigcg.so")
+
+EIGCG_OK, EIGCG_EINVAL, EIGCG_ENOMEM, EIGCG_ENOTCONV = 0, -1, -2, -3
+EIGCG_EBREAKDOWN, EIGCG_EHIP, EIGCG_EBUSY = -4, -5, -6
+EIGCG_FP64, EIGCG_MIXED_FP32 = 0, 1
+EIGCG_MODE_CG, EIGCG_MODE_EIGCG, EIGCG_MODE_INITCG = 0, 1, 2
+EIGCG_OP_M, EIGCG_OP_MDAG, EIGCG_OP_A = 0, 1, 2
+
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "ENOTCONV", -4: "EBREAKDOWN",
+                -5: "EHIP", -6: "EBUSY"}
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("dims", ctypes.c_int32 * 4),
+        ("mass", ctypes.c_double),
+        ("nev", ctypes.c_int32),
+        ("m", ctypes.c_int32),
+        ("max_bank", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("max_batch", ctypes.c_int32),
+        ("reliable_every", ctypes.c_int32),
+        ("max_iter", ctypes.c_int32),
+        ("restart_tol", ctypes.c_double),
+        ("hbm_budget", ctypes.c_uint64),
+        ("compress_links", ctypes.c_int32),
+        ("check_every", ctypes.c_int32),
+        ("use_graphs", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int32),
+        ("restarts", ctypes.c_int32),
+        ("outer_steps", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+        ("true_rel_res", ctypes.c_double),
+        ("seconds", ctypes.c_double),
+        ("bank_added", ctypes.c_int32),
+        ("nritz", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_VP = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_DP = ctypes.POINTER(ctypes.c_double)
+
+# name -> (restype, argtypes), one per declaration of include/eigcg.h
+SIGNATURES = {
+    "eigcg_default_params": (_I32, [ctypes.POINTER(Params)]),
+    "eigcg_create": (_I32, [ctypes.POINTER(Params), _VP, _VP, ctypes.POINTER(_VP)]),
+    "eigcg_solve": (_I32, [_VP, _I32, _VP, _VP, ctypes.c_double, _I32, ctypes.POINTER(Stats)]),
+    "eigcg_deflate_init": (_I32, [_VP, _I32, _VP, _VP]),
+    "eigcg_destroy": (_I32, [_VP]),
+    "eigcg_apply": (_I32, [_VP, _I32, _I32, _VP, _VP]),
+    "eigcg_bank_info": (_I32, [_VP, ctypes.POINTER(_I32), _DP, _DP]),
+    "eigcg_bank_vectors": (_I32, [_VP, _I32, _I32, _VP]),
+    "eigcg_bank_load": (_I32, [_VP, _I32, _VP, ctypes.POINTER(_I32)]),
+    "eigcg_bank_matrix": (_I32, [_VP, _DP]),
+    "eigcg_last_ritz": (_I32, [_VP, _DP, _I32, ctypes.POINTER(_I32)]),
+    "eigcg_bank_reset": (_I32, [_VP]),
+    "eigcg_memory": (_I32, [_VP, ctypes.POINTER(ctypes.c_uint64)]),
+    "eigcg_last_error": (ctypes.c_char_p, [_VP]),
+    "eigcg_server_create": (_I32, [ctypes.c_uint64, ctypes.POINTER(_VP)]),
+    "eigcg_server_add": (_I32, [_VP, _VP, ctypes.POINTER(_I32)]),
+    "eigcg_submit": (_I32, [_VP, _I32, _VP, _VP, ctypes.c_double, ctypes.POINTER(ctypes.c_uint64)]),
+    "eigcg_poll": (_I32, [_VP, ctypes.c_uint64, ctypes.POINTER(Stats)]),
+    "eigcg_server_drain": (_I32, [_VP]),
+    "eigcg_server_destroy": (_I32, [_VP]),
+    "eigcg_debug_mfma_probe": (_I32, [_VP]),
+    "eigcg_debug_gemm": (_I32, [_I32, _I32, ctypes.c_uint64, _I32, _I32, _VP, _VP, _VP, _VP, _VP,
+                                ctypes.c_uint64]),
+    "eigcg_host_eig_lowest": (_I32, [_I32, _DP, _I32, _DP, _DP]),
+    "eigcg_host_qr": (_I32, [_I32, _I32, _DP, _DP, _DP]),
+    "eigcg_host_chol_solve": (_I32, [_I32, _DP, _I32, _DP]),
+}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_0707_0131_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+LIB = _load()
+
+
+class EigcgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(stream)
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dptr(a):
+    return a.ctypes.data_as(_DP)
+
+
+def _check_field(t, what):
+    import torch
+    if not (t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()):
+        raise ValueError(f"{what} must be a contiguous complex128 device tensor")
+
+
+def eigcg_default_params(**overrides) -> Params:
+    p = Params()
+    LIB.eigcg_default_params(ctypes.byref(p))
+    for k, v in overrides.items():
+        if k == "dims":
+            for i in range(4):
+                p.dims[i] = int(v[i])
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def eigcg_create(params: Params, gauge, stream=None):
+    _check_field(gauge, "gauge")
+    ctx = ctypes.c_void_p()
+    rc = LIB.eigcg_create(ctypes.byref(params), _ptr(gauge), _stream(stream), ctypes.byref(ctx))
+    if rc != EIGCG_OK:
+        raise EigcgError(rc, "eigcg_create failed")
+    return ctx
+
+
+def eigcg_last_error(ctx) -> str:
+    msg = LIB.eigcg_last_error(ctx)
+    return msg.decode() if msg else ""
+
+
+def eigcg_destroy(ctx):
+    return LIB.eigcg_destroy(ctx)
+
+
+def eigcg_solve(ctx, b, x, tol, mode=EIGCG_MODE_CG):
+    """Returns (status, [stats dict per right-hand side])."""
+    _check_field(b, "b")
+    _check_field(x, "x")
+    nrhs = b.shape[0]
+    st = (Stats * max(1, nrhs))()
+    rc = LIB.eigcg_solve(ctx, nrhs, _ptr(b), _ptr(x), float(tol), int(mode), st)
+    if rc in (EIGCG_EINVAL, EIGCG_ENOMEM, EIGCG_EHIP):
+        raise EigcgError(rc, eigcg_last_error(ctx))
+    return rc, [st[i].as_dict() for i in range(nrhs)]
+
+
+def eigcg_deflate_init(ctx, b, x):
+    _check_field(b, "b")
+    _check_field(x, "x")
+    rc = LIB.eigcg_deflate_init(ctx, b.shape[0], _ptr(b), _ptr(x))
+    if rc != EIGCG_OK:
+        raise EigcgError(rc, eigcg_last_error(ctx))
+
+
+def eigcg_apply(ctx, op, inp, out):
+    _check_field(inp, "in")
+    _check_field(out, "out")
+    rc = LIB.eigcg_apply(ctx, int(op), inp.shape[0], _ptr(inp), _ptr(out))
+    if rc != EIGCG_OK:
+        raise EigcgError(rc, eigcg_last_error(ctx))
+
+
+def eigcg_bank_info(ctx, residuals=False, cap=256):
+    l = _I32()
+    vals = np.zeros(cap)
+    res = np.zeros(cap) if residuals else None
+    rc = LIB.eigcg_bank_info(ctx, ctypes.byref(l), _dptr(vals),
+                             _dptr(res) if residuals else None)
+    if rc != EIGCG_OK:
+        raise EigcgError(rc, eigcg_last_error(ctx))
+    n = l.value
+    return vals[:n].copy(), (res[:n].copy() if residuals else None)
+
+
+def eigcg_bank_vectors(ctx, first, count, out):
+    _check_field(out, "out")
+    rc = LIB.eigcg_bank_vectors(ctx, int(first), int(count), _ptr(out))
+    if rc != EIGCG_OK:
+        raise EigcgError(rc, eigcg_last_error(ctx))
+
+
+def eigcg_bank_load(ctx, vecs):
+    _check_field(vecs, "vectors")
+    added = _I32()
+    rc = LIB.eigcg_bank_load(ctx, vecs.shape[0], _ptr(vecs), ctypes.byref(added))
+    if rc != EIGCG_OK:
+        raise EigcgError(rc, eigcg_last_error(ctx))
+    return added.value
+
+
+def eigcg_bank_matrix(ctx, l):
+    h = np.zeros(2 * l * l)
+    rc = LIB.eigcg_bank_matrix(ctx, _dptr(h))
+    if rc != EIGCG_OK:
+        raise EigcgError(rc, eigcg_last_error(ctx))
+    return h.view(np.complex128).reshape(l, l).T.copy()  # column-major -> [row, col]
+
+
+def eigcg_last_ritz(ctx, cap=4096):
+    vals = np.zeros(cap)
+    n = _I32()
+    LIB.eigcg_last_ritz(ctx, _dptr(vals), cap, ctypes.byref(n))
+    return vals[: n.value].copy()
+
+
+def eigcg_bank_reset(ctx):
+    return LIB.eigcg_bank_reset(ctx)
+
+
+def eigcg_memory(ctx):
+    b = ctypes.c_uint64()
+    LIB.eigcg_memory(ctx, ctypes.byref(b))
+    return b.value
+
+
+# ---- serving ----------------------------------------------------------------
+
+def eigcg_server_create(hbm_budget=0):
+    srv = ctypes.c_void_p()
+    rc = LIB.eigcg_server_create(ctypes.c_uint64(hbm_budget), ctypes.byref(srv))
+    if rc != EIGCG_OK:
+        raise EigcgError(rc, "eigcg_server_create failed")
+    return srv
+
+
+def eigcg_server_add(srv, ctx):
+    fid = _I32()
+    rc = LIB.eigcg_server_add(srv, ctx, ctypes.byref(fid))
+    if rc != EIGCG_OK:
+        raise EigcgError(rc, "eigcg_server_add failed")
+    return fid.value
+
+
+def eigcg_submit(srv, field_id, b, x, tol):
+    _check_field(b, "b")
+    _check_field(x, "x")
+    t = ctypes.c_uint64()
+    rc = LIB.eigcg_submit(srv, int(field_id), _ptr(b), _ptr(x), float(tol), ctypes.byref(t))
+    if rc != EIGCG_OK:
+        raise EigcgError(rc, "eigcg_submit failed")
+    return t.value
+
+
+def eigcg_poll(srv, ticket):
+    st = Stats()
+    rc = LIB.eigcg_poll(srv, ctypes.c_uint64(ticket), ctypes.byref(st))
+    return rc, st.as_dict()
+
+
+def eigcg_server_drain(srv):
+    return LIB.eigcg_server_drain(srv)
+
+
+def eigcg_server_destroy(srv):
+    return LIB.eigcg_server_destroy(srv)
+
+
+# ---- device probes (test support) ------------------------------------------------
+
+def eigcg_debug_mfma_probe():
+    import torch
+    out = torch.zeros(1024, dtype=torch.float64, device="cuda:0")
+    rc = LIB.eigcg_debug_mfma_probe(_ptr(out))
+    if rc != EIGCG_OK:
+        raise EigcgError(rc, "probe failed")
+    return out.cpu().numpy()
+
+
+def eigcg_debug_gemm(kind, inp, s=None, r=None):
+    """kind 0: inp (K, n) columns times s (K, N) -> (N, n); kind 1: inp^H r ->
+    (K, N).  Tensors are complex128 or complex64 device tensors."""
+    import torch
+    K, n = inp.shape
+    prec = 0 if inp.dtype == torch.complex128 else 1
+    if kind == 0:
+        N = s.shape[1]
+        sd = s.to(torch.complex128).t().contiguous()  # column-major (K x N)
+        out = torch.zeros((N, n), dtype=inp.dtype, device=inp.device)
+        rc = LIB.eigcg_debug_gemm(prec, 0, n, K, N, _ptr(inp), None, _ptr(sd), _ptr(out), None, 0)
+    else:
+        N = r.shape[0]
+        out = torch.zeros((N, K), dtype=torch.complex128, device=inp.device)
+        scratch = torch.zeros(1 << 22, dtype=torch.float64, device=inp.device)
+        rc = LIB.eigcg_debug_gemm(prec, 1, n, K, N, _ptr(inp), _ptr(r), None, _ptr(out),
+                                  _ptr(scratch), scratch.numel())
+    if rc != EIGCG_OK:
+        raise EigcgError(rc, "debug gemm failed")
+    return out.cpu().numpy() if kind == 0 else out.cpu().numpy().T
+
+
+# ---- host linear algebra (no GPU) --------------------------------------------
+
+def eigcg_host_eig_lowest(a: np.ndarray, k: int):
+    n = a.shape[0]
+    af = np.asfortranarray(a.astype(np.complex128))
+    w = np.zeros(n)
+    z = np.zeros((n, max(k, 1)), dtype=np.complex128, order="F")
+    rc = LIB.eigcg_host_eig_lowest(n, af.ctypes.data_as(_DP), k, _dptr(w),
+                                   z.ctypes.data_as(_DP))
+    if rc != EIGCG_OK:
+        raise EigcgError(rc, "host eigensolver failed")
+    return w, z[:, :k]
+
+
+def eigcg_host_qr(a: np.ndarray):
+    m, n = a.shape
+    af = np.asfortranarray(a.astype(np.complex128))
+    q = np.zeros((m, n), dtype=np.complex128, order="F")
+    r = np.zeros((n, n), dtype=np.complex128, order="F")
+    rc = LIB.eigcg_host_qr(m, n, af.ctypes.data_as(_DP), q.ctypes.data_as(_DP),
+                           r.ctypes.data_as(_DP))
+    if rc != EIGCG_OK:
+        raise EigcgError(rc, "host QR failed")
+    return q, r
+
+
+def eigcg_host_chol_solve(h: np.ndarray, b: np.ndarray):
+    n = h.shape[0]
+    hf = np.asfortranarray(h.astype(np.complex128))
+    bf = np.asfortranarray(b.astype(np.complex128).reshape(n, -1))
+    rc = LIB.eigcg_host_chol_solve(n, hf.ctypes.data_as(_DP), bf.shape[1],
+                                   bf.ctypes.data_as(_DP))
+    if rc != EIGCG_OK:
+        raise EigcgError(rc, "host Cholesky failed")
+    return bf.reshape(b.shape)

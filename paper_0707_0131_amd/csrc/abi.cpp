@@ -1,0 +1,281 @@
+// extern "C" boundary of libeigcg.so: argument validation, error codes and
+// exception translation around the engine (engine.cpp) and the host linear
+// algebra (hostla.cpp).
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "engine.h"
+#include "hostla.h"
+
+using eigcg::ApiError;
+using eigcg::Ctx;
+using eigcg::HipError;
+
+struct eigcg_ctx {
+  Ctx c;
+};
+
+namespace {
+
+int fail(eigcg_ctx* ctx, int code, const std::string& msg) {
+  if (ctx) {
+    ctx->c.err = msg;
+    if (code == EIGCG_EHIP) ctx->c.sticky = 1;
+  }
+  return code;
+}
+
+template <typename F> int guarded(eigcg_ctx* ctx, F&& f) {
+  if (ctx && ctx->c.sticky) return fail(ctx, EIGCG_EHIP, "context unusable after a HIP error");
+  try {
+    return f();
+  } catch (const HipError& e) {
+    (void)hipGetLastError();
+    return fail(ctx, EIGCG_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+  } catch (const ApiError& e) {
+    return fail(ctx, e.code, e.msg);
+  } catch (const std::bad_alloc&) {
+    return fail(ctx, EIGCG_ENOMEM, "host allocation failed");
+  }
+}
+
+int validate(const eigcg_params* p, std::string& why) {
+  if (!p) { why = "null params"; return EIGCG_EINVAL; }
+  long long V = 1;
+  for (int i = 0; i < 4; ++i) {
+    if (p->dims[i] < 2 || p->dims[i] > 4096) { why = "lattice extent out of range"; return EIGCG_EINVAL; }
+    V *= p->dims[i];
+  }
+  if (V * 12 * 16 > (1ll << 40) || V >= (1ll << 30)) { why = "lattice too large"; return EIGCG_EINVAL; }
+  if (!std::isfinite(p->mass)) { why = "mass not finite"; return EIGCG_EINVAL; }
+  if (!(p->m > 2 * p->nev && p->nev >= 1)) { why = "eigCG needs m > 2 nev >= 2"; return EIGCG_EINVAL; }
+  if ((long long)p->m * 2 * p->nev > 4096 || p->nev > 32 || p->m > 256) {
+    why = "window too large (m * 2 nev <= 4096, nev <= 32, m <= 256)";
+    return EIGCG_EINVAL;
+  }
+  if (p->max_bank < 0 || p->max_bank > 256) { why = "max_bank must be in [0, 256]"; return EIGCG_EINVAL; }
+  if (p->precision != EIGCG_FP64 && p->precision != EIGCG_MIXED_FP32) { why = "bad precision"; return EIGCG_EINVAL; }
+  if (p->max_batch < 1 || p->max_batch > 12) { why = "max_batch must be in [1, 12]"; return EIGCG_EINVAL; }
+  if (p->max_iter < 1 || p->max_iter > 10000000) { why = "bad max_iter"; return EIGCG_EINVAL; }
+  if (p->check_every < 1) { why = "check_every must be >= 1"; return EIGCG_EINVAL; }
+  if (p->precision == EIGCG_MIXED_FP32 && p->reliable_every < 1) { why = "reliable_every must be >= 1"; return EIGCG_EINVAL; }
+  return EIGCG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int eigcg_default_params(eigcg_params* p) {
+  if (!p) return EIGCG_EINVAL;
+  std::memset(p, 0, sizeof(*p));
+  p->dims[0] = p->dims[1] = p->dims[2] = p->dims[3] = 4;
+  p->mass = 0.0;
+  p->nev = 10;
+  p->m = 100;
+  p->max_bank = 240;
+  p->precision = EIGCG_FP64;
+  p->max_batch = 1;
+  p->reliable_every = 50;
+  p->max_iter = 20000;
+  p->restart_tol = 0.0;
+  p->hbm_budget = 0;
+  p->compress_links = 1;
+  p->check_every = 16;
+  p->use_graphs = 0;
+  return EIGCG_OK;
+}
+
+int eigcg_create(const eigcg_params* p, const void* gauge_dev, void* hip_stream, eigcg_ctx** out) {
+  if (!out) return EIGCG_EINVAL;
+  *out = nullptr;
+  std::string why;
+  int v = validate(p, why);
+  if (v != EIGCG_OK) return v;
+  if (!gauge_dev) return EIGCG_EINVAL;
+  eigcg_ctx* ctx = new (std::nothrow) eigcg_ctx();
+  if (!ctx) return EIGCG_ENOMEM;
+  int rc = guarded(ctx, [&] {
+    eigcg::ctx_init(ctx->c, *p, gauge_dev, (hipStream_t)hip_stream);
+    return EIGCG_OK;
+  });
+  if (rc != EIGCG_OK) {
+    eigcg::ctx_release(ctx->c);
+    delete ctx;
+    return rc;
+  }
+  *out = ctx;
+  return EIGCG_OK;
+}
+
+int eigcg_destroy(eigcg_ctx* ctx) {
+  if (!ctx) return EIGCG_EINVAL;
+  eigcg::ctx_release(ctx->c);
+  delete ctx;
+  return EIGCG_OK;
+}
+
+int eigcg_solve(eigcg_ctx* ctx, int32_t nrhs, const void* b_dev, void* x_dev, double tol,
+                int32_t mode, eigcg_stats* stats) {
+  if (!ctx) return EIGCG_EINVAL;
+  if (nrhs < 0 || (nrhs > 0 && (!b_dev || !x_dev)))
+    return fail(ctx, EIGCG_EINVAL, "bad right-hand side arguments");
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(ctx, EIGCG_EINVAL, "tol must be > 0");
+  if (mode < EIGCG_MODE_CG || mode > EIGCG_MODE_INITCG) return fail(ctx, EIGCG_EINVAL, "bad mode");
+  if (nrhs == 0) return EIGCG_OK;
+  return guarded(ctx, [&] { return eigcg::solve(ctx->c, nrhs, b_dev, x_dev, tol, mode, stats); });
+}
+
+int eigcg_deflate_init(eigcg_ctx* ctx, int32_t nrhs, const void* b_dev, void* x_dev) {
+  if (!ctx) return EIGCG_EINVAL;
+  if (nrhs < 0 || (nrhs > 0 && (!b_dev || !x_dev)))
+    return fail(ctx, EIGCG_EINVAL, "bad arguments");
+  if (nrhs == 0) return EIGCG_OK;
+  return guarded(ctx, [&] {
+    eigcg::deflate_init(ctx->c, nrhs, b_dev, x_dev);
+    return EIGCG_OK;
+  });
+}
+
+int eigcg_apply(eigcg_ctx* ctx, int32_t op, int32_t nrhs, const void* in_dev, void* out_dev) {
+  if (!ctx) return EIGCG_EINVAL;
+  if (op < EIGCG_OP_M || op > EIGCG_OP_A) return fail(ctx, EIGCG_EINVAL, "bad op");
+  if (nrhs < 0 || (nrhs > 0 && (!in_dev || !out_dev))) return fail(ctx, EIGCG_EINVAL, "bad arguments");
+  if (nrhs == 0) return EIGCG_OK;
+  return guarded(ctx, [&] {
+    eigcg::apply_op(ctx->c, op, nrhs, in_dev, out_dev);
+    return EIGCG_OK;
+  });
+}
+
+int eigcg_bank_info(eigcg_ctx* ctx, int32_t* l, double* ritz_vals, double* ritz_res) {
+  if (!ctx || !l) return EIGCG_EINVAL;
+  return guarded(ctx, [&] {
+    int ll = 0;
+    eigcg::bank_info(ctx->c, &ll, ritz_vals, ritz_res);
+    *l = ll;
+    return EIGCG_OK;
+  });
+}
+
+int eigcg_bank_vectors(eigcg_ctx* ctx, int32_t first, int32_t count, void* out_dev) {
+  if (!ctx) return EIGCG_EINVAL;
+  if (first < 0 || count < 0 || first + count > ctx->c.l || (count > 0 && !out_dev))
+    return fail(ctx, EIGCG_EINVAL, "bank range out of bounds");
+  return guarded(ctx, [&] {
+    eigcg::bank_vectors(ctx->c, first, count, out_dev);
+    return EIGCG_OK;
+  });
+}
+
+int eigcg_bank_load(eigcg_ctx* ctx, int32_t count, const void* vecs_dev, int32_t* added) {
+  if (!ctx || count < 0 || (count > 0 && !vecs_dev)) return EIGCG_EINVAL;
+  return guarded(ctx, [&] {
+    int a = eigcg::bank_load(ctx->c, count, vecs_dev);
+    if (added) *added = a;
+    return EIGCG_OK;
+  });
+}
+
+int eigcg_bank_matrix(eigcg_ctx* ctx, double* h_host) {
+  if (!ctx || !h_host) return EIGCG_EINVAL;
+  const int l = ctx->c.l, ld = ctx->c.P.max_bank;
+  for (int j = 0; j < l; ++j)
+    for (int i = 0; i < l; ++i) {
+      const auto v = ctx->c.H[(size_t)j * ld + i];
+      h_host[2 * ((size_t)j * l + i)] = v.real();
+      h_host[2 * ((size_t)j * l + i) + 1] = v.imag();
+    }
+  return EIGCG_OK;
+}
+
+int eigcg_last_ritz(eigcg_ctx* ctx, double* vals, int32_t cap, int32_t* count) {
+  if (!ctx || !count || cap < 0 || (cap > 0 && !vals)) return EIGCG_EINVAL;
+  const int n = std::min<int>(cap, (int)ctx->c.last_ritz.size());
+  for (int i = 0; i < n; ++i) vals[i] = ctx->c.last_ritz[i];
+  *count = n;
+  return EIGCG_OK;
+}
+
+int eigcg_bank_reset(eigcg_ctx* ctx) {
+  if (!ctx) return EIGCG_EINVAL;
+  ctx->c.l = 0;
+  ctx->c.chol_ok = false;
+  return EIGCG_OK;
+}
+
+int eigcg_memory(eigcg_ctx* ctx, uint64_t* bytes) {
+  if (!ctx || !bytes) return EIGCG_EINVAL;
+  *bytes = ctx->c.bytes;
+  return EIGCG_OK;
+}
+
+const char* eigcg_last_error(const eigcg_ctx* ctx) {
+  if (!ctx) return "null context";
+  return ctx->c.err.c_str();
+}
+
+// ---- device kernel probes (test support) ---------------------------------------
+
+int eigcg_debug_mfma_probe(double* out_dev) {
+  if (!out_dev) return EIGCG_EINVAL;
+  if (eigcg::launch_mfma_probe(out_dev, nullptr) != hipSuccess) return EIGCG_EHIP;
+  return hipDeviceSynchronize() == hipSuccess ? EIGCG_OK : EIGCG_EHIP;
+}
+
+int eigcg_debug_gemm(int32_t prec, int32_t kind, uint64_t n, int32_t K, int32_t N,
+                     const void* in_dev, const void* r_dev, const double* s_dev, void* out_dev,
+                     double* scratch_dev, uint64_t scratch_elems) {
+  if (K <= 0 || N <= 0 || K > 256 || N > 24 || !in_dev || !out_dev || n == 0) return EIGCG_EINVAL;
+  const size_t eb = prec == 0 ? 16 : 8;
+  std::vector<const void*> in(K);
+  for (int i = 0; i < K; ++i) in[i] = (const char*)in_dev + (size_t)i * n * eb;
+  hipError_t e;
+  if (kind == 0) {  // out (n x N) = in (n x K) * S (K x N)
+    if (!s_dev) return EIGCG_EINVAL;
+    std::vector<void*> out(N);
+    for (int j = 0; j < N; ++j) out[j] = (char*)out_dev + (size_t)j * n * eb;
+    e = eigcg::launch_gemm_tall(prec == 0 ? eigcg::kF64 : eigcg::kF32, n, K, N, in.data(),
+                                out.data(), (const double2*)s_dev, 0, 0, nullptr);
+  } else {  // out (K x N complex FP64) = in^H r
+    if (!r_dev || N > 16 || !scratch_dev) return EIGCG_EINVAL;
+    std::vector<const void*> rc(N);
+    for (int j = 0; j < N; ++j) rc[j] = (const char*)r_dev + (size_t)j * n * eb;
+    e = eigcg::launch_gemm_reduce(prec == 0 ? eigcg::kF64 : eigcg::kF32, n, K, N, in.data(),
+                                  rc.data(), (double2*)scratch_dev, scratch_elems / 2,
+                                  (double2*)out_dev, nullptr);
+  }
+  if (e != hipSuccess) return EIGCG_EHIP;
+  return hipDeviceSynchronize() == hipSuccess ? EIGCG_OK : EIGCG_EHIP;
+}
+
+// ---- host linear algebra exports (test support) ------------------------------
+
+int eigcg_host_eig_lowest(int32_t n, const double* a, int32_t k, double* w, double* z) {
+  if (n <= 0 || k < 0 || k > n || !a || !w || (k > 0 && !z)) return EIGCG_EINVAL;
+  const auto* A = reinterpret_cast<const eigcg::hostla::cplx*>(a);
+  auto* Z = reinterpret_cast<eigcg::hostla::cplx*>(z);
+  return eigcg::hostla::herm_eig_lowest(n, A, n, k, w, Z, n) == 0 ? EIGCG_OK : EIGCG_EBREAKDOWN;
+}
+
+int eigcg_host_qr(int32_t m, int32_t n, const double* a, double* q, double* r) {
+  if (m <= 0 || n <= 0 || n > m || !a || !q) return EIGCG_EINVAL;
+  eigcg::hostla::qr_thin(m, n, reinterpret_cast<const eigcg::hostla::cplx*>(a), m,
+                         reinterpret_cast<eigcg::hostla::cplx*>(q), m,
+                         reinterpret_cast<eigcg::hostla::cplx*>(r), n);
+  return EIGCG_OK;
+}
+
+int eigcg_host_chol_solve(int32_t n, const double* h, int32_t nrhs, double* b) {
+  if (n <= 0 || nrhs < 0 || !h || (nrhs > 0 && !b)) return EIGCG_EINVAL;
+  std::vector<eigcg::hostla::cplx> L(reinterpret_cast<const eigcg::hostla::cplx*>(h),
+                                     reinterpret_cast<const eigcg::hostla::cplx*>(h) + (size_t)n * n);
+  if (eigcg::hostla::cholesky(n, L.data(), n) != 0) return EIGCG_EBREAKDOWN;
+  eigcg::hostla::cholesky_solve(n, L.data(), n, nrhs, reinterpret_cast<eigcg::hostla::cplx*>(b), n);
+  return EIGCG_OK;
+}
+
+}  // extern "C"

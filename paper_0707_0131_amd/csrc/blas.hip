@@ -1,0 +1,466 @@
+// Streaming BLAS1 kernels of the CG/eigCG iteration, layout conversions and
+// small helpers (gfx950).  All are HBM-bound; every access is a contiguous
+// 64-lane load or store of one SoA plane, and every reduction is
+// deterministic (fixed-order sums, see common.h).
+#include <float.h>
+
+#include "kernels.h"
+
+namespace eigcg {
+
+namespace {
+
+inline int grid_for(size_t n) {
+  size_t g = (n + kBlock - 1) / kBlock;
+  if (g > (size_t)kMaxGrid) g = kMaxGrid;
+  if (g == 0) g = 1;
+  return (int)g;
+}
+
+// CG step 3 (Figure 3.1, steps 13, 3-9 and 11.13 of the next iteration):
+// x += alpha p; p = r + beta p; window slot (iter+1) % ring = r / sqrt(rho).
+template <typename VS>
+__global__ __launch_bounds__(kBlock) void k_cg_update(UpdateLaunch a, Geom g) {
+  using R = typename Storage<VS>::real;
+  const int col = blockIdx.y;
+  if (!((a.mask >> col) & 1u)) return;
+  const ColState S = a.st[col];
+  if (S.state == ColStopped) return;
+  const bool run = S.state == ColRun;
+  const R alpha = (R)S.alpha, beta = (R)S.beta;
+  const R inv = run ? (R)(1.0 / sqrt(S.rho)) : R(0);
+  VS* x = reinterpret_cast<VS*>(a.x) + (size_t)col * a.x_cs;
+  VS* p = reinterpret_cast<VS*>(a.p) + (size_t)col * a.p_cs;
+  const VS* r = reinterpret_cast<const VS*>(a.r) + (size_t)col * a.r_cs;
+  VS* v = nullptr;
+  if (run && a.ring) {
+    const int slot = (S.iter + 1) % a.ring_len;
+    v = reinterpret_cast<VS*>(a.ring) + (size_t)col * a.ring_col_cs + (size_t)slot * a.ring_cs;
+  }
+  const size_t vs = (size_t)g.vs;
+  for (uint32_t s = blockIdx.x * kBlock + threadIdx.x; s < (uint32_t)g.V; s += gridDim.x * kBlock) {
+#pragma unroll
+    for (int e = 0; e < 12; ++e) {
+      const size_t i = (size_t)e * vs + s;
+      cpx<R> pv = Storage<VS>::ld(p, i);
+      cpx<R> xv = Storage<VS>::ld(x, i);
+      xv.re += alpha * pv.re;
+      xv.im += alpha * pv.im;
+      Storage<VS>::st(x, i, xv);
+      if (run) {
+        cpx<R> rv = Storage<VS>::ld(r, i);
+        Storage<VS>::st(p, i, {rv.re + beta * pv.re, rv.im + beta * pv.im});
+        if (v) Storage<VS>::st(v, i, {rv.re * inv, rv.im * inv});
+      }
+    }
+  }
+}
+
+// CG start: p = r; window slot 1 = r / sqrt(rho) (first eigCG column).
+template <typename VS>
+__global__ __launch_bounds__(kBlock) void k_cg_start(UpdateLaunch a, Geom g) {
+  using R = typename Storage<VS>::real;
+  const int col = blockIdx.y;
+  if (!((a.mask >> col) & 1u)) return;
+  const ColState S = a.st[col];
+  if (S.state != ColRun) return;
+  const R inv = (R)(1.0 / sqrt(S.rho));
+  VS* p = reinterpret_cast<VS*>(a.p) + (size_t)col * a.p_cs;
+  const VS* r = reinterpret_cast<const VS*>(a.r) + (size_t)col * a.r_cs;
+  VS* v = nullptr;
+  if (a.ring) {
+    const int slot = (S.iter + 1) % a.ring_len;
+    v = reinterpret_cast<VS*>(a.ring) + (size_t)col * a.ring_col_cs + (size_t)slot * a.ring_cs;
+  }
+  const size_t vs = (size_t)g.vs;
+  for (uint32_t s = blockIdx.x * kBlock + threadIdx.x; s < (uint32_t)g.V; s += gridDim.x * kBlock) {
+#pragma unroll
+    for (int e = 0; e < 12; ++e) {
+      const size_t i = (size_t)e * vs + s;
+      cpx<R> rv = Storage<VS>::ld(r, i);
+      Storage<VS>::st(p, i, rv);
+      if (v) Storage<VS>::st(v, i, {rv.re * inv, rv.im * inv});
+    }
+  }
+}
+
+template <typename VS>
+__global__ __launch_bounds__(kBlock) void k_to_soa(const double2* __restrict__ aos, VS* soa,
+                                                   Geom g, size_t soa_cs) {
+  using R = typename Storage<VS>::real;
+  const int col = blockIdx.y;
+  const double2* src = aos + (size_t)col * 12 * g.V;
+  VS* dst = soa + (size_t)col * soa_cs;
+  for (uint32_t s = blockIdx.x * kBlock + threadIdx.x; s < (uint32_t)g.V; s += gridDim.x * kBlock) {
+#pragma unroll
+    for (int e = 0; e < 12; ++e) {
+      double2 v = src[(size_t)s * 12 + e];
+      Storage<VS>::st(dst, (size_t)e * g.vs + s, {(R)v.x, (R)v.y});
+    }
+  }
+}
+
+template <typename VS>
+__global__ __launch_bounds__(kBlock) void k_from_soa(const VS* __restrict__ soa, double2* aos,
+                                                     Geom g, size_t soa_cs) {
+  const int col = blockIdx.y;
+  double2* dst = aos + (size_t)col * 12 * g.V;
+  const VS* src = soa + (size_t)col * soa_cs;
+  for (uint32_t s = blockIdx.x * kBlock + threadIdx.x; s < (uint32_t)g.V; s += gridDim.x * kBlock) {
+#pragma unroll
+    for (int e = 0; e < 12; ++e) {
+      auto v = Storage<VS>::ld(src, (size_t)e * g.vs + s);
+      dst[(size_t)s * 12 + e] = make_double2((double)v.re, (double)v.im);
+    }
+  }
+}
+
+template <typename LS>
+__global__ __launch_bounds__(kBlock) void k_gauge_to_soa(const double2* __restrict__ aos, LS* soa,
+                                                         Geom g, int comp) {
+  using R = typename Storage<LS>::real;
+  const int per = comp ? 6 : 9;
+  for (uint32_t s = blockIdx.x * kBlock + threadIdx.x; s < (uint32_t)g.V; s += gridDim.x * kBlock) {
+    for (int mu = 0; mu < 4; ++mu) {
+      for (int e = 0; e < per; ++e) {
+        double2 v = aos[((size_t)s * 4 + mu) * 9 + e];
+        Storage<LS>::st(soa, (size_t)(mu * per + e) * g.vs + s, {(R)v.x, (R)v.y});
+      }
+    }
+  }
+}
+
+// max |U U^H - I| and max |det U - 1| over all links (unitarity check that
+// decides whether links may be stored as two rows).
+__global__ __launch_bounds__(kBlock) void k_gauge_check(const double2* __restrict__ aos, Geom g,
+                                                        double* out2, double* partial,
+                                                        unsigned int* counter) {
+  __shared__ double lds[2][kBlock];
+  double m1 = 0.0, m2 = 0.0;
+  for (uint32_t s = blockIdx.x * kBlock + threadIdx.x; s < (uint32_t)g.V; s += gridDim.x * kBlock) {
+    for (int mu = 0; mu < 4; ++mu) {
+      cpx<double> U[9];
+      for (int e = 0; e < 9; ++e) {
+        double2 v = aos[((size_t)s * 4 + mu) * 9 + e];
+        U[e] = {v.x, v.y};
+      }
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+          cpx<double> t = {0.0, 0.0};
+          for (int c = 0; c < 3; ++c) {
+            // (U U^H)_ab = sum_c U_ac conj(U_bc)
+            cpx<double> p = cmulc(U[b * 3 + c], U[a * 3 + c]);
+            t = cadd(t, p);
+          }
+          if (a == b) t.re -= 1.0;
+          m1 = fmax(m1, sqrt(t.re * t.re + t.im * t.im));
+        }
+      cpx<double> det = cmul(U[0], csub(cmul(U[4], U[8]), cmul(U[5], U[7])));
+      det = csub(det, cmul(U[1], csub(cmul(U[3], U[8]), cmul(U[5], U[6]))));
+      det = cadd(det, cmul(U[2], csub(cmul(U[3], U[7]), cmul(U[4], U[6]))));
+      det.re -= 1.0;
+      m2 = fmax(m2, sqrt(det.re * det.re + det.im * det.im));
+    }
+  }
+  lds[0][threadIdx.x] = m1;
+  lds[1][threadIdx.x] = m2;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      lds[0][threadIdx.x] = fmax(lds[0][threadIdx.x], lds[0][threadIdx.x + off]);
+      lds[1][threadIdx.x] = fmax(lds[1][threadIdx.x], lds[1][threadIdx.x + off]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = lds[0][0];
+    partial[2 * blockIdx.x + 1] = lds[1][0];
+  }
+  if (!elect_last_block(counter)) return;
+  if (threadIdx.x == 0) {
+    double a = 0.0, b = 0.0;
+    for (unsigned i = 0; i < gridDim.x; ++i) {
+      a = fmax(a, load_relaxed(partial + 2 * i));
+      b = fmax(b, load_relaxed(partial + 2 * i + 1));
+    }
+    out2[0] = a;
+    out2[1] = b;
+  }
+}
+
+// ---- generic BLAS1 over n complex entries per column ------------------------
+
+template <typename VS>
+__global__ __launch_bounds__(kBlock) void k_axpy(size_t n, const double* a_dev, double are,
+                                                 double aim, const VS* x, size_t x_cs, VS* y,
+                                                 size_t y_cs) {
+  using R = typename Storage<VS>::real;
+  const int col = blockIdx.y;
+  double ar = are, ai = aim;
+  if (a_dev) { ar = a_dev[2 * col]; ai = a_dev[2 * col + 1]; }
+  const cpx<R> a = {(R)ar, (R)ai};
+  const VS* xc = x + (size_t)col * x_cs;
+  VS* yc = y + (size_t)col * y_cs;
+  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+    cpx<R> yv = Storage<VS>::ld(yc, i);
+    Storage<VS>::st(yc, i, cadd(yv, cmul(a, Storage<VS>::ld(xc, i))));
+  }
+}
+
+template <typename SS, typename DS>
+__global__ __launch_bounds__(kBlock) void k_copy(size_t n, const SS* x, size_t x_cs, DS* y,
+                                                 size_t y_cs) {
+  using R = typename Storage<DS>::real;
+  const int col = blockIdx.y;
+  const SS* xc = x + (size_t)col * x_cs;
+  DS* yc = y + (size_t)col * y_cs;
+  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+    auto v = Storage<SS>::ld(xc, i);
+    Storage<DS>::st(yc, i, {(R)v.re, (R)v.im});
+  }
+}
+
+template <typename VS>
+__global__ __launch_bounds__(kBlock) void k_norm2(size_t n, const VS* x, size_t x_cs,
+                                                  double* partial, unsigned int* counter,
+                                                  double* out, int ncols) {
+  using R = typename Storage<VS>::real;
+  __shared__ double lds4[kBlock / 64];
+  const int col = blockIdx.y;
+  const VS* xc = x + (size_t)col * x_cs;
+  double acc = 0.0;
+  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+    auto v = Storage<VS>::ld(xc, i);
+    acc += (double)v.re * (double)v.re + (double)v.im * (double)v.im;
+  }
+  double bs = block_sum(acc, lds4);
+  if (threadIdx.x == 0) partial[(size_t)col * gridDim.x + blockIdx.x] = bs;
+  if (!elect_last_block(counter)) return;
+  for (int c = 0; c < ncols; ++c) {
+    double t = reduce_partials(partial + (size_t)c * gridDim.x, gridDim.x, lds4);
+    if (threadIdx.x == 0) out[c] = t;
+  }
+}
+
+template <typename VS>
+__global__ __launch_bounds__(kBlock) void k_scale(size_t n, const double* sc, VS* y, size_t y_cs) {
+  using R = typename Storage<VS>::real;
+  const int col = blockIdx.y;
+  const R f = (R)sc[col];
+  VS* yc = y + (size_t)col * y_cs;
+  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+    auto v = Storage<VS>::ld(yc, i);
+    Storage<VS>::st(yc, i, {v.re * f, v.im * f});
+  }
+}
+
+template <typename VS>
+__global__ __launch_bounds__(kBlock) void k_xpby(size_t n, const VS* t1, const VS* t0,
+                                                 size_t t_cs, const double* beta, VS* w,
+                                                 size_t w_cs) {
+  using R = typename Storage<VS>::real;
+  const int col = blockIdx.y;
+  const R b = (R)beta[col];
+  const VS* a1 = t1 + (size_t)col * t_cs;
+  const VS* a0 = t0 + (size_t)col * t_cs;
+  VS* wc = w + (size_t)col * w_cs;
+  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+    auto u1 = Storage<VS>::ld(a1, i);
+    auto u0 = Storage<VS>::ld(a0, i);
+    Storage<VS>::st(wc, i, {u1.re - b * u0.re, u1.im - b * u0.im});
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_accum(size_t n, double2* x, size_t x_cs, float2* e,
+                                                  size_t e_cs) {
+  const int col = blockIdx.y;
+  double2* xc = x + (size_t)col * x_cs;
+  float2* ec = e + (size_t)col * e_cs;
+  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+    float2 ev = ec[i];
+    double2 xv = xc[i];
+    xv.x += (double)ev.x;
+    xv.y += (double)ev.y;
+    xc[i] = xv;
+    ec[i] = make_float2(0.f, 0.f);
+  }
+}
+
+__global__ void k_post_residual(ColState* st, int ncols, uint32_t mask) {
+  const int c = threadIdx.x;
+  if (c >= ncols || !((mask >> c) & 1u)) return;
+  ColState& S = st[c];
+  const bool waiting = S.state == ColStopPending && S.reason == ReasonRestart;
+  if (S.state != ColRun && !waiting) return;
+  if (S.rho <= S.res_stop2) {
+    S.state = ColStopped;
+    S.reason = ReasonConverged;
+  } else if (S.rho <= S.defl2) {
+    S.defl2 = 0.0;
+    S.state = ColStopped;
+    S.reason = ReasonRestart;
+  } else {
+    S.state = ColRun;
+    S.reason = ReasonNone;
+  }
+}
+
+__global__ void k_set_state(ColState* st, int ncols, uint32_t mask, int state, int reason,
+                            int clear_restart) {
+  const int c = threadIdx.x;
+  if (c >= ncols || !((mask >> c) & 1u)) return;
+  st[c].state = state;
+  st[c].reason = reason;
+  if (clear_restart) st[c].restart2 = 0.0;
+}
+
+}  // namespace
+
+hipError_t launch_post_residual(ColState* st, int ncols, uint32_t mask, hipStream_t s) {
+  hipLaunchKernelGGL(k_post_residual, dim3(1), dim3(64), 0, s, st, ncols, mask);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_state(ColState* st, int ncols, uint32_t mask, int state, int reason,
+                            int clear_restart, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_state, dim3(1), dim3(64), 0, s, st, ncols, mask, state, reason,
+                     clear_restart);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_update(const UpdateLaunch& L, hipStream_t s) {
+  dim3 grid(grid_for(L.g->V), L.ncols);
+  if (L.prec == kF64)
+    hipLaunchKernelGGL(k_cg_update<double2>, grid, dim3(kBlock), 0, s, L, *L.g);
+  else
+    hipLaunchKernelGGL(k_cg_update<float2>, grid, dim3(kBlock), 0, s, L, *L.g);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_start(const UpdateLaunch& L, hipStream_t s) {
+  dim3 grid(grid_for(L.g->V), L.ncols);
+  if (L.prec == kF64)
+    hipLaunchKernelGGL(k_cg_start<double2>, grid, dim3(kBlock), 0, s, L, *L.g);
+  else
+    hipLaunchKernelGGL(k_cg_start<float2>, grid, dim3(kBlock), 0, s, L, *L.g);
+  return hipGetLastError();
+}
+
+hipError_t launch_spinor_to_soa(const double2* aos, void* soa, int prec, const Geom* g, int ncols,
+                                size_t soa_cs, hipStream_t s) {
+  dim3 grid(grid_for(g->V), ncols);
+  if (prec == kF64)
+    hipLaunchKernelGGL(k_to_soa<double2>, grid, dim3(kBlock), 0, s, aos, (double2*)soa, *g, soa_cs);
+  else
+    hipLaunchKernelGGL(k_to_soa<float2>, grid, dim3(kBlock), 0, s, aos, (float2*)soa, *g, soa_cs);
+  return hipGetLastError();
+}
+
+hipError_t launch_spinor_from_soa(const void* soa, double2* aos, int prec, const Geom* g,
+                                  int ncols, size_t soa_cs, hipStream_t s) {
+  dim3 grid(grid_for(g->V), ncols);
+  if (prec == kF64)
+    hipLaunchKernelGGL(k_from_soa<double2>, grid, dim3(kBlock), 0, s, (const double2*)soa, aos, *g,
+                       soa_cs);
+  else
+    hipLaunchKernelGGL(k_from_soa<float2>, grid, dim3(kBlock), 0, s, (const float2*)soa, aos, *g,
+                       soa_cs);
+  return hipGetLastError();
+}
+
+hipError_t launch_gauge_to_soa(const double2* aos, void* soa, int prec, int compressed,
+                               const Geom* g, hipStream_t s) {
+  dim3 grid(grid_for(g->V));
+  if (prec == kF64)
+    hipLaunchKernelGGL(k_gauge_to_soa<double2>, grid, dim3(kBlock), 0, s, aos, (double2*)soa, *g,
+                       compressed);
+  else
+    hipLaunchKernelGGL(k_gauge_to_soa<float2>, grid, dim3(kBlock), 0, s, aos, (float2*)soa, *g,
+                       compressed);
+  return hipGetLastError();
+}
+
+hipError_t launch_gauge_check(const double2* aos, const Geom* g, double* out2, hipStream_t s) {
+  // scratch after the two outputs: partials then a counter
+  int gx = grid_for(g->V);
+  double* partial = out2 + 2;
+  unsigned int* counter = reinterpret_cast<unsigned int*>(partial + 2 * kMaxGrid);
+  hipLaunchKernelGGL(k_gauge_check, dim3(gx), dim3(kBlock), 0, s, aos, *g, out2, partial, counter);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy(int prec, int ncols, size_t n, const double* a_dev, double a_re,
+                       double a_im, const void* x, size_t x_cs, void* y, size_t y_cs,
+                       hipStream_t s) {
+  dim3 grid(grid_for(n), ncols);
+  if (prec == kF64)
+    hipLaunchKernelGGL(k_axpy<double2>, grid, dim3(kBlock), 0, s, n, a_dev, a_re, a_im,
+                       (const double2*)x, x_cs, (double2*)y, y_cs);
+  else
+    hipLaunchKernelGGL(k_axpy<float2>, grid, dim3(kBlock), 0, s, n, a_dev, a_re, a_im,
+                       (const float2*)x, x_cs, (float2*)y, y_cs);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(int src_prec, int dst_prec, int ncols, size_t n, const void* x,
+                       size_t x_cs, void* y, size_t y_cs, hipStream_t s) {
+  dim3 grid(grid_for(n), ncols);
+  if (src_prec == kF64 && dst_prec == kF64)
+    hipLaunchKernelGGL((k_copy<double2, double2>), grid, dim3(kBlock), 0, s, n, (const double2*)x,
+                       x_cs, (double2*)y, y_cs);
+  else if (src_prec == kF64)
+    hipLaunchKernelGGL((k_copy<double2, float2>), grid, dim3(kBlock), 0, s, n, (const double2*)x,
+                       x_cs, (float2*)y, y_cs);
+  else if (dst_prec == kF64)
+    hipLaunchKernelGGL((k_copy<float2, double2>), grid, dim3(kBlock), 0, s, n, (const float2*)x,
+                       x_cs, (double2*)y, y_cs);
+  else
+    hipLaunchKernelGGL((k_copy<float2, float2>), grid, dim3(kBlock), 0, s, n, (const float2*)x,
+                       x_cs, (float2*)y, y_cs);
+  return hipGetLastError();
+}
+
+hipError_t launch_norm2(int prec, int ncols, size_t n, const void* x, size_t x_cs,
+                        double* partial, unsigned int* counter, double* out, hipStream_t s) {
+  dim3 grid(grid_for(n), ncols);
+  if (prec == kF64)
+    hipLaunchKernelGGL(k_norm2<double2>, grid, dim3(kBlock), 0, s, n, (const double2*)x, x_cs,
+                       partial, counter, out, ncols);
+  else
+    hipLaunchKernelGGL(k_norm2<float2>, grid, dim3(kBlock), 0, s, n, (const float2*)x, x_cs,
+                       partial, counter, out, ncols);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale(int prec, int ncols, size_t n, const double* scale_dev, void* y,
+                        size_t y_cs, hipStream_t s) {
+  dim3 grid(grid_for(n), ncols);
+  if (prec == kF64)
+    hipLaunchKernelGGL(k_scale<double2>, grid, dim3(kBlock), 0, s, n, scale_dev, (double2*)y, y_cs);
+  else
+    hipLaunchKernelGGL(k_scale<float2>, grid, dim3(kBlock), 0, s, n, scale_dev, (float2*)y, y_cs);
+  return hipGetLastError();
+}
+
+hipError_t launch_xpby(int prec, int ncols, size_t n, const void* t1, const void* t0,
+                       size_t t_cs, const double* beta_dev, void* w, size_t w_cs,
+                       hipStream_t s) {
+  dim3 grid(grid_for(n), ncols);
+  if (prec == kF64)
+    hipLaunchKernelGGL(k_xpby<double2>, grid, dim3(kBlock), 0, s, n, (const double2*)t1,
+                       (const double2*)t0, t_cs, beta_dev, (double2*)w, w_cs);
+  else
+    hipLaunchKernelGGL(k_xpby<float2>, grid, dim3(kBlock), 0, s, n, (const float2*)t1,
+                       (const float2*)t0, t_cs, beta_dev, (float2*)w, w_cs);
+  return hipGetLastError();
+}
+
+hipError_t launch_accum_f32_into_f64(int ncols, size_t n, void* x64, size_t x_cs, void* e32,
+                                     size_t e_cs, hipStream_t s) {
+  dim3 grid(grid_for(n), ncols);
+  hipLaunchKernelGGL(k_accum, grid, dim3(kBlock), 0, s, n, (double2*)x64, x_cs, (float2*)e32,
+                     e_cs);
+  return hipGetLastError();
+}
+
+}  // namespace eigcg

@@ -1,0 +1,177 @@
+// Shared device/host definitions of the eigCG HIP library (gfx950).
+//
+// Internal data layout (all vectors and links live in HBM in this form):
+//
+//  * sites are numbered lexicographically with x fastest, then y, z, t;
+//  * a spinor field is 12 complex planes (component c = 3*spin + colour),
+//    each plane holding `vs` sites (vs = V rounded up to a multiple of 64,
+//    the pad is kept zero), so lane i of a wavefront reads site s0+i of one
+//    plane: every load of the stencil and of BLAS1 is a contiguous 64-lane
+//    access;
+//  * several right-hand sides are separate fields one after the other
+//    (column stride 12*vs complex);
+//  * links are 4 directions x 9 (full) or 6 (first two rows, third row
+//    rebuilt from unitarity) complex planes of vs sites.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace eigcg {
+
+constexpr int kBlock = 256;        // threads per workgroup of the streaming kernels
+constexpr int kMaxGrid = 2048;     // cap on workgroups of grid-stride kernels
+constexpr int kMaxCols = 16;       // most right-hand sides a kernel handles at once
+
+// Exact unsigned division by a runtime constant: q = (n * mul) >> shift for
+// every n < 2^31 (round-up method of Granlund and Montgomery).
+struct FastDiv {
+  uint64_t mul;
+  uint32_t shift;
+  uint32_t d;
+  FastDiv() : mul(1), shift(0), d(1) {}
+  explicit FastDiv(uint32_t div) : d(div) {
+    uint32_t l = 0;
+    while ((1ull << l) < div) ++l;
+    shift = 32 + l;
+    mul = ((1ull << shift) / div) + 1;
+  }
+  __host__ __device__ inline uint32_t div(uint32_t n) const {
+    return (uint32_t)(((uint64_t)n * mul) >> shift);
+  }
+};
+
+struct Geom {
+  int L[4];        // Lx, Ly, Lz, Lt
+  int V;           // sites
+  int vs;          // plane stride (sites, multiple of 64)
+  int stride[4];   // site-index step of a unit hop: 1, Lx, Lx*Ly, Lx*Ly*Lz
+  FastDiv dx, dy, dz;
+};
+
+// Per right-hand-side solver state on the device.  Scalars of the CG
+// recurrence are FP64 in every precision mode.
+struct ColState {
+  double rho;       // r^H r of the current residual
+  double rho_prev;
+  double alpha;     // alpha of the last completed iteration
+  double beta;      // beta for the next search direction
+  double pap;       // p^H A p of the current iteration
+  double stop2;     // recursive r^H r at or below this: converged
+  double restart2;  // recursive r^H r at or below this: stop for a host-driven
+                    // restart (init-CG re-deflation, mixed-precision update)
+  double res_stop2; // true-residual r^H r at or below this: converged
+  double defl2;     // true-residual r^H r at or below this: re-deflate once
+  int iter;         // completed iterations
+  int max_iter;
+  int state;        // ColRun / ColStopPending / ColStopped
+  int reason;       // ReasonNone / Converged / MaxIter / Breakdown / Restart
+  int save_t0;      // iterations j whose t_j = A p_j is kept (eigCG arrow row,
+  int save_t1;      // Figure 3.1 steps 10.1 and 11.8); slot j & 1; 0 = none
+  int tperiod;      // after saving at save_t1 both advance by this (m - 2 nev)
+  int pad_;
+};
+
+enum { ColRun = 0, ColStopPending = 1, ColStopped = 2 };
+enum { ReasonNone = 0, ReasonConverged = 1, ReasonMaxIter = 2, ReasonBreakdown = 3,
+       ReasonRestart = 4 };
+
+// --- small complex helpers -------------------------------------------------
+template <typename R> struct cpx { R re, im; };
+
+template <typename R> __device__ __forceinline__ cpx<R> cmul(cpx<R> a, cpx<R> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename R> __device__ __forceinline__ cpx<R> cmulc(cpx<R> a, cpx<R> b) {
+  // conj(a) * b
+  return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+template <typename R> __device__ __forceinline__ cpx<R> cadd(cpx<R> a, cpx<R> b) {
+  return {a.re + b.re, a.im + b.im};
+}
+template <typename R> __device__ __forceinline__ cpx<R> csub(cpx<R> a, cpx<R> b) {
+  return {a.re - b.re, a.im - b.im};
+}
+template <typename R> __device__ __forceinline__ cpx<R> ci(cpx<R> a) {  // i*a
+  return {-a.im, a.re};
+}
+template <typename R> __device__ __forceinline__ cpx<R> cmi(cpx<R> a) {  // -i*a
+  return {a.im, -a.re};
+}
+template <typename R> __device__ __forceinline__ cpx<R> cneg(cpx<R> a) { return {-a.re, -a.im}; }
+
+// --- storage types -----------------------------------------------------------
+template <typename S> struct Storage;
+template <> struct Storage<double2> {
+  using real = double;
+  __device__ static __forceinline__ cpx<double> ld(const double2* p, size_t i) {
+    double2 v = p[i];
+    return {v.x, v.y};
+  }
+  __device__ static __forceinline__ void st(double2* p, size_t i, cpx<double> v) {
+    p[i] = make_double2(v.re, v.im);
+  }
+};
+template <> struct Storage<float2> {
+  using real = float;
+  __device__ static __forceinline__ cpx<float> ld(const float2* p, size_t i) {
+    float2 v = p[i];
+    return {v.x, v.y};
+  }
+  __device__ static __forceinline__ void st(float2* p, size_t i, cpx<float> v) {
+    p[i] = make_float2(v.re, v.im);
+  }
+};
+
+// --- deterministic reductions --------------------------------------------------
+// Sum over a 256-thread workgroup in a fixed order (wavefront butterfly, then
+// the four wave partials in order).  Every thread gets the total.
+template <typename T> __device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+template <typename T> __device__ __forceinline__ T block_sum(T v, T* lds4) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) lds4[w] = v;
+  __syncthreads();
+  T s = lds4[0];
+#pragma unroll
+  for (int i = 1; i < kBlock / 64; ++i) s += lds4[i];
+  return s;
+}
+
+// "Last workgroup" election: every workgroup publishes its partials, then the
+// workgroup that increments the counter last sees all partials and finishes
+// the reduction in a fixed order.  The counter is reset by that workgroup.
+__device__ __forceinline__ bool elect_last_block(unsigned int* counter) {
+  __shared__ bool last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned int prev = atomicAdd(counter, 1u);
+    last = (prev == gridDim.x * gridDim.y * gridDim.z - 1);
+  }
+  __syncthreads();
+  if (last) {
+    __threadfence();
+    if (threadIdx.x == 0) *counter = 0u;
+  }
+  return last;
+}
+
+__device__ __forceinline__ double load_relaxed(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Fixed-order sum of n partials (n <= kMaxGrid) by one workgroup.
+__device__ __forceinline__ double reduce_partials(const double* part, int n, double* lds4) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += kBlock) s += load_relaxed(part + i);
+  return block_sum(s, lds4);
+}
+
+}  // namespace eigcg

@@ -1,0 +1,1168 @@
+// Solver engine: context set-up, batched CG / eigCG / init-CG drivers and the
+// Incremental eigCG bank (Figure 3.1, eq. (2.1) and Section 4 of the paper).
+//
+// Execution model.  The CG scalars live on the device (ColState); a CG
+// iteration is three kernels (stencil M with ||M p||^2 -> alpha; stencil M^H
+// fused with r -= alpha t and r^H r -> beta and the stop test; x/p update with
+// the eigCG window append), so the host never waits inside the iteration.  The
+// host enqueues segments of iterations, each followed by an asynchronous copy
+// of the column states (and of the alpha/beta history for eigCG) and an event,
+// and processes segment s while segment s+1 already runs.  eigCG restarts fall
+// on segment ends: the host builds the window matrix T from the history,
+// computes the restart coefficients in FP64 (steps 11.3-11.6), uploads QZ and
+// enqueues the MFMA product V <- V (QZ) (step 11.7) while the GPU keeps
+// iterating; the window is a ring of residual slots large enough for that lag.
+// The arrow row w^H V (step 11.8) uses t saved by the device on a schedule it
+// advances itself.
+#include "engine.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <unordered_map>
+
+#include "hostla.h"
+
+namespace eigcg {
+
+namespace {
+
+std::unordered_map<void*, size_t>& alloc_sizes() {
+  static thread_local std::unordered_map<void*, size_t> m;
+  return m;
+}
+
+size_t round_up(size_t a, size_t b) { return (a + b - 1) / b * b; }
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+// Partition of the small-matrix staging area (d_small / h_small, 2^17
+// complex entries): per-column restart coefficients QZ, per-column arrow rows,
+// and a generic region for synchronous products.
+constexpr size_t kSmallElems = (size_t)1 << 17;
+constexpr size_t kQzSlot = kSmallElems / 2 / kMaxCols;  // m * 2 nev <= 4096
+inline size_t qz_off(int col) { return (size_t)col * kQzSlot; }
+inline size_t arrow_off(int col) { return kSmallElems / 2 + (size_t)col * 64; }
+constexpr size_t kGenericOff = kSmallElems * 3 / 4;
+
+}  // namespace
+
+void Ctx::check(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw HipError{e, what};
+}
+
+void* Ctx::dalloc(size_t n) {
+  n = round_up(n, 256);
+  if (P.hbm_budget && bytes + n > P.hbm_budget)
+    throw ApiError{EIGCG_ENOMEM, "HBM budget of the context exceeded"};
+  void* p = nullptr;
+  if (hipMalloc(&p, n) != hipSuccess) {
+    (void)hipGetLastError();
+    throw ApiError{EIGCG_ENOMEM, "hipMalloc failed"};
+  }
+  check(hipMemsetAsync(p, 0, n, stream), "hipMemsetAsync");
+  bytes += n;
+  alloc_sizes()[p] = n;
+  return p;
+}
+
+void Ctx::dfree(void*& p) {
+  if (!p) return;
+  auto it = alloc_sizes().find(p);
+  if (it != alloc_sizes().end()) {
+    bytes -= it->second;
+    alloc_sizes().erase(it);
+  }
+  (void)hipFree(p);
+  p = nullptr;
+}
+
+static size_t elem_bytes(int prec) { return prec == kF64 ? 16 : 8; }
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+
+void ctx_init(Ctx& c, const eigcg_params& p, const void* gauge_dev, hipStream_t s) {
+  c.P = p;
+  c.stream = s;
+  c.check(hipGetDevice(&c.device), "hipGetDevice");
+  Geom& g = c.g;
+  for (int i = 0; i < 4; ++i) g.L[i] = p.dims[i];
+  g.V = p.dims[0] * p.dims[1] * p.dims[2] * p.dims[3];
+  g.vs = (int)round_up((size_t)g.V, 64);
+  g.stride[0] = 1;
+  g.stride[1] = p.dims[0];
+  g.stride[2] = p.dims[0] * p.dims[1];
+  g.stride[3] = p.dims[0] * p.dims[1] * p.dims[2];
+  g.dx = FastDiv((uint32_t)p.dims[0]);
+  g.dy = FastDiv((uint32_t)p.dims[1]);
+  g.dz = FastDiv((uint32_t)p.dims[2]);
+  c.cs = (size_t)12 * g.vs;
+
+  // scratch
+  c.hist_stride = 3 * (p.max_iter + 8);
+  c.d_st = (ColState*)c.dalloc(sizeof(ColState) * kMaxCols);
+  c.check(hipHostMalloc((void**)&c.h_st, sizeof(ColState) * kMaxCols * 2, 0), "hipHostMalloc");
+  c.d_hist = (double*)c.dalloc(sizeof(double) * (size_t)kMaxCols * c.hist_stride);
+  c.check(hipHostMalloc((void**)&c.h_hist, sizeof(double) * (size_t)kMaxCols * c.hist_stride, 0),
+          "hipHostMalloc");
+  c.d_partial = (double*)c.dalloc(sizeof(double) * (size_t)(kMaxCols + 2) * kMaxGrid * 2);
+  c.d_counter = (unsigned int*)c.dalloc(256);
+  c.gpart_elems = (size_t)1 << 21;  // 32 MiB of double2 chunk partials
+  c.d_gpart = (double2*)c.dalloc(sizeof(double2) * c.gpart_elems);
+  c.small_elems = kSmallElems;
+  c.d_small = (double2*)c.dalloc(sizeof(double2) * c.small_elems);
+  c.check(hipHostMalloc((void**)&c.h_small, sizeof(double2) * c.small_elems, 0), "hipHostMalloc");
+  c.d_norm = (double*)c.dalloc(sizeof(double) * kMaxCols * 4);
+  c.check(hipHostMalloc((void**)&c.h_norm, sizeof(double) * kMaxCols * 4, 0), "hipHostMalloc");
+
+  // gauge field: unitarity check decides two-row storage
+  double* chk = c.d_partial;  // out2 + partials + counter (see launch_gauge_check)
+  c.check(launch_gauge_check((const double2*)gauge_dev, &g, chk, s), "gauge check");
+  double h2[2];
+  c.check(hipMemcpyAsync(h2, chk, sizeof(h2), hipMemcpyDeviceToHost, s), "memcpy");
+  c.check(hipStreamSynchronize(s), "sync");
+  const bool su3 = h2[0] < 1e-12 && h2[1] < 1e-12;
+  c.comp64 = (p.compress_links && su3) ? 1 : 0;
+  c.u64 = c.dalloc((size_t)4 * (c.comp64 ? 6 : 9) * g.vs * 16);
+  c.check(launch_gauge_to_soa((const double2*)gauge_dev, c.u64, kF64, c.comp64, &g, s),
+          "gauge to soa");
+  if (p.precision == EIGCG_MIXED_FP32) {
+    c.comp32 = (p.compress_links && h2[0] < 1e-6 && h2[1] < 1e-6) ? 1 : 0;
+    c.u32 = c.dalloc((size_t)4 * (c.comp32 ? 6 : 9) * g.vs * 8);
+    c.check(launch_gauge_to_soa((const double2*)gauge_dev, c.u32, kF32, c.comp32, &g, s),
+            "gauge to soa f32");
+  }
+  c.bank_prec = p.precision == EIGCG_FP64 ? kF64 : kF32;
+  c.H.assign((size_t)p.max_bank * p.max_bank, cplx(0.0, 0.0));
+  c.L.assign((size_t)p.max_bank * p.max_bank, cplx(0.0, 0.0));
+  c.events.resize(4 + 2 * kMaxCols);
+  for (auto& e : c.events) c.check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+  c.check(hipStreamSynchronize(s), "sync");
+}
+
+static void ws_release(Ctx& c, Workspace& w) {
+  c.dfree(w.b); c.dfree(w.x); c.dfree(w.r); c.dfree(w.p); c.dfree(w.tmp);
+  c.dfree(w.ring); c.dfree(w.vr); c.dfree(w.tbuf); c.dfree(w.w); c.dfree(w.ritz);
+  w.K = 0;
+  w.eig = false;
+}
+
+void ctx_release(Ctx& c) {
+  if (c.stream) (void)hipStreamSynchronize(c.stream);
+  ws_release(c, c.ws64);
+  ws_release(c, c.ws32);
+  c.dfree(c.U);
+  c.dfree(c.bwork);
+  c.dfree(c.u64);
+  c.dfree(c.u32);
+  void* v;
+  v = c.d_st; c.dfree(v);
+  v = c.d_hist; c.dfree(v);
+  v = c.d_partial; c.dfree(v);
+  v = c.d_counter; c.dfree(v);
+  v = c.d_gpart; c.dfree(v);
+  v = c.d_small; c.dfree(v);
+  v = c.d_norm; c.dfree(v);
+  if (c.h_st) (void)hipHostFree(c.h_st);
+  if (c.h_hist) (void)hipHostFree(c.h_hist);
+  if (c.h_small) (void)hipHostFree(c.h_small);
+  if (c.h_norm) (void)hipHostFree(c.h_norm);
+  for (auto& e : c.events) (void)hipEventDestroy(e);
+  c.events.clear();
+}
+
+static int seg_len_eig(const eigcg_params& P) {
+  int d = (P.m - 2 * P.nev - 1) / 2;
+  d = std::min(d, std::max(1, P.check_every));
+  return std::max(1, d);
+}
+
+static void ws_ensure(Ctx& c, Workspace& w, int prec, bool eig) {
+  const int K = c.P.max_batch;
+  const size_t vb = c.cs * elem_bytes(prec);
+  if (w.K == 0) {
+    w.prec = prec;
+    w.K = K;
+    w.b = c.dalloc(vb * K);
+    w.x = c.dalloc(vb * K);
+    w.r = c.dalloc(vb * K);
+    w.p = c.dalloc(vb * K);
+    w.tmp = c.dalloc(vb * K);
+  }
+  if (eig && !w.eig) {
+    w.nev = c.P.nev;
+    w.ring_len = c.P.m + seg_len_eig(c.P) + 2;
+    w.ring = c.dalloc(vb * (size_t)K * w.ring_len);
+    w.vr = c.dalloc(vb * (size_t)K * 2 * c.P.nev);
+    w.tbuf = c.dalloc(vb * (size_t)K * 2);
+    w.w = c.dalloc(vb * (size_t)K);
+    w.ritz = c.dalloc(vb * (size_t)K * c.P.nev);
+    w.eig = true;
+  }
+}
+
+static void* col_ptr(void* base, int prec, size_t cs, size_t idx) {
+  return (char*)base + idx * cs * elem_bytes(prec);
+}
+
+// ---------------------------------------------------------------------------
+// operator application
+// ---------------------------------------------------------------------------
+
+static StencilLaunch stencil_base(Ctx& c, int prec) {
+  StencilLaunch L{};
+  L.prec = prec;
+  L.compressed = prec == kF64 ? c.comp64 : c.comp32;
+  L.u = prec == kF64 ? c.u64 : c.u32;
+  L.g = &c.g;
+  L.diag = 4.0 + c.P.mass;
+  L.st = c.d_st;
+  L.partial = c.d_partial;
+  L.counter = c.d_counter;
+  L.hist = c.d_hist;
+  L.hist_stride = c.hist_stride;
+  return L;
+}
+
+// out = op(in) (op = M or M^H) on ncols internal fields
+static void stencil_store(Ctx& c, int prec, int op, int ncols, const void* in, void* out) {
+  StencilLaunch L = stencil_base(c, prec);
+  L.op = op;
+  L.epi = kEpiStore;
+  L.in = in; L.in_cs = c.cs;
+  L.out = out; L.out_cs = c.cs;
+  L.ncols = ncols;
+  L.mask = (ncols >= 32) ? 0xffffffffu : ((1u << ncols) - 1);
+  c.check(launch_stencil(L, c.stream), "stencil");
+}
+
+// r = b - A x for masked columns, rho = ||r||^2 into the column states
+static void true_residual(Ctx& c, int prec, int ncols, uint32_t mask, const void* x,
+                          const void* b, void* r, void* tmp) {
+  StencilLaunch L = stencil_base(c, prec);
+  L.op = kOpM;
+  L.epi = kEpiStore;
+  L.in = x; L.in_cs = c.cs;
+  L.out = tmp; L.out_cs = c.cs;
+  L.ncols = ncols;
+  L.mask = mask;
+  c.check(launch_stencil(L, c.stream), "stencil M");
+  L.op = kOpMdag;
+  L.epi = kEpiRes;
+  L.in = tmp;
+  L.r = r; L.r_cs = c.cs;
+  L.b = b; L.b_cs = c.cs;
+  c.check(launch_stencil(L, c.stream), "stencil Mdag res");
+}
+
+void apply_op(Ctx& c, int op, int nrhs, const void* in_aos, void* out_aos) {
+  Workspace& w = c.ws64;
+  ws_ensure(c, w, kF64, false);
+  for (int c0 = 0; c0 < nrhs; c0 += w.K) {
+    const int k = std::min(w.K, nrhs - c0);
+    const double2* src = (const double2*)in_aos + (size_t)c0 * 12 * c.g.V;
+    double2* dst = (double2*)out_aos + (size_t)c0 * 12 * c.g.V;
+    c.check(launch_spinor_to_soa(src, w.x, kF64, &c.g, k, c.cs, c.stream), "to soa");
+    if (op == EIGCG_OP_A) {
+      stencil_store(c, kF64, kOpM, k, w.x, w.tmp);
+      stencil_store(c, kF64, kOpMdag, k, w.tmp, w.r);
+    } else {
+      stencil_store(c, kF64, op == EIGCG_OP_M ? kOpM : kOpMdag, k, w.x, w.r);
+    }
+    c.check(launch_spinor_from_soa(w.r, dst, kF64, &c.g, k, c.cs, c.stream), "from soa");
+  }
+  c.check(hipStreamSynchronize(c.stream), "sync");
+}
+
+// ---------------------------------------------------------------------------
+// small device products with host-side coefficient matrices
+// ---------------------------------------------------------------------------
+
+// G (K x N) = In^H R on the device, copied to host (synchronous)
+static void reduce_to_host(Ctx& c, int prec, int K, int N, const std::vector<const void*>& in,
+                           const std::vector<const void*>& rc, std::vector<cplx>& G) {
+  G.assign((size_t)K * N, cplx(0.0, 0.0));
+  for (int k0 = 0; k0 < K; k0 += 256) {
+    const int kk = std::min(256, K - k0);
+    for (int n0 = 0; n0 < N; n0 += 16) {
+      const int nn = std::min(16, N - n0);
+      double2* dg = c.d_small + kGenericOff;
+      double2* hg = c.h_small + kGenericOff;
+      c.check(launch_gemm_reduce(prec, c.cs, kk, nn, in.data() + k0, rc.data() + n0, c.d_gpart,
+                                 c.gpart_elems, dg, c.stream),
+              "gemm reduce");
+      c.check(hipMemcpyAsync(hg, dg, sizeof(double2) * kk * nn, hipMemcpyDeviceToHost, c.stream),
+              "memcpy");
+      c.check(hipStreamSynchronize(c.stream), "sync");
+      for (int j = 0; j < nn; ++j)
+        for (int i = 0; i < kk; ++i) {
+          double2 v = hg[(size_t)j * kk + i];
+          G[(size_t)(n0 + j) * K + k0 + i] = cplx(v.x, v.y);
+        }
+    }
+  }
+}
+
+// Out (+)= In * S with host S (K x N, ld K); uses the staging area at
+// element offset `slot` of d_small / h_small.  Synchronous staging.
+static void tall_from_host(Ctx& c, int prec, int K, int N, const std::vector<const void*>& in,
+                           const std::vector<void*>& out, const cplx* S, int beta_one,
+                           int negate) {
+  for (int k0 = 0; k0 < K; k0 += 256) {
+    const int kk = std::min(256, K - k0);
+    for (int n0 = 0; n0 < N; n0 += 24) {
+      const int nn = std::min(24, N - n0);
+      c.check(hipStreamSynchronize(c.stream), "sync");
+      double2* dg = c.d_small + kGenericOff;
+      double2* hg = c.h_small + kGenericOff;
+      for (int j = 0; j < nn; ++j)
+        for (int i = 0; i < kk; ++i) {
+          cplx v = S[(size_t)(n0 + j) * K + k0 + i];
+          hg[(size_t)j * kk + i] = make_double2(v.real(), v.imag());
+        }
+      c.check(hipMemcpyAsync(dg, hg, sizeof(double2) * kk * nn, hipMemcpyHostToDevice, c.stream),
+              "memcpy");
+      c.check(launch_gemm_tall(prec, c.cs, kk, nn, in.data() + k0, out.data() + n0, dg,
+                               (beta_one || k0 > 0) ? 1 : 0, negate, c.stream),
+              "gemm tall");
+    }
+  }
+  c.check(hipStreamSynchronize(c.stream), "sync");
+}
+
+// ---------------------------------------------------------------------------
+// init-CG deflation, eq. (2.1): x += U H^{-1} U^H (b - A x)
+// ---------------------------------------------------------------------------
+
+static void ensure_chol(Ctx& c) {
+  if (c.chol_ok) return;
+  const int l = c.l, ld = c.P.max_bank;
+  for (int j = 0; j < l; ++j)
+    for (int i = 0; i < l; ++i) c.L[(size_t)j * ld + i] = c.H[(size_t)j * ld + i];
+  if (hostla::cholesky(l, c.L.data(), ld) != 0)
+    throw ApiError{EIGCG_EBREAKDOWN, "H = U^H A U is not positive definite"};
+  c.chol_ok = true;
+}
+
+// columns of ws (prec) given by mask; r holds b - A x on entry (prec storage)
+static void deflate_columns(Ctx& c, int prec, int ncols, uint32_t mask, void* x, const void* r) {
+  if (c.l == 0) return;
+  ensure_chol(c);
+  const int l = c.l;
+  std::vector<int> cols;
+  for (int j = 0; j < ncols; ++j)
+    if ((mask >> j) & 1u) cols.push_back(j);
+  if (cols.empty()) return;
+  if (prec != c.bank_prec) throw ApiError{EIGCG_EINVAL, "bank precision mismatch"};
+  std::vector<const void*> in(l), rc;
+  for (int i = 0; i < l; ++i) in[i] = col_ptr(c.U, c.bank_prec, c.cs, i);
+  for (int j : cols) rc.push_back(col_ptr(const_cast<void*>(r), prec, c.cs, j));
+  std::vector<cplx> G;
+  reduce_to_host(c, prec, l, (int)cols.size(), in, rc, G);
+  hostla::cholesky_solve(l, c.L.data(), c.P.max_bank, (int)cols.size(), G.data(), l);
+  std::vector<void*> out;
+  for (int j : cols) out.push_back(col_ptr(x, prec, c.cs, j));
+  tall_from_host(c, prec, l, (int)cols.size(), in, out, G.data(), 1, 0);
+}
+
+// ---------------------------------------------------------------------------
+// eigCG window bookkeeping (host side, one per column)
+// ---------------------------------------------------------------------------
+
+struct EigCol {
+  int k_lo = 1;            // first residual index in the window
+  bool has_vr = false;     // restarted block present (2 nev columns)
+  std::vector<double> Mv;  // its Ritz values (diagonal of T)
+  std::vector<cplx> arrow; // arrow row, T(2nev, 0:2nev)
+  int arrow_J = 0;         // iteration whose residual carries the arrow row
+  int arrow_state = 0;     // 0 none, 1 needs enqueue, 2 enqueued, 3 read
+  int next_full = 0;       // iteration after which the window is full
+  int restarts = 0;
+  bool finalized = false;
+  std::vector<double> ritz_vals;
+  int nritz = 0;
+};
+
+struct Run {
+  Ctx& c;
+  Workspace& w;
+  int prec;
+  int K;
+  uint32_t mask;
+  bool eig;
+  int nev, m, period;
+  std::vector<EigCol> ec;
+  std::vector<int> hist_read;    // iterations of history copied to the host
+  std::vector<int> done;         // column processed as stopped
+  std::vector<int> reason;
+  std::vector<int> iters;
+  std::vector<int> outer;        // host-driven restarts
+  std::vector<int> stale_until;  // snapshots of segments <= this id predate a host restart
+  int enq_iter = 0;              // iterations enqueued (all columns in lockstep)
+  int seg_id = 0;                // id of the last enqueued segment
+
+  Run(Ctx& c_, Workspace& w_, int prec_, int K_, uint32_t mask_, bool eig_)
+      : c(c_), w(w_), prec(prec_), K(K_), mask(mask_), eig(eig_) {
+    nev = c.P.nev;
+    m = c.P.m;
+    period = m - 2 * nev;
+    ec.resize(K);
+    hist_read.assign(K, 0);
+    done.assign(K, 0);
+    reason.assign(K, 0);
+    iters.assign(K, 0);
+    outer.assign(K, 0);
+    stale_until.assign(K, -1);
+    for (int j = 0; j < K; ++j) ec[j].next_full = m;
+  }
+
+  void* ringslot(int col, int k) const {
+    const int slot = k % w.ring_len;
+    return col_ptr(w.ring, prec, c.cs, (size_t)col * w.ring_len + slot);
+  }
+  void* vrcol(int col, int i) const { return col_ptr(w.vr, prec, c.cs, (size_t)col * 2 * nev + i); }
+
+  // alpha_k, beta_k, rho_k from the host history copy (k is 1-based)
+  double alpha(int col, int k) const { return c.h_hist[(size_t)col * c.hist_stride + 3 * (k - 1)]; }
+  double beta(int col, int k) const {
+    return k <= 1 ? 0.0 : c.h_hist[(size_t)col * c.hist_stride + 3 * (k - 2) + 1];
+  }
+  double rho(int col, int k) const {
+    return c.h_hist[(size_t)col * c.hist_stride + 3 * (k - 2) + 2];  // k >= 2
+  }
+
+  void enqueue_iters(int n) {
+    StencilLaunch L1 = stencil_base(c, prec);
+    L1.op = kOpM;
+    L1.epi = kEpiNorm;
+    L1.in = w.p; L1.in_cs = c.cs;
+    L1.out = w.tmp; L1.out_cs = c.cs;
+    L1.ncols = K;
+    L1.mask = mask;
+    StencilLaunch L2 = L1;
+    L2.op = kOpMdag;
+    L2.epi = kEpiCGR;
+    L2.in = w.tmp;
+    L2.r = w.r; L2.r_cs = c.cs;
+    L2.tbuf = eig ? w.tbuf : nullptr;
+    L2.t_cs = c.cs;
+    UpdateLaunch L3{};
+    L3.prec = prec;
+    L3.ncols = K;
+    L3.mask = mask;
+    L3.st = c.d_st;
+    L3.g = &c.g;
+    L3.x = w.x; L3.x_cs = c.cs;
+    L3.p = w.p; L3.p_cs = c.cs;
+    L3.r = w.r; L3.r_cs = c.cs;
+    L3.ring = eig ? w.ring : nullptr;
+    L3.ring_cs = c.cs;
+    L3.ring_len = w.ring_len;
+    L3.ring_col_cs = (size_t)w.ring_len * c.cs;
+    for (int i = 0; i < n; ++i) {
+      c.check(launch_stencil(L1, c.stream), "K1");
+      c.check(launch_stencil(L2, c.stream), "K2");
+      c.check(launch_cg_update(L3, c.stream), "K3");
+    }
+    enq_iter += n;
+  }
+
+  // states (slot) and history up to `upto` iterations, then an event
+  void enqueue_poll(int slot, int upto) {
+    c.check(hipMemcpyAsync(c.h_st + slot * kMaxCols, c.d_st, sizeof(ColState) * K,
+                           hipMemcpyDeviceToHost, c.stream),
+            "poll states");
+    if (eig) {
+      for (int j = 0; j < K; ++j) {
+        if (!((mask >> j) & 1u) || done[j]) continue;
+        const int from = hist_read[j];
+        if (upto <= from) continue;
+        const size_t off = (size_t)j * c.hist_stride + 3 * (size_t)from;
+        c.check(hipMemcpyAsync(c.h_hist + off, c.d_hist + off, sizeof(double) * 3 * (upto - from),
+                               hipMemcpyDeviceToHost, c.stream),
+                "poll hist");
+        hist_read[j] = upto;
+      }
+    }
+    c.check(hipEventRecord(c.events[slot], c.stream), "event");
+  }
+
+  // full window matrix T (i x i) of column col given iterations up to j_last
+  // (diagonal of the last residual filled when with_last_diag)
+  int build_T(int col, int k_hi, std::vector<cplx>& T, int ld) {
+    EigCol& e = ec[col];
+    const int base = e.has_vr ? 2 * nev : 0;
+    const int i = base + (k_hi - e.k_lo + 1);
+    T.assign((size_t)ld * ld, cplx(0.0, 0.0));
+    if (e.has_vr) {
+      for (int q = 0; q < 2 * nev; ++q) T[(size_t)q * ld + q] = e.Mv[q];
+      // column-major: T(row, col) = T[col * ld + row]; arrow[q] = T(q, base)
+      for (int q = 0; q < 2 * nev; ++q) {
+        T[(size_t)base * ld + q] = e.arrow[q];
+        T[(size_t)q * ld + base] = std::conj(e.arrow[q]);
+      }
+    }
+    for (int k = e.k_lo; k <= k_hi; ++k) {
+      const int pidx = base + (k - e.k_lo);
+      const double a = alpha(col, k);
+      double d = 1.0 / a;
+      if (k >= 2) d += beta(col, k) / alpha(col, k - 1);
+      T[(size_t)pidx * ld + pidx] = d;
+      if (k > e.k_lo) {
+        const double off = -std::sqrt(beta(col, k)) / alpha(col, k - 1);
+        T[(size_t)pidx * ld + pidx - 1] = off;
+        T[(size_t)(pidx - 1) * ld + pidx] = off;
+      }
+    }
+    return i;
+  }
+
+  void window_cols(int col, int k_hi, std::vector<const void*>& in) {
+    EigCol& e = ec[col];
+    in.clear();
+    if (e.has_vr)
+      for (int q = 0; q < 2 * nev; ++q) in.push_back(vrcol(col, q));
+    for (int k = e.k_lo; k <= k_hi; ++k) in.push_back(ringslot(col, k));
+  }
+
+  void wait_arrow(int col) {
+    EigCol& e = ec[col];
+    if (e.arrow_state == 2) {
+      c.check(hipEventSynchronize(c.events[4 + kMaxCols + col]), "arrow wait");
+      e.arrow.resize(2 * nev);
+      const double inv = 1.0 / std::sqrt(rho(col, e.arrow_J));
+      for (int q = 0; q < 2 * nev; ++q) {
+        // the device computed v_q^H w, i.e. T(q, 2nev) sqrt(rho) (T = V^H A V, A r = w)
+        double2 v = c.h_small[arrow_off(col) + q];
+        e.arrow[q] = cplx(v.x, v.y) * inv;
+      }
+      e.arrow_state = 3;
+    }
+  }
+
+  // Figure 3.1, steps 11.3-11.7 for one column whose window filled at E
+  void do_restart(int col, int E) {
+    EigCol& e = ec[col];
+    if (e.has_vr) wait_arrow(col);
+    std::vector<cplx> T;
+    const int i = build_T(col, E, T, m);
+    if (i != m) throw ApiError{EIGCG_EINVAL, "internal: window size mismatch at restart"};
+    // steps 11.3-11.6
+    std::vector<double> w1(m), w2(m);
+    std::vector<cplx> Y((size_t)m * nev), Yb((size_t)m * nev, cplx(0.0, 0.0));
+    if (hostla::herm_eig_lowest(m, T.data(), m, nev, w1.data(), Y.data(), m) != 0)
+      throw ApiError{EIGCG_EBREAKDOWN, "window eigensolver failed"};
+    c.amax = std::max(c.amax, w1[m - 1]);
+    if (hostla::herm_eig_lowest(m - 1, T.data(), m, nev, w2.data(), Yb.data(), m) != 0)
+      throw ApiError{EIGCG_EBREAKDOWN, "window eigensolver failed"};
+    for (int q = 0; q < nev; ++q) Yb[(size_t)q * m + (m - 1)] = 0.0;  // step 11.4
+    std::vector<cplx> YY((size_t)m * 2 * nev);
+    std::copy(Y.begin(), Y.end(), YY.begin());
+    std::copy(Yb.begin(), Yb.end(), YY.begin() + (size_t)m * nev);
+    std::vector<cplx> Q((size_t)m * 2 * nev);
+    hostla::qr_thin(m, 2 * nev, YY.data(), m, Q.data(), m, nullptr, 0);  // step 11.5
+    std::vector<cplx> TQ((size_t)m * 2 * nev), Hs((size_t)4 * nev * nev);
+    hostla::matmul_sparse_a(m, 2 * nev, m, T.data(), m, Q.data(), m, TQ.data(), m);
+    hostla::matmul_ah_b(2 * nev, 2 * nev, m, Q.data(), m, TQ.data(), m, Hs.data(), 2 * nev);
+    std::vector<double> Mv(2 * nev);
+    std::vector<cplx> Z((size_t)4 * nev * nev);
+    if (hostla::herm_eig_lowest(2 * nev, Hs.data(), 2 * nev, 2 * nev, Mv.data(), Z.data(),
+                                2 * nev) != 0)  // step 11.6
+      throw ApiError{EIGCG_EBREAKDOWN, "restart eigensolver failed"};
+    std::vector<cplx> QZ((size_t)m * 2 * nev);
+    hostla::matmul_sparse_a(m, 2 * nev, 2 * nev, Q.data(), m, Z.data(), 2 * nev, QZ.data(), m);
+    // step 11.7: V <- V (QZ) on the device, in place over the restart block
+    hipEvent_t ev = c.events[4 + col];
+    c.check(hipEventSynchronize(ev), "qz slot wait");
+    double2* hq = c.h_small + qz_off(col);
+    double2* dq = c.d_small + qz_off(col);
+    for (size_t q = 0; q < QZ.size(); ++q) hq[q] = make_double2(QZ[q].real(), QZ[q].imag());
+    c.check(hipMemcpyAsync(dq, hq, sizeof(double2) * QZ.size(), hipMemcpyHostToDevice, c.stream),
+            "qz upload");
+    std::vector<const void*> in;
+    window_cols(col, E, in);
+    std::vector<void*> out(2 * nev);
+    for (int q = 0; q < 2 * nev; ++q) out[q] = vrcol(col, q);
+    c.check(launch_gemm_tall(prec, c.cs, m, 2 * nev, in.data(), out.data(), dq, 0, 0, c.stream),
+            "restart gemm");
+    c.check(hipEventRecord(ev, c.stream), "event");
+    e.has_vr = true;
+    e.Mv = Mv;
+    e.k_lo = E + 1;
+    e.arrow_J = E + 1;
+    e.arrow_state = 1;
+    e.next_full = E + period;
+    e.restarts++;
+  }
+
+  // step 11.8: w = t_J - beta_J t_{J-1}; arrow = V^H w (conj-transposed later)
+  void enqueue_arrow(int col) {
+    EigCol& e = ec[col];
+    const int J = e.arrow_J;
+    const double bJ = beta(col, J);
+    void* tJ = col_ptr(w.tbuf, prec, c.cs, (size_t)col * 2 + (J & 1));
+    void* tJ1 = col_ptr(w.tbuf, prec, c.cs, (size_t)col * 2 + ((J - 1) & 1));
+    void* wv = col_ptr(w.w, prec, c.cs, col);
+    // w = tJ - bJ tJ1: copy, then axpy
+    c.check(launch_copy(prec, prec, 1, c.cs, tJ, c.cs, wv, c.cs, c.stream), "copy");
+    c.check(launch_axpy(prec, 1, c.cs, nullptr, -bJ, 0.0, tJ1, c.cs, wv, c.cs, c.stream), "axpy");
+    std::vector<const void*> in(2 * nev), rc(1, wv);
+    for (int q = 0; q < 2 * nev; ++q) in[q] = vrcol(col, q);
+    double2* G = c.d_small + arrow_off(col);
+    c.check(launch_gemm_reduce(prec, c.cs, 2 * nev, 1, in.data(), rc.data(), c.d_gpart,
+                               c.gpart_elems, G, c.stream),
+            "arrow gemm");
+    c.check(hipMemcpyAsync(c.h_small + arrow_off(col), G,
+                           sizeof(double2) * 2 * nev, hipMemcpyDeviceToHost, c.stream),
+            "arrow copy");
+    c.check(hipEventRecord(c.events[4 + kMaxCols + col], c.stream), "event");
+    e.arrow_state = 2;
+  }
+
+  // final Rayleigh-Ritz on T_i and the nev Ritz vectors (eigCG output)
+  void finalize_eig(int col, int j) {
+    EigCol& e = ec[col];
+    if (e.finalized) return;
+    e.finalized = true;
+    if (j < 1) return;
+    if (e.has_vr && e.arrow_state == 1) enqueue_arrow(col);
+    if (e.has_vr) wait_arrow(col);
+    std::vector<cplx> T;
+    const int i = build_T(col, j, T, m);
+    const int k = std::min(nev, i);
+    std::vector<double> th(i);
+    std::vector<cplx> Y((size_t)i * k);
+    if (hostla::herm_eig_lowest(i, T.data(), m, k, th.data(), Y.data(), i) != 0)
+      throw ApiError{EIGCG_EBREAKDOWN, "final eigensolver failed"};
+    c.amax = std::max(c.amax, th[i - 1]);
+    e.ritz_vals.assign(th.begin(), th.begin() + k);
+    e.nritz = k;
+    std::vector<const void*> in;
+    window_cols(col, j, in);
+    std::vector<void*> out(k);
+    for (int q = 0; q < k; ++q) out[q] = col_ptr(w.ritz, prec, c.cs, (size_t)col * nev + q);
+    c.check(hipStreamSynchronize(c.stream), "sync");
+    tall_from_host(c, prec, i, k, in, out, Y.data(), 0, 0);
+  }
+};
+
+// Set up the column states for a run (host -> device), then r = b - A x,
+// p = r and the first window column.
+static void start_run(Run& R, const std::vector<double>& bn2, double tol, double restart_tol,
+                      bool mixed) {
+  Ctx& c = R.c;
+  std::vector<ColState> st(R.K);
+  for (int j = 0; j < R.K; ++j) {
+    ColState& S = st[j];
+    std::memset(&S, 0, sizeof(S));
+    S.max_iter = c.P.max_iter;
+    S.state = ((R.mask >> j) & 1u) ? ColRun : ColStopped;
+    const double t2 = tol * tol * bn2[j];
+    S.res_stop2 = t2;
+    if (mixed) {
+      S.stop2 = 0.0;      // FP32 recursive residuals are never trusted ...
+      // ... they only request an FP64 reliable update; eigCG columns never
+      // pause (their window schedule follows the iteration count), they
+      // stop at the reliable update that meets the tolerance
+      S.restart2 = R.eig ? 0.0 : t2;
+      S.defl2 = restart_tol > tol ? restart_tol * restart_tol * bn2[j] : 0.0;
+    } else {
+      S.stop2 = t2;
+      S.restart2 = restart_tol > tol ? restart_tol * restart_tol * bn2[j] : 0.0;
+      S.defl2 = 0.0;
+    }
+    if (R.eig) {
+      S.save_t0 = R.m;
+      S.save_t1 = R.m + 1;
+      S.tperiod = R.period;
+    }
+  }
+  std::memcpy(c.h_st, st.data(), sizeof(ColState) * R.K);
+  c.check(hipMemcpyAsync(c.d_st, c.h_st, sizeof(ColState) * R.K, hipMemcpyHostToDevice,
+                         c.stream),
+          "state upload");
+}
+
+}  // namespace eigcg
+
+namespace eigcg {
+
+// ---------------------------------------------------------------------------
+// the batched iteration driver
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct Mixed {
+  Workspace* w64 = nullptr;  // FP64 b, x, r, tmp for reliable updates
+};
+
+// FP64 reliable update of a mixed-precision run: x64 += x32; r64 = b - A x64;
+// r32 = r64; rho = ||r64||^2; convergence / re-deflation decided on device.
+void reliable_update(Run& R, Mixed& mx) {
+  Ctx& c = R.c;
+  Workspace& w64 = *mx.w64;
+  c.check(launch_accum_f32_into_f64(R.K, c.cs, w64.x, c.cs, R.w.x, c.cs, c.stream), "accum");
+  true_residual(c, kF64, R.K, R.mask, w64.x, w64.b, w64.r, w64.tmp);
+  c.check(launch_copy(kF64, kF32, R.K, c.cs, w64.r, c.cs, R.w.r, c.cs, c.stream), "copy");
+  c.check(launch_post_residual(c.d_st, R.K, R.mask, c.stream), "post");
+}
+
+void cg_start(Run& R, uint32_t mask) {
+  UpdateLaunch L{};
+  L.prec = R.prec;
+  L.ncols = R.K;
+  L.mask = mask;
+  L.st = R.c.d_st;
+  L.g = &R.c.g;
+  L.p = R.w.p; L.p_cs = R.c.cs;
+  L.r = R.w.r; L.r_cs = R.c.cs;
+  L.ring = R.eig ? R.w.ring : nullptr;
+  L.ring_cs = R.c.cs;
+  L.ring_len = R.w.ring_len;
+  L.ring_col_cs = (size_t)R.w.ring_len * R.c.cs;
+  R.c.check(launch_cg_start(L, R.c.stream), "cg start");
+}
+
+// init-CG restart (Section 5.3) of one column: deflate the current iterate
+// again and restart CG from it.
+void host_restart(Run& R, Mixed* mx, int col) {
+  Ctx& c = R.c;
+  const uint32_t m1 = 1u << col;
+  c.check(hipStreamSynchronize(c.stream), "sync");
+  if (!mx) {
+    true_residual(c, kF64, R.K, m1, R.w.x, R.w.b, R.w.r, R.w.tmp);
+    deflate_columns(c, kF64, R.K, m1, R.w.x, R.w.r);
+    true_residual(c, kF64, R.K, m1, R.w.x, R.w.b, R.w.r, R.w.tmp);
+  } else {
+    Workspace& w64 = *mx->w64;
+    c.check(launch_accum_f32_into_f64(R.K, c.cs, w64.x, c.cs, R.w.x, c.cs, c.stream), "accum");
+    true_residual(c, kF64, R.K, m1, w64.x, w64.b, w64.r, w64.tmp);
+    c.check(launch_copy(kF64, kF32, R.K, c.cs, w64.r, c.cs, R.w.r, c.cs, c.stream), "copy");
+    deflate_columns(c, kF32, R.K, m1, R.w.x, R.w.r);  // x32 = U H^-1 U^H r
+    c.check(launch_accum_f32_into_f64(R.K, c.cs, w64.x, c.cs, R.w.x, c.cs, c.stream), "accum");
+    true_residual(c, kF64, R.K, m1, w64.x, w64.b, w64.r, w64.tmp);
+    c.check(launch_copy(kF64, kF32, R.K, c.cs, w64.r, c.cs, R.w.r, c.cs, c.stream), "copy");
+  }
+  c.check(launch_set_state(c.d_st, R.K, m1, ColRun, ReasonNone, 1, c.stream), "state");
+  c.check(launch_post_residual(c.d_st, R.K, m1, c.stream), "post");
+  cg_start(R, m1);
+  R.outer[col]++;
+  // the segment already in flight was polled before this restart: ignore it
+  R.stale_until[col] = R.seg_id;
+}
+
+void process(Run& R, Mixed* mx, int slot, int end, int id) {
+  Ctx& c = R.c;
+  c.check(hipEventSynchronize(c.events[slot]), "poll wait");
+  const ColState* hs = c.h_st + slot * kMaxCols;
+  for (int j = 0; j < R.K; ++j) {
+    if (!((R.mask >> j) & 1u) || R.done[j]) continue;
+    if (id <= R.stale_until[j]) continue;
+    const ColState S = hs[j];
+    R.iters[j] = S.iter;
+    if (R.eig) {
+      EigCol& e = R.ec[j];
+      if (e.arrow_state == 1 && S.iter >= e.arrow_J) R.enqueue_arrow(j);
+      if (S.state == ColRun && S.iter == end && e.next_full == end) R.do_restart(j, end);
+    }
+    if (S.state == ColRun) continue;
+    if (S.reason == ReasonRestart && S.state != ColRun) {
+      if (R.eig) continue;  // mixed eigCG waits for its next reliable update
+      host_restart(R, mx, j);
+      continue;
+    }
+    R.done[j] = 1;
+    R.reason[j] = S.reason;
+    if (R.eig) R.finalize_eig(j, S.iter);
+  }
+}
+
+void run_loop(Run& R, Mixed* mx) {
+  Ctx& c = R.c;
+  const int seg = R.eig ? seg_len_eig(c.P) : std::max(1, c.P.check_every);
+  const int relf = mx ? std::max(1, c.P.reliable_every) : 0;
+  bool pending = false;
+  int pslot = 0, pend = 0, pid = 0, slot = 0;
+  const int hard_cap = c.P.max_iter + 4 * seg + 8;
+  while (true) {
+    int end = R.enq_iter + seg;
+    if (R.eig)
+      for (int j = 0; j < R.K; ++j)
+        if (((R.mask >> j) & 1u) && !R.done[j] && R.ec[j].next_full > R.enq_iter)
+          end = std::min(end, R.ec[j].next_full);
+    if (relf) {
+      const int next_rel = (R.enq_iter / relf + 1) * relf;
+      end = std::min(end, next_rel);
+    }
+    R.enqueue_iters(end - R.enq_iter);
+    if (relf && end % relf == 0) reliable_update(R, *mx);
+    R.enqueue_poll(slot, end);
+    const int id = ++R.seg_id;
+    if (pending) process(R, mx, pslot, pend, pid);
+    pending = true;
+    pslot = slot;
+    pend = end;
+    pid = id;
+    slot ^= 1;
+    bool all = true;
+    for (int j = 0; j < R.K; ++j)
+      if (((R.mask >> j) & 1u) && !R.done[j]) all = false;
+    if (all) break;
+    if (R.enq_iter > hard_cap) break;
+  }
+  c.check(hipStreamSynchronize(c.stream), "sync");
+  // columns still not marked done (hard cap) are read from the final states
+  c.check(hipMemcpy(c.h_st, c.d_st, sizeof(ColState) * R.K, hipMemcpyDeviceToHost), "states");
+  for (int j = 0; j < R.K; ++j) {
+    if (!((R.mask >> j) & 1u) || R.done[j]) continue;
+    R.iters[j] = c.h_st[j].iter;
+    R.reason[j] = c.h_st[j].reason == ReasonNone ? ReasonMaxIter : c.h_st[j].reason;
+    R.done[j] = 1;
+    if (R.eig) R.finalize_eig(j, c.h_st[j].iter);
+  }
+}
+
+// Section 4: orthonormalise the Ritz vectors of one column against U and among
+// themselves (classical Gram-Schmidt twice), W = A Vbar, grow H by the new
+// rows/columns and append Vbar to U.  Returns the number of vectors added.
+void ensure_bank(Ctx& c) {
+  if (!c.U) c.U = c.dalloc(c.cs * elem_bytes(c.bank_prec) * (size_t)c.P.max_bank);
+  if (!c.bwork) c.bwork = c.dalloc(c.cs * elem_bytes(c.bank_prec) * (size_t)2 * c.P.nev);
+}
+
+// src: k contiguous fields (bank precision) of new directions; they may
+// already sit in the bank slots l..l+k-1.
+int bank_append_from(Ctx& c, const void* src, int nsrc) {
+  const int prec = c.bank_prec;
+  const int nev = c.P.nev;
+  const int room = c.P.max_bank - c.l;
+  const int k = std::min(nsrc, room);
+  if (k <= 0) return 0;
+  ensure_bank(c);
+  const int l = c.l;
+  // norms before projection (drop test), then copy into the bank slots
+  c.check(launch_norm2(prec, k, c.cs, src, c.cs, c.d_partial, c.d_counter, c.d_norm, c.stream),
+          "norm");
+  c.check(hipMemcpyAsync(c.h_norm, c.d_norm, sizeof(double) * k, hipMemcpyDeviceToHost, c.stream),
+          "norm copy");
+  c.check(hipStreamSynchronize(c.stream), "sync");
+  std::vector<double> n0(c.h_norm, c.h_norm + k);
+  void* vb = col_ptr(c.U, prec, c.cs, l);
+  if (vb != src) c.check(launch_copy(prec, prec, k, c.cs, src, c.cs, vb, c.cs, c.stream), "copy");
+  std::vector<const void*> ucols(l);
+  for (int i = 0; i < l; ++i) ucols[i] = col_ptr(c.U, prec, c.cs, i);
+  // CGS2 against U
+  if (l > 0) {
+    std::vector<const void*> rc(k);
+    std::vector<void*> out(k);
+    for (int q = 0; q < k; ++q) {
+      rc[q] = col_ptr(c.U, prec, c.cs, l + q);
+      out[q] = col_ptr(c.U, prec, c.cs, l + q);
+    }
+    for (int pass = 0; pass < 2; ++pass) {
+      std::vector<cplx> G;
+      reduce_to_host(c, prec, l, k, ucols, rc, G);
+      tall_from_host(c, prec, l, k, ucols, out, G.data(), 1, 1);
+    }
+  }
+  // CGS2 inside the new block, column by column, with the drop rule
+  int kept = 0;
+  for (int q = 0; q < k; ++q) {
+    void* v = col_ptr(c.U, prec, c.cs, l + q);
+    void* dst = col_ptr(c.U, prec, c.cs, l + kept);
+    if (kept > 0) {
+      std::vector<const void*> prev(kept), rc(1, v);
+      std::vector<void*> out(1, v);
+      for (int i = 0; i < kept; ++i) prev[i] = col_ptr(c.U, prec, c.cs, l + i);
+      for (int pass = 0; pass < 2; ++pass) {
+        std::vector<cplx> g;
+        reduce_to_host(c, prec, kept, 1, prev, rc, g);
+        tall_from_host(c, prec, kept, 1, prev, out, g.data(), 1, 1);
+      }
+    }
+    c.check(launch_norm2(prec, 1, c.cs, v, c.cs, c.d_partial, c.d_counter, c.d_norm, c.stream),
+            "norm");
+    c.check(hipMemcpyAsync(c.h_norm, c.d_norm, sizeof(double), hipMemcpyDeviceToHost, c.stream),
+            "norm copy");
+    c.check(hipStreamSynchronize(c.stream), "sync");
+    const double nrm = std::sqrt(c.h_norm[0]);
+    if (!(nrm > 1e-10 * std::sqrt(n0[q]))) continue;
+    const double inv = 1.0 / nrm;
+    // scale into its final slot
+    if (dst != v) c.check(launch_copy(prec, prec, 1, c.cs, v, c.cs, dst, c.cs, c.stream), "copy");
+    c.h_norm[1] = inv;
+    c.check(hipMemcpyAsync(c.d_norm + 1, c.h_norm + 1, sizeof(double), hipMemcpyHostToDevice,
+                           c.stream),
+            "scale upload");
+    c.check(launch_scale(prec, 1, c.cs, c.d_norm + 1, dst, c.cs, c.stream), "scale");
+    c.check(hipStreamSynchronize(c.stream), "sync");
+    ++kept;
+  }
+  if (kept == 0) return 0;
+  // W = A Vbar, then [U Vbar]^H W (kept <= nev; the work area holds 2 nev fields)
+  void* W = c.bwork;
+  void* tmp = col_ptr(c.bwork, prec, c.cs, nev);
+  for (int q = 0; q < kept; ++q) {
+    stencil_store(c, prec, kOpM, 1, col_ptr(c.U, prec, c.cs, l + q), tmp);
+    stencil_store(c, prec, kOpMdag, 1, tmp, col_ptr(W, prec, c.cs, q));
+  }
+  std::vector<const void*> all(l + kept), wc(kept);
+  for (int i = 0; i < l + kept; ++i) all[i] = col_ptr(c.U, prec, c.cs, i);
+  for (int q = 0; q < kept; ++q) wc[q] = col_ptr(W, prec, c.cs, q);
+  std::vector<cplx> G2;
+  reduce_to_host(c, prec, l + kept, kept, all, wc, G2);
+  const int ld = c.P.max_bank;
+  for (int q = 0; q < kept; ++q) {
+    for (int i = 0; i < l + kept; ++i) {
+      const cplx v = G2[(size_t)q * (l + kept) + i];  // (U Vbar)_i^H A vbar_q
+      c.H[(size_t)(l + q) * ld + i] = v;
+      if (i < l) c.H[(size_t)i * ld + (l + q)] = std::conj(v);
+    }
+  }
+  for (int a = 0; a < kept; ++a)  // Hermitian part of the new diagonal block
+    for (int b = a; b < kept; ++b) {
+      const cplx x = c.H[(size_t)(l + b) * ld + (l + a)];
+      const cplx y = c.H[(size_t)(l + a) * ld + (l + b)];
+      const cplx h = 0.5 * (x + std::conj(y));
+      c.H[(size_t)(l + b) * ld + (l + a)] = h;
+      c.H[(size_t)(l + a) * ld + (l + b)] = std::conj(h);
+    }
+  for (int a = 0; a < kept; ++a) {
+    cplx& d = c.H[(size_t)(l + a) * ld + (l + a)];
+    d = cplx(d.real(), 0.0);
+  }
+  c.l = l + kept;
+  c.chol_ok = false;
+  return kept;
+}
+
+void check_finite(const std::vector<double>& v) {
+  for (double x : v)
+    if (!std::isfinite(x)) throw ApiError{EIGCG_EINVAL, "right-hand side has NaN or Inf"};
+}
+
+std::vector<double> col_norms(Ctx& c, int prec, int k, const void* base) {
+  c.check(launch_norm2(prec, k, c.cs, base, c.cs, c.d_partial, c.d_counter, c.d_norm, c.stream),
+          "norm");
+  c.check(hipMemcpyAsync(c.h_norm, c.d_norm, sizeof(double) * k, hipMemcpyDeviceToHost, c.stream),
+          "norm copy");
+  c.check(hipStreamSynchronize(c.stream), "sync");
+  return std::vector<double>(c.h_norm, c.h_norm + k);
+}
+
+int status_of(int reason) {
+  if (reason == ReasonConverged) return EIGCG_OK;
+  if (reason == ReasonBreakdown) return EIGCG_EBREAKDOWN;
+  return EIGCG_ENOTCONV;
+}
+
+}  // namespace
+
+int solve(Ctx& c, int nrhs, const void* b_aos, void* x_aos, double tol, int mode,
+          eigcg_stats* stats) {
+  const bool mixed = c.P.precision == EIGCG_MIXED_FP32;
+  const bool eig = mode == EIGCG_MODE_EIGCG;
+  const int prec = mixed ? kF32 : kF64;
+  ws_ensure(c, c.ws64, kF64, eig && !mixed);
+  if (mixed) ws_ensure(c, c.ws32, kF32, eig);
+  Workspace& w = mixed ? c.ws32 : c.ws64;
+  Workspace& w64 = c.ws64;
+  int worst = EIGCG_OK;
+  c.last_ritz.clear();
+  double restart_tol = c.P.restart_tol;
+  for (int c0 = 0; c0 < nrhs; c0 += w.K) {
+    const double t0 = now_s();
+    const int K = std::min(w.K, nrhs - c0);
+    const double2* bsrc = (const double2*)b_aos + (size_t)c0 * 12 * c.g.V;
+    double2* xdst = (double2*)x_aos + (size_t)c0 * 12 * c.g.V;
+    c.check(launch_spinor_to_soa(bsrc, w64.b, kF64, &c.g, K, c.cs, c.stream), "to soa");
+    c.check(launch_spinor_to_soa(xdst, w64.x, kF64, &c.g, K, c.cs, c.stream), "to soa");
+    std::vector<double> bn2 = col_norms(c, kF64, K, w64.b);
+    check_finite(bn2);
+    uint32_t mask = 0;
+    for (int j = 0; j < K; ++j) {
+      if (bn2[j] > 0.0) {
+        mask |= 1u << j;
+      } else {  // b = 0: x = 0
+        c.check(hipMemsetAsync(col_ptr(w64.x, kF64, c.cs, j), 0, c.cs * 16, c.stream), "zero");
+      }
+    }
+    // init-CG restart threshold (Section 5.3): 10 eps ||A|| with ||A|| from
+    // the largest Ritz value seen (or the Gershgorin-style bound (8+|m|)^2)
+    if (mode == EIGCG_MODE_INITCG && c.P.restart_tol == 0.0) {
+      const double anorm = c.amax > 0 ? c.amax : (8.0 + std::fabs(c.P.mass)) * (8.0 + std::fabs(c.P.mass));
+      restart_tol = 10.0 * (mixed ? 1.1920929e-7 : 2.220446049250313e-16) * anorm;
+    } else if (mode != EIGCG_MODE_INITCG || c.P.restart_tol < 0) {
+      restart_tol = 0.0;
+    }
+    Run R(c, w, prec, K, mask, eig);
+    Mixed mx;
+    mx.w64 = &w64;
+    if (mask) {
+      start_run(R, bn2, tol, restart_tol, mixed);
+      if (!mixed) {
+        if (mode != EIGCG_MODE_CG && c.l > 0) {
+          true_residual(c, kF64, K, mask, w64.x, w64.b, w64.r, w64.tmp);
+          deflate_columns(c, kF64, K, mask, w64.x, w64.r);
+        }
+        true_residual(c, kF64, K, mask, w.x, w.b, w.r, w.tmp);
+      } else {
+        c.check(hipMemsetAsync(w.x, 0, c.cs * 8 * K, c.stream), "zero x32");
+        true_residual(c, kF64, K, mask, w64.x, w64.b, w64.r, w64.tmp);
+        if (mode != EIGCG_MODE_CG && c.l > 0) {
+          c.check(launch_copy(kF64, kF32, K, c.cs, w64.r, c.cs, w.r, c.cs, c.stream), "copy");
+          deflate_columns(c, kF32, K, mask, w.x, w.r);
+          c.check(launch_accum_f32_into_f64(K, c.cs, w64.x, c.cs, w.x, c.cs, c.stream), "accum");
+          true_residual(c, kF64, K, mask, w64.x, w64.b, w64.r, w64.tmp);
+        }
+        c.check(launch_copy(kF64, kF32, K, c.cs, w64.r, c.cs, w.r, c.cs, c.stream), "copy");
+      }
+      c.check(launch_post_residual(c.d_st, K, mask, c.stream), "post");
+      cg_start(R, mask);
+      run_loop(R, mixed ? &mx : nullptr);
+      if (mixed)
+        c.check(launch_accum_f32_into_f64(K, c.cs, w64.x, c.cs, w.x, c.cs, c.stream), "accum");
+    }
+    // final FP64 true residual
+    std::vector<double> res(K, 0.0);
+    if (mask) {
+      // states: mark stopped so that the residual pass changes nothing else
+      c.check(launch_set_state(c.d_st, K, mask, ColStopped, ReasonConverged, 0, c.stream), "st");
+      true_residual(c, kF64, K, mask, w64.x, w64.b, w64.r, w64.tmp);
+      c.check(hipMemcpy(c.h_st, c.d_st, sizeof(ColState) * K, hipMemcpyDeviceToHost), "states");
+      for (int j = 0; j < K; ++j)
+        if ((mask >> j) & 1u) res[j] = std::sqrt(c.h_st[j].rho / bn2[j]);
+    }
+    c.check(launch_spinor_from_soa(w64.x, xdst, kF64, &c.g, K, c.cs, c.stream), "from soa");
+    c.check(hipStreamSynchronize(c.stream), "sync");
+    // Incremental eigCG: append each column's Ritz vectors in column order
+    std::vector<int> added(K, 0);
+    if (eig) {
+      for (int j = 0; j < K; ++j) {
+        if (!((mask >> j) & 1u)) continue;
+        const EigCol& e = R.ec[j];
+        for (double v : e.ritz_vals) c.last_ritz.push_back(v);
+        for (int q0 = 0; q0 < e.nritz; q0 += c.P.nev)
+          added[j] += bank_append_from(c, col_ptr(w.ritz, prec, c.cs, (size_t)j * c.P.nev + q0),
+                                       std::min(c.P.nev, e.nritz - q0));
+      }
+    }
+    const double dt = now_s() - t0;
+    for (int j = 0; j < K; ++j) {
+      int stt = EIGCG_OK;
+      if ((mask >> j) & 1u) {
+        stt = status_of(R.reason[j]);
+        if (stt == EIGCG_OK && !(res[j] <= tol)) stt = EIGCG_ENOTCONV;
+      }
+      if (stt < worst) worst = stt;
+      if (stats) {
+        eigcg_stats& s = stats[c0 + j];
+        s.iters = R.iters[j];
+        s.restarts = eig ? R.ec[j].restarts : 0;
+        s.outer_steps = R.outer[j] + (mixed ? R.iters[j] / std::max(1, c.P.reliable_every) : 0);
+        s.status = stt;
+        s.true_rel_res = res[j];
+        s.seconds = dt;
+        s.bank_added = added[j];
+        s.nritz = eig ? R.ec[j].nritz : 0;
+      }
+    }
+  }
+  return worst;
+}
+
+void deflate_init(Ctx& c, int nrhs, const void* b_aos, void* x_aos) {
+  const bool mixed = c.P.precision == EIGCG_MIXED_FP32;
+  ws_ensure(c, c.ws64, kF64, false);
+  if (mixed) ws_ensure(c, c.ws32, kF32, false);
+  Workspace& w64 = c.ws64;
+  for (int c0 = 0; c0 < nrhs; c0 += w64.K) {
+    const int K = std::min(w64.K, nrhs - c0);
+    const uint32_t mask = (K >= 32) ? 0xffffffffu : ((1u << K) - 1);
+    const double2* bsrc = (const double2*)b_aos + (size_t)c0 * 12 * c.g.V;
+    double2* xdst = (double2*)x_aos + (size_t)c0 * 12 * c.g.V;
+    c.check(launch_spinor_to_soa(bsrc, w64.b, kF64, &c.g, K, c.cs, c.stream), "to soa");
+    c.check(launch_spinor_to_soa(xdst, w64.x, kF64, &c.g, K, c.cs, c.stream), "to soa");
+    if (c.l > 0) {
+      std::vector<ColState> st(K);
+      std::memset(st.data(), 0, sizeof(ColState) * K);
+      for (auto& s : st) s.state = ColStopped;
+      std::memcpy(c.h_st, st.data(), sizeof(ColState) * K);
+      c.check(hipMemcpy(c.d_st, c.h_st, sizeof(ColState) * K, hipMemcpyHostToDevice), "st");
+      true_residual(c, kF64, K, mask, w64.x, w64.b, w64.r, w64.tmp);
+      if (!mixed) {
+        deflate_columns(c, kF64, K, mask, w64.x, w64.r);
+      } else {
+        Workspace& w = c.ws32;
+        c.check(hipMemsetAsync(w.x, 0, c.cs * 8 * K, c.stream), "zero");
+        c.check(launch_copy(kF64, kF32, K, c.cs, w64.r, c.cs, w.r, c.cs, c.stream), "copy");
+        deflate_columns(c, kF32, K, mask, w.x, w.r);
+        c.check(launch_accum_f32_into_f64(K, c.cs, w64.x, c.cs, w.x, c.cs, c.stream), "accum");
+      }
+    }
+    c.check(launch_spinor_from_soa(w64.x, xdst, kF64, &c.g, K, c.cs, c.stream), "from soa");
+  }
+  c.check(hipStreamSynchronize(c.stream), "sync");
+}
+
+void bank_info(Ctx& c, int* l_out, double* vals, double* res) {
+  const int l = c.l, ld = c.P.max_bank;
+  *l_out = l;
+  if (l == 0 || !vals) return;
+  std::vector<double> th(l);
+  std::vector<cplx> Y((size_t)l * l);
+  if (hostla::herm_eig_lowest(l, c.H.data(), ld, res ? l : 0, th.data(), res ? Y.data() : nullptr,
+                              l) != 0)
+    throw ApiError{EIGCG_EBREAKDOWN, "bank eigensolver failed"};
+  for (int i = 0; i < l; ++i) vals[i] = th[i];
+  if (!res) return;
+  // residuals ||A U y - theta U y|| in the bank precision
+  const int prec = c.bank_prec;
+  Workspace& w = prec == kF64 ? c.ws64 : c.ws32;
+  ws_ensure(c, w, prec, false);
+  std::vector<const void*> in(l);
+  for (int i = 0; i < l; ++i) in[i] = col_ptr(c.U, prec, c.cs, i);
+  for (int q = 0; q < l; ++q) {
+    std::vector<void*> out(1, w.x);
+    tall_from_host(c, prec, l, 1, in, out, Y.data() + (size_t)q * l, 0, 0);
+    stencil_store(c, prec, kOpM, 1, w.x, w.tmp);
+    stencil_store(c, prec, kOpMdag, 1, w.tmp, w.r);
+    c.check(launch_axpy(prec, 1, c.cs, nullptr, -th[q], 0.0, w.x, c.cs, w.r, c.cs, c.stream),
+            "axpy");
+    std::vector<double> n = col_norms(c, prec, 1, w.r);
+    res[q] = std::sqrt(n[0]);
+  }
+}
+
+int bank_load(Ctx& c, int count, const void* vecs_aos) {
+  ensure_bank(c);
+  int added = 0;
+  const int nev = c.P.nev;
+  for (int q0 = 0; q0 < count && c.l < c.P.max_bank; q0 += nev) {
+    const int k = std::min(std::min(nev, count - q0), c.P.max_bank - c.l);
+    void* slot = col_ptr(c.U, c.bank_prec, c.cs, c.l);
+    const double2* src = (const double2*)vecs_aos + (size_t)q0 * 12 * c.g.V;
+    c.check(launch_spinor_to_soa(src, slot, c.bank_prec, &c.g, k, c.cs, c.stream), "to soa");
+    added += bank_append_from(c, slot, k);
+  }
+  return added;
+}
+
+void bank_vectors(Ctx& c, int first, int count, void* out_aos) {
+  for (int q = 0; q < count; ++q) {
+    double2* dst = (double2*)out_aos + (size_t)q * 12 * c.g.V;
+    c.check(launch_spinor_from_soa(col_ptr(c.U, c.bank_prec, c.cs, first + q), dst, c.bank_prec,
+                                   &c.g, 1, c.cs, c.stream),
+            "from soa");
+  }
+  c.check(hipStreamSynchronize(c.stream), "sync");
+}
+
+}  // namespace eigcg

@@ -1,0 +1,104 @@
+// Solver engine of the eigCG library: context, device workspaces, and the
+// CG / eigCG / init-CG / Incremental eigCG drivers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "eigcg.h"
+#include "kernels.h"
+
+namespace eigcg {
+
+using cplx = std::complex<double>;
+
+struct HipError {
+  hipError_t e;
+  const char* what;
+};
+struct ApiError {
+  int code;
+  std::string msg;
+};
+
+// Device vectors of one batched solve (K columns, one precision).
+struct Workspace {
+  int K = 0;
+  int prec = kF64;
+  bool eig = false;
+  int ring_len = 0;
+  int nev = 0;
+  void* b = nullptr;
+  void* x = nullptr;
+  void* r = nullptr;
+  void* p = nullptr;
+  void* tmp = nullptr;
+  void* ring = nullptr;  // K * ring_len window residuals
+  void* vr = nullptr;    // K * 2nev restarted window block
+  void* tbuf = nullptr;  // K * 2 saved A p
+  void* w = nullptr;     // K arrow-row vectors
+  void* ritz = nullptr;  // K * nev Ritz vectors
+};
+
+struct Ctx {
+  eigcg_params P{};
+  Geom g{};
+  size_t cs = 0;         // complex elements per field (12 * vs)
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int comp64 = 0, comp32 = 0;
+  void* u64 = nullptr;
+  void* u32 = nullptr;
+  // bank (Section 4): U columns, H = U^H A U and its Cholesky factor
+  int bank_prec = kF64;
+  void* U = nullptr;
+  void* bwork = nullptr;  // 2 nev fields: W = A Vbar and a temporary
+  int l = 0;
+  std::vector<cplx> H;    // max_bank x max_bank, ld = max_bank
+  std::vector<cplx> L;    // Cholesky factor of H(0:l, 0:l)
+  bool chol_ok = false;
+  double amax = 0.0;      // largest Ritz value seen (norm of A estimate)
+  // scratch
+  ColState* d_st = nullptr;
+  ColState* h_st = nullptr;        // pinned, 2 x kMaxCols (double-buffered polls)
+  double* d_hist = nullptr;
+  double* h_hist = nullptr;        // pinned mirror
+  int hist_stride = 0;             // doubles per column
+  double* d_partial = nullptr;
+  unsigned int* d_counter = nullptr;
+  double2* d_gpart = nullptr;
+  size_t gpart_elems = 0;
+  double2* d_small = nullptr;      // small matrices (S, G) for GEMMs
+  double2* h_small = nullptr;      // pinned mirror
+  size_t small_elems = 0;
+  double* d_norm = nullptr;        // kMaxCols norms
+  double* h_norm = nullptr;
+  Workspace ws64, ws32;
+  size_t bytes = 0;
+  std::string err;
+  int sticky = 0;
+  std::vector<double> last_ritz;
+  std::vector<hipEvent_t> events;
+
+  // memory
+  void* dalloc(size_t bytes_);
+  void dfree(void*& p);
+  void check(hipError_t e, const char* what);
+};
+
+// Engine entry points (throw HipError / ApiError; the ABI layer converts).
+void ctx_init(Ctx& c, const eigcg_params& p, const void* gauge_dev, hipStream_t s);
+void ctx_release(Ctx& c);
+void apply_op(Ctx& c, int op, int nrhs, const void* in_aos, void* out_aos);
+int solve(Ctx& c, int nrhs, const void* b_aos, void* x_aos, double tol, int mode,
+          eigcg_stats* stats);
+void deflate_init(Ctx& c, int nrhs, const void* b_aos, void* x_aos);
+void bank_info(Ctx& c, int* l, double* vals, double* res);
+void bank_vectors(Ctx& c, int first, int count, void* out_aos);
+int bank_load(Ctx& c, int count, const void* vecs_aos);
+
+}  // namespace eigcg

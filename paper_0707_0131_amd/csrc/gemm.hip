@@ -1,0 +1,319 @@
+// Complex tall-skinny products on the gfx950 matrix cores (MFMA 16x16x4).
+//
+//  * launch_gemm_tall:   Out(n x N) (+)= In(n x K) S(K x N)
+//      eigCG restart V <- V (QZ) (Figure 3.1, step 11.7), Ritz vectors V Y,
+//      the init-CG lift X += U C (eq. (2.1)) and the Gram-Schmidt update
+//      Vbar -= U (U^H Vbar) of the Incremental eigCG bank (Section 4).
+//  * launch_gemm_reduce: G(K x N) = In(n x K)^H R(n x N)
+//      U^H R of init-CG, U^H Vbar / U^H W / Vbar^H W of the bank update and
+//      the arrow row w^H V (step 11.8).
+//
+// Complex arithmetic is embedded in real MFMA tiles.  For the tall product the
+// real K index interleaves (Re, Im) of each input column and the real output
+// columns interleave (Re, Im) of each output column, so the 2x2 real block of
+// S = a + ib is [[a, b], [-b, a]]; lanes 2q and 2q+1 of an accumulator tile
+// then hold Re and Im of the same output element.  For the reduction the
+// conjugate-transpose puts In on the M side: the real block is
+// [[Re R, Im R], [Im R, -Re R]].
+//
+// MFMA lane layout of the 16x16x4 single-block instructions: lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator register r of lane l
+// holds D[4 (l / 16) + r][l % 16] for FP32 and D[l / 16 + 4 r][l % 16] for
+// FP64 (measured by the lane-layout probe, which a unit test runs).
+#include "kernels.h"
+
+namespace eigcg {
+
+namespace {
+
+constexpr int kMaxK = 256;
+constexpr int kMaxN = 24;
+
+struct TallArgs {
+  const void* in[kMaxK];
+  void* out[kMaxN];
+};
+
+template <typename R> struct Mfma;
+template <> struct Mfma<double> {
+  using acc_t = __attribute__((__vector_size__(4 * sizeof(double)))) double;
+  __device__ static __forceinline__ acc_t op(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // row of accumulator register r in lane group g = lane / 16
+  __device__ static __forceinline__ int row(int g, int r) { return g + 4 * r; }
+};
+template <> struct Mfma<float> {
+  using acc_t = __attribute__((__vector_size__(4 * sizeof(float)))) float;
+  __device__ static __forceinline__ acc_t op(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static __forceinline__ int row(int g, int r) { return 4 * g + r; }
+};
+
+// Out rows [row0, row0 + 64) per wave; 4 waves per workgroup.
+template <typename VS, int NT>
+__global__ __launch_bounds__(256) void k_gemm_tall(size_t n, int K, int N, const double2* S,
+                                                   int beta_one, int negate, TallArgs cols) {
+  using R = typename Storage<VS>::real;
+  using M = Mfma<R>;
+  extern __shared__ double2 sS[];  // K x N complex, column-major (ld K)
+  __shared__ const VS* sin[kMaxK];
+  __shared__ R* sout[kMaxN];
+  for (int i = threadIdx.x; i < K * N; i += blockDim.x) {
+    double2 v = S[i];
+    sS[i] = negate ? make_double2(-v.x, -v.y) : v;
+  }
+  for (int i = threadIdx.x; i < K; i += blockDim.x) sin[i] = reinterpret_cast<const VS*>(cols.in[i]);
+  for (int i = threadIdx.x; i < N; i += blockDim.x) sout[i] = reinterpret_cast<R*>(cols.out[i]);
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const size_t row0 = ((size_t)blockIdx.x * 4 + wave) * 64;
+  if (row0 >= n) return;
+  const int li = lane & 15;   // A row within a 16-row subtile / B column within a tile
+  const int lk = lane >> 4;   // real k within the 4-step
+  const int kpart = lk & 1;   // 0: Re, 1: Im of the input entry
+  const int kcol = lk >> 1;   // which of the two complex input columns of the step
+
+  typename M::acc_t acc[4][NT];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[m][t] = typename M::acc_t{};
+
+  for (int k0 = 0; k0 < K; k0 += 2) {
+    const int kc = k0 + kcol;
+    const bool kvalid = kc < K;
+    // A fragments (4 row subtiles)
+    R afrag[4];
+    const VS* src = kvalid ? sin[kc] : nullptr;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const size_t row = row0 + m * 16 + li;
+      R v = R(0);
+      if (kvalid && row < n) {
+        cpx<R> z = Storage<VS>::ld(src, row);
+        v = kpart ? z.im : z.re;
+      }
+      afrag[m] = v;
+    }
+    // B fragments: real column jj = 16 t + li -> output column j = 8 t + li/2, part li&1
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int j = 8 * t + (li >> 1);
+      R bv = R(0);
+      if (kvalid && j < N) {
+        const double2 s = sS[(size_t)j * K + kc];
+        // [[a, b], [-b, a]] with rows (Re-in, Im-in), cols (Re-out, Im-out)
+        if (kpart == 0) bv = (li & 1) ? (R)s.y : (R)s.x;
+        else bv = (li & 1) ? (R)s.x : (R)(-s.y);
+      }
+#pragma unroll
+      for (int m = 0; m < 4; ++m) acc[m][t] = M::op(afrag[m], bv, acc[m][t]);
+    }
+  }
+  // epilogue: register r of the lane holds D[M::row(lane/16, r)][li] of each tile
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int j = 8 * t + (li >> 1);
+    if (j >= N) continue;
+    R* dst = sout[j];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const size_t row = row0 + m * 16 + M::row(lk, r);
+        if (row >= n) continue;
+        R v = acc[m][t][r];
+        R* p = dst + 2 * row + (li & 1);
+        if (beta_one) v += *p;
+        *p = v;
+      }
+    }
+  }
+}
+
+// Reduction product partials: wave handles (row chunk, 16 input columns).
+template <typename VS, int NT>
+__global__ __launch_bounds__(256) void k_gemm_reduce(size_t n, int K, int N, size_t chunk,
+                                                     TallArgs cols, double* partial) {
+  using R = typename Storage<VS>::real;
+  using M = Mfma<R>;
+  __shared__ const VS* sin[kMaxK];
+  __shared__ const VS* sr[kMaxN];
+  for (int i = threadIdx.x; i < K; i += blockDim.x) sin[i] = reinterpret_cast<const VS*>(cols.in[i]);
+  for (int i = threadIdx.x; i < N; i += blockDim.x) sr[i] = reinterpret_cast<const VS*>(cols.out[i]);
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int mtile = blockIdx.y * 4 + wave;
+  const int mtiles = (K + 15) / 16;
+  if (mtile >= mtiles) return;
+  const int li = lane & 15;
+  const int lk = lane >> 4;
+  const int kpart = lk & 1;
+  const int krow = lk >> 1;
+  const int icol = mtile * 16 + li;
+  const VS* a = icol < K ? sin[icol] : nullptr;
+  const size_t r0 = (size_t)blockIdx.x * chunk;
+  size_t r1 = r0 + chunk;
+  if (r1 > n) r1 = n;
+
+  typename M::acc_t acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = typename M::acc_t{};
+
+  for (size_t r = r0; r < r1; r += 2) {
+    const size_t row = r + krow;
+    const bool rv = row < r1;
+    R av = R(0);
+    if (a && rv) {
+      cpx<R> z = Storage<VS>::ld(a, row);
+      av = kpart ? z.im : z.re;
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int j = 8 * t + (li >> 1);
+      R bv = R(0);
+      if (rv && j < N) {
+        cpx<R> z = Storage<VS>::ld(sr[j], row);
+        // [[Re R, Im R], [Im R, -Re R]] with rows (Re-in, Im-in), cols (Re-out, Im-out)
+        if (kpart == 0) bv = (li & 1) ? z.im : z.re;
+        else bv = (li & 1) ? -z.re : z.im;
+      }
+      acc[t] = M::op(av, bv, acc[t]);
+    }
+  }
+  // partial layout: [chunk][i in 0..K)][jj in 0..2N) doubles
+  double* dst = partial + (size_t)blockIdx.x * K * 2 * N;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int jj = 16 * t + li;
+    if (jj >= 2 * N) continue;
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const int i = mtile * 16 + M::row(lk, rr);
+      if (i < K) dst[(size_t)i * 2 * N + jj] = (double)acc[t][rr];
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_gemm_reduce_final(int K, int N, int nchunk,
+                                                           const double* partial, double2* G) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;  // over K*N complex outputs
+  if (idx >= K * N) return;
+  const int i = idx % K, j = idx / K;
+  double re = 0.0, im = 0.0;
+  const size_t stride = (size_t)K * 2 * N;
+  for (int c = 0; c < nchunk; ++c) {
+    const double* p = partial + (size_t)c * stride + (size_t)i * 2 * N + 2 * j;
+    re += p[0];
+    im += p[1];
+  }
+  G[(size_t)j * K + i] = make_double2(re, im);
+}
+
+template <typename VS>
+hipError_t tall_typed(size_t n, int K, int N, const void* const* in_cols, void* const* out_cols,
+                      const double2* S, int beta_one, int negate, hipStream_t s) {
+  TallArgs a;
+  for (int i = 0; i < K; ++i) a.in[i] = in_cols[i];
+  for (int j = 0; j < N; ++j) a.out[j] = out_cols[j];
+  const int nt = (N + 7) / 8;
+  dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  size_t lds = (size_t)K * N * sizeof(double2);
+  if (nt == 1)
+    hipLaunchKernelGGL((k_gemm_tall<VS, 1>), grid, block, lds, s, n, K, N, S, beta_one, negate, a);
+  else if (nt == 2)
+    hipLaunchKernelGGL((k_gemm_tall<VS, 2>), grid, block, lds, s, n, K, N, S, beta_one, negate, a);
+  else
+    hipLaunchKernelGGL((k_gemm_tall<VS, 3>), grid, block, lds, s, n, K, N, S, beta_one, negate, a);
+  return hipGetLastError();
+}
+
+template <typename VS>
+hipError_t reduce_typed(size_t n, int K, int N, const void* const* in_cols,
+                        const void* const* r_cols, double2* partial, size_t partial_elems,
+                        double2* G, hipStream_t s) {
+  TallArgs a;
+  for (int i = 0; i < K; ++i) a.in[i] = in_cols[i];
+  for (int j = 0; j < N; ++j) a.out[j] = const_cast<void*>(r_cols[j]);
+  // chunk so that the partial buffer (nchunk * K * 2N doubles) fits
+  size_t per_chunk = (size_t)K * N;  // double2 elements per chunk
+  size_t max_chunks = partial_elems / per_chunk;
+  if (max_chunks == 0) return hipErrorInvalidValue;
+  size_t want = 1024;
+  if (want > max_chunks) want = max_chunks;
+  size_t chunk = (n + want - 1) / want;
+  if (chunk < 256) chunk = 256;
+  chunk = (chunk + 1) & ~(size_t)1;
+  const int nchunk = (int)((n + chunk - 1) / chunk);
+  const int nt = (N + 7) / 8;
+  dim3 grid(nchunk, ((K + 15) / 16 + 3) / 4), block(256);
+  double* part = reinterpret_cast<double*>(partial);
+  if (nt == 1)
+    hipLaunchKernelGGL((k_gemm_reduce<VS, 1>), grid, block, 0, s, n, K, N, chunk, a, part);
+  else
+    hipLaunchKernelGGL((k_gemm_reduce<VS, 2>), grid, block, 0, s, n, K, N, chunk, a, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int outs = K * N;
+  hipLaunchKernelGGL(k_gemm_reduce_final, dim3((outs + 255) / 256), dim3(256), 0, s, K, N, nchunk,
+                     part, G);
+  return hipGetLastError();
+}
+
+// Lane-layout probe of the 16x16x4 MFMA instructions: two products whose
+// results encode the row index (A[i][0] = i + 1, B[0][j] = 1) and the column
+// index (A[i][0] = 1, B[0][j] = j + 1) of every accumulator entry.
+// out: 64 lanes x 4 registers x 2 (row, column) for FP64, then the same for FP32.
+__global__ void k_mfma_probe(double* out) {
+  const int l = threadIdx.x;
+  const int i = l & 15, k = l >> 4;
+  using A64 = Mfma<double>;
+  using A32 = Mfma<float>;
+  typename A64::acc_t r64 = A64::op(k == 0 ? double(i + 1) : 0.0, k == 0 ? 1.0 : 0.0,
+                                    typename A64::acc_t{});
+  typename A64::acc_t c64 = A64::op(k == 0 ? 1.0 : 0.0, k == 0 ? double(i + 1) : 0.0,
+                                    typename A64::acc_t{});
+  typename A32::acc_t r32 = A32::op(k == 0 ? float(i + 1) : 0.f, k == 0 ? 1.f : 0.f,
+                                    typename A32::acc_t{});
+  typename A32::acc_t c32 = A32::op(k == 0 ? 1.f : 0.f, k == 0 ? float(i + 1) : 0.f,
+                                    typename A32::acc_t{});
+  for (int r = 0; r < 4; ++r) {
+    out[(l * 4 + r) * 2 + 0] = r64[r];
+    out[(l * 4 + r) * 2 + 1] = c64[r];
+    out[512 + (l * 4 + r) * 2 + 0] = (double)r32[r];
+    out[512 + (l * 4 + r) * 2 + 1] = (double)c32[r];
+  }
+}
+
+}  // namespace
+
+hipError_t launch_mfma_probe(double* out_dev, hipStream_t s) {
+  hipLaunchKernelGGL(k_mfma_probe, dim3(1), dim3(64), 0, s, out_dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_tall(int prec, size_t n, int K, int N, const void* const* in_cols,
+                            void* const* out_cols, const double2* S, int beta_one, int negate,
+                            hipStream_t s) {
+  if (K <= 0 || N <= 0 || K > kMaxK || N > kMaxN || (size_t)K * N * 16 > 65536)
+    return hipErrorInvalidValue;
+  if (prec == kF64)
+    return tall_typed<double2>(n, K, N, in_cols, out_cols, S, beta_one, negate, s);
+  return tall_typed<float2>(n, K, N, in_cols, out_cols, S, beta_one, negate, s);
+}
+
+hipError_t launch_gemm_reduce(int prec, size_t n, int K, int N, const void* const* in_cols,
+                              const void* const* r_cols, double2* partial, size_t partial_elems,
+                              double2* G, hipStream_t s) {
+  if (K <= 0 || N <= 0 || K > kMaxK || N > 16) return hipErrorInvalidValue;
+  if (prec == kF64)
+    return reduce_typed<double2>(n, K, N, in_cols, r_cols, partial, partial_elems, G, s);
+  return reduce_typed<float2>(n, K, N, in_cols, r_cols, partial, partial_elems, G, s);
+}
+
+}  // namespace eigcg

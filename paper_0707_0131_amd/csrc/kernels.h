@@ -1,0 +1,127 @@
+// Host-side launchers of the HIP kernels (declarations).  Every launcher
+// enqueues on the given stream and returns hipSuccess or the launch error.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace eigcg {
+
+enum Prec { kF64 = 0, kF32 = 1 };
+enum StencilOp { kOpM = 0, kOpMdag = 1 };
+// epilogues of the stencil launch
+enum StencilEpi {
+  kEpiStore = 0,   // out = op(in)
+  kEpiNorm = 1,    // out = op(in); p^H A p = ||out||^2 -> alpha (CG step 1)
+  kEpiCGR = 2,     // t = op(in); r -= alpha t; r^H r -> beta, stop test (CG step 2)
+  kEpiRes = 3,     // r = b - op(in); r^H r -> rho (true residual)
+};
+
+struct StencilLaunch {
+  int prec;                 // kF64 / kF32 (vectors and links)
+  int op;                   // kOpM / kOpMdag
+  int epi;                  // StencilEpi
+  int compressed;           // links stored as two rows
+  const void* in; size_t in_cs;     // column stride in complex elements
+  void* out; size_t out_cs;         // kEpiStore / kEpiNorm target
+  const void* u;
+  const Geom* g;
+  double diag;              // 4 + m_q
+  int ncols;
+  uint32_t mask;            // columns to process
+  ColState* st;             // per-column state (kEpiNorm / kEpiCGR / kEpiRes)
+  double* partial;          // ncols * kMaxGrid doubles
+  unsigned int* counter;
+  void* r; size_t r_cs;     // kEpiCGR residual, kEpiRes residual output
+  const void* b; size_t b_cs;       // kEpiRes right-hand side
+  void* tbuf; size_t t_cs;  // kEpiCGR: two t slots per column (slot = j & 1)
+  double* hist; int hist_stride;    // kEpiCGR: per column 3 doubles per iteration
+};
+
+hipError_t launch_stencil(const StencilLaunch& L, hipStream_t s);
+
+// CG step 3: x += alpha p; (running) p = r + beta p; optional window append
+// V_ring[(iter + 1) % ring] = r / sqrt(rho).
+struct UpdateLaunch {
+  int prec;
+  int ncols;
+  uint32_t mask;
+  ColState* st;
+  const Geom* g;
+  void* x; size_t x_cs;
+  void* p; size_t p_cs;
+  const void* r; size_t r_cs;
+  void* ring; size_t ring_cs; int ring_len; size_t ring_col_cs;  // slot stride, column stride
+};
+hipError_t launch_cg_update(const UpdateLaunch& L, hipStream_t s);
+
+// Initial CG state: p = r (rho already in st), optional ring slot 1 write;
+// per column: rho = r^H r given by kEpiRes.
+hipError_t launch_cg_start(const UpdateLaunch& L, hipStream_t s);
+
+// After a true-residual computation (kEpiRes): per masked column in state
+// Run, or stopped for a restart, decide converged (rho <= res_stop2),
+// re-deflation (rho <= defl2, reason Restart, defl2 cleared) or running.
+hipError_t launch_post_residual(ColState* st, int ncols, uint32_t mask, hipStream_t s);
+// Set state/reason of masked columns (host-driven transitions).
+hipError_t launch_set_state(ColState* st, int ncols, uint32_t mask, int state, int reason,
+                            int clear_restart, hipStream_t s);
+
+// Layout conversion between the boundary (AoS complex128, [site][spin][colour])
+// and the internal SoA planes; prec selects the internal storage.
+hipError_t launch_spinor_to_soa(const double2* aos, void* soa, int prec, const Geom* g, int ncols,
+                                size_t soa_cs, hipStream_t s);
+hipError_t launch_spinor_from_soa(const void* soa, double2* aos, int prec, const Geom* g,
+                                  int ncols, size_t soa_cs, hipStream_t s);
+// gauge AoS [site][mu][a][b] -> SoA planes (full 9 or compressed 6 per mu)
+hipError_t launch_gauge_to_soa(const double2* aos, void* soa, int prec, int compressed,
+                               const Geom* g, hipStream_t s);
+// max over links of |U U^H - 1| and |det U - 1| (unitarity check), one double each
+hipError_t launch_gauge_check(const double2* aos, const Geom* g, double* out2, hipStream_t s);
+
+// Generic BLAS1 over n complex entries per column (FP64 or FP32 storage).
+// y = a*x + y with per-column complex a (device array of 2*ncols doubles or
+// host scalar when a_dev is null).
+hipError_t launch_axpy(int prec, int ncols, size_t n, const double* a_dev, double a_re,
+                       double a_im, const void* x, size_t x_cs, void* y, size_t y_cs,
+                       hipStream_t s);
+// y = x (with conversion between precisions: src_prec -> dst_prec)
+hipError_t launch_copy(int src_prec, int dst_prec, int ncols, size_t n, const void* x,
+                       size_t x_cs, void* y, size_t y_cs, hipStream_t s);
+// norms2[c] = ||x_c||^2 in FP64, deterministic; partial/counter as for stencils
+hipError_t launch_norm2(int prec, int ncols, size_t n, const void* x, size_t x_cs,
+                        double* partial, unsigned int* counter, double* out, hipStream_t s);
+// y_c *= scale[c] (scale from device, FP64)
+hipError_t launch_scale(int prec, int ncols, size_t n, const double* scale_dev, void* y,
+                        size_t y_cs, hipStream_t s);
+// w = t1 - beta * t0 per column with beta = hist-derived scalar from device
+hipError_t launch_xpby(int prec, int ncols, size_t n, const void* t1, const void* t0,
+                       size_t t_cs, const double* beta_dev, void* w, size_t w_cs,
+                       hipStream_t s);
+// mixed precision accumulation: x64 += (double) e32 ; e32 = 0
+hipError_t launch_accum_f32_into_f64(int ncols, size_t n, void* x64, size_t x_cs, void* e32,
+                                     size_t e_cs, hipStream_t s);
+
+// Tall-skinny products on MFMA (complex):
+//   Out(n x N) = beta*Out + In(n x K) * S(K x N)
+// In columns come from a device array of column pointers (K entries), Out
+// columns likewise (N entries); S is column-major complex FP64 on the device
+// (ld = K).  beta is 0 (overwrite) or 1 (accumulate).  Out may alias In
+// columns (each output row depends only on the same input row).
+hipError_t launch_gemm_tall(int prec, size_t n, int K, int N, const void* const* in_cols,
+                            void* const* out_cols, const double2* S, int beta_one, int negate,
+                            hipStream_t s);
+// Reduction products: G(K x N) = In(n x K)^H * R(n x N), column pointer
+// arrays as above; deterministic two-pass (chunk partials then fixed-order
+// sum); result FP64 complex column-major (ld = K) on the device.
+hipError_t launch_gemm_reduce(int prec, size_t n, int K, int N, const void* const* in_cols,
+                              const void* const* r_cols, double2* partial, size_t partial_elems,
+                              double2* G, hipStream_t s);
+
+// Test support: MFMA lane-layout probe (1024 doubles written to out_dev).
+hipError_t launch_mfma_probe(double* out_dev, hipStream_t s);
+
+}  // namespace eigcg

@@ -1,0 +1,149 @@
+// Wilson-Dirac stencil building blocks (device side).
+//
+//   (M psi)(x) = (4 + m_q) psi(x)
+//                - 1/2 sum_mu [ (1 - g_mu) U_mu(x) psi(x+mu) + (1 + g_mu) U_mu(x-mu)^+ psi(x-mu) ]
+//
+// and M^H, which swaps the two projectors (gamma5-Hermiticity, Section 1 of the
+// paper).  Gamma matrices are Euclidean and chiral: g_mu = [[0, B_mu], [B_mu^H, 0]]
+// with B_k = -i sigma_k (k = x, y, z) and B_t = I, so gamma5 = diag(1, 1, -1, -1).
+//
+// Spin projection: for psi = (u, l) (upper / lower spin pairs) and s = +-1,
+// (1 + s g_mu) psi = (h, s B_mu^H h) with h = u + s B_mu l, because B_mu is
+// unitary.  A hop therefore loads the neighbour spinor, forms the 2x3 half
+// spinor h, applies the 3x3 link to its two spin rows and rebuilds the lower
+// half from the upper one: 2 SU(3) mat-vecs instead of 4.
+#pragma once
+
+#include "common.h"
+
+namespace eigcg {
+
+// h = u + s B_mu l for one colour (spin components c0..c3 of the neighbour).
+template <int MU, int S, typename R>
+__device__ __forceinline__ void project(const cpx<R> u0, const cpx<R> u1, const cpx<R> l0,
+                                        const cpx<R> l1, cpx<R>& h0, cpx<R>& h1) {
+  cpx<R> b0, b1;  // B_mu l
+  if (MU == 0) { b0 = cmi(l1); b1 = cmi(l0); }
+  else if (MU == 1) { b0 = cneg(l1); b1 = l0; }
+  else if (MU == 2) { b0 = cmi(l0); b1 = ci(l1); }
+  else { b0 = l0; b1 = l1; }
+  if (S > 0) { h0 = cadd(u0, b0); h1 = cadd(u1, b1); }
+  else { h0 = csub(u0, b0); h1 = csub(u1, b1); }
+}
+
+// acc += (g, s B_mu^H g) for one colour.
+template <int MU, int S, typename R>
+__device__ __forceinline__ void accumulate(cpx<R>* acc, int a, const cpx<R> g0, const cpx<R> g1) {
+  cpx<R> d0, d1;  // B_mu^H g
+  if (MU == 0) { d0 = ci(g1); d1 = ci(g0); }
+  else if (MU == 1) { d0 = g1; d1 = cneg(g0); }
+  else if (MU == 2) { d0 = ci(g0); d1 = cmi(g1); }
+  else { d0 = g0; d1 = g1; }
+  acc[0 * 3 + a] = cadd(acc[0 * 3 + a], g0);
+  acc[1 * 3 + a] = cadd(acc[1 * 3 + a], g1);
+  if (S > 0) {
+    acc[2 * 3 + a] = cadd(acc[2 * 3 + a], d0);
+    acc[3 * 3 + a] = cadd(acc[3 * 3 + a], d1);
+  } else {
+    acc[2 * 3 + a] = csub(acc[2 * 3 + a], d0);
+    acc[3 * 3 + a] = csub(acc[3 * 3 + a], d1);
+  }
+}
+
+// Load link U_mu(site) as 9 complex numbers (row-major [a][b]).
+template <typename LS, bool COMP>
+__device__ __forceinline__ void load_link(const LS* __restrict__ u, int mu, size_t vs,
+                                          uint32_t site, cpx<typename Storage<LS>::real>* U) {
+  using R = typename Storage<LS>::real;
+  if (!COMP) {
+#pragma unroll
+    for (int e = 0; e < 9; ++e) U[e] = Storage<LS>::ld(u, (size_t)(mu * 9 + e) * vs + site);
+  } else {
+#pragma unroll
+    for (int e = 0; e < 6; ++e) U[e] = Storage<LS>::ld(u, (size_t)(mu * 6 + e) * vs + site);
+    // third row = conj(row0 x row1) for a special unitary matrix
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const int b1 = (b + 1) % 3, b2 = (b + 2) % 3;
+      cpx<R> t = csub(cmul(U[b1], U[3 + b2]), cmul(U[b2], U[3 + b1]));
+      U[6 + b] = {t.re, -t.im};
+    }
+  }
+}
+
+// Hopping sum for one site: acc = sum_mu [(1 + sf g_mu) U_mu(x) psi(x+mu)
+// + (1 - sf g_mu) U_mu(x-mu)^+ psi(x-mu)], sf = -1 for M, +1 for M^H.
+template <typename VS, typename LS, bool COMP, int SF>
+__device__ __forceinline__ void hopping_site(const VS* __restrict__ in,
+                                             const LS* __restrict__ u, const Geom& g,
+                                             uint32_t s, cpx<typename Storage<VS>::real>* acc) {
+  using R = typename Storage<VS>::real;
+  const size_t vs = (size_t)g.vs;
+  const uint32_t xyz = g.dx.div(s);
+  const uint32_t x = s - xyz * (uint32_t)g.L[0];
+  const uint32_t zt = g.dy.div(xyz);
+  const uint32_t y = xyz - zt * (uint32_t)g.L[1];
+  const uint32_t t = g.dz.div(zt);
+  const uint32_t z = zt - t * (uint32_t)g.L[2];
+  const uint32_t coord[4] = {x, y, z, t};
+#pragma unroll
+  for (int e = 0; e < 12; ++e) acc[e] = {R(0), R(0)};
+
+#define EIGCG_HOP(MU)                                                                        \
+  {                                                                                          \
+    const uint32_t c_ = coord[MU];                                                           \
+    const uint32_t st_ = (uint32_t)g.stride[MU];                                             \
+    const uint32_t span_ = (uint32_t)(g.L[MU] - 1) * st_;                                    \
+    const uint32_t sf_ = (c_ + 1 < (uint32_t)g.L[MU]) ? s + st_ : s - span_;                 \
+    const uint32_t sb_ = (c_ > 0) ? s - st_ : s + span_;                                     \
+    {                                                                                        \
+      cpx<R> U[9];                                                                           \
+      load_link<LS, COMP>(u, MU, vs, s, U);                                                  \
+      cpx<R> h[6];                                                                           \
+      _Pragma("unroll") for (int a = 0; a < 3; ++a) {                                        \
+        cpx<R> u0 = Storage<VS>::ld(in, (size_t)(0 + a) * vs + sf_);                         \
+        cpx<R> u1 = Storage<VS>::ld(in, (size_t)(3 + a) * vs + sf_);                         \
+        cpx<R> l0 = Storage<VS>::ld(in, (size_t)(6 + a) * vs + sf_);                         \
+        cpx<R> l1 = Storage<VS>::ld(in, (size_t)(9 + a) * vs + sf_);                         \
+        project<MU, SF>(u0, u1, l0, l1, h[a], h[3 + a]);                                     \
+      }                                                                                      \
+      _Pragma("unroll") for (int a = 0; a < 3; ++a) {                                        \
+        cpx<R> g0 = cmul(U[a * 3 + 0], h[0]);                                                \
+        cpx<R> g1 = cmul(U[a * 3 + 0], h[3]);                                                \
+        g0 = cadd(g0, cmul(U[a * 3 + 1], h[1]));                                             \
+        g1 = cadd(g1, cmul(U[a * 3 + 1], h[4]));                                             \
+        g0 = cadd(g0, cmul(U[a * 3 + 2], h[2]));                                             \
+        g1 = cadd(g1, cmul(U[a * 3 + 2], h[5]));                                             \
+        accumulate<MU, SF>(acc, a, g0, g1);                                                  \
+      }                                                                                      \
+    }                                                                                        \
+    {                                                                                        \
+      cpx<R> U[9];                                                                           \
+      load_link<LS, COMP>(u, MU, vs, sb_, U);                                                \
+      cpx<R> h[6];                                                                           \
+      _Pragma("unroll") for (int a = 0; a < 3; ++a) {                                        \
+        cpx<R> u0 = Storage<VS>::ld(in, (size_t)(0 + a) * vs + sb_);                         \
+        cpx<R> u1 = Storage<VS>::ld(in, (size_t)(3 + a) * vs + sb_);                         \
+        cpx<R> l0 = Storage<VS>::ld(in, (size_t)(6 + a) * vs + sb_);                         \
+        cpx<R> l1 = Storage<VS>::ld(in, (size_t)(9 + a) * vs + sb_);                         \
+        project<MU, -SF>(u0, u1, l0, l1, h[a], h[3 + a]);                                    \
+      }                                                                                      \
+      _Pragma("unroll") for (int a = 0; a < 3; ++a) {                                        \
+        cpx<R> g0 = cmulc(U[0 * 3 + a], h[0]);                                               \
+        cpx<R> g1 = cmulc(U[0 * 3 + a], h[3]);                                               \
+        g0 = cadd(g0, cmulc(U[1 * 3 + a], h[1]));                                            \
+        g1 = cadd(g1, cmulc(U[1 * 3 + a], h[4]));                                            \
+        g0 = cadd(g0, cmulc(U[2 * 3 + a], h[2]));                                            \
+        g1 = cadd(g1, cmulc(U[2 * 3 + a], h[5]));                                            \
+        accumulate<MU, -SF>(acc, a, g0, g1);                                                 \
+      }                                                                                      \
+    }                                                                                        \
+  }
+  EIGCG_HOP(0)
+  EIGCG_HOP(1)
+  EIGCG_HOP(2)
+  EIGCG_HOP(3)
+#undef EIGCG_HOP
+}
+
+}  // namespace eigcg

@@ -1,0 +1,68 @@
+"""GPU unit tests of the MFMA products against plain numpy products.
+
+The complex tall-skinny products of the library (restart V (QZ), Ritz vectors,
+U C, U^H R) run on the 16x16x4 matrix-core instructions; the lane-layout probe
+pins the register layout they rely on, the products are then compared element
+by element with numpy in FP64 (1e-13) and FP32 (1e-5, relative to the norms).
+"""
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0707_0131_amd import binding
+    return binding
+
+
+def test_mfma_lane_layout(B):
+    out = B.eigcg_debug_mfma_probe()
+    for base, name in [(0, "f64"), (512, "f32")]:
+        got = {}
+        for lane in range(64):
+            for r in range(4):
+                row = int(round(out[base + (lane * 4 + r) * 2])) - 1
+                col = int(round(out[base + (lane * 4 + r) * 2 + 1])) - 1
+                got[(lane, r)] = (row, col)
+        if name == "f32":
+            expect = {(l, r): (4 * (l // 16) + r, l % 16) for l in range(64) for r in range(4)}
+        else:
+            expect = {(l, r): (l // 16 + 4 * r, l % 16) for l in range(64) for r in range(4)}
+        bad = [(k, got[k], expect[k]) for k in expect if got[k] != expect[k]]
+        assert not bad, f"{name} layout differs, first: {bad[:6]}"
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("n,K,N", [(1000, 1, 1), (3072, 7, 5), (1024, 40, 20), (777, 33, 24)])
+def test_gemm_tall(B, dt, n, K, N):
+    import torch
+    rng = np.random.default_rng(K * 100 + N)
+    cdt = np.complex128 if dt == "c128" else np.complex64
+    A = (rng.standard_normal((K, n)) + 1j * rng.standard_normal((K, n))).astype(cdt)
+    S = rng.standard_normal((K, N)) + 1j * rng.standard_normal((K, N))
+    out = B.eigcg_debug_gemm(0, torch.from_numpy(A).to("cuda:0"),
+                             s=torch.from_numpy(S).to("cuda:0"))
+    ref = (A.astype(np.complex128).T @ S).T
+    tol = 1e-13 if dt == "c128" else 2e-6
+    assert np.max(np.abs(out - ref)) <= tol * np.max(np.abs(ref)) * np.sqrt(K)
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("n,K,N", [(1000, 1, 1), (3072, 20, 1), (1024, 40, 12), (4097, 17, 16)])
+def test_gemm_reduce(B, dt, n, K, N):
+    import torch
+    rng = np.random.default_rng(K * 7 + N)
+    cdt = np.complex128 if dt == "c128" else np.complex64
+    A = (rng.standard_normal((K, n)) + 1j * rng.standard_normal((K, n))).astype(cdt)
+    R = (rng.standard_normal((N, n)) + 1j * rng.standard_normal((N, n))).astype(cdt)
+    out = B.eigcg_debug_gemm(1, torch.from_numpy(A).to("cuda:0"),
+                             r=torch.from_numpy(R).to("cuda:0"))
+    ref = A.astype(np.complex128).conj() @ R.astype(np.complex128).T
+    tol = 1e-13 if dt == "c128" else 2e-6
+    assert np.max(np.abs(out - ref)) <= tol * np.sqrt(n) * 2
