@@ -1,0 +1,280 @@
+"""Benchmark of the eigCG hot path on one MI355X.
+
+Workload (one step = one quark mass): 16^3 x 32 Wilson lattice, synthetic
+SU(3) links exp(i 0.5 H) (seed 1), FP64, single-RHS launches:
+  phase 1: Incremental eigCG(10, 100) on 24 Gaussian right-hand sides (the bank
+           grows to 240 vectors);
+  phase 2: init-CG deflated by the 240 vectors on 100 more right-hand sides;
+every solve to FP64 true relative residual <= 1e-10.  Steps cycle over three
+masses approaching the critical one.  `value` = right-hand sides solved per
+second over the timed steps (phase 1 and 2 together, bank building amortised
+as in the paper's phase accounting).  Extra fields give plain FP64 CG on a
+sample of the same right-hand sides (the speed-up baseline), the stencil's
+achieved bandwidth against the HBM roofline (dominant kernel) and the CPU
+oracle timed on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+LATTICE = (16, 16, 16, 32)
+EPS, SEED = 0.5, 1
+MASSES = (-0.40, -0.50, -0.55)
+NEV, M, NBANK = 10, 100, 240
+N_EIG, N_DEFL = 24, 100
+TOL = 1e-10
+HBM_LATTICE, HBM_SEED = (24, 24, 24, 48), 3
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def site_bytes_stencil(two_row_links: bool, elem=16):
+    # spinor in + links as stored + spinor out, each read/written once per site
+    links = 4 * (6 if two_row_links else 9) * elem
+    return 12 * elem + links + 12 * elem
+
+
+def run_step(B, torch, g, mass, bt, xt):
+    p = B.eigcg_default_params(dims=LATTICE, mass=mass, nev=NEV, m=M, max_bank=NBANK,
+                               max_iter=40000, check_every=16)
+    ctx = B.eigcg_create(p, g)
+    try:
+        xt.zero_()
+        t0 = time.perf_counter()
+        rc1, st1 = B.eigcg_solve(ctx, bt[:N_EIG], xt[:N_EIG], TOL, B.EIGCG_MODE_EIGCG)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rc2, st2 = B.eigcg_solve(ctx, bt[N_EIG:], xt[N_EIG:], TOL, B.EIGCG_MODE_INITCG)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        vals, _ = B.eigcg_bank_info(ctx)
+    finally:
+        B.eigcg_destroy(ctx)
+    bad = [s for s in st1 + st2 if s["status"] != 0 or s["true_rel_res"] > TOL]
+    return {
+        "mass": mass,
+        "phase1_s": t1 - t0,
+        "phase2_s": t2 - t1,
+        "phase1_iters": [s["iters"] for s in st1],
+        "phase2_iters": [s["iters"] for s in st2],
+        "max_true_rel_res": max(s["true_rel_res"] for s in st1 + st2),
+        "failed": len(bad),
+        "bank_lambda_min": float(vals[0]) if len(vals) else None,
+        "bank_size": int(len(vals)),
+    }
+
+
+def plain_cg(B, torch, g, mass, bt, xt, n):
+    p = B.eigcg_default_params(dims=LATTICE, mass=mass, max_iter=40000, check_every=32)
+    ctx = B.eigcg_create(p, g)
+    try:
+        xt[:n].zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, st = B.eigcg_solve(ctx, bt[:n], xt[:n], TOL, B.EIGCG_MODE_CG)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    finally:
+        B.eigcg_destroy(ctx)
+    return dt, [s["iters"] for s in st], max(s["true_rel_res"] for s in st)
+
+
+def stencil_roofline(B, torch, dims, seed, reps):
+    from synthetic import gauge_field
+    U = gauge_field(dims, EPS, seed)
+    g = torch.from_numpy(U).to("cuda:0")
+    del U
+    p = B.eigcg_default_params(dims=dims, mass=-0.5, max_bank=0)
+    ctx = B.eigcg_create(p, g)
+    try:
+        info = B.eigcg_layout_info(ctx)
+        ms_m = B.eigcg_time_kernel(ctx, 0, reps)
+        ms_r = B.eigcg_time_kernel(ctx, 1, reps)
+        ms_it = B.eigcg_time_kernel(ctx, 2, max(1, reps // 4))
+    finally:
+        B.eigcg_destroy(ctx)
+    V = info["sites"]
+    bytes_m = V * site_bytes_stencil(info["links64_two_rows"])
+    bytes_r = bytes_m + V * 192  # + read of r (r is the written output)
+    return {
+        "sites": V,
+        "two_row_links": info["links64_two_rows"],
+        "stencil_M_ms": ms_m,
+        "stencil_M_GBs": bytes_m / ms_m / 1e6,
+        "stencil_Mdag_cgr_ms": ms_r,
+        "stencil_Mdag_cgr_GBs": bytes_r / ms_r / 1e6,
+        "cg_iteration_ms": ms_it,
+        "bytes_per_launch_M": bytes_m,
+    }
+
+
+def cpu_baseline(total_rhs, total_iters, budget_s=20.0):
+    """Oracle CG on the bench lattice for a bounded number of iterations."""
+    import numpy as np
+    from oracle.dirac import WilsonOperator
+    from synthetic import gauge_field, gaussian_rhs
+    U = gauge_field(LATTICE, EPS, SEED)
+    op = WilsonOperator(U, MASSES[0])
+    b = gaussian_rhs(LATTICE, 1000).reshape(-1)
+    from oracle.cg import cg
+    t0 = time.perf_counter()
+    n = 0
+    # one iteration first to size the sample to the budget
+    cg(op.A, b, tol=0.0, max_iter=1, true_residual_restarts=0)
+    one = time.perf_counter() - t0
+    n_it = max(2, min(40, int(budget_s / max(one, 1e-3))))
+    t0 = time.perf_counter()
+    cg(op.A, b, tol=0.0, max_iter=n_it, true_residual_restarts=0)
+    dt = time.perf_counter() - t0
+    # cg() also applies A once for r0 and once for the final true residual
+    per_iter = dt / (n_it + 2)
+    rhs_per_s = total_rhs / (total_iters * per_iter)
+    return {"value": rhs_per_s, "unit": "RHS/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_it} FP64 CG iterations of the NumPy oracle on the 16^3x32 lattice "
+                      f"({per_iter:.3f} s per iteration incl. A = M^H M); RHS/s extrapolated "
+                      f"with the GPU run's {total_iters} iterations for {total_rhs} RHS"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--baseline-rhs", type=int, default=4)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              f"(this build runs on a single MI355X)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_0707_0131_amd import binding as B
+    from synthetic import gauge_field, gaussian_rhs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    log(f"generating {LATTICE} links and {N_EIG + N_DEFL} right-hand sides")
+    U = gauge_field(LATTICE, EPS, SEED)
+    g = torch.from_numpy(U).to("cuda:0")
+    del U
+    nrhs = N_EIG + N_DEFL
+    shape = (LATTICE[3], LATTICE[2], LATTICE[1], LATTICE[0], 4, 3)
+    bt = torch.empty((nrhs,) + shape, dtype=torch.complex128, device="cuda:0")
+    for i in range(nrhs):
+        bt[i].copy_(torch.from_numpy(gaussian_rhs(LATTICE, 1000 + i)))
+    xt = torch.zeros_like(bt)
+    torch.cuda.synchronize()
+
+    for w in range(args.warmup):
+        log(f"warmup step {w}")
+        run_step(B, torch, g, MASSES[w % len(MASSES)], bt, xt)
+
+    steps = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        r = run_step(B, torch, g, MASSES[k % len(MASSES)], bt, xt)
+        steps.append(r)
+        log(f"step {k}: mass {r['mass']} phase1 {r['phase1_s']:.2f}s "
+            f"(iters {r['phase1_iters'][0]}..{r['phase1_iters'][-1]}) phase2 {r['phase2_s']:.2f}s "
+            f"(mean iters {sum(r['phase2_iters']) / len(r['phase2_iters']):.0f}) "
+            f"max res {r['max_true_rel_res']:.1e} failed {r['failed']}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    total_rhs = nrhs * args.steps
+    value = total_rhs / elapsed
+
+    # plain FP64 CG on a sample of the same right-hand sides, same masses
+    base = []
+    for k in range(min(args.steps, len(MASSES))):
+        mass = MASSES[k]
+        dt, its, res = plain_cg(B, torch, g, mass, bt[N_EIG:], xt[N_EIG:], args.baseline_rhs)
+        base.append({"mass": mass, "s_per_rhs": dt / args.baseline_rhs, "iters": its,
+                     "max_true_rel_res": res})
+        log(f"plain CG mass {mass}: {dt / args.baseline_rhs:.3f} s/RHS, iters {its}")
+    # per-mass RHS/s of the deflated workload vs plain CG
+    per_mass = []
+    for k, s in enumerate(steps[: len(base)]):
+        defl = nrhs / (s["phase1_s"] + s["phase2_s"])
+        plain = 1.0 / base[k]["s_per_rhs"]
+        per_mass.append({"mass": s["mass"], "deflated_rhs_per_s": defl, "plain_cg_rhs_per_s": plain,
+                         "speedup": defl / plain,
+                         "phase2_rhs_per_s": N_DEFL / s["phase2_s"],
+                         "phase2_speedup": (N_DEFL / s["phase2_s"]) / plain})
+    plain_all = len(base) / sum(b["s_per_rhs"] for b in base)
+
+    log("stencil roofline (bench lattice, MALL-resident)")
+    roof_small = stencil_roofline(B, torch, LATTICE, SEED, 200)
+    del g
+    torch.cuda.empty_cache()
+    log(f"stencil roofline ({HBM_LATTICE}, working set above the 256 MB MALL)")
+    roof_hbm = stencil_roofline(B, torch, HBM_LATTICE, HBM_SEED, 100)
+
+    total_iters = sum(sum(s["phase1_iters"]) + sum(s["phase2_iters"]) for s in steps)
+    cpu = None
+    if not args.no_cpu:
+        log("CPU oracle baseline (bounded sample)")
+        cpu = cpu_baseline(total_rhs, total_iters)
+
+    achieved = roof_hbm["stencil_M_GBs"]
+    out = {
+        "metric": "deflated RHS solves/sec at 1e-10 rel. residual vs plain CG; stencil HBM GB/s; p99",
+        "value": value,
+        "unit": "RHS/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1000.0 * elapsed / max(1, args.steps),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "Incremental eigCG(10,100) on 24 RHS + init-CG (240 vectors) on 100 RHS, "
+                        "16^3x32 Wilson, synthetic SU(3) links eps 0.5, FP64 single-RHS, tol 1e-10",
+            "lattice": list(LATTICE),
+            "masses": list(MASSES),
+            "rhs_per_step": nrhs,
+        },
+        "plain_cg_rhs_per_s": plain_all,
+        "speedup_vs_plain_cg": value / plain_all,
+        "per_mass": per_mass,
+        "steps_detail": [{k: v for k, v in s.items() if k not in ("phase1_iters", "phase2_iters")}
+                         | {"phase1_iters": s["phase1_iters"],
+                            "phase2_mean_iters": sum(s["phase2_iters"]) / len(s["phase2_iters"])}
+                         for s in steps],
+        "plain_cg": base,
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "FP64 Wilson stencil M (k_wilson, store epilogue) on "
+                      f"{'x'.join(map(str, HBM_LATTICE))}",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+        },
+        "stencil_bench_lattice": roof_small,
+        "stencil_hbm_lattice": roof_hbm,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -149,6 +149,18 @@ int eigcg_bank_reset(eigcg_ctx* ctx);
 /* Bytes of device memory the context holds. */
 int eigcg_memory(eigcg_ctx* ctx, uint64_t* bytes);
 
+/* info[0] = lattice sites V, info[1] = padded plane stride, info[2] = 1 when
+ * the FP64 links are stored as two rows (12 reals), info[3] likewise for the
+ * FP32 links of a mixed-precision context. */
+int eigcg_layout_info(eigcg_ctx* ctx, int32_t* info);
+
+/* Average device time (ms) of one launch, from HIP events on the context's
+ * stream around reps back-to-back launches: what 0 = FP64 stencil M, 1 = FP64
+ * stencil M^H fused with the CG residual update and its reduction, 2 = one
+ * full FP64 CG iteration (three kernels), 3 = FP32 stencil M (mixed contexts).
+ * Runs on the context's internal work vectors (their contents change). */
+int eigcg_time_kernel(eigcg_ctx* ctx, int32_t what, int32_t reps, double* ms);
+
 const char* eigcg_last_error(const eigcg_ctx* ctx);
 
 /* ---- serving: continuous batching over several contexts --------------------

@@ -84,6 +84,8 @@ SIGNATURES = {
     "eigcg_bank_reset": (_I32, [_VP]),
     "eigcg_memory": (_I32, [_VP, ctypes.POINTER(ctypes.c_uint64)]),
     "eigcg_last_error": (ctypes.c_char_p, [_VP]),
+    "eigcg_layout_info": (_I32, [_VP, ctypes.POINTER(_I32)]),
+    "eigcg_time_kernel": (_I32, [_VP, _I32, _I32, _DP]),
     "eigcg_server_create": (_I32, [ctypes.c_uint64, ctypes.POINTER(_VP)]),
     "eigcg_server_add": (_I32, [_VP, _VP, ctypes.POINTER(_I32)]),
     "eigcg_submit": (_I32, [_VP, _I32, _VP, _VP, ctypes.c_double, ctypes.POINTER(ctypes.c_uint64)]),
@@ -250,6 +252,21 @@ def eigcg_memory(ctx):
     b = ctypes.c_uint64()
     LIB.eigcg_memory(ctx, ctypes.byref(b))
     return b.value
+
+
+def eigcg_layout_info(ctx):
+    info = (_I32 * 4)()
+    LIB.eigcg_layout_info(ctx, info)
+    return {"sites": info[0], "plane_stride": info[1], "links64_two_rows": bool(info[2]),
+            "links32_two_rows": bool(info[3])}
+
+
+def eigcg_time_kernel(ctx, what, reps):
+    ms = ctypes.c_double()
+    rc = LIB.eigcg_time_kernel(ctx, int(what), int(reps), ctypes.byref(ms))
+    if rc != EIGCG_OK:
+        raise EigcgError(rc, eigcg_last_error(ctx))
+    return ms.value
 
 
 # ---- serving ----------------------------------------------------------------

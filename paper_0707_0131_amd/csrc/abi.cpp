@@ -14,9 +14,6 @@ using eigcg::ApiError;
 using eigcg::Ctx;
 using eigcg::HipError;
 
-struct eigcg_ctx {
-  Ctx c;
-};
 
 namespace {
 
@@ -211,6 +208,23 @@ int eigcg_memory(eigcg_ctx* ctx, uint64_t* bytes) {
   if (!ctx || !bytes) return EIGCG_EINVAL;
   *bytes = ctx->c.bytes;
   return EIGCG_OK;
+}
+
+int eigcg_layout_info(eigcg_ctx* ctx, int32_t* info) {
+  if (!ctx || !info) return EIGCG_EINVAL;
+  info[0] = ctx->c.g.V;
+  info[1] = ctx->c.g.vs;
+  info[2] = ctx->c.comp64;
+  info[3] = ctx->c.comp32;
+  return EIGCG_OK;
+}
+
+int eigcg_time_kernel(eigcg_ctx* ctx, int32_t what, int32_t reps, double* ms) {
+  if (!ctx || !ms || reps < 1 || what < 0 || what > 3) return EIGCG_EINVAL;
+  return guarded(ctx, [&] {
+    *ms = eigcg::bench_kernels(ctx->c, what, reps);
+    return EIGCG_OK;
+  });
 }
 
 const char* eigcg_last_error(const eigcg_ctx* ctx) {

@@ -209,9 +209,10 @@ __global__ __launch_bounds__(kBlock) void k_axpy(size_t n, const double* a_dev, 
 
 template <typename SS, typename DS>
 __global__ __launch_bounds__(kBlock) void k_copy(size_t n, const SS* x, size_t x_cs, DS* y,
-                                                 size_t y_cs) {
+                                                 size_t y_cs, uint32_t mask) {
   using R = typename Storage<DS>::real;
   const int col = blockIdx.y;
+  if (!((mask >> col) & 1u)) return;
   const SS* xc = x + (size_t)col * x_cs;
   DS* yc = y + (size_t)col * y_cs;
   for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
@@ -272,8 +273,9 @@ __global__ __launch_bounds__(kBlock) void k_xpby(size_t n, const VS* t1, const V
 }
 
 __global__ __launch_bounds__(kBlock) void k_accum(size_t n, double2* x, size_t x_cs, float2* e,
-                                                  size_t e_cs) {
+                                                  size_t e_cs, uint32_t mask) {
   const int col = blockIdx.y;
+  if (!((mask >> col) & 1u)) return;
   double2* xc = x + (size_t)col * x_cs;
   float2* ec = e + (size_t)col * e_cs;
   for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
@@ -290,18 +292,15 @@ __global__ void k_post_residual(ColState* st, int ncols, uint32_t mask) {
   const int c = threadIdx.x;
   if (c >= ncols || !((mask >> c) & 1u)) return;
   ColState& S = st[c];
-  const bool waiting = S.state == ColStopPending && S.reason == ReasonRestart;
+  const bool waiting = S.state != ColRun && S.reason == ReasonRestart;
   if (S.state != ColRun && !waiting) return;
   if (S.rho <= S.res_stop2) {
     S.state = ColStopped;
     S.reason = ReasonConverged;
-  } else if (S.rho <= S.defl2) {
-    S.defl2 = 0.0;
-    S.state = ColStopped;
-    S.reason = ReasonRestart;
   } else {
     S.state = ColRun;
     S.reason = ReasonNone;
+    if (S.inner_rel2 > 0.0) S.restart2 = fmax(S.inner_rel2 * S.rho, 0.25 * S.res_stop2);
   }
 }
 
@@ -403,20 +402,20 @@ hipError_t launch_axpy(int prec, int ncols, size_t n, const double* a_dev, doubl
 }
 
 hipError_t launch_copy(int src_prec, int dst_prec, int ncols, size_t n, const void* x,
-                       size_t x_cs, void* y, size_t y_cs, hipStream_t s) {
+                       size_t x_cs, void* y, size_t y_cs, hipStream_t s, uint32_t mask) {
   dim3 grid(grid_for(n), ncols);
   if (src_prec == kF64 && dst_prec == kF64)
     hipLaunchKernelGGL((k_copy<double2, double2>), grid, dim3(kBlock), 0, s, n, (const double2*)x,
-                       x_cs, (double2*)y, y_cs);
+                       x_cs, (double2*)y, y_cs, mask);
   else if (src_prec == kF64)
     hipLaunchKernelGGL((k_copy<double2, float2>), grid, dim3(kBlock), 0, s, n, (const double2*)x,
-                       x_cs, (float2*)y, y_cs);
+                       x_cs, (float2*)y, y_cs, mask);
   else if (dst_prec == kF64)
     hipLaunchKernelGGL((k_copy<float2, double2>), grid, dim3(kBlock), 0, s, n, (const float2*)x,
-                       x_cs, (double2*)y, y_cs);
+                       x_cs, (double2*)y, y_cs, mask);
   else
     hipLaunchKernelGGL((k_copy<float2, float2>), grid, dim3(kBlock), 0, s, n, (const float2*)x,
-                       x_cs, (float2*)y, y_cs);
+                       x_cs, (float2*)y, y_cs, mask);
   return hipGetLastError();
 }
 
@@ -456,10 +455,10 @@ hipError_t launch_xpby(int prec, int ncols, size_t n, const void* t1, const void
 }
 
 hipError_t launch_accum_f32_into_f64(int ncols, size_t n, void* x64, size_t x_cs, void* e32,
-                                     size_t e_cs, hipStream_t s) {
+                                     size_t e_cs, hipStream_t s, uint32_t mask) {
   dim3 grid(grid_for(n), ncols);
   hipLaunchKernelGGL(k_accum, grid, dim3(kBlock), 0, s, n, (double2*)x64, x_cs, (float2*)e32,
-                     e_cs);
+                     e_cs, mask);
   return hipGetLastError();
 }
 

@@ -61,7 +61,8 @@ struct ColState {
   double restart2;  // recursive r^H r at or below this: stop for a host-driven
                     // restart (init-CG re-deflation, mixed-precision update)
   double res_stop2; // true-residual r^H r at or below this: converged
-  double defl2;     // true-residual r^H r at or below this: re-deflate once
+  double inner_rel2;// iterative refinement: after a true residual rho, the inner
+                    // solve stops at restart2 = max(inner_rel2 rho, res_stop2 / 4)
   int iter;         // completed iterations
   int max_iter;
   int state;        // ColRun / ColStopPending / ColStopped

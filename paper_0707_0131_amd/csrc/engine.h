@@ -64,7 +64,7 @@ struct Ctx {
   double amax = 0.0;      // largest Ritz value seen (norm of A estimate)
   // scratch
   ColState* d_st = nullptr;
-  ColState* h_st = nullptr;        // pinned, 2 x kMaxCols (double-buffered polls)
+  ColState* h_st = nullptr;        // pinned: 2 x kMaxCols polls, kMaxCols upload slots
   double* d_hist = nullptr;
   double* h_hist = nullptr;        // pinned mirror
   int hist_stride = 0;             // doubles per column
@@ -100,5 +100,28 @@ void deflate_init(Ctx& c, int nrhs, const void* b_aos, void* x_aos);
 void bank_info(Ctx& c, int* l, double* vals, double* res);
 void bank_vectors(Ctx& c, int first, int count, void* out_aos);
 int bank_load(Ctx& c, int count, const void* vecs_aos);
+double bench_kernels(Ctx& c, int what, int reps);
+
+// Serving sessions (continuous batching over max_batch slots of one context).
+struct Session;
+struct SessionDone {
+  uint64_t tag;
+  int status;
+  int iters;
+  int outer;
+  double true_rel_res;
+};
+Session* session_open(Ctx& c);
+int session_free_slot(Session* s);
+int session_active(Session* s);
+int session_admit(Session* s, const void* b_aos, void* x_aos, double tol, uint64_t tag,
+                  std::vector<SessionDone>& done);
+void session_step(Session* s, std::vector<SessionDone>& done);
+void session_close(Session* s);
 
 }  // namespace eigcg
+
+// The opaque handle of the C ABI.
+struct eigcg_ctx {
+  eigcg::Ctx c;
+};

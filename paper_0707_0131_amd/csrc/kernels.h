@@ -63,8 +63,8 @@ hipError_t launch_cg_update(const UpdateLaunch& L, hipStream_t s);
 hipError_t launch_cg_start(const UpdateLaunch& L, hipStream_t s);
 
 // After a true-residual computation (kEpiRes): per masked column in state
-// Run, or stopped for a restart, decide converged (rho <= res_stop2),
-// re-deflation (rho <= defl2, reason Restart, defl2 cleared) or running.
+// Run, or stopped for a restart, decide converged (rho <= res_stop2) or
+// running again (with the refinement's next inner stop when inner_rel2 > 0).
 hipError_t launch_post_residual(ColState* st, int ncols, uint32_t mask, hipStream_t s);
 // Set state/reason of masked columns (host-driven transitions).
 hipError_t launch_set_state(ColState* st, int ncols, uint32_t mask, int state, int reason,
@@ -90,7 +90,8 @@ hipError_t launch_axpy(int prec, int ncols, size_t n, const double* a_dev, doubl
                        hipStream_t s);
 // y = x (with conversion between precisions: src_prec -> dst_prec)
 hipError_t launch_copy(int src_prec, int dst_prec, int ncols, size_t n, const void* x,
-                       size_t x_cs, void* y, size_t y_cs, hipStream_t s);
+                       size_t x_cs, void* y, size_t y_cs, hipStream_t s,
+                       uint32_t mask = 0xffffffffu);
 // norms2[c] = ||x_c||^2 in FP64, deterministic; partial/counter as for stencils
 hipError_t launch_norm2(int prec, int ncols, size_t n, const void* x, size_t x_cs,
                         double* partial, unsigned int* counter, double* out, hipStream_t s);
@@ -103,7 +104,7 @@ hipError_t launch_xpby(int prec, int ncols, size_t n, const void* t1, const void
                        hipStream_t s);
 // mixed precision accumulation: x64 += (double) e32 ; e32 = 0
 hipError_t launch_accum_f32_into_f64(int ncols, size_t n, void* x64, size_t x_cs, void* e32,
-                                     size_t e_cs, hipStream_t s);
+                                     size_t e_cs, hipStream_t s, uint32_t mask = 0xffffffffu);
 
 // Tall-skinny products on MFMA (complex):
 //   Out(n x N) = beta*Out + In(n x K) * S(K x N)

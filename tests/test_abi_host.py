@@ -1,0 +1,120 @@
+"""CPU tests of the C-ABI library: it loads, exports every function that
+include/eigcg.h declares, validates arguments without touching a GPU, and its
+host FP64 linear algebra (window eigensolver, thin QR, Cholesky) agrees with
+numpy.linalg."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "eigcg.h")
+
+
+@pytest.fixture(scope="module")
+def B():
+    lib = os.path.join(ROOT, "paper_0707_0131_amd", "libeigcg.so")
+    if not os.path.exists(lib):
+        from paper_0707_0131_amd.build import build
+        build()
+    from paper_0707_0131_amd import binding
+    return binding
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(eigcg_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_header_symbols_exported(B):
+    names = _declared()
+    assert len(names) >= 25
+    lib = ctypes.CDLL(B.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    # and the binding wraps each one under the same name
+    assert set(names) <= set(B.SIGNATURES)
+
+
+def test_default_params_and_validation(B):
+    p = B.eigcg_default_params()
+    assert (p.nev, p.m, p.max_bank, p.precision, p.max_batch) == (10, 100, 240, 0, 1)
+    ctx = ctypes.c_void_p()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    for bad in [dict(nev=10, m=20), dict(dims=(1, 4, 4, 4)), dict(max_batch=13),
+                dict(max_bank=300), dict(precision=7), dict(max_iter=0),
+                dict(mass=float("nan")), dict(nev=0)]:
+        q = B.eigcg_default_params(**bad)
+        rc = B.LIB.eigcg_create(ctypes.byref(q), fake, None, ctypes.byref(ctx))
+        assert rc == B.EIGCG_EINVAL, bad
+    assert B.LIB.eigcg_create(ctypes.byref(p), None, None, ctypes.byref(ctx)) == B.EIGCG_EINVAL
+    assert B.LIB.eigcg_solve(None, 1, None, None, 1e-10, 0, None) == B.EIGCG_EINVAL
+    assert B.LIB.eigcg_destroy(None) == B.EIGCG_EINVAL
+
+
+def test_server_validation_without_gpu(B):
+    srv = B.eigcg_server_create(0)
+    t = ctypes.c_uint64()
+    assert B.LIB.eigcg_submit(srv, 0, ctypes.c_void_p(8), ctypes.c_void_p(8), 1e-10,
+                              ctypes.byref(t)) == B.EIGCG_EINVAL
+    assert B.LIB.eigcg_poll(srv, 12345, None) == B.EIGCG_EINVAL
+    assert B.eigcg_server_destroy(srv) == B.EIGCG_OK
+
+
+def _herm(rng, n):
+    a = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    return a + a.conj().T
+
+
+def _check_eig(B, a, k, tol=1e-12):
+    w, z = B.eigcg_host_eig_lowest(a, k)
+    w0 = np.linalg.eigvalsh(a)
+    scale = max(1.0, np.max(np.abs(w0)))
+    assert np.max(np.abs(w - w0)) <= tol * scale
+    assert np.max(np.abs(a @ z - z * w[:k])) <= 10 * tol * scale
+    assert np.max(np.abs(z.conj().T @ z - np.eye(k))) <= 1e-12
+
+
+def test_host_eig_dense_tridiagonal_arrowhead_clustered(B):
+    rng = np.random.default_rng(0)
+    _check_eig(B, _herm(rng, 60), 10)
+    _check_eig(B, _herm(rng, 7), 7)
+    # real symmetric tridiagonal (a window before its first restart)
+    d = rng.uniform(0.1, 60, 100)
+    e = -rng.uniform(0.01, 5, 99)
+    _check_eig(B, (np.diag(d) + np.diag(e, 1) + np.diag(e, -1)).astype(complex), 10)
+    # restarted window: diagonal block, complex arrow row, tridiagonal tail
+    m, b = 100, 20
+    T = np.zeros((m, m), dtype=complex)
+    T[np.arange(b), np.arange(b)] = np.sort(rng.uniform(0.001, 1, b))
+    T[b, :b] = rng.standard_normal(b) + 1j * rng.standard_normal(b)
+    T[:b, b] = T[b, :b].conj()
+    for i in range(b, m):
+        T[i, i] = rng.uniform(0.5, 50)
+        if i + 1 < m:
+            T[i, i + 1] = T[i + 1, i] = -rng.uniform(0.1, 3)
+    _check_eig(B, T, 10)
+    # clustered and exactly repeated eigenvalues
+    Q, _ = np.linalg.qr(rng.standard_normal((9, 9)) + 1j * rng.standard_normal((9, 9)))
+    lam = np.array([1.0, 1.0, 1.0 + 1e-14, 2.0, 2.0, 3.0, 4.0, 4.0 + 1e-9, 5.0])
+    a = Q @ np.diag(lam) @ Q.conj().T
+    _check_eig(B, 0.5 * (a + a.conj().T), 9)
+
+
+def test_host_qr_and_cholesky(B):
+    rng = np.random.default_rng(1)
+    a = rng.standard_normal((50, 20)) + 1j * rng.standard_normal((50, 20))
+    q, r = B.eigcg_host_qr(a)
+    assert np.max(np.abs(q @ r - a)) < 1e-13
+    assert np.max(np.abs(q.conj().T @ q - np.eye(20))) < 1e-14
+    assert np.allclose(np.tril(r, -1), 0)
+    h = a.conj().T @ a + np.eye(20)
+    bb = rng.standard_normal((20, 3)) + 1j * rng.standard_normal((20, 3))
+    x = B.eigcg_host_chol_solve(h, bb)
+    assert np.max(np.abs(h @ x - bb)) < 1e-12
+    with pytest.raises(B.EigcgError):
+        B.eigcg_host_chol_solve(-np.eye(3, dtype=complex), np.ones(3, dtype=complex))

@@ -1,0 +1,127 @@
+"""GPU tests of the serving loop (continuous batching over several fields).
+
+Every request's result must be the same alone and in the mix: each column of
+the batched iteration is reduced in a fixed order of its own and refined on
+its own schedule, so the comparison is bitwise.  Results are also checked
+against the FP64 oracle's deflated solve (same bank).
+"""
+
+import time
+
+import numpy as np
+import pytest
+
+from gpu_common import dev, host, make_ctx, rel
+from oracle.dense import dense_A
+from oracle.dirac import WilsonOperator
+from oracle.initcg import init_cg
+from synthetic import gauge_field, gaussian_rhs_block
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0707_0131_amd import binding
+    return binding
+
+
+FIELDS = [((4, 4, 4, 4), 0.3, 0, -0.2), ((4, 4, 2, 8), 0.4, 6, -0.1)]
+
+
+def _setup(B, precision, max_batch, nbank=12):
+    ctxs, keep, ops, banks = [], [], [], []
+    for dims, eps, seed, mass in FIELDS:
+        U = gauge_field(dims, eps, seed)
+        op = WilsonOperator(U, mass)
+        A, _ = dense_A(op)
+        lam, X = np.linalg.eigh(A)
+        ctx, g = make_ctx(U, mass, precision=precision, max_batch=max_batch, max_bank=nbank,
+                          nev=6, m=20, max_iter=4000)
+        shape = (dims[3], dims[2], dims[1], dims[0], 4, 3)
+        B.eigcg_bank_load(ctx, dev(X[:, :nbank].T.reshape((nbank,) + shape).copy()))
+        ctxs.append(ctx)
+        keep.append(g)
+        ops.append((op, shape))
+        banks.append((X[:, :nbank], A))
+    return ctxs, keep, ops, banks
+
+
+def _serve(B, ctxs, jobs, budget=0, one_by_one=False):
+    srv = B.eigcg_server_create(budget)
+    fids = [B.eigcg_server_add(srv, c) for c in ctxs]
+    try:
+        tickets = []
+        for f, b, x in jobs:
+            tickets.append(B.eigcg_submit(srv, fids[f], b, x, 1e-10))
+            if one_by_one:
+                B.eigcg_server_drain(srv)
+        B.eigcg_server_drain(srv)
+        out = [B.eigcg_poll(srv, t) for t in tickets]
+    finally:
+        B.eigcg_server_destroy(srv)
+    return out
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_alone_equals_mixed(B, precision):
+    import torch
+    ctxs, keep, ops, banks = _setup(B, precision, max_batch=3)
+    try:
+        rhs = []
+        for f, (op, shape) in enumerate(ops):
+            bs = gaussian_rhs_block(tuple(reversed(shape[:4])), [3000 + 10 * f + i for i in range(5)])
+            rhs.append(bs)
+        jobs_alone, jobs_mix = [], []
+        for f in range(2):
+            for i in range(5):
+                b = dev(rhs[f][i][None].copy())
+                jobs_alone.append((f, b, torch.zeros_like(b)))
+                jobs_mix.append((f, b, torch.zeros_like(b)))
+        res_alone = _serve(B, ctxs, jobs_alone, one_by_one=True)
+        # interleave fields and submit everything at once (more requests than slots)
+        order = [0, 5, 1, 6, 2, 7, 3, 8, 4, 9]
+        jobs_mix2 = [jobs_mix[k] for k in order]
+        res_mix = _serve(B, ctxs, jobs_mix2)
+        for k, (f, b, x) in enumerate(jobs_alone):
+            rc, st = res_alone[k]
+            assert rc == B.EIGCG_OK and st["true_rel_res"] <= 1e-10
+        for pos, k in enumerate(order):
+            rc, st = res_mix[pos]
+            assert rc == B.EIGCG_OK
+            assert res_alone[k][1]["iters"] == st["iters"]
+            assert torch.equal(jobs_alone[k][2], jobs_mix[k][2])
+        # against the oracle's init-CG with the same bank
+        for k, (f, b, x) in enumerate(jobs_alone):
+            op, shape = ops[f]
+            X, A = banks[f]
+            H = X.conj().T @ A @ X
+            xo, io = init_cg(op.A, X, H, host(b).reshape(-1), tol=1e-10)
+            tolx = 1e-9 if precision == 0 else 1e-6
+            assert rel(host(x).reshape(-1), xo) <= tolx
+    finally:
+        for c in ctxs:
+            B.eigcg_destroy(c)
+
+
+def test_small_budget_still_completes(B):
+    import torch
+    ctxs, keep, ops, banks = _setup(B, 0, max_batch=4)
+    try:
+        jobs = []
+        for f, (op, shape) in enumerate(ops):
+            bs = gaussian_rhs_block(tuple(reversed(shape[:4])), [5000 + i for i in range(4)])
+            for i in range(4):
+                b = dev(bs[i][None].copy())
+                jobs.append((f, b, torch.zeros_like(b)))
+        mem = sum(B.eigcg_memory(c) for c in ctxs)
+        res = _serve(B, ctxs, jobs, budget=mem + 1)  # room for no extra working set
+        for rc, st in res:
+            assert rc == B.EIGCG_OK and st["true_rel_res"] <= 1e-10
+            assert st["seconds"] > 0
+    finally:
+        for c in ctxs:
+            B.eigcg_destroy(c)
