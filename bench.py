@@ -48,17 +48,17 @@ def site_bytes_stencil(two_row_links: bool, elem=16):
     return 12 * elem + links + 12 * elem
 
 
-def run_step(B, torch, g, mass, bt, xt):
+def run_step(B, torch, g, mass, bt, xt, n_eig=N_EIG):
     p = B.eigcg_default_params(dims=LATTICE, mass=mass, nev=NEV, m=M, max_bank=NBANK,
                                max_iter=40000, check_every=16)
     ctx = B.eigcg_create(p, g)
     try:
         xt.zero_()
         t0 = time.perf_counter()
-        rc1, st1 = B.eigcg_solve(ctx, bt[:N_EIG], xt[:N_EIG], TOL, B.EIGCG_MODE_EIGCG)
+        rc1, st1 = B.eigcg_solve(ctx, bt[:n_eig], xt[:n_eig], TOL, B.EIGCG_MODE_EIGCG)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        rc2, st2 = B.eigcg_solve(ctx, bt[N_EIG:], xt[N_EIG:], TOL, B.EIGCG_MODE_INITCG)
+        rc2, st2 = B.eigcg_solve(ctx, bt[n_eig:], xt[n_eig:], TOL, B.EIGCG_MODE_INITCG)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         vals, _ = B.eigcg_bank_info(ctx)
@@ -113,6 +113,8 @@ def stencil_roofline(B, torch, dims, seed, reps):
     return {
         "sites": V,
         "two_row_links": info["links64_two_rows"],
+        "stencil_variant": info["variant64"],
+        "variant_ms": info["tune_ms64"],
         "stencil_M_ms": ms_m,
         "stencil_M_GBs": bytes_m / ms_m / 1e6,
         "stencil_Mdag_cgr_ms": ms_r,
@@ -156,6 +158,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--baseline-rhs", type=int, default=4)
+    ap.add_argument("--n-eig", type=int, default=N_EIG, help="phase-1 RHS per step (profiling)")
+    ap.add_argument("--n-defl", type=int, default=N_DEFL, help="phase-2 RHS per step (profiling)")
+    ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="only time the stencil on the HBM-bound lattice (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -167,11 +174,17 @@ def main():
     from synthetic import gauge_field, gaussian_rhs
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    log(f"generating {LATTICE} links and {N_EIG + N_DEFL} right-hand sides")
+    if args.roofline_only:
+        log(f"stencil roofline only ({HBM_LATTICE})")
+        print(json.dumps({"stencil_hbm_lattice": stencil_roofline(B, torch, HBM_LATTICE, HBM_SEED,
+                                                                  100)}))
+        return
+    log(f"generating {LATTICE} links and {args.n_eig + args.n_defl} right-hand sides")
     U = gauge_field(LATTICE, EPS, SEED)
     g = torch.from_numpy(U).to("cuda:0")
     del U
-    nrhs = N_EIG + N_DEFL
+    n_eig, n_defl = args.n_eig, args.n_defl
+    nrhs = n_eig + n_defl
     shape = (LATTICE[3], LATTICE[2], LATTICE[1], LATTICE[0], 4, 3)
     bt = torch.empty((nrhs,) + shape, dtype=torch.complex128, device="cuda:0")
     for i in range(nrhs):
@@ -181,13 +194,13 @@ def main():
 
     for w in range(args.warmup):
         log(f"warmup step {w}")
-        run_step(B, torch, g, MASSES[w % len(MASSES)], bt, xt)
+        run_step(B, torch, g, MASSES[w % len(MASSES)], bt, xt, n_eig)
 
     steps = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        r = run_step(B, torch, g, MASSES[k % len(MASSES)], bt, xt)
+        r = run_step(B, torch, g, MASSES[k % len(MASSES)], bt, xt, n_eig)
         steps.append(r)
         log(f"step {k}: mass {r['mass']} phase1 {r['phase1_s']:.2f}s "
             f"(iters {r['phase1_iters'][0]}..{r['phase1_iters'][-1]}) phase2 {r['phase2_s']:.2f}s "
@@ -202,7 +215,7 @@ def main():
     base = []
     for k in range(min(args.steps, len(MASSES))):
         mass = MASSES[k]
-        dt, its, res = plain_cg(B, torch, g, mass, bt[N_EIG:], xt[N_EIG:], args.baseline_rhs)
+        dt, its, res = plain_cg(B, torch, g, mass, bt[n_eig:], xt[n_eig:], args.baseline_rhs)
         base.append({"mass": mass, "s_per_rhs": dt / args.baseline_rhs, "iters": its,
                      "max_true_rel_res": res})
         log(f"plain CG mass {mass}: {dt / args.baseline_rhs:.3f} s/RHS, iters {its}")
@@ -213,16 +226,18 @@ def main():
         plain = 1.0 / base[k]["s_per_rhs"]
         per_mass.append({"mass": s["mass"], "deflated_rhs_per_s": defl, "plain_cg_rhs_per_s": plain,
                          "speedup": defl / plain,
-                         "phase2_rhs_per_s": N_DEFL / s["phase2_s"],
-                         "phase2_speedup": (N_DEFL / s["phase2_s"]) / plain})
+                         "phase2_rhs_per_s": n_defl / s["phase2_s"],
+                         "phase2_speedup": (n_defl / s["phase2_s"]) / plain})
     plain_all = len(base) / sum(b["s_per_rhs"] for b in base)
 
-    log("stencil roofline (bench lattice, MALL-resident)")
-    roof_small = stencil_roofline(B, torch, LATTICE, SEED, 200)
-    del g
-    torch.cuda.empty_cache()
-    log(f"stencil roofline ({HBM_LATTICE}, working set above the 256 MB MALL)")
-    roof_hbm = stencil_roofline(B, torch, HBM_LATTICE, HBM_SEED, 100)
+    roof_small = roof_hbm = None
+    if not args.no_roofline:
+        log("stencil roofline (bench lattice, MALL-resident)")
+        roof_small = stencil_roofline(B, torch, LATTICE, SEED, 200)
+        del g
+        torch.cuda.empty_cache()
+        log(f"stencil roofline ({HBM_LATTICE}, working set above the 256 MB MALL)")
+        roof_hbm = stencil_roofline(B, torch, HBM_LATTICE, HBM_SEED, 100)
 
     total_iters = sum(sum(s["phase1_iters"]) + sum(s["phase2_iters"]) for s in steps)
     cpu = None
@@ -230,7 +245,7 @@ def main():
         log("CPU oracle baseline (bounded sample)")
         cpu = cpu_baseline(total_rhs, total_iters)
 
-    achieved = roof_hbm["stencil_M_GBs"]
+    achieved = roof_hbm["stencil_M_GBs"] if roof_hbm else None
     out = {
         "metric": "deflated RHS solves/sec at 1e-10 rel. residual vs plain CG; stencil HBM GB/s; p99",
         "value": value,
@@ -266,7 +281,7 @@ def main():
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
+            "frac": achieved / HBM_PEAK_GBS if achieved else None,
             "traffic": None,
         },
         "stencil_bench_lattice": roof_small,

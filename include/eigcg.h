@@ -77,6 +77,12 @@ typedef struct {
   int32_t compress_links; /* 1: store links as two rows when they are SU(3) */
   int32_t check_every;    /* iterations between host convergence polls */
   int32_t use_graphs;     /* 1: replay CG iterations from a captured HIP graph */
+  int32_t stencil_variant;/* 0: pick the fastest stencil kernel by timing at create
+                             (cached per lattice shape and precision in the process);
+                             1..3: force a variant (see eigcg_layout_info) */
+  int32_t plane_pad;      /* extra sites (in units of 64) after each SoA plane so
+                             that planes do not start on the same memory channel:
+                             0 = library default, < 0 = none */
   int32_t reserved;
 } eigcg_params;
 
@@ -151,8 +157,14 @@ int eigcg_memory(eigcg_ctx* ctx, uint64_t* bytes);
 
 /* info[0] = lattice sites V, info[1] = padded plane stride, info[2] = 1 when
  * the FP64 links are stored as two rows (12 reals), info[3] likewise for the
- * FP32 links of a mixed-precision context. */
+ * FP32 links of a mixed-precision context, info[4] / info[5] = stencil
+ * variant used for FP64 / FP32 (1: thread per site, round-robin workgroups;
+ * 2: thread per site, XCD-contiguous workgroups; 3: two waves per 64-site
+ * tile, directions split, LDS exchange); info needs 6 entries.  tune_ms
+ * (NULL or 6 doubles) receives the timed stencil ms of variants 1..3 for
+ * FP64 then FP32 (0 where not timed). */
 int eigcg_layout_info(eigcg_ctx* ctx, int32_t* info);
+int eigcg_tune_report(eigcg_ctx* ctx, double* tune_ms);
 
 /* Average device time (ms) of one launch, from HIP events on the context's
  * stream around reps back-to-back launches: what 0 = FP64 stencil M, 1 = FP64

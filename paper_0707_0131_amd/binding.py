@@ -44,6 +44,8 @@ class Params(ctypes.Structure):
         ("compress_links", ctypes.c_int32),
         ("check_every", ctypes.c_int32),
         ("use_graphs", ctypes.c_int32),
+        ("stencil_variant", ctypes.c_int32),
+        ("plane_pad", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
     ]
 
@@ -85,6 +87,7 @@ SIGNATURES = {
     "eigcg_memory": (_I32, [_VP, ctypes.POINTER(ctypes.c_uint64)]),
     "eigcg_last_error": (ctypes.c_char_p, [_VP]),
     "eigcg_layout_info": (_I32, [_VP, ctypes.POINTER(_I32)]),
+    "eigcg_tune_report": (_I32, [_VP, _DP]),
     "eigcg_time_kernel": (_I32, [_VP, _I32, _I32, _DP]),
     "eigcg_server_create": (_I32, [ctypes.c_uint64, ctypes.POINTER(_VP)]),
     "eigcg_server_add": (_I32, [_VP, _VP, ctypes.POINTER(_I32)]),
@@ -255,10 +258,13 @@ def eigcg_memory(ctx):
 
 
 def eigcg_layout_info(ctx):
-    info = (_I32 * 4)()
+    info = (_I32 * 6)()
     LIB.eigcg_layout_info(ctx, info)
+    ms = np.zeros(6)
+    LIB.eigcg_tune_report(ctx, _dptr(ms))
     return {"sites": info[0], "plane_stride": info[1], "links64_two_rows": bool(info[2]),
-            "links32_two_rows": bool(info[3])}
+            "links32_two_rows": bool(info[3]), "variant64": info[4], "variant32": info[5],
+            "tune_ms64": ms[:3].tolist(), "tune_ms32": ms[3:].tolist()}
 
 
 def eigcg_time_kernel(ctx, what, reps):

@@ -58,6 +58,8 @@ int validate(const eigcg_params* p, std::string& why) {
   if (p->max_batch < 1 || p->max_batch > 12) { why = "max_batch must be in [1, 12]"; return EIGCG_EINVAL; }
   if (p->max_iter < 1 || p->max_iter > 10000000) { why = "bad max_iter"; return EIGCG_EINVAL; }
   if (p->check_every < 1) { why = "check_every must be >= 1"; return EIGCG_EINVAL; }
+  if (p->stencil_variant < 0 || p->stencil_variant > 3) { why = "stencil_variant must be 0..3"; return EIGCG_EINVAL; }
+  if (p->plane_pad > 4096) { why = "plane_pad too large"; return EIGCG_EINVAL; }
   if (p->precision == EIGCG_MIXED_FP32 && p->reliable_every < 1) { why = "reliable_every must be >= 1"; return EIGCG_EINVAL; }
   return EIGCG_OK;
 }
@@ -83,6 +85,8 @@ int eigcg_default_params(eigcg_params* p) {
   p->compress_links = 1;
   p->check_every = 16;
   p->use_graphs = 0;
+  p->stencil_variant = 0;
+  p->plane_pad = 0;
   return EIGCG_OK;
 }
 
@@ -216,6 +220,14 @@ int eigcg_layout_info(eigcg_ctx* ctx, int32_t* info) {
   info[1] = ctx->c.g.vs;
   info[2] = ctx->c.comp64;
   info[3] = ctx->c.comp32;
+  info[4] = ctx->c.var64;
+  info[5] = ctx->c.var32;
+  return EIGCG_OK;
+}
+
+int eigcg_tune_report(eigcg_ctx* ctx, double* tune_ms) {
+  if (!ctx || !tune_ms) return EIGCG_EINVAL;
+  for (int i = 0; i < 6; ++i) tune_ms[i] = ctx->c.tune_ms[i];
   return EIGCG_OK;
 }
 

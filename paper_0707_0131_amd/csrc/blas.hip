@@ -133,8 +133,7 @@ __global__ __launch_bounds__(kBlock) void k_gauge_to_soa(const double2* __restri
 // max |U U^H - I| and max |det U - 1| over all links (unitarity check that
 // decides whether links may be stored as two rows).
 __global__ __launch_bounds__(kBlock) void k_gauge_check(const double2* __restrict__ aos, Geom g,
-                                                        double* out2, double* partial,
-                                                        unsigned int* counter) {
+                                                        double* partial) {
   __shared__ double lds[2][kBlock];
   double m1 = 0.0, m2 = 0.0;
   for (uint32_t s = blockIdx.x * kBlock + threadIdx.x; s < (uint32_t)g.V; s += gridDim.x * kBlock) {
@@ -176,16 +175,17 @@ __global__ __launch_bounds__(kBlock) void k_gauge_check(const double2* __restric
     partial[2 * blockIdx.x] = lds[0][0];
     partial[2 * blockIdx.x + 1] = lds[1][0];
   }
-  if (!elect_last_block(counter)) return;
-  if (threadIdx.x == 0) {
-    double a = 0.0, b = 0.0;
-    for (unsigned i = 0; i < gridDim.x; ++i) {
-      a = fmax(a, load_relaxed(partial + 2 * i));
-      b = fmax(b, load_relaxed(partial + 2 * i + 1));
-    }
-    out2[0] = a;
-    out2[1] = b;
+}
+
+__global__ void k_gauge_check_final(const double* partial, int nb, double* out2) {
+  if (threadIdx.x != 0) return;
+  double a = 0.0, b = 0.0;
+  for (int i = 0; i < nb; ++i) {
+    a = fmax(a, partial[2 * i]);
+    b = fmax(b, partial[2 * i + 1]);
   }
+  out2[0] = a;
+  out2[1] = b;
 }
 
 // ---- generic BLAS1 over n complex entries per column ------------------------
@@ -223,9 +223,7 @@ __global__ __launch_bounds__(kBlock) void k_copy(size_t n, const SS* x, size_t x
 
 template <typename VS>
 __global__ __launch_bounds__(kBlock) void k_norm2(size_t n, const VS* x, size_t x_cs,
-                                                  double* partial, unsigned int* counter,
-                                                  double* out, int ncols) {
-  using R = typename Storage<VS>::real;
+                                                  double* partial) {
   __shared__ double lds4[kBlock / 64];
   const int col = blockIdx.y;
   const VS* xc = x + (size_t)col * x_cs;
@@ -236,9 +234,13 @@ __global__ __launch_bounds__(kBlock) void k_norm2(size_t n, const VS* x, size_t 
   }
   double bs = block_sum(acc, lds4);
   if (threadIdx.x == 0) partial[(size_t)col * gridDim.x + blockIdx.x] = bs;
-  if (!elect_last_block(counter)) return;
+}
+
+__global__ __launch_bounds__(kBlock) void k_norm2_final(const double* partial, int nb, int ncols,
+                                                        double* out) {
+  __shared__ double lds4[kBlock / 64];
   for (int c = 0; c < ncols; ++c) {
-    double t = reduce_partials(partial + (size_t)c * gridDim.x, gridDim.x, lds4);
+    double t = reduce_partials(partial + (size_t)c * nb, nb, lds4);
     if (threadIdx.x == 0) out[c] = t;
   }
 }
@@ -380,11 +382,13 @@ hipError_t launch_gauge_to_soa(const double2* aos, void* soa, int prec, int comp
 }
 
 hipError_t launch_gauge_check(const double2* aos, const Geom* g, double* out2, hipStream_t s) {
-  // scratch after the two outputs: partials then a counter
+  // scratch after the two outputs: one (max, max) pair per workgroup
   int gx = grid_for(g->V);
   double* partial = out2 + 2;
-  unsigned int* counter = reinterpret_cast<unsigned int*>(partial + 2 * kMaxGrid);
-  hipLaunchKernelGGL(k_gauge_check, dim3(gx), dim3(kBlock), 0, s, aos, *g, out2, partial, counter);
+  hipLaunchKernelGGL(k_gauge_check, dim3(gx), dim3(kBlock), 0, s, aos, *g, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_gauge_check_final, dim3(1), dim3(64), 0, s, partial, gx, out2);
   return hipGetLastError();
 }
 
@@ -421,13 +425,18 @@ hipError_t launch_copy(int src_prec, int dst_prec, int ncols, size_t n, const vo
 
 hipError_t launch_norm2(int prec, int ncols, size_t n, const void* x, size_t x_cs,
                         double* partial, unsigned int* counter, double* out, hipStream_t s) {
-  dim3 grid(grid_for(n), ncols);
+  (void)counter;
+  const int gx = grid_for(n);
+  dim3 grid(gx, ncols);
   if (prec == kF64)
     hipLaunchKernelGGL(k_norm2<double2>, grid, dim3(kBlock), 0, s, n, (const double2*)x, x_cs,
-                       partial, counter, out, ncols);
+                       partial);
   else
     hipLaunchKernelGGL(k_norm2<float2>, grid, dim3(kBlock), 0, s, n, (const float2*)x, x_cs,
-                       partial, counter, out, ncols);
+                       partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_norm2_final, dim3(1), dim3(kBlock), 0, s, partial, gx, ncols, out);
   return hipGetLastError();
 }
 

@@ -145,33 +145,11 @@ template <typename T> __device__ __forceinline__ T block_sum(T v, T* lds4) {
   return s;
 }
 
-// "Last workgroup" election: every workgroup publishes its partials, then the
-// workgroup that increments the counter last sees all partials and finishes
-// the reduction in a fixed order.  The counter is reset by that workgroup.
-__device__ __forceinline__ bool elect_last_block(unsigned int* counter) {
-  __shared__ bool last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned int prev = atomicAdd(counter, 1u);
-    last = (prev == gridDim.x * gridDim.y * gridDim.z - 1);
-  }
-  __syncthreads();
-  if (last) {
-    __threadfence();
-    if (threadIdx.x == 0) *counter = 0u;
-  }
-  return last;
-}
-
-__device__ __forceinline__ double load_relaxed(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Fixed-order sum of n partials (n <= kMaxGrid) by one workgroup.
+// Fixed-order sum of n partials (written by an earlier kernel of the same
+// stream) by one workgroup; every workgroup that calls it gets the same bits.
 __device__ __forceinline__ double reduce_partials(const double* part, int n, double* lds4) {
   double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += kBlock) s += load_relaxed(part + i);
+  for (int i = threadIdx.x; i < n; i += kBlock) s += part[i];
   return block_sum(s, lds4);
 }
 

@@ -4,9 +4,13 @@
 // per blockIdx.y.  Loads are SoA planes, so each of the 12 spinor components
 // and each link entry is a contiguous 64-lane access; the 8 neighbour spinors
 // of a site are shared with 8 other sites through L2.  Reductions
-// (||M p||^2 and r^H r) are deterministic: fixed-order wave/workgroup sums,
-// workgroup partials in a fixed slot, and the last workgroup to finish sums
-// the partials in index order and updates the CG scalars of every column.
+// (||M p||^2 and r^H r) are deterministic and fence-free: fixed-order
+// wave/workgroup sums into one partial slot per workgroup; the second pass
+// sums the first pass's partials itself (same order in every workgroup) to
+// get alpha, and a one-workgroup finalize kernel, ordered by the stream,
+// updates the CG scalars of every column.
+#include <algorithm>
+
 #include "kernels.h"
 #include "wilson.h"
 
@@ -23,38 +27,128 @@ struct DevArgs {
   int ncols;
   uint32_t mask;
   ColState* st;
-  double* partial;
-  unsigned int* counter;
+  double* partial;          // this pass's per-workgroup partials
+  const double* partial_in;  // kEpiCGR: partials of the first pass (p^H A p)
   void* r; size_t r_cs;
   const void* b; size_t b_cs;
   void* tbuf; size_t t_cs;
   double* hist; int hist_stride;
 };
 
-template <typename VS, typename LS, bool COMP, bool DAG, int EPI>
+// Work units (blocks of sites) handed to workgroups.  With xcd set, the
+// units are split into eight contiguous chunks and workgroup b (which the
+// hardware places on XCD b % 8) walks chunk b % 8, so the workgroups sharing
+// an XCD's L2 sweep neighbouring sites together.
+struct Units {
+  uint32_t u, end, step;
+  __device__ __forceinline__ Units(uint32_t T, bool xcd) {
+    if (!xcd) {
+      u = blockIdx.x;
+      end = T;
+      step = gridDim.x;
+    } else {
+      const uint32_t x = blockIdx.x & 7u, q = blockIdx.x >> 3;
+      const uint32_t C = (T + 7u) >> 3;
+      u = x * C + q;
+      end = min((x + 1) * C, T);
+      step = gridDim.x >> 3;
+    }
+  }
+};
+
+// CG epilogue for components [C0, C0 + NC) of site s, given o = op(in) there.
+template <typename VS, int EPI, int C0, int NC>
+__device__ __forceinline__ void epilogue(const DevArgs& a, int col, uint32_t s,
+                                         const cpx<typename Storage<VS>::real>* o,
+                                         typename Storage<VS>::real alpha, bool save_t,
+                                         int save_slot, typename Storage<VS>::real& acc2) {
+  using R = typename Storage<VS>::real;
+  const size_t vs = (size_t)a.g.vs;
+  if (EPI == kEpiStore || EPI == kEpiNorm) {
+    VS* out = reinterpret_cast<VS*>(a.out) + (size_t)col * a.out_cs;
+#pragma unroll
+    for (int e = C0; e < C0 + NC; ++e) {
+      Storage<VS>::st(out, (size_t)e * vs + s, o[e]);
+      if (EPI == kEpiNorm) acc2 += o[e].re * o[e].re + o[e].im * o[e].im;
+    }
+  } else if (EPI == kEpiCGR) {
+    VS* r = reinterpret_cast<VS*>(a.r) + (size_t)col * a.r_cs;
+    if (save_t) {
+      VS* t = reinterpret_cast<VS*>(a.tbuf) + ((size_t)col * 2 + save_slot) * a.t_cs;
+#pragma unroll
+      for (int e = C0; e < C0 + NC; ++e) Storage<VS>::st(t, (size_t)e * vs + s, o[e]);
+    }
+#pragma unroll
+    for (int e = C0; e < C0 + NC; ++e) {
+      cpx<R> rv = Storage<VS>::ld(r, (size_t)e * vs + s);
+      rv.re -= alpha * o[e].re;
+      rv.im -= alpha * o[e].im;
+      Storage<VS>::st(r, (size_t)e * vs + s, rv);
+      acc2 += rv.re * rv.re + rv.im * rv.im;
+    }
+  } else {  // kEpiRes: r = b - op(in)
+    VS* r = reinterpret_cast<VS*>(a.r) + (size_t)col * a.r_cs;
+    const VS* b = reinterpret_cast<const VS*>(a.b) + (size_t)col * a.b_cs;
+#pragma unroll
+    for (int e = C0; e < C0 + NC; ++e) {
+      cpx<R> bv = Storage<VS>::ld(b, (size_t)e * vs + s);
+      cpx<R> rv = {bv.re - o[e].re, bv.im - o[e].im};
+      Storage<VS>::st(r, (size_t)e * vs + s, rv);
+      acc2 += rv.re * rv.re + rv.im * rv.im;
+    }
+  }
+}
+
+// Column activity and (second pass) alpha for this workgroup's column.
+template <typename VS, int EPI>
+__device__ __forceinline__ bool column_setup(const DevArgs& a, int col, double* lds4,
+                                             typename Storage<VS>::real& alpha, bool& save_t,
+                                             int& save_slot) {
+  using R = typename Storage<VS>::real;
+  bool active = ((a.mask >> col) & 1u) != 0;
+  if (active && (EPI == kEpiNorm || EPI == kEpiCGR)) active = a.st[col].state == ColRun;
+  alpha = R(0);
+  save_t = false;
+  save_slot = 0;
+  if (EPI == kEpiCGR) {
+    // alpha = rho / ||M p||^2 from the first pass's partials, summed in the
+    // same fixed order by every workgroup (and by the finalize kernel)
+    const double pap = reduce_partials(a.partial_in + (size_t)col * gridDim.x, gridDim.x, lds4);
+    if (active) {
+      if (pap > 0.0 && pap < INFINITY) {
+        alpha = (R)(a.st[col].rho / pap);
+        const int j = a.st[col].iter + 1;  // iteration being completed
+        save_t = a.tbuf != nullptr && (j == a.st[col].save_t0 || j == a.st[col].save_t1);
+        save_slot = j & 1;
+      } else {
+        active = false;  // breakdown: the finalize kernel stops the column
+      }
+    }
+  }
+  return active;
+}
+
+// Variants 1 and 2: one thread per site, all eight hops; 256 sites per unit,
+// round-robin (1) or XCD-contiguous (2) unit mapping.
+template <typename VS, typename LS, bool COMP, bool DAG, int EPI, bool XCD>
 __global__ __launch_bounds__(kBlock) void k_wilson(DevArgs a) {
   using R = typename Storage<VS>::real;
   __shared__ double lds4[kBlock / 64];
   __shared__ R ldsr[kBlock / 64];
   const int col = blockIdx.y;
-  bool active = ((a.mask >> col) & 1u) != 0;
-  if (active && (EPI == kEpiNorm || EPI == kEpiCGR)) active = a.st[col].state == ColRun;
-  R alpha = R(0);
-  bool save_t = false;
-  int save_slot = 0;
-  if (EPI == kEpiCGR && active) {
-    alpha = (R)a.st[col].alpha;
-    const int j = a.st[col].iter + 1;  // iteration being completed
-    save_t = a.tbuf != nullptr && (j == a.st[col].save_t0 || j == a.st[col].save_t1);
-    save_slot = j & 1;
-  }
+  R alpha;
+  bool save_t;
+  int save_slot;
+  const bool active = column_setup<VS, EPI>(a, col, lds4, alpha, save_t, save_slot);
   const VS* in = reinterpret_cast<const VS*>(a.in) + (size_t)col * a.in_cs;
   const LS* u = reinterpret_cast<const LS*>(a.u);
   const size_t vs = (size_t)a.g.vs;
   R acc2 = R(0);
   if (active) {
-    for (uint32_t s = blockIdx.x * kBlock + threadIdx.x; s < (uint32_t)a.g.V;
-         s += gridDim.x * kBlock) {
+    const uint32_t T = ((uint32_t)a.g.V + kBlock - 1) / kBlock;
+    for (Units it(T, XCD); it.u < it.end; it.u += it.step) {
+      const uint32_t s = it.u * kBlock + threadIdx.x;
+      if (s >= (uint32_t)a.g.V) continue;
       cpx<R> h[12];
       hopping_site<VS, LS, COMP, DAG ? 1 : -1>(in, u, a.g, s, h);
       const R d = (R)a.diag;
@@ -64,100 +158,159 @@ __global__ __launch_bounds__(kBlock) void k_wilson(DevArgs a) {
         cpx<R> v = Storage<VS>::ld(in, (size_t)e * vs + s);
         o[e] = {d * v.re - R(0.5) * h[e].re, d * v.im - R(0.5) * h[e].im};
       }
-      if (EPI == kEpiStore || EPI == kEpiNorm) {
-        VS* out = reinterpret_cast<VS*>(a.out) + (size_t)col * a.out_cs;
-#pragma unroll
-        for (int e = 0; e < 12; ++e) {
-          Storage<VS>::st(out, (size_t)e * vs + s, o[e]);
-          if (EPI == kEpiNorm) acc2 += o[e].re * o[e].re + o[e].im * o[e].im;
-        }
-      } else if (EPI == kEpiCGR) {
-        VS* r = reinterpret_cast<VS*>(a.r) + (size_t)col * a.r_cs;
-        if (save_t) {
-          VS* t = reinterpret_cast<VS*>(a.tbuf) + ((size_t)col * 2 + save_slot) * a.t_cs;
-#pragma unroll
-          for (int e = 0; e < 12; ++e) Storage<VS>::st(t, (size_t)e * vs + s, o[e]);
-        }
-#pragma unroll
-        for (int e = 0; e < 12; ++e) {
-          cpx<R> rv = Storage<VS>::ld(r, (size_t)e * vs + s);
-          rv.re -= alpha * o[e].re;
-          rv.im -= alpha * o[e].im;
-          Storage<VS>::st(r, (size_t)e * vs + s, rv);
-          acc2 += rv.re * rv.re + rv.im * rv.im;
-        }
-      } else {  // kEpiRes: r = b - op(in)
-        VS* r = reinterpret_cast<VS*>(a.r) + (size_t)col * a.r_cs;
-        const VS* b = reinterpret_cast<const VS*>(a.b) + (size_t)col * a.b_cs;
-#pragma unroll
-        for (int e = 0; e < 12; ++e) {
-          cpx<R> bv = Storage<VS>::ld(b, (size_t)e * vs + s);
-          cpx<R> rv = {bv.re - o[e].re, bv.im - o[e].im};
-          Storage<VS>::st(r, (size_t)e * vs + s, rv);
-          acc2 += rv.re * rv.re + rv.im * rv.im;
-        }
-      }
+      epilogue<VS, EPI, 0, 12>(a, col, s, o, alpha, save_t, save_slot, acc2);
     }
   }
   if (EPI == kEpiStore) return;
-  // deterministic reduction: workgroup sum in R, partial slot per workgroup
   R bs = block_sum(acc2, ldsr);
   if (threadIdx.x == 0) a.partial[(size_t)col * gridDim.x + blockIdx.x] = (double)bs;
-  if (!elect_last_block(a.counter)) return;
-  for (int c = 0; c < a.ncols; ++c) {
-    const bool on = ((a.mask >> c) & 1u) != 0;
-    if (!on) continue;
-    const double tot = reduce_partials(a.partial + (size_t)c * gridDim.x, gridDim.x, lds4);
-    if (threadIdx.x != 0) continue;
-    ColState& S = a.st[c];
-    if (EPI == kEpiNorm) {
-      if (S.state != ColRun) continue;
-      S.pap = tot;
-      if (tot > 0.0 && tot < INFINITY) {
-        S.alpha = S.rho / tot;
+}
+
+// Variant 3: a unit is two 64-site tiles; each tile is handled by a pair of
+// waves, the even wave doing directions x and y, the odd wave z and t.  They
+// swap half of their partial sums through LDS and each finishes six of the
+// twelve output components, so per-thread state is half of variant 1's and
+// twice as many waves stream the lattice.
+template <typename VS, typename LS, bool COMP, bool DAG, int EPI>
+__global__ __launch_bounds__(kBlock) void k_wilson_pair(DevArgs a) {
+  using R = typename Storage<VS>::real;
+  __shared__ double lds4[kBlock / 64];
+  __shared__ R ldsr[kBlock / 64];
+  __shared__ cpx<R> xbuf[2][2][6][64];  // [tile][writer parity][component][lane]
+  const int col = blockIdx.y;
+  R alpha;
+  bool save_t;
+  int save_slot;
+  const bool active = column_setup<VS, EPI>(a, col, lds4, alpha, save_t, save_slot);
+  const VS* in = reinterpret_cast<const VS*>(a.in) + (size_t)col * a.in_cs;
+  const LS* u = reinterpret_cast<const LS*>(a.u);
+  const size_t vs = (size_t)a.g.vs;
+  const int tile = threadIdx.x >> 7;
+  const int odd = (threadIdx.x >> 6) & 1;
+  const int lane = threadIdx.x & 63;
+  R acc2 = R(0);
+  if (active) {
+    const uint32_t T = ((uint32_t)a.g.V + 127u) / 128u;
+    for (Units it(T, true); it.u < it.end; it.u += it.step) {
+      const uint32_t s = it.u * 128u + tile * 64u + lane;
+      const bool valid = s < (uint32_t)a.g.V;
+      cpx<R> acc[12];
+#pragma unroll
+      for (int e = 0; e < 12; ++e) acc[e] = {R(0), R(0)};
+      if (valid) {
+        uint32_t coord[4];
+        site_coords(a.g, s, coord);
+        if (!odd) {
+          hop_dir<0, VS, LS, COMP, DAG ? 1 : -1>(in, u, a.g, s, coord, acc);
+          hop_dir<1, VS, LS, COMP, DAG ? 1 : -1>(in, u, a.g, s, coord, acc);
+        } else {
+          hop_dir<2, VS, LS, COMP, DAG ? 1 : -1>(in, u, a.g, s, coord, acc);
+          hop_dir<3, VS, LS, COMP, DAG ? 1 : -1>(in, u, a.g, s, coord, acc);
+        }
+      }
+      // hand the partner the half it finishes: even keeps 0..5, odd keeps 6..11
+      if (odd) {
+#pragma unroll
+        for (int e = 0; e < 6; ++e) xbuf[tile][1][e][lane] = acc[e];
       } else {
+#pragma unroll
+        for (int e = 0; e < 6; ++e) xbuf[tile][0][e][lane] = acc[6 + e];
+      }
+      __syncthreads();
+      const R d = (R)a.diag;
+      cpx<R> o[12];
+      if (!odd) {
+#pragma unroll
+        for (int e = 0; e < 6; ++e) {
+          const cpx<R> p = xbuf[tile][1][e][lane];
+          cpx<R> v = valid ? Storage<VS>::ld(in, (size_t)e * vs + s) : cpx<R>{R(0), R(0)};
+          const R hr = acc[e].re + p.re, hi = acc[e].im + p.im;
+          o[e] = {d * v.re - R(0.5) * hr, d * v.im - R(0.5) * hi};
+        }
+        if (valid) epilogue<VS, EPI, 0, 6>(a, col, s, o, alpha, save_t, save_slot, acc2);
+      } else {
+#pragma unroll
+        for (int e = 6; e < 12; ++e) {
+          const cpx<R> p = xbuf[tile][0][e - 6][lane];
+          cpx<R> v = valid ? Storage<VS>::ld(in, (size_t)e * vs + s) : cpx<R>{R(0), R(0)};
+          const R hr = p.re + acc[e].re, hi = p.im + acc[e].im;
+          o[e] = {d * v.re - R(0.5) * hr, d * v.im - R(0.5) * hi};
+        }
+        if (valid) epilogue<VS, EPI, 6, 6>(a, col, s, o, alpha, save_t, save_slot, acc2);
+      }
+      __syncthreads();
+    }
+  }
+  if (EPI == kEpiStore) return;
+  R bs = block_sum(acc2, ldsr);
+  if (threadIdx.x == 0) a.partial[(size_t)col * gridDim.x + blockIdx.x] = (double)bs;
+}
+
+// CG scalars after the second stencil pass (one workgroup): p^H A p from the
+// first pass's partials (alpha, or breakdown), r^H r from the second pass's
+// partials (beta, history, stop tests, eigCG t-save schedule).
+__global__ __launch_bounds__(kBlock) void k_finalize_cg(ColState* st, int ncols, uint32_t mask,
+                                                        const double* part_a, const double* part_b,
+                                                        int nb, double* hist, int hist_stride) {
+  __shared__ double lds4[kBlock / 64];
+  for (int c = 0; c < ncols; ++c) {
+    if (!((mask >> c) & 1u)) continue;
+    const double pap = reduce_partials(part_a + (size_t)c * nb, nb, lds4);
+    const double rho_new = reduce_partials(part_b + (size_t)c * nb, nb, lds4);
+    if (threadIdx.x != 0) continue;
+    ColState& S = st[c];
+    if (S.state == ColRun) {
+      S.pap = pap;
+      if (!(pap > 0.0 && pap < INFINITY)) {
         S.alpha = 0.0;
         S.state = ColStopPending;
         S.reason = ReasonBreakdown;
+        continue;
       }
-    } else if (EPI == kEpiCGR) {
-      if (S.state == ColRun) {
-        const int j = S.iter + 1;
-        const double rho_new = tot;
-        const double beta = rho_new / S.rho;
-        if (a.hist) {
-          double* h = a.hist + (size_t)c * a.hist_stride + (size_t)3 * (j - 1);
-          h[0] = S.alpha;
-          h[1] = beta;
-          h[2] = rho_new;
-        }
-        S.iter = j;
-        if (j == S.save_t1 && S.tperiod > 0) {
-          S.save_t0 += S.tperiod;
-          S.save_t1 += S.tperiod;
-        }
-        S.rho_prev = S.rho;
-        S.rho = rho_new;
-        S.beta = beta;
-        if (!(rho_new < INFINITY)) {
-          S.state = ColStopPending;
-          S.reason = ReasonBreakdown;
-        } else if (rho_new <= S.stop2) {
-          S.state = ColStopPending;
-          S.reason = ReasonConverged;
-        } else if (rho_new <= S.restart2) {
-          S.state = ColStopPending;
-          S.reason = ReasonRestart;
-        } else if (j >= S.max_iter) {
-          S.state = ColStopPending;
-          S.reason = ReasonMaxIter;
-        }
-      } else if (S.state == ColStopPending) {
-        S.state = ColStopped;
+      S.alpha = S.rho / pap;
+      const int j = S.iter + 1;
+      const double beta = rho_new / S.rho;
+      if (hist) {
+        double* h = hist + (size_t)c * hist_stride + (size_t)3 * (j - 1);
+        h[0] = S.alpha;
+        h[1] = beta;
+        h[2] = rho_new;
       }
-    } else {  // kEpiRes
-      S.rho = tot;
+      S.iter = j;
+      if (j == S.save_t1 && S.tperiod > 0) {
+        S.save_t0 += S.tperiod;
+        S.save_t1 += S.tperiod;
+      }
+      S.rho_prev = S.rho;
+      S.rho = rho_new;
+      S.beta = beta;
+      if (!(rho_new < INFINITY)) {
+        S.state = ColStopPending;
+        S.reason = ReasonBreakdown;
+      } else if (rho_new <= S.stop2) {
+        S.state = ColStopPending;
+        S.reason = ReasonConverged;
+      } else if (rho_new <= S.restart2) {
+        S.state = ColStopPending;
+        S.reason = ReasonRestart;
+      } else if (j >= S.max_iter) {
+        S.state = ColStopPending;
+        S.reason = ReasonMaxIter;
+      }
+    } else if (S.state == ColStopPending) {
+      S.state = ColStopped;
     }
+  }
+}
+
+// rho = ||b - A x||^2 of a true-residual pass
+__global__ __launch_bounds__(kBlock) void k_finalize_res(ColState* st, int ncols, uint32_t mask,
+                                                         const double* part, int nb) {
+  __shared__ double lds4[kBlock / 64];
+  for (int c = 0; c < ncols; ++c) {
+    if (!((mask >> c) & 1u)) continue;
+    const double tot = reduce_partials(part + (size_t)c * nb, nb, lds4);
+    if (threadIdx.x == 0) st[c].rho = tot;
   }
 }
 
@@ -165,20 +318,37 @@ template <typename VS, typename LS>
 hipError_t launch_typed(const StencilLaunch& L, hipStream_t s) {
   DevArgs a;
   a.in = L.in; a.in_cs = L.in_cs; a.out = L.out; a.out_cs = L.out_cs; a.u = L.u; a.g = *L.g;
-  a.diag = L.diag; a.ncols = L.ncols; a.mask = L.mask; a.st = L.st; a.partial = L.partial;
-  a.counter = L.counter; a.r = L.r; a.r_cs = L.r_cs; a.b = L.b; a.b_cs = L.b_cs;
+  a.diag = L.diag; a.ncols = L.ncols; a.mask = L.mask; a.st = L.st;
+  // first pass (kEpiNorm) writes partial slot A, second pass (kEpiCGR, kEpiRes) slot B
+  double* part_a = L.partial;
+  double* part_b = L.partial + (size_t)kMaxCols * kMaxGrid;
+  a.partial = (L.epi == kEpiNorm) ? part_a : part_b;
+  a.partial_in = part_a;
+  a.r = L.r; a.r_cs = L.r_cs; a.b = L.b; a.b_cs = L.b_cs;
   a.tbuf = L.tbuf; a.t_cs = L.t_cs; a.hist = L.hist; a.hist_stride = L.hist_stride;
-  int gx = (L.g->V + kBlock - 1) / kBlock;
-  if (gx > kMaxGrid) gx = kMaxGrid;
+  const int variant = L.variant <= 0 ? 1 : L.variant;
+  const uint32_t unit = variant == 3 ? 128u : (uint32_t)kBlock;
+  const uint32_t T = ((uint32_t)L.g->V + unit - 1) / unit;
+  int gx;
+  if (variant == 1) {
+    gx = (int)std::min<uint32_t>(T, kMaxGrid);
+  } else {
+    gx = (int)std::min<uint32_t>((T + 7u) & ~7u, kMaxGrid);  // a multiple of 8 (XCDs)
+  }
   dim3 grid(gx, L.ncols), block(kBlock);
-#define EIGCG_DISPATCH(COMP, DAG, EPI) \
-  hipLaunchKernelGGL((k_wilson<VS, LS, COMP, DAG, EPI>), grid, block, 0, s, a)
+#define EIGCG_K(COMP, DAG, EPI)                                                            \
+  if (variant == 3)                                                                        \
+    hipLaunchKernelGGL((k_wilson_pair<VS, LS, COMP, DAG, EPI>), grid, block, 0, s, a);     \
+  else if (variant == 2)                                                                   \
+    hipLaunchKernelGGL((k_wilson<VS, LS, COMP, DAG, EPI, true>), grid, block, 0, s, a);    \
+  else                                                                                     \
+    hipLaunchKernelGGL((k_wilson<VS, LS, COMP, DAG, EPI, false>), grid, block, 0, s, a);
 #define EIGCG_EPI(COMP, DAG)                                  \
   switch (L.epi) {                                            \
-    case kEpiStore: EIGCG_DISPATCH(COMP, DAG, kEpiStore); break; \
-    case kEpiNorm: EIGCG_DISPATCH(COMP, DAG, kEpiNorm); break;   \
-    case kEpiCGR: EIGCG_DISPATCH(COMP, DAG, kEpiCGR); break;     \
-    default: EIGCG_DISPATCH(COMP, DAG, kEpiRes); break;          \
+    case kEpiStore: { EIGCG_K(COMP, DAG, kEpiStore) } break;  \
+    case kEpiNorm: { EIGCG_K(COMP, DAG, kEpiNorm) } break;    \
+    case kEpiCGR: { EIGCG_K(COMP, DAG, kEpiCGR) } break;      \
+    default: { EIGCG_K(COMP, DAG, kEpiRes) } break;           \
   }
   if (L.compressed) {
     if (L.op == kOpMdag) { EIGCG_EPI(true, true) } else { EIGCG_EPI(true, false) }
@@ -186,7 +356,15 @@ hipError_t launch_typed(const StencilLaunch& L, hipStream_t s) {
     if (L.op == kOpMdag) { EIGCG_EPI(false, true) } else { EIGCG_EPI(false, false) }
   }
 #undef EIGCG_EPI
-#undef EIGCG_DISPATCH
+#undef EIGCG_K
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (L.epi == kEpiCGR)
+    hipLaunchKernelGGL(k_finalize_cg, dim3(1), dim3(kBlock), 0, s, L.st, L.ncols, L.mask, part_a,
+                       part_b, gx, L.hist, L.hist_stride);
+  else if (L.epi == kEpiRes)
+    hipLaunchKernelGGL(k_finalize_res, dim3(1), dim3(kBlock), 0, s, L.st, L.ncols, L.mask, part_b,
+                       gx);
   return hipGetLastError();
 }
 

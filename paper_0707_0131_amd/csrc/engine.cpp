@@ -20,6 +20,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <unordered_map>
 
 #include "hostla.h"
@@ -87,6 +89,73 @@ static size_t elem_bytes(int prec) { return prec == kF64 ? 16 : 8; }
 // context
 // ---------------------------------------------------------------------------
 
+static void ws_ensure(Ctx& c, Workspace& w, int prec, bool eig);
+static StencilLaunch stencil_base(Ctx& c, int prec);
+
+// Stencil autotuner: times every kernel variant (store epilogue, one column)
+// on this lattice and keeps the fastest.  The choice is cached per (lattice
+// shape, precision, link storage) for the process so that every context on
+// the same lattice runs the same arithmetic (variants differ in summation
+// order at the rounding level).  A forced variant in the parameters wins.
+static void autotune_stencil(Ctx& c, int prec) {
+  static std::mutex mu;
+  static std::map<std::vector<int>, int> cache;
+  int& var = prec == kF64 ? c.var64 : c.var32;
+  if (c.P.stencil_variant > 0) {
+    var = c.P.stencil_variant;
+    return;
+  }
+  const std::vector<int> key = {c.g.L[0], c.g.L[1], c.g.L[2], c.g.L[3], c.g.vs, prec,
+                                prec == kF64 ? c.comp64 : c.comp32};
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+      var = it->second;
+      return;
+    }
+  }
+  Workspace& w = prec == kF64 ? c.ws64 : c.ws32;
+  ws_ensure(c, w, prec, false);
+  hipEvent_t e0, e1;
+  c.check(hipEventCreate(&e0), "ev");
+  c.check(hipEventCreate(&e1), "ev");
+  double best = 1e30;
+  int best_v = 1;
+  for (int v = 1; v <= 3; ++v) {
+    StencilLaunch L = stencil_base(c, prec);
+    L.variant = v;
+    L.op = kOpM;
+    L.epi = kEpiStore;
+    L.in = w.x; L.in_cs = c.cs;
+    L.out = w.tmp; L.out_cs = c.cs;
+    L.ncols = 1;
+    L.mask = 1u;
+    for (int i = 0; i < 3; ++i) c.check(launch_stencil(L, c.stream), "tune");
+    const int reps = 12;
+    c.check(hipEventRecord(e0, c.stream), "ev");
+    for (int i = 0; i < reps; ++i) c.check(launch_stencil(L, c.stream), "tune");
+    c.check(hipEventRecord(e1, c.stream), "ev");
+    c.check(hipEventSynchronize(e1), "ev");
+    float ms = 0.f;
+    c.check(hipEventElapsedTime(&ms, e0, e1), "ev");
+    const double t = (double)ms / reps;
+    c.tune_ms[(prec == kF64 ? 0 : 3) + v - 1] = t;
+    if (t < best) {
+      best = t;
+      best_v = v;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c.check(hipMemsetAsync(w.tmp, 0, c.cs * elem_bytes(prec) * w.K, c.stream), "clear");
+  c.check(hipStreamSynchronize(c.stream), "sync");
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(key);
+  var = it != cache.end() ? it->second : best_v;
+  if (it == cache.end()) cache[key] = best_v;
+}
+
 void ctx_init(Ctx& c, const eigcg_params& p, const void* gauge_dev, hipStream_t s) {
   c.P = p;
   c.stream = s;
@@ -94,7 +163,11 @@ void ctx_init(Ctx& c, const eigcg_params& p, const void* gauge_dev, hipStream_t 
   Geom& g = c.g;
   for (int i = 0; i < 4; ++i) g.L[i] = p.dims[i];
   g.V = p.dims[0] * p.dims[1] * p.dims[2] * p.dims[3];
-  g.vs = (int)round_up((size_t)g.V, 64);
+  // plane stride: V rounded up to 64 sites, plus an odd number of 64-site
+  // blocks by default so that the 12 spinor planes and the link planes of a
+  // site start on different memory channels
+  const int pad = p.plane_pad < 0 ? 0 : (p.plane_pad == 0 ? 1 : p.plane_pad);
+  g.vs = (int)round_up((size_t)g.V, 64) + 64 * pad;
   g.stride[0] = 1;
   g.stride[1] = p.dims[0];
   g.stride[2] = p.dims[0] * p.dims[1];
@@ -144,6 +217,8 @@ void ctx_init(Ctx& c, const eigcg_params& p, const void* gauge_dev, hipStream_t 
   c.events.resize(4 + 3 * kMaxCols);
   for (auto& e : c.events) c.check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
   c.check(hipStreamSynchronize(s), "sync");
+  autotune_stencil(c, kF64);
+  if (p.precision == EIGCG_MIXED_FP32) autotune_stencil(c, kF32);
 }
 
 static void ws_release(Ctx& c, Workspace& w) {
@@ -219,6 +294,7 @@ static StencilLaunch stencil_base(Ctx& c, int prec) {
   StencilLaunch L{};
   L.prec = prec;
   L.compressed = prec == kF64 ? c.comp64 : c.comp32;
+  L.variant = prec == kF64 ? c.var64 : c.var32;
   L.u = prec == kF64 ? c.u64 : c.u32;
   L.g = &c.g;
   L.diag = 4.0 + c.P.mass;
@@ -1389,7 +1465,8 @@ void bank_vectors(Ctx& c, int first, int count, void* out_aos) {
 
 // Kernel timing on the context's stream (HIP events around `reps` launches):
 // what 0: FP64 stencil M (store); 1: FP64 stencil M^H fused with the CG
-// residual update (kEpiCGR); 2: one FP64 CG iteration (three kernels);
+// residual update (kEpiCGR, with its finalize kernel); 2: one FP64 CG
+// iteration (four kernels);
 // 3: FP32 stencil M (store; mixed-precision contexts only).
 double bench_kernels(Ctx& c, int what, int reps) {
   const int prec = what == 3 ? kF32 : kF64;
@@ -1398,10 +1475,18 @@ double bench_kernels(Ctx& c, int what, int reps) {
   ws_ensure(c, w, prec, false);
   // fill x and p with something non-trivial: copy of a scaled ones-like field is
   // not needed for timing; zero fields time identically
+  // non-zero, finite work vectors (byte pattern 0x3F) and a state that never
+  // stops, so every timed launch does its full work
+  const size_t vb = c.cs * elem_bytes(prec);
+  for (void* v : {w.x, w.p, w.r, w.tmp}) c.check(hipMemsetAsync(v, 0x3F, vb, c.stream), "fill");
   std::vector<ColState> st(1);
   std::memset(st.data(), 0, sizeof(ColState));
   st[0].state = ColRun;
-  st[0].rho = 1.0;
+  st[0].rho = col_norms(c, prec, 1, w.r)[0];  // a consistent CG state: r = p
+  c.check(launch_copy(prec, prec, 1, c.cs, w.r, c.cs, w.p, c.cs, c.stream), "copy");
+  st[0].stop2 = -1.0;
+  st[0].restart2 = -1.0;
+  st[0].res_stop2 = -1.0;
   st[0].max_iter = 0x3fffffff;
   std::memcpy(c.h_st, st.data(), sizeof(ColState));
   c.check(hipMemcpy(c.d_st, c.h_st, sizeof(ColState), hipMemcpyHostToDevice), "st");
@@ -1425,6 +1510,17 @@ double bench_kernels(Ctx& c, int what, int reps) {
       R.enqueue_iters(1);
     }
   };
+  if (reps + 8 > c.P.max_iter) throw ApiError{EIGCG_EINVAL, "reps must stay below max_iter"};
+  if (what == 1) {  // the fused second pass needs the first pass's partials (p^H A p)
+    StencilLaunch L = stencil_base(c, prec);
+    L.op = kOpM;
+    L.epi = kEpiNorm;
+    L.in = w.p; L.in_cs = c.cs;
+    L.out = w.tmp; L.out_cs = c.cs;
+    L.ncols = 1;
+    L.mask = 1u;
+    c.check(launch_stencil(L, c.stream), "stencil");
+  }
   for (int i = 0; i < 3; ++i) launch();
   c.check(hipEventRecord(e0, c.stream), "ev");
   for (int i = 0; i < reps; ++i) launch();
@@ -1434,6 +1530,8 @@ double bench_kernels(Ctx& c, int what, int reps) {
   c.check(hipEventElapsedTime(&ms, e0, e1), "ev");
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  for (void* v : {w.x, w.p, w.r, w.tmp}) c.check(hipMemsetAsync(v, 0, vb, c.stream), "clear");
+  c.check(hipStreamSynchronize(c.stream), "sync");
   return (double)ms / reps;
 }
 

@@ -51,6 +51,8 @@ struct Ctx {
   hipStream_t stream = nullptr;
   int device = 0;
   int comp64 = 0, comp32 = 0;
+  int var64 = 1, var32 = 1;        // stencil kernel variants in use
+  double tune_ms[6] = {0, 0, 0, 0, 0, 0};
   void* u64 = nullptr;
   void* u32 = nullptr;
   // bank (Section 4): U columns, H = U^H A U and its Cholesky factor

@@ -15,9 +15,10 @@ enum StencilOp { kOpM = 0, kOpMdag = 1 };
 // epilogues of the stencil launch
 enum StencilEpi {
   kEpiStore = 0,   // out = op(in)
-  kEpiNorm = 1,    // out = op(in); p^H A p = ||out||^2 -> alpha (CG step 1)
-  kEpiCGR = 2,     // t = op(in); r -= alpha t; r^H r -> beta, stop test (CG step 2)
-  kEpiRes = 3,     // r = b - op(in); r^H r -> rho (true residual)
+  kEpiNorm = 1,    // out = op(in); partials of ||out||^2 = p^H A p (CG step 1)
+  kEpiCGR = 2,     // alpha from step 1; t = op(in); r -= alpha t; r^H r; then a
+                   // finalize kernel updates alpha, beta and the stop tests
+  kEpiRes = 3,     // r = b - op(in); r^H r -> rho (true residual, with finalize)
 };
 
 struct StencilLaunch {
@@ -25,6 +26,7 @@ struct StencilLaunch {
   int op;                   // kOpM / kOpMdag
   int epi;                  // StencilEpi
   int compressed;           // links stored as two rows
+  int variant;              // stencil kernel variant 1..3 (0 = 1)
   const void* in; size_t in_cs;     // column stride in complex elements
   void* out; size_t out_cs;         // kEpiStore / kEpiNorm target
   const void* u;
@@ -33,8 +35,8 @@ struct StencilLaunch {
   int ncols;
   uint32_t mask;            // columns to process
   ColState* st;             // per-column state (kEpiNorm / kEpiCGR / kEpiRes)
-  double* partial;          // ncols * kMaxGrid doubles
-  unsigned int* counter;
+  double* partial;          // 2 * kMaxCols * kMaxGrid doubles (first/second pass)
+  unsigned int* counter;    // unused by the stencil (kept for the launch ABI)
   void* r; size_t r_cs;     // kEpiCGR residual, kEpiRes residual output
   const void* b; size_t b_cs;       // kEpiRes right-hand side
   void* tbuf; size_t t_cs;  // kEpiCGR: two t slots per column (slot = j & 1)

@@ -71,79 +71,92 @@ __device__ __forceinline__ void load_link(const LS* __restrict__ u, int mu, size
   }
 }
 
-// Hopping sum for one site: acc = sum_mu [(1 + sf g_mu) U_mu(x) psi(x+mu)
-// + (1 - sf g_mu) U_mu(x-mu)^+ psi(x-mu)], sf = -1 for M, +1 for M^H.
+// Site coordinates of lexicographic site index s (x fastest).
+__device__ __forceinline__ void site_coords(const Geom& g, uint32_t s, uint32_t* coord) {
+  const uint32_t xyz = g.dx.div(s);
+  coord[0] = s - xyz * (uint32_t)g.L[0];
+  const uint32_t zt = g.dy.div(xyz);
+  coord[1] = xyz - zt * (uint32_t)g.L[1];
+  coord[3] = g.dz.div(zt);
+  coord[2] = zt - coord[3] * (uint32_t)g.L[2];
+}
+
+// Both hops of direction MU for one site, accumulated into acc:
+// acc += (1 + sf g_mu) U_mu(x) psi(x+mu) + (1 - sf g_mu) U_mu(x-mu)^+ psi(x-mu),
+// sf = -1 for M, +1 for M^H.
+template <int MU, typename VS, typename LS, bool COMP, int SF>
+__device__ __forceinline__ void hop_dir(const VS* __restrict__ in, const LS* __restrict__ u,
+                                        const Geom& g, uint32_t s, const uint32_t* coord,
+                                        cpx<typename Storage<VS>::real>* acc) {
+  using R = typename Storage<VS>::real;
+  const size_t vs = (size_t)g.vs;
+  const uint32_t c_ = coord[MU];
+  const uint32_t st_ = (uint32_t)g.stride[MU];
+  const uint32_t span_ = (uint32_t)(g.L[MU] - 1) * st_;
+  const uint32_t sf_ = (c_ + 1 < (uint32_t)g.L[MU]) ? s + st_ : s - span_;
+  const uint32_t sb_ = (c_ > 0) ? s - st_ : s + span_;
+  {
+    cpx<R> U[9];
+    load_link<LS, COMP>(u, MU, vs, s, U);
+    cpx<R> h[6];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      cpx<R> u0 = Storage<VS>::ld(in, (size_t)(0 + a) * vs + sf_);
+      cpx<R> u1 = Storage<VS>::ld(in, (size_t)(3 + a) * vs + sf_);
+      cpx<R> l0 = Storage<VS>::ld(in, (size_t)(6 + a) * vs + sf_);
+      cpx<R> l1 = Storage<VS>::ld(in, (size_t)(9 + a) * vs + sf_);
+      project<MU, SF>(u0, u1, l0, l1, h[a], h[3 + a]);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      cpx<R> g0 = cmul(U[a * 3 + 0], h[0]);
+      cpx<R> g1 = cmul(U[a * 3 + 0], h[3]);
+      g0 = cadd(g0, cmul(U[a * 3 + 1], h[1]));
+      g1 = cadd(g1, cmul(U[a * 3 + 1], h[4]));
+      g0 = cadd(g0, cmul(U[a * 3 + 2], h[2]));
+      g1 = cadd(g1, cmul(U[a * 3 + 2], h[5]));
+      accumulate<MU, SF>(acc, a, g0, g1);
+    }
+  }
+  {
+    cpx<R> U[9];
+    load_link<LS, COMP>(u, MU, vs, sb_, U);
+    cpx<R> h[6];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      cpx<R> u0 = Storage<VS>::ld(in, (size_t)(0 + a) * vs + sb_);
+      cpx<R> u1 = Storage<VS>::ld(in, (size_t)(3 + a) * vs + sb_);
+      cpx<R> l0 = Storage<VS>::ld(in, (size_t)(6 + a) * vs + sb_);
+      cpx<R> l1 = Storage<VS>::ld(in, (size_t)(9 + a) * vs + sb_);
+      project<MU, -SF>(u0, u1, l0, l1, h[a], h[3 + a]);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      cpx<R> g0 = cmulc(U[0 * 3 + a], h[0]);
+      cpx<R> g1 = cmulc(U[0 * 3 + a], h[3]);
+      g0 = cadd(g0, cmulc(U[1 * 3 + a], h[1]));
+      g1 = cadd(g1, cmulc(U[1 * 3 + a], h[4]));
+      g0 = cadd(g0, cmulc(U[2 * 3 + a], h[2]));
+      g1 = cadd(g1, cmulc(U[2 * 3 + a], h[5]));
+      accumulate<MU, -SF>(acc, a, g0, g1);
+    }
+  }
+}
+
+// Hopping sum over all four directions for one site.
 template <typename VS, typename LS, bool COMP, int SF>
 __device__ __forceinline__ void hopping_site(const VS* __restrict__ in,
                                              const LS* __restrict__ u, const Geom& g,
                                              uint32_t s, cpx<typename Storage<VS>::real>* acc) {
   using R = typename Storage<VS>::real;
-  const size_t vs = (size_t)g.vs;
-  const uint32_t xyz = g.dx.div(s);
-  const uint32_t x = s - xyz * (uint32_t)g.L[0];
-  const uint32_t zt = g.dy.div(xyz);
-  const uint32_t y = xyz - zt * (uint32_t)g.L[1];
-  const uint32_t t = g.dz.div(zt);
-  const uint32_t z = zt - t * (uint32_t)g.L[2];
-  const uint32_t coord[4] = {x, y, z, t};
+  uint32_t coord[4];
+  site_coords(g, s, coord);
 #pragma unroll
   for (int e = 0; e < 12; ++e) acc[e] = {R(0), R(0)};
-
-#define EIGCG_HOP(MU)                                                                        \
-  {                                                                                          \
-    const uint32_t c_ = coord[MU];                                                           \
-    const uint32_t st_ = (uint32_t)g.stride[MU];                                             \
-    const uint32_t span_ = (uint32_t)(g.L[MU] - 1) * st_;                                    \
-    const uint32_t sf_ = (c_ + 1 < (uint32_t)g.L[MU]) ? s + st_ : s - span_;                 \
-    const uint32_t sb_ = (c_ > 0) ? s - st_ : s + span_;                                     \
-    {                                                                                        \
-      cpx<R> U[9];                                                                           \
-      load_link<LS, COMP>(u, MU, vs, s, U);                                                  \
-      cpx<R> h[6];                                                                           \
-      _Pragma("unroll") for (int a = 0; a < 3; ++a) {                                        \
-        cpx<R> u0 = Storage<VS>::ld(in, (size_t)(0 + a) * vs + sf_);                         \
-        cpx<R> u1 = Storage<VS>::ld(in, (size_t)(3 + a) * vs + sf_);                         \
-        cpx<R> l0 = Storage<VS>::ld(in, (size_t)(6 + a) * vs + sf_);                         \
-        cpx<R> l1 = Storage<VS>::ld(in, (size_t)(9 + a) * vs + sf_);                         \
-        project<MU, SF>(u0, u1, l0, l1, h[a], h[3 + a]);                                     \
-      }                                                                                      \
-      _Pragma("unroll") for (int a = 0; a < 3; ++a) {                                        \
-        cpx<R> g0 = cmul(U[a * 3 + 0], h[0]);                                                \
-        cpx<R> g1 = cmul(U[a * 3 + 0], h[3]);                                                \
-        g0 = cadd(g0, cmul(U[a * 3 + 1], h[1]));                                             \
-        g1 = cadd(g1, cmul(U[a * 3 + 1], h[4]));                                             \
-        g0 = cadd(g0, cmul(U[a * 3 + 2], h[2]));                                             \
-        g1 = cadd(g1, cmul(U[a * 3 + 2], h[5]));                                             \
-        accumulate<MU, SF>(acc, a, g0, g1);                                                  \
-      }                                                                                      \
-    }                                                                                        \
-    {                                                                                        \
-      cpx<R> U[9];                                                                           \
-      load_link<LS, COMP>(u, MU, vs, sb_, U);                                                \
-      cpx<R> h[6];                                                                           \
-      _Pragma("unroll") for (int a = 0; a < 3; ++a) {                                        \
-        cpx<R> u0 = Storage<VS>::ld(in, (size_t)(0 + a) * vs + sb_);                         \
-        cpx<R> u1 = Storage<VS>::ld(in, (size_t)(3 + a) * vs + sb_);                         \
-        cpx<R> l0 = Storage<VS>::ld(in, (size_t)(6 + a) * vs + sb_);                         \
-        cpx<R> l1 = Storage<VS>::ld(in, (size_t)(9 + a) * vs + sb_);                         \
-        project<MU, -SF>(u0, u1, l0, l1, h[a], h[3 + a]);                                    \
-      }                                                                                      \
-      _Pragma("unroll") for (int a = 0; a < 3; ++a) {                                        \
-        cpx<R> g0 = cmulc(U[0 * 3 + a], h[0]);                                               \
-        cpx<R> g1 = cmulc(U[0 * 3 + a], h[3]);                                               \
-        g0 = cadd(g0, cmulc(U[1 * 3 + a], h[1]));                                            \
-        g1 = cadd(g1, cmulc(U[1 * 3 + a], h[4]));                                            \
-        g0 = cadd(g0, cmulc(U[2 * 3 + a], h[2]));                                            \
-        g1 = cadd(g1, cmulc(U[2 * 3 + a], h[5]));                                            \
-        accumulate<MU, -SF>(acc, a, g0, g1);                                                 \
-      }                                                                                      \
-    }                                                                                        \
-  }
-  EIGCG_HOP(0)
-  EIGCG_HOP(1)
-  EIGCG_HOP(2)
-  EIGCG_HOP(3)
-#undef EIGCG_HOP
+  hop_dir<0, VS, LS, COMP, SF>(in, u, g, s, coord, acc);
+  hop_dir<1, VS, LS, COMP, SF>(in, u, g, s, coord, acc);
+  hop_dir<2, VS, LS, COMP, SF>(in, u, g, s, coord, acc);
+  hop_dir<3, VS, LS, COMP, SF>(in, u, g, s, coord, acc);
 }
 
 }  // namespace eigcg

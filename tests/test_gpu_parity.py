@@ -37,11 +37,11 @@ CASES = [
 
 
 @pytest.mark.parametrize("name,dims,eps,seed,mass", CASES)
-@pytest.mark.parametrize("compress", [0, 1])
-def test_apply_matches_oracle(B, name, dims, eps, seed, mass, compress):
+@pytest.mark.parametrize("compress,variant", [(0, 1), (1, 1), (1, 2), (1, 3), (0, 3)])
+def test_apply_matches_oracle(B, name, dims, eps, seed, mass, compress, variant):
     U = gauge_field(dims, eps, seed)
     op = WilsonOperator(U, mass)
-    ctx, _ = make_ctx(U, mass, compress_links=compress, max_batch=2)
+    ctx, _ = make_ctx(U, mass, compress_links=compress, max_batch=2, stencil_variant=variant)
     try:
         psi = gaussian_rhs_block(dims, [11, 12])
         inp = dev(psi)
@@ -89,10 +89,11 @@ def cfg0():
     return U, op, b
 
 
-def test_cg_parity_cfg0(B, cfg0):
+@pytest.mark.parametrize("variant", [1, 2, 3])
+def test_cg_parity_cfg0(B, cfg0, variant):
     U, op, b = cfg0
     xo, io = cg(op.A, b.reshape(-1), tol=1e-10)
-    ctx, _ = make_ctx(U, -0.2, max_iter=5000)
+    ctx, _ = make_ctx(U, -0.2, max_iter=5000, stencil_variant=variant)
     try:
         x = dev(np.zeros((1,) + b.shape, dtype=np.complex128))
         rc, st = B.eigcg_solve(ctx, dev(b[None]), x, 1e-10, B.EIGCG_MODE_CG)
