@@ -48,9 +48,15 @@ def site_bytes_stencil(two_row_links: bool, elem=16):
     return 12 * elem + links + 12 * elem
 
 
+SAMPLE_EVERY = 4  # stencil passes of every 4th CG iteration are timed with events
+STENCIL_SOURCES = ("paper_0707_0131_amd/csrc/dslash.hip", "paper_0707_0131_amd/csrc/wilson.h",
+                   "paper_0707_0131_amd/csrc/common.h")
+TRAFFIC_SUMMARY = "profiles/k_wilson_pair_cgr_f64_16x16x16x32.md"
+
+
 def run_step(B, torch, g, mass, bt, xt, n_eig=N_EIG):
     p = B.eigcg_default_params(dims=LATTICE, mass=mass, nev=NEV, m=M, max_bank=NBANK,
-                               max_iter=40000, check_every=16)
+                               max_iter=40000, check_every=16, sample_every=SAMPLE_EVERY)
     ctx = B.eigcg_create(p, g)
     try:
         xt.zero_()
@@ -62,6 +68,7 @@ def run_step(B, torch, g, mass, bt, xt, n_eig=N_EIG):
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         vals, _ = B.eigcg_bank_info(ctx)
+        samples = B.eigcg_kernel_samples(ctx)["f64"]
     finally:
         B.eigcg_destroy(ctx)
     bad = [s for s in st1 + st2 if s["status"] != 0 or s["true_rel_res"] > TOL]
@@ -75,6 +82,7 @@ def run_step(B, torch, g, mass, bt, xt, n_eig=N_EIG):
         "failed": len(bad),
         "bank_lambda_min": float(vals[0]) if len(vals) else None,
         "bank_size": int(len(vals)),
+        "samples": samples,
     }
 
 
@@ -93,6 +101,30 @@ def plain_cg(B, torch, g, mass, bt, xt, n):
     return dt, [s["iters"] for s in st], max(s["true_rel_res"] for s in st)
 
 
+def source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in STENCIL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, or None when the stencil sources changed since it was taken."""
+    import re
+    path = os.path.join(ROOT, TRAFFIC_SUMMARY)
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"source_sha256_16:\s*([0-9a-f]{16})", txt)
+    t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m or not t or m.group(1) != source_hash():
+        return None
+    return float(t.group(1))
+
+
 def stencil_roofline(B, torch, dims, seed, reps):
     from synthetic import gauge_field
     U = gauge_field(dims, EPS, seed)
@@ -103,13 +135,13 @@ def stencil_roofline(B, torch, dims, seed, reps):
     try:
         info = B.eigcg_layout_info(ctx)
         ms_m = B.eigcg_time_kernel(ctx, 0, reps)
-        ms_r = B.eigcg_time_kernel(ctx, 1, reps)
+        ms_copy = B.eigcg_time_kernel(ctx, 1, reps)
         ms_it = B.eigcg_time_kernel(ctx, 2, max(1, reps // 4))
     finally:
         B.eigcg_destroy(ctx)
     V = info["sites"]
     bytes_m = V * site_bytes_stencil(info["links64_two_rows"])
-    bytes_r = bytes_m + V * 192  # + read of r (r is the written output)
+    bytes_copy = 2 * 16 * 12 * info["plane_stride"]  # one padded FP64 field read + written
     return {
         "sites": V,
         "two_row_links": info["links64_two_rows"],
@@ -117,8 +149,8 @@ def stencil_roofline(B, torch, dims, seed, reps):
         "variant_ms": info["tune_ms64"],
         "stencil_M_ms": ms_m,
         "stencil_M_GBs": bytes_m / ms_m / 1e6,
-        "stencil_Mdag_cgr_ms": ms_r,
-        "stencil_Mdag_cgr_GBs": bytes_r / ms_r / 1e6,
+        "copy_ms": ms_copy,
+        "copy_GBs": bytes_copy / ms_copy / 1e6,
         "cg_iteration_ms": ms_it,
         "bytes_per_launch_M": bytes_m,
     }
@@ -161,8 +193,9 @@ def main():
     ap.add_argument("--n-eig", type=int, default=N_EIG, help="phase-1 RHS per step (profiling)")
     ap.add_argument("--n-defl", type=int, default=N_DEFL, help="phase-2 RHS per step (profiling)")
     ap.add_argument("--no-roofline", action="store_true")
-    ap.add_argument("--roofline-only", action="store_true",
-                    help="only time the stencil on the HBM-bound lattice (for counter runs)")
+    ap.add_argument("--roofline-only", choices=("bench", "hbm"),
+                    help="only time the stencil, copy and CG iteration on the bench lattice "
+                         "or the 24^3x48 lattice (short runs for counter collection)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -175,9 +208,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.roofline_only:
-        log(f"stencil roofline only ({HBM_LATTICE})")
-        print(json.dumps({"stencil_hbm_lattice": stencil_roofline(B, torch, HBM_LATTICE, HBM_SEED,
-                                                                  100)}))
+        dims, seed = (LATTICE, SEED) if args.roofline_only == "bench" else (HBM_LATTICE, HBM_SEED)
+        log(f"stencil timings only ({dims})")
+        print(json.dumps({"stencil": stencil_roofline(B, torch, dims, seed, 100)}))
         return
     log(f"generating {LATTICE} links and {args.n_eig + args.n_defl} right-hand sides")
     U = gauge_field(LATTICE, EPS, SEED)
@@ -245,7 +278,18 @@ def main():
         log("CPU oracle baseline (bounded sample)")
         cpu = cpu_baseline(total_rhs, total_iters)
 
-    achieved = roof_hbm["stencil_M_GBs"] if roof_hbm else None
+    # dominant kernel: the second stencil pass of every CG iteration (M^H fused
+    # with r -= alpha t and ||r||^2), timed live with events on the solver's
+    # stream during the timed steps
+    n_s = sum(s["samples"]["n"] for s in steps)
+    pass2_ms = sum(s["samples"]["n"] * s["samples"]["pass2_ms"] for s in steps) / max(1, n_s)
+    pass1_ms = sum(s["samples"]["n"] * s["samples"]["pass1_ms"] for s in steps) / max(1, n_s)
+    V = LATTICE[0] * LATTICE[1] * LATTICE[2] * LATTICE[3]
+    # per site: t in (192 B), two-row links (384 B), r in and out (2 x 192 B)
+    pass2_bytes = V * (192 + 384 + 192 + 192)
+    pass1_bytes = V * site_bytes_stencil(True)  # p in, links, t out
+    achieved = pass2_bytes / pass2_ms / 1e6 if n_s else None
+    traffic = measured_traffic()
     out = {
         "metric": "deflated RHS solves/sec at 1e-10 rel. residual vs plain CG; stencil HBM GB/s; p99",
         "value": value,
@@ -276,14 +320,19 @@ def main():
         "plain_cg": base,
         "roofline": {
             "bound": "hbm",
-            "kernel": "FP64 Wilson stencil M (k_wilson, store epilogue) on "
-                      f"{'x'.join(map(str, HBM_LATTICE))}",
+            "kernel": "k_wilson_pair FP64 M^H pass fused with the CG residual update "
+                      "(960 algorithmic B/site, 16^3x32)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS if achieved else None,
-            "traffic": None,
+            "traffic": traffic,
+            "launch_ms": pass2_ms,
+            "sampled_launches": n_s,
+            "algorithmic_bytes_per_launch": pass2_bytes,
         },
+        "stencil_pass1": {"launch_ms": pass1_ms, "GBs": pass1_bytes / pass1_ms / 1e6 if n_s else None,
+                          "algorithmic_bytes_per_launch": pass1_bytes},
         "stencil_bench_lattice": roof_small,
         "stencil_hbm_lattice": roof_hbm,
         "cpu_baseline": cpu,

@@ -79,11 +79,13 @@ typedef struct {
   int32_t use_graphs;     /* 1: replay CG iterations from a captured HIP graph */
   int32_t stencil_variant;/* 0: pick the fastest stencil kernel by timing at create
                              (cached per lattice shape and precision in the process);
-                             1..3: force a variant (see eigcg_layout_info) */
+                             1..9: force a variant (see eigcg_layout_info) */
   int32_t plane_pad;      /* extra sites (in units of 64) after each SoA plane so
                              that planes do not start on the same memory channel:
                              0 = library default, < 0 = none */
-  int32_t reserved;
+  int32_t sample_every;   /* > 0: time the two stencil passes of every n-th CG
+                             iteration with events on the context's stream
+                             (read with eigcg_kernel_samples); 0 = off */
 } eigcg_params;
 
 typedef struct {
@@ -158,20 +160,38 @@ int eigcg_memory(eigcg_ctx* ctx, uint64_t* bytes);
 /* info[0] = lattice sites V, info[1] = padded plane stride, info[2] = 1 when
  * the FP64 links are stored as two rows (12 reals), info[3] likewise for the
  * FP32 links of a mixed-precision context, info[4] / info[5] = stencil
- * variant used for FP64 / FP32 (1: thread per site, round-robin workgroups;
- * 2: thread per site, XCD-contiguous workgroups; 3: two waves per 64-site
- * tile, directions split, LDS exchange); info needs 6 entries.  tune_ms
- * (NULL or 6 doubles) receives the timed stencil ms of variants 1..3 for
- * FP64 then FP32 (0 where not timed). */
+ * variant used for FP64 / FP32; info needs 6 entries.  Variants:
+ *   1  thread per site, 256-site units dealt round-robin to workgroups
+ *   2  thread per site, XCD-contiguous chunks of units
+ *   3  two waves per 64-site tile (directions split, LDS exchange), XCD chunks
+ *   4  as 3 with streaming (nontemporal) epilogue loads and stores
+ *   5  as 4 with a grid of the resident size (one sweeping front per XCD)
+ *   6  as 5 with at most two workgroups per compute unit
+ *   7  as 5 with one workgroup per compute unit
+ *   8  as 5, each XCD sweeping its t-slab in (z, t, xy) tile order
+ *   9  as 8 with at most two workgroups per compute unit
+ * (8 and 9 need Lx Ly divisible by 64 and Lt by 8, else they run as 5 / 6).
+ * eigcg_tune_report: tune_ms (18 doubles) receives the ms that variants 1..9
+ * took for one CG-shaped pair of stencil passes at create, FP64 then FP32
+ * (0 where not timed, e.g. a forced variant). */
 int eigcg_layout_info(eigcg_ctx* ctx, int32_t* info);
 int eigcg_tune_report(eigcg_ctx* ctx, double* tune_ms);
 
 /* Average device time (ms) of one launch, from HIP events on the context's
- * stream around reps back-to-back launches: what 0 = FP64 stencil M, 1 = FP64
- * stencil M^H fused with the CG residual update and its reduction, 2 = one
- * full FP64 CG iteration (three kernels), 3 = FP32 stencil M (mixed contexts).
- * Runs on the context's internal work vectors (their contents change). */
+ * stream around reps back-to-back launches: what 0 = FP64 stencil M, 1 = plain
+ * copy of one FP64 field (12 V complex numbers read and written; a reference
+ * for memory counters), 2 = one full FP64 CG iteration (three kernels),
+ * 3 = FP32 stencil M (mixed contexts).  Runs on the context's internal work
+ * vectors (their contents change); reps + 8 must not exceed max_iter. */
 int eigcg_time_kernel(eigcg_ctx* ctx, int32_t what, int32_t reps, double* ms);
+
+/* Sampled stencil timings (params.sample_every).  out[0..3] for FP64 and
+ * out[4..7] for FP32 iterations: number of sampled iterations, mean duration in
+ * ms of the first pass (M p with the p^H A p partials), mean duration of the
+ * second pass (M^H fused with the residual update and its norm, without the
+ * one-workgroup finalize kernel), mean batch width.  Waits for the context's
+ * stream; reset != 0 clears the accumulated samples. */
+int eigcg_kernel_samples(eigcg_ctx* ctx, int32_t reset, double* out);
 
 const char* eigcg_last_error(const eigcg_ctx* ctx);
 

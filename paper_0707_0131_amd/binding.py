@@ -19,6 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libeigcg.so")
 
 EIGCG_OK, EIGCG_EINVAL, EIGCG_ENOMEM, EIGCG_ENOTCONV = 0, -1, -2, -3
+STENCIL_VARIANTS = 9
 EIGCG_EBREAKDOWN, EIGCG_EHIP, EIGCG_EBUSY = -4, -5, -6
 EIGCG_FP64, EIGCG_MIXED_FP32 = 0, 1
 EIGCG_MODE_CG, EIGCG_MODE_EIGCG, EIGCG_MODE_INITCG = 0, 1, 2
@@ -46,7 +47,7 @@ class Params(ctypes.Structure):
         ("use_graphs", ctypes.c_int32),
         ("stencil_variant", ctypes.c_int32),
         ("plane_pad", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("sample_every", ctypes.c_int32),
     ]
 
 
@@ -89,6 +90,7 @@ SIGNATURES = {
     "eigcg_layout_info": (_I32, [_VP, ctypes.POINTER(_I32)]),
     "eigcg_tune_report": (_I32, [_VP, _DP]),
     "eigcg_time_kernel": (_I32, [_VP, _I32, _I32, _DP]),
+    "eigcg_kernel_samples": (_I32, [_VP, _I32, _DP]),
     "eigcg_server_create": (_I32, [ctypes.c_uint64, ctypes.POINTER(_VP)]),
     "eigcg_server_add": (_I32, [_VP, _VP, ctypes.POINTER(_I32)]),
     "eigcg_submit": (_I32, [_VP, _I32, _VP, _VP, ctypes.c_double, ctypes.POINTER(ctypes.c_uint64)]),
@@ -260,11 +262,11 @@ def eigcg_memory(ctx):
 def eigcg_layout_info(ctx):
     info = (_I32 * 6)()
     LIB.eigcg_layout_info(ctx, info)
-    ms = np.zeros(6)
+    ms = np.zeros(2 * STENCIL_VARIANTS)
     LIB.eigcg_tune_report(ctx, _dptr(ms))
     return {"sites": info[0], "plane_stride": info[1], "links64_two_rows": bool(info[2]),
             "links32_two_rows": bool(info[3]), "variant64": info[4], "variant32": info[5],
-            "tune_ms64": ms[:3].tolist(), "tune_ms32": ms[3:].tolist()}
+            "tune_ms64": ms[:STENCIL_VARIANTS].tolist(), "tune_ms32": ms[STENCIL_VARIANTS:].tolist()}
 
 
 def eigcg_time_kernel(ctx, what, reps):
@@ -273,6 +275,17 @@ def eigcg_time_kernel(ctx, what, reps):
     if rc != EIGCG_OK:
         raise EigcgError(rc, eigcg_last_error(ctx))
     return ms.value
+
+
+def eigcg_kernel_samples(ctx, reset=False):
+    """Sampled stencil pass timings: {"f64": {...}, "f32": {...}} with the
+    number of sampled iterations, mean ms of pass 1 and pass 2, mean batch width."""
+    out = (ctypes.c_double * 8)()
+    rc = LIB.eigcg_kernel_samples(ctx, int(bool(reset)), out)
+    if rc != EIGCG_OK:
+        raise EigcgError(rc, eigcg_last_error(ctx))
+    keys = ("n", "pass1_ms", "pass2_ms", "cols")
+    return {"f64": dict(zip(keys, out[0:4])), "f32": dict(zip(keys, out[4:8]))}
 
 
 # ---- serving ----------------------------------------------------------------

@@ -58,8 +58,9 @@ int validate(const eigcg_params* p, std::string& why) {
   if (p->max_batch < 1 || p->max_batch > 12) { why = "max_batch must be in [1, 12]"; return EIGCG_EINVAL; }
   if (p->max_iter < 1 || p->max_iter > 10000000) { why = "bad max_iter"; return EIGCG_EINVAL; }
   if (p->check_every < 1) { why = "check_every must be >= 1"; return EIGCG_EINVAL; }
-  if (p->stencil_variant < 0 || p->stencil_variant > 3) { why = "stencil_variant must be 0..3"; return EIGCG_EINVAL; }
+  if (p->stencil_variant < 0 || p->stencil_variant > eigcg::kStencilVariants) { why = "stencil_variant out of range"; return EIGCG_EINVAL; }
   if (p->plane_pad > 4096) { why = "plane_pad too large"; return EIGCG_EINVAL; }
+  if (p->sample_every < 0) { why = "sample_every must be >= 0"; return EIGCG_EINVAL; }
   if (p->precision == EIGCG_MIXED_FP32 && p->reliable_every < 1) { why = "reliable_every must be >= 1"; return EIGCG_EINVAL; }
   return EIGCG_OK;
 }
@@ -87,6 +88,7 @@ int eigcg_default_params(eigcg_params* p) {
   p->use_graphs = 0;
   p->stencil_variant = 0;
   p->plane_pad = 0;
+  p->sample_every = 0;
   return EIGCG_OK;
 }
 
@@ -227,7 +229,7 @@ int eigcg_layout_info(eigcg_ctx* ctx, int32_t* info) {
 
 int eigcg_tune_report(eigcg_ctx* ctx, double* tune_ms) {
   if (!ctx || !tune_ms) return EIGCG_EINVAL;
-  for (int i = 0; i < 6; ++i) tune_ms[i] = ctx->c.tune_ms[i];
+  for (int i = 0; i < 2 * eigcg::kStencilVariants; ++i) tune_ms[i] = ctx->c.tune_ms[i];
   return EIGCG_OK;
 }
 
@@ -235,6 +237,14 @@ int eigcg_time_kernel(eigcg_ctx* ctx, int32_t what, int32_t reps, double* ms) {
   if (!ctx || !ms || reps < 1 || what < 0 || what > 3) return EIGCG_EINVAL;
   return guarded(ctx, [&] {
     *ms = eigcg::bench_kernels(ctx->c, what, reps);
+    return EIGCG_OK;
+  });
+}
+
+int eigcg_kernel_samples(eigcg_ctx* ctx, int32_t reset, double* out) {
+  if (!ctx || !out) return EIGCG_EINVAL;
+  return guarded(ctx, [&] {
+    eigcg::kernel_samples(ctx->c, reset != 0, out);
     return EIGCG_OK;
   });
 }

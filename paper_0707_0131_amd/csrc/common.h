@@ -103,6 +103,10 @@ template <typename R> __device__ __forceinline__ cpx<R> cneg(cpx<R> a) { return 
 
 // --- storage types -----------------------------------------------------------
 template <typename S> struct Storage;
+// ld_nt / st_nt: streaming (nontemporal) access for data touched once per
+// launch, so that it does not displace reused stencil data from the L2.
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+typedef float nt_f2 __attribute__((ext_vector_type(2)));
 template <> struct Storage<double2> {
   using real = double;
   __device__ static __forceinline__ cpx<double> ld(const double2* p, size_t i) {
@@ -111,6 +115,16 @@ template <> struct Storage<double2> {
   }
   __device__ static __forceinline__ void st(double2* p, size_t i, cpx<double> v) {
     p[i] = make_double2(v.re, v.im);
+  }
+  __device__ static __forceinline__ cpx<double> ld_nt(const double2* p, size_t i) {
+    const nt_d2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(p) + i);
+    return {v.x, v.y};
+  }
+  __device__ static __forceinline__ void st_nt(double2* p, size_t i, cpx<double> v) {
+    nt_d2 w;
+    w.x = v.re;
+    w.y = v.im;
+    __builtin_nontemporal_store(w, reinterpret_cast<nt_d2*>(p) + i);
   }
 };
 template <> struct Storage<float2> {
@@ -121,6 +135,16 @@ template <> struct Storage<float2> {
   }
   __device__ static __forceinline__ void st(float2* p, size_t i, cpx<float> v) {
     p[i] = make_float2(v.re, v.im);
+  }
+  __device__ static __forceinline__ cpx<float> ld_nt(const float2* p, size_t i) {
+    const nt_f2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f2*>(p) + i);
+    return {v.x, v.y};
+  }
+  __device__ static __forceinline__ void st_nt(float2* p, size_t i, cpx<float> v) {
+    nt_f2 w;
+    w.x = v.re;
+    w.y = v.im;
+    __builtin_nontemporal_store(w, reinterpret_cast<nt_f2*>(p) + i);
   }
 };
 

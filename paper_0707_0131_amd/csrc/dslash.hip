@@ -11,6 +11,8 @@
 // updates the CG scalars of every column.
 #include <algorithm>
 
+#include <mutex>
+
 #include "kernels.h"
 #include "wilson.h"
 
@@ -33,6 +35,7 @@ struct DevArgs {
   const void* b; size_t b_cs;
   void* tbuf; size_t t_cs;
   double* hist; int hist_stride;
+  uint32_t ord_P, ord_Ls;   // slab sweep: 64-site tiles per xy-plane, t-slices per XCD
 };
 
 // Work units (blocks of sites) handed to workgroups.  With xcd set, the
@@ -57,7 +60,7 @@ struct Units {
 };
 
 // CG epilogue for components [C0, C0 + NC) of site s, given o = op(in) there.
-template <typename VS, int EPI, int C0, int NC>
+template <typename VS, int EPI, int C0, int NC, bool NT = false>
 __device__ __forceinline__ void epilogue(const DevArgs& a, int col, uint32_t s,
                                          const cpx<typename Storage<VS>::real>* o,
                                          typename Storage<VS>::real alpha, bool save_t,
@@ -68,7 +71,8 @@ __device__ __forceinline__ void epilogue(const DevArgs& a, int col, uint32_t s,
     VS* out = reinterpret_cast<VS*>(a.out) + (size_t)col * a.out_cs;
 #pragma unroll
     for (int e = C0; e < C0 + NC; ++e) {
-      Storage<VS>::st(out, (size_t)e * vs + s, o[e]);
+      if (NT) Storage<VS>::st_nt(out, (size_t)e * vs + s, o[e]);
+      else Storage<VS>::st(out, (size_t)e * vs + s, o[e]);
       if (EPI == kEpiNorm) acc2 += o[e].re * o[e].re + o[e].im * o[e].im;
     }
   } else if (EPI == kEpiCGR) {
@@ -80,10 +84,11 @@ __device__ __forceinline__ void epilogue(const DevArgs& a, int col, uint32_t s,
     }
 #pragma unroll
     for (int e = C0; e < C0 + NC; ++e) {
-      cpx<R> rv = Storage<VS>::ld(r, (size_t)e * vs + s);
+      cpx<R> rv = NT ? Storage<VS>::ld_nt(r, (size_t)e * vs + s) : Storage<VS>::ld(r, (size_t)e * vs + s);
       rv.re -= alpha * o[e].re;
       rv.im -= alpha * o[e].im;
-      Storage<VS>::st(r, (size_t)e * vs + s, rv);
+      if (NT) Storage<VS>::st_nt(r, (size_t)e * vs + s, rv);
+      else Storage<VS>::st(r, (size_t)e * vs + s, rv);
       acc2 += rv.re * rv.re + rv.im * rv.im;
     }
   } else {  // kEpiRes: r = b - op(in)
@@ -91,9 +96,10 @@ __device__ __forceinline__ void epilogue(const DevArgs& a, int col, uint32_t s,
     const VS* b = reinterpret_cast<const VS*>(a.b) + (size_t)col * a.b_cs;
 #pragma unroll
     for (int e = C0; e < C0 + NC; ++e) {
-      cpx<R> bv = Storage<VS>::ld(b, (size_t)e * vs + s);
+      cpx<R> bv = NT ? Storage<VS>::ld_nt(b, (size_t)e * vs + s) : Storage<VS>::ld(b, (size_t)e * vs + s);
       cpx<R> rv = {bv.re - o[e].re, bv.im - o[e].im};
-      Storage<VS>::st(r, (size_t)e * vs + s, rv);
+      if (NT) Storage<VS>::st_nt(r, (size_t)e * vs + s, rv);
+      else Storage<VS>::st(r, (size_t)e * vs + s, rv);
       acc2 += rv.re * rv.re + rv.im * rv.im;
     }
   }
@@ -171,7 +177,7 @@ __global__ __launch_bounds__(kBlock) void k_wilson(DevArgs a) {
 // swap half of their partial sums through LDS and each finishes six of the
 // twelve output components, so per-thread state is half of variant 1's and
 // twice as many waves stream the lattice.
-template <typename VS, typename LS, bool COMP, bool DAG, int EPI>
+template <typename VS, typename LS, bool COMP, bool DAG, int EPI, bool NT, int ORD>
 __global__ __launch_bounds__(kBlock) void k_wilson_pair(DevArgs a) {
   using R = typename Storage<VS>::real;
   __shared__ double lds4[kBlock / 64];
@@ -189,11 +195,8 @@ __global__ __launch_bounds__(kBlock) void k_wilson_pair(DevArgs a) {
   const int odd = (threadIdx.x >> 6) & 1;
   const int lane = threadIdx.x & 63;
   R acc2 = R(0);
-  if (active) {
-    const uint32_t T = ((uint32_t)a.g.V + 127u) / 128u;
-    for (Units it(T, true); it.u < it.end; it.u += it.step) {
-      const uint32_t s = it.u * 128u + tile * 64u + lane;
-      const bool valid = s < (uint32_t)a.g.V;
+  // one 128-site unit: tile `tile` of this workgroup covers sites s (valid)
+  auto unit = [&](uint32_t s, bool valid) {
       cpx<R> acc[12];
 #pragma unroll
       for (int e = 0; e < 12; ++e) acc[e] = {R(0), R(0)};
@@ -227,7 +230,7 @@ __global__ __launch_bounds__(kBlock) void k_wilson_pair(DevArgs a) {
           const R hr = acc[e].re + p.re, hi = acc[e].im + p.im;
           o[e] = {d * v.re - R(0.5) * hr, d * v.im - R(0.5) * hi};
         }
-        if (valid) epilogue<VS, EPI, 0, 6>(a, col, s, o, alpha, save_t, save_slot, acc2);
+        if (valid) epilogue<VS, EPI, 0, 6, NT>(a, col, s, o, alpha, save_t, save_slot, acc2);
       } else {
 #pragma unroll
         for (int e = 6; e < 12; ++e) {
@@ -236,9 +239,37 @@ __global__ __launch_bounds__(kBlock) void k_wilson_pair(DevArgs a) {
           const R hr = p.re + acc[e].re, hi = p.im + acc[e].im;
           o[e] = {d * v.re - R(0.5) * hr, d * v.im - R(0.5) * hi};
         }
-        if (valid) epilogue<VS, EPI, 6, 6>(a, col, s, o, alpha, save_t, save_slot, acc2);
+        if (valid) epilogue<VS, EPI, 6, 6, NT>(a, col, s, o, alpha, save_t, save_slot, acc2);
       }
       __syncthreads();
+  };
+  if (active) {
+    if (ORD == 0) {
+      const uint32_t T = ((uint32_t)a.g.V + 127u) / 128u;
+      for (Units it(T, true); it.u < it.end; it.u += it.step) {
+        const uint32_t s = it.u * 128u + tile * 64u + lane;
+        unit(s, s < (uint32_t)a.g.V);
+      }
+    } else {
+      // XCD x owns the t-slab [x Ls, (x + 1) Ls) and visits its 64-site tiles
+      // (P per xy-plane) in (z, t, xy) order: t-neighbours are P tiles apart
+      // and z-neighbours Ls P tiles apart in the sweep, so both are still in
+      // the XCD's L2 when the sweeping front reaches them
+      const uint32_t x = blockIdx.x & 7u, step = gridDim.x >> 3;
+      const uint32_t P = a.ord_P, Ls = a.ord_Ls;
+      const uint32_t ntx = P * Ls * (uint32_t)a.g.L[2];
+      const uint32_t units = (ntx + 1u) >> 1;
+      for (uint32_t un = blockIdx.x >> 3; un < units; un += step) {
+        const uint32_t pos = 2u * un + (uint32_t)tile;
+        const bool valid = pos < ntx;
+        uint32_t s = 0;
+        if (valid) {
+          const uint32_t xyt = pos % P, rest = pos / P;
+          const uint32_t t = x * Ls + rest % Ls, z = rest / Ls;
+          s = ((t * (uint32_t)a.g.L[2] + z) * P + xyt) * 64u + (uint32_t)lane;
+        }
+        unit(s, valid);
+      }
     }
   }
   if (EPI == kEpiStore) return;
@@ -314,6 +345,46 @@ __global__ __launch_bounds__(kBlock) void k_finalize_res(ColState* st, int ncols
   }
 }
 
+// Two-tile kernel occupancy control.  `per_cu` > 0 caps the workgroups that
+// share a CU by reserving LDS (fewer misses in flight per XCD, so stencil
+// neighbours stay in the L2 until their second use); 0 leaves the natural
+// occupancy.  Returns the dynamic LDS bytes to request and sets the number of
+// workgroups resident on the whole device (a multiple of 8).
+template <typename VS, typename LS>
+size_t pair_occupancy(int per_cu, int* resident) {
+  struct Info { size_t lds; int resident; };
+  static Info cache[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lk(mu);
+  Info& I = cache[per_cu & 3];
+  if (I.resident == 0) {
+    auto kern = k_wilson_pair<VS, LS, true, false, kEpiCGR, true, 0>;
+    int dev = 0, cus = 0, lds_cu = 0, lds_wg = 0, per = 0;
+    hipFuncAttributes fa{};
+    size_t extra = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) ==
+            hipSuccess &&
+        hipDeviceGetAttribute(&lds_wg, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) ==
+            hipSuccess &&
+        hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(kern)) == hipSuccess) {
+      if (per_cu > 0) {
+        // smallest per-workgroup LDS that lets only per_cu workgroups fit
+        const size_t want = (size_t)lds_cu / (size_t)(per_cu + 1) + 1024;
+        if (want > fa.sharedSizeBytes && want <= (size_t)lds_wg) extra = want - fa.sharedSizeBytes;
+      }
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, kBlock, extra) != hipSuccess)
+        per = 0;
+    }
+    I.lds = extra;
+    I.resident = (per > 0 && cus > 0) ? std::max(8, std::min(kMaxGrid, (per * cus) & ~7))
+                                      : kMaxGrid;
+  }
+  *resident = I.resident;
+  return I.lds;
+}
+
 template <typename VS, typename LS>
 hipError_t launch_typed(const StencilLaunch& L, hipStream_t s) {
   DevArgs a;
@@ -326,20 +397,40 @@ hipError_t launch_typed(const StencilLaunch& L, hipStream_t s) {
   a.partial_in = part_a;
   a.r = L.r; a.r_cs = L.r_cs; a.b = L.b; a.b_cs = L.b_cs;
   a.tbuf = L.tbuf; a.t_cs = L.t_cs; a.hist = L.hist; a.hist_stride = L.hist_stride;
-  const int variant = L.variant <= 0 ? 1 : L.variant;
-  const uint32_t unit = variant == 3 ? 128u : (uint32_t)kBlock;
+  int variant = L.variant <= 0 ? 1 : L.variant;
+  const uint32_t plane = (uint32_t)(L.g->L[0] * L.g->L[1]);
+  if (variant >= 8 && (plane % 64u != 0 || L.g->L[3] % 8 != 0))
+    variant = variant == 8 ? 5 : 6;  // the slab sweep needs whole tiles per plane, 8 slabs
+  a.ord_P = plane / 64u;
+  a.ord_Ls = (uint32_t)L.g->L[3] / 8u;
+  const uint32_t unit = variant >= 3 ? 128u : (uint32_t)kBlock;
   const uint32_t T = ((uint32_t)L.g->V + unit - 1) / unit;
   int gx;
+  size_t dyn_lds = 0;
   if (variant == 1) {
     gx = (int)std::min<uint32_t>(T, kMaxGrid);
+  } else if (variant >= 5) {
+    // as many workgroups as are resident at once (multiple of 8), so each
+    // XCD's workgroups sweep one contiguous front of its chunk
+    int res = 0;
+    const int per_cu = (variant == 6 || variant == 9) ? 2 : variant == 7 ? 1 : 0;
+    dyn_lds = pair_occupancy<VS, LS>(per_cu, &res);
+    gx = (int)std::min<uint32_t>((T + 7u) & ~7u, (uint32_t)res);
   } else {
     gx = (int)std::min<uint32_t>((T + 7u) & ~7u, kMaxGrid);  // a multiple of 8 (XCDs)
   }
   dim3 grid(gx, L.ncols), block(kBlock);
-#define EIGCG_K(COMP, DAG, EPI)                                                            \
-  if (variant == 3)                                                                        \
-    hipLaunchKernelGGL((k_wilson_pair<VS, LS, COMP, DAG, EPI>), grid, block, 0, s, a);     \
-  else if (variant == 2)                                                                   \
+#define EIGCG_K(COMP, DAG, EPI)                                                               \
+  if (variant >= 8)                                                                           \
+    hipLaunchKernelGGL((k_wilson_pair<VS, LS, COMP, DAG, EPI, true, 1>), grid, block, dyn_lds, \
+                       s, a);                                                                 \
+  else if (variant >= 4)                                                                      \
+    hipLaunchKernelGGL((k_wilson_pair<VS, LS, COMP, DAG, EPI, true, 0>), grid, block, dyn_lds, \
+                       s, a);                                                                 \
+  else if (variant == 3)                                                                      \
+    hipLaunchKernelGGL((k_wilson_pair<VS, LS, COMP, DAG, EPI, false, 0>), grid, block, 0, s,   \
+                       a);                                                                    \
+  else if (variant == 2)                                                                      \
     hipLaunchKernelGGL((k_wilson<VS, LS, COMP, DAG, EPI, true>), grid, block, 0, s, a);    \
   else                                                                                     \
     hipLaunchKernelGGL((k_wilson<VS, LS, COMP, DAG, EPI, false>), grid, block, 0, s, a);
@@ -359,6 +450,10 @@ hipError_t launch_typed(const StencilLaunch& L, hipStream_t s) {
 #undef EIGCG_K
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (L.ev_mid) {
+    e = hipEventRecord(L.ev_mid, s);
+    if (e != hipSuccess) return e;
+  }
   if (L.epi == kEpiCGR)
     hipLaunchKernelGGL(k_finalize_cg, dim3(1), dim3(kBlock), 0, s, L.st, L.ncols, L.mask, part_a,
                        part_b, gx, L.hist, L.hist_stride);

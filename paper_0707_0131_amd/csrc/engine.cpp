@@ -99,61 +99,78 @@ static StencilLaunch stencil_base(Ctx& c, int prec);
 // order at the rounding level).  A forced variant in the parameters wins.
 static void autotune_stencil(Ctx& c, int prec) {
   static std::mutex mu;
-  static std::map<std::vector<int>, int> cache;
+  static std::map<std::vector<int>, std::vector<double>> cache;
   int& var = prec == kF64 ? c.var64 : c.var32;
+  double* tms = c.tune_ms + (prec == kF64 ? 0 : kStencilVariants);
   if (c.P.stencil_variant > 0) {
     var = c.P.stencil_variant;
     return;
   }
   const std::vector<int> key = {c.g.L[0], c.g.L[1], c.g.L[2], c.g.L[3], c.g.vs, prec,
                                 prec == kF64 ? c.comp64 : c.comp32};
+  auto pick = [&](const std::vector<double>& t) {
+    int best = 1;
+    for (int v = 1; v <= kStencilVariants; ++v) {
+      tms[v - 1] = t[v - 1];
+      if (t[v - 1] < t[best - 1]) best = v;
+    }
+    var = best;
+  };
   {
     std::lock_guard<std::mutex> lk(mu);
     auto it = cache.find(key);
     if (it != cache.end()) {
-      var = it->second;
+      pick(it->second);
       return;
     }
   }
+  // Each candidate runs the two passes of a CG iteration with their memory
+  // traffic: M p -> t with the partial-sum epilogue, then M^H t against a
+  // right-hand side with the residual epilogue (reads b, writes r), on the
+  // context's scratch vectors and state slot.
   Workspace& w = prec == kF64 ? c.ws64 : c.ws32;
   ws_ensure(c, w, prec, false);
   hipEvent_t e0, e1;
   c.check(hipEventCreate(&e0), "ev");
   c.check(hipEventCreate(&e1), "ev");
-  double best = 1e30;
-  int best_v = 1;
-  for (int v = 1; v <= 3; ++v) {
-    StencilLaunch L = stencil_base(c, prec);
-    L.variant = v;
-    L.op = kOpM;
-    L.epi = kEpiStore;
-    L.in = w.x; L.in_cs = c.cs;
-    L.out = w.tmp; L.out_cs = c.cs;
-    L.ncols = 1;
-    L.mask = 1u;
-    for (int i = 0; i < 3; ++i) c.check(launch_stencil(L, c.stream), "tune");
-    const int reps = 12;
+  std::vector<double> t(kStencilVariants, 0.0);
+  for (int v = 1; v <= kStencilVariants; ++v) {
+    StencilLaunch L1 = stencil_base(c, prec);
+    L1.variant = v;
+    L1.op = kOpM;
+    L1.epi = kEpiNorm;
+    L1.in = w.x; L1.in_cs = c.cs;
+    L1.out = w.tmp; L1.out_cs = c.cs;
+    L1.ncols = 1;
+    L1.mask = 1u;
+    StencilLaunch L2 = L1;
+    L2.op = kOpMdag;
+    L2.epi = kEpiRes;
+    L2.in = w.tmp;
+    L2.b = w.p; L2.b_cs = c.cs;
+    L2.r = w.r; L2.r_cs = c.cs;
+    auto pair = [&]() {
+      c.check(launch_stencil(L1, c.stream), "tune");
+      c.check(launch_stencil(L2, c.stream), "tune");
+    };
+    for (int i = 0; i < 2; ++i) pair();
+    const int reps = 8;
     c.check(hipEventRecord(e0, c.stream), "ev");
-    for (int i = 0; i < reps; ++i) c.check(launch_stencil(L, c.stream), "tune");
+    for (int i = 0; i < reps; ++i) pair();
     c.check(hipEventRecord(e1, c.stream), "ev");
     c.check(hipEventSynchronize(e1), "ev");
     float ms = 0.f;
     c.check(hipEventElapsedTime(&ms, e0, e1), "ev");
-    const double t = (double)ms / reps;
-    c.tune_ms[(prec == kF64 ? 0 : 3) + v - 1] = t;
-    if (t < best) {
-      best = t;
-      best_v = v;
-    }
+    t[v - 1] = (double)ms / reps;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  c.check(hipMemsetAsync(w.tmp, 0, c.cs * elem_bytes(prec) * w.K, c.stream), "clear");
+  for (void* v : {w.tmp, w.r}) c.check(hipMemsetAsync(v, 0, c.cs * elem_bytes(prec) * w.K, c.stream), "clear");
   c.check(hipStreamSynchronize(c.stream), "sync");
   std::lock_guard<std::mutex> lk(mu);
   auto it = cache.find(key);
-  var = it != cache.end() ? it->second : best_v;
-  if (it == cache.end()) cache[key] = best_v;
+  if (it == cache.end()) it = cache.emplace(key, t).first;
+  pick(it->second);
 }
 
 void ctx_init(Ctx& c, const eigcg_params& p, const void* gauge_dev, hipStream_t s) {
@@ -250,6 +267,53 @@ void ctx_release(Ctx& c) {
   if (c.h_norm) (void)hipHostFree(c.h_norm);
   for (auto& e : c.events) (void)hipEventDestroy(e);
   c.events.clear();
+  for (auto& k : c.ks_pool)
+    for (auto& e : k.e) (void)hipEventDestroy(e);
+  c.ks_pool.clear();
+}
+
+// Fold the recorded stencil samples into the running sums.  All samples were
+// recorded on one in-order stream, so the last one completing means all have.
+bool Ctx::ks_harvest(bool wait) {
+  if (ks_used == 0) return true;
+  hipEvent_t last = ks_pool[ks_used - 1].e[2];
+  if (wait) {
+    check(hipEventSynchronize(last), "sample wait");
+  } else {
+    const hipError_t q = hipEventQuery(last);
+    if (q == hipErrorNotReady) return false;
+    check(q, "sample query");
+  }
+  for (int i = 0; i < ks_used; ++i) {
+    KSample& k = ks_pool[i];
+    float a = 0.f, b = 0.f;
+    check(hipEventElapsedTime(&a, k.e[0], k.e[1]), "sample time");
+    check(hipEventElapsedTime(&b, k.e[1], k.e[2]), "sample time");
+    const int p = k.prec == kF64 ? 0 : 1;
+    ks_sum[p][0] += a;
+    ks_sum[p][1] += b;
+    ks_n[p] += 1;
+    ks_cols[p] += k.ncols;
+  }
+  ks_used = 0;
+  return true;
+}
+
+void kernel_samples(Ctx& c, bool reset, double* out) {
+  c.ks_harvest(true);
+  for (int p = 0; p < 2; ++p) {
+    const double n = (double)c.ks_n[p];
+    out[4 * p + 0] = n;
+    out[4 * p + 1] = n > 0 ? c.ks_sum[p][0] / n : 0.0;
+    out[4 * p + 2] = n > 0 ? c.ks_sum[p][1] / n : 0.0;
+    out[4 * p + 3] = n > 0 ? (double)c.ks_cols[p] / n : 0.0;
+  }
+  if (reset) {
+    for (int p = 0; p < 2; ++p) {
+      c.ks_sum[p][0] = c.ks_sum[p][1] = 0.0;
+      c.ks_n[p] = c.ks_cols[p] = 0;
+    }
+  }
 }
 
 static int seg_len_eig(const eigcg_params& P) {
@@ -513,6 +577,23 @@ struct Run {
     return c.h_hist[(size_t)col * c.hist_stride + 3 * (k - 2) + 2];  // k >= 2
   }
 
+  // event triple for this iteration when it is sampled, else null
+  Ctx::KSample* sample_slot() {
+    const int every = c.P.sample_every;
+    if (every <= 0 || (c.ks_tick++ % every) != 0) return nullptr;
+    constexpr int kPool = 256;
+    if (c.ks_pool.empty()) {
+      c.ks_pool.resize(kPool);
+      for (auto& k : c.ks_pool)
+        for (auto& e : k.e) c.check(hipEventCreate(&e), "sample event");
+    }
+    if (c.ks_used == kPool && !c.ks_harvest(false)) return nullptr;
+    Ctx::KSample* k = &c.ks_pool[c.ks_used++];
+    k->prec = prec;
+    k->ncols = __builtin_popcount(mask);
+    return k;
+  }
+
   void enqueue_iters(int n) {
     StencilLaunch L1 = stencil_base(c, prec);
     L1.op = kOpM;
@@ -542,7 +623,11 @@ struct Run {
     L3.ring_len = w.ring_len;
     L3.ring_col_cs = (size_t)w.ring_len * c.cs;
     for (int i = 0; i < n; ++i) {
+      Ctx::KSample* ks = sample_slot();
+      if (ks) c.check(hipEventRecord(ks->e[0], c.stream), "sample");
       c.check(launch_stencil(L1, c.stream), "K1");
+      if (ks) c.check(hipEventRecord(ks->e[1], c.stream), "sample");
+      L2.ev_mid = ks ? ks->e[2] : nullptr;
       c.check(launch_stencil(L2, c.stream), "K2");
       c.check(launch_cg_update(L3, c.stream), "K3");
     }
@@ -1473,8 +1558,6 @@ double bench_kernels(Ctx& c, int what, int reps) {
   if (prec == kF32 && !c.u32) throw ApiError{EIGCG_EINVAL, "context has no FP32 links"};
   Workspace& w = prec == kF64 ? c.ws64 : c.ws32;
   ws_ensure(c, w, prec, false);
-  // fill x and p with something non-trivial: copy of a scaled ones-like field is
-  // not needed for timing; zero fields time identically
   // non-zero, finite work vectors (byte pattern 0x3F) and a state that never
   // stops, so every timed launch does its full work
   const size_t vb = c.cs * elem_bytes(prec);
@@ -1498,29 +1581,12 @@ double bench_kernels(Ctx& c, int what, int reps) {
     if (what == 0 || what == 3) {
       stencil_store(c, prec, kOpM, 1, w.x, w.tmp);
     } else if (what == 1) {
-      StencilLaunch L = stencil_base(c, prec);
-      L.op = kOpMdag;
-      L.epi = kEpiCGR;
-      L.in = w.tmp; L.in_cs = c.cs;
-      L.r = w.r; L.r_cs = c.cs;
-      L.ncols = 1;
-      L.mask = 1u;
-      c.check(launch_stencil(L, c.stream), "stencil");
+      c.check(launch_copy(prec, prec, 1, c.cs, w.x, c.cs, w.tmp, c.cs, c.stream), "copy");
     } else {
       R.enqueue_iters(1);
     }
   };
   if (reps + 8 > c.P.max_iter) throw ApiError{EIGCG_EINVAL, "reps must stay below max_iter"};
-  if (what == 1) {  // the fused second pass needs the first pass's partials (p^H A p)
-    StencilLaunch L = stencil_base(c, prec);
-    L.op = kOpM;
-    L.epi = kEpiNorm;
-    L.in = w.p; L.in_cs = c.cs;
-    L.out = w.tmp; L.out_cs = c.cs;
-    L.ncols = 1;
-    L.mask = 1u;
-    c.check(launch_stencil(L, c.stream), "stencil");
-  }
   for (int i = 0; i < 3; ++i) launch();
   c.check(hipEventRecord(e0, c.stream), "ev");
   for (int i = 0; i < reps; ++i) launch();

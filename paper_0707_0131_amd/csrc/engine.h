@@ -52,7 +52,7 @@ struct Ctx {
   int device = 0;
   int comp64 = 0, comp32 = 0;
   int var64 = 1, var32 = 1;        // stencil kernel variants in use
-  double tune_ms[6] = {0, 0, 0, 0, 0, 0};
+  double tune_ms[2 * kStencilVariants] = {};  // FP64 then FP32, per variant
   void* u64 = nullptr;
   void* u32 = nullptr;
   // bank (Section 4): U columns, H = U^H A U and its Cholesky factor
@@ -85,6 +85,20 @@ struct Ctx {
   int sticky = 0;
   std::vector<double> last_ritz;
   std::vector<hipEvent_t> events;
+  // sampled stencil timings: events around the two passes of every
+  // P.sample_every-th iteration, harvested when the pool is full or on request
+  struct KSample {
+    hipEvent_t e[3];
+    int prec;
+    int ncols;
+  };
+  std::vector<KSample> ks_pool;
+  int ks_used = 0;
+  long ks_tick = 0;
+  double ks_sum[2][2] = {{0, 0}, {0, 0}};  // [prec][pass] ms
+  long ks_n[2] = {0, 0};
+  long ks_cols[2] = {0, 0};
+  bool ks_harvest(bool wait);
 
   // memory
   void* dalloc(size_t bytes_);
@@ -103,6 +117,7 @@ void bank_info(Ctx& c, int* l, double* vals, double* res);
 void bank_vectors(Ctx& c, int first, int count, void* out_aos);
 int bank_load(Ctx& c, int count, const void* vecs_aos);
 double bench_kernels(Ctx& c, int what, int reps);
+void kernel_samples(Ctx& c, bool reset, double* out);
 
 // Serving sessions (continuous batching over max_batch slots of one context).
 struct Session;

@@ -21,6 +21,20 @@ enum StencilEpi {
   kEpiRes = 3,     // r = b - op(in); r^H r -> rho (true residual, with finalize)
 };
 
+// Stencil kernel variants (StencilLaunch::variant):
+//  1: thread per site, 256-site units dealt round-robin to workgroups
+//  2: thread per site, XCD-contiguous chunks of units
+//  3: two waves per 64-site tile (directions split, LDS exchange), XCD chunks
+//  4: as 3 with streaming (nontemporal) epilogue loads and stores
+//  5: as 4 with a resident-size grid (one contiguous front per XCD)
+//  6: as 5 with at most two workgroups per CU
+//  7: as 5 with one workgroup per CU
+//  8: as 5, each XCD sweeping a t-slab in (z, t, xy) tile order
+//  9: as 8 with at most two workgroups per CU
+// 8 and 9 need whole 64-site tiles per xy-plane and Lt divisible by 8; other
+// lattices run 5 and 6 instead.
+constexpr int kStencilVariants = 9;
+
 struct StencilLaunch {
   int prec;                 // kF64 / kF32 (vectors and links)
   int op;                   // kOpM / kOpMdag
@@ -41,6 +55,8 @@ struct StencilLaunch {
   const void* b; size_t b_cs;       // kEpiRes right-hand side
   void* tbuf; size_t t_cs;  // kEpiCGR: two t slots per column (slot = j & 1)
   double* hist; int hist_stride;    // kEpiCGR: per column 3 doubles per iteration
+  hipEvent_t ev_mid = nullptr;      // recorded after the stencil kernel, before the
+                                    // finalize kernel of kEpiCGR / kEpiRes
 };
 
 hipError_t launch_stencil(const StencilLaunch& L, hipStream_t s);

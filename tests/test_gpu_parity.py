@@ -33,11 +33,13 @@ CASES = [
     ("ragged_4628", (4, 6, 2, 8), 0.5, 5, -0.1),
     ("L8", (8, 8, 8, 8), 0.5, 2, -0.3),
     ("odd_3535", (3, 5, 3, 5), 0.4, 9, 0.2),
+    ("slab_8_8_3_16", (8, 8, 3, 16), 0.5, 4, -0.15),  # whole 64-site tiles per xy-plane
 ]
 
 
 @pytest.mark.parametrize("name,dims,eps,seed,mass", CASES)
-@pytest.mark.parametrize("compress,variant", [(0, 1), (1, 1), (1, 2), (1, 3), (0, 3)])
+@pytest.mark.parametrize("compress,variant", [(0, 1), (1, 1), (1, 2), (1, 3), (0, 3), (1, 4),
+                                              (1, 5), (1, 6), (1, 7), (1, 8), (1, 9), (0, 9)])
 def test_apply_matches_oracle(B, name, dims, eps, seed, mass, compress, variant):
     U = gauge_field(dims, eps, seed)
     op = WilsonOperator(U, mass)
@@ -89,7 +91,7 @@ def cfg0():
     return U, op, b
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3])
+@pytest.mark.parametrize("variant", [1, 2, 3, 6, 9])
 def test_cg_parity_cfg0(B, cfg0, variant):
     U, op, b = cfg0
     xo, io = cg(op.A, b.reshape(-1), tol=1e-10)
