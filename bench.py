@@ -156,6 +156,177 @@ def stencil_roofline(B, torch, dims, seed, reps):
     }
 
 
+BATCH_MASS = -0.50
+BATCH_SIZES = (1, 4, 8, 12)
+SERVE_FIELDS = (((8, 8, 8, 8), 11), ((16, 16, 16, 32), SEED), ((24, 24, 24, 48), HBM_SEED))
+SERVE_MASS = -0.50
+SERVE_MAX_ITER = 6000  # per request (inner iterations over all refinement steps)
+
+
+def batching_leg(B, torch, g, bt, nrhs=12):
+    """Plain CG on nrhs right-hand sides in blocks of k columns per stencil
+    launch: FP32 inner iteration with FP64 reliable updates every 50
+    iterations (and FP64 for k = 1 and 4, for comparison), tol 1e-10."""
+    out = []
+    for prec in (1, 0):
+        for k in BATCH_SIZES:
+            if prec == 0 and k > 4:
+                continue
+            p = B.eigcg_default_params(dims=LATTICE, mass=BATCH_MASS, precision=prec, max_batch=k,
+                                       reliable_every=50, max_iter=40000, check_every=32,
+                                       max_bank=0)
+            ctx = B.eigcg_create(p, g)
+            try:
+                x = torch.zeros_like(bt[:nrhs])
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                rc, st = B.eigcg_solve(ctx, bt[:nrhs], x, TOL, B.EIGCG_MODE_CG)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                info = B.eigcg_layout_info(ctx)
+            finally:
+                B.eigcg_destroy(ctx)
+            r = {"precision": "fp32+fp64-reliable" if prec else "fp64", "k": k,
+                 "rhs_per_s": nrhs / dt, "mean_iters": sum(s["iters"] for s in st) / nrhs,
+                 "max_true_rel_res": max(s["true_rel_res"] for s in st),
+                 "failed": sum(1 for s in st if s["status"] != 0 or s["true_rel_res"] > TOL),
+                 "stencil_variant": info["variant32" if prec else "variant64"]}
+            log(f"batching {r['precision']} k={k}: {r['rhs_per_s']:.1f} RHS/s, "
+                f"mean iters {r['mean_iters']:.0f}, max res {r['max_true_rel_res']:.1e}")
+            out.append(r)
+    return out
+
+
+def serving_leg(B, torch, n_bank_rhs, n_requests, seed=5):
+    """Continuous batching over three resident gauge fields (8^4, 16^3x32,
+    24^3x48): each field's FP32 bank is grown by mixed-precision eigCG on
+    n_bank_rhs right-hand sides (not timed), then a seeded Poisson stream of
+    n_requests deflated mixed-precision solves (tol 1e-10) is submitted to the
+    server; latency = submit to completion."""
+    import numpy as np
+    from synthetic import gauge_field, gaussian_rhs
+    rng = np.random.default_rng(seed)
+    fields = []
+    for dims, fseed in SERVE_FIELDS:
+        U = gauge_field(dims, EPS, fseed)
+        g = torch.from_numpy(U).to("cuda:0")
+        del U
+        p = B.eigcg_default_params(dims=dims, mass=SERVE_MASS, precision=1, max_batch=12, nev=NEV,
+                                   m=M, max_bank=NBANK, reliable_every=50, max_iter=SERVE_MAX_ITER,
+                                   check_every=16)
+        ctx = B.eigcg_create(p, g)
+        shape = (dims[3], dims[2], dims[1], dims[0], 4, 3)
+        bb = torch.empty((n_bank_rhs,) + shape, dtype=torch.complex128, device="cuda:0")
+        for i in range(n_bank_rhs):
+            bb[i].copy_(torch.from_numpy(gaussian_rhs(dims, 7000 + i)))
+        t0 = time.perf_counter()
+        for i in range(n_bank_rhs):  # one at a time: each RHS is deflated by the bank so far
+            B.eigcg_solve(ctx, bb[i:i + 1], torch.zeros_like(bb[i:i + 1]), TOL, B.EIGCG_MODE_EIGCG)
+        torch.cuda.synchronize()
+        del bb
+        vals = B.eigcg_bank_info(ctx)[0]
+        l = len(vals)
+        log(f"serving field {dims}: bank {l} vectors (lowest {vals[0] if l else 0:.3e}) "
+            f"in {time.perf_counter() - t0:.1f}s")
+        fields.append({"dims": dims, "g": g, "ctx": ctx, "shape": shape, "bank": l})
+    # one isolated deflated request per field through the server first
+    iso = {}
+    srv = B.eigcg_server_create(0)
+    try:
+        fids = [B.eigcg_server_add(srv, F["ctx"]) for F in fields]
+        for k, F in enumerate(fields):
+            b = torch.from_numpy(gaussian_rhs(F["dims"], 8000 + k)).to("cuda:0")[None]
+            tk = B.eigcg_submit(srv, fids[k], b, torch.zeros_like(b), TOL)
+            B.eigcg_server_drain(srv)
+            rc, st = B.eigcg_poll(srv, tk)
+            iso[k] = st["seconds"]
+            log(f"serving isolated request on {F['dims']}: rc {rc} {st['seconds'] * 1e3:.0f} ms, "
+                f"iters {st['iters']}, outer {st['outer_steps']}, res {st['true_rel_res']:.1e}")
+    finally:
+        B.eigcg_server_destroy(srv)
+    # requests: field chosen uniformly, right-hand sides pre-generated on the device
+    which = rng.integers(0, len(fields), n_requests)
+    reqs = []
+    for i, f in enumerate(which):
+        F = fields[f]
+        b = torch.from_numpy(gaussian_rhs(F["dims"], 9000 + i)).to("cuda:0")[None]
+        reqs.append((int(f), b, torch.zeros_like(b)))
+    torch.cuda.synchronize()
+    # offered load: mean gap = 1/4 of the mean isolated latency over the mix
+    mean_iso = float(np.mean([iso[int(f)] for f in which]))
+    gaps = rng.exponential(mean_iso / 4.0, n_requests)
+    srv = B.eigcg_server_create(0)
+    try:
+        fids = [B.eigcg_server_add(srv, F["ctx"]) for F in fields]
+        tickets = []
+        t0 = time.perf_counter()
+        t_next = t0
+        t_log = t0
+        for i, (f, b, x) in enumerate(reqs):
+            t_next += gaps[i]
+            while time.perf_counter() < t_next:
+                time.sleep(min(1e-3, max(0.0, t_next - time.perf_counter())))
+            tickets.append(B.eigcg_submit(srv, fids[f], b, x, TOL))
+            if time.perf_counter() - t_log > 5.0:
+                t_log = time.perf_counter()
+                ndone = sum(1 for t in tickets if B.eigcg_poll(srv, t)[0] != B.EIGCG_EBUSY)
+                log(f"serving: {len(tickets)} submitted, {ndone} done")
+        while True:  # drain with progress lines
+            ndone = sum(1 for t in tickets if B.eigcg_poll(srv, t)[0] != B.EIGCG_EBUSY)
+            if ndone == len(tickets):
+                break
+            if time.perf_counter() - t_log > 5.0:
+                t_log = time.perf_counter()
+                log(f"serving: all {len(tickets)} submitted, {ndone} done")
+            time.sleep(2e-3)
+        t1 = time.perf_counter()
+        res = [B.eigcg_poll(srv, t) for t in tickets]
+    finally:
+        B.eigcg_server_destroy(srv)
+    lat = np.array([st["seconds"] for _, st in res])
+    ok = [rc == 0 and st["true_rel_res"] <= TOL for rc, st in res]
+    per_field = []
+    for k, F in enumerate(fields):
+        sel = which == k
+        if sel.any():
+            per_field.append({"dims": list(F["dims"]), "bank": F["bank"], "requests": int(sel.sum()),
+                              "p50_s": float(np.percentile(lat[sel], 50)),
+                              "p99_s": float(np.percentile(lat[sel], 99)),
+                              "mean_iters": float(np.mean([res[i][1]["iters"] for i in np.nonzero(sel)[0]]))})
+    # plain FP64 single-RHS CG on each field (one of its requests' b) as the reference
+    plain_s = []
+    for k, F in enumerate(fields):
+        B.eigcg_destroy(F["ctx"])
+        i0 = int(np.nonzero(which == k)[0][0]) if (which == k).any() else 0
+        b = reqs[i0][1] if which[i0] == k else torch.from_numpy(
+            gaussian_rhs(F["dims"], 9000)).to("cuda:0")[None]
+        p = B.eigcg_default_params(dims=F["dims"], mass=SERVE_MASS, max_iter=40000, check_every=32,
+                                   max_bank=0)
+        ctx = B.eigcg_create(p, F["g"])
+        try:
+            x = torch.zeros_like(b)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            B.eigcg_solve(ctx, b, x, TOL, B.EIGCG_MODE_CG)
+            torch.cuda.synchronize()
+            plain_s.append(time.perf_counter() - t)
+        finally:
+            B.eigcg_destroy(ctx)
+    for k, pf in enumerate(per_field):
+        pf["plain_fp64_cg_s"] = plain_s[[list(F["dims"]) for F in fields].index(pf["dims"])]
+    plain_mix = float(sum(plain_s[f] for f in which))
+    out = {"requests": n_requests, "rhs_per_s": n_requests / (t1 - t0), "wall_s": t1 - t0,
+           "plain_fp64_cg_same_mix_s": plain_mix, "speedup_vs_plain_fp64_cg": plain_mix / (t1 - t0),
+           "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+           "isolated_request_s": {str(list(fields[k]["dims"])): v for k, v in iso.items()},
+           "failed": int(len(ok) - sum(ok)),
+           "max_true_rel_res": max(st["true_rel_res"] for _, st in res), "per_field": per_field}
+    log(f"serving: {out['rhs_per_s']:.1f} RHS/s p50 {out['p50_s'] * 1e3:.0f} ms "
+        f"p99 {out['p99_s'] * 1e3:.0f} ms failed {out['failed']}, "
+        f"{out['speedup_vs_plain_fp64_cg']:.2f}x plain FP64 CG on the same mix")
+    return out
+
+
 def cpu_baseline(total_rhs, total_iters, budget_s=20.0):
     """Oracle CG on the bench lattice for a bounded number of iterations."""
     import numpy as np
@@ -193,6 +364,10 @@ def main():
     ap.add_argument("--n-eig", type=int, default=N_EIG, help="phase-1 RHS per step (profiling)")
     ap.add_argument("--n-defl", type=int, default=N_DEFL, help="phase-2 RHS per step (profiling)")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--no-batching", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-bank-rhs", type=int, default=N_EIG)
+    ap.add_argument("--serve-requests", type=int, default=120)
     ap.add_argument("--roofline-only", choices=("bench", "hbm"),
                     help="only time the stencil, copy and CG iteration on the bench lattice "
                          "or the 24^3x48 lattice (short runs for counter collection)")
@@ -263,6 +438,10 @@ def main():
                          "phase2_speedup": (n_defl / s["phase2_s"]) / plain})
     plain_all = len(base) / sum(b["s_per_rhs"] for b in base)
 
+    batching = None
+    if not args.no_batching:
+        batching = batching_leg(B, torch, g, bt)
+
     roof_small = roof_hbm = None
     if not args.no_roofline:
         log("stencil roofline (bench lattice, MALL-resident)")
@@ -271,6 +450,12 @@ def main():
         torch.cuda.empty_cache()
         log(f"stencil roofline ({HBM_LATTICE}, working set above the 256 MB MALL)")
         roof_hbm = stencil_roofline(B, torch, HBM_LATTICE, HBM_SEED, 100)
+
+    serving = None
+    if not args.no_serving:
+        del bt, xt
+        torch.cuda.empty_cache()
+        serving = serving_leg(B, torch, args.serve_bank_rhs, args.serve_requests)
 
     total_iters = sum(sum(s["phase1_iters"]) + sum(s["phase2_iters"]) for s in steps)
     cpu = None
@@ -333,6 +518,8 @@ def main():
         },
         "stencil_pass1": {"launch_ms": pass1_ms, "GBs": pass1_bytes / pass1_ms / 1e6 if n_s else None,
                           "algorithmic_bytes_per_launch": pass1_bytes},
+        "batching": batching,
+        "serving": serving,
         "stencil_bench_lattice": roof_small,
         "stencil_hbm_lattice": roof_hbm,
         "cpu_baseline": cpu,

@@ -1196,7 +1196,11 @@ int bank_append_from(Ctx& c, const void* src, int nsrc) {
             "norm copy");
     c.check(hipStreamSynchronize(c.stream), "sync");
     const double nrm = std::sqrt(c.h_norm[0]);
-    if (!(nrm > 1e-10 * std::sqrt(n0[q]))) continue;
+    // drop rule of Section 4 (1e-10 of the input norm) for an FP64 bank; an
+    // FP32 bank's projections are only accurate to its rounding level, so a
+    // remainder below 1e-4 of the input is rounding noise and is dropped too
+    const double drop = prec == kF64 ? 1e-10 : 1e-4;
+    if (!(nrm > drop * std::sqrt(n0[q]))) continue;
     const double inv = 1.0 / nrm;
     // scale into its final slot
     if (dst != v) c.check(launch_copy(prec, prec, 1, c.cs, v, c.cs, dst, c.cs, c.stream), "copy");
@@ -1417,9 +1421,20 @@ int session_admit(Session* s, const void* b_aos, void* x_aos, double tol, uint64
   s->tol[j] = tol;
   s->tag[j] = tg;
   s->xdst[j] = x_aos;
-  s->active[j] = 1;
   s->t_admit[j] = now_s();
-  s->D.start_columns(1u << j, bn2, tol, restart_tol_for(c, EIGCG_MODE_INITCG, s->D.scheme), true);
+  try {
+    s->D.start_columns(1u << j, bn2, tol, restart_tol_for(c, EIGCG_MODE_INITCG, s->D.scheme), true);
+  } catch (...) {
+    // the slot stays free and idle; the caller reports the request as failed
+    std::vector<ColState> idle(s->K);
+    std::memset(idle.data(), 0, sizeof(ColState) * s->K);
+    idle[j].state = ColStopped;
+    idle[j].reason = ReasonConverged;
+    s->D.upload_states(1u << j, idle);
+    s->D.R.done[j] = 1;
+    throw;
+  }
+  s->active[j] = 1;
   return j;
 }
 

@@ -132,7 +132,7 @@ struct eigcg_server {
         const double t = now_s();
         for (auto& d : done) {
           auto it = reqs.find(d.tag);
-          if (it == reqs.end()) continue;
+          if (it == reqs.end() || it->second.done) continue;
           Request& r = it->second;
           r.done = true;
           r.t_done = t;

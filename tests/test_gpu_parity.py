@@ -293,3 +293,34 @@ def test_mixed_precision_cg(B, cfg0):
         assert rel(host(x)[0].reshape(-1), xo) <= 1e-6
     finally:
         B.eigcg_destroy(ctx)
+
+
+def test_mixed_precision_eigcg_bank(B, cfg0):
+    """Mixed-precision Incremental eigCG: FP32 window and bank, FP64 reliable
+    updates.  The bank stays a valid Rayleigh-Ritz space of the HPD A: its
+    Ritz values lie in the spectrum's range (up to FP32 rounding of the
+    stored vectors), the lowest approximates the smallest eigenvalue, and
+    deflated solves converge to 1e-10.  Error against the dense spectrum is
+    stated in the assertions."""
+    from oracle.dense import dense_A
+    U, op, b = cfg0
+    A, _ = dense_A(op)
+    lam = np.linalg.eigvalsh(A)
+    ctx, _ = make_ctx(U, -0.2, precision=B.EIGCG_MIXED_FP32, reliable_every=50, max_iter=5000,
+                      nev=6, m=24, max_bank=24)
+    try:
+        rhs = gaussian_rhs_block((4, 4, 4, 4), [2100 + i for i in range(4)])
+        for i in range(4):
+            x = dev(np.zeros((1,) + rhs[i].shape, dtype=np.complex128))
+            rc, st = B.eigcg_solve(ctx, dev(rhs[i][None].copy()), x, 1e-10, B.EIGCG_MODE_EIGCG)
+            assert rc == B.EIGCG_OK and st[0]["true_rel_res"] <= 1e-10
+        vals, _ = B.eigcg_bank_info(ctx)
+        assert len(vals) >= 6
+        assert vals[0] >= lam[0] * (1 - 1e-3) - 1e-5 * lam[-1]
+        assert vals[-1] <= lam[-1] * (1 + 1e-5)
+        assert abs(vals[0] - lam[0]) <= 1e-2 * lam[0]
+        x = dev(np.zeros((1,) + b.shape, dtype=np.complex128))
+        rc, st = B.eigcg_solve(ctx, dev(b[None]), x, 1e-10, B.EIGCG_MODE_INITCG)
+        assert rc == B.EIGCG_OK and st[0]["true_rel_res"] <= 1e-10
+    finally:
+        B.eigcg_destroy(ctx)
