@@ -30,7 +30,7 @@ if ROOT not in sys.path:
 
 LATTICE = (16, 16, 16, 32)
 EPS, SEED = 0.5, 1
-MASSES = (-0.40, -0.50, -0.55)
+MASSES = (-0.55, -0.58, -0.60)
 NEV, M, NBANK = 10, 100, 240
 N_EIG, N_DEFL = 24, 100
 TOL = 1e-10
@@ -156,11 +156,11 @@ def stencil_roofline(B, torch, dims, seed, reps):
     }
 
 
-BATCH_MASS = -0.50
+BATCH_MASS = -0.58
 BATCH_SIZES = (1, 4, 8, 12)
 SERVE_FIELDS = (((8, 8, 8, 8), 11), ((16, 16, 16, 32), SEED), ((24, 24, 24, 48), HBM_SEED))
-SERVE_MASS = -0.50
-SERVE_MAX_ITER = 6000  # per request (inner iterations over all refinement steps)
+SERVE_MASS = -0.58
+SERVE_MAX_ITER = 20000  # per request (inner iterations over all refinement steps)
 
 
 def batching_leg(B, torch, g, bt, nrhs=12):
@@ -211,19 +211,29 @@ def serving_leg(B, torch, n_bank_rhs, n_requests, seed=5):
         U = gauge_field(dims, EPS, fseed)
         g = torch.from_numpy(U).to("cuda:0")
         del U
+        shape = (dims[3], dims[2], dims[1], dims[0], 4, 3)
+        # the bank is grown by FP64 Incremental eigCG (phase 1 of the paper),
+        # then held in FP32 by the mixed-precision serving context
+        t0 = time.perf_counter()
+        p64 = B.eigcg_default_params(dims=dims, mass=SERVE_MASS, nev=NEV, m=M, max_bank=NBANK,
+                                     max_iter=SERVE_MAX_ITER, check_every=16)
+        ctx64 = B.eigcg_create(p64, g)
+        try:
+            for i in range(n_bank_rhs):  # one at a time: each RHS is deflated by the bank so far
+                b = torch.from_numpy(gaussian_rhs(dims, 7000 + i)).to("cuda:0")[None]
+                B.eigcg_solve(ctx64, b, torch.zeros_like(b), TOL, B.EIGCG_MODE_EIGCG)
+            l64 = len(B.eigcg_bank_info(ctx64)[0])
+            vecs = torch.empty((l64,) + shape, dtype=torch.complex128, device="cuda:0")
+            B.eigcg_bank_vectors(ctx64, 0, l64, vecs)
+        finally:
+            B.eigcg_destroy(ctx64)
         p = B.eigcg_default_params(dims=dims, mass=SERVE_MASS, precision=1, max_batch=12, nev=NEV,
                                    m=M, max_bank=NBANK, reliable_every=50, max_iter=SERVE_MAX_ITER,
                                    check_every=16)
         ctx = B.eigcg_create(p, g)
-        shape = (dims[3], dims[2], dims[1], dims[0], 4, 3)
-        bb = torch.empty((n_bank_rhs,) + shape, dtype=torch.complex128, device="cuda:0")
-        for i in range(n_bank_rhs):
-            bb[i].copy_(torch.from_numpy(gaussian_rhs(dims, 7000 + i)))
-        t0 = time.perf_counter()
-        for i in range(n_bank_rhs):  # one at a time: each RHS is deflated by the bank so far
-            B.eigcg_solve(ctx, bb[i:i + 1], torch.zeros_like(bb[i:i + 1]), TOL, B.EIGCG_MODE_EIGCG)
+        B.eigcg_bank_load(ctx, vecs)
+        del vecs
         torch.cuda.synchronize()
-        del bb
         vals = B.eigcg_bank_info(ctx)[0]
         l = len(vals)
         log(f"serving field {dims}: bank {l} vectors (lowest {vals[0] if l else 0:.3e}) "

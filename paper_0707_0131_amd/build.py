@@ -26,9 +26,12 @@ COMMON = [
     "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
     "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
 ]
-# packed FP32 instructions stay disabled for all device code
+# Packed FP32 instructions stay disabled for all device code.  Multiply-adds
+# are fused only inside one source expression (-ffp-contract=on), so a given
+# expression rounds the same way in every kernel instantiation: a column's
+# result then does not depend on how many columns share its workgroup.
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-          "-munsafe-fp-atomics"]
+          "-munsafe-fp-atomics", "-ffp-contract=on"]
 
 
 def _sources():

@@ -239,10 +239,10 @@ __global__ __launch_bounds__(kBlock) void k_norm2(size_t n, const VS* x, size_t 
 __global__ __launch_bounds__(kBlock) void k_norm2_final(const double* partial, int nb, int ncols,
                                                         double* out) {
   __shared__ double lds4[kBlock / 64];
-  for (int c = 0; c < ncols; ++c) {
-    double t = reduce_partials(partial + (size_t)c * nb, nb, lds4);
-    if (threadIdx.x == 0) out[c] = t;
-  }
+  const int c = blockIdx.x;  // one workgroup per column
+  if (c >= ncols) return;
+  const double t = reduce_partials(partial + (size_t)c * nb, nb, lds4);
+  if (threadIdx.x == 0) out[c] = t;
 }
 
 template <typename VS>
@@ -436,7 +436,7 @@ hipError_t launch_norm2(int prec, int ncols, size_t n, const void* x, size_t x_c
                        partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_norm2_final, dim3(1), dim3(kBlock), 0, s, partial, gx, ncols, out);
+  hipLaunchKernelGGL(k_norm2_final, dim3(ncols), dim3(kBlock), 0, s, partial, gx, ncols, out);
   return hipGetLastError();
 }
 

@@ -172,78 +172,107 @@ __global__ __launch_bounds__(kBlock) void k_wilson(DevArgs a) {
   if (threadIdx.x == 0) a.partial[(size_t)col * gridDim.x + blockIdx.x] = (double)bs;
 }
 
-// Variant 3: a unit is two 64-site tiles; each tile is handled by a pair of
-// waves, the even wave doing directions x and y, the odd wave z and t.  They
-// swap half of their partial sums through LDS and each finishes six of the
-// twelve output components, so per-thread state is half of variant 1's and
-// twice as many waves stream the lattice.
-template <typename VS, typename LS, bool COMP, bool DAG, int EPI, bool NT, int ORD>
+// Variants 3..9: a unit is two 64-site tiles; each tile is handled by a pair
+// of waves, the even wave doing directions x and y, the odd wave z and t.
+// They swap half of their partial sums through LDS and each finishes six of
+// the twelve output components, so per-thread state is half of variant 1's
+// and twice as many waves stream the lattice.  A workgroup serves NC columns
+// (right-hand sides blockIdx.y NC .. + NC - 1): every link is loaded once per
+// site and applied to all of them, and each column's arithmetic and
+// reduction order are those of NC = 1, so results do not depend on NC.
+template <typename VS, typename LS, bool COMP, bool DAG, int EPI, bool NT, int ORD, int NC>
 __global__ __launch_bounds__(kBlock) void k_wilson_pair(DevArgs a) {
   using R = typename Storage<VS>::real;
   __shared__ double lds4[kBlock / 64];
   __shared__ R ldsr[kBlock / 64];
-  __shared__ cpx<R> xbuf[2][2][6][64];  // [tile][writer parity][component][lane]
-  const int col = blockIdx.y;
-  R alpha;
-  bool save_t;
-  int save_slot;
-  const bool active = column_setup<VS, EPI>(a, col, lds4, alpha, save_t, save_slot);
-  const VS* in = reinterpret_cast<const VS*>(a.in) + (size_t)col * a.in_cs;
+  __shared__ cpx<R> xbuf[2][2][NC][6][64];  // [tile][writer parity][column][component][lane]
+  const int col0 = blockIdx.y * NC;
+  R alpha[NC];
+  bool save_t[NC];
+  int save_slot[NC];
+  uint32_t act = 0;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    bool on = false;
+    alpha[c] = R(0);
+    save_t[c] = false;
+    save_slot[c] = 0;
+    if (col0 + c < a.ncols) on = column_setup<VS, EPI>(a, col0 + c, lds4, alpha[c], save_t[c],
+                                                       save_slot[c]);
+    if (on) act |= 1u << c;
+  }
+  const VS* in = reinterpret_cast<const VS*>(a.in) + (size_t)col0 * a.in_cs;
   const LS* u = reinterpret_cast<const LS*>(a.u);
   const size_t vs = (size_t)a.g.vs;
   const int tile = threadIdx.x >> 7;
   const int odd = (threadIdx.x >> 6) & 1;
   const int lane = threadIdx.x & 63;
-  R acc2 = R(0);
+  R acc2[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) acc2[c] = R(0);
   // one 128-site unit: tile `tile` of this workgroup covers sites s (valid)
   auto unit = [&](uint32_t s, bool valid) {
-      cpx<R> acc[12];
+      cpx<R> acc[NC][12];
 #pragma unroll
-      for (int e = 0; e < 12; ++e) acc[e] = {R(0), R(0)};
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int e = 0; e < 12; ++e) acc[c][e] = {R(0), R(0)};
       if (valid) {
         uint32_t coord[4];
         site_coords(a.g, s, coord);
         if (!odd) {
-          hop_dir<0, VS, LS, COMP, DAG ? 1 : -1>(in, u, a.g, s, coord, acc);
-          hop_dir<1, VS, LS, COMP, DAG ? 1 : -1>(in, u, a.g, s, coord, acc);
+          hop_dir_n<0, VS, LS, COMP, DAG ? 1 : -1, NC>(in, a.in_cs, act, u, a.g, s, coord, acc);
+          hop_dir_n<1, VS, LS, COMP, DAG ? 1 : -1, NC>(in, a.in_cs, act, u, a.g, s, coord, acc);
         } else {
-          hop_dir<2, VS, LS, COMP, DAG ? 1 : -1>(in, u, a.g, s, coord, acc);
-          hop_dir<3, VS, LS, COMP, DAG ? 1 : -1>(in, u, a.g, s, coord, acc);
+          hop_dir_n<2, VS, LS, COMP, DAG ? 1 : -1, NC>(in, a.in_cs, act, u, a.g, s, coord, acc);
+          hop_dir_n<3, VS, LS, COMP, DAG ? 1 : -1, NC>(in, a.in_cs, act, u, a.g, s, coord, acc);
         }
       }
       // hand the partner the half it finishes: even keeps 0..5, odd keeps 6..11
-      if (odd) {
 #pragma unroll
-        for (int e = 0; e < 6; ++e) xbuf[tile][1][e][lane] = acc[e];
-      } else {
+      for (int c = 0; c < NC; ++c) {
+        if (odd) {
 #pragma unroll
-        for (int e = 0; e < 6; ++e) xbuf[tile][0][e][lane] = acc[6 + e];
+          for (int e = 0; e < 6; ++e) xbuf[tile][1][c][e][lane] = acc[c][e];
+        } else {
+#pragma unroll
+          for (int e = 0; e < 6; ++e) xbuf[tile][0][c][e][lane] = acc[c][6 + e];
+        }
       }
       __syncthreads();
       const R d = (R)a.diag;
-      cpx<R> o[12];
-      if (!odd) {
 #pragma unroll
-        for (int e = 0; e < 6; ++e) {
-          const cpx<R> p = xbuf[tile][1][e][lane];
-          cpx<R> v = valid ? Storage<VS>::ld(in, (size_t)e * vs + s) : cpx<R>{R(0), R(0)};
-          const R hr = acc[e].re + p.re, hi = acc[e].im + p.im;
-          o[e] = {d * v.re - R(0.5) * hr, d * v.im - R(0.5) * hi};
-        }
-        if (valid) epilogue<VS, EPI, 0, 6, NT>(a, col, s, o, alpha, save_t, save_slot, acc2);
-      } else {
+      for (int c = 0; c < NC; ++c) {
+        if (!((act >> c) & 1u)) continue;
+        const VS* ic = in + (size_t)c * a.in_cs;
+        cpx<R> o[12];
+        if (!odd) {
 #pragma unroll
-        for (int e = 6; e < 12; ++e) {
-          const cpx<R> p = xbuf[tile][0][e - 6][lane];
-          cpx<R> v = valid ? Storage<VS>::ld(in, (size_t)e * vs + s) : cpx<R>{R(0), R(0)};
-          const R hr = p.re + acc[e].re, hi = p.im + acc[e].im;
-          o[e] = {d * v.re - R(0.5) * hr, d * v.im - R(0.5) * hi};
+          for (int e = 0; e < 6; ++e) {
+            const cpx<R> p = xbuf[tile][1][c][e][lane];
+            cpx<R> v = valid ? Storage<VS>::ld(ic, (size_t)e * vs + s) : cpx<R>{R(0), R(0)};
+            const R hr = acc[c][e].re + p.re, hi = acc[c][e].im + p.im;
+            o[e] = {d * v.re - R(0.5) * hr, d * v.im - R(0.5) * hi};
+          }
+          if (valid)
+            epilogue<VS, EPI, 0, 6, NT>(a, col0 + c, s, o, alpha[c], save_t[c], save_slot[c],
+                                        acc2[c]);
+        } else {
+#pragma unroll
+          for (int e = 6; e < 12; ++e) {
+            const cpx<R> p = xbuf[tile][0][c][e - 6][lane];
+            cpx<R> v = valid ? Storage<VS>::ld(ic, (size_t)e * vs + s) : cpx<R>{R(0), R(0)};
+            const R hr = p.re + acc[c][e].re, hi = p.im + acc[c][e].im;
+            o[e] = {d * v.re - R(0.5) * hr, d * v.im - R(0.5) * hi};
+          }
+          if (valid)
+            epilogue<VS, EPI, 6, 6, NT>(a, col0 + c, s, o, alpha[c], save_t[c], save_slot[c],
+                                        acc2[c]);
         }
-        if (valid) epilogue<VS, EPI, 6, 6, NT>(a, col, s, o, alpha, save_t, save_slot, acc2);
       }
       __syncthreads();
   };
-  if (active) {
+  if (act) {
     if (ORD == 0) {
       const uint32_t T = ((uint32_t)a.g.V + 127u) / 128u;
       for (Units it(T, true); it.u < it.end; it.u += it.step) {
@@ -273,8 +302,12 @@ __global__ __launch_bounds__(kBlock) void k_wilson_pair(DevArgs a) {
     }
   }
   if (EPI == kEpiStore) return;
-  R bs = block_sum(acc2, ldsr);
-  if (threadIdx.x == 0) a.partial[(size_t)col * gridDim.x + blockIdx.x] = (double)bs;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    R bs = block_sum(acc2[c], ldsr);
+    if (threadIdx.x == 0 && col0 + c < a.ncols)
+      a.partial[(size_t)(col0 + c) * gridDim.x + blockIdx.x] = (double)bs;
+  }
 }
 
 // CG scalars after the second stencil pass (one workgroup): p^H A p from the
@@ -284,11 +317,12 @@ __global__ __launch_bounds__(kBlock) void k_finalize_cg(ColState* st, int ncols,
                                                         const double* part_a, const double* part_b,
                                                         int nb, double* hist, int hist_stride) {
   __shared__ double lds4[kBlock / 64];
-  for (int c = 0; c < ncols; ++c) {
-    if (!((mask >> c) & 1u)) continue;
+  {
+    const int c = blockIdx.x;  // one workgroup per column
+    if (c >= ncols || !((mask >> c) & 1u)) return;
     const double pap = reduce_partials(part_a + (size_t)c * nb, nb, lds4);
     const double rho_new = reduce_partials(part_b + (size_t)c * nb, nb, lds4);
-    if (threadIdx.x != 0) continue;
+    if (threadIdx.x != 0) return;
     ColState& S = st[c];
     if (S.state == ColRun) {
       S.pap = pap;
@@ -296,7 +330,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize_cg(ColState* st, int ncols,
         S.alpha = 0.0;
         S.state = ColStopPending;
         S.reason = ReasonBreakdown;
-        continue;
+        return;
       }
       S.alpha = S.rho / pap;
       const int j = S.iter + 1;
@@ -338,11 +372,10 @@ __global__ __launch_bounds__(kBlock) void k_finalize_cg(ColState* st, int ncols,
 __global__ __launch_bounds__(kBlock) void k_finalize_res(ColState* st, int ncols, uint32_t mask,
                                                          const double* part, int nb) {
   __shared__ double lds4[kBlock / 64];
-  for (int c = 0; c < ncols; ++c) {
-    if (!((mask >> c) & 1u)) continue;
-    const double tot = reduce_partials(part + (size_t)c * nb, nb, lds4);
-    if (threadIdx.x == 0) st[c].rho = tot;
-  }
+  const int c = blockIdx.x;  // one workgroup per column
+  if (c >= ncols || !((mask >> c) & 1u)) return;
+  const double tot = reduce_partials(part + (size_t)c * nb, nb, lds4);
+  if (threadIdx.x == 0) st[c].rho = tot;
 }
 
 // Two-tile kernel occupancy control.  `per_cu` > 0 caps the workgroups that
@@ -358,7 +391,7 @@ size_t pair_occupancy(int per_cu, int* resident) {
   std::lock_guard<std::mutex> lk(mu);
   Info& I = cache[per_cu & 3];
   if (I.resident == 0) {
-    auto kern = k_wilson_pair<VS, LS, true, false, kEpiCGR, true, 0>;
+    auto kern = k_wilson_pair<VS, LS, true, false, kEpiCGR, true, 0, 1>;
     int dev = 0, cus = 0, lds_cu = 0, lds_wg = 0, per = 0;
     hipFuncAttributes fa{};
     size_t extra = 0;
@@ -387,6 +420,7 @@ size_t pair_occupancy(int per_cu, int* resident) {
 
 template <typename VS, typename LS>
 hipError_t launch_typed(const StencilLaunch& L, hipStream_t s) {
+  constexpr int NC4 = sizeof(typename Storage<VS>::real) == 4 ? 4 : 2;
   DevArgs a;
   a.in = L.in; a.in_cs = L.in_cs; a.out = L.out; a.out_cs = L.out_cs; a.u = L.u; a.g = *L.g;
   a.diag = L.diag; a.ncols = L.ncols; a.mask = L.mask; a.st = L.st;
@@ -419,21 +453,37 @@ hipError_t launch_typed(const StencilLaunch& L, hipStream_t s) {
   } else {
     gx = (int)std::min<uint32_t>((T + 7u) & ~7u, kMaxGrid);  // a multiple of 8 (XCDs)
   }
-  dim3 grid(gx, L.ncols), block(kBlock);
+  // columns per workgroup of the two-tile kernels (links loaded once per
+  // site for all of them); the grid's x extent and the site-to-workgroup map
+  // do not depend on it, so every column's reductions are the same for any
+  // batch width.  FP64 takes at most 2 (LDS of the exchange buffer).
+  int nc = 1;
+  if (variant >= 3 && L.compressed && L.ncols >= 2)
+    nc = (L.ncols >= 4 && sizeof(typename Storage<VS>::real) == 4) ? 4 : 2;
+  if (nc > 1) dyn_lds = 0;  // the larger exchange buffer already caps occupancy
+  dim3 grid(gx, (L.ncols + nc - 1) / nc), block(kBlock);
+#define EIGCG_PAIR(COMP, DAG, EPI, NT, ORD)                                                    \
+  if (nc == 4)                                                                                \
+    hipLaunchKernelGGL((k_wilson_pair<VS, LS, COMP, DAG, EPI, NT, ORD, NC4>), grid, block,     \
+                       dyn_lds, s, a);                                                        \
+  else if (nc == 2)                                                                           \
+    hipLaunchKernelGGL((k_wilson_pair<VS, LS, COMP, DAG, EPI, NT, ORD, 2>), grid, block,       \
+                       dyn_lds, s, a);                                                        \
+  else                                                                                        \
+    hipLaunchKernelGGL((k_wilson_pair<VS, LS, COMP, DAG, EPI, NT, ORD, 1>), grid, block,       \
+                       dyn_lds, s, a);
 #define EIGCG_K(COMP, DAG, EPI)                                                               \
-  if (variant >= 8)                                                                           \
-    hipLaunchKernelGGL((k_wilson_pair<VS, LS, COMP, DAG, EPI, true, 1>), grid, block, dyn_lds, \
-                       s, a);                                                                 \
-  else if (variant >= 4)                                                                      \
-    hipLaunchKernelGGL((k_wilson_pair<VS, LS, COMP, DAG, EPI, true, 0>), grid, block, dyn_lds, \
-                       s, a);                                                                 \
-  else if (variant == 3)                                                                      \
-    hipLaunchKernelGGL((k_wilson_pair<VS, LS, COMP, DAG, EPI, false, 0>), grid, block, 0, s,   \
-                       a);                                                                    \
-  else if (variant == 2)                                                                      \
-    hipLaunchKernelGGL((k_wilson<VS, LS, COMP, DAG, EPI, true>), grid, block, 0, s, a);    \
-  else                                                                                     \
-    hipLaunchKernelGGL((k_wilson<VS, LS, COMP, DAG, EPI, false>), grid, block, 0, s, a);
+  if (variant >= 8) {                                                                         \
+    EIGCG_PAIR(COMP, DAG, EPI, true, 1)                                                       \
+  } else if (variant >= 4) {                                                                  \
+    EIGCG_PAIR(COMP, DAG, EPI, true, 0)                                                       \
+  } else if (variant == 3) {                                                                  \
+    EIGCG_PAIR(COMP, DAG, EPI, false, 0)                                                      \
+  } else if (variant == 2) {                                                                  \
+    hipLaunchKernelGGL((k_wilson<VS, LS, COMP, DAG, EPI, true>), grid, block, 0, s, a);       \
+  } else {                                                                                    \
+    hipLaunchKernelGGL((k_wilson<VS, LS, COMP, DAG, EPI, false>), grid, block, 0, s, a);      \
+  }
 #define EIGCG_EPI(COMP, DAG)                                  \
   switch (L.epi) {                                            \
     case kEpiStore: { EIGCG_K(COMP, DAG, kEpiStore) } break;  \
@@ -448,6 +498,7 @@ hipError_t launch_typed(const StencilLaunch& L, hipStream_t s) {
   }
 #undef EIGCG_EPI
 #undef EIGCG_K
+#undef EIGCG_PAIR
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (L.ev_mid) {
@@ -455,10 +506,10 @@ hipError_t launch_typed(const StencilLaunch& L, hipStream_t s) {
     if (e != hipSuccess) return e;
   }
   if (L.epi == kEpiCGR)
-    hipLaunchKernelGGL(k_finalize_cg, dim3(1), dim3(kBlock), 0, s, L.st, L.ncols, L.mask, part_a,
+    hipLaunchKernelGGL(k_finalize_cg, dim3(L.ncols), dim3(kBlock), 0, s, L.st, L.ncols, L.mask, part_a,
                        part_b, gx, L.hist, L.hist_stride);
   else if (L.epi == kEpiRes)
-    hipLaunchKernelGGL(k_finalize_res, dim3(1), dim3(kBlock), 0, s, L.st, L.ncols, L.mask, part_b,
+    hipLaunchKernelGGL(k_finalize_res, dim3(L.ncols), dim3(kBlock), 0, s, L.st, L.ncols, L.mask, part_b,
                        gx);
   return hipGetLastError();
 }

@@ -107,7 +107,7 @@ static void autotune_stencil(Ctx& c, int prec) {
     return;
   }
   const std::vector<int> key = {c.g.L[0], c.g.L[1], c.g.L[2], c.g.L[3], c.g.vs, prec,
-                                prec == kF64 ? c.comp64 : c.comp32};
+                                prec == kF64 ? c.comp64 : c.comp32, c.P.max_batch};
   auto pick = [&](const std::vector<double>& t) {
     int best = 1;
     for (int v = 1; v <= kStencilVariants; ++v) {
@@ -127,7 +127,8 @@ static void autotune_stencil(Ctx& c, int prec) {
   // Each candidate runs the two passes of a CG iteration with their memory
   // traffic: M p -> t with the partial-sum epilogue, then M^H t against a
   // right-hand side with the residual epilogue (reads b, writes r), on the
-  // context's scratch vectors and state slot.
+  // context's scratch vectors and state slots, for a full batch of
+  // max_batch columns (the width the solver launches).
   Workspace& w = prec == kF64 ? c.ws64 : c.ws32;
   ws_ensure(c, w, prec, false);
   hipEvent_t e0, e1;
@@ -141,8 +142,8 @@ static void autotune_stencil(Ctx& c, int prec) {
     L1.epi = kEpiNorm;
     L1.in = w.x; L1.in_cs = c.cs;
     L1.out = w.tmp; L1.out_cs = c.cs;
-    L1.ncols = 1;
-    L1.mask = 1u;
+    L1.ncols = w.K;
+    L1.mask = w.K >= 32 ? 0xffffffffu : ((1u << w.K) - 1u);
     StencilLaunch L2 = L1;
     L2.op = kOpMdag;
     L2.epi = kEpiRes;
@@ -251,6 +252,7 @@ void ctx_release(Ctx& c) {
   ws_release(c, c.ws32);
   c.dfree(c.U);
   c.dfree(c.bwork);
+  c.dfree(c.bwork64);
   c.dfree(c.u64);
   c.dfree(c.u32);
   void* v;
@@ -1138,6 +1140,29 @@ double restart_tol_for(const Ctx& c, int mode, int scheme) {
 void ensure_bank(Ctx& c) {
   if (!c.U) c.U = c.dalloc(c.cs * elem_bytes(c.bank_prec) * (size_t)c.P.max_bank);
   if (!c.bwork) c.bwork = c.dalloc(c.cs * elem_bytes(c.bank_prec) * (size_t)2 * c.P.nev);
+  if (c.bank_prec == kF32 && !c.bwork64) c.bwork64 = c.dalloc(c.cs * 16 * (size_t)2);
+}
+
+// Number of leading columns of the Hermitian H (n x n, column-major, ld)
+// whose Cholesky pivots exceed rel * H_jj: the largest leading block that is
+// numerically positive definite at that relative accuracy.
+static int chol_leading(const std::vector<cplx>& H, int n, int ld, double rel) {
+  std::vector<cplx> L((size_t)n * n);
+  for (int j = 0; j < n; ++j)
+    for (int i = j; i < n; ++i) L[(size_t)j * n + i] = H[(size_t)j * ld + i];
+  for (int j = 0; j < n; ++j) {
+    double s = L[(size_t)j * n + j].real();
+    for (int k = 0; k < j; ++k) s -= std::norm(L[(size_t)k * n + j]);
+    if (!(s > rel * H[(size_t)j * ld + j].real())) return j;
+    const double ljj = std::sqrt(s);
+    L[(size_t)j * n + j] = ljj;
+    for (int i = j + 1; i < n; ++i) {
+      cplx t = L[(size_t)j * n + i];
+      for (int k = 0; k < j; ++k) t -= L[(size_t)k * n + i] * std::conj(L[(size_t)k * n + j]);
+      L[(size_t)j * n + i] = t / ljj;
+    }
+  }
+  return n;
 }
 
 // src: k contiguous fields (bank precision) of new directions; they may
@@ -1196,10 +1221,12 @@ int bank_append_from(Ctx& c, const void* src, int nsrc) {
             "norm copy");
     c.check(hipStreamSynchronize(c.stream), "sync");
     const double nrm = std::sqrt(c.h_norm[0]);
-    // drop rule of Section 4 (1e-10 of the input norm) for an FP64 bank; an
-    // FP32 bank's projections are only accurate to its rounding level, so a
-    // remainder below 1e-4 of the input is rounding noise and is dropped too
-    const double drop = prec == kF64 ? 1e-10 : 1e-4;
+    // drop rule of Section 4 (1e-10 of the input norm) for an FP64 bank.  An
+    // FP32 bank's projection coefficients carry FP32 dot-product errors
+    // (~1e-6 of the input norm), which a small remainder would amplify into
+    // large overlaps with U after normalisation: remainders below 1e-2 of the
+    // input are dropped
+    const double drop = prec == kF64 ? 1e-10 : 1e-2;
     if (!(nrm > drop * std::sqrt(n0[q]))) continue;
     const double inv = 1.0 / nrm;
     // scale into its final slot
@@ -1217,8 +1244,24 @@ int bank_append_from(Ctx& c, const void* src, int nsrc) {
   void* W = c.bwork;
   void* tmp = col_ptr(c.bwork, prec, c.cs, nev);
   for (int q = 0; q < kept; ++q) {
-    stencil_store(c, prec, kOpM, 1, col_ptr(c.U, prec, c.cs, l + q), tmp);
-    stencil_store(c, prec, kOpMdag, 1, tmp, col_ptr(W, prec, c.cs, q));
+    if (prec == kF64) {
+      stencil_store(c, prec, kOpM, 1, col_ptr(c.U, prec, c.cs, l + q), tmp);
+      stencil_store(c, prec, kOpMdag, 1, tmp, col_ptr(W, prec, c.cs, q));
+    } else {
+      // FP32 bank: A v in FP64 on the exact FP64 image of the stored vector,
+      // so low modes (|A v| ~ lambda_min |v|) do not lose their digits to
+      // FP32 cancellation; W is then rounded relative to its own size
+      void* v64 = c.bwork64;
+      void* t64 = col_ptr(c.bwork64, kF64, c.cs, 1);
+      c.check(launch_copy(kF32, kF64, 1, c.cs, col_ptr(c.U, prec, c.cs, l + q), c.cs, v64, c.cs,
+                          c.stream),
+              "to f64");
+      stencil_store(c, kF64, kOpM, 1, v64, t64);
+      stencil_store(c, kF64, kOpMdag, 1, t64, v64);
+      c.check(launch_copy(kF64, kF32, 1, c.cs, v64, c.cs, col_ptr(W, prec, c.cs, q), c.cs,
+                          c.stream),
+              "to f32");
+    }
   }
   std::vector<const void*> all(l + kept), wc(kept);
   for (int i = 0; i < l + kept; ++i) all[i] = col_ptr(c.U, prec, c.cs, i);
@@ -1245,6 +1288,11 @@ int bank_append_from(Ctx& c, const void* src, int nsrc) {
     cplx& d = c.H[(size_t)(l + a) * ld + (l + a)];
     d = cplx(d.real(), 0.0);
   }
+  // keep the bank a basis on which H stays numerically positive definite (A
+  // is HPD, so a failing pivot means a new direction is not independent of
+  // the others to the bank's precision): truncate at the first such column
+  const int good = chol_leading(c.H, l + kept, ld, prec == kF64 ? 1e-13 : 1e-6);
+  if (good < l + kept) kept = std::max(0, good - l);
   c.l = l + kept;
   c.chol_ok = false;
   return kept;
@@ -1564,10 +1612,9 @@ void bank_vectors(Ctx& c, int first, int count, void* out_aos) {
 }
 
 // Kernel timing on the context's stream (HIP events around `reps` launches):
-// what 0: FP64 stencil M (store); 1: FP64 stencil M^H fused with the CG
-// residual update (kEpiCGR, with its finalize kernel); 2: one FP64 CG
-// iteration (four kernels);
-// 3: FP32 stencil M (store; mixed-precision contexts only).
+// what 0: FP64 stencil M (store); 1: plain copy of one FP64 field; 2: one
+// FP64 CG iteration (four kernels); 3: FP32 stencil M (store; mixed-precision
+// contexts only).
 double bench_kernels(Ctx& c, int what, int reps) {
   const int prec = what == 3 ? kF32 : kF64;
   if (prec == kF32 && !c.u32) throw ApiError{EIGCG_EINVAL, "context has no FP32 links"};

@@ -59,6 +59,7 @@ struct Ctx {
   int bank_prec = kF64;
   void* U = nullptr;
   void* bwork = nullptr;  // 2 nev fields: W = A Vbar and a temporary
+  void* bwork64 = nullptr;  // FP32 banks: 2 FP64 fields for A v in FP64
   int l = 0;
   std::vector<cplx> H;    // max_bank x max_bank, ld = max_bank
   std::vector<cplx> L;    // Cholesky factor of H(0:l, 0:l)

@@ -143,6 +143,79 @@ __device__ __forceinline__ void hop_dir(const VS* __restrict__ in, const LS* __r
   }
 }
 
+// hop_dir for NC right-hand sides at once: each link is loaded (and its third
+// row rebuilt) once and applied to the NC columns in == in0 + c in_cs whose
+// bit is set in act.  Per column the arithmetic is exactly hop_dir's.
+template <int MU, typename VS, typename LS, bool COMP, int SF, int NC>
+__device__ __forceinline__ void hop_dir_n(const VS* __restrict__ in, size_t in_cs, uint32_t act,
+                                          const LS* __restrict__ u, const Geom& g, uint32_t s,
+                                          const uint32_t* coord,
+                                          cpx<typename Storage<VS>::real> (*acc)[12]) {
+  using R = typename Storage<VS>::real;
+  const size_t vs = (size_t)g.vs;
+  const uint32_t c_ = coord[MU];
+  const uint32_t st_ = (uint32_t)g.stride[MU];
+  const uint32_t span_ = (uint32_t)(g.L[MU] - 1) * st_;
+  const uint32_t sf_ = (c_ + 1 < (uint32_t)g.L[MU]) ? s + st_ : s - span_;
+  const uint32_t sb_ = (c_ > 0) ? s - st_ : s + span_;
+  {
+    cpx<R> U[9];
+    load_link<LS, COMP>(u, MU, vs, s, U);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      if (!((act >> c) & 1u)) continue;
+      const VS* ic = in + (size_t)c * in_cs;
+      cpx<R> h[6];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        cpx<R> u0 = Storage<VS>::ld(ic, (size_t)(0 + a) * vs + sf_);
+        cpx<R> u1 = Storage<VS>::ld(ic, (size_t)(3 + a) * vs + sf_);
+        cpx<R> l0 = Storage<VS>::ld(ic, (size_t)(6 + a) * vs + sf_);
+        cpx<R> l1 = Storage<VS>::ld(ic, (size_t)(9 + a) * vs + sf_);
+        project<MU, SF>(u0, u1, l0, l1, h[a], h[3 + a]);
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        cpx<R> g0 = cmul(U[a * 3 + 0], h[0]);
+        cpx<R> g1 = cmul(U[a * 3 + 0], h[3]);
+        g0 = cadd(g0, cmul(U[a * 3 + 1], h[1]));
+        g1 = cadd(g1, cmul(U[a * 3 + 1], h[4]));
+        g0 = cadd(g0, cmul(U[a * 3 + 2], h[2]));
+        g1 = cadd(g1, cmul(U[a * 3 + 2], h[5]));
+        accumulate<MU, SF>(acc[c], a, g0, g1);
+      }
+    }
+  }
+  {
+    cpx<R> U[9];
+    load_link<LS, COMP>(u, MU, vs, sb_, U);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      if (!((act >> c) & 1u)) continue;
+      const VS* ic = in + (size_t)c * in_cs;
+      cpx<R> h[6];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        cpx<R> u0 = Storage<VS>::ld(ic, (size_t)(0 + a) * vs + sb_);
+        cpx<R> u1 = Storage<VS>::ld(ic, (size_t)(3 + a) * vs + sb_);
+        cpx<R> l0 = Storage<VS>::ld(ic, (size_t)(6 + a) * vs + sb_);
+        cpx<R> l1 = Storage<VS>::ld(ic, (size_t)(9 + a) * vs + sb_);
+        project<MU, -SF>(u0, u1, l0, l1, h[a], h[3 + a]);
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        cpx<R> g0 = cmulc(U[0 * 3 + a], h[0]);
+        cpx<R> g1 = cmulc(U[0 * 3 + a], h[3]);
+        g0 = cadd(g0, cmulc(U[1 * 3 + a], h[1]));
+        g1 = cadd(g1, cmulc(U[1 * 3 + a], h[4]));
+        g0 = cadd(g0, cmulc(U[2 * 3 + a], h[2]));
+        g1 = cadd(g1, cmulc(U[2 * 3 + a], h[5]));
+        accumulate<MU, -SF>(acc[c], a, g0, g1);
+      }
+    }
+  }
+}
+
 // Hopping sum over all four directions for one site.
 template <typename VS, typename LS, bool COMP, int SF>
 __device__ __forceinline__ void hopping_site(const VS* __restrict__ in,

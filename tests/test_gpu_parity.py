@@ -129,9 +129,12 @@ def test_eigcg_same_trajectory(B, cfg0, nev, m, iters):
 
 
 def test_eigcg_full_run_cfg0(B, cfg0):
-    """eigCG(10, 40) to 1e-8 on 4^4: same iterations and x as the oracle; every
-    Ritz pair of the resulting bank lies within its residual of the spectrum
-    of A (dense eigendecomposition)."""
+    """eigCG(10, 40) to 1e-8 on 4^4: the iteration count matches the oracle's
+    (to one iteration: both stop tests compare a recursively updated residual
+    with the tolerance, and their rounding differs), x matches the oracle's
+    iterate after the same number of iterations to 1e-10; every Ritz pair of
+    the resulting bank lies within its residual of the spectrum of A (dense
+    eigendecomposition)."""
     from oracle.dense import dense_A
     U, op, b = cfg0
     xo, _, _, io = eigcg(op.A, b.reshape(-1), 10, 40, tol=1e-8)
@@ -140,7 +143,9 @@ def test_eigcg_full_run_cfg0(B, cfg0):
         x = dev(np.zeros((1,) + b.shape, dtype=np.complex128))
         rc, st = B.eigcg_solve(ctx, dev(b[None]), x, 1e-8, B.EIGCG_MODE_EIGCG)
         assert rc == B.EIGCG_OK
-        assert st[0]["iters"] == io["iterations"]
+        assert abs(st[0]["iters"] - io["iterations"]) <= 1
+        if st[0]["iters"] != io["iterations"]:
+            xo, _, _, io = eigcg(op.A, b.reshape(-1), 10, 40, tol=0.0, max_iter=st[0]["iters"])
         assert rel(host(x)[0].reshape(-1), xo) <= 1e-10
         vals, res = B.eigcg_bank_info(ctx, residuals=True)
         A, _ = dense_A(op)
@@ -224,12 +229,19 @@ def test_incremental_eigcg_bank(B, cfg0):
             rc, st = B.eigcg_solve(ctx, dev(bs[i][None]), x, 1e-8, B.EIGCG_MODE_EIGCG)
             assert rc == B.EIGCG_OK
             its.append(st[0]["iters"])
-            # the first solve is the oracle's trajectory; later ones start from
-            # banks built past loss of orthogonality, whose rounding-level
-            # differences change the init-CG guess: both solutions then only
-            # agree to the accuracy their 1e-8 residuals fix
-            assert rel(host(x)[0].reshape(-1), xs[i]) <= (1e-10 if i == 0 else 1e-6)
-        assert its[0] == infos[0]["iterations"]
+            # the first solve is the oracle's trajectory (its stop test may fire
+            # one iteration apart: both test a recursive residual against the
+            # tolerance with different rounding; then compare after the same
+            # number of iterations); later ones start from banks built past
+            # loss of orthogonality, whose rounding-level differences change
+            # the init-CG guess: both solutions then only agree to the accuracy
+            # their 1e-8 residuals fix
+            ref = xs[i]
+            if i == 0:
+                assert abs(its[0] - infos[0]["iterations"]) <= 1
+                if its[0] != infos[0]["iterations"]:
+                    ref = eigcg(op.A, bs[0].reshape(-1), 4, 30, tol=0.0, max_iter=its[0])[0]
+            assert rel(host(x)[0].reshape(-1), ref) <= (1e-10 if i == 0 else 1e-6)
         assert its[2] < its[0]
         vals, _ = B.eigcg_bank_info(ctx)
         vo = np.linalg.eigvalsh(Ho)
@@ -240,11 +252,15 @@ def test_incremental_eigcg_bank(B, cfg0):
 
 
 def test_batched_columns_match_single(B, cfg0):
-    """Each column of a batched solve is bitwise the single-RHS solve."""
+    """Each column of a batched solve is bitwise the single-RHS solve run with
+    the same stencil variant (the autotuner may pick different variants for
+    different batch widths; each variant's results do not depend on the
+    width)."""
     U, op, _ = cfg0
     bs = gaussian_rhs_block((4, 4, 4, 4), [2000, 2001, 2002, 2003])
-    ctx1, _ = make_ctx(U, -0.2, max_batch=1)
     ctx4, _ = make_ctx(U, -0.2, max_batch=4)
+    ctx1, _ = make_ctx(U, -0.2, max_batch=1,
+                       stencil_variant=B.eigcg_layout_info(ctx4)["variant64"])
     try:
         x4 = dev(np.zeros_like(bs))
         rc, st4 = B.eigcg_solve(ctx4, dev(bs), x4, 1e-10, B.EIGCG_MODE_CG)
@@ -257,6 +273,34 @@ def test_batched_columns_match_single(B, cfg0):
     finally:
         B.eigcg_destroy(ctx1)
         B.eigcg_destroy(ctx4)
+
+
+@pytest.mark.parametrize("dims,variant", [((4, 4, 4, 4), 9), ((4, 4, 4, 4), 3),
+                                          ((8, 8, 2, 8), 9), ((8, 8, 2, 8), 5)])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batched_multicolumn_kernels_match_single(B, dims, variant, precision):
+    """Batches of 5 columns run the stencil with several right-hand sides per
+    workgroup (links loaded once for all of them); every column is bitwise
+    the single-RHS solve, in FP64 and in mixed precision (FP32 inner
+    iteration, lockstep FP64 reliable updates)."""
+    U = gauge_field(dims, 0.4, 3)
+    bs = gaussian_rhs_block(dims, [2200 + i for i in range(5)])
+    kw = dict(precision=precision, reliable_every=20, stencil_variant=variant, max_iter=3000)
+    ctx1, _ = make_ctx(U, -0.1, max_batch=1, **kw)
+    ctx5, _ = make_ctx(U, -0.1, max_batch=5, **kw)
+    try:
+        x5 = dev(np.zeros_like(bs))
+        rc, st5 = B.eigcg_solve(ctx5, dev(bs), x5, 1e-10, B.EIGCG_MODE_CG)
+        assert rc == B.EIGCG_OK
+        for i in range(5):
+            x1 = dev(np.zeros_like(bs[i:i + 1]))
+            rc, st1 = B.eigcg_solve(ctx1, dev(bs[i:i + 1]), x1, 1e-10, B.EIGCG_MODE_CG)
+            assert st1[0]["iters"] == st5[i]["iters"]
+            assert np.array_equal(host(x1)[0], host(x5)[i])
+            assert st5[i]["true_rel_res"] <= 1e-10
+    finally:
+        B.eigcg_destroy(ctx1)
+        B.eigcg_destroy(ctx5)
 
 
 def test_edge_cases(B, cfg0):
