@@ -202,7 +202,9 @@ def serving_leg(B, torch, n_bank_rhs, n_requests, seed=5):
     24^3x48): each field's FP32 bank is grown by mixed-precision eigCG on
     n_bank_rhs right-hand sides (not timed), then a seeded Poisson stream of
     n_requests deflated mixed-precision solves (tol 1e-10) is submitted to the
-    server; latency = submit to completion."""
+    server at a saturating rate (throughput, p50/p99 under queueing) and again
+    at half the measured capacity (p50/p99 latency); latency = submit to
+    completion."""
     import numpy as np
     from synthetic import gauge_field, gaussian_rhs
     rng = np.random.default_rng(seed)
@@ -262,37 +264,52 @@ def serving_leg(B, torch, n_bank_rhs, n_requests, seed=5):
         b = torch.from_numpy(gaussian_rhs(F["dims"], 9000 + i)).to("cuda:0")[None]
         reqs.append((int(f), b, torch.zeros_like(b)))
     torch.cuda.synchronize()
-    # offered load: mean gap = 1/4 of the mean isolated latency over the mix
-    mean_iso = float(np.mean([iso[int(f)] for f in which]))
-    gaps = rng.exponential(mean_iso / 4.0, n_requests)
-    srv = B.eigcg_server_create(0)
-    try:
-        fids = [B.eigcg_server_add(srv, F["ctx"]) for F in fields]
-        tickets = []
-        t0 = time.perf_counter()
-        t_next = t0
-        t_log = t0
-        for i, (f, b, x) in enumerate(reqs):
-            t_next += gaps[i]
-            while time.perf_counter() < t_next:
-                time.sleep(min(1e-3, max(0.0, t_next - time.perf_counter())))
-            tickets.append(B.eigcg_submit(srv, fids[f], b, x, TOL))
-            if time.perf_counter() - t_log > 5.0:
-                t_log = time.perf_counter()
+    def stream(idx, mean_gap, label):
+        """Submit requests idx with exponential gaps; returns (wall, results)."""
+        gaps = rng.exponential(mean_gap, len(idx))
+        srv = B.eigcg_server_create(0)
+        try:
+            fids = [B.eigcg_server_add(srv, F["ctx"]) for F in fields]
+            tickets = []
+            t0 = time.perf_counter()
+            t_next = t_log = t0
+            for n, i in enumerate(idx):
+                f, b, x = reqs[i]
+                t_next += gaps[n]
+                while time.perf_counter() < t_next:
+                    time.sleep(min(1e-3, max(0.0, t_next - time.perf_counter())))
+                tickets.append(B.eigcg_submit(srv, fids[f], b, x, TOL))
+                if time.perf_counter() - t_log > 5.0:
+                    t_log = time.perf_counter()
+                    ndone = sum(1 for t in tickets if B.eigcg_poll(srv, t)[0] != B.EIGCG_EBUSY)
+                    log(f"serving ({label}): {len(tickets)} submitted, {ndone} done")
+            while True:  # drain with progress lines
                 ndone = sum(1 for t in tickets if B.eigcg_poll(srv, t)[0] != B.EIGCG_EBUSY)
-                log(f"serving: {len(tickets)} submitted, {ndone} done")
-        while True:  # drain with progress lines
-            ndone = sum(1 for t in tickets if B.eigcg_poll(srv, t)[0] != B.EIGCG_EBUSY)
-            if ndone == len(tickets):
-                break
-            if time.perf_counter() - t_log > 5.0:
-                t_log = time.perf_counter()
-                log(f"serving: all {len(tickets)} submitted, {ndone} done")
-            time.sleep(2e-3)
-        t1 = time.perf_counter()
-        res = [B.eigcg_poll(srv, t) for t in tickets]
-    finally:
-        B.eigcg_server_destroy(srv)
+                if ndone == len(tickets):
+                    break
+                if time.perf_counter() - t_log > 5.0:
+                    t_log = time.perf_counter()
+                    log(f"serving ({label}): all {len(tickets)} submitted, {ndone} done")
+                time.sleep(2e-3)
+            t1 = time.perf_counter()
+            return t1 - t0, [B.eigcg_poll(srv, t) for t in tickets]
+        finally:
+            B.eigcg_server_destroy(srv)
+
+    # saturating load (throughput): mean gap = 1/4 of the mean isolated latency
+    mean_iso = float(np.mean([iso[int(f)] for f in which]))
+    all_idx = list(range(n_requests))
+    wall, res = stream(all_idx, mean_iso / 4.0, "saturated")
+    t0, t1 = 0.0, wall
+    # half of the measured capacity (latency): every other request again
+    half_idx = all_idx[::2]
+    wall_l, res_l = stream(half_idx, 2.0 * wall / n_requests, "half load")
+    lat_l = np.array([st["seconds"] for _, st in res_l])
+    light = {"requests": len(half_idx), "offered_rhs_per_s": 0.5 * n_requests / wall,
+             "rhs_per_s": len(half_idx) / wall_l,
+             "p50_s": float(np.percentile(lat_l, 50)), "p99_s": float(np.percentile(lat_l, 99)),
+             "failed": int(sum(1 for rc, st in res_l if rc != 0 or st["true_rel_res"] > TOL))}
+    log(f"serving at half capacity: p50 {light['p50_s'] * 1e3:.0f} ms p99 {light['p99_s'] * 1e3:.0f} ms")
     lat = np.array([st["seconds"] for _, st in res])
     ok = [rc == 0 and st["true_rel_res"] <= TOL for rc, st in res]
     per_field = []
@@ -302,7 +319,8 @@ def serving_leg(B, torch, n_bank_rhs, n_requests, seed=5):
             per_field.append({"dims": list(F["dims"]), "bank": F["bank"], "requests": int(sel.sum()),
                               "p50_s": float(np.percentile(lat[sel], 50)),
                               "p99_s": float(np.percentile(lat[sel], 99)),
-                              "mean_iters": float(np.mean([res[i][1]["iters"] for i in np.nonzero(sel)[0]]))})
+                              "mean_iters": float(np.mean([res[i][1]["iters"]
+                                                           for i in np.nonzero(sel)[0]]))})
     # plain FP64 single-RHS CG on each field (one of its requests' b) as the reference
     plain_s = []
     for k, F in enumerate(fields):
@@ -328,6 +346,7 @@ def serving_leg(B, torch, n_bank_rhs, n_requests, seed=5):
     out = {"requests": n_requests, "rhs_per_s": n_requests / (t1 - t0), "wall_s": t1 - t0,
            "plain_fp64_cg_same_mix_s": plain_mix, "speedup_vs_plain_fp64_cg": plain_mix / (t1 - t0),
            "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+           "half_load": light,
            "isolated_request_s": {str(list(fields[k]["dims"])): v for k, v in iso.items()},
            "failed": int(len(ok) - sum(ok)),
            "max_true_rel_res": max(st["true_rel_res"] for _, st in res), "per_field": per_field}
