@@ -160,7 +160,9 @@ int eigcg_memory(eigcg_ctx* ctx, uint64_t* bytes);
 /* info[0] = lattice sites V, info[1] = padded plane stride, info[2] = 1 when
  * the FP64 links are stored as two rows (12 reals), info[3] likewise for the
  * FP32 links of a mixed-precision context, info[4] / info[5] = stencil
- * variant used for FP64 / FP32; info needs 6 entries.  Variants:
+ * variant used for FP64 / FP32, info[6] / info[7] = columns per workgroup
+ * those variants run with (0 = the widest the batch allows: 2 for FP64, 4
+ * for FP32); info needs 8 entries.  Variants:
  *   1  thread per site, 256-site units dealt round-robin to workgroups
  *   2  thread per site, XCD-contiguous chunks of units
  *   3  two waves per 64-site tile (directions split, LDS exchange), XCD chunks
@@ -172,8 +174,9 @@ int eigcg_memory(eigcg_ctx* ctx, uint64_t* bytes);
  *   9  as 8 with at most two workgroups per compute unit
  * (8 and 9 need Lx Ly divisible by 64 and Lt by 8, else they run as 5 / 6).
  * eigcg_tune_report: tune_ms (18 doubles) receives the ms that variants 1..9
- * took for one CG-shaped pair of stencil passes at create, FP64 then FP32
- * (0 where not timed, e.g. a forced variant). */
+ * took (best over columns per workgroup) for one CG-shaped pair of stencil
+ * passes over a full batch at create, FP64 then FP32 (0 where not timed, e.g.
+ * a forced variant). */
 int eigcg_layout_info(eigcg_ctx* ctx, int32_t* info);
 int eigcg_tune_report(eigcg_ctx* ctx, double* tune_ms);
 

@@ -260,12 +260,13 @@ def eigcg_memory(ctx):
 
 
 def eigcg_layout_info(ctx):
-    info = (_I32 * 6)()
+    info = (_I32 * 8)()
     LIB.eigcg_layout_info(ctx, info)
     ms = np.zeros(2 * STENCIL_VARIANTS)
     LIB.eigcg_tune_report(ctx, _dptr(ms))
     return {"sites": info[0], "plane_stride": info[1], "links64_two_rows": bool(info[2]),
             "links32_two_rows": bool(info[3]), "variant64": info[4], "variant32": info[5],
+            "cols_per_group64": info[6], "cols_per_group32": info[7],
             "tune_ms64": ms[:STENCIL_VARIANTS].tolist(), "tune_ms32": ms[STENCIL_VARIANTS:].tolist()}
 
 

@@ -224,6 +224,8 @@ int eigcg_layout_info(eigcg_ctx* ctx, int32_t* info) {
   info[3] = ctx->c.comp32;
   info[4] = ctx->c.var64;
   info[5] = ctx->c.var32;
+  info[6] = ctx->c.nc64;
+  info[7] = ctx->c.nc32;
   return EIGCG_OK;
 }
 

@@ -458,8 +458,11 @@ hipError_t launch_typed(const StencilLaunch& L, hipStream_t s) {
   // do not depend on it, so every column's reductions are the same for any
   // batch width.  FP64 takes at most 2 (LDS of the exchange buffer).
   int nc = 1;
-  if (variant >= 3 && L.compressed && L.ncols >= 2)
-    nc = (L.ncols >= 4 && sizeof(typename Storage<VS>::real) == 4) ? 4 : 2;
+  if (variant >= 3 && L.compressed && L.ncols >= 2) {
+    const int widest = (L.ncols >= 4 && sizeof(typename Storage<VS>::real) == 4) ? 4 : 2;
+    nc = L.nc > 0 ? std::min(L.nc, widest) : widest;
+    if (nc == 3) nc = 2;
+  }
   if (nc > 1) dyn_lds = 0;  // the larger exchange buffer already caps occupancy
   dim3 grid(gx, (L.ncols + nc - 1) / nc), block(kBlock);
 #define EIGCG_PAIR(COMP, DAG, EPI, NT, ORD)                                                    \

@@ -92,35 +92,40 @@ static size_t elem_bytes(int prec) { return prec == kF64 ? 16 : 8; }
 static void ws_ensure(Ctx& c, Workspace& w, int prec, bool eig);
 static StencilLaunch stencil_base(Ctx& c, int prec);
 
-// Stencil autotuner: times every kernel variant (store epilogue, one column)
-// on this lattice and keeps the fastest.  The choice is cached per (lattice
-// shape, precision, link storage) for the process so that every context on
-// the same lattice runs the same arithmetic (variants differ in summation
-// order at the rounding level).  A forced variant in the parameters wins.
+// Stencil autotuner: times every kernel variant, and for the two-tile
+// variants every number of columns per workgroup, on this lattice at the
+// context's batch width, and keeps the fastest.  The choice is cached per
+// (lattice shape, precision, link storage, batch width) for the process.
+// Variants differ in summation order at the rounding level; columns per
+// workgroup do not change any column's arithmetic.  A forced variant in the
+// parameters wins (with the widest column grouping).
 static void autotune_stencil(Ctx& c, int prec) {
+  struct Pick {
+    std::vector<double> ms;  // best time per variant
+    int var, nc;
+  };
   static std::mutex mu;
-  static std::map<std::vector<int>, std::vector<double>> cache;
+  static std::map<std::vector<int>, Pick> cache;
   int& var = prec == kF64 ? c.var64 : c.var32;
+  int& ncs = prec == kF64 ? c.nc64 : c.nc32;
   double* tms = c.tune_ms + (prec == kF64 ? 0 : kStencilVariants);
   if (c.P.stencil_variant > 0) {
     var = c.P.stencil_variant;
+    ncs = 0;
     return;
   }
   const std::vector<int> key = {c.g.L[0], c.g.L[1], c.g.L[2], c.g.L[3], c.g.vs, prec,
                                 prec == kF64 ? c.comp64 : c.comp32, c.P.max_batch};
-  auto pick = [&](const std::vector<double>& t) {
-    int best = 1;
-    for (int v = 1; v <= kStencilVariants; ++v) {
-      tms[v - 1] = t[v - 1];
-      if (t[v - 1] < t[best - 1]) best = v;
-    }
-    var = best;
+  auto apply = [&](const Pick& pk) {
+    for (int v = 1; v <= kStencilVariants; ++v) tms[v - 1] = pk.ms[v - 1];
+    var = pk.var;
+    ncs = pk.nc;
   };
   {
     std::lock_guard<std::mutex> lk(mu);
     auto it = cache.find(key);
     if (it != cache.end()) {
-      pick(it->second);
+      apply(it->second);
       return;
     }
   }
@@ -134,35 +139,50 @@ static void autotune_stencil(Ctx& c, int prec) {
   hipEvent_t e0, e1;
   c.check(hipEventCreate(&e0), "ev");
   c.check(hipEventCreate(&e1), "ev");
-  std::vector<double> t(kStencilVariants, 0.0);
+  Pick pk;
+  pk.ms.assign(kStencilVariants, 0.0);
+  pk.var = 1;
+  pk.nc = 0;
+  double best = 1e300;
+  const int ncmax = (w.K >= 4 && prec == kF32) ? 4 : (w.K >= 2 ? 2 : 1);
   for (int v = 1; v <= kStencilVariants; ++v) {
-    StencilLaunch L1 = stencil_base(c, prec);
-    L1.variant = v;
-    L1.op = kOpM;
-    L1.epi = kEpiNorm;
-    L1.in = w.x; L1.in_cs = c.cs;
-    L1.out = w.tmp; L1.out_cs = c.cs;
-    L1.ncols = w.K;
-    L1.mask = w.K >= 32 ? 0xffffffffu : ((1u << w.K) - 1u);
-    StencilLaunch L2 = L1;
-    L2.op = kOpMdag;
-    L2.epi = kEpiRes;
-    L2.in = w.tmp;
-    L2.b = w.p; L2.b_cs = c.cs;
-    L2.r = w.r; L2.r_cs = c.cs;
-    auto pair = [&]() {
-      c.check(launch_stencil(L1, c.stream), "tune");
-      c.check(launch_stencil(L2, c.stream), "tune");
-    };
-    for (int i = 0; i < 2; ++i) pair();
-    const int reps = 8;
-    c.check(hipEventRecord(e0, c.stream), "ev");
-    for (int i = 0; i < reps; ++i) pair();
-    c.check(hipEventRecord(e1, c.stream), "ev");
-    c.check(hipEventSynchronize(e1), "ev");
-    float ms = 0.f;
-    c.check(hipEventElapsedTime(&ms, e0, e1), "ev");
-    t[v - 1] = (double)ms / reps;
+    for (int nc = 1; nc <= ncmax; nc *= 2) {
+      if (v < 3 && nc > 1) break;
+      StencilLaunch L1 = stencil_base(c, prec);
+      L1.variant = v;
+      L1.nc = nc;
+      L1.op = kOpM;
+      L1.epi = kEpiNorm;
+      L1.in = w.x; L1.in_cs = c.cs;
+      L1.out = w.tmp; L1.out_cs = c.cs;
+      L1.ncols = w.K;
+      L1.mask = w.K >= 32 ? 0xffffffffu : ((1u << w.K) - 1u);
+      StencilLaunch L2 = L1;
+      L2.op = kOpMdag;
+      L2.epi = kEpiRes;
+      L2.in = w.tmp;
+      L2.b = w.p; L2.b_cs = c.cs;
+      L2.r = w.r; L2.r_cs = c.cs;
+      auto pair = [&]() {
+        c.check(launch_stencil(L1, c.stream), "tune");
+        c.check(launch_stencil(L2, c.stream), "tune");
+      };
+      for (int i = 0; i < 2; ++i) pair();
+      const int reps = 8;
+      c.check(hipEventRecord(e0, c.stream), "ev");
+      for (int i = 0; i < reps; ++i) pair();
+      c.check(hipEventRecord(e1, c.stream), "ev");
+      c.check(hipEventSynchronize(e1), "ev");
+      float ms = 0.f;
+      c.check(hipEventElapsedTime(&ms, e0, e1), "ev");
+      const double t = (double)ms / reps;
+      if (pk.ms[v - 1] == 0.0 || t < pk.ms[v - 1]) pk.ms[v - 1] = t;
+      if (t < best) {
+        best = t;
+        pk.var = v;
+        pk.nc = nc;
+      }
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -170,8 +190,8 @@ static void autotune_stencil(Ctx& c, int prec) {
   c.check(hipStreamSynchronize(c.stream), "sync");
   std::lock_guard<std::mutex> lk(mu);
   auto it = cache.find(key);
-  if (it == cache.end()) it = cache.emplace(key, t).first;
-  pick(it->second);
+  if (it == cache.end()) it = cache.emplace(key, pk).first;
+  apply(it->second);
 }
 
 void ctx_init(Ctx& c, const eigcg_params& p, const void* gauge_dev, hipStream_t s) {
@@ -361,6 +381,7 @@ static StencilLaunch stencil_base(Ctx& c, int prec) {
   L.prec = prec;
   L.compressed = prec == kF64 ? c.comp64 : c.comp32;
   L.variant = prec == kF64 ? c.var64 : c.var32;
+  L.nc = prec == kF64 ? c.nc64 : c.nc32;
   L.u = prec == kF64 ? c.u64 : c.u32;
   L.g = &c.g;
   L.diag = 4.0 + c.P.mass;

@@ -52,6 +52,7 @@ struct Ctx {
   int device = 0;
   int comp64 = 0, comp32 = 0;
   int var64 = 1, var32 = 1;        // stencil kernel variants in use
+  int nc64 = 0, nc32 = 0;          // their columns per workgroup (0 = widest)
   double tune_ms[2 * kStencilVariants] = {};  // FP64 then FP32, per variant
   void* u64 = nullptr;
   void* u32 = nullptr;

@@ -200,19 +200,35 @@ __global__ __launch_bounds__(256) void k_gemm_reduce(size_t n, int K, int N, siz
   }
 }
 
+// One workgroup per output G[i, j]: thread t sums chunks t, t + 256, ... in
+// order, then the workgroup combines the 256 sums in a fixed order, so the
+// result depends only on the chunking (which does not depend on N).
 __global__ __launch_bounds__(256) void k_gemm_reduce_final(int K, int N, int nchunk,
                                                            const double* partial, double2* G) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;  // over K*N complex outputs
-  if (idx >= K * N) return;
+  __shared__ double lds[2][4];
+  const int idx = blockIdx.x;  // over K*N complex outputs
   const int i = idx % K, j = idx / K;
-  double re = 0.0, im = 0.0;
   const size_t stride = (size_t)K * 2 * N;
-  for (int c = 0; c < nchunk; ++c) {
+  double re = 0.0, im = 0.0;
+  for (int c = threadIdx.x; c < nchunk; c += 256) {
     const double* p = partial + (size_t)c * stride + (size_t)i * 2 * N + 2 * j;
     re += p[0];
     im += p[1];
   }
-  G[(size_t)j * K + i] = make_double2(re, im);
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    re += __shfl_xor(re, off, 64);
+    im += __shfl_xor(im, off, 64);
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    lds[0][w] = re;
+    lds[1][w] = im;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    G[(size_t)j * K + i] = make_double2(lds[0][0] + lds[0][1] + lds[0][2] + lds[0][3],
+                                        lds[1][0] + lds[1][1] + lds[1][2] + lds[1][3]);
 }
 
 template <typename VS>
@@ -240,8 +256,11 @@ hipError_t reduce_typed(size_t n, int K, int N, const void* const* in_cols,
   TallArgs a;
   for (int i = 0; i < K; ++i) a.in[i] = in_cols[i];
   for (int j = 0; j < N; ++j) a.out[j] = const_cast<void*>(r_cols[j]);
-  // chunk so that the partial buffer (nchunk * K * 2N doubles) fits
-  size_t per_chunk = (size_t)K * N;  // double2 elements per chunk
+  // chunk so that the partial buffer (nchunk * K * 2N doubles) fits for the
+  // widest N, so the chunking (and every column's summation order) does not
+  // depend on how many columns are reduced together
+  if (N > kMaxN) return hipErrorInvalidValue;
+  size_t per_chunk = (size_t)K * kMaxN;  // double2 elements per chunk
   size_t max_chunks = partial_elems / per_chunk;
   if (max_chunks == 0) return hipErrorInvalidValue;
   size_t want = 1024;
@@ -260,8 +279,7 @@ hipError_t reduce_typed(size_t n, int K, int N, const void* const* in_cols,
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int outs = K * N;
-  hipLaunchKernelGGL(k_gemm_reduce_final, dim3((outs + 255) / 256), dim3(256), 0, s, K, N, nchunk,
-                     part, G);
+  hipLaunchKernelGGL(k_gemm_reduce_final, dim3(outs), dim3(256), 0, s, K, N, nchunk, part, G);
   return hipGetLastError();
 }
 

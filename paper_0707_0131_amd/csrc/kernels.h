@@ -57,6 +57,8 @@ struct StencilLaunch {
   double* hist; int hist_stride;    // kEpiCGR: per column 3 doubles per iteration
   hipEvent_t ev_mid = nullptr;      // recorded after the stencil kernel, before the
                                     // finalize kernel of kEpiCGR / kEpiRes
+  int nc = 0;                       // variants 3..9: columns per workgroup (1, 2, or 4
+                                    // for FP32); 0 = widest that ncols allows
 };
 
 hipError_t launch_stencil(const StencilLaunch& L, hipStream_t s);
