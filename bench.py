@@ -69,6 +69,7 @@ def run_step(B, torch, g, mass, bt, xt, n_eig=N_EIG):
         t2 = time.perf_counter()
         vals, _ = B.eigcg_bank_info(ctx)
         samples = B.eigcg_kernel_samples(ctx)["f64"]
+        samples["stencil_variant"] = B.eigcg_layout_info(ctx)["variant64"]
     finally:
         B.eigcg_destroy(ctx)
     bad = [s for s in st1 + st2 if s["status"] != 0 or s["true_rel_res"] > TOL]
@@ -125,12 +126,12 @@ def measured_traffic():
     return float(t.group(1))
 
 
-def stencil_roofline(B, torch, dims, seed, reps):
+def stencil_roofline(B, torch, dims, seed, reps, variant=0):
     from synthetic import gauge_field
     U = gauge_field(dims, EPS, seed)
     g = torch.from_numpy(U).to("cuda:0")
     del U
-    p = B.eigcg_default_params(dims=dims, mass=-0.5, max_bank=0)
+    p = B.eigcg_default_params(dims=dims, mass=-0.5, max_bank=0, stencil_variant=variant)
     ctx = B.eigcg_create(p, g)
     try:
         info = B.eigcg_layout_info(ctx)
@@ -174,7 +175,7 @@ def batching_leg(B, torch, g, bt, nrhs=12):
                 continue
             p = B.eigcg_default_params(dims=LATTICE, mass=BATCH_MASS, precision=prec, max_batch=k,
                                        reliable_every=50, max_iter=40000, check_every=32,
-                                       max_bank=0)
+                                       max_bank=0, use_graphs=1)
             ctx = B.eigcg_create(p, g)
             try:
                 x = torch.zeros_like(bt[:nrhs])
@@ -231,7 +232,7 @@ def serving_leg(B, torch, n_bank_rhs, n_requests, seed=5):
             B.eigcg_destroy(ctx64)
         p = B.eigcg_default_params(dims=dims, mass=SERVE_MASS, precision=1, max_batch=12, nev=NEV,
                                    m=M, max_bank=NBANK, reliable_every=50, max_iter=SERVE_MAX_ITER,
-                                   check_every=16)
+                                   check_every=16, use_graphs=1)
         ctx = B.eigcg_create(p, g)
         B.eigcg_bank_load(ctx, vecs)
         del vecs
@@ -397,6 +398,9 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-bank-rhs", type=int, default=N_EIG)
     ap.add_argument("--serve-requests", type=int, default=120)
+    ap.add_argument("--stencil-variant", type=int, default=0,
+                    help="with --roofline-only: force this stencil variant (counter runs "
+                         "use the variant the full bench run picked)")
     ap.add_argument("--roofline-only", choices=("bench", "hbm"),
                     help="only time the stencil, copy and CG iteration on the bench lattice "
                          "or the 24^3x48 lattice (short runs for counter collection)")
@@ -414,7 +418,8 @@ def main():
     if args.roofline_only:
         dims, seed = (LATTICE, SEED) if args.roofline_only == "bench" else (HBM_LATTICE, HBM_SEED)
         log(f"stencil timings only ({dims})")
-        print(json.dumps({"stencil": stencil_roofline(B, torch, dims, seed, 100)}))
+        print(json.dumps({"stencil": stencil_roofline(B, torch, dims, seed, 100,
+                                                      args.stencil_variant)}))
         return
     log(f"generating {LATTICE} links and {args.n_eig + args.n_defl} right-hand sides")
     U = gauge_field(LATTICE, EPS, SEED)
@@ -435,6 +440,7 @@ def main():
 
     steps = []
     torch.cuda.synchronize()
+    win0 = time.monotonic_ns()  # timed window on the clock kernel traces use
     t0 = time.perf_counter()
     for k in range(args.steps):
         r = run_step(B, torch, g, MASSES[k % len(MASSES)], bt, xt, n_eig)
@@ -445,6 +451,7 @@ def main():
             f"max res {r['max_true_rel_res']:.1e} failed {r['failed']}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    win1 = time.monotonic_ns()
     total_rhs = nrhs * args.steps
     value = total_rhs / elapsed
 
@@ -542,9 +549,11 @@ def main():
             "frac": achieved / HBM_PEAK_GBS if achieved else None,
             "traffic": traffic,
             "launch_ms": pass2_ms,
+            "stencil_variant": steps[0]["samples"]["stencil_variant"] if steps else None,
             "sampled_launches": n_s,
             "algorithmic_bytes_per_launch": pass2_bytes,
         },
+        "timed_window_monotonic_ns": [win0, win1],
         "stencil_pass1": {"launch_ms": pass1_ms, "GBs": pass1_bytes / pass1_ms / 1e6 if n_s else None,
                           "algorithmic_bytes_per_launch": pass1_bytes},
         "batching": batching,

@@ -13,6 +13,8 @@
 
 #include <mutex>
 
+#include <hip/hip_ext.h>
+
 #include "kernels.h"
 #include "wilson.h"
 
@@ -465,27 +467,27 @@ hipError_t launch_typed(const StencilLaunch& L, hipStream_t s) {
   }
   if (nc > 1) dyn_lds = 0;  // the larger exchange buffer already caps occupancy
   dim3 grid(gx, (L.ncols + nc - 1) / nc), block(kBlock);
-#define EIGCG_PAIR(COMP, DAG, EPI, NT, ORD)                                                    \
-  if (nc == 4)                                                                                \
-    hipLaunchKernelGGL((k_wilson_pair<VS, LS, COMP, DAG, EPI, NT, ORD, NC4>), grid, block,     \
-                       dyn_lds, s, a);                                                        \
-  else if (nc == 2)                                                                           \
-    hipLaunchKernelGGL((k_wilson_pair<VS, LS, COMP, DAG, EPI, NT, ORD, 2>), grid, block,       \
-                       dyn_lds, s, a);                                                        \
-  else                                                                                        \
-    hipLaunchKernelGGL((k_wilson_pair<VS, LS, COMP, DAG, EPI, NT, ORD, 1>), grid, block,       \
-                       dyn_lds, s, a);
-#define EIGCG_K(COMP, DAG, EPI)                                                               \
-  if (variant >= 8) {                                                                         \
-    EIGCG_PAIR(COMP, DAG, EPI, true, 1)                                                       \
-  } else if (variant >= 4) {                                                                  \
-    EIGCG_PAIR(COMP, DAG, EPI, true, 0)                                                       \
-  } else if (variant == 3) {                                                                  \
-    EIGCG_PAIR(COMP, DAG, EPI, false, 0)                                                      \
-  } else if (variant == 2) {                                                                  \
-    hipLaunchKernelGGL((k_wilson<VS, LS, COMP, DAG, EPI, true>), grid, block, 0, s, a);       \
-  } else {                                                                                    \
-    hipLaunchKernelGGL((k_wilson<VS, LS, COMP, DAG, EPI, false>), grid, block, 0, s, a);      \
+#define EIGCG_LAUNCH(KERNEL, LDS)                                                     \
+  hipExtLaunchKernelGGL(KERNEL, grid, block, LDS, s, L.ev_start, L.ev_stop, 0, a);
+#define EIGCG_PAIR(COMP, DAG, EPI, NT, ORD)                                           \
+  if (nc == 4) {                                                                     \
+    EIGCG_LAUNCH((k_wilson_pair<VS, LS, COMP, DAG, EPI, NT, ORD, NC4>), dyn_lds)     \
+  } else if (nc == 2) {                                                              \
+    EIGCG_LAUNCH((k_wilson_pair<VS, LS, COMP, DAG, EPI, NT, ORD, 2>), dyn_lds)       \
+  } else {                                                                           \
+    EIGCG_LAUNCH((k_wilson_pair<VS, LS, COMP, DAG, EPI, NT, ORD, 1>), dyn_lds)       \
+  }
+#define EIGCG_K(COMP, DAG, EPI)                                                      \
+  if (variant >= 8) {                                                                \
+    EIGCG_PAIR(COMP, DAG, EPI, true, 1)                                              \
+  } else if (variant >= 4) {                                                         \
+    EIGCG_PAIR(COMP, DAG, EPI, true, 0)                                              \
+  } else if (variant == 3) {                                                         \
+    EIGCG_PAIR(COMP, DAG, EPI, false, 0)                                             \
+  } else if (variant == 2) {                                                         \
+    EIGCG_LAUNCH((k_wilson<VS, LS, COMP, DAG, EPI, true>), 0)                        \
+  } else {                                                                           \
+    EIGCG_LAUNCH((k_wilson<VS, LS, COMP, DAG, EPI, false>), 0)                       \
   }
 #define EIGCG_EPI(COMP, DAG)                                  \
   switch (L.epi) {                                            \
@@ -502,12 +504,9 @@ hipError_t launch_typed(const StencilLaunch& L, hipStream_t s) {
 #undef EIGCG_EPI
 #undef EIGCG_K
 #undef EIGCG_PAIR
+#undef EIGCG_LAUNCH
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (L.ev_mid) {
-    e = hipEventRecord(L.ev_mid, s);
-    if (e != hipSuccess) return e;
-  }
   if (L.epi == kEpiCGR)
     hipLaunchKernelGGL(k_finalize_cg, dim3(L.ncols), dim3(kBlock), 0, s, L.st, L.ncols, L.mask, part_a,
                        part_b, gx, L.hist, L.hist_stride);

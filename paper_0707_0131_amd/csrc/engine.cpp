@@ -292,13 +292,15 @@ void ctx_release(Ctx& c) {
   for (auto& k : c.ks_pool)
     for (auto& e : k.e) (void)hipEventDestroy(e);
   c.ks_pool.clear();
+  if (c.gstream) (void)hipStreamDestroy(c.gstream);
+  c.gstream = nullptr;
 }
 
 // Fold the recorded stencil samples into the running sums.  All samples were
 // recorded on one in-order stream, so the last one completing means all have.
 bool Ctx::ks_harvest(bool wait) {
   if (ks_used == 0) return true;
-  hipEvent_t last = ks_pool[ks_used - 1].e[2];
+  hipEvent_t last = ks_pool[ks_used - 1].e[3];
   if (wait) {
     check(hipEventSynchronize(last), "sample wait");
   } else {
@@ -310,7 +312,7 @@ bool Ctx::ks_harvest(bool wait) {
     KSample& k = ks_pool[i];
     float a = 0.f, b = 0.f;
     check(hipEventElapsedTime(&a, k.e[0], k.e[1]), "sample time");
-    check(hipEventElapsedTime(&b, k.e[1], k.e[2]), "sample time");
+    check(hipEventElapsedTime(&b, k.e[2], k.e[3]), "sample time");
     const int p = k.prec == kF64 ? 0 : 1;
     ks_sum[p][0] += a;
     ks_sum[p][1] += b;
@@ -569,6 +571,10 @@ struct Run {
   std::vector<int> stale_until;  // snapshots of segments <= this id predate a host restart
   int enq_iter = 0;              // iterations enqueued (all columns in lockstep)
   int seg_id = 0;                // id of the last enqueued segment
+  // captured segments of n iterations (params.use_graphs): the kernels of a
+  // segment only depend on this run's buffers, mask and width, so one graph
+  // per segment length serves the whole run
+  std::map<int, hipGraphExec_t> graphs;
 
   Run(Ctx& c_, Workspace& w_, int prec_, int K_, uint32_t mask_, bool eig_)
       : c(c_), w(w_), prec(prec_), K(K_), mask(mask_), eig(eig_) {
@@ -584,6 +590,11 @@ struct Run {
     stale_until.assign(K, -1);
     for (int j = 0; j < K; ++j) ec[j].next_full = m;
   }
+  ~Run() {
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+  }
+  Run(const Run&) = delete;
+  Run& operator=(const Run&) = delete;
 
   void* ringslot(int col, int k) const {
     const int slot = k % w.ring_len;
@@ -645,12 +656,42 @@ struct Run {
     L3.ring_cs = c.cs;
     L3.ring_len = w.ring_len;
     L3.ring_col_cs = (size_t)w.ring_len * c.cs;
+    if (c.P.use_graphs && c.P.sample_every <= 0 && n > 0) {
+      auto it = graphs.find(n);
+      if (it == graphs.end()) {
+        // captured on a private stream (the context's stream may be the null
+        // stream, which cannot be captured); replayed on the context's stream
+        if (!c.gstream) c.check(hipStreamCreateWithFlags(&c.gstream, hipStreamNonBlocking), "stream");
+        hipGraph_t gr = nullptr;
+        hipGraphExec_t ex = nullptr;
+        c.check(hipStreamBeginCapture(c.gstream, hipStreamCaptureModeThreadLocal), "capture");
+        hipError_t e = hipSuccess;
+        for (int i = 0; i < n && e == hipSuccess; ++i) {
+          e = launch_stencil(L1, c.gstream);
+          if (e == hipSuccess) e = launch_stencil(L2, c.gstream);
+          if (e == hipSuccess) e = launch_cg_update(L3, c.gstream);
+        }
+        const hipError_t e2 = hipStreamEndCapture(c.gstream, &gr);
+        c.check(e, "captured launch");
+        c.check(e2, "end capture");
+        const hipError_t e3 = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+        c.check(e3, "graph instantiate");
+        it = graphs.emplace(n, ex).first;
+      }
+      c.check(hipGraphLaunch(it->second, c.stream), "graph launch");
+      enq_iter += n;
+      return;
+    }
     for (int i = 0; i < n; ++i) {
+      // sampled iterations time each stencil kernel by its own dispatch
+      // timestamps (no extra packets between the kernels)
       Ctx::KSample* ks = sample_slot();
-      if (ks) c.check(hipEventRecord(ks->e[0], c.stream), "sample");
+      L1.ev_start = ks ? ks->e[0] : nullptr;
+      L1.ev_stop = ks ? ks->e[1] : nullptr;
+      L2.ev_start = ks ? ks->e[2] : nullptr;
+      L2.ev_stop = ks ? ks->e[3] : nullptr;
       c.check(launch_stencil(L1, c.stream), "K1");
-      if (ks) c.check(hipEventRecord(ks->e[1], c.stream), "sample");
-      L2.ev_mid = ks ? ks->e[2] : nullptr;
       c.check(launch_stencil(L2, c.stream), "K2");
       c.check(launch_cg_update(L3, c.stream), "K3");
     }

@@ -49,6 +49,7 @@ struct Ctx {
   Geom g{};
   size_t cs = 0;         // complex elements per field (12 * vs)
   hipStream_t stream = nullptr;
+  hipStream_t gstream = nullptr;  // capture-only stream for HIP graphs
   int device = 0;
   int comp64 = 0, comp32 = 0;
   int var64 = 1, var32 = 1;        // stencil kernel variants in use
@@ -90,7 +91,7 @@ struct Ctx {
   // sampled stencil timings: events around the two passes of every
   // P.sample_every-th iteration, harvested when the pool is full or on request
   struct KSample {
-    hipEvent_t e[3];
+    hipEvent_t e[4];  // start / end of pass 1, start / end of pass 2
     int prec;
     int ncols;
   };

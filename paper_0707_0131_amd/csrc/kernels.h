@@ -55,8 +55,8 @@ struct StencilLaunch {
   const void* b; size_t b_cs;       // kEpiRes right-hand side
   void* tbuf; size_t t_cs;  // kEpiCGR: two t slots per column (slot = j & 1)
   double* hist; int hist_stride;    // kEpiCGR: per column 3 doubles per iteration
-  hipEvent_t ev_mid = nullptr;      // recorded after the stencil kernel, before the
-                                    // finalize kernel of kEpiCGR / kEpiRes
+  hipEvent_t ev_start = nullptr;    // when set: timestamps of the stencil kernel's own
+  hipEvent_t ev_stop = nullptr;     // start and end, taken by its dispatch
   int nc = 0;                       // variants 3..9: columns per workgroup (1, 2, or 4
                                     // for FP32); 0 = widest that ncols allows
 };

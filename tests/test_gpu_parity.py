@@ -368,3 +368,27 @@ def test_mixed_precision_eigcg_bank(B, cfg0):
         assert rc == B.EIGCG_OK and st[0]["true_rel_res"] <= 1e-10
     finally:
         B.eigcg_destroy(ctx)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_graph_replay_matches_eager(B, cfg0, precision):
+    """CG segments replayed from captured HIP graphs give bitwise the eager
+    result, over several solves in a row (each replays its graphs many times,
+    with the solver's own copies and host synchronisations in between)."""
+    U, op, _ = cfg0
+    bs = gaussian_rhs_block((4, 4, 4, 4), [2300 + i for i in range(3)])
+    kw = dict(precision=precision, max_batch=3, reliable_every=20, max_iter=3000, check_every=8)
+    ctx_e, _ = make_ctx(U, -0.2, **kw)
+    ctx_g, _ = make_ctx(U, -0.2, use_graphs=1, **kw)
+    try:
+        for rep in range(3):
+            xe = dev(np.zeros_like(bs))
+            xg = dev(np.zeros_like(bs))
+            rc_e, st_e = B.eigcg_solve(ctx_e, dev(bs), xe, 1e-10, B.EIGCG_MODE_CG)
+            rc_g, st_g = B.eigcg_solve(ctx_g, dev(bs), xg, 1e-10, B.EIGCG_MODE_CG)
+            assert rc_e == rc_g == B.EIGCG_OK
+            assert [s["iters"] for s in st_e] == [s["iters"] for s in st_g]
+            assert np.array_equal(host(xe), host(xg)), rep
+    finally:
+        B.eigcg_destroy(ctx_e)
+        B.eigcg_destroy(ctx_g)
