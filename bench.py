@@ -49,7 +49,8 @@ def site_bytes_stencil(two_row_links: bool, elem=16):
 
 
 SAMPLE_EVERY = 4  # stencil passes of every 4th CG iteration are timed with events
-STENCIL_SOURCES = ("paper_0707_0131_amd/csrc/dslash.hip", "paper_0707_0131_amd/csrc/wilson.h",
+STENCIL_SOURCES = ("paper_0707_0131_amd/csrc/stencil_impl.h",
+                   "paper_0707_0131_amd/csrc/dslash_f64.hip", "paper_0707_0131_amd/csrc/wilson.h",
                    "paper_0707_0131_amd/csrc/common.h")
 TRAFFIC_SUMMARY = "profiles/k_wilson_pair_cgr_f64_16x16x16x32.md"
 

@@ -58,7 +58,7 @@ enum {
   EIGCG_EBUSY = -6        /* serving: ticket not finished yet */
 };
 
-enum { EIGCG_FP64 = 0, EIGCG_MIXED_FP32 = 1 };
+enum { EIGCG_FP64 = 0, EIGCG_MIXED_FP32 = 1, EIGCG_MIXED_HALF = 2 };
 enum { EIGCG_MODE_CG = 0, EIGCG_MODE_EIGCG = 1, EIGCG_MODE_INITCG = 2 };
 enum { EIGCG_OP_M = 0, EIGCG_OP_MDAG = 1, EIGCG_OP_A = 2 };
 
@@ -67,7 +67,12 @@ typedef struct {
   double mass;            /* m_q */
   int32_t nev, m;         /* eigCG(nev, m); requires m > 2 nev >= 2 (Figure 3.1) */
   int32_t max_bank;       /* most columns of U (<= 256) */
-  int32_t precision;      /* EIGCG_FP64 or EIGCG_MIXED_FP32 */
+  int32_t precision;      /* EIGCG_FP64; EIGCG_MIXED_FP32 (FP32 iterations, FP64
+                             reliable updates in CG and eigCG modes, FP64
+                             refinement in init-CG mode); EIGCG_MIXED_HALF
+                             (16-bit links and vectors with FP32 arithmetic and
+                             an FP32 iterate, each inner solve rescaled, FP64
+                             refinement; CG and init-CG modes only) */
   int32_t max_batch;      /* right-hand sides per batched launch, 1..12 */
   int32_t reliable_every; /* mixed precision: FP64 reliable update period */
   int32_t max_iter;       /* per right-hand side */

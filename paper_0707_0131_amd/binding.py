@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(HERE, "libeigcg.so")
 EIGCG_OK, EIGCG_EINVAL, EIGCG_ENOMEM, EIGCG_ENOTCONV = 0, -1, -2, -3
 STENCIL_VARIANTS = 9
 EIGCG_EBREAKDOWN, EIGCG_EHIP, EIGCG_EBUSY = -4, -5, -6
-EIGCG_FP64, EIGCG_MIXED_FP32 = 0, 1
+EIGCG_FP64, EIGCG_MIXED_FP32, EIGCG_MIXED_HALF = 0, 1, 2
 EIGCG_MODE_CG, EIGCG_MODE_EIGCG, EIGCG_MODE_INITCG = 0, 1, 2
 EIGCG_OP_M, EIGCG_OP_MDAG, EIGCG_OP_A = 0, 1, 2
 

@@ -54,7 +54,8 @@ int validate(const eigcg_params* p, std::string& why) {
     return EIGCG_EINVAL;
   }
   if (p->max_bank < 0 || p->max_bank > 256) { why = "max_bank must be in [0, 256]"; return EIGCG_EINVAL; }
-  if (p->precision != EIGCG_FP64 && p->precision != EIGCG_MIXED_FP32) { why = "bad precision"; return EIGCG_EINVAL; }
+  if (p->precision != EIGCG_FP64 && p->precision != EIGCG_MIXED_FP32 &&
+      p->precision != EIGCG_MIXED_HALF) { why = "bad precision"; return EIGCG_EINVAL; }
   if (p->max_batch < 1 || p->max_batch > 12) { why = "max_batch must be in [1, 12]"; return EIGCG_EINVAL; }
   if (p->max_iter < 1 || p->max_iter > 10000000) { why = "bad max_iter"; return EIGCG_EINVAL; }
   if (p->check_every < 1) { why = "check_every must be >= 1"; return EIGCG_EINVAL; }

@@ -19,7 +19,7 @@ inline int grid_for(size_t n) {
 
 // CG step 3 (Figure 3.1, steps 13, 3-9 and 11.13 of the next iteration):
 // x += alpha p; p = r + beta p; window slot (iter+1) % ring = r / sqrt(rho).
-template <typename VS>
+template <typename VS, typename XS>
 __global__ __launch_bounds__(kBlock) void k_cg_update(UpdateLaunch a, Geom g) {
   using R = typename Storage<VS>::real;
   const int col = blockIdx.y;
@@ -29,7 +29,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(UpdateLaunch a, Geom g) {
   const bool run = S.state == ColRun;
   const R alpha = (R)S.alpha, beta = (R)S.beta;
   const R inv = run ? (R)(1.0 / sqrt(S.rho)) : R(0);
-  VS* x = reinterpret_cast<VS*>(a.x) + (size_t)col * a.x_cs;
+  XS* x = reinterpret_cast<XS*>(a.x) + (size_t)col * a.x_cs;
   VS* p = reinterpret_cast<VS*>(a.p) + (size_t)col * a.p_cs;
   const VS* r = reinterpret_cast<const VS*>(a.r) + (size_t)col * a.r_cs;
   VS* v = nullptr;
@@ -43,10 +43,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(UpdateLaunch a, Geom g) {
     for (int e = 0; e < 12; ++e) {
       const size_t i = (size_t)e * vs + s;
       cpx<R> pv = Storage<VS>::ld(p, i);
-      cpx<R> xv = Storage<VS>::ld(x, i);
+      cpx<R> xv = Storage<XS>::ld(x, i);
       xv.re += alpha * pv.re;
       xv.im += alpha * pv.im;
-      Storage<VS>::st(x, i, xv);
+      Storage<XS>::st(x, i, xv);
       if (run) {
         cpx<R> rv = Storage<VS>::ld(r, i);
         Storage<VS>::st(p, i, {rv.re + beta * pv.re, rv.im + beta * pv.im});
@@ -274,19 +274,56 @@ __global__ __launch_bounds__(kBlock) void k_xpby(size_t n, const VS* t1, const V
   }
 }
 
+// x64 += e32 (divided by the column's inner scale when st is given); e32 = 0
 __global__ __launch_bounds__(kBlock) void k_accum(size_t n, double2* x, size_t x_cs, float2* e,
-                                                  size_t e_cs, uint32_t mask) {
+                                                  size_t e_cs, uint32_t mask, const ColState* st) {
   const int col = blockIdx.y;
   if (!((mask >> col) & 1u)) return;
+  const double inv = st ? 1.0 / st[col].scale : 1.0;
   double2* xc = x + (size_t)col * x_cs;
   float2* ec = e + (size_t)col * e_cs;
   for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
     float2 ev = ec[i];
     double2 xv = xc[i];
-    xv.x += (double)ev.x;
-    xv.y += (double)ev.y;
+    if (st) {
+      xv.x += (double)ev.x * inv;
+      xv.y += (double)ev.y * inv;
+    } else {
+      xv.x += (double)ev.x;
+      xv.y += (double)ev.y;
+    }
     xc[i] = xv;
     ec[i] = make_float2(0.f, 0.f);
+  }
+}
+
+// Inner-solve scaling of 16-bit iterations: for every masked running column
+// s = c0 / sqrt(rho) (rho = FP64 true r^H r), so the scaled residual has an
+// RMS entry of c0 / sqrt(n); rho and the inner stop move to the scaled units.
+__global__ void k_set_scale(ColState* st, int ncols, uint32_t mask, double c0) {
+  const int c = threadIdx.x;
+  if (c >= ncols || !((mask >> c) & 1u)) return;
+  ColState& S = st[c];
+  if (S.state != ColRun) return;
+  const double s = S.rho > 0.0 ? c0 / sqrt(S.rho) : 1.0;
+  S.scale = s;
+  S.rho *= s * s;
+  S.restart2 *= s * s;
+}
+
+// y (16-bit) = scale_col * x (FP64) for running columns
+__global__ __launch_bounds__(kBlock) void k_to_inner16(size_t n, const double2* x, size_t x_cs,
+                                                       f16x2* y, size_t y_cs, uint32_t mask,
+                                                       const ColState* st) {
+  const int col = blockIdx.y;
+  if (!((mask >> col) & 1u)) return;
+  if (st[col].state != ColRun) return;
+  const double f = st[col].scale;
+  const double2* xc = x + (size_t)col * x_cs;
+  f16x2* yc = y + (size_t)col * y_cs;
+  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+    const double2 v = xc[i];
+    Storage<f16x2>::st(yc, i, {(float)(v.x * f), (float)(v.y * f)});
   }
 }
 
@@ -332,9 +369,11 @@ hipError_t launch_set_state(ColState* st, int ncols, uint32_t mask, int state, i
 hipError_t launch_cg_update(const UpdateLaunch& L, hipStream_t s) {
   dim3 grid(grid_for(L.g->V), L.ncols);
   if (L.prec == kF64)
-    hipLaunchKernelGGL(k_cg_update<double2>, grid, dim3(kBlock), 0, s, L, *L.g);
-  else
-    hipLaunchKernelGGL(k_cg_update<float2>, grid, dim3(kBlock), 0, s, L, *L.g);
+    hipLaunchKernelGGL((k_cg_update<double2, double2>), grid, dim3(kBlock), 0, s, L, *L.g);
+  else if (L.prec == kF32)
+    hipLaunchKernelGGL((k_cg_update<float2, float2>), grid, dim3(kBlock), 0, s, L, *L.g);
+  else  // 16-bit p, r; the iterate accumulates in FP32
+    hipLaunchKernelGGL((k_cg_update<f16x2, float2>), grid, dim3(kBlock), 0, s, L, *L.g);
   return hipGetLastError();
 }
 
@@ -342,8 +381,23 @@ hipError_t launch_cg_start(const UpdateLaunch& L, hipStream_t s) {
   dim3 grid(grid_for(L.g->V), L.ncols);
   if (L.prec == kF64)
     hipLaunchKernelGGL(k_cg_start<double2>, grid, dim3(kBlock), 0, s, L, *L.g);
-  else
+  else if (L.prec == kF32)
     hipLaunchKernelGGL(k_cg_start<float2>, grid, dim3(kBlock), 0, s, L, *L.g);
+  else
+    hipLaunchKernelGGL(k_cg_start<f16x2>, grid, dim3(kBlock), 0, s, L, *L.g);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_scale(ColState* st, int ncols, uint32_t mask, double c0, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_scale, dim3(1), dim3(64), 0, s, st, ncols, mask, c0);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_inner16(int ncols, size_t n, const void* x64, size_t x_cs, void* y16,
+                             size_t y_cs, uint32_t mask, const ColState* st, hipStream_t s) {
+  dim3 grid(grid_for(n), ncols);
+  hipLaunchKernelGGL(k_to_inner16, grid, dim3(kBlock), 0, s, n, (const double2*)x64, x_cs,
+                     (f16x2*)y16, y_cs, mask, st);
   return hipGetLastError();
 }
 
@@ -375,8 +429,11 @@ hipError_t launch_gauge_to_soa(const double2* aos, void* soa, int prec, int comp
   if (prec == kF64)
     hipLaunchKernelGGL(k_gauge_to_soa<double2>, grid, dim3(kBlock), 0, s, aos, (double2*)soa, *g,
                        compressed);
-  else
+  else if (prec == kF32)
     hipLaunchKernelGGL(k_gauge_to_soa<float2>, grid, dim3(kBlock), 0, s, aos, (float2*)soa, *g,
+                       compressed);
+  else
+    hipLaunchKernelGGL(k_gauge_to_soa<f16x2>, grid, dim3(kBlock), 0, s, aos, (f16x2*)soa, *g,
                        compressed);
   return hipGetLastError();
 }
@@ -464,10 +521,11 @@ hipError_t launch_xpby(int prec, int ncols, size_t n, const void* t1, const void
 }
 
 hipError_t launch_accum_f32_into_f64(int ncols, size_t n, void* x64, size_t x_cs, void* e32,
-                                     size_t e_cs, hipStream_t s, uint32_t mask) {
+                                     size_t e_cs, hipStream_t s, uint32_t mask,
+                                     const ColState* scale_st) {
   dim3 grid(grid_for(n), ncols);
   hipLaunchKernelGGL(k_accum, grid, dim3(kBlock), 0, s, n, (double2*)x64, x_cs, (float2*)e32,
-                     e_cs, mask);
+                     e_cs, mask, scale_st);
   return hipGetLastError();
 }
 

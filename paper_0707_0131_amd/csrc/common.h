@@ -71,6 +71,7 @@ struct ColState {
   int save_t1;      // Figure 3.1 steps 10.1 and 11.8); slot j & 1; 0 = none
   int tperiod;      // after saving at save_t1 both advance by this (m - 2 nev)
   int pad_;
+  double scale;     // 16-bit inner solves: the inner system is A e = scale r
 };
 
 enum { ColRun = 0, ColStopPending = 1, ColStopped = 2 };
@@ -125,6 +126,37 @@ template <> struct Storage<double2> {
     w.x = v.re;
     w.y = v.im;
     __builtin_nontemporal_store(w, reinterpret_cast<nt_d2*>(p) + i);
+  }
+};
+// 16-bit storage (IEEE half pairs), FP32 arithmetic
+struct __attribute__((aligned(4))) f16x2 {
+  _Float16 x, y;
+};
+template <> struct Storage<f16x2> {
+  using real = float;
+  __device__ static __forceinline__ cpx<float> ld(const f16x2* p, size_t i) {
+    const f16x2 v = p[i];
+    return {(float)v.x, (float)v.y};
+  }
+  __device__ static __forceinline__ void st(f16x2* p, size_t i, cpx<float> v) {
+    f16x2 w;
+    w.x = (_Float16)v.re;
+    w.y = (_Float16)v.im;
+    p[i] = w;
+  }
+  __device__ static __forceinline__ cpx<float> ld_nt(const f16x2* p, size_t i) {
+    const unsigned int u = __builtin_nontemporal_load(reinterpret_cast<const unsigned int*>(p) + i);
+    f16x2 v;
+    __builtin_memcpy(&v, &u, 4);
+    return {(float)v.x, (float)v.y};
+  }
+  __device__ static __forceinline__ void st_nt(f16x2* p, size_t i, cpx<float> v) {
+    f16x2 w;
+    w.x = (_Float16)v.re;
+    w.y = (_Float16)v.im;
+    unsigned int u;
+    __builtin_memcpy(&u, &w, 4);
+    __builtin_nontemporal_store(u, reinterpret_cast<unsigned int*>(p) + i);
   }
 };
 template <> struct Storage<float2> {

@@ -1,0 +1,18 @@
+// Stencil launches for FP64 storage (and the precision dispatcher): instantiates the kernels of
+// stencil_impl.h for this precision in a translation unit of its own.
+#include "stencil_impl.h"
+
+namespace eigcg {
+
+hipError_t launch_stencil_f64(const StencilLaunch& L, hipStream_t s) {
+  return launch_typed<double2, double2>(L, s);
+}
+
+hipError_t launch_stencil(const StencilLaunch& L, hipStream_t s) {
+  if (L.ncols <= 0 || L.ncols > kMaxCols) return hipErrorInvalidValue;
+  if (L.prec == kF64) return launch_stencil_f64(L, s);
+  if (L.prec == kF32) return launch_stencil_f32(L, s);
+  return launch_stencil_f16(L, s);
+}
+
+}  // namespace eigcg

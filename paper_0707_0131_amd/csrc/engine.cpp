@@ -83,7 +83,7 @@ void Ctx::dfree(void*& p) {
   p = nullptr;
 }
 
-static size_t elem_bytes(int prec) { return prec == kF64 ? 16 : 8; }
+static size_t elem_bytes(int prec) { return prec == kF64 ? 16 : (prec == kF32 ? 8 : 4); }
 
 // ---------------------------------------------------------------------------
 // context
@@ -144,7 +144,7 @@ static void autotune_stencil(Ctx& c, int prec) {
   pk.var = 1;
   pk.nc = 0;
   double best = 1e300;
-  const int ncmax = (w.K >= 4 && prec == kF32) ? 4 : (w.K >= 2 ? 2 : 1);
+  const int ncmax = (w.K >= 4 && prec != kF64) ? 4 : (w.K >= 2 ? 2 : 1);
   for (int v = 1; v <= kStencilVariants; ++v) {
     for (int nc = 1; nc <= ncmax; nc *= 2) {
       if (v < 3 && nc > 1) break;
@@ -153,7 +153,7 @@ static void autotune_stencil(Ctx& c, int prec) {
       L1.nc = nc;
       L1.op = kOpM;
       L1.epi = kEpiNorm;
-      L1.in = w.x; L1.in_cs = c.cs;
+      L1.in = w.b; L1.in_cs = c.cs;
       L1.out = w.tmp; L1.out_cs = c.cs;
       L1.ncols = w.K;
       L1.mask = w.K >= 32 ? 0xffffffffu : ((1u << w.K) - 1u);
@@ -243,11 +243,12 @@ void ctx_init(Ctx& c, const eigcg_params& p, const void* gauge_dev, hipStream_t 
   c.u64 = c.dalloc((size_t)4 * (c.comp64 ? 6 : 9) * g.vs * 16);
   c.check(launch_gauge_to_soa((const double2*)gauge_dev, c.u64, kF64, c.comp64, &g, s),
           "gauge to soa");
-  if (p.precision == EIGCG_MIXED_FP32) {
+  if (p.precision != EIGCG_FP64) {  // inner links: FP32, or 16-bit for the half mode
+    c.iprec = p.precision == EIGCG_MIXED_HALF ? kF16 : kF32;
     c.comp32 = (p.compress_links && h2[0] < 1e-6 && h2[1] < 1e-6) ? 1 : 0;
-    c.u32 = c.dalloc((size_t)4 * (c.comp32 ? 6 : 9) * g.vs * 8);
-    c.check(launch_gauge_to_soa((const double2*)gauge_dev, c.u32, kF32, c.comp32, &g, s),
-            "gauge to soa f32");
+    c.u32 = c.dalloc((size_t)4 * (c.comp32 ? 6 : 9) * g.vs * elem_bytes(c.iprec));
+    c.check(launch_gauge_to_soa((const double2*)gauge_dev, c.u32, c.iprec, c.comp32, &g, s),
+            "gauge to soa inner");
   }
   c.bank_prec = p.precision == EIGCG_FP64 ? kF64 : kF32;
   c.H.assign((size_t)p.max_bank * p.max_bank, cplx(0.0, 0.0));
@@ -256,7 +257,7 @@ void ctx_init(Ctx& c, const eigcg_params& p, const void* gauge_dev, hipStream_t 
   for (auto& e : c.events) c.check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
   c.check(hipStreamSynchronize(s), "sync");
   autotune_stencil(c, kF64);
-  if (p.precision == EIGCG_MIXED_FP32) autotune_stencil(c, kF32);
+  if (p.precision != EIGCG_FP64) autotune_stencil(c, c.iprec);
 }
 
 static void ws_release(Ctx& c, Workspace& w) {
@@ -353,7 +354,8 @@ static void ws_ensure(Ctx& c, Workspace& w, int prec, bool eig) {
     w.prec = prec;
     w.K = K;
     w.b = c.dalloc(vb * K);
-    w.x = c.dalloc(vb * K);
+    // the iterate of a 16-bit inner solve accumulates in FP32
+    w.x = c.dalloc((prec == kF16 ? c.cs * 8 : vb) * K);
     w.r = c.dalloc(vb * K);
     w.p = c.dalloc(vb * K);
     w.tmp = c.dalloc(vb * K);
@@ -891,6 +893,9 @@ struct Run {
 // schedule, which keeps results independent of the batch composition).
 enum Scheme { kSchemeF64 = 0, kSchemeReliable = 1, kSchemeRefine = 2 };
 constexpr double kRefineRel = 1e-4;
+// 16-bit storage keeps ~3 decimal digits: inner solves reduce their residual
+// by 1e-2 before the next FP64 outer step
+constexpr double kRefineRelHalf = 1e-2;
 
 static void cg_start(Run& R, uint32_t mask) {
   UpdateLaunch L{};
@@ -957,6 +962,7 @@ struct Driver {
       ColState& S = st[j];
       std::memset(&S, 0, sizeof(S));
       S.max_iter = cx.P.max_iter;
+      S.scale = 1.0;
       S.state = ColRun;
       const double t2 = tol * tol * bn2[j];
       S.res_stop2 = t2;
@@ -986,16 +992,12 @@ struct Driver {
         if ((m >> j) & 1u)
           cx.check(hipMemsetAsync(colp(w.x, kF32, j), 0, cx.cs * 8, cx.stream), "zero e");
       true_residual(cx, kF64, R.K, m, w64.x, w64.b, w64.r, w64.tmp);
-      if (deflate && cx.l > 0) {
+      if (deflate && cx.l > 0) deflate_mixed(m);
+      if (R.prec == kF32)
         cx.check(launch_copy(kF64, kF32, R.K, cx.cs, w64.r, cx.cs, w.r, cx.cs, cx.stream, m), "copy");
-        deflate_columns(cx, kF32, R.K, m, w.x, w.r);
-        cx.check(launch_accum_f32_into_f64(R.K, cx.cs, w64.x, cx.cs, w.x, cx.cs, cx.stream, m),
-                 "accum");
-        true_residual(cx, kF64, R.K, m, w64.x, w64.b, w64.r, w64.tmp);
-      }
-      cx.check(launch_copy(kF64, kF32, R.K, cx.cs, w64.r, cx.cs, w.r, cx.cs, cx.stream, m), "copy");
     }
     cx.check(launch_post_residual(cx.d_st, R.K, m, cx.stream), "post");
+    if (R.prec == kF16) to_inner16(m);
     cg_start(R, m);
     for (int j = 0; j < R.K; ++j) {
       if (!((m >> j) & 1u)) continue;
@@ -1008,6 +1010,42 @@ struct Driver {
       R.hist_read[j] = 0;
       R.stale_until[j] = R.seg_id;  // snapshots already in flight predate this start
     }
+  }
+
+  // FP32 residual scratch for the deflation of a mixed-precision column: the
+  // inner residual itself for FP32 iterations, the FP64 tmp field (viewed as
+  // FP32 columns) for 16-bit ones
+  void* r32_scratch() { return R.prec == kF32 ? R.w.r : w64.tmp; }
+
+  // init-CG deflation (eq. (2.1)) of the masked columns with the FP32 bank:
+  // x64 += U H^-1 U^H r64, then the FP64 true residual again
+  void deflate_mixed(uint32_t m) {
+    Ctx& cx = c();
+    void* r32 = r32_scratch();
+    cx.check(launch_copy(kF64, kF32, R.K, cx.cs, w64.r, cx.cs, r32, cx.cs, cx.stream, m), "copy");
+    deflate_columns(cx, kF32, R.K, m, R.w.x, r32);
+    cx.check(launch_accum_f32_into_f64(R.K, cx.cs, w64.x, cx.cs, R.w.x, cx.cs, cx.stream, m),
+             "accum");
+    true_residual(cx, kF64, R.K, m, w64.x, w64.b, w64.r, w64.tmp);
+  }
+
+  // 16-bit inner solve of the masked running columns: scale the FP64
+  // residual to an RMS entry of 2^-5 (well inside the half range while the
+  // inner solve reduces it by its tolerance) and store it in 16 bits
+  void to_inner16(uint32_t m) {
+    Ctx& cx = c();
+    const double c0 = std::sqrt((double)cx.cs) / 32.0;
+    cx.check(launch_set_scale(cx.d_st, R.K, m, c0, cx.stream), "scale");
+    cx.check(launch_to_inner16(R.K, cx.cs, w64.r, cx.cs, R.w.r, cx.cs, m, cx.d_st, cx.stream),
+             "to f16");
+  }
+
+  // inner correction into the FP64 iterate (undoing the 16-bit scale)
+  void accum_inner(uint32_t m) {
+    Ctx& cx = c();
+    cx.check(launch_accum_f32_into_f64(R.K, cx.cs, w64.x, cx.cs, R.w.x, cx.cs, cx.stream, m,
+                                       R.prec == kF16 ? cx.d_st : nullptr),
+             "accum");
   }
 
   // lockstep FP64 reliable update of every column of the run
@@ -1042,7 +1080,7 @@ struct Driver {
     Ctx& cx = c();
     const uint32_t m1 = 1u << col;
     Workspace& w = R.w;
-    cx.check(launch_accum_f32_into_f64(R.K, cx.cs, w64.x, cx.cs, w.x, cx.cs, cx.stream, m1), "accum");
+    accum_inner(m1);
     true_residual(cx, kF64, R.K, m1, w64.x, w64.b, w64.r, w64.tmp);
     cx.check(launch_post_residual(cx.d_st, R.K, m1, cx.stream), "post");
     R.outer[col]++;
@@ -1053,13 +1091,13 @@ struct Driver {
     const ColState S = cx.h_st[2 * kMaxCols + kMaxCols - 1];
     if (S.state == ColStopped && S.reason == ReasonConverged) return true;
     if (cx.l > 0) {  // deflation per outer step
-      cx.check(launch_copy(kF64, kF32, R.K, cx.cs, w64.r, cx.cs, w.r, cx.cs, cx.stream, m1), "copy");
-      deflate_columns(cx, kF32, R.K, m1, w.x, w.r);
-      cx.check(launch_accum_f32_into_f64(R.K, cx.cs, w64.x, cx.cs, w.x, cx.cs, cx.stream, m1), "accum");
-      true_residual(cx, kF64, R.K, m1, w64.x, w64.b, w64.r, w64.tmp);
+      deflate_mixed(m1);
       cx.check(launch_post_residual(cx.d_st, R.K, m1, cx.stream), "post");
     }
-    cx.check(launch_copy(kF64, kF32, R.K, cx.cs, w64.r, cx.cs, w.r, cx.cs, cx.stream, m1), "copy");
+    if (R.prec == kF32)
+      cx.check(launch_copy(kF64, kF32, R.K, cx.cs, w64.r, cx.cs, w.r, cx.cs, cx.stream, m1), "copy");
+    else
+      to_inner16(m1);
     cg_start(R, m1);
     R.stale_until[col] = R.seg_id;
     return false;
@@ -1150,8 +1188,7 @@ struct Driver {
   // final FP64 true residuals of the masked columns (x already final in w64)
   std::vector<double> final_residuals(uint32_t m, const std::vector<double>& bn2) {
     Ctx& cx = c();
-    if (scheme != kSchemeF64)
-      cx.check(launch_accum_f32_into_f64(R.K, cx.cs, w64.x, cx.cs, R.w.x, cx.cs, cx.stream, m), "accum");
+    if (scheme != kSchemeF64) accum_inner(m);
     cx.check(launch_set_state(cx.d_st, R.K, m, ColStopped, ReasonConverged, 0, cx.stream), "st");
     true_residual(cx, kF64, R.K, m, w64.x, w64.b, w64.r, w64.tmp);
     cx.check(hipMemcpy(cx.h_st, cx.d_st, sizeof(ColState) * R.K, hipMemcpyDeviceToHost), "states");
@@ -1180,11 +1217,14 @@ std::vector<double> col_norms(Ctx& c, int prec, int k, const void* base) {
 
 int scheme_for(const Ctx& c, int mode) {
   if (c.P.precision == EIGCG_FP64) return kSchemeF64;
+  if (c.P.precision == EIGCG_MIXED_HALF) return kSchemeRefine;  // rescaled 16-bit inner solves
   return mode == EIGCG_MODE_INITCG ? kSchemeRefine : kSchemeReliable;
 }
 
 double restart_tol_for(const Ctx& c, int mode, int scheme) {
-  if (scheme == kSchemeRefine) return c.P.restart_tol > 0 ? c.P.restart_tol : kRefineRel;
+  if (scheme == kSchemeRefine)
+    return c.P.restart_tol > 0 ? c.P.restart_tol
+                               : (c.P.precision == EIGCG_MIXED_HALF ? kRefineRelHalf : kRefineRel);
   if (mode != EIGCG_MODE_INITCG || c.P.restart_tol < 0) return 0.0;
   if (c.P.restart_tol > 0) return c.P.restart_tol;
   // Section 5.3: within an order of magnitude of machine precision scaled by
@@ -1362,12 +1402,15 @@ int bank_append_from(Ctx& c, const void* src, int nsrc) {
 
 int solve(Ctx& c, int nrhs, const void* b_aos, void* x_aos, double tol, int mode,
           eigcg_stats* stats) {
-  const bool mixed = c.P.precision == EIGCG_MIXED_FP32;
+  const bool mixed = c.P.precision != EIGCG_FP64;
   const bool eig = mode == EIGCG_MODE_EIGCG;
-  const int prec = mixed ? kF32 : kF64;
+  if (eig && c.P.precision == EIGCG_MIXED_HALF)
+    throw ApiError{EIGCG_EINVAL, "eigCG mode needs FP64 or FP32 iterations (16-bit inner solves "
+                                 "restart at every refinement step)"};
+  const int prec = mixed ? c.iprec : kF64;
   const int scheme = scheme_for(c, mode);
   ws_ensure(c, c.ws64, kF64, eig && !mixed);
-  if (mixed) ws_ensure(c, c.ws32, kF32, eig);
+  if (mixed) ws_ensure(c, c.ws32, c.iprec, eig);
   Workspace& w = mixed ? c.ws32 : c.ws64;
   Workspace& w64 = c.ws64;
   int worst = EIGCG_OK;
@@ -1472,10 +1515,10 @@ struct Session {
 };
 
 Session* session_open(Ctx& c) {
-  const bool mixed = c.P.precision == EIGCG_MIXED_FP32;
-  const int prec = mixed ? kF32 : kF64;
+  const bool mixed = c.P.precision != EIGCG_FP64;
+  const int prec = mixed ? c.iprec : kF64;
   ws_ensure(c, c.ws64, kF64, false);
-  if (mixed) ws_ensure(c, c.ws32, kF32, false);
+  if (mixed) ws_ensure(c, c.ws32, c.iprec, false);
   Session* s = new Session(c, mixed ? c.ws32 : c.ws64, c.ws64, prec,
                            scheme_for(c, EIGCG_MODE_INITCG));
   std::vector<ColState> idle(s->K);
@@ -1587,9 +1630,9 @@ void session_close(Session* s) {
 }
 
 void deflate_init(Ctx& c, int nrhs, const void* b_aos, void* x_aos) {
-  const bool mixed = c.P.precision == EIGCG_MIXED_FP32;
+  const bool mixed = c.P.precision != EIGCG_FP64;
   ws_ensure(c, c.ws64, kF64, false);
-  if (mixed) ws_ensure(c, c.ws32, kF32, false);
+  if (mixed) ws_ensure(c, c.ws32, c.iprec, false);
   Workspace& w64 = c.ws64;
   for (int c0 = 0; c0 < nrhs; c0 += w64.K) {
     const int K = std::min(w64.K, nrhs - c0);
@@ -1608,10 +1651,11 @@ void deflate_init(Ctx& c, int nrhs, const void* b_aos, void* x_aos) {
       if (!mixed) {
         deflate_columns(c, kF64, K, mask, w64.x, w64.r);
       } else {
-        Workspace& w = c.ws32;
+        Workspace& w = c.ws32;  // FP32 iterate (also for 16-bit inner solves)
+        void* r32 = c.iprec == kF32 ? w.r : w64.tmp;  // FP32 residual scratch
         c.check(hipMemsetAsync(w.x, 0, c.cs * 8 * K, c.stream), "zero");
-        c.check(launch_copy(kF64, kF32, K, c.cs, w64.r, c.cs, w.r, c.cs, c.stream), "copy");
-        deflate_columns(c, kF32, K, mask, w.x, w.r);
+        c.check(launch_copy(kF64, kF32, K, c.cs, w64.r, c.cs, r32, c.cs, c.stream), "copy");
+        deflate_columns(c, kF32, K, mask, w.x, r32);
         c.check(launch_accum_f32_into_f64(K, c.cs, w64.x, c.cs, w.x, c.cs, c.stream), "accum");
       }
     }
@@ -1678,8 +1722,8 @@ void bank_vectors(Ctx& c, int first, int count, void* out_aos) {
 // FP64 CG iteration (four kernels); 3: FP32 stencil M (store; mixed-precision
 // contexts only).
 double bench_kernels(Ctx& c, int what, int reps) {
-  const int prec = what == 3 ? kF32 : kF64;
-  if (prec == kF32 && !c.u32) throw ApiError{EIGCG_EINVAL, "context has no FP32 links"};
+  const int prec = what == 3 ? c.iprec : kF64;
+  if (what == 3 && !c.u32) throw ApiError{EIGCG_EINVAL, "context has no inner-precision links"};
   Workspace& w = prec == kF64 ? c.ws64 : c.ws32;
   ws_ensure(c, w, prec, false);
   // non-zero, finite work vectors (byte pattern 0x3F) and a state that never
@@ -1689,8 +1733,10 @@ double bench_kernels(Ctx& c, int what, int reps) {
   std::vector<ColState> st(1);
   std::memset(st.data(), 0, sizeof(ColState));
   st[0].state = ColRun;
-  st[0].rho = col_norms(c, prec, 1, w.r)[0];  // a consistent CG state: r = p
-  c.check(launch_copy(prec, prec, 1, c.cs, w.r, c.cs, w.p, c.cs, c.stream), "copy");
+  if (what == 2) {
+    st[0].rho = col_norms(c, prec, 1, w.r)[0];  // a consistent CG state: r = p
+    c.check(launch_copy(prec, prec, 1, c.cs, w.r, c.cs, w.p, c.cs, c.stream), "copy");
+  }
   st[0].stop2 = -1.0;
   st[0].restart2 = -1.0;
   st[0].res_stop2 = -1.0;

@@ -52,7 +52,8 @@ struct Ctx {
   hipStream_t gstream = nullptr;  // capture-only stream for HIP graphs
   int device = 0;
   int comp64 = 0, comp32 = 0;
-  int var64 = 1, var32 = 1;        // stencil kernel variants in use
+  int iprec = kF32;                // inner precision of mixed contexts (kF32 or kF16)
+  int var64 = 1, var32 = 1;        // stencil kernel variants in use (var32: inner precision)
   int nc64 = 0, nc32 = 0;          // their columns per workgroup (0 = widest)
   double tune_ms[2 * kStencilVariants] = {};  // FP64 then FP32, per variant
   void* u64 = nullptr;

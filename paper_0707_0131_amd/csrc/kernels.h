@@ -10,7 +10,7 @@
 
 namespace eigcg {
 
-enum Prec { kF64 = 0, kF32 = 1 };
+enum Prec { kF64 = 0, kF32 = 1, kF16 = 2 };  // kF16: IEEE half storage, FP32 arithmetic
 enum StencilOp { kOpM = 0, kOpMdag = 1 };
 // epilogues of the stencil launch
 enum StencilEpi {
@@ -62,6 +62,10 @@ struct StencilLaunch {
 };
 
 hipError_t launch_stencil(const StencilLaunch& L, hipStream_t s);
+// per-precision entry points (one translation unit each)
+hipError_t launch_stencil_f64(const StencilLaunch& L, hipStream_t s);
+hipError_t launch_stencil_f32(const StencilLaunch& L, hipStream_t s);
+hipError_t launch_stencil_f16(const StencilLaunch& L, hipStream_t s);
 
 // CG step 3: x += alpha p; (running) p = r + beta p; optional window append
 // V_ring[(iter + 1) % ring] = r / sqrt(rho).
@@ -122,9 +126,17 @@ hipError_t launch_scale(int prec, int ncols, size_t n, const double* scale_dev, 
 hipError_t launch_xpby(int prec, int ncols, size_t n, const void* t1, const void* t0,
                        size_t t_cs, const double* beta_dev, void* w, size_t w_cs,
                        hipStream_t s);
-// mixed precision accumulation: x64 += (double) e32 ; e32 = 0
+// mixed precision accumulation: x64 += (double) e32 / scale ; e32 = 0, where
+// scale is the column's inner-solve scale from scale_st (1 when null)
 hipError_t launch_accum_f32_into_f64(int ncols, size_t n, void* x64, size_t x_cs, void* e32,
-                                     size_t e_cs, hipStream_t s, uint32_t mask = 0xffffffffu);
+                                     size_t e_cs, hipStream_t s, uint32_t mask = 0xffffffffu,
+                                     const ColState* scale_st = nullptr);
+// 16-bit inner solves: per running column, scale = c0 / sqrt(rho); rho and
+// restart2 are rescaled to the inner solve's units
+hipError_t launch_set_scale(ColState* st, int ncols, uint32_t mask, double c0, hipStream_t s);
+// y16 = scale * x64 for running masked columns (16-bit storage)
+hipError_t launch_to_inner16(int ncols, size_t n, const void* x64, size_t x_cs, void* y16,
+                             size_t y_cs, uint32_t mask, const ColState* st, hipStream_t s);
 
 // Tall-skinny products on MFMA (complex):
 //   Out(n x N) = beta*Out + In(n x K) * S(K x N)

@@ -195,9 +195,12 @@ int eigcg_server_add(eigcg_server* srv, eigcg_ctx* ctx, int32_t* field_id) {
     return EIGCG_EHIP;
   (void)hipStreamSynchronize(ctx->c.stream);
   ctx->c.stream = f.own_stream;
-  // per-request working set: FP64 b, x, r, tmp (+ FP32 e, r, p, tmp when mixed)
+  // per-request working set: FP64 b, x, r, tmp (+ FP32 e, r, p, tmp when mixed;
+  // FP32 e and 16-bit r, p, tmp in the half mode)
   const size_t v64 = ctx->c.cs * 16, v32 = ctx->c.cs * 8;
-  f.per_request = 4 * v64 + (ctx->c.P.precision == EIGCG_MIXED_FP32 ? 4 * v32 : v64);
+  const size_t v16 = ctx->c.cs * 4;
+  f.per_request = 4 * v64 + (ctx->c.P.precision == EIGCG_MIXED_FP32 ? 4 * v32
+                             : ctx->c.P.precision == EIGCG_MIXED_HALF ? v32 + 3 * v16 : v64);
   if (field_id) *field_id = (int32_t)srv->fields.size();
   srv->fields.push_back(f);
   return EIGCG_OK;

@@ -1,4 +1,7 @@
-// Wilson-Dirac stencil kernels with fused CG epilogues (gfx950).
+#pragma once
+// Wilson-Dirac stencil kernels with fused CG epilogues (gfx950).  Included
+// by one translation unit per storage precision (dslash_f64/f32/f16.hip), each
+// instantiating launch_typed for its type, so the kernels build in parallel.
 //
 // One thread per lattice site (grid-stride over sites), one right-hand side
 // per blockIdx.y.  Loads are SoA planes, so each of the 12 spinor components
@@ -10,6 +13,7 @@
 // get alpha, and a one-workgroup finalize kernel, ordered by the stream,
 // updates the CG scalars of every column.
 #include <algorithm>
+#include <type_traits>
 
 #include <mutex>
 
@@ -433,7 +437,14 @@ hipError_t launch_typed(const StencilLaunch& L, hipStream_t s) {
   a.partial_in = part_a;
   a.r = L.r; a.r_cs = L.r_cs; a.b = L.b; a.b_cs = L.b_cs;
   a.tbuf = L.tbuf; a.t_cs = L.t_cs; a.hist = L.hist; a.hist_stride = L.hist_stride;
+  // 16-bit storage instantiates only the streaming two-tile kernels with
+  // two-row links: other variants run as 5, uncompressed links are refused
+  constexpr bool kHalf = std::is_same<VS, f16x2>::value;
   int variant = L.variant <= 0 ? 1 : L.variant;
+  if (kHalf) {
+    if (!L.compressed) return hipErrorInvalidValue;
+    if (variant < 5) variant = 5;
+  }
   const uint32_t plane = (uint32_t)(L.g->L[0] * L.g->L[1]);
   if (variant >= 8 && (plane % 64u != 0 || L.g->L[3] % 8 != 0))
     variant = variant == 8 ? 5 : 6;  // the slab sweep needs whole tiles per plane, 8 slabs
@@ -496,10 +507,30 @@ hipError_t launch_typed(const StencilLaunch& L, hipStream_t s) {
     case kEpiCGR: { EIGCG_K(COMP, DAG, kEpiCGR) } break;      \
     default: { EIGCG_K(COMP, DAG, kEpiRes) } break;           \
   }
-  if (L.compressed) {
-    if (L.op == kOpMdag) { EIGCG_EPI(true, true) } else { EIGCG_EPI(true, false) }
+  if constexpr (kHalf) {
+#define EIGCG_KH(COMP, DAG, EPI)                                                     \
+  if (variant >= 8) {                                                                \
+    EIGCG_PAIR(COMP, DAG, EPI, true, 1)                                              \
+  } else {                                                                           \
+    EIGCG_PAIR(COMP, DAG, EPI, true, 0)                                              \
+  }
+    switch ((L.op == kOpMdag ? 4 : 0) + L.epi) {
+      case 0: { EIGCG_KH(true, false, kEpiStore) } break;
+      case 1: { EIGCG_KH(true, false, kEpiNorm) } break;
+      case 2: { EIGCG_KH(true, false, kEpiCGR) } break;
+      case 3: { EIGCG_KH(true, false, kEpiRes) } break;
+      case 4: { EIGCG_KH(true, true, kEpiStore) } break;
+      case 5: { EIGCG_KH(true, true, kEpiNorm) } break;
+      case 6: { EIGCG_KH(true, true, kEpiCGR) } break;
+      default: { EIGCG_KH(true, true, kEpiRes) } break;
+    }
+#undef EIGCG_KH
   } else {
-    if (L.op == kOpMdag) { EIGCG_EPI(false, true) } else { EIGCG_EPI(false, false) }
+    if (L.compressed) {
+      if (L.op == kOpMdag) { EIGCG_EPI(true, true) } else { EIGCG_EPI(true, false) }
+    } else {
+      if (L.op == kOpMdag) { EIGCG_EPI(false, true) } else { EIGCG_EPI(false, false) }
+    }
   }
 #undef EIGCG_EPI
 #undef EIGCG_K
@@ -517,11 +548,5 @@ hipError_t launch_typed(const StencilLaunch& L, hipStream_t s) {
 }
 
 }  // namespace
-
-hipError_t launch_stencil(const StencilLaunch& L, hipStream_t s) {
-  if (L.ncols <= 0 || L.ncols > kMaxCols) return hipErrorInvalidValue;
-  if (L.prec == kF64) return launch_typed<double2, double2>(L, s);
-  return launch_typed<float2, float2>(L, s);
-}
 
 }  // namespace eigcg

@@ -114,12 +114,14 @@ def test_fullsize_cg_and_eigcg_bank(B, field):
         B.eigcg_destroy(ctx)
 
 
-def test_fullsize_batched_mixed_precision(B, field):
+@pytest.mark.parametrize("precision", [1, 2])
+def test_fullsize_batched_mixed_precision(B, field, precision):
     """The batching form at full size: 4 right-hand sides per launch, FP32
-    inner iteration with FP64 reliable updates; every column's FP64 true
-    residual (oracle's A) is below 1e-10."""
+    inner iteration with FP64 reliable updates (precision 1) or 16-bit
+    storage with rescaled inner solves and FP64 refinement (precision 2);
+    every column's FP64 true residual (oracle's A) is below 1e-10."""
     U, op = field
-    ctx, _ = make_ctx(U, MASS, precision=B.EIGCG_MIXED_FP32, max_batch=4, reliable_every=50,
+    ctx, _ = make_ctx(U, MASS, precision=precision, max_batch=4, reliable_every=50,
                       max_iter=20000, max_bank=0)
     try:
         bs = np.stack([gaussian_rhs(DIMS, 1100 + i) for i in range(4)])

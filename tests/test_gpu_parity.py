@@ -392,3 +392,48 @@ def test_graph_replay_matches_eager(B, cfg0, precision):
     finally:
         B.eigcg_destroy(ctx_e)
         B.eigcg_destroy(ctx_g)
+
+
+def test_half_precision_cg_and_initcg(B, cfg0):
+    """16-bit links and vectors with FP32 arithmetic (FP32 iterate), each inner
+    solve rescaled, FP64 refinement: CG and init-CG reach the FP64 tolerance;
+    error against the FP64 oracle solution stated: <= 1e-6 relative.  A batch
+    of three columns is bitwise the three single solves (per-column
+    refinement schedule), and eigCG mode is refused."""
+    from oracle.dense import dense_A
+    U, op, b = cfg0
+    xo, _ = cg(op.A, b.reshape(-1), tol=1e-10)
+    ctx, _ = make_ctx(U, -0.2, precision=B.EIGCG_MIXED_HALF, max_iter=20000, max_bank=12)
+    ctx3, _ = make_ctx(U, -0.2, precision=B.EIGCG_MIXED_HALF, max_iter=20000, max_batch=3,
+                       stencil_variant=B.eigcg_layout_info(ctx)["variant32"])
+    try:
+        x = dev(np.zeros((1,) + b.shape, dtype=np.complex128))
+        rc, st = B.eigcg_solve(ctx, dev(b[None]), x, 1e-10, B.EIGCG_MODE_CG)
+        assert rc == B.EIGCG_OK, B.eigcg_last_error(ctx)
+        assert st[0]["true_rel_res"] <= 1e-10 and st[0]["outer_steps"] >= 2
+        assert rel(host(x)[0].reshape(-1), xo) <= 1e-6
+        bs = gaussian_rhs_block((4, 4, 4, 4), [2400, 2401, 2402])
+        x3 = dev(np.zeros_like(bs))
+        rc, st3 = B.eigcg_solve(ctx3, dev(bs), x3, 1e-10, B.EIGCG_MODE_CG)
+        assert rc == B.EIGCG_OK
+        for i in range(3):
+            x1 = dev(np.zeros_like(bs[i:i + 1]))
+            rc, st1 = B.eigcg_solve(ctx, dev(bs[i:i + 1]), x1, 1e-10, B.EIGCG_MODE_CG)
+            assert st1[0]["iters"] == st3[i]["iters"]
+            assert np.array_equal(host(x1)[0], host(x3)[i])
+        # init-CG with a bank of exact low eigenvectors
+        A, _ = dense_A(op)
+        lam, X = np.linalg.eigh(A)
+        B.eigcg_bank_load(ctx, dev(X[:, :12].T.reshape((12, 4, 4, 4, 4, 4, 3)).copy()))
+        Xb = X[:, :12]
+        xi, _ = init_cg(op.A, Xb, Xb.conj().T @ A @ Xb, b.reshape(-1), tol=1e-10)
+        x = dev(np.zeros((1,) + b.shape, dtype=np.complex128))
+        rc, st2 = B.eigcg_solve(ctx, dev(b[None]), x, 1e-10, B.EIGCG_MODE_INITCG)
+        assert rc == B.EIGCG_OK and st2[0]["true_rel_res"] <= 1e-10
+        assert rel(host(x)[0].reshape(-1), xi) <= 1e-6
+        assert st2[0]["iters"] < st[0]["iters"]
+        with pytest.raises(B.EigcgError):
+            B.eigcg_solve(ctx, dev(b[None]), x, 1e-10, B.EIGCG_MODE_EIGCG)
+    finally:
+        B.eigcg_destroy(ctx)
+        B.eigcg_destroy(ctx3)

@@ -66,7 +66,7 @@ def _serve(B, ctxs, jobs, budget=0, one_by_one=False):
     return out
 
 
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 2])
 def test_alone_equals_mixed(B, precision):
     import torch
     ctxs, keep, ops, banks = _setup(B, precision, max_batch=3)
