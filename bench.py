@@ -170,9 +170,9 @@ def batching_leg(B, torch, g, bt, nrhs=12):
     launch: FP32 inner iteration with FP64 reliable updates every 50
     iterations (and FP64 for k = 1 and 4, for comparison), tol 1e-10."""
     out = []
-    for prec in (1, 0):
+    for prec in (2, 1, 0):
         for k in BATCH_SIZES:
-            if prec == 0 and k > 4:
+            if (prec == 0 and k > 4) or (prec == 2 and k == 8):
                 continue
             p = B.eigcg_default_params(dims=LATTICE, mass=BATCH_MASS, precision=prec, max_batch=k,
                                        reliable_every=50, max_iter=40000, check_every=32,
@@ -188,11 +188,14 @@ def batching_leg(B, torch, g, bt, nrhs=12):
                 info = B.eigcg_layout_info(ctx)
             finally:
                 B.eigcg_destroy(ctx)
-            r = {"precision": "fp32+fp64-reliable" if prec else "fp64", "k": k,
+            r = {"precision": ("fp16-storage+fp64-refinement", "fp32+fp64-reliable")[prec % 2]
+                 if prec else "fp64", "k": k,
                  "rhs_per_s": nrhs / dt, "mean_iters": sum(s["iters"] for s in st) / nrhs,
                  "max_true_rel_res": max(s["true_rel_res"] for s in st),
                  "failed": sum(1 for s in st if s["status"] != 0 or s["true_rel_res"] > TOL),
                  "stencil_variant": info["variant32" if prec else "variant64"]}
+            if prec == 2:
+                r["mean_outer_steps"] = sum(q["outer_steps"] for q in st) / nrhs
             log(f"batching {r['precision']} k={k}: {r['rhs_per_s']:.1f} RHS/s, "
                 f"mean iters {r['mean_iters']:.0f}, max res {r['max_true_rel_res']:.1e}")
             out.append(r)
@@ -358,6 +361,78 @@ def serving_leg(B, torch, n_bank_rhs, n_requests, seed=5):
     return out
 
 
+LARGE_LATTICE, LARGE_SEED, LARGE_MASS = (32, 32, 32, 64), 4, -0.58
+
+
+def large_leg(B, torch, n_bank_rhs=6, n_rhs=12):
+    """The largest configuration: 32^3 x 64, a bank grown by FP64 Incremental
+    eigCG on n_bank_rhs right-hand sides and held in FP32, then n_rhs deflated
+    solves to 1e-10 in one batch of 12 columns with 16-bit (half) inner
+    storage, and with FP32 inner iterations, against plain FP64 CG."""
+    from synthetic import gauge_field, gaussian_rhs
+    dims = LARGE_LATTICE
+    t0 = time.perf_counter()
+    U = gauge_field(dims, EPS, LARGE_SEED)
+    g = torch.from_numpy(U).to("cuda:0")
+    del U
+    log(f"large lattice {dims}: links in {time.perf_counter() - t0:.0f}s")
+    shape = (dims[3], dims[2], dims[1], dims[0], 4, 3)
+    p64 = B.eigcg_default_params(dims=dims, mass=LARGE_MASS, nev=NEV, m=M, max_bank=NBANK,
+                                 max_iter=20000, check_every=16)
+    ctx64 = B.eigcg_create(p64, g)
+    t0 = time.perf_counter()
+    try:
+        for i in range(n_bank_rhs):
+            b = torch.from_numpy(gaussian_rhs(dims, 7500 + i)).to("cuda:0")[None]
+            rc, st = B.eigcg_solve(ctx64, b, torch.zeros_like(b), TOL, B.EIGCG_MODE_EIGCG)
+            log(f"large lattice bank: RHS {i} {st[0]['iters']} iterations")
+        l = len(B.eigcg_bank_info(ctx64)[0])
+        vecs = torch.empty((l,) + shape, dtype=torch.complex128, device="cuda:0")
+        B.eigcg_bank_vectors(ctx64, 0, l, vecs)
+        # plain FP64 single-RHS CG reference on the first solve's right-hand side
+        bt = torch.stack([torch.from_numpy(gaussian_rhs(dims, 9500 + i)) for i in range(n_rhs)]).to("cuda:0")
+        x = torch.zeros_like(bt[:1])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rc, stp = B.eigcg_solve(ctx64, bt[:1], x, TOL, B.EIGCG_MODE_CG)
+        torch.cuda.synchronize()
+        plain_s = time.perf_counter() - t1
+    finally:
+        B.eigcg_destroy(ctx64)
+    log(f"large lattice: bank {l} vectors in {time.perf_counter() - t0:.0f}s; plain FP64 CG "
+        f"{plain_s:.2f} s ({stp[0]['iters']} iterations)")
+    out = {"lattice": list(dims), "mass": LARGE_MASS, "bank": l, "rhs": n_rhs,
+           "plain_fp64_cg_s_per_rhs": plain_s, "plain_fp64_cg_iters": stp[0]["iters"], "runs": []}
+    for prec, name in ((2, "half storage, FP32 arithmetic"), (1, "FP32")):
+        p = B.eigcg_default_params(dims=dims, mass=LARGE_MASS, precision=prec, max_batch=12,
+                                   max_bank=NBANK, reliable_every=50, max_iter=20000,
+                                   check_every=16, use_graphs=1)
+        ctx = B.eigcg_create(p, g)
+        try:
+            B.eigcg_bank_load(ctx, vecs)
+            x = torch.zeros_like(bt)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            rc, st = B.eigcg_solve(ctx, bt, x, TOL, B.EIGCG_MODE_INITCG)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t1
+        finally:
+            B.eigcg_destroy(ctx)
+        r = {"inner": name, "rhs_per_s": n_rhs / dt, "wall_s": dt,
+             "speedup_vs_plain_fp64_cg": (n_rhs / dt) * plain_s,
+             "mean_iters": sum(q["iters"] for q in st) / n_rhs,
+             "mean_outer_steps": sum(q["outer_steps"] for q in st) / n_rhs,
+             "max_true_rel_res": max(q["true_rel_res"] for q in st),
+             "failed": sum(1 for q in st if q["status"] != 0 or q["true_rel_res"] > TOL)}
+        log(f"large lattice, {name}, 12 columns, deflated: {r['rhs_per_s']:.2f} RHS/s "
+            f"({r['speedup_vs_plain_fp64_cg']:.1f}x plain FP64 CG), mean iters {r['mean_iters']:.0f}, "
+            f"outer {r['mean_outer_steps']:.1f}, max res {r['max_true_rel_res']:.1e}")
+        out["runs"].append(r)
+    del vecs, bt, g
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(total_rhs, total_iters, budget_s=20.0):
     """Oracle CG on the bench lattice for a bounded number of iterations."""
     import numpy as np
@@ -397,6 +472,7 @@ def main():
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-batching", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-large", action="store_true", help="skip the 32^3x64 half-precision leg")
     ap.add_argument("--serve-bank-rhs", type=int, default=N_EIG)
     ap.add_argument("--serve-requests", type=int, default=120)
     ap.add_argument("--stencil-variant", type=int, default=0,
@@ -494,6 +570,10 @@ def main():
         torch.cuda.empty_cache()
         serving = serving_leg(B, torch, args.serve_bank_rhs, args.serve_requests)
 
+    large = None
+    if not args.no_large:
+        large = large_leg(B, torch)
+
     total_iters = sum(sum(s["phase1_iters"]) + sum(s["phase2_iters"]) for s in steps)
     cpu = None
     if not args.no_cpu:
@@ -559,6 +639,7 @@ def main():
                           "algorithmic_bytes_per_launch": pass1_bytes},
         "batching": batching,
         "serving": serving,
+        "large_lattice": large,
         "stencil_bench_lattice": roof_small,
         "stencil_hbm_lattice": roof_hbm,
         "cpu_baseline": cpu,
