@@ -205,6 +205,8 @@ int eigcg_time_kernel(eigcg_ctx* ctx, int32_t what, int32_t reps, double* ms);
  * stream; reset != 0 clears the accumulated samples. */
 int eigcg_kernel_samples(eigcg_ctx* ctx, int32_t reset, double* out);
 
+/* Text of the context's last error; with ctx == NULL, of this thread's last
+ * failed eigcg_create. */
 const char* eigcg_last_error(const eigcg_ctx* ctx);
 
 /* ---- serving: continuous batching over several contexts --------------------

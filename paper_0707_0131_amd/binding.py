@@ -110,6 +110,13 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(
             f"{LIB_PATH} is missing: build it with `python -m paper_0707_0131_amd.build`")
+    # the device buffers come from PyTorch: load its HIP runtime first so the
+    # library binds to the same runtime instance (a second runtime loaded
+    # earlier would not see the device PyTorch opened)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)
@@ -165,7 +172,7 @@ def eigcg_create(params: Params, gauge, stream=None):
     ctx = ctypes.c_void_p()
     rc = LIB.eigcg_create(ctypes.byref(params), _ptr(gauge), _stream(stream), ctypes.byref(ctx))
     if rc != EIGCG_OK:
-        raise EigcgError(rc, "eigcg_create failed")
+        raise EigcgError(rc, "eigcg_create failed: " + eigcg_last_error(None))
     return ctx
 
 

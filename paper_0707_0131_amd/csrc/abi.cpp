@@ -25,6 +25,12 @@ int fail(eigcg_ctx* ctx, int code, const std::string& msg) {
   return code;
 }
 
+// message of this thread's last failed eigcg_create (no context to hold it)
+std::string& create_error() {
+  static thread_local std::string e = "no context";
+  return e;
+}
+
 template <typename F> int guarded(eigcg_ctx* ctx, F&& f) {
   if (ctx && ctx->c.sticky) return fail(ctx, EIGCG_EHIP, "context unusable after a HIP error");
   try {
@@ -98,8 +104,14 @@ int eigcg_create(const eigcg_params* p, const void* gauge_dev, void* hip_stream,
   *out = nullptr;
   std::string why;
   int v = validate(p, why);
-  if (v != EIGCG_OK) return v;
-  if (!gauge_dev) return EIGCG_EINVAL;
+  if (v != EIGCG_OK) {
+    create_error() = why;
+    return v;
+  }
+  if (!gauge_dev) {
+    create_error() = "null gauge field";
+    return EIGCG_EINVAL;
+  }
   eigcg_ctx* ctx = new (std::nothrow) eigcg_ctx();
   if (!ctx) return EIGCG_ENOMEM;
   int rc = guarded(ctx, [&] {
@@ -107,6 +119,7 @@ int eigcg_create(const eigcg_params* p, const void* gauge_dev, void* hip_stream,
     return EIGCG_OK;
   });
   if (rc != EIGCG_OK) {
+    create_error() = ctx->c.err;
     eigcg::ctx_release(ctx->c);
     delete ctx;
     return rc;
@@ -253,7 +266,7 @@ int eigcg_kernel_samples(eigcg_ctx* ctx, int32_t reset, double* out) {
 }
 
 const char* eigcg_last_error(const eigcg_ctx* ctx) {
-  if (!ctx) return "null context";
+  if (!ctx) return create_error().c_str();
   return ctx->c.err.c_str();
 }
 

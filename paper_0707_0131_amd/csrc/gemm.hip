@@ -83,22 +83,21 @@ __global__ __launch_bounds__(256) void k_gemm_tall(size_t n, int K, int N, const
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[m][t] = typename M::acc_t{};
 
-  for (int k0 = 0; k0 < K; k0 += 2) {
+  // A fragments of input columns k0 + kcol: one real part per lane (lanes of
+  // the two parts of a complex entry read adjacent words)
+  const R* const* sinr = reinterpret_cast<const R* const*>(sin);
+  auto load_a = [&](int k0, R* af) {
     const int kc = k0 + kcol;
-    const bool kvalid = kc < K;
-    // A fragments (4 row subtiles)
-    R afrag[4];
-    const VS* src = kvalid ? sin[kc] : nullptr;
+    const R* src = kc < K ? sinr[kc] : nullptr;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       const size_t row = row0 + m * 16 + li;
-      R v = R(0);
-      if (kvalid && row < n) {
-        cpx<R> z = Storage<VS>::ld(src, row);
-        v = kpart ? z.im : z.re;
-      }
-      afrag[m] = v;
+      af[m] = (src && row < n) ? src[2 * row + kpart] : R(0);
     }
+  };
+  auto step = [&](int k0, const R* af) {
+    const int kc = k0 + kcol;
+    const bool kvalid = kc < K;
     // B fragments: real column jj = 16 t + li -> output column j = 8 t + li/2, part li&1
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
@@ -111,7 +110,25 @@ __global__ __launch_bounds__(256) void k_gemm_tall(size_t n, int K, int N, const
         else bv = (li & 1) ? (R)s.x : (R)(-s.y);
       }
 #pragma unroll
-      for (int m = 0; m < 4; ++m) acc[m][t] = M::op(afrag[m], bv, acc[m][t]);
+      for (int m = 0; m < 4; ++m) acc[m][t] = M::op(af[m], bv, acc[m][t]);
+    }
+  };
+  // software pipeline: the A fragments of the next kPre steps are in flight
+  // while the current step's products run (same product order as unpipelined)
+  constexpr int kPre = 4;
+  R af[kPre][4];
+#pragma unroll
+  for (int q = 0; q < kPre; ++q) load_a(2 * q, af[q]);
+  for (int k0 = 0; k0 < K; k0 += 2 * kPre) {
+#pragma unroll
+    for (int q = 0; q < kPre; ++q) {
+      const int kq = k0 + 2 * q;
+      if (kq >= K) break;
+      R cur[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) cur[m] = af[q][m];
+      load_a(kq + 2 * kPre, af[q]);
+      step(kq, cur);
     }
   }
   // epilogue: register r of the lane holds D[M::row(lane/16, r)][li] of each tile
@@ -165,13 +182,18 @@ __global__ __launch_bounds__(256) void k_gemm_reduce(size_t n, int K, int N, siz
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = typename M::acc_t{};
 
-  for (size_t r = r0; r < r1; r += 2) {
+  // operands of the rows r + krow (two rows per step)
+  struct Frag {
+    R a;
+    R b[NT];
+  };
+  auto load = [&](size_t r, Frag& f) {
     const size_t row = r + krow;
     const bool rv = row < r1;
-    R av = R(0);
+    f.a = R(0);
     if (a && rv) {
       cpx<R> z = Storage<VS>::ld(a, row);
-      av = kpart ? z.im : z.re;
+      f.a = kpart ? z.im : z.re;
     }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
@@ -183,7 +205,24 @@ __global__ __launch_bounds__(256) void k_gemm_reduce(size_t n, int K, int N, siz
         if (kpart == 0) bv = (li & 1) ? z.im : z.re;
         else bv = (li & 1) ? -z.re : z.im;
       }
-      acc[t] = M::op(av, bv, acc[t]);
+      f.b[t] = bv;
+    }
+  };
+  // software pipeline: the operands of the next kPre steps are in flight while
+  // the current step's products run (same product order as unpipelined)
+  constexpr int kPre = 4;
+  Frag fr[kPre];
+#pragma unroll
+  for (int q = 0; q < kPre; ++q) load(r0 + 2 * q, fr[q]);
+  for (size_t r = r0; r < r1; r += 2 * kPre) {
+#pragma unroll
+    for (int q = 0; q < kPre; ++q) {
+      const size_t rq = r + 2 * q;
+      if (rq >= r1) break;
+      const Frag cur = fr[q];
+      load(rq + 2 * kPre, fr[q]);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[t] = M::op(cur.a, cur.b[t], acc[t]);
     }
   }
   // partial layout: [chunk][i in 0..K)][jj in 0..2N) doubles
