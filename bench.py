@@ -160,7 +160,7 @@ def stencil_roofline(B, torch, dims, seed, reps, variant=0):
 
 BATCH_MASS = -0.58
 BATCH_SIZES = (1, 4, 8, 12)
-SERVE_FIELDS = (((8, 8, 8, 8), 11), ((16, 16, 16, 32), SEED), ((24, 24, 24, 48), HBM_SEED))
+SERVE_FIELDS = (((8, 8, 8, 8), 2), ((16, 16, 16, 32), SEED), ((24, 24, 24, 48), HBM_SEED))
 SERVE_MASS = -0.58
 SERVE_MAX_ITER = 20000  # per request (inner iterations over all refinement steps)
 
@@ -202,7 +202,7 @@ def batching_leg(B, torch, g, bt, nrhs=12):
     return out
 
 
-def serving_leg(B, torch, n_bank_rhs, n_requests, seed=5):
+def serving_leg(B, torch, n_bank_rhs, n_requests, seed=7):
     """Continuous batching over three resident gauge fields (8^4, 16^3x32,
     24^3x48): each field's FP32 bank is grown by mixed-precision eigCG on
     n_bank_rhs right-hand sides (not timed), then a seeded Poisson stream of
@@ -306,15 +306,23 @@ def serving_leg(B, torch, n_bank_rhs, n_requests, seed=5):
     all_idx = list(range(n_requests))
     wall, res = stream(all_idx, mean_iso / 4.0, "saturated")
     t0, t1 = 0.0, wall
-    # half of the measured capacity (latency): every other request again
+    # latency at 50 %, 80 % and 95 % of the measured capacity: every other
+    # request of the same mix again, Poisson arrivals at that rate
+    loads = []
     half_idx = all_idx[::2]
-    wall_l, res_l = stream(half_idx, 2.0 * wall / n_requests, "half load")
-    lat_l = np.array([st["seconds"] for _, st in res_l])
-    light = {"requests": len(half_idx), "offered_rhs_per_s": 0.5 * n_requests / wall,
-             "rhs_per_s": len(half_idx) / wall_l,
-             "p50_s": float(np.percentile(lat_l, 50)), "p99_s": float(np.percentile(lat_l, 99)),
-             "failed": int(sum(1 for rc, st in res_l if rc != 0 or st["true_rel_res"] > TOL))}
-    log(f"serving at half capacity: p50 {light['p50_s'] * 1e3:.0f} ms p99 {light['p99_s'] * 1e3:.0f} ms")
+    for frac in (0.5, 0.8, 0.95):
+        rate = frac * n_requests / wall
+        wall_l, res_l = stream(half_idx, 1.0 / rate, f"{int(frac * 100)}% load")
+        lat_l = np.array([st["seconds"] for _, st in res_l])
+        loads.append({"load": frac, "requests": len(half_idx), "offered_rhs_per_s": rate,
+                      "rhs_per_s": len(half_idx) / wall_l,
+                      "p50_s": float(np.percentile(lat_l, 50)),
+                      "p99_s": float(np.percentile(lat_l, 99)),
+                      "failed": int(sum(1 for rc, st in res_l
+                                        if rc != 0 or st["true_rel_res"] > TOL))})
+        log(f"serving at {int(frac * 100)}% of capacity: p50 {loads[-1]['p50_s'] * 1e3:.0f} ms "
+            f"p99 {loads[-1]['p99_s'] * 1e3:.0f} ms")
+    light = loads[0]
     lat = np.array([st["seconds"] for _, st in res])
     ok = [rc == 0 and st["true_rel_res"] <= TOL for rc, st in res]
     per_field = []
@@ -352,6 +360,7 @@ def serving_leg(B, torch, n_bank_rhs, n_requests, seed=5):
            "plain_fp64_cg_same_mix_s": plain_mix, "speedup_vs_plain_fp64_cg": plain_mix / (t1 - t0),
            "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
            "half_load": light,
+           "loads": loads,
            "isolated_request_s": {str(list(fields[k]["dims"])): v for k, v in iso.items()},
            "failed": int(len(ok) - sum(ok)),
            "max_true_rel_res": max(st["true_rel_res"] for _, st in res), "per_field": per_field}
@@ -454,10 +463,23 @@ def cpu_baseline(total_rhs, total_iters, budget_s=20.0):
     # cg() also applies A once for r0 and once for the final true residual
     per_iter = dt / (n_it + 2)
     rhs_per_s = total_rhs / (total_iters * per_iter)
+    import platform
+    cpu_model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu_model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": rhs_per_s, "unit": "RHS/s", "cores": 1, "kind": "oracle",
+            "host_cores_available": len(os.sched_getaffinity(0)), "cpu_model": cpu_model,
+            "seconds_per_cg_iteration": per_iter, "extrapolated": True,
             "sample": f"{n_it} FP64 CG iterations of the NumPy oracle on the 16^3x32 lattice "
-                      f"({per_iter:.3f} s per iteration incl. A = M^H M); RHS/s extrapolated "
-                      f"with the GPU run's {total_iters} iterations for {total_rhs} RHS"}
+                      f"({per_iter:.3f} s per iteration incl. A = M^H M; the NumPy stencil runs "
+                      f"on one core); RHS/s extrapolated with the GPU run's {total_iters} "
+                      f"iterations for {total_rhs} RHS"}
 
 
 def main():
