@@ -87,7 +87,7 @@ typedef struct {
                              ignored while sample_every > 0 */
   int32_t stencil_variant;/* 0: pick the fastest stencil kernel by timing at create
                              (cached per lattice shape and precision in the process);
-                             1..9: force a variant (see eigcg_layout_info) */
+                             1..10: force a variant (see eigcg_layout_info) */
   int32_t plane_pad;      /* extra sites (in units of 64) after each SoA plane so
                              that planes do not start on the same memory channel:
                              0 = library default, < 0 = none */
@@ -180,8 +180,10 @@ int eigcg_memory(eigcg_ctx* ctx, uint64_t* bytes);
  *   7  as 5 with one workgroup per compute unit
  *   8  as 5, each XCD sweeping its t-slab in (z, t, xy) tile order
  *   9  as 8 with at most two workgroups per compute unit
- * (8 and 9 need Lx Ly divisible by 64 and Lt by 8, else they run as 5 / 6).
- * eigcg_tune_report: tune_ms (18 doubles) receives the ms that variants 1..9
+ *  10  as 9 with cached (not streaming) epilogue loads and stores
+ * (8-10 need Lx Ly divisible by 64 and Lt by 8, else they run as 5 / 6 / 6;
+ * 16-bit storage runs 1-4 as 5 and 10 as 9).
+ * eigcg_tune_report: tune_ms (20 doubles) receives the ms that variants 1..10
  * took (best over columns per workgroup) for one CG-shaped pair of stencil
  * passes over a full batch at create, FP64 then FP32 (0 where not timed, e.g.
  * a forced variant). */

@@ -31,9 +31,10 @@ enum StencilEpi {
 //  7: as 5 with one workgroup per CU
 //  8: as 5, each XCD sweeping a t-slab in (z, t, xy) tile order
 //  9: as 8 with at most two workgroups per CU
-// 8 and 9 need whole 64-site tiles per xy-plane and Lt divisible by 8; other
-// lattices run 5 and 6 instead.
-constexpr int kStencilVariants = 9;
+// 10: as 9 with cached (not streaming) epilogue loads and stores
+// 8-10 need whole 64-site tiles per xy-plane and Lt divisible by 8; other
+// lattices run 5 and 6 (10 as 6) instead.
+constexpr int kStencilVariants = 10;
 
 struct StencilLaunch {
   int prec;                 // kF64 / kF32 (vectors and links)

@@ -444,6 +444,7 @@ hipError_t launch_typed(const StencilLaunch& L, hipStream_t s) {
   if (kHalf) {
     if (!L.compressed) return hipErrorInvalidValue;
     if (variant < 5) variant = 5;
+    if (variant == 10) variant = 9;
   }
   const uint32_t plane = (uint32_t)(L.g->L[0] * L.g->L[1]);
   if (variant >= 8 && (plane % 64u != 0 || L.g->L[3] % 8 != 0))
@@ -460,7 +461,7 @@ hipError_t launch_typed(const StencilLaunch& L, hipStream_t s) {
     // as many workgroups as are resident at once (multiple of 8), so each
     // XCD's workgroups sweep one contiguous front of its chunk
     int res = 0;
-    const int per_cu = (variant == 6 || variant == 9) ? 2 : variant == 7 ? 1 : 0;
+    const int per_cu = (variant == 6 || variant >= 9) ? 2 : variant == 7 ? 1 : 0;
     dyn_lds = pair_occupancy<VS, LS>(per_cu, &res);
     gx = (int)std::min<uint32_t>((T + 7u) & ~7u, (uint32_t)res);
   } else {
@@ -489,7 +490,9 @@ hipError_t launch_typed(const StencilLaunch& L, hipStream_t s) {
     EIGCG_LAUNCH((k_wilson_pair<VS, LS, COMP, DAG, EPI, NT, ORD, 1>), dyn_lds)       \
   }
 #define EIGCG_K(COMP, DAG, EPI)                                                      \
-  if (variant >= 8) {                                                                \
+  if (variant == 10) {                                                               \
+    EIGCG_PAIR(COMP, DAG, EPI, false, 1)                                             \
+  } else if (variant >= 8) {                                                         \
     EIGCG_PAIR(COMP, DAG, EPI, true, 1)                                              \
   } else if (variant >= 4) {                                                         \
     EIGCG_PAIR(COMP, DAG, EPI, true, 0)                                              \

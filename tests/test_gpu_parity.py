@@ -39,7 +39,8 @@ CASES = [
 
 @pytest.mark.parametrize("name,dims,eps,seed,mass", CASES)
 @pytest.mark.parametrize("compress,variant", [(0, 1), (1, 1), (1, 2), (1, 3), (0, 3), (1, 4),
-                                              (1, 5), (1, 6), (1, 7), (1, 8), (1, 9), (0, 9)])
+                                              (1, 5), (1, 6), (1, 7), (1, 8), (1, 9), (0, 9),
+                                              (1, 10)])
 def test_apply_matches_oracle(B, name, dims, eps, seed, mass, compress, variant):
     U = gauge_field(dims, eps, seed)
     op = WilsonOperator(U, mass)
@@ -91,7 +92,7 @@ def cfg0():
     return U, op, b
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3, 6, 9])
+@pytest.mark.parametrize("variant", [1, 2, 3, 6, 9, 10])
 def test_cg_parity_cfg0(B, cfg0, variant):
     U, op, b = cfg0
     xo, io = cg(op.A, b.reshape(-1), tol=1e-10)
@@ -276,7 +277,7 @@ def test_batched_columns_match_single(B, cfg0):
 
 
 @pytest.mark.parametrize("dims,variant", [((4, 4, 4, 4), 9), ((4, 4, 4, 4), 3),
-                                          ((8, 8, 2, 8), 9), ((8, 8, 2, 8), 5)])
+                                          ((8, 8, 2, 8), 9), ((8, 8, 2, 8), 5), ((8, 8, 2, 8), 10)])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_batched_multicolumn_kernels_match_single(B, dims, variant, precision):
     """Batches of 5 columns run the stencil with several right-hand sides per
