@@ -23,10 +23,13 @@ Modules:
                      init-CG of Section 5.3.
 * ``incremental``  - Incremental eigCG outer loop (Section 4 algorithm box).
 * ``dense``        - dense matrices of the operator for tiny lattices.
+* ``schur``        - odd-even (Schur complement) preconditioned operator on
+                     the even sites, with the maps to and from the full
+                     system (the operator of the paper's lattice runs).
 
 Parity status: every function here is pinned by a test under ``tests/``
 (closed forms, invariants, dense linear algebra or brute force); nothing is
 "parity unpinned".
 """
 
-from . import dirac, cg, eigcg, initcg, incremental, dense  # noqa: F401
+from . import dirac, cg, eigcg, initcg, incremental, dense, schur  # noqa: F401

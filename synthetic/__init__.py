@@ -25,4 +25,5 @@ from .fields import (  # noqa: F401
     random_su3_sites,
     gaussian_rhs,
     gaussian_rhs_block,
+    gaussian_half_rhs,
 )

@@ -100,3 +100,11 @@ def gaussian_rhs(dims, seed: int) -> np.ndarray:
 def gaussian_rhs_block(dims, seeds) -> np.ndarray:
     """Several right-hand sides stacked on a leading axis, one seed each."""
     return np.stack([gaussian_rhs(dims, s) for s in seeds], axis=0)
+
+
+def gaussian_half_rhs(dims, seed: int) -> np.ndarray:
+    """One complex Gaussian field on half of the sites, ``(V/2, 4, 3)``: a
+    vector of the odd-even preconditioned system (one entry per even site, in
+    lexicographic order)."""
+    rng = np.random.default_rng(seed)
+    return _complex_gaussian(rng, (n_sites(dims) // 2, 4, 3))
