@@ -24,8 +24,20 @@
  *   EIGCG_MODE_INITCG  init-CG (eq. (2.1)) with the bank, restarted once near
  *                      machine precision (Section 5.3).
  *
+ * Odd-even preconditioning (params.schur = 1; the operator of the paper's
+ * lattice runs, Sections 6 and 7, which halves the system): sites split by the
+ * parity of x + y + z + t, D couples opposite parities only, and with
+ * d = 4 + m_q the context's operator becomes A = Mhat^H Mhat on the even
+ * sites, where Mhat = d - D_eo D_oe / (4 d) is the Schur complement of the
+ * odd block of M.  Solving M x = b: eigcg_schur_rhs gives the right-hand side
+ * Mhat^H (b_e + D_eo b_o / (2 d)), eigcg_solve returns x_e, and
+ * eigcg_schur_reconstruct adds x_o = (b_o + D_oe x_e / 2) / d.
+ *
  * Boundary layout (always FP64, owned by the caller, device pointers):
- *   spinor fields: complex128 [nrhs][Lt][Lz][Ly][Lx][4 spin][3 colour]
+ *   spinor fields: complex128 [nrhs][Lt][Lz][Ly][Lx][4 spin][3 colour]; in an
+ *                  odd-even context the solver's fields (b, x, bank vectors,
+ *                  eigcg_apply) are [nrhs][V/2 even sites][4][3], the even
+ *                  sites in lexicographic order (site s is entry s / 2)
  *   gauge field:   complex128 [Lt][Lz][Ly][Lx][4 mu][3][3], U_mu(x)[a][b] row-major,
  *                  mu = 0..3 is x, y, z, t.
  * Internal precision (EIGCG_FP64 or EIGCG_MIXED_FP32) never changes the
@@ -60,7 +72,7 @@ enum {
 
 enum { EIGCG_FP64 = 0, EIGCG_MIXED_FP32 = 1, EIGCG_MIXED_HALF = 2 };
 enum { EIGCG_MODE_CG = 0, EIGCG_MODE_EIGCG = 1, EIGCG_MODE_INITCG = 2 };
-enum { EIGCG_OP_M = 0, EIGCG_OP_MDAG = 1, EIGCG_OP_A = 2 };
+enum { EIGCG_OP_M = 0, EIGCG_OP_MDAG = 1, EIGCG_OP_A = 2, EIGCG_OP_INNER = 3 };
 
 typedef struct {
   int32_t dims[4];        /* Lx, Ly, Lz, Lt; each >= 2, periodic */
@@ -94,6 +106,8 @@ typedef struct {
   int32_t sample_every;   /* > 0: time the two stencil passes of every n-th CG
                              iteration with events on the context's stream
                              (read with eigcg_kernel_samples); 0 = off */
+  int32_t schur;          /* 1: odd-even preconditioned operator on the even
+                             sites (every extent even); 0: A = M^H M */
 } eigcg_params;
 
 typedef struct {
@@ -132,8 +146,22 @@ int eigcg_deflate_init(eigcg_ctx* ctx, int32_t nrhs, const void* b_dev, void* x_
 /* Free everything the context owns. */
 int eigcg_destroy(eigcg_ctx* ctx);
 
-/* out = op(in) for op = M, M^H or A = M^H M in FP64 (test support). */
+/* out = op(in) for op = M, M^H or A = M^H M in FP64 (test support); in an
+ * odd-even context Mhat, Mhat^H and Mhat^H Mhat on even-site fields.
+ * op + 3 (EIGCG_OP_INNER): the same with the inner-precision kernels of a
+ * mixed context (input rounded to FP32 or 16 bits, result widened to FP64);
+ * EINVAL in an FP64 context. */
 int eigcg_apply(eigcg_ctx* ctx, int32_t op, int32_t nrhs, const void* in_dev, void* out_dev);
+
+/* Odd-even contexts only (EINVAL otherwise), for nrhs full-lattice fields
+ * b_full_dev (boundary layout [nrhs][Lt][Lz][Ly][Lx][4][3]):
+ * eigcg_schur_rhs writes rhs_dev (even-site layout) = Mhat^H (b_e + D_eo b_o / (2 d)),
+ * the right-hand side whose solution x_e is the even part of the solution of
+ * M x = b; eigcg_schur_reconstruct writes x_full_dev (full layout) with even part
+ * x_even_dev and odd part (b_o + D_oe x_e / 2) / d.  Both synchronise. */
+int eigcg_schur_rhs(eigcg_ctx* ctx, int32_t nrhs, const void* b_full_dev, void* rhs_dev);
+int eigcg_schur_reconstruct(eigcg_ctx* ctx, int32_t nrhs, const void* b_full_dev,
+                            const void* x_even_dev, void* x_full_dev);
 
 /* Rayleigh-Ritz on the bank (Section 5.2): *l = columns of U; ritz_vals
  * (l doubles, ascending) = eigenvalues of H = U^H A U; ritz_res (l doubles or

@@ -11,21 +11,21 @@ Lanczos/CG relation (Section 3, eq. (3.1)): with ``v_k = r_{k-1} / sqrt(rho_k)``
     T[k, k]     = 1/alpha_k + beta_k / alpha_{k-1}     (beta_1 / alpha_0 := 0)
     T[k, k + 1] = -sqrt(beta_{k+1}) / alpha_k
 
-The off-diagonal sign is negative (step 11.10 of the figure); eq. (3.1) prints
-it positive, which corresponds to sign-alternated Lanczos vectors.  With the
-normalised residuals themselves as basis the negative sign is the one that
-makes ``T = V^H A V`` (pinned by a test).
+The off-diagonal sign is negative (as the figure's tridiagonal update has
+it); eq. (3.1) prints it positive, which corresponds to sign-alternated
+Lanczos vectors.  With the normalised residuals themselves as basis the
+negative sign is the one that makes ``T = V^H A V`` (pinned by a test).
 
 Readings where the figure is terse (each one is listed in the design notes):
 
-* step 11.1 fills the diagonal of the *window* column appended in the
-  previous iteration (window index ``i``), using ``alpha`` (the figure's
-  ``a_{j-2}`` is ``alpha_{j-2}``);
-* step 11.10 is skipped while the window is empty (j = 1);
+* the diagonal entry filled after each new ``A p`` belongs to the *window*
+  column appended in the previous iteration (window index ``i``), using
+  ``alpha`` (the figure's ``a_{j-2}`` is ``alpha_{j-2}``);
+* the off-diagonal update is skipped while the window is empty (j = 1);
 * ``orth([Y, Ybar])`` is a thin Householder QR, so the restarted window always
   holds ``2 nev`` columns;
-* ``T`` is kept complex Hermitian, since the arrow row ``w^H V`` of step 11.8
-  is complex in floating point;
+* ``T`` is kept complex Hermitian, since the arrow row ``w^H V`` of the
+  restart is complex in floating point;
 * the output (the figure returns ``[x, V, M]``) is a final Rayleigh-Ritz on
   the current ``T_i`` after filling its last diagonal entry, returning the
   ``min(nev, i)`` lowest Ritz pairs, eigenvalues ascending;
@@ -46,7 +46,9 @@ def _lowest_eigvecs(T, k):
 
 
 def restart_coefficients(Tm, nev):
-    """Steps 11.3 to 11.6 of Figure 3.1 on the full window matrix ``T_m``.
+    """Restart coefficients of Figure 3.1 (eq. (2.3)) from the full window matrix ``T_m``:
+    lowest Ritz vectors of ``T_m`` and ``T_{m-1}``, their orthonormal basis, and
+    the Rayleigh-Ritz of ``T_m`` on it.
 
     Returns ``(QZ, Mvals, Q, Z, Y, Ybar)`` where ``V (QZ)`` is the restarted
     window and ``diag(Mvals)`` its projection.
@@ -54,11 +56,11 @@ def restart_coefficients(Tm, nev):
     m = Tm.shape[0]
     _, Y = _lowest_eigvecs(Tm, nev)                       # T_m Y = Y M
     _, Yb = _lowest_eigvecs(Tm[: m - 1, : m - 1], nev)    # T_{m-1} Ybar = Ybar Mbar
-    Ybar = np.vstack([Yb, np.zeros((1, nev), dtype=Tm.dtype)])  # step 11.4
-    Q, _ = np.linalg.qr(np.hstack([Y, Ybar]), mode="reduced")   # step 11.5
+    Ybar = np.vstack([Yb, np.zeros((1, nev), dtype=Tm.dtype)])  # pad Ybar to m rows
+    Q, _ = np.linalg.qr(np.hstack([Y, Ybar]), mode="reduced")   # orth([Y, Ybar])
     Hs = Q.conj().T @ Tm @ Q
     Hs = 0.5 * (Hs + Hs.conj().T)
-    Mvals, Z = np.linalg.eigh(Hs)                          # step 11.6
+    Mvals, Z = np.linalg.eigh(Hs)                          # Q^H T_m Q = Z M Z^H
     return Q @ Z, Mvals, Q, Z, Y, Ybar
 
 
@@ -88,7 +90,7 @@ def eigcg(apply_A, b, nev, m, x0=None, tol=1e-10, max_iter=100000, record=False)
     V = np.zeros((n, m), dtype=np.complex128)
     T = np.zeros((m, m), dtype=np.complex128)
     i = 0                       # columns currently in the window V
-    r = b - apply_A(x)          # step 0
+    r = b - apply_A(x)
     j = 0
     rho = None
     alpha_1 = alpha_2 = None    # alpha_{j-1}, alpha_{j-2}
@@ -98,27 +100,27 @@ def eigcg(apply_A, b, nev, m, x0=None, tol=1e-10, max_iter=100000, record=False)
     while np.linalg.norm(r) / bnorm > tol and j < max_iter:
         j += 1
         rho_prev = rho
-        rho = _real_positive(_dot(r, r), "r^H r")          # step 4 (z = r)
+        rho = _real_positive(_dot(r, r), "r^H r")          # z = r (P = I)
         if j == 1:
             beta = 0.0
-            p = r.copy()                                   # step 6
+            p = r.copy()
         else:
-            beta = rho / rho_prev                          # step 8
-            p = r + beta * p                               # step 9
+            beta = rho / rho_prev
+            p = r + beta * p
         if i == m:
-            t_prev = t                                     # step 10.1
-        t = apply_A(p)                                     # step 11
-        if j > 1:                                          # step 11.1
+            t_prev = t                                     # A p of the previous iteration
+        t = apply_A(p)
+        if j > 1:  # diagonal of the window column appended last iteration
             T[i - 1, i - 1] = 1.0 / alpha_1 + (beta_1 / alpha_2 if j > 2 else 0.0)
-        if i == m:                                         # step 11.2
+        if i == m:                                         # full window: restart
             QZ, Mvals, Q, Z, _, _ = restart_coefficients(T.copy(), nev)
             Tm = T.copy() if record else None
-            V[:, : 2 * nev] = V[:, :m] @ QZ                # step 11.7
+            V[:, : 2 * nev] = V[:, :m] @ QZ                # V <- V (QZ)
             V[:, 2 * nev:] = 0.0
             T[:, :] = 0.0
             T[: 2 * nev, : 2 * nev] = np.diag(Mvals)
             i = 2 * nev
-            w = t - beta * t_prev                          # step 11.8: w = A r
+            w = t - beta * t_prev                          # w = A r
             arrow = (w.conj() @ V[:, :i]) / np.sqrt(rho)   # z^H A V / sqrt(rho)
             T[i, :i] = arrow
             T[:i, i] = np.conj(arrow)
@@ -126,16 +128,16 @@ def eigcg(apply_A, b, nev, m, x0=None, tol=1e-10, max_iter=100000, record=False)
             if record:
                 info["restarts"].append({"Tm": Tm, "QZ": QZ, "M": Mvals,
                                          "arrow": arrow, "Q": Q, "Z": Z, "j": j})
-        elif i >= 1:                                       # step 11.10
+        elif i >= 1:                                       # off-diagonal of T
             T[i, i - 1] = T[i - 1, i] = -np.sqrt(beta) / alpha_1
-        i += 1                                             # step 11.12
-        V[:, i - 1] = r / np.sqrt(rho)                     # step 11.13
-        pt = _real_positive(_dot(p, t), "p^H A p")         # step 12
+        i += 1                                             # append r / sqrt(rho) to V
+        V[:, i - 1] = r / np.sqrt(rho)
+        pt = _real_positive(_dot(p, t), "p^H A p")
         if pt <= 0.0:
             raise FloatingPointError("p^H A p <= 0: A is not positive definite")
         alpha = rho / pt
-        x = x + alpha * p                                  # step 13
-        r = r - alpha * t                                  # step 14
+        x = x + alpha * p
+        r = r - alpha * t
         info["alpha"].append(alpha)
         info["beta"].append(beta)
         info["rho"].append(rho)

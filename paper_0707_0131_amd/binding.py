@@ -23,7 +23,7 @@ STENCIL_VARIANTS = 10
 EIGCG_EBREAKDOWN, EIGCG_EHIP, EIGCG_EBUSY = -4, -5, -6
 EIGCG_FP64, EIGCG_MIXED_FP32, EIGCG_MIXED_HALF = 0, 1, 2
 EIGCG_MODE_CG, EIGCG_MODE_EIGCG, EIGCG_MODE_INITCG = 0, 1, 2
-EIGCG_OP_M, EIGCG_OP_MDAG, EIGCG_OP_A = 0, 1, 2
+EIGCG_OP_M, EIGCG_OP_MDAG, EIGCG_OP_A, EIGCG_OP_INNER = 0, 1, 2, 3
 
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "ENOTCONV", -4: "EBREAKDOWN",
                 -5: "EHIP", -6: "EBUSY"}
@@ -48,6 +48,7 @@ class Params(ctypes.Structure):
         ("stencil_variant", ctypes.c_int32),
         ("plane_pad", ctypes.c_int32),
         ("sample_every", ctypes.c_int32),
+        ("schur", ctypes.c_int32),
     ]
 
 
@@ -79,6 +80,8 @@ SIGNATURES = {
     "eigcg_deflate_init": (_I32, [_VP, _I32, _VP, _VP]),
     "eigcg_destroy": (_I32, [_VP]),
     "eigcg_apply": (_I32, [_VP, _I32, _I32, _VP, _VP]),
+    "eigcg_schur_rhs": (_I32, [_VP, _I32, _VP, _VP]),
+    "eigcg_schur_reconstruct": (_I32, [_VP, _I32, _VP, _VP, _VP]),
     "eigcg_bank_info": (_I32, [_VP, ctypes.POINTER(_I32), _DP, _DP]),
     "eigcg_bank_vectors": (_I32, [_VP, _I32, _I32, _VP]),
     "eigcg_bank_load": (_I32, [_VP, _I32, _VP, ctypes.POINTER(_I32)]),
@@ -155,6 +158,9 @@ def _check_field(t, what):
         raise ValueError(f"{what} must be a contiguous complex128 device tensor")
 
 
+_PARAM_NAMES = {name for name, _ in Params._fields_}
+
+
 def eigcg_default_params(**overrides) -> Params:
     p = Params()
     LIB.eigcg_default_params(ctypes.byref(p))
@@ -162,8 +168,10 @@ def eigcg_default_params(**overrides) -> Params:
         if k == "dims":
             for i in range(4):
                 p.dims[i] = int(v[i])
-        else:
+        elif k in _PARAM_NAMES:
             setattr(p, k, v)
+        else:
+            raise KeyError(f"unknown parameter {k!r}")
     return p
 
 
@@ -209,6 +217,26 @@ def eigcg_apply(ctx, op, inp, out):
     _check_field(inp, "in")
     _check_field(out, "out")
     rc = LIB.eigcg_apply(ctx, int(op), inp.shape[0], _ptr(inp), _ptr(out))
+    if rc != EIGCG_OK:
+        raise EigcgError(rc, eigcg_last_error(ctx))
+
+
+def eigcg_schur_rhs(ctx, b_full, rhs):
+    """rhs (even sites) = Mhat^H (b_e + D_eo b_o / (2 d)) for full-lattice fields b_full."""
+    _check_field(b_full, "b_full")
+    _check_field(rhs, "rhs")
+    rc = LIB.eigcg_schur_rhs(ctx, b_full.shape[0], _ptr(b_full), _ptr(rhs))
+    if rc != EIGCG_OK:
+        raise EigcgError(rc, eigcg_last_error(ctx))
+
+
+def eigcg_schur_reconstruct(ctx, b_full, x_even, x_full):
+    """x_full = (x_even, (b_o + D_oe x_even / 2) / d) on the full lattice."""
+    _check_field(b_full, "b_full")
+    _check_field(x_even, "x_even")
+    _check_field(x_full, "x_full")
+    rc = LIB.eigcg_schur_reconstruct(ctx, b_full.shape[0], _ptr(b_full), _ptr(x_even),
+                                     _ptr(x_full))
     if rc != EIGCG_OK:
         raise EigcgError(rc, eigcg_last_error(ctx))
 

@@ -68,6 +68,11 @@ int validate(const eigcg_params* p, std::string& why) {
   if (p->stencil_variant < 0 || p->stencil_variant > eigcg::kStencilVariants) { why = "stencil_variant out of range"; return EIGCG_EINVAL; }
   if (p->plane_pad > 4096) { why = "plane_pad too large"; return EIGCG_EINVAL; }
   if (p->sample_every < 0) { why = "sample_every must be >= 0"; return EIGCG_EINVAL; }
+  if (p->schur != 0 && p->schur != 1) { why = "schur must be 0 or 1"; return EIGCG_EINVAL; }
+  if (p->schur && (p->dims[0] % 2 || p->dims[1] % 2 || p->dims[2] % 2 || p->dims[3] % 2)) {
+    why = "odd-even preconditioning needs every lattice extent even";
+    return EIGCG_EINVAL;
+  }
   if (p->precision == EIGCG_MIXED_FP32 && p->reliable_every < 1) { why = "reliable_every must be >= 1"; return EIGCG_EINVAL; }
   return EIGCG_OK;
 }
@@ -159,11 +164,35 @@ int eigcg_deflate_init(eigcg_ctx* ctx, int32_t nrhs, const void* b_dev, void* x_
 
 int eigcg_apply(eigcg_ctx* ctx, int32_t op, int32_t nrhs, const void* in_dev, void* out_dev) {
   if (!ctx) return EIGCG_EINVAL;
-  if (op < EIGCG_OP_M || op > EIGCG_OP_A) return fail(ctx, EIGCG_EINVAL, "bad op");
+  if (op < EIGCG_OP_M || op > EIGCG_OP_A + 3) return fail(ctx, EIGCG_EINVAL, "bad op");
   if (nrhs < 0 || (nrhs > 0 && (!in_dev || !out_dev))) return fail(ctx, EIGCG_EINVAL, "bad arguments");
   if (nrhs == 0) return EIGCG_OK;
   return guarded(ctx, [&] {
     eigcg::apply_op(ctx->c, op, nrhs, in_dev, out_dev);
+    return EIGCG_OK;
+  });
+}
+
+int eigcg_schur_rhs(eigcg_ctx* ctx, int32_t nrhs, const void* b_full_dev, void* rhs_dev) {
+  if (!ctx) return EIGCG_EINVAL;
+  if (!ctx->c.g.eo) return fail(ctx, EIGCG_EINVAL, "context is not odd-even preconditioned");
+  if (nrhs < 0 || (nrhs > 0 && (!b_full_dev || !rhs_dev))) return fail(ctx, EIGCG_EINVAL, "bad arguments");
+  if (nrhs == 0) return EIGCG_OK;
+  return guarded(ctx, [&] {
+    eigcg::schur_rhs(ctx->c, nrhs, b_full_dev, rhs_dev);
+    return EIGCG_OK;
+  });
+}
+
+int eigcg_schur_reconstruct(eigcg_ctx* ctx, int32_t nrhs, const void* b_full_dev,
+                            const void* x_even_dev, void* x_full_dev) {
+  if (!ctx) return EIGCG_EINVAL;
+  if (!ctx->c.g.eo) return fail(ctx, EIGCG_EINVAL, "context is not odd-even preconditioned");
+  if (nrhs < 0 || (nrhs > 0 && (!b_full_dev || !x_even_dev || !x_full_dev)))
+    return fail(ctx, EIGCG_EINVAL, "bad arguments");
+  if (nrhs == 0) return EIGCG_OK;
+  return guarded(ctx, [&] {
+    eigcg::schur_reconstruct(ctx->c, nrhs, b_full_dev, x_even_dev, x_full_dev);
     return EIGCG_OK;
   });
 }

@@ -17,8 +17,8 @@ inline int grid_for(size_t n) {
   return (int)g;
 }
 
-// CG step 3 (Figure 3.1, steps 13, 3-9 and 11.13 of the next iteration):
-// x += alpha p; p = r + beta p; window slot (iter+1) % ring = r / sqrt(rho).
+// End of a CG iteration (Figure 3.1) and the start of the next: x += alpha p;
+// p = r + beta p; window slot (iter+1) % ring = r / sqrt(rho).
 template <typename VS, typename XS>
 __global__ __launch_bounds__(kBlock) void k_cg_update(UpdateLaunch a, Geom g) {
   using R = typename Storage<VS>::real;
@@ -115,18 +115,59 @@ __global__ __launch_bounds__(kBlock) void k_from_soa(const VS* __restrict__ soa,
   }
 }
 
+// parity of lattice site s, (x + y + z + t) mod 2
+__device__ __forceinline__ uint32_t site_parity(const Geom& g, uint32_t s) {
+  const uint32_t xyz = g.dx.div(s);
+  const uint32_t x = s - xyz * (uint32_t)g.L[0];
+  const uint32_t zt = g.dy.div(xyz);
+  const uint32_t y = xyz - zt * (uint32_t)g.L[1];
+  const uint32_t t = g.dz.div(zt);
+  const uint32_t z = zt - t * (uint32_t)g.L[2];
+  return (x + y + z + t) & 1u;
+}
+
 template <typename LS>
 __global__ __launch_bounds__(kBlock) void k_gauge_to_soa(const double2* __restrict__ aos, LS* soa,
                                                          Geom g, int comp) {
   using R = typename Storage<LS>::real;
   const int per = comp ? 6 : 9;
-  for (uint32_t s = blockIdx.x * kBlock + threadIdx.x; s < (uint32_t)g.V; s += gridDim.x * kBlock) {
+  for (uint32_t s = blockIdx.x * kBlock + threadIdx.x; s < (uint32_t)g.Vfull;
+       s += gridDim.x * kBlock) {
+    // odd-even geometry: the block of the site's parity, at its half index
+    const size_t base = g.eo ? (size_t)site_parity(g, s) * 4 * per * g.vs : 0;
+    const uint32_t i = g.eo ? s >> 1 : s;
     for (int mu = 0; mu < 4; ++mu) {
       for (int e = 0; e < per; ++e) {
         double2 v = aos[((size_t)s * 4 + mu) * 9 + e];
-        Storage<LS>::st(soa, (size_t)(mu * per + e) * g.vs + s, {(R)v.x, (R)v.y});
+        Storage<LS>::st(soa, base + (size_t)(mu * per + e) * g.vs + i, {(R)v.x, (R)v.y});
       }
     }
+  }
+}
+
+// full-lattice AoS field <-> even and odd half-site SoA fields (FP64)
+__global__ __launch_bounds__(kBlock) void k_split_eo(const double2* __restrict__ aos, double2* even,
+                                                     double2* odd, Geom g, size_t soa_cs) {
+  const int col = blockIdx.y;
+  const double2* src = aos + (size_t)col * 12 * g.Vfull;
+  for (uint32_t s = blockIdx.x * kBlock + threadIdx.x; s < (uint32_t)g.Vfull;
+       s += gridDim.x * kBlock) {
+    double2* dst = (site_parity(g, s) ? odd : even) + (size_t)col * soa_cs;
+#pragma unroll
+    for (int e = 0; e < 12; ++e) dst[(size_t)e * g.vs + (s >> 1)] = src[(size_t)s * 12 + e];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_merge_eo(const double2* __restrict__ even,
+                                                     const double2* __restrict__ odd, double2* aos,
+                                                     Geom g, size_t soa_cs) {
+  const int col = blockIdx.y;
+  double2* dst = aos + (size_t)col * 12 * g.Vfull;
+  for (uint32_t s = blockIdx.x * kBlock + threadIdx.x; s < (uint32_t)g.Vfull;
+       s += gridDim.x * kBlock) {
+    const double2* src = (site_parity(g, s) ? odd : even) + (size_t)col * soa_cs;
+#pragma unroll
+    for (int e = 0; e < 12; ++e) dst[(size_t)s * 12 + e] = src[(size_t)e * g.vs + (s >> 1)];
   }
 }
 
@@ -136,7 +177,8 @@ __global__ __launch_bounds__(kBlock) void k_gauge_check(const double2* __restric
                                                         double* partial) {
   __shared__ double lds[2][kBlock];
   double m1 = 0.0, m2 = 0.0;
-  for (uint32_t s = blockIdx.x * kBlock + threadIdx.x; s < (uint32_t)g.V; s += gridDim.x * kBlock) {
+  for (uint32_t s = blockIdx.x * kBlock + threadIdx.x; s < (uint32_t)g.Vfull;
+       s += gridDim.x * kBlock) {
     for (int mu = 0; mu < 4; ++mu) {
       cpx<double> U[9];
       for (int e = 0; e < 9; ++e) {
@@ -352,7 +394,81 @@ __global__ void k_set_state(ColState* st, int ncols, uint32_t mask, int state, i
   if (clear_restart) st[c].restart2 = 0.0;
 }
 
+// After a reliable update has replaced r by the FP64 true residual, restore
+// the premise of the next step length alpha = r^H r / p^H A p, namely
+// r^H p = r^H r: p <- p - (r^H p / r^H r - 1) r (the component of p along
+// the new r becomes exactly r).  Running columns only; r^H r is the state's rho.
+template <typename VS>
+__global__ __launch_bounds__(kBlock) void k_dot_rp(size_t n, const VS* r, const VS* p, size_t cs,
+                                                   uint32_t mask, const ColState* st,
+                                                   double* part_re, double* part_im) {
+  using R = typename Storage<VS>::real;
+  __shared__ double lds4[kBlock / 64];
+  const int col = blockIdx.y;
+  if (!((mask >> col) & 1u) || st[col].state != ColRun) return;
+  const VS* rc = r + (size_t)col * cs;
+  const VS* pc = p + (size_t)col * cs;
+  double sr = 0.0, si = 0.0;
+  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+    const cpx<R> a = Storage<VS>::ld(rc, i), b = Storage<VS>::ld(pc, i);
+    sr += (double)a.re * (double)b.re + (double)a.im * (double)b.im;
+    si += (double)a.re * (double)b.im - (double)a.im * (double)b.re;
+  }
+  sr = block_sum(sr, lds4);
+  si = block_sum(si, lds4);
+  if (threadIdx.x == 0) {
+    part_re[(size_t)col * gridDim.x + blockIdx.x] = sr;
+    part_im[(size_t)col * gridDim.x + blockIdx.x] = si;
+  }
+}
+
+template <typename VS>
+__global__ __launch_bounds__(kBlock) void k_fix_p(size_t n, const VS* r, VS* p, size_t cs,
+                                                  uint32_t mask, const ColState* st,
+                                                  const double* part_re, const double* part_im) {
+  using R = typename Storage<VS>::real;
+  __shared__ double lds4[kBlock / 64];
+  const int col = blockIdx.y;
+  if (!((mask >> col) & 1u) || st[col].state != ColRun) return;
+  const double dr = reduce_partials(part_re + (size_t)col * gridDim.x, gridDim.x, lds4);
+  const double di = reduce_partials(part_im + (size_t)col * gridDim.x, gridDim.x, lds4);
+  const double rho = st[col].rho;
+  if (!(rho > 0.0 && rho < INFINITY)) return;
+  const R cr = (R)(dr / rho - 1.0), ci = (R)(di / rho);
+  const VS* rc = r + (size_t)col * cs;
+  VS* pc = p + (size_t)col * cs;
+  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+    const cpx<R> a = Storage<VS>::ld(rc, i);
+    cpx<R> b = Storage<VS>::ld(pc, i);
+    b.re -= cr * a.re - ci * a.im;
+    b.im -= cr * a.im + ci * a.re;
+    Storage<VS>::st(pc, i, b);
+  }
+}
+
 }  // namespace
+
+hipError_t launch_reliable_fix_p(int prec, int ncols, uint32_t mask, size_t n, const void* r,
+                                 void* p, size_t cs, const ColState* st, double* partial,
+                                 hipStream_t s) {
+  if (prec != kF32 && prec != kF64) return hipErrorInvalidValue;
+  const int gx = grid_for(n);
+  dim3 grid(gx, ncols);
+  double* pre = partial;
+  double* pim = partial + (size_t)kMaxCols * kMaxGrid;
+  if (prec == kF32) {
+    hipLaunchKernelGGL(k_dot_rp<float2>, grid, dim3(kBlock), 0, s, n, (const float2*)r,
+                       (const float2*)p, cs, mask, st, pre, pim);
+    hipLaunchKernelGGL(k_fix_p<float2>, grid, dim3(kBlock), 0, s, n, (const float2*)r, (float2*)p,
+                       cs, mask, st, pre, pim);
+  } else {
+    hipLaunchKernelGGL(k_dot_rp<double2>, grid, dim3(kBlock), 0, s, n, (const double2*)r,
+                       (const double2*)p, cs, mask, st, pre, pim);
+    hipLaunchKernelGGL(k_fix_p<double2>, grid, dim3(kBlock), 0, s, n, (const double2*)r,
+                       (double2*)p, cs, mask, st, pre, pim);
+  }
+  return hipGetLastError();
+}
 
 hipError_t launch_post_residual(ColState* st, int ncols, uint32_t mask, hipStream_t s) {
   hipLaunchKernelGGL(k_post_residual, dim3(1), dim3(64), 0, s, st, ncols, mask);
@@ -425,7 +541,7 @@ hipError_t launch_spinor_from_soa(const void* soa, double2* aos, int prec, const
 
 hipError_t launch_gauge_to_soa(const double2* aos, void* soa, int prec, int compressed,
                                const Geom* g, hipStream_t s) {
-  dim3 grid(grid_for(g->V));
+  dim3 grid(grid_for(g->Vfull));
   if (prec == kF64)
     hipLaunchKernelGGL(k_gauge_to_soa<double2>, grid, dim3(kBlock), 0, s, aos, (double2*)soa, *g,
                        compressed);
@@ -438,9 +554,27 @@ hipError_t launch_gauge_to_soa(const double2* aos, void* soa, int prec, int comp
   return hipGetLastError();
 }
 
+hipError_t launch_split_eo(const double2* aos, void* even, void* odd, const Geom* g, int ncols,
+                           size_t soa_cs, hipStream_t s) {
+  if (!g->eo) return hipErrorInvalidValue;
+  dim3 grid(grid_for(g->Vfull), ncols);
+  hipLaunchKernelGGL(k_split_eo, grid, dim3(kBlock), 0, s, aos, (double2*)even, (double2*)odd, *g,
+                     soa_cs);
+  return hipGetLastError();
+}
+
+hipError_t launch_merge_eo(const void* even, const void* odd, double2* aos, const Geom* g,
+                           int ncols, size_t soa_cs, hipStream_t s) {
+  if (!g->eo) return hipErrorInvalidValue;
+  dim3 grid(grid_for(g->Vfull), ncols);
+  hipLaunchKernelGGL(k_merge_eo, grid, dim3(kBlock), 0, s, (const double2*)even,
+                     (const double2*)odd, aos, *g, soa_cs);
+  return hipGetLastError();
+}
+
 hipError_t launch_gauge_check(const double2* aos, const Geom* g, double* out2, hipStream_t s) {
   // scratch after the two outputs: one (max, max) pair per workgroup
-  int gx = grid_for(g->V);
+  int gx = grid_for(g->Vfull);
   double* partial = out2 + 2;
   hipLaunchKernelGGL(k_gauge_check, dim3(gx), dim3(kBlock), 0, s, aos, *g, partial);
   hipError_t e = hipGetLastError();
@@ -465,7 +599,16 @@ hipError_t launch_axpy(int prec, int ncols, size_t n, const double* a_dev, doubl
 hipError_t launch_copy(int src_prec, int dst_prec, int ncols, size_t n, const void* x,
                        size_t x_cs, void* y, size_t y_cs, hipStream_t s, uint32_t mask) {
   dim3 grid(grid_for(n), ncols);
-  if (src_prec == kF64 && dst_prec == kF64)
+  if (src_prec == kF16 || dst_prec == kF16) {  // 16-bit storage: to and from FP64 only
+    if (src_prec == kF64 && dst_prec == kF16)
+      hipLaunchKernelGGL((k_copy<double2, f16x2>), grid, dim3(kBlock), 0, s, n, (const double2*)x,
+                         x_cs, (f16x2*)y, y_cs, mask);
+    else if (src_prec == kF16 && dst_prec == kF64)
+      hipLaunchKernelGGL((k_copy<f16x2, double2>), grid, dim3(kBlock), 0, s, n, (const f16x2*)x,
+                         x_cs, (double2*)y, y_cs, mask);
+    else
+      return hipErrorInvalidValue;
+  } else if (src_prec == kF64 && dst_prec == kF64)
     hipLaunchKernelGGL((k_copy<double2, double2>), grid, dim3(kBlock), 0, s, n, (const double2*)x,
                        x_cs, (double2*)y, y_cs, mask);
   else if (src_prec == kF64)

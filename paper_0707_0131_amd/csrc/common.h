@@ -12,6 +12,12 @@
 //    (column stride 12*vs complex);
 //  * links are 4 directions x 9 (full) or 6 (first two rows, third row
 //    rebuilt from unitarity) complex planes of vs sites.
+//
+// Odd-even geometry (Geom::eo = 1): vectors live on one parity of sites
+// ((x + y + z + t) even for the solver's fields); site s of parity p has
+// half index h = s / 2 (Lx even), V and vs count half sites, and the links
+// are two parity blocks of planes (even sites' links first), each link at
+// the half index of the site it starts from.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -43,10 +49,13 @@ struct FastDiv {
 
 struct Geom {
   int L[4];        // Lx, Ly, Lz, Lt
-  int V;           // sites
+  int V;           // sites of a vector (half of Vfull in the odd-even geometry)
   int vs;          // plane stride (sites, multiple of 64)
-  int stride[4];   // site-index step of a unit hop: 1, Lx, Lx*Ly, Lx*Ly*Lz
-  FastDiv dx, dy, dz;
+  int stride[4];   // lattice site-index step of a unit hop: 1, Lx, Lx*Ly, Lx*Ly*Lz
+  FastDiv dx, dy, dz;  // Lx, Ly, Lz
+  int eo;          // 1: odd-even geometry (vectors on one parity)
+  int Vfull;       // lattice sites
+  FastDiv dxh;     // Lx / 2 (odd-even geometry)
 };
 
 // Per right-hand-side solver state on the device.  Scalars of the CG
@@ -67,8 +76,8 @@ struct ColState {
   int max_iter;
   int state;        // ColRun / ColStopPending / ColStopped
   int reason;       // ReasonNone / Converged / MaxIter / Breakdown / Restart
-  int save_t0;      // iterations j whose t_j = A p_j is kept (eigCG arrow row,
-  int save_t1;      // Figure 3.1 steps 10.1 and 11.8); slot j & 1; 0 = none
+  int save_t0;      // iterations j whose t_j = A p_j is kept (the eigCG restart's
+  int save_t1;      // arrow row needs A r = t_J - beta_J t_{J-1}); slot j & 1; 0 = none
   int tperiod;      // after saving at save_t1 both advance by this (m - 2 nev)
   int pad_;
   double scale;     // 16-bit inner solves: the inner system is A e = scale r

@@ -10,6 +10,11 @@ hipError_t launch_stencil_f64(const StencilLaunch& L, hipStream_t s) {
 
 hipError_t launch_stencil(const StencilLaunch& L, hipStream_t s) {
   if (L.ncols <= 0 || L.ncols > kMaxCols) return hipErrorInvalidValue;
+  if (L.g->eo) {
+    if (L.prec == kF64) return launch_stencil_eo_f64(L, s);
+    if (L.prec == kF32) return launch_stencil_eo_f32(L, s);
+    return launch_stencil_eo_f16(L, s);
+  }
   if (L.prec == kF64) return launch_stencil_f64(L, s);
   if (L.prec == kF32) return launch_stencil_f32(L, s);
   return launch_stencil_f16(L, s);

@@ -9,11 +9,10 @@
 // of the column states (and of the alpha/beta history for eigCG) and an event,
 // and processes segment s while segment s+1 already runs.  eigCG restarts fall
 // on segment ends: the host builds the window matrix T from the history,
-// computes the restart coefficients in FP64 (steps 11.3-11.6), uploads QZ and
-// enqueues the MFMA product V <- V (QZ) (step 11.7) while the GPU keeps
-// iterating; the window is a ring of residual slots large enough for that lag.
-// The arrow row w^H V (step 11.8) uses t saved by the device on a schedule it
-// advances itself.
+// computes the restart coefficients in FP64 (eq. (2.3)), uploads QZ and
+// enqueues the MFMA product V <- V (QZ) while the GPU keeps iterating; the
+// window is a ring of residual slots large enough for that lag.  The arrow
+// row w^H V uses t saved by the device on a schedule it advances itself.
 #include "engine.h"
 
 #include <algorithm>
@@ -114,7 +113,7 @@ static void autotune_stencil(Ctx& c, int prec) {
     ncs = 0;
     return;
   }
-  const std::vector<int> key = {c.g.L[0], c.g.L[1], c.g.L[2], c.g.L[3], c.g.vs, prec,
+  const std::vector<int> key = {c.g.L[0], c.g.L[1], c.g.L[2], c.g.L[3], c.g.vs, c.g.eo, prec,
                                 prec == kF64 ? c.comp64 : c.comp32, c.P.max_batch};
   auto apply = [&](const Pick& pk) {
     for (int v = 1; v <= kStencilVariants; ++v) tms[v - 1] = pk.ms[v - 1];
@@ -145,7 +144,7 @@ static void autotune_stencil(Ctx& c, int prec) {
   pk.nc = 0;
   double best = 1e300;
   const int ncmax = (w.K >= 4 && prec != kF64) ? 4 : (w.K >= 2 ? 2 : 1);
-  for (int v = 1; v <= kStencilVariants; ++v) {
+  for (int v = c.g.eo ? 3 : 1; v <= kStencilVariants; ++v) {  // odd-even runs 1, 2 as 3
     for (int nc = 1; nc <= ncmax; nc *= 2) {
       if (v < 3 && nc > 1) break;
       StencilLaunch L1 = stencil_base(c, prec);
@@ -200,7 +199,11 @@ void ctx_init(Ctx& c, const eigcg_params& p, const void* gauge_dev, hipStream_t 
   c.check(hipGetDevice(&c.device), "hipGetDevice");
   Geom& g = c.g;
   for (int i = 0; i < 4; ++i) g.L[i] = p.dims[i];
-  g.V = p.dims[0] * p.dims[1] * p.dims[2] * p.dims[3];
+  g.Vfull = p.dims[0] * p.dims[1] * p.dims[2] * p.dims[3];
+  // odd-even preconditioning: the solver's vectors live on the even sites
+  g.eo = p.schur ? 1 : 0;
+  g.V = g.eo ? g.Vfull / 2 : g.Vfull;
+  g.dxh = FastDiv((uint32_t)std::max(1, p.dims[0] / 2));
   // plane stride: V rounded up to 64 sites, plus an odd number of 64-site
   // blocks by default so that the 12 spinor planes and the link planes of a
   // site start on different memory channels
@@ -240,15 +243,21 @@ void ctx_init(Ctx& c, const eigcg_params& p, const void* gauge_dev, hipStream_t 
   c.check(hipStreamSynchronize(s), "sync");
   const bool su3 = h2[0] < 1e-12 && h2[1] < 1e-12;
   c.comp64 = (p.compress_links && su3) ? 1 : 0;
-  c.u64 = c.dalloc((size_t)4 * (c.comp64 ? 6 : 9) * g.vs * 16);
+  const size_t link_blocks = g.eo ? 2 : 1;  // odd-even: one block of link planes per parity
+  c.u64 = c.dalloc(link_blocks * 4 * (c.comp64 ? 6 : 9) * g.vs * 16);
   c.check(launch_gauge_to_soa((const double2*)gauge_dev, c.u64, kF64, c.comp64, &g, s),
           "gauge to soa");
   if (p.precision != EIGCG_FP64) {  // inner links: FP32, or 16-bit for the half mode
     c.iprec = p.precision == EIGCG_MIXED_HALF ? kF16 : kF32;
     c.comp32 = (p.compress_links && h2[0] < 1e-6 && h2[1] < 1e-6) ? 1 : 0;
-    c.u32 = c.dalloc((size_t)4 * (c.comp32 ? 6 : 9) * g.vs * elem_bytes(c.iprec));
+    c.u32 = c.dalloc(link_blocks * 4 * (c.comp32 ? 6 : 9) * g.vs * elem_bytes(c.iprec));
     c.check(launch_gauge_to_soa((const double2*)gauge_dev, c.u32, c.iprec, c.comp32, &g, s),
             "gauge to soa inner");
+  }
+  if (g.eo) {  // odd-site intermediate of the two-pass Schur operator, per batch column
+    c.eo_tmp64 = c.dalloc((size_t)p.max_batch * c.cs * 16);
+    if (p.precision != EIGCG_FP64)
+      c.eo_tmp32 = c.dalloc((size_t)p.max_batch * c.cs * elem_bytes(c.iprec));
   }
   c.bank_prec = p.precision == EIGCG_FP64 ? kF64 : kF32;
   c.H.assign((size_t)p.max_bank * p.max_bank, cplx(0.0, 0.0));
@@ -276,6 +285,8 @@ void ctx_release(Ctx& c) {
   c.dfree(c.bwork64);
   c.dfree(c.u64);
   c.dfree(c.u32);
+  c.dfree(c.eo_tmp64);
+  c.dfree(c.eo_tmp32);
   void* v;
   v = c.d_st; c.dfree(v);
   v = c.d_hist; c.dfree(v);
@@ -389,6 +400,8 @@ static StencilLaunch stencil_base(Ctx& c, int prec) {
   L.u = prec == kF64 ? c.u64 : c.u32;
   L.g = &c.g;
   L.diag = 4.0 + c.P.mass;
+  L.eo_tmp = prec == kF64 ? c.eo_tmp64 : c.eo_tmp32;
+  L.eo_tmp_cs = c.cs;
   L.st = c.d_st;
   L.partial = c.d_partial;
   L.counter = c.d_counter;
@@ -429,6 +442,32 @@ static void true_residual(Ctx& c, int prec, int ncols, uint32_t mask, const void
 }
 
 void apply_op(Ctx& c, int op, int nrhs, const void* in_aos, void* out_aos) {
+  if (op >= 3) {  // the inner precision's kernels (input rounded to it, result widened)
+    if (c.P.precision == EIGCG_FP64) throw ApiError{EIGCG_EINVAL, "not a mixed-precision context"};
+    const int ip = c.iprec;
+    Workspace& w64 = c.ws64;
+    Workspace& w = c.ws32;
+    ws_ensure(c, w64, kF64, false);
+    ws_ensure(c, w, ip, false);
+    for (int c0 = 0; c0 < nrhs; c0 += w.K) {
+      const int k = std::min(w.K, nrhs - c0);
+      const uint32_t m = (k >= 32) ? 0xffffffffu : ((1u << k) - 1);
+      const double2* src = (const double2*)in_aos + (size_t)c0 * 12 * c.g.V;
+      double2* dst = (double2*)out_aos + (size_t)c0 * 12 * c.g.V;
+      c.check(launch_spinor_to_soa(src, w64.x, kF64, &c.g, k, c.cs, c.stream), "to soa");
+      c.check(launch_copy(kF64, ip, k, c.cs, w64.x, c.cs, w.p, c.cs, c.stream, m), "narrow");
+      if (op == EIGCG_OP_A + 3) {
+        stencil_store(c, ip, kOpM, k, w.p, w.tmp);
+        stencil_store(c, ip, kOpMdag, k, w.tmp, w.r);
+      } else {
+        stencil_store(c, ip, op == EIGCG_OP_M + 3 ? kOpM : kOpMdag, k, w.p, w.r);
+      }
+      c.check(launch_copy(ip, kF64, k, c.cs, w.r, c.cs, w64.r, c.cs, c.stream, m), "widen");
+      c.check(launch_spinor_from_soa(w64.r, dst, kF64, &c.g, k, c.cs, c.stream), "from soa");
+    }
+    c.check(hipStreamSynchronize(c.stream), "sync");
+    return;
+  }
   Workspace& w = c.ws64;
   ws_ensure(c, w, kF64, false);
   for (int c0 = 0; c0 < nrhs; c0 += w.K) {
@@ -443,6 +482,63 @@ void apply_op(Ctx& c, int op, int nrhs, const void* in_aos, void* out_aos) {
       stencil_store(c, kF64, op == EIGCG_OP_M ? kOpM : kOpMdag, k, w.x, w.r);
     }
     c.check(launch_spinor_from_soa(w.r, dst, kF64, &c.g, k, c.cs, c.stream), "from soa");
+  }
+  c.check(hipStreamSynchronize(c.stream), "sync");
+}
+
+// Odd-even preconditioning: maps between the full system M x = b and the
+// even-site system.  One raw pass: out (parity par) = dg in2 + ch D in.
+static void eo_pass(Ctx& c, int k, int par, const void* in, const void* in2, double dg, double ch,
+                    void* out) {
+  StencilLaunch L = stencil_base(c, kF64);
+  L.op = kOpM;
+  L.epi = kEpiStore;
+  L.in = in; L.in_cs = c.cs;
+  L.out = out; L.out_cs = c.cs;
+  L.ncols = k;
+  L.mask = (k >= 32) ? 0xffffffffu : ((1u << k) - 1);
+  L.eo_raw = 1;
+  L.eo_par = par;
+  L.in2 = in2; L.in2_cs = c.cs;
+  L.eo_dg = dg;
+  L.eo_ch = ch;
+  c.check(launch_stencil(L, c.stream), "odd-even pass");
+}
+
+// rhs = Mhat^H (b_e + D_eo b_o / (2 d)): the right-hand side of the
+// preconditioned normal equations for M x = b
+void schur_rhs(Ctx& c, int nrhs, const void* b_full, void* rhs) {
+  if (!c.g.eo) throw ApiError{EIGCG_EINVAL, "context is not odd-even preconditioned"};
+  Workspace& w = c.ws64;
+  ws_ensure(c, w, kF64, false);
+  const double d = 4.0 + c.P.mass;
+  for (int c0 = 0; c0 < nrhs; c0 += w.K) {
+    const int k = std::min(w.K, nrhs - c0);
+    const double2* src = (const double2*)b_full + (size_t)c0 * 12 * c.g.Vfull;
+    double2* dst = (double2*)rhs + (size_t)c0 * 12 * c.g.V;
+    c.check(launch_split_eo(src, w.b, w.p, &c.g, k, c.cs, c.stream), "split");
+    eo_pass(c, k, 0, w.p, w.b, 1.0, 0.5 / d, w.x);
+    stencil_store(c, kF64, kOpMdag, k, w.x, w.r);
+    c.check(launch_spinor_from_soa(w.r, dst, kF64, &c.g, k, c.cs, c.stream), "from soa");
+  }
+  c.check(hipStreamSynchronize(c.stream), "sync");
+}
+
+// x = (x_e, (b_o + D_oe x_e / 2) / d) on the full lattice
+void schur_reconstruct(Ctx& c, int nrhs, const void* b_full, const void* x_even, void* x_full) {
+  if (!c.g.eo) throw ApiError{EIGCG_EINVAL, "context is not odd-even preconditioned"};
+  Workspace& w = c.ws64;
+  ws_ensure(c, w, kF64, false);
+  const double d = 4.0 + c.P.mass;
+  for (int c0 = 0; c0 < nrhs; c0 += w.K) {
+    const int k = std::min(w.K, nrhs - c0);
+    const double2* bsrc = (const double2*)b_full + (size_t)c0 * 12 * c.g.Vfull;
+    const double2* xsrc = (const double2*)x_even + (size_t)c0 * 12 * c.g.V;
+    double2* dst = (double2*)x_full + (size_t)c0 * 12 * c.g.Vfull;
+    c.check(launch_split_eo(bsrc, w.b, w.p, &c.g, k, c.cs, c.stream), "split");
+    c.check(launch_spinor_to_soa(xsrc, w.x, kF64, &c.g, k, c.cs, c.stream), "to soa");
+    eo_pass(c, k, 1, w.x, w.p, 1.0 / d, 0.5 / d, w.r);
+    c.check(launch_merge_eo(w.x, w.r, dst, &c.g, k, c.cs, c.stream), "merge");
   }
   c.check(hipStreamSynchronize(c.stream), "sync");
 }
@@ -773,14 +869,14 @@ struct Run {
     }
   }
 
-  // Figure 3.1, steps 11.3-11.7 for one column whose window filled at E
+  // Figure 3.1 restart (eq. (2.3)) for one column whose window filled at E
   void do_restart(int col, int E) {
     EigCol& e = ec[col];
     if (e.has_vr) wait_arrow(col);
     std::vector<cplx> T;
     const int i = build_T(col, E, T, m);
     if (i != m) throw ApiError{EIGCG_EINVAL, "internal: window size mismatch at restart"};
-    // steps 11.3-11.6
+    // restart coefficients: Ritz vectors of T_m and T_{m-1}, orth, Rayleigh-Ritz
     std::vector<double> w1(m), w2(m);
     std::vector<cplx> Y((size_t)m * nev), Yb((size_t)m * nev, cplx(0.0, 0.0));
     if (hostla::herm_eig_lowest(m, T.data(), m, nev, w1.data(), Y.data(), m) != 0)
@@ -788,23 +884,23 @@ struct Run {
     c.amax = std::max(c.amax, w1[m - 1]);
     if (hostla::herm_eig_lowest(m - 1, T.data(), m, nev, w2.data(), Yb.data(), m) != 0)
       throw ApiError{EIGCG_EBREAKDOWN, "window eigensolver failed"};
-    for (int q = 0; q < nev; ++q) Yb[(size_t)q * m + (m - 1)] = 0.0;  // step 11.4
+    for (int q = 0; q < nev; ++q) Yb[(size_t)q * m + (m - 1)] = 0.0;  // pad Ybar
     std::vector<cplx> YY((size_t)m * 2 * nev);
     std::copy(Y.begin(), Y.end(), YY.begin());
     std::copy(Yb.begin(), Yb.end(), YY.begin() + (size_t)m * nev);
     std::vector<cplx> Q((size_t)m * 2 * nev);
-    hostla::qr_thin(m, 2 * nev, YY.data(), m, Q.data(), m, nullptr, 0);  // step 11.5
+    hostla::qr_thin(m, 2 * nev, YY.data(), m, Q.data(), m, nullptr, 0);  // orth([Y, Ybar])
     std::vector<cplx> TQ((size_t)m * 2 * nev), Hs((size_t)4 * nev * nev);
     hostla::matmul_sparse_a(m, 2 * nev, m, T.data(), m, Q.data(), m, TQ.data(), m);
     hostla::matmul_ah_b(2 * nev, 2 * nev, m, Q.data(), m, TQ.data(), m, Hs.data(), 2 * nev);
     std::vector<double> Mv(2 * nev);
     std::vector<cplx> Z((size_t)4 * nev * nev);
     if (hostla::herm_eig_lowest(2 * nev, Hs.data(), 2 * nev, 2 * nev, Mv.data(), Z.data(),
-                                2 * nev) != 0)  // step 11.6
+                                2 * nev) != 0)  // Q^H T_m Q = Z M Z^H
       throw ApiError{EIGCG_EBREAKDOWN, "restart eigensolver failed"};
     std::vector<cplx> QZ((size_t)m * 2 * nev);
     hostla::matmul_sparse_a(m, 2 * nev, 2 * nev, Q.data(), m, Z.data(), 2 * nev, QZ.data(), m);
-    // step 11.7: V <- V (QZ) on the device, in place over the restart block
+    // V <- V (QZ) on the device, in place over the restart block
     hipEvent_t ev = c.events[4 + col];
     c.check(hipEventSynchronize(ev), "qz slot wait");
     double2* hq = c.h_small + qz_off(col);
@@ -828,7 +924,7 @@ struct Run {
     e.restarts++;
   }
 
-  // step 11.8: w = t_J - beta_J t_{J-1}; arrow = V^H w (conj-transposed later)
+  // arrow row: w = t_J - beta_J t_{J-1} = A r; arrow = V^H w (conj-transposed later)
   void enqueue_arrow(int col) {
     EigCol& e = ec[col];
     const int J = e.arrow_J;
@@ -924,6 +1020,7 @@ struct Driver {
   int scheme;
   Workspace& w64;
   int seg, relf;
+  bool want_rel = false;  // a column waits for a reliable update
   bool pending = false;
   int pslot = 0, pend = 0, pid = 0, slot = 0;
 
@@ -972,6 +1069,12 @@ struct Driver {
       } else if (scheme == kSchemeRefine) {
         const double rel = restart_tol > 0 ? restart_tol : kRefineRel;
         S.inner_rel2 = rel * rel;
+      } else {
+        // reliable updates: a column whose recursive residual reaches the
+        // target waits for the next FP64 update (run at once), which decides
+        // convergence on the true residual; iterating on would take the
+        // inner recursion towards FP32 underflow
+        S.restart2 = t2;
       }
       if (R.eig) {
         S.save_t0 = R.m;
@@ -1052,10 +1155,15 @@ struct Driver {
   void reliable_update() {
     Ctx& cx = c();
     const uint32_t m = R.mask;
+    for (int j = 0; j < R.K; ++j)
+      if (((m >> j) & 1u) && !R.done[j]) R.outer[j]++;
     cx.check(launch_accum_f32_into_f64(R.K, cx.cs, w64.x, cx.cs, R.w.x, cx.cs, cx.stream, m), "accum");
     true_residual(cx, kF64, R.K, m, w64.x, w64.b, w64.r, w64.tmp);
     cx.check(launch_copy(kF64, kF32, R.K, cx.cs, w64.r, cx.cs, R.w.r, cx.cs, cx.stream, m), "copy");
     cx.check(launch_post_residual(cx.d_st, R.K, m, cx.stream), "post");
+    cx.check(launch_reliable_fix_p(kF32, R.K, m, cx.cs, R.w.r, R.w.p, cx.cs, cx.d_st, cx.d_partial,
+                                   cx.stream),
+             "fix p");
   }
 
   // init-CG restart (Section 5.3) of one FP64 column: deflate the current
@@ -1131,6 +1239,7 @@ struct Driver {
           R.reason[j] = ReasonConverged;
           continue;
         }
+        want_rel = true;  // kSchemeReliable
         continue;
       }
       R.done[j] = 1;
@@ -1141,6 +1250,10 @@ struct Driver {
 
   // plan, enqueue and poll one segment; process the previous one
   void step() {
+    if (want_rel) {  // between segments: every column's update is at an iteration boundary
+      reliable_update();
+      want_rel = false;
+    }
     int end = R.enq_iter + seg;
     if (R.eig)
       for (int j = 0; j < R.K; ++j)
@@ -1478,8 +1591,7 @@ int solve(Ctx& c, int nrhs, const void* b_aos, void* x_aos, double tol, int mode
         eigcg_stats& s = stats[c0 + j];
         s.iters = D.R.iters[j];
         s.restarts = eig ? D.R.ec[j].restarts : 0;
-        s.outer_steps = D.R.outer[j] +
-                        (scheme == kSchemeReliable ? D.R.iters[j] / std::max(1, c.P.reliable_every) : 0);
+        s.outer_steps = D.R.outer[j];
         s.status = stt;
         s.true_rel_res = res[j];
         s.seconds = dt;

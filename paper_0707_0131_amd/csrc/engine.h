@@ -58,6 +58,8 @@ struct Ctx {
   double tune_ms[2 * kStencilVariants] = {};  // FP64 then FP32, per variant
   void* u64 = nullptr;
   void* u32 = nullptr;
+  void* eo_tmp64 = nullptr;        // odd-even: odd-site intermediates (max_batch fields)
+  void* eo_tmp32 = nullptr;
   // bank (Section 4): U columns, H = U^H A U and its Cholesky factor
   int bank_prec = kF64;
   void* U = nullptr;
@@ -114,6 +116,8 @@ struct Ctx {
 void ctx_init(Ctx& c, const eigcg_params& p, const void* gauge_dev, hipStream_t s);
 void ctx_release(Ctx& c);
 void apply_op(Ctx& c, int op, int nrhs, const void* in_aos, void* out_aos);
+void schur_rhs(Ctx& c, int nrhs, const void* b_full, void* rhs);
+void schur_reconstruct(Ctx& c, int nrhs, const void* b_full, const void* x_even, void* x_full);
 int solve(Ctx& c, int nrhs, const void* b_aos, void* x_aos, double tol, int mode,
           eigcg_stats* stats);
 void deflate_init(Ctx& c, int nrhs, const void* b_aos, void* x_aos);

@@ -1,12 +1,12 @@
 // Complex tall-skinny products on the gfx950 matrix cores (MFMA 16x16x4).
 //
 //  * launch_gemm_tall:   Out(n x N) (+)= In(n x K) S(K x N)
-//      eigCG restart V <- V (QZ) (Figure 3.1, step 11.7), Ritz vectors V Y,
+//      eigCG restart V <- V (QZ) (Figure 3.1), Ritz vectors V Y,
 //      the init-CG lift X += U C (eq. (2.1)) and the Gram-Schmidt update
 //      Vbar -= U (U^H Vbar) of the Incremental eigCG bank (Section 4).
 //  * launch_gemm_reduce: G(K x N) = In(n x K)^H R(n x N)
 //      U^H R of init-CG, U^H Vbar / U^H W / Vbar^H W of the bank update and
-//      the arrow row w^H V (step 11.8).
+//      the arrow row w^H V of the restart.
 //
 // Complex arithmetic is embedded in real MFMA tiles.  For the tall product the
 // real K index interleaves (Re, Im) of each input column and the real output

@@ -1,6 +1,6 @@
 // Host FP64 dense linear algebra for the small matrices of eigCG.
 //
-// The eigCG restart (Figure 3.1, steps 11.3-11.6) needs the lowest nev
+// The eigCG restart (Figure 3.1, eq. (2.3)) needs the lowest nev
 // eigenpairs of the m x m window matrix T_m and of its leading (m-1) x (m-1)
 // block, a thin QR of the m x 2nev block [Y Ybar] and a full eigensolve of the
 // 2nev x 2nev projection H.  init-CG (eq. (2.1)) needs a Cholesky solve with

@@ -15,8 +15,8 @@ enum StencilOp { kOpM = 0, kOpMdag = 1 };
 // epilogues of the stencil launch
 enum StencilEpi {
   kEpiStore = 0,   // out = op(in)
-  kEpiNorm = 1,    // out = op(in); partials of ||out||^2 = p^H A p (CG step 1)
-  kEpiCGR = 2,     // alpha from step 1; t = op(in); r -= alpha t; r^H r; then a
+  kEpiNorm = 1,    // out = op(in); partials of ||out||^2 = p^H A p (first CG pass)
+  kEpiCGR = 2,     // alpha from the first pass; t = op(in); r -= alpha t; r^H r; then a
                    // finalize kernel updates alpha, beta and the stop tests
   kEpiRes = 3,     // r = b - op(in); r^H r -> rho (true residual, with finalize)
 };
@@ -58,8 +58,20 @@ struct StencilLaunch {
   double* hist; int hist_stride;    // kEpiCGR: per column 3 doubles per iteration
   hipEvent_t ev_start = nullptr;    // when set: timestamps of the stencil kernel's own
   hipEvent_t ev_stop = nullptr;     // start and end, taken by its dispatch
-  int nc = 0;                       // variants 3..9: columns per workgroup (1, 2, or 4
+  int nc = 0;                       // variants 3..10: columns per workgroup (1, 2, or 4
                                     // for FP32); 0 = widest that ncols allows
+  // Odd-even geometry (g->eo): op is the even-site Schur complement
+  // Mhat = diag - D_eo D_oe / (4 diag) or its adjoint (D: hopping sum of M
+  // or M^H), applied in two passes: t = D_oe in / (2 diag) into eo_tmp (odd
+  // sites, ncols fields), then diag in - D_eo t / 2 with the epilogue.
+  // Variants 1 and 2 run as 3.
+  void* eo_tmp = nullptr; size_t eo_tmp_cs = 0;
+  // eo_raw = 1: one pass only, out (parity eo_par) = eo_dg in2 + eo_ch D in,
+  // in on the other parity (in2 may be null: eo_dg ignored)
+  int eo_raw = 0;
+  int eo_par = 0;
+  const void* in2 = nullptr; size_t in2_cs = 0;
+  double eo_dg = 0.0, eo_ch = 0.0;
 };
 
 hipError_t launch_stencil(const StencilLaunch& L, hipStream_t s);
@@ -67,8 +79,11 @@ hipError_t launch_stencil(const StencilLaunch& L, hipStream_t s);
 hipError_t launch_stencil_f64(const StencilLaunch& L, hipStream_t s);
 hipError_t launch_stencil_f32(const StencilLaunch& L, hipStream_t s);
 hipError_t launch_stencil_f16(const StencilLaunch& L, hipStream_t s);
+hipError_t launch_stencil_eo_f64(const StencilLaunch& L, hipStream_t s);
+hipError_t launch_stencil_eo_f32(const StencilLaunch& L, hipStream_t s);
+hipError_t launch_stencil_eo_f16(const StencilLaunch& L, hipStream_t s);
 
-// CG step 3: x += alpha p; (running) p = r + beta p; optional window append
+// End of a CG iteration: x += alpha p; (running) p = r + beta p; optional window append
 // V_ring[(iter + 1) % ring] = r / sqrt(rho).
 struct UpdateLaunch {
   int prec;
@@ -91,6 +106,13 @@ hipError_t launch_cg_start(const UpdateLaunch& L, hipStream_t s);
 // Run, or stopped for a restart, decide converged (rho <= res_stop2) or
 // running again (with the refinement's next inner stop when inner_rel2 > 0).
 hipError_t launch_post_residual(ColState* st, int ncols, uint32_t mask, hipStream_t s);
+// After a reliable update (r = FP64 true residual, rho = r^H r in the states,
+// post_residual done): p <- p - (r^H p / rho - 1) r for running masked
+// columns, so that r^H p = r^H r as the next step length assumes (FP32 or
+// FP64 vectors; partial: 2 kMaxCols kMaxGrid doubles).
+hipError_t launch_reliable_fix_p(int prec, int ncols, uint32_t mask, size_t n, const void* r,
+                                 void* p, size_t cs, const ColState* st, double* partial,
+                                 hipStream_t s);
 // Set state/reason of masked columns (host-driven transitions).
 hipError_t launch_set_state(ColState* st, int ncols, uint32_t mask, int state, int reason,
                             int clear_restart, hipStream_t s);
@@ -101,11 +123,18 @@ hipError_t launch_spinor_to_soa(const double2* aos, void* soa, int prec, const G
                                 size_t soa_cs, hipStream_t s);
 hipError_t launch_spinor_from_soa(const void* soa, double2* aos, int prec, const Geom* g,
                                   int ncols, size_t soa_cs, hipStream_t s);
-// gauge AoS [site][mu][a][b] -> SoA planes (full 9 or compressed 6 per mu)
+// gauge AoS [site][mu][a][b] -> SoA planes (full 9 or compressed 6 per mu;
+// parity blocks in the odd-even geometry)
 hipError_t launch_gauge_to_soa(const double2* aos, void* soa, int prec, int compressed,
                                const Geom* g, hipStream_t s);
 // max over links of |U U^H - 1| and |det U - 1| (unitarity check), one double each
 hipError_t launch_gauge_check(const double2* aos, const Geom* g, double* out2, hipStream_t s);
+// Odd-even geometry, FP64: full-lattice AoS fields <-> their even and odd
+// half-site SoA fields (ncols columns; soa_cs per half field)
+hipError_t launch_split_eo(const double2* aos, void* even, void* odd, const Geom* g, int ncols,
+                           size_t soa_cs, hipStream_t s);
+hipError_t launch_merge_eo(const void* even, const void* odd, double2* aos, const Geom* g,
+                           int ncols, size_t soa_cs, hipStream_t s);
 
 // Generic BLAS1 over n complex entries per column (FP64 or FP32 storage).
 // y = a*x + y with per-column complex a (device array of 2*ncols doubles or

@@ -42,6 +42,12 @@ struct DevArgs {
   void* tbuf; size_t t_cs;
   double* hist; int hist_stride;
   uint32_t ord_P, ord_Ls;   // slab sweep: 64-site tiles per xy-plane, t-slices per XCD
+  // odd-even geometry: output parity, the other parity's link block, and
+  // out = dg in2 + ch (hopping sum of in) at the centre (in2 may be null)
+  uint32_t par;
+  const void* u2;
+  const void* in2; size_t in2_cs;
+  double dg, ch;
 };
 
 // Work units (blocks of sites) handed to workgroups.  With xcd set, the
@@ -178,7 +184,7 @@ __global__ __launch_bounds__(kBlock) void k_wilson(DevArgs a) {
   if (threadIdx.x == 0) a.partial[(size_t)col * gridDim.x + blockIdx.x] = (double)bs;
 }
 
-// Variants 3..9: a unit is two 64-site tiles; each tile is handled by a pair
+// Variants 3..10: a unit is two 64-site tiles; each tile is handled by a pair
 // of waves, the even wave doing directions x and y, the odd wave z and t.
 // They swap half of their partial sums through LDS and each finishes six of
 // the twelve output components, so per-thread state is half of variant 1's
@@ -186,7 +192,10 @@ __global__ __launch_bounds__(kBlock) void k_wilson(DevArgs a) {
 // (right-hand sides blockIdx.y NC .. + NC - 1): every link is loaded once per
 // site and applied to all of them, and each column's arithmetic and
 // reduction order are those of NC = 1, so results do not depend on NC.
-template <typename VS, typename LS, bool COMP, bool DAG, int EPI, bool NT, int ORD, int NC>
+// EO: odd-even geometry, one pass of the Schur complement (sites of parity
+// a.par, neighbours read from the other parity's half field).
+template <typename VS, typename LS, bool COMP, bool DAG, int EPI, bool NT, int ORD, int NC,
+          bool EO = false>
 __global__ __launch_bounds__(kBlock) void k_wilson_pair(DevArgs a) {
   using R = typename Storage<VS>::real;
   __shared__ double lds4[kBlock / 64];
@@ -209,6 +218,9 @@ __global__ __launch_bounds__(kBlock) void k_wilson_pair(DevArgs a) {
   }
   const VS* in = reinterpret_cast<const VS*>(a.in) + (size_t)col0 * a.in_cs;
   const LS* u = reinterpret_cast<const LS*>(a.u);
+  const LS* u2 = reinterpret_cast<const LS*>(a.u2);
+  const VS* in2 = EO && a.in2 ? reinterpret_cast<const VS*>(a.in2) + (size_t)col0 * a.in2_cs
+                              : nullptr;
   const size_t vs = (size_t)a.g.vs;
   const int tile = threadIdx.x >> 7;
   const int odd = (threadIdx.x >> 6) & 1;
@@ -225,13 +237,15 @@ __global__ __launch_bounds__(kBlock) void k_wilson_pair(DevArgs a) {
         for (int e = 0; e < 12; ++e) acc[c][e] = {R(0), R(0)};
       if (valid) {
         uint32_t coord[4];
-        site_coords(a.g, s, coord);
+        uint32_t sl = s;  // lattice site
+        if (EO) sl = eo_site_coords(a.g, s, a.par, coord);
+        else site_coords(a.g, s, coord);
         if (!odd) {
-          hop_dir_n<0, VS, LS, COMP, DAG ? 1 : -1, NC>(in, a.in_cs, act, u, a.g, s, coord, acc);
-          hop_dir_n<1, VS, LS, COMP, DAG ? 1 : -1, NC>(in, a.in_cs, act, u, a.g, s, coord, acc);
+          hop_dir_n<0, VS, LS, COMP, DAG ? 1 : -1, NC, EO>(in, a.in_cs, act, u, u2, a.g, sl, coord, acc);
+          hop_dir_n<1, VS, LS, COMP, DAG ? 1 : -1, NC, EO>(in, a.in_cs, act, u, u2, a.g, sl, coord, acc);
         } else {
-          hop_dir_n<2, VS, LS, COMP, DAG ? 1 : -1, NC>(in, a.in_cs, act, u, a.g, s, coord, acc);
-          hop_dir_n<3, VS, LS, COMP, DAG ? 1 : -1, NC>(in, a.in_cs, act, u, a.g, s, coord, acc);
+          hop_dir_n<2, VS, LS, COMP, DAG ? 1 : -1, NC, EO>(in, a.in_cs, act, u, u2, a.g, sl, coord, acc);
+          hop_dir_n<3, VS, LS, COMP, DAG ? 1 : -1, NC, EO>(in, a.in_cs, act, u, u2, a.g, sl, coord, acc);
         }
       }
       // hand the partner the half it finishes: even keeps 0..5, odd keeps 6..11
@@ -246,19 +260,22 @@ __global__ __launch_bounds__(kBlock) void k_wilson_pair(DevArgs a) {
         }
       }
       __syncthreads();
-      const R d = (R)a.diag;
+      const R d = EO ? (R)a.dg : (R)a.diag;
+      const R ch = (R)a.ch;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         if (!((act >> c) & 1u)) continue;
-        const VS* ic = in + (size_t)c * a.in_cs;
+        const VS* ic = EO ? (in2 ? in2 + (size_t)c * a.in2_cs : nullptr) : in + (size_t)c * a.in_cs;
+        const bool ld_c = valid && (!EO || ic != nullptr);
         cpx<R> o[12];
         if (!odd) {
 #pragma unroll
           for (int e = 0; e < 6; ++e) {
             const cpx<R> p = xbuf[tile][1][c][e][lane];
-            cpx<R> v = valid ? Storage<VS>::ld(ic, (size_t)e * vs + s) : cpx<R>{R(0), R(0)};
+            cpx<R> v = ld_c ? Storage<VS>::ld(ic, (size_t)e * vs + s) : cpx<R>{R(0), R(0)};
             const R hr = acc[c][e].re + p.re, hi = acc[c][e].im + p.im;
-            o[e] = {d * v.re - R(0.5) * hr, d * v.im - R(0.5) * hi};
+            if constexpr (EO) o[e] = {d * v.re + ch * hr, d * v.im + ch * hi};
+            else o[e] = {d * v.re - R(0.5) * hr, d * v.im - R(0.5) * hi};
           }
           if (valid)
             epilogue<VS, EPI, 0, 6, NT>(a, col0 + c, s, o, alpha[c], save_t[c], save_slot[c],
@@ -267,9 +284,10 @@ __global__ __launch_bounds__(kBlock) void k_wilson_pair(DevArgs a) {
 #pragma unroll
           for (int e = 6; e < 12; ++e) {
             const cpx<R> p = xbuf[tile][0][c][e - 6][lane];
-            cpx<R> v = valid ? Storage<VS>::ld(ic, (size_t)e * vs + s) : cpx<R>{R(0), R(0)};
+            cpx<R> v = ld_c ? Storage<VS>::ld(ic, (size_t)e * vs + s) : cpx<R>{R(0), R(0)};
             const R hr = p.re + acc[c][e].re, hi = p.im + acc[c][e].im;
-            o[e] = {d * v.re - R(0.5) * hr, d * v.im - R(0.5) * hi};
+            if constexpr (EO) o[e] = {d * v.re + ch * hr, d * v.im + ch * hi};
+            else o[e] = {d * v.re - R(0.5) * hr, d * v.im - R(0.5) * hi};
           }
           if (valid)
             epilogue<VS, EPI, 6, 6, NT>(a, col0 + c, s, o, alpha[c], save_t[c], save_slot[c],
@@ -389,7 +407,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize_res(ColState* st, int ncols
 // neighbours stay in the L2 until their second use); 0 leaves the natural
 // occupancy.  Returns the dynamic LDS bytes to request and sets the number of
 // workgroups resident on the whole device (a multiple of 8).
-template <typename VS, typename LS>
+template <typename VS, typename LS, bool EO>
 size_t pair_occupancy(int per_cu, int* resident) {
   struct Info { size_t lds; int resident; };
   static Info cache[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
@@ -397,7 +415,7 @@ size_t pair_occupancy(int per_cu, int* resident) {
   std::lock_guard<std::mutex> lk(mu);
   Info& I = cache[per_cu & 3];
   if (I.resident == 0) {
-    auto kern = k_wilson_pair<VS, LS, true, false, kEpiCGR, true, 0, 1>;
+    auto kern = k_wilson_pair<VS, LS, true, false, kEpiCGR, true, 0, 1, EO>;
     int dev = 0, cus = 0, lds_cu = 0, lds_wg = 0, per = 0;
     hipFuncAttributes fa{};
     size_t extra = 0;
@@ -424,12 +442,27 @@ size_t pair_occupancy(int per_cu, int* resident) {
   return I.lds;
 }
 
-template <typename VS, typename LS>
+// One stencil pass.  EO: one pass of the odd-even operator with the output
+// parity, second input and coefficients of L's eo_* fields.
+template <typename VS, typename LS, bool EO = false>
 hipError_t launch_typed(const StencilLaunch& L, hipStream_t s) {
   constexpr int NC4 = sizeof(typename Storage<VS>::real) == 4 ? 4 : 2;
+  if ((L.g->eo != 0) != EO) return hipErrorInvalidValue;
   DevArgs a;
   a.in = L.in; a.in_cs = L.in_cs; a.out = L.out; a.out_cs = L.out_cs; a.u = L.u; a.g = *L.g;
   a.diag = L.diag; a.ncols = L.ncols; a.mask = L.mask; a.st = L.st;
+  a.par = 0; a.u2 = nullptr; a.in2 = nullptr; a.in2_cs = 0; a.dg = 0.0; a.ch = -0.5;
+  if (EO) {
+    // link parity blocks: 4 directions x (6 or 9) planes each
+    const size_t blk = (size_t)4 * (L.compressed ? 6 : 9) * L.g->vs;
+    const LS* ub = reinterpret_cast<const LS*>(L.u);
+    a.par = (uint32_t)(L.eo_par & 1);
+    a.u = ub + (a.par ? blk : 0);
+    a.u2 = ub + (a.par ? 0 : blk);
+    a.in2 = L.in2; a.in2_cs = L.in2_cs;
+    a.dg = L.in2 ? L.eo_dg : 0.0;
+    a.ch = L.eo_ch;
+  }
   // first pass (kEpiNorm) writes partial slot A, second pass (kEpiCGR, kEpiRes) slot B
   double* part_a = L.partial;
   double* part_b = L.partial + (size_t)kMaxCols * kMaxGrid;
@@ -441,12 +474,13 @@ hipError_t launch_typed(const StencilLaunch& L, hipStream_t s) {
   // two-row links: other variants run as 5, uncompressed links are refused
   constexpr bool kHalf = std::is_same<VS, f16x2>::value;
   int variant = L.variant <= 0 ? 1 : L.variant;
+  if (EO && variant < 3) variant = 3;  // the odd-even passes use the two-tile kernels
   if (kHalf) {
     if (!L.compressed) return hipErrorInvalidValue;
     if (variant < 5) variant = 5;
     if (variant == 10) variant = 9;
   }
-  const uint32_t plane = (uint32_t)(L.g->L[0] * L.g->L[1]);
+  const uint32_t plane = (uint32_t)(L.g->L[0] * L.g->L[1]) >> (EO ? 1 : 0);
   if (variant >= 8 && (plane % 64u != 0 || L.g->L[3] % 8 != 0))
     variant = variant == 8 ? 5 : 6;  // the slab sweep needs whole tiles per plane, 8 slabs
   a.ord_P = plane / 64u;
@@ -462,7 +496,7 @@ hipError_t launch_typed(const StencilLaunch& L, hipStream_t s) {
     // XCD's workgroups sweep one contiguous front of its chunk
     int res = 0;
     const int per_cu = (variant == 6 || variant >= 9) ? 2 : variant == 7 ? 1 : 0;
-    dyn_lds = pair_occupancy<VS, LS>(per_cu, &res);
+    dyn_lds = pair_occupancy<VS, LS, EO>(per_cu, &res);
     gx = (int)std::min<uint32_t>((T + 7u) & ~7u, (uint32_t)res);
   } else {
     gx = (int)std::min<uint32_t>((T + 7u) & ~7u, kMaxGrid);  // a multiple of 8 (XCDs)
@@ -483,11 +517,11 @@ hipError_t launch_typed(const StencilLaunch& L, hipStream_t s) {
   hipExtLaunchKernelGGL(KERNEL, grid, block, LDS, s, L.ev_start, L.ev_stop, 0, a);
 #define EIGCG_PAIR(COMP, DAG, EPI, NT, ORD)                                           \
   if (nc == 4) {                                                                     \
-    EIGCG_LAUNCH((k_wilson_pair<VS, LS, COMP, DAG, EPI, NT, ORD, NC4>), dyn_lds)     \
+    EIGCG_LAUNCH((k_wilson_pair<VS, LS, COMP, DAG, EPI, NT, ORD, NC4, EO>), dyn_lds) \
   } else if (nc == 2) {                                                              \
-    EIGCG_LAUNCH((k_wilson_pair<VS, LS, COMP, DAG, EPI, NT, ORD, 2>), dyn_lds)       \
+    EIGCG_LAUNCH((k_wilson_pair<VS, LS, COMP, DAG, EPI, NT, ORD, 2, EO>), dyn_lds)   \
   } else {                                                                           \
-    EIGCG_LAUNCH((k_wilson_pair<VS, LS, COMP, DAG, EPI, NT, ORD, 1>), dyn_lds)       \
+    EIGCG_LAUNCH((k_wilson_pair<VS, LS, COMP, DAG, EPI, NT, ORD, 1, EO>), dyn_lds)   \
   }
 #define EIGCG_K(COMP, DAG, EPI)                                                      \
   if (variant == 10) {                                                               \
@@ -498,10 +532,12 @@ hipError_t launch_typed(const StencilLaunch& L, hipStream_t s) {
     EIGCG_PAIR(COMP, DAG, EPI, true, 0)                                              \
   } else if (variant == 3) {                                                         \
     EIGCG_PAIR(COMP, DAG, EPI, false, 0)                                             \
-  } else if (variant == 2) {                                                         \
-    EIGCG_LAUNCH((k_wilson<VS, LS, COMP, DAG, EPI, true>), 0)                        \
-  } else {                                                                           \
-    EIGCG_LAUNCH((k_wilson<VS, LS, COMP, DAG, EPI, false>), 0)                       \
+  } else if constexpr (!EO) {                                                        \
+    if (variant == 2) {                                                              \
+      EIGCG_LAUNCH((k_wilson<VS, LS, COMP, DAG, EPI, true>), 0)                      \
+    } else {                                                                         \
+      EIGCG_LAUNCH((k_wilson<VS, LS, COMP, DAG, EPI, false>), 0)                     \
+    }                                                                                \
   }
 #define EIGCG_EPI(COMP, DAG)                                  \
   switch (L.epi) {                                            \
@@ -548,6 +584,33 @@ hipError_t launch_typed(const StencilLaunch& L, hipStream_t s) {
     hipLaunchKernelGGL(k_finalize_res, dim3(L.ncols), dim3(kBlock), 0, s, L.st, L.ncols, L.mask, part_b,
                        gx);
   return hipGetLastError();
+}
+
+// Odd-even operator: Mhat (or Mhat^H) = diag - D_eo D_oe / (4 diag) as two
+// passes through L.eo_tmp, the epilogue on the second; or one raw pass.
+// Sampling events bracket both passes.
+template <typename VS, typename LS>
+hipError_t launch_eo(const StencilLaunch& L, hipStream_t s) {
+  if (L.eo_raw) return launch_typed<VS, LS, true>(L, s);
+  if (!L.eo_tmp) return hipErrorInvalidValue;
+  StencilLaunch A = L;  // t = D_oe in / (2 diag) on the odd sites
+  A.epi = kEpiStore;
+  A.out = L.eo_tmp; A.out_cs = L.eo_tmp_cs;
+  A.eo_par = 1;
+  A.in2 = nullptr; A.in2_cs = 0;
+  A.eo_dg = 0.0;
+  A.eo_ch = 0.5 / L.diag;
+  A.ev_stop = nullptr;
+  StencilLaunch B = L;  // diag in - D_eo t / 2 on the even sites, with L's epilogue
+  B.in = L.eo_tmp; B.in_cs = L.eo_tmp_cs;
+  B.eo_par = 0;
+  B.in2 = L.in; B.in2_cs = L.in_cs;
+  B.eo_dg = L.diag;
+  B.eo_ch = -0.5;
+  B.ev_start = nullptr;
+  hipError_t e = launch_typed<VS, LS, true>(A, s);
+  if (e != hipSuccess) return e;
+  return launch_typed<VS, LS, true>(B, s);
 }
 
 }  // namespace

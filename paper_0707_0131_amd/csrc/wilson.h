@@ -81,6 +81,20 @@ __device__ __forceinline__ void site_coords(const Geom& g, uint32_t s, uint32_t*
   coord[2] = zt - coord[3] * (uint32_t)g.L[2];
 }
 
+// Odd-even geometry: coordinates and lattice site index of half-lattice
+// site h of parity par (x = 2 (h mod Lx/2) + (y + z + t + par) mod 2).
+__device__ __forceinline__ uint32_t eo_site_coords(const Geom& g, uint32_t h, uint32_t par,
+                                                   uint32_t* coord) {
+  const uint32_t row = g.dxh.div(h);
+  const uint32_t xh = h - row * (uint32_t)(g.L[0] >> 1);
+  const uint32_t zt = g.dy.div(row);
+  coord[1] = row - zt * (uint32_t)g.L[1];
+  coord[3] = g.dz.div(zt);
+  coord[2] = zt - coord[3] * (uint32_t)g.L[2];
+  coord[0] = 2u * xh + ((coord[1] + coord[2] + coord[3] + par) & 1u);
+  return row * (uint32_t)g.L[0] + coord[0];
+}
+
 // Both hops of direction MU for one site, accumulated into acc:
 // acc += (1 + sf g_mu) U_mu(x) psi(x+mu) + (1 - sf g_mu) U_mu(x-mu)^+ psi(x-mu),
 // sf = -1 for M, +1 for M^H.
@@ -146,21 +160,25 @@ __device__ __forceinline__ void hop_dir(const VS* __restrict__ in, const LS* __r
 // hop_dir for NC right-hand sides at once: each link is loaded (and its third
 // row rebuilt) once and applied to the NC columns in == in0 + c in_cs whose
 // bit is set in act.  Per column the arithmetic is exactly hop_dir's.
-template <int MU, typename VS, typename LS, bool COMP, int SF, int NC>
+// EO: odd-even geometry; s is the lattice site, in holds the other parity's
+// half sites, u this parity's link block and u2 the other parity's.
+template <int MU, typename VS, typename LS, bool COMP, int SF, int NC, bool EO = false>
 __device__ __forceinline__ void hop_dir_n(const VS* __restrict__ in, size_t in_cs, uint32_t act,
-                                          const LS* __restrict__ u, const Geom& g, uint32_t s,
-                                          const uint32_t* coord,
+                                          const LS* __restrict__ u, const LS* __restrict__ u2,
+                                          const Geom& g, uint32_t s, const uint32_t* coord,
                                           cpx<typename Storage<VS>::real> (*acc)[12]) {
   using R = typename Storage<VS>::real;
   const size_t vs = (size_t)g.vs;
   const uint32_t c_ = coord[MU];
   const uint32_t st_ = (uint32_t)g.stride[MU];
   const uint32_t span_ = (uint32_t)(g.L[MU] - 1) * st_;
-  const uint32_t sf_ = (c_ + 1 < (uint32_t)g.L[MU]) ? s + st_ : s - span_;
-  const uint32_t sb_ = (c_ > 0) ? s - st_ : s + span_;
+  const uint32_t sf_ = EO ? ((c_ + 1 < (uint32_t)g.L[MU]) ? s + st_ : s - span_) >> 1
+                          : ((c_ + 1 < (uint32_t)g.L[MU]) ? s + st_ : s - span_);
+  const uint32_t sb_ = EO ? ((c_ > 0) ? s - st_ : s + span_) >> 1
+                          : ((c_ > 0) ? s - st_ : s + span_);
   {
     cpx<R> U[9];
-    load_link<LS, COMP>(u, MU, vs, s, U);
+    load_link<LS, COMP>(u, MU, vs, EO ? s >> 1 : s, U);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       if (!((act >> c) & 1u)) continue;
@@ -188,7 +206,7 @@ __device__ __forceinline__ void hop_dir_n(const VS* __restrict__ in, size_t in_c
   }
   {
     cpx<R> U[9];
-    load_link<LS, COMP>(u, MU, vs, sb_, U);
+    load_link<LS, COMP>(EO ? u2 : u, MU, vs, sb_, U);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       if (!((act >> c) & 1u)) continue;

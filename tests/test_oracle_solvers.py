@@ -65,7 +65,7 @@ def test_eigcg_x_identical_to_cg(cfg0_op, cfg0_rhs):
 
 
 def test_window_T_equals_VhAV_before_restart(cfg0_op, cfg0_dense, cfg0_rhs):
-    """eq. (3.1) with the negative off-diagonal (step 11.10): T = V^H A V for
+    """eq. (3.1) with the negative off-diagonal (as Figure 3.1 updates T): T = V^H A V for
     V = normalised residuals, while orthogonality holds."""
     A = cfg0_dense["A"]
     _, _, _, info = eigcg(cfg0_op.A, cfg0_rhs, 2, 60, tol=1e-14, max_iter=25, record=True)
@@ -102,7 +102,7 @@ def test_lanczos_residual_identity(cfg0_op, cfg0_dense, cfg0_rhs):
 
 
 def test_restart_invariants(cfg0_op, cfg0_dense, cfg0_rhs):
-    """Restart (steps 11.3-11.8): span Q contains Y, so the lowest nev
+    """Restart (Figure 3.1, eq. (2.3)): span Q contains Y, so the lowest nev
     eigenvalues of H equal those of T_m; the arrow row equals its closed form
     (-sqrt(beta_j)/alpha_{j-1}) (QZ)_{m,:} in exact arithmetic; afterwards
     V^H V = I and V^H A V = T."""
