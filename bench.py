@@ -103,6 +103,99 @@ def plain_cg(B, torch, g, mass, bt, xt, n):
     return dt, [s["iters"] for s in st], max(s["true_rel_res"] for s in st)
 
 
+SCHUR_MASS = -0.58
+
+
+def schur_leg(B, torch, g, bt, n_plain=4, n_eig=N_EIG, n_defl=N_DEFL):
+    """Odd-even (Schur complement) preconditioning on the bench lattice: M x = b
+    for the same right-hand sides through the full normal equations
+    (M^H M x = M^H b) and through the even-site system (Mhat^H Mhat x_e =
+    Mhat^H bhat, then x_o), plain FP64 CG both ways, then the deflated
+    workload (Incremental eigCG on n_eig, init-CG on n_defl) on the even-site
+    system.  Every timing includes the maps between the two systems."""
+    log(f"odd-even leg (mass {SCHUR_MASS})")
+    mass = SCHUR_MASS
+    nh = bt[0].numel() // 12 // 2
+    full = B.eigcg_create(B.eigcg_default_params(dims=LATTICE, mass=mass, max_iter=40000,
+                                                 check_every=32), g)
+    out = {"mass": mass}
+    try:
+        b = bt[:n_plain]
+        xf = torch.zeros_like(b)
+        mb = torch.empty_like(b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B.eigcg_apply(full, B.EIGCG_OP_MDAG, b, mb)
+        rc, st = B.eigcg_solve(full, mb, xf, TOL, B.EIGCG_MODE_CG)
+        torch.cuda.synchronize()
+        dt_full = time.perf_counter() - t0
+        out["plain_full_cg"] = {"s_per_rhs": dt_full / n_plain, "iters": [s["iters"] for s in st]}
+        sch = B.eigcg_create(B.eigcg_default_params(dims=LATTICE, mass=mass, max_iter=40000,
+                                                    check_every=32, schur=1), g)
+        try:
+            rhs = torch.empty((n_plain, nh, 4, 3), dtype=torch.complex128, device="cuda:0")
+            xe = torch.zeros_like(rhs)
+            xs = torch.empty_like(b)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            B.eigcg_schur_rhs(sch, b, rhs)
+            rc, st = B.eigcg_solve(sch, rhs, xe, TOL, B.EIGCG_MODE_CG)
+            B.eigcg_schur_reconstruct(sch, b, xe, xs)
+            torch.cuda.synchronize()
+            dt_s = time.perf_counter() - t0
+        finally:
+            B.eigcg_destroy(sch)
+        # both solutions of M x = b: residual with the full operator, and their difference
+        mx = torch.empty_like(b)
+        B.eigcg_apply(full, B.EIGCG_OP_M, xs, mx)
+        res_m = max(float(torch.linalg.vector_norm(mx[i] - b[i]) / torch.linalg.vector_norm(b[i]))
+                    for i in range(n_plain))
+        dx = max(float(torch.linalg.vector_norm(xs[i] - xf[i]) / torch.linalg.vector_norm(xf[i]))
+                 for i in range(n_plain))
+        out["plain_schur_cg"] = {"s_per_rhs": dt_s / n_plain, "iters": [s["iters"] for s in st],
+                                 "max_true_rel_res": max(s["true_rel_res"] for s in st),
+                                 "max_M_rel_res": res_m, "max_rel_diff_vs_full": dx}
+        out["plain_speedup"] = dt_full / dt_s
+        del mx, mb, xf, xs, rhs, xe
+    finally:
+        B.eigcg_destroy(full)
+    # deflated workload on the even-site system
+    sch = B.eigcg_create(B.eigcg_default_params(dims=LATTICE, mass=mass, nev=NEV, m=M,
+                                                max_bank=NBANK, max_iter=40000, check_every=16,
+                                                schur=1), g)
+    try:
+        n = n_eig + n_defl
+        rhs = torch.empty((n, nh, 4, 3), dtype=torch.complex128, device="cuda:0")
+        xe = torch.zeros_like(rhs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B.eigcg_schur_rhs(sch, bt[:n], rhs)
+        rc1, st1 = B.eigcg_solve(sch, rhs[:n_eig], xe[:n_eig], TOL, B.EIGCG_MODE_EIGCG)
+        rc2, st2 = B.eigcg_solve(sch, rhs[n_eig:], xe[n_eig:], TOL, B.EIGCG_MODE_INITCG)
+        xs = torch.empty_like(bt[:1])
+        for i in range(n):  # reconstruction of every solution, one at a time (memory)
+            B.eigcg_schur_reconstruct(sch, bt[i:i + 1], xe[i:i + 1], xs)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        vals, _ = B.eigcg_bank_info(sch)
+    finally:
+        B.eigcg_destroy(sch)
+    allst = st1 + st2
+    out["deflated_schur"] = {
+        "rhs_per_s": n / dt,
+        "wall_s": dt,
+        "phase1_iters": [s["iters"] for s in st1],
+        "phase2_mean_iters": sum(s["iters"] for s in st2) / max(1, len(st2)),
+        "bank": int(len(vals)),
+        "max_true_rel_res": max(s["true_rel_res"] for s in allst),
+        "failed": sum(1 for s in allst if s["status"] != 0 or s["true_rel_res"] > TOL),
+    }
+    out["deflated_schur_speedup_vs_plain_full_cg"] = (n / dt) * out["plain_full_cg"]["s_per_rhs"]
+    log(f"odd-even: plain full {out['plain_full_cg']['s_per_rhs']:.3f} s/RHS, plain Schur "
+        f"{out['plain_schur_cg']['s_per_rhs']:.3f} s/RHS, deflated Schur {n / dt:.1f} RHS/s")
+    return out
+
+
 def source_hash():
     import hashlib
     h = hashlib.sha256()
@@ -495,6 +588,7 @@ def main():
     ap.add_argument("--no-batching", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-large", action="store_true", help="skip the 32^3x64 half-precision leg")
+    ap.add_argument("--no-schur", action="store_true", help="skip the odd-even preconditioning leg")
     ap.add_argument("--serve-bank-rhs", type=int, default=N_EIG)
     ap.add_argument("--serve-requests", type=int, default=120)
     ap.add_argument("--stencil-variant", type=int, default=0,
@@ -576,6 +670,10 @@ def main():
     batching = None
     if not args.no_batching:
         batching = batching_leg(B, torch, g, bt)
+
+    odd_even = None
+    if not args.no_schur:
+        odd_even = schur_leg(B, torch, g, bt, n_eig=n_eig, n_defl=n_defl)
 
     roof_small = roof_hbm = None
     if not args.no_roofline:
@@ -660,6 +758,7 @@ def main():
         "stencil_pass1": {"launch_ms": pass1_ms, "GBs": pass1_bytes / pass1_ms / 1e6 if n_s else None,
                           "algorithmic_bytes_per_launch": pass1_bytes},
         "batching": batching,
+        "odd_even": odd_even,
         "serving": serving,
         "large_lattice": large,
         "stencil_bench_lattice": roof_small,

@@ -133,3 +133,43 @@ def test_fullsize_batched_mixed_precision(B, field, precision):
             assert _true_rel_res(op, bs[i], xs[i]) <= 1.01e-10
     finally:
         B.eigcg_destroy(ctx)
+
+
+def test_fullsize_schur_stencil_and_solve(B, field):
+    """Odd-even preconditioning at full size (the bench's odd-even leg):
+    Mhat, Mhat^H element-wise against the oracle, then M x = b through the
+    even-site system (rhs, CG, reconstruction) checked with the oracle's full
+    M and its Ahat."""
+    from oracle.schur import SchurOperator
+    from synthetic import gaussian_half_rhs
+    U, op = field
+    sop = SchurOperator(U, MASS)
+    ctx, _ = make_ctx(U, MASS, max_iter=20000, check_every=32, schur=1)
+    try:
+        psi = gaussian_half_rhs(DIMS, 4343)[None]
+        out = dev(np.zeros_like(psi))
+        for code, fn in [(B.EIGCG_OP_M, sop.Mhat), (B.EIGCG_OP_MDAG, sop.Mhat_dag)]:
+            B.eigcg_apply(ctx, code, dev(psi), out)
+            ref = fn(psi.reshape(-1))
+            got = host(out).reshape(-1)
+            assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref)), code
+        b = gaussian_rhs(DIMS, 1200)[None]
+        bd = dev(b)
+        rhs = dev(np.zeros_like(psi))
+        B.eigcg_schur_rhs(ctx, bd, rhs)
+        ref = sop.rhs(b.reshape(-1))
+        assert np.max(np.abs(host(rhs).reshape(-1) - ref)) <= 1e-13 * np.max(np.abs(ref))
+        xe = dev(np.zeros_like(psi))
+        rc, st = B.eigcg_solve(ctx, rhs, xe, 1e-10, B.EIGCG_MODE_CG)
+        assert rc == B.EIGCG_OK
+        xe_h = host(xe).reshape(-1)
+        assert np.linalg.norm(ref - sop.A(xe_h)) <= 1.01e-10 * np.linalg.norm(ref)
+        xf = dev(np.zeros_like(b))
+        B.eigcg_schur_reconstruct(ctx, bd, xe, xf)
+        xf_h = host(xf).reshape(-1)
+        # the odd half from the oracle's reconstruction, the full system with its M
+        assert np.max(np.abs(xf_h - sop.reconstruct(b.reshape(-1), xe_h))) <= \
+            1e-13 * np.max(np.abs(xf_h))
+        assert np.linalg.norm(op.M(xf_h) - b.reshape(-1)) <= 1e-8 * np.linalg.norm(b)
+    finally:
+        B.eigcg_destroy(ctx)
