@@ -221,7 +221,7 @@ void ctx_init(Ctx& c, const eigcg_params& p, const void* gauge_dev, hipStream_t 
   // scratch
   c.hist_stride = 3 * (p.max_iter + 8);
   c.d_st = (ColState*)c.dalloc(sizeof(ColState) * kMaxCols);
-  c.check(hipHostMalloc((void**)&c.h_st, sizeof(ColState) * kMaxCols * 3, 0), "hipHostMalloc");
+  c.check(hipHostMalloc((void**)&c.h_st, sizeof(ColState) * kMaxCols * 4, 0), "hipHostMalloc");
   c.d_hist = (double*)c.dalloc(sizeof(double) * (size_t)kMaxCols * c.hist_stride);
   c.check(hipHostMalloc((void**)&c.h_hist, sizeof(double) * (size_t)kMaxCols * c.hist_stride, 0),
           "hipHostMalloc");
@@ -1182,39 +1182,48 @@ struct Driver {
     R.stale_until[col] = R.seg_id;
   }
 
-  // FP64 outer step of iterative refinement for one mixed-precision column;
-  // returns true when the column has converged.
-  bool host_refine(int col) {
+  // FP64 outer step of iterative refinement for the masked mixed-precision
+  // columns, together (one pass over the bank U deflates all of them);
+  // returns the mask of columns that have converged.
+  uint32_t host_refine(uint32_t m) {
     Ctx& cx = c();
-    const uint32_t m1 = 1u << col;
     Workspace& w = R.w;
-    accum_inner(m1);
-    true_residual(cx, kF64, R.K, m1, w64.x, w64.b, w64.r, w64.tmp);
-    cx.check(launch_post_residual(cx.d_st, R.K, m1, cx.stream), "post");
-    R.outer[col]++;
-    cx.check(hipMemcpyAsync(cx.h_st + 2 * kMaxCols + kMaxCols - 1, cx.d_st + col, sizeof(ColState),
-                            hipMemcpyDeviceToHost, cx.stream),
+    accum_inner(m);
+    true_residual(cx, kF64, R.K, m, w64.x, w64.b, w64.r, w64.tmp);
+    cx.check(launch_post_residual(cx.d_st, R.K, m, cx.stream), "post");
+    ColState* hs = cx.h_st + 3 * kMaxCols;  // read-back area (not an upload slot)
+    cx.check(hipMemcpyAsync(hs, cx.d_st, sizeof(ColState) * R.K, hipMemcpyDeviceToHost, cx.stream),
              "state");
     cx.check(hipStreamSynchronize(cx.stream), "sync");
-    const ColState S = cx.h_st[2 * kMaxCols + kMaxCols - 1];
-    if (S.state == ColStopped && S.reason == ReasonConverged) return true;
-    if (cx.l > 0) {  // deflation per outer step
-      deflate_mixed(m1);
-      cx.check(launch_post_residual(cx.d_st, R.K, m1, cx.stream), "post");
+    uint32_t conv = 0, run = 0;
+    for (int j = 0; j < R.K; ++j) {
+      if (!((m >> j) & 1u)) continue;
+      R.outer[j]++;
+      if (hs[j].state == ColStopped && hs[j].reason == ReasonConverged) conv |= 1u << j;
+      else run |= 1u << j;
     }
-    if (R.prec == kF32)
-      cx.check(launch_copy(kF64, kF32, R.K, cx.cs, w64.r, cx.cs, w.r, cx.cs, cx.stream, m1), "copy");
-    else
-      to_inner16(m1);
-    cg_start(R, m1);
-    R.stale_until[col] = R.seg_id;
-    return false;
+    if (run) {
+      if (cx.l > 0) {  // deflation per outer step
+        deflate_mixed(run);
+        cx.check(launch_post_residual(cx.d_st, R.K, run, cx.stream), "post");
+      }
+      if (R.prec == kF32)
+        cx.check(launch_copy(kF64, kF32, R.K, cx.cs, w64.r, cx.cs, w.r, cx.cs, cx.stream, run),
+                 "copy");
+      else
+        to_inner16(run);
+      cg_start(R, run);
+      for (int j = 0; j < R.K; ++j)
+        if ((run >> j) & 1u) R.stale_until[j] = R.seg_id;
+    }
+    return conv;
   }
 
   void process(int pslot_, int end, int id) {
     Ctx& cx = c();
     cx.check(hipEventSynchronize(cx.events[pslot_]), "poll wait");
     const ColState* hs = cx.h_st + pslot_ * kMaxCols;
+    uint32_t mref = 0;  // columns due for an FP64 refinement step
     for (int j = 0; j < R.K; ++j) {
       if (!((R.mask >> j) & 1u) || R.done[j]) continue;
       if (id <= R.stale_until[j]) continue;
@@ -1233,10 +1242,7 @@ struct Driver {
           continue;
         }
         if (scheme == kSchemeRefine) {
-          cx.check(hipStreamSynchronize(cx.stream), "sync");
-          if (!host_refine(j)) continue;
-          R.done[j] = 1;
-          R.reason[j] = ReasonConverged;
+          mref |= 1u << j;
           continue;
         }
         want_rel = true;  // kSchemeReliable
@@ -1245,6 +1251,15 @@ struct Driver {
       R.done[j] = 1;
       R.reason[j] = S.reason;
       if (R.eig) R.finalize_eig(j, S.iter);
+    }
+    if (mref) {
+      cx.check(hipStreamSynchronize(cx.stream), "sync");
+      const uint32_t conv = host_refine(mref);
+      for (int j = 0; j < R.K; ++j) {
+        if (!((conv >> j) & 1u)) continue;
+        R.done[j] = 1;
+        R.reason[j] = ReasonConverged;
+      }
     }
   }
 
