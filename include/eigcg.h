@@ -22,7 +22,14 @@
  *                      orthonormalised against U and appended, H = U^H A U
  *                      grows by nev rows and columns;
  *   EIGCG_MODE_INITCG  init-CG (eq. (2.1)) with the bank, restarted once near
- *                      machine precision (Section 5.3).
+ *                      machine precision (Section 5.3);
+ *   EIGCG_MODE_AUTO    the nrhs right-hand sides of the call are one sequence:
+ *                      Incremental eigCG while it pays, then init-CG for the
+ *                      rest (Section 5.5: the best number of eigCG solves grows
+ *                      with the number of right-hand sides; chosen at run time
+ *                      from measured iterations and times, see
+ *                      eigcg_host_auto_continue).  Init-CG only with 16-bit
+ *                      inner solves.
  *
  * Odd-even preconditioning (params.schur = 1; the operator of the paper's
  * lattice runs, Sections 6 and 7, which halves the system): sites split by the
@@ -71,7 +78,7 @@ enum {
 };
 
 enum { EIGCG_FP64 = 0, EIGCG_MIXED_FP32 = 1, EIGCG_MIXED_HALF = 2 };
-enum { EIGCG_MODE_CG = 0, EIGCG_MODE_EIGCG = 1, EIGCG_MODE_INITCG = 2 };
+enum { EIGCG_MODE_CG = 0, EIGCG_MODE_EIGCG = 1, EIGCG_MODE_INITCG = 2, EIGCG_MODE_AUTO = 3 };
 enum { EIGCG_OP_M = 0, EIGCG_OP_MDAG = 1, EIGCG_OP_A = 2, EIGCG_OP_INNER = 3 };
 
 typedef struct {
@@ -119,6 +126,8 @@ typedef struct {
   double seconds;         /* wall time of this right-hand side's batch */
   int32_t bank_added;     /* vectors appended to U (EIGCG mode) */
   int32_t nritz;          /* Ritz pairs produced by eigCG (EIGCG mode) */
+  int32_t mode_used;      /* mode this right-hand side was solved in (EIGCG_MODE_AUTO
+                             resolves to EIGCG or INITCG) */
 } eigcg_stats;
 
 /* Fill *p with defaults (nev 10, m 100, bank 240, FP64, batch 1, ...). */
@@ -290,6 +299,18 @@ int eigcg_host_eig_lowest(int32_t n, const double* a, int32_t k, double* w, doub
 int eigcg_host_qr(int32_t m, int32_t n, const double* a, double* q, double* r);
 /* Solve H X = B (H n x n HPD, B n x nrhs; complex128 column-major). */
 int eigcg_host_chol_solve(int32_t n, const double* h, int32_t nrhs, double* b);
+/* The rule of EIGCG_MODE_AUTO: after `done` eigCG groups (batches of right-
+ * hand sides) with mean iteration counts iters[done] and wall times
+ * secs[done] (seconds), `left` groups still to solve (the next included),
+ * iter_ms the measured time of one CG iteration of a group and bank_room the
+ * nev-blocks U can still take: 1 when the next group should run eigCG (its
+ * overhead over plain CG, estimated by the last group as
+ * secs - iters * iter_ms, is smaller than the iterations it is predicted to
+ * save the left - 1 later groups: the last drop in iterations times the
+ * ratio of the last two drops, capped at 1), else 0.  Always 1 for done < 2
+ * (with left > 1 and room), always 0 for left <= 1 or no room. */
+int eigcg_host_auto_continue(int32_t done, int32_t left, const double* iters, const double* secs,
+                             double iter_ms, int32_t bank_room);
 
 #ifdef __cplusplus
 }

@@ -22,7 +22,7 @@ EIGCG_OK, EIGCG_EINVAL, EIGCG_ENOMEM, EIGCG_ENOTCONV = 0, -1, -2, -3
 STENCIL_VARIANTS = 10
 EIGCG_EBREAKDOWN, EIGCG_EHIP, EIGCG_EBUSY = -4, -5, -6
 EIGCG_FP64, EIGCG_MIXED_FP32, EIGCG_MIXED_HALF = 0, 1, 2
-EIGCG_MODE_CG, EIGCG_MODE_EIGCG, EIGCG_MODE_INITCG = 0, 1, 2
+EIGCG_MODE_CG, EIGCG_MODE_EIGCG, EIGCG_MODE_INITCG, EIGCG_MODE_AUTO = 0, 1, 2, 3
 EIGCG_OP_M, EIGCG_OP_MDAG, EIGCG_OP_A, EIGCG_OP_INNER = 0, 1, 2, 3
 
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "ENOTCONV", -4: "EBREAKDOWN",
@@ -62,6 +62,7 @@ class Stats(ctypes.Structure):
         ("seconds", ctypes.c_double),
         ("bank_added", ctypes.c_int32),
         ("nritz", ctypes.c_int32),
+        ("mode_used", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -106,6 +107,7 @@ SIGNATURES = {
     "eigcg_host_eig_lowest": (_I32, [_I32, _DP, _I32, _DP, _DP]),
     "eigcg_host_qr": (_I32, [_I32, _I32, _DP, _DP, _DP]),
     "eigcg_host_chol_solve": (_I32, [_I32, _DP, _I32, _DP]),
+    "eigcg_host_auto_continue": (_I32, [_I32, _I32, _DP, _DP, ctypes.c_double, _I32]),
 }
 
 
@@ -434,3 +436,14 @@ def eigcg_host_chol_solve(h: np.ndarray, b: np.ndarray):
     if rc != EIGCG_OK:
         raise EigcgError(rc, "host Cholesky failed")
     return bf.reshape(b.shape)
+
+
+def eigcg_host_auto_continue(iters, secs, left, iter_ms, bank_room):
+    """The automatic mode's rule: True when the next group should run eigCG."""
+    it = np.ascontiguousarray(np.asarray(iters, dtype=np.float64))
+    sc = np.ascontiguousarray(np.asarray(secs, dtype=np.float64))
+    rc = LIB.eigcg_host_auto_continue(len(it), int(left), it.ctypes.data_as(_DP),
+                                      sc.ctypes.data_as(_DP), float(iter_ms), int(bank_room))
+    if rc < 0:
+        raise EigcgError(rc, "bad arguments")
+    return rc == 1

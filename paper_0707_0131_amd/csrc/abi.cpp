@@ -146,7 +146,7 @@ int eigcg_solve(eigcg_ctx* ctx, int32_t nrhs, const void* b_dev, void* x_dev, do
   if (nrhs < 0 || (nrhs > 0 && (!b_dev || !x_dev)))
     return fail(ctx, EIGCG_EINVAL, "bad right-hand side arguments");
   if (!(tol > 0.0) || !std::isfinite(tol)) return fail(ctx, EIGCG_EINVAL, "tol must be > 0");
-  if (mode < EIGCG_MODE_CG || mode > EIGCG_MODE_INITCG) return fail(ctx, EIGCG_EINVAL, "bad mode");
+  if (mode < EIGCG_MODE_CG || mode > EIGCG_MODE_AUTO) return fail(ctx, EIGCG_EINVAL, "bad mode");
   if (nrhs == 0) return EIGCG_OK;
   return guarded(ctx, [&] { return eigcg::solve(ctx->c, nrhs, b_dev, x_dev, tol, mode, stats); });
 }
@@ -357,6 +357,12 @@ int eigcg_host_chol_solve(int32_t n, const double* h, int32_t nrhs, double* b) {
   if (eigcg::hostla::cholesky(n, L.data(), n) != 0) return EIGCG_EBREAKDOWN;
   eigcg::hostla::cholesky_solve(n, L.data(), n, nrhs, reinterpret_cast<eigcg::hostla::cplx*>(b), n);
   return EIGCG_OK;
+}
+
+int eigcg_host_auto_continue(int32_t done, int32_t left, const double* iters, const double* secs,
+                             double iter_ms, int32_t bank_room) {
+  if (done < 0 || (done > 0 && (!iters || !secs))) return EIGCG_EINVAL;
+  return eigcg::auto_continue(done, left, iters, secs, iter_ms, bank_room) ? 1 : 0;
 }
 
 }  // extern "C"

@@ -1528,25 +1528,113 @@ int bank_append_from(Ctx& c, const void* src, int nsrc) {
   return kept;
 }
 
+// Time of one CG iteration (stencil passes, finalize, update) of a batch of K
+// columns in precision prec, from events around reps iterations on the
+// context's work vectors (cached per precision and width).
+static double cg_iteration_ms(Ctx& c, int prec, int K) {
+  const int key = prec * 64 + K;
+  auto it = c.iter_ms.find(key);
+  if (it != c.iter_ms.end()) return it->second;
+  Workspace& w = prec == kF64 ? c.ws64 : c.ws32;
+  ws_ensure(c, w, prec, false);
+  const size_t vb = c.cs * elem_bytes(prec);
+  for (void* v : {w.x, w.p, w.r, w.tmp})
+    c.check(hipMemsetAsync(v, 0x3F, vb * w.K, c.stream), "fill");
+  const std::vector<double> rn = col_norms(c, prec, K, w.r);
+  c.check(launch_copy(prec, prec, K, c.cs, w.r, c.cs, w.p, c.cs, c.stream), "copy");
+  std::vector<ColState> st(K);
+  std::memset(st.data(), 0, sizeof(ColState) * K);
+  for (int j = 0; j < K; ++j) {  // a consistent CG state (r = p) that never stops
+    st[j].state = ColRun;
+    st[j].rho = rn[j];
+    st[j].stop2 = st[j].restart2 = st[j].res_stop2 = -1.0;
+    st[j].max_iter = 0x3fffffff;
+    st[j].scale = 1.0;
+  }
+  std::memcpy(c.h_st, st.data(), sizeof(ColState) * K);
+  c.check(hipMemcpy(c.d_st, c.h_st, sizeof(ColState) * K, hipMemcpyHostToDevice), "st");
+  const int reps = 10;
+  Run R(c, w, prec, K, K >= 32 ? 0xffffffffu : ((1u << K) - 1), false);
+  hipEvent_t e0, e1;
+  c.check(hipEventCreate(&e0), "ev");
+  c.check(hipEventCreate(&e1), "ev");
+  R.enqueue_iters(2);
+  c.check(hipEventRecord(e0, c.stream), "ev");
+  R.enqueue_iters(reps);
+  c.check(hipEventRecord(e1, c.stream), "ev");
+  c.check(hipEventSynchronize(e1), "ev");
+  float ms = 0.f;
+  c.check(hipEventElapsedTime(&ms, e0, e1), "ev");
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  for (void* v : {w.x, w.p, w.r, w.tmp}) c.check(hipMemsetAsync(v, 0, vb * w.K, c.stream), "clear");
+  c.check(hipStreamSynchronize(c.stream), "sync");
+  const double t = (double)ms / reps;
+  c.iter_ms[key] = t;
+  return t;
+}
+
+// The dynamic switch from Incremental eigCG to init-CG (Section 5.5: run
+// eigCG for the number of right-hand sides that minimises the total time,
+// monitored at run time).  After `done` eigCG groups with mean iterations
+// iters[] and wall times secs[], with `left` groups still to solve (the next
+// one included) and room for `bank_room` more nev-blocks in U: one more eigCG
+// group pays its overhead over plain iterations (estimated by the last group:
+// secs - iters * iter_ms) to shorten each of the later left - 1 groups by the
+// next drop in iterations, predicted from the last two drops as a geometric
+// decay.  Returns true to run the next group with eigCG.
+bool auto_continue(int done, int left, const double* iters, const double* secs, double iter_ms,
+                   int bank_room) {
+  if (bank_room <= 0 || left <= 1) return false;
+  if (done < 2) return true;  // two groups give the first measured drop
+  const double d = iters[done - 2] - iters[done - 1];
+  if (!(d > 0.0)) return false;
+  double rho = 1.0;
+  if (done >= 3) {
+    const double d0 = iters[done - 3] - iters[done - 2];
+    rho = d0 > 0.0 ? std::min(1.0, std::max(0.0, d / d0)) : 1.0;
+  }
+  const double gain_s = (left - 1) * rho * d * iter_ms * 1e-3;
+  const double over_s = secs[done - 1] - iters[done - 1] * iter_ms * 1e-3;
+  return over_s < gain_s;
+}
+
 int solve(Ctx& c, int nrhs, const void* b_aos, void* x_aos, double tol, int mode,
           eigcg_stats* stats) {
   const bool mixed = c.P.precision != EIGCG_FP64;
-  const bool eig = mode == EIGCG_MODE_EIGCG;
-  if (eig && c.P.precision == EIGCG_MIXED_HALF)
+  const bool automatic = mode == EIGCG_MODE_AUTO;
+  // 16-bit inner solves cannot run eigCG: the automatic mode is init-CG there
+  if (automatic && c.P.precision == EIGCG_MIXED_HALF) mode = EIGCG_MODE_INITCG;
+  if (mode == EIGCG_MODE_EIGCG && c.P.precision == EIGCG_MIXED_HALF)
     throw ApiError{EIGCG_EINVAL, "eigCG mode needs FP64 or FP32 iterations (16-bit inner solves "
                                  "restart at every refinement step)"};
+  const bool any_eig = mode == EIGCG_MODE_EIGCG || mode == EIGCG_MODE_AUTO;
   const int prec = mixed ? c.iprec : kF64;
-  const int scheme = scheme_for(c, mode);
-  ws_ensure(c, c.ws64, kF64, eig && !mixed);
-  if (mixed) ws_ensure(c, c.ws32, c.iprec, eig);
+  ws_ensure(c, c.ws64, kF64, any_eig && !mixed);
+  if (mixed) ws_ensure(c, c.ws32, c.iprec, any_eig);
   Workspace& w = mixed ? c.ws32 : c.ws64;
   Workspace& w64 = c.ws64;
   int worst = EIGCG_OK;
   c.last_ritz.clear();
-  const double rtol = restart_tol_for(c, mode, scheme);
+  std::vector<double> auto_iters, auto_secs;  // eigCG groups of the automatic mode
+  bool auto_eig = true;
   for (int c0 = 0; c0 < nrhs; c0 += w.K) {
-    const double t0 = now_s();
     const int K = std::min(w.K, nrhs - c0);
+    int gmode = mode;
+    if (automatic) {
+      if (auto_eig) {
+        const int left = (nrhs - c0 + w.K - 1) / w.K;
+        const int room = (c.P.max_bank - c.l) / std::max(1, c.P.nev * K);
+        const double it_ms = auto_iters.size() >= 2 ? cg_iteration_ms(c, prec, K) : 0.0;
+        auto_eig = auto_continue((int)auto_iters.size(), left, auto_iters.data(),
+                                 auto_secs.data(), it_ms, room);
+      }
+      gmode = auto_eig ? EIGCG_MODE_EIGCG : EIGCG_MODE_INITCG;
+    }
+    const bool eig = gmode == EIGCG_MODE_EIGCG;
+    const int scheme = scheme_for(c, gmode);
+    const double rtol = restart_tol_for(c, gmode, scheme);
+    const double t0 = now_s();
     const double2* bsrc = (const double2*)b_aos + (size_t)c0 * 12 * c.g.V;
     double2* xdst = (double2*)x_aos + (size_t)c0 * 12 * c.g.V;
     c.check(launch_spinor_to_soa(bsrc, w64.b, kF64, &c.g, K, c.cs, c.stream), "to soa");
@@ -1573,7 +1661,7 @@ int solve(Ctx& c, int nrhs, const void* b_aos, void* x_aos, double tol, int mode
     }
     std::vector<double> res(K, 0.0);
     if (mask) {
-      D.start_columns(mask, bn2, tol, rtol, mode != EIGCG_MODE_CG);
+      D.start_columns(mask, bn2, tol, rtol, gmode != EIGCG_MODE_CG);
       const int hard_cap = c.P.max_iter + 4 * D.seg + 8;
       while (!D.all_done(mask) && D.R.enq_iter <= hard_cap) D.step();
       D.finish();
@@ -1595,6 +1683,14 @@ int solve(Ctx& c, int nrhs, const void* b_aos, void* x_aos, double tol, int mode
       }
     }
     const double dt = now_s() - t0;
+    if (automatic && eig && mask) {
+      double it = 0.0;
+      int n = 0;
+      for (int j = 0; j < K; ++j)
+        if ((mask >> j) & 1u) { it += D.R.iters[j]; ++n; }
+      auto_iters.push_back(it / std::max(1, n));
+      auto_secs.push_back(dt);
+    }
     for (int j = 0; j < K; ++j) {
       int stt = EIGCG_OK;
       if ((mask >> j) & 1u) {
@@ -1612,6 +1708,7 @@ int solve(Ctx& c, int nrhs, const void* b_aos, void* x_aos, double tol, int mode
         s.seconds = dt;
         s.bank_added = added[j];
         s.nritz = eig ? D.R.ec[j].nritz : 0;
+        s.mode_used = gmode;
       }
     }
   }

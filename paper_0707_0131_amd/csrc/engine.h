@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <complex>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -90,6 +91,7 @@ struct Ctx {
   std::string err;
   int sticky = 0;
   std::vector<double> last_ritz;
+  std::map<int, double> iter_ms;   // measured CG iteration time per (precision, width)
   std::vector<hipEvent_t> events;
   // sampled stencil timings: events around the two passes of every
   // P.sample_every-th iteration, harvested when the pool is full or on request
@@ -125,6 +127,8 @@ void bank_info(Ctx& c, int* l, double* vals, double* res);
 void bank_vectors(Ctx& c, int first, int count, void* out_aos);
 int bank_load(Ctx& c, int count, const void* vecs_aos);
 double bench_kernels(Ctx& c, int what, int reps);
+bool auto_continue(int done, int left, const double* iters, const double* secs, double iter_ms,
+                   int bank_room);
 void kernel_samples(Ctx& c, bool reset, double* out);
 
 // Serving sessions (continuous batching over max_batch slots of one context).

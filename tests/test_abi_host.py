@@ -118,3 +118,61 @@ def test_host_qr_and_cholesky(B):
     assert np.max(np.abs(h @ x - bb)) < 1e-12
     with pytest.raises(B.EigcgError):
         B.eigcg_host_chol_solve(-np.eye(3, dtype=complex), np.ones(3, dtype=complex))
+
+
+def test_auto_switch_rule_cases(B):
+    f = B.eigcg_host_auto_continue
+    # no bank room, or nothing left to gain from: init-CG
+    assert not f([], [], 5, 1.0, 0)
+    assert not f([900.0, 700.0], [1.5, 1.2], 1, 1.0, 10)
+    # fewer than two eigCG groups: no measured drop yet, keep growing
+    assert f([], [], 5, 1.0, 10)
+    assert f([900.0], [1.5], 5, 1.0, 10)
+    # no drop in iterations: stop
+    assert not f([700.0, 700.0], [1.0, 1.0], 20, 1.0, 10)
+    # overhead 0.2 s per group against (left - 1) * 100 iterations * 1 ms saved
+    assert f([900.0, 800.0], [1.0, 1.0], 4, 1.0, 10)       # 0.2 < 0.3
+    assert not f([900.0, 800.0], [1.0, 1.0], 2, 1.0, 10)   # 0.2 > 0.1
+    # the next drop is predicted from the ratio of the last two drops
+    assert not f([1000.0, 800.0, 790.0], [1.0, 1.0, 0.99], 20, 1.0, 10)
+    # a history without times is refused
+    rc = B.LIB.eigcg_host_auto_continue(1, 3, None, None, 1.0, 1)
+    assert rc == B.EIGCG_EINVAL
+
+
+def _model(k, n1=1000.0, ninf=160.0, tau=4.0):
+    """Iterations of the k-th right-hand side (1-based) after k - 1 eigCG solves."""
+    return ninf + (n1 - ninf) * np.exp(-(k - 1) / tau)
+
+
+def test_auto_switch_grows_with_the_number_of_rhs(B):
+    """Section 5.5's observation, on a model of its shape: iterations decay
+    with each eigCG solve towards a floor, an eigCG solve costs its
+    iterations plus a 30 % overhead plus a bank update growing with the bank.
+    The rule's plan (decided one right-hand side at a time from the measured
+    history) never runs eigCG for every right-hand side, runs more of them for
+    longer sequences, and costs within 5 % of the best fixed number of eigCG
+    solves of the same model."""
+    iter_ms = 1.0
+
+    def eig_secs(k):
+        return (1.3 * _model(k) + 20.0 * k) * iter_ms * 1e-3
+
+    def total(s, keig):
+        t = sum(eig_secs(k) for k in range(1, keig + 1))
+        return t + (s - keig) * _model(keig + 1) * iter_ms * 1e-3
+
+    chosen = []
+    for s in (6, 12, 24, 32, 48):
+        iters, secs = [], []
+        for k in range(1, s + 1):
+            if not B.eigcg_host_auto_continue(iters, secs, s - k + 1, iter_ms, 100):
+                break
+            iters.append(_model(k))
+            secs.append(eig_secs(k))
+        keig = len(iters)
+        best = min(total(s, q) for q in range(0, s + 1))
+        assert 2 <= keig < s
+        assert total(s, keig) <= 1.05 * best, (s, keig)
+        chosen.append(keig)
+    assert chosen == sorted(chosen) and chosen[-1] > chosen[0], chosen

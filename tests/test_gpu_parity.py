@@ -442,3 +442,44 @@ def test_half_precision_cg_and_initcg(B, cfg0):
         B.eigcg_destroy(ctx)
         B.eigcg_destroy(ctx1)
         B.eigcg_destroy(ctx3)
+
+
+def test_auto_mode_matches_explicit_modes(B, cfg0):
+    """EIGCG_MODE_AUTO over eight right-hand sides: a prefix solved with
+    Incremental eigCG (at least two), the rest with init-CG, every solve to
+    1e-10; the same right-hand sides through explicit EIGCG then INITCG calls
+    on a fresh context give the same bits."""
+    import torch
+    U, op, _ = cfg0
+    bs = gaussian_rhs_block((4, 4, 4, 4), [4000 + i for i in range(8)])
+    kw = dict(nev=4, m=20, max_bank=40, max_iter=5000, stencil_variant=6)
+    ctx, _ = make_ctx(U, -0.2, **kw)
+    try:
+        x = dev(np.zeros_like(bs))
+        rc, st = B.eigcg_solve(ctx, dev(bs), x, 1e-10, B.EIGCG_MODE_AUTO)
+        assert rc == B.EIGCG_OK
+        modes = [s["mode_used"] for s in st]
+        keig = modes.count(B.EIGCG_MODE_EIGCG)
+        assert keig >= 2 and modes == [B.EIGCG_MODE_EIGCG] * keig + [B.EIGCG_MODE_INITCG] * (8 - keig)
+        xa = host(x)
+        for j in range(8):  # FP64 residual with the oracle's A
+            r = bs[j].reshape(-1) - op.A(xa[j].reshape(-1))
+            assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(bs[j])
+        l_auto = len(B.eigcg_bank_info(ctx)[0])
+    finally:
+        B.eigcg_destroy(ctx)
+    ctx, _ = make_ctx(U, -0.2, **kw)
+    try:
+        x = dev(np.zeros_like(bs))
+        rc1, _ = B.eigcg_solve(ctx, dev(bs[:keig]), x[:keig], 1e-10, B.EIGCG_MODE_EIGCG)
+        xr = torch.zeros_like(x[keig:])
+        rc2, _ = B.eigcg_solve(ctx, dev(bs[keig:]), xr, 1e-10, B.EIGCG_MODE_INITCG) \
+            if keig < 8 else (B.EIGCG_OK, [])
+        assert rc1 == B.EIGCG_OK and rc2 == B.EIGCG_OK
+        assert np.array_equal(host(x)[:keig], xa[:keig])
+        if keig < 8:
+            assert np.array_equal(host(xr), xa[keig:])
+        assert len(B.eigcg_bank_info(ctx)[0]) == l_auto
+    finally:
+        B.eigcg_destroy(ctx)
+

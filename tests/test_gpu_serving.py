@@ -125,3 +125,53 @@ def test_small_budget_still_completes(B):
     finally:
         for c in ctxs:
             B.eigcg_destroy(c)
+
+
+def test_schur_field_alone_equals_mixed(B):
+    """An odd-even preconditioned context served beside an unpreconditioned
+    one (FP32 inner solves, FP64 refinement): each even-site request gives the
+    same bits alone and in the mix and matches the oracle's init-CG on Ahat
+    with the same bank."""
+    import torch
+    from oracle.dense import dense_matrix
+    from oracle.schur import SchurOperator
+    from synthetic import gaussian_half_rhs
+    dims, eps, seed, mass = (4, 4, 4, 4), 0.3, 0, -0.2
+    U = gauge_field(dims, eps, seed)
+    sop = SchurOperator(U, mass)
+    A = dense_matrix(sop.A, sop.n)
+    lam, X = np.linalg.eigh(A)
+    nbank = 12
+    sctx, g1 = make_ctx(U, mass, precision=1, max_batch=3, max_bank=nbank, nev=6, m=20,
+                        max_iter=4000, schur=1)
+    ctxs, keep, ops, banks = _setup(B, 1, max_batch=3)
+    try:
+        B.eigcg_bank_load(sctx, dev(X[:, :nbank].T.reshape((nbank, sop.n // 12, 4, 3)).copy()))
+        allc = [sctx, ctxs[1]]
+        jobs_alone, jobs_mix = [], []
+        for i in range(4):
+            b = dev(gaussian_half_rhs(dims, 3100 + i)[None].copy())
+            jobs_alone.append((0, b, torch.zeros_like(b)))
+            jobs_mix.append((0, b, torch.zeros_like(b)))
+        op1, shape1 = ops[1]
+        bs = gaussian_rhs_block(tuple(reversed(shape1[:4])), [3200 + i for i in range(4)])
+        for i in range(4):
+            b = dev(bs[i][None].copy())
+            jobs_alone.append((1, b, torch.zeros_like(b)))
+            jobs_mix.append((1, b, torch.zeros_like(b)))
+        res_alone = _serve(B, allc, jobs_alone, one_by_one=True)
+        order = [0, 4, 1, 5, 2, 6, 3, 7]
+        res_mix = _serve(B, allc, [jobs_mix[k] for k in order])
+        for pos, k in enumerate(order):
+            assert res_alone[k][0] == B.EIGCG_OK and res_mix[pos][0] == B.EIGCG_OK
+            assert res_alone[k][1]["iters"] == res_mix[pos][1]["iters"]
+            assert torch.equal(jobs_alone[k][2], jobs_mix[k][2])
+        H = X[:, :nbank].conj().T @ A @ X[:, :nbank]
+        for k in range(4):
+            _, b, x = jobs_alone[k]
+            xo, _ = init_cg(sop.A, X[:, :nbank], H, host(b).reshape(-1), tol=1e-10)
+            assert rel(host(x).reshape(-1), xo) <= 1e-6
+    finally:
+        B.eigcg_destroy(sctx)
+        for c in ctxs:
+            B.eigcg_destroy(c)
