@@ -196,6 +196,33 @@ def schur_leg(B, torch, g, bt, n_plain=4, n_eig=N_EIG, n_defl=N_DEFL):
     return out
 
 
+def auto_leg(B, torch, g, bt, xt, mass=-0.58):
+    """The whole right-hand-side sequence of one step in EIGCG_MODE_AUTO: the
+    library runs Incremental eigCG while its measured gain outweighs its
+    overhead, then init-CG (against the step's fixed 24 + 100 plan)."""
+    log(f"automatic eigCG/init-CG switch (mass {mass})")
+    p = B.eigcg_default_params(dims=LATTICE, mass=mass, nev=NEV, m=M, max_bank=NBANK,
+                               max_iter=40000, check_every=16)
+    ctx = B.eigcg_create(p, g)
+    try:
+        xt.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, st = B.eigcg_solve(ctx, bt, xt, TOL, B.EIGCG_MODE_AUTO)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        bank = len(B.eigcg_bank_info(ctx)[0])
+    finally:
+        B.eigcg_destroy(ctx)
+    keig = sum(1 for s in st if s["mode_used"] == B.EIGCG_MODE_EIGCG)
+    out = {"mass": mass, "rhs": len(st), "eigcg_rhs": keig, "bank": bank,
+           "rhs_per_s": len(st) / dt, "wall_s": dt,
+           "max_true_rel_res": max(s["true_rel_res"] for s in st),
+           "failed": sum(1 for s in st if s["status"] != 0 or s["true_rel_res"] > TOL)}
+    log(f"automatic switch: {keig} eigCG right-hand sides (bank {bank}), {len(st) / dt:.1f} RHS/s")
+    return out
+
+
 def source_hash():
     import hashlib
     h = hashlib.sha256()
@@ -589,6 +616,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-large", action="store_true", help="skip the 32^3x64 half-precision leg")
     ap.add_argument("--no-schur", action="store_true", help="skip the odd-even preconditioning leg")
+    ap.add_argument("--no-auto", action="store_true", help="skip the automatic eigCG/init-CG leg")
     ap.add_argument("--serve-bank-rhs", type=int, default=N_EIG)
     ap.add_argument("--serve-requests", type=int, default=120)
     ap.add_argument("--stencil-variant", type=int, default=0,
@@ -670,6 +698,13 @@ def main():
     batching = None
     if not args.no_batching:
         batching = batching_leg(B, torch, g, bt)
+
+    auto = None
+    if not args.no_auto:
+        auto = auto_leg(B, torch, g, bt, xt)
+        fixed = [s for s in steps if s["mass"] == auto["mass"]]
+        if fixed:
+            auto["fixed_plan_rhs_per_s"] = nrhs / (fixed[0]["phase1_s"] + fixed[0]["phase2_s"])
 
     odd_even = None
     if not args.no_schur:
@@ -759,6 +794,7 @@ def main():
                           "algorithmic_bytes_per_launch": pass1_bytes},
         "batching": batching,
         "odd_even": odd_even,
+        "auto_switch": auto,
         "serving": serving,
         "large_lattice": large,
         "stencil_bench_lattice": roof_small,

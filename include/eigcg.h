@@ -306,8 +306,8 @@ int eigcg_host_chol_solve(int32_t n, const double* h, int32_t nrhs, double* b);
  * nev-blocks U can still take: 1 when the next group should run eigCG (its
  * overhead over plain CG, estimated by the last group as
  * secs - iters * iter_ms, is smaller than the iterations it is predicted to
- * save the left - 1 later groups: the last drop in iterations times the
- * ratio of the last two drops, capped at 1), else 0.  Always 1 for done < 2
+ * save the left - 1 later groups: the mean drop in iterations over the last
+ * three groups, or fewer while done < 4), else 0.  Always 1 for done < 3
  * (with left > 1 and room), always 0 for left <= 1 or no room. */
 int eigcg_host_auto_continue(int32_t done, int32_t left, const double* iters, const double* secs,
                              double iter_ms, int32_t bank_room);

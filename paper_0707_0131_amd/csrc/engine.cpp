@@ -1581,21 +1581,18 @@ static double cg_iteration_ms(Ctx& c, int prec, int K) {
 // one included) and room for `bank_room` more nev-blocks in U: one more eigCG
 // group pays its overhead over plain iterations (estimated by the last group:
 // secs - iters * iter_ms) to shorten each of the later left - 1 groups by the
-// next drop in iterations, predicted from the last two drops as a geometric
-// decay.  Returns true to run the next group with eigCG.
+// next drop in iterations, predicted as the mean drop over the last (up to
+// three) groups, which smooths the spread of iteration counts between
+// right-hand sides.  Returns true to run the next group with eigCG.
 bool auto_continue(int done, int left, const double* iters, const double* secs, double iter_ms,
                    int bank_room) {
   if (bank_room <= 0 || left <= 1) return false;
-  if (done < 2) return true;  // two groups give the first measured drop
-  const double d = iters[done - 2] - iters[done - 1];
+  if (done < 3) return true;  // the first drops are measured over three groups
+  const int w = std::min(done - 1, 3);
+  const double d = (iters[done - 1 - w] - iters[done - 1]) / w;
   if (!(d > 0.0)) return false;
-  double rho = 1.0;
-  if (done >= 3) {
-    const double d0 = iters[done - 3] - iters[done - 2];
-    rho = d0 > 0.0 ? std::min(1.0, std::max(0.0, d / d0)) : 1.0;
-  }
-  const double gain_s = (left - 1) * rho * d * iter_ms * 1e-3;
-  const double over_s = secs[done - 1] - iters[done - 1] * iter_ms * 1e-3;
+  const double gain_s = (left - 1) * d * iter_ms * 1e-3;
+  const double over_s = std::max(0.0, secs[done - 1] - iters[done - 1] * iter_ms * 1e-3);
   return over_s < gain_s;
 }
 
@@ -1625,7 +1622,7 @@ int solve(Ctx& c, int nrhs, const void* b_aos, void* x_aos, double tol, int mode
       if (auto_eig) {
         const int left = (nrhs - c0 + w.K - 1) / w.K;
         const int room = (c.P.max_bank - c.l) / std::max(1, c.P.nev * K);
-        const double it_ms = auto_iters.size() >= 2 ? cg_iteration_ms(c, prec, K) : 0.0;
+        const double it_ms = auto_iters.size() >= 3 ? cg_iteration_ms(c, prec, K) : 0.0;
         auto_eig = auto_continue((int)auto_iters.size(), left, auto_iters.data(),
                                  auto_secs.data(), it_ms, room);
       }

@@ -446,7 +446,7 @@ def test_half_precision_cg_and_initcg(B, cfg0):
 
 def test_auto_mode_matches_explicit_modes(B, cfg0):
     """EIGCG_MODE_AUTO over eight right-hand sides: a prefix solved with
-    Incremental eigCG (at least two), the rest with init-CG, every solve to
+    Incremental eigCG (at least three), the rest with init-CG, every solve to
     1e-10; the same right-hand sides through explicit EIGCG then INITCG calls
     on a fresh context give the same bits."""
     import torch
@@ -460,7 +460,7 @@ def test_auto_mode_matches_explicit_modes(B, cfg0):
         assert rc == B.EIGCG_OK
         modes = [s["mode_used"] for s in st]
         keig = modes.count(B.EIGCG_MODE_EIGCG)
-        assert keig >= 2 and modes == [B.EIGCG_MODE_EIGCG] * keig + [B.EIGCG_MODE_INITCG] * (8 - keig)
+        assert keig >= 3 and modes == [B.EIGCG_MODE_EIGCG] * keig + [B.EIGCG_MODE_INITCG] * (8 - keig)
         xa = host(x)
         for j in range(8):  # FP64 residual with the oracle's A
             r = bs[j].reshape(-1) - op.A(xa[j].reshape(-1))
