@@ -199,6 +199,20 @@ int eigcg_last_ritz(eigcg_ctx* ctx, double* vals, int32_t cap, int32_t* count);
 /* Drop every bank vector (l = 0). */
 int eigcg_bank_reset(eigcg_ctx* ctx);
 
+/* Truncate U to its k lowest Ritz vectors (the Section 4 discussion of
+ * limiting the size of U): with H Y = Y Theta, U <- U Y_k and H <- Theta_k
+ * (k >= l leaves the bank unchanged, k = 0 empties it).  Needs k fields of
+ * device memory for the duration of the call.  EINVAL for k < 0. */
+int eigcg_bank_truncate(eigcg_ctx* ctx, int32_t k);
+
+/* Restore a saved bank (checkpoint / resume): U <- l fields from vecs_dev
+ * (boundary layout, as eigcg_bank_vectors wrote them; stored in the bank's
+ * precision) and H <- h_host (l x l complex128 column-major, as
+ * eigcg_bank_matrix wrote it).  Nothing is re-orthonormalised and A is not
+ * applied, so the restored context deflates exactly as the saved one did.
+ * EINVAL when l > max_bank or H is not Hermitian positive definite. */
+int eigcg_bank_restore(eigcg_ctx* ctx, int32_t l, const void* vecs_dev, const double* h_host);
+
 /* Bytes of device memory the context holds. */
 int eigcg_memory(eigcg_ctx* ctx, uint64_t* bytes);
 

@@ -89,6 +89,8 @@ SIGNATURES = {
     "eigcg_bank_matrix": (_I32, [_VP, _DP]),
     "eigcg_last_ritz": (_I32, [_VP, _DP, _I32, ctypes.POINTER(_I32)]),
     "eigcg_bank_reset": (_I32, [_VP]),
+    "eigcg_bank_truncate": (_I32, [_VP, _I32]),
+    "eigcg_bank_restore": (_I32, [_VP, _I32, _VP, _DP]),
     "eigcg_memory": (_I32, [_VP, ctypes.POINTER(ctypes.c_uint64)]),
     "eigcg_last_error": (ctypes.c_char_p, [_VP]),
     "eigcg_layout_info": (_I32, [_VP, ctypes.POINTER(_I32)]),
@@ -288,6 +290,22 @@ def eigcg_last_ritz(ctx, cap=4096):
 
 def eigcg_bank_reset(ctx):
     return LIB.eigcg_bank_reset(ctx)
+
+
+def eigcg_bank_truncate(ctx, k):
+    rc = LIB.eigcg_bank_truncate(ctx, int(k))
+    if rc != EIGCG_OK:
+        raise EigcgError(rc, eigcg_last_error(ctx))
+
+
+def eigcg_bank_restore(ctx, vecs, h):
+    """Restore U from l device fields and H (l x l complex, [row, col]) on the host."""
+    _check_field(vecs, "vectors")
+    l = vecs.shape[0]
+    hf = np.ascontiguousarray(np.asarray(h, dtype=np.complex128).T)  # column-major
+    rc = LIB.eigcg_bank_restore(ctx, l, _ptr(vecs), hf.ctypes.data_as(_DP))
+    if rc != EIGCG_OK:
+        raise EigcgError(rc, eigcg_last_error(ctx))
 
 
 def eigcg_memory(ctx):

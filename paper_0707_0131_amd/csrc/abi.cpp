@@ -246,6 +246,24 @@ int eigcg_last_ritz(eigcg_ctx* ctx, double* vals, int32_t cap, int32_t* count) {
   return EIGCG_OK;
 }
 
+int eigcg_bank_truncate(eigcg_ctx* ctx, int32_t k) {
+  if (!ctx) return EIGCG_EINVAL;
+  if (k < 0) return fail(ctx, EIGCG_EINVAL, "negative bank size");
+  return guarded(ctx, [&] {
+    eigcg::bank_truncate(ctx->c, k);
+    return EIGCG_OK;
+  });
+}
+
+int eigcg_bank_restore(eigcg_ctx* ctx, int32_t l, const void* vecs_dev, const double* h_host) {
+  if (!ctx) return EIGCG_EINVAL;
+  if (l < 0 || (l > 0 && (!vecs_dev || !h_host))) return fail(ctx, EIGCG_EINVAL, "bad arguments");
+  return guarded(ctx, [&] {
+    eigcg::bank_restore(ctx->c, l, vecs_dev, h_host);
+    return EIGCG_OK;
+  });
+}
+
 int eigcg_bank_reset(eigcg_ctx* ctx) {
   if (!ctx) return EIGCG_EINVAL;
   ctx->c.l = 0;

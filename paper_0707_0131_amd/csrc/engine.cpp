@@ -1928,6 +1928,69 @@ int bank_load(Ctx& c, int count, const void* vecs_aos) {
   return added;
 }
 
+// Truncation of U to its k lowest Ritz vectors (the Section 4 discussion of
+// limiting U): with H Y = Y Theta, U <- U Y_k and H <- Theta_k.  The product
+// goes through a temporary of k fields (the bank's own columns are inputs).
+void bank_truncate(Ctx& c, int k) {
+  if (k < 0) throw ApiError{EIGCG_EINVAL, "negative bank size"};
+  if (k >= c.l) return;
+  if (k == 0) {
+    c.l = 0;
+    c.chol_ok = false;
+    return;
+  }
+  const int l = c.l, ld = c.P.max_bank, prec = c.bank_prec;
+  std::vector<double> th(l);
+  std::vector<cplx> Y((size_t)l * k);
+  if (hostla::herm_eig_lowest(l, c.H.data(), ld, k, th.data(), Y.data(), l) != 0)
+    throw ApiError{EIGCG_EBREAKDOWN, "bank eigensolver failed"};
+  void* tmp = c.dalloc(c.cs * elem_bytes(prec) * (size_t)k);
+  try {
+    std::vector<const void*> in(l);
+    for (int i = 0; i < l; ++i) in[i] = col_ptr(c.U, prec, c.cs, i);
+    std::vector<void*> out(k);
+    for (int j = 0; j < k; ++j) out[j] = col_ptr(tmp, prec, c.cs, j);
+    tall_from_host(c, prec, l, k, in, out, Y.data(), 0, 0);
+    c.check(launch_copy(prec, prec, k, c.cs, tmp, c.cs, c.U, c.cs, c.stream), "copy");
+    c.check(hipStreamSynchronize(c.stream), "sync");
+  } catch (...) {
+    c.dfree(tmp);
+    throw;
+  }
+  c.dfree(tmp);
+  std::fill(c.H.begin(), c.H.end(), cplx(0.0, 0.0));
+  for (int i = 0; i < k; ++i) c.H[(size_t)i * ld + i] = cplx(th[i], 0.0);
+  c.l = k;
+  c.chol_ok = false;
+}
+
+// Restore a saved bank: U <- the given fields (in the bank's precision) and
+// H <- h (l x l, column-major), both as eigcg_bank_vectors and
+// eigcg_bank_matrix returned them; no orthonormalisation, no applications of A.
+void bank_restore(Ctx& c, int l, const void* vecs_aos, const double* h_host) {
+  if (l < 0 || l > c.P.max_bank) throw ApiError{EIGCG_EINVAL, "bank size out of range"};
+  ensure_bank(c);
+  const int ld = c.P.max_bank;
+  const cplx* h = reinterpret_cast<const cplx*>(h_host);
+  std::vector<cplx> Hn((size_t)ld * ld, cplx(0.0, 0.0));
+  for (int j = 0; j < l; ++j)
+    for (int i = 0; i < l; ++i) Hn[(size_t)j * ld + i] = h[(size_t)j * l + i];
+  std::vector<cplx> Lt = Hn;  // H must be Hermitian positive definite
+  if (l > 0 && hostla::cholesky(l, Lt.data(), ld) != 0)
+    throw ApiError{EIGCG_EINVAL, "bank matrix is not positive definite"};
+  for (int q0 = 0; q0 < l; q0 += 16) {
+    const int k = std::min(16, l - q0);
+    const double2* src = (const double2*)vecs_aos + (size_t)q0 * 12 * c.g.V;
+    c.check(launch_spinor_to_soa(src, col_ptr(c.U, c.bank_prec, c.cs, q0), c.bank_prec, &c.g, k,
+                                 c.cs, c.stream),
+            "to soa");
+  }
+  c.check(hipStreamSynchronize(c.stream), "sync");
+  c.H = Hn;
+  c.l = l;
+  c.chol_ok = false;
+}
+
 void bank_vectors(Ctx& c, int first, int count, void* out_aos) {
   for (int q = 0; q < count; ++q) {
     double2* dst = (double2*)out_aos + (size_t)q * 12 * c.g.V;

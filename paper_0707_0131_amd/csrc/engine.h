@@ -126,6 +126,8 @@ void deflate_init(Ctx& c, int nrhs, const void* b_aos, void* x_aos);
 void bank_info(Ctx& c, int* l, double* vals, double* res);
 void bank_vectors(Ctx& c, int first, int count, void* out_aos);
 int bank_load(Ctx& c, int count, const void* vecs_aos);
+void bank_truncate(Ctx& c, int k);
+void bank_restore(Ctx& c, int l, const void* vecs_aos, const double* h_host);
 double bench_kernels(Ctx& c, int what, int reps);
 bool auto_continue(int done, int left, const double* iters, const double* secs, double iter_ms,
                    int bank_room);

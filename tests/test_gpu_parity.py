@@ -483,3 +483,52 @@ def test_auto_mode_matches_explicit_modes(B, cfg0):
     finally:
         B.eigcg_destroy(ctx)
 
+
+
+def test_bank_truncate_and_restore(B, cfg0):
+    """A bank from three Incremental eigCG(6, 30) solves: saved with
+    eigcg_bank_vectors / eigcg_bank_matrix and restored into a fresh context,
+    init-CG gives the same bits; truncated to its 8 lowest Ritz vectors, the
+    bank holds the 8 lowest Ritz values of before, stays orthonormal with
+    H = U^H A U diagonal (oracle's A), and still deflates init-CG to 1e-10."""
+    import torch
+    U, op, _ = cfg0
+    kw = dict(nev=6, m=30, max_bank=36, max_iter=5000, stencil_variant=6)
+    bs = gaussian_rhs_block((4, 4, 4, 4), [4100, 4101, 4102, 4103])
+    ctx, _ = make_ctx(U, -0.2, **kw)
+    ctx2, _ = make_ctx(U, -0.2, **kw)
+    try:
+        x = dev(np.zeros_like(bs))
+        rc, _ = B.eigcg_solve(ctx, dev(bs[:3]), x[:3], 1e-10, B.EIGCG_MODE_EIGCG)
+        assert rc == B.EIGCG_OK
+        vals, _ = B.eigcg_bank_info(ctx)
+        l = len(vals)
+        Ut = dev(np.zeros((l,) + bs.shape[1:], dtype=np.complex128))
+        B.eigcg_bank_vectors(ctx, 0, l, Ut)
+        H = B.eigcg_bank_matrix(ctx, l)
+        B.eigcg_bank_restore(ctx2, Ut, H)
+        assert np.array_equal(B.eigcg_bank_matrix(ctx2, l), H)
+        xa, xb = torch.zeros_like(x[3:]), torch.zeros_like(x[3:])
+        B.eigcg_solve(ctx, dev(bs[3:]), xa, 1e-10, B.EIGCG_MODE_INITCG)
+        B.eigcg_solve(ctx2, dev(bs[3:]), xb, 1e-10, B.EIGCG_MODE_INITCG)
+        assert torch.equal(xa, xb)
+        # truncation
+        B.eigcg_bank_truncate(ctx, 8)
+        tvals, _ = B.eigcg_bank_info(ctx)
+        assert len(tvals) == 8
+        assert np.max(np.abs(tvals - vals[:8]) / vals[:8]) <= 1e-10
+        Ut8 = dev(np.zeros((8,) + bs.shape[1:], dtype=np.complex128))
+        B.eigcg_bank_vectors(ctx, 0, 8, Ut8)
+        Um = host(Ut8).reshape(8, -1).T
+        assert np.max(np.abs(Um.conj().T @ Um - np.eye(8))) < 1e-12
+        AU = np.stack([op.A(Um[:, j]) for j in range(8)], axis=1)
+        G = Um.conj().T @ AU
+        assert np.max(np.abs(G - np.diag(tvals))) <= 1e-10 * tvals[-1]
+        xt = torch.zeros_like(x[3:])
+        rc, st = B.eigcg_solve(ctx, dev(bs[3:]), xt, 1e-10, B.EIGCG_MODE_INITCG)
+        assert rc == B.EIGCG_OK and st[0]["true_rel_res"] <= 1e-10
+        with pytest.raises(B.EigcgError):
+            B.eigcg_bank_restore(ctx2, Ut[:2], -np.eye(2))  # not positive definite
+    finally:
+        B.eigcg_destroy(ctx)
+        B.eigcg_destroy(ctx2)
