@@ -223,6 +223,62 @@ def auto_leg(B, torch, g, bt, xt, mass=-0.58):
     return out
 
 
+FP64_MFMA_PEAK_TF = 78.6
+FP32_MFMA_PEAK_TF = 157.3
+
+
+def gemm_roofline(B, torch, reps=10):
+    """The window and deflation contractions alone, at the bench lattice's
+    vector length (n = 12 V complex entries), through eigcg_debug_gemm:
+    V (QZ) of the eigCG restart (m = 100 -> 2 nev = 20, FP64), the init-CG
+    deflation U^H r and U c with a 240-vector FP64 bank (one column), and the
+    batched FP32 forms for 12 columns.  Each shape: mean time of reps calls,
+    algorithmic bytes (every input column read once, every output written
+    once) and complex flops (8 n K N)."""
+    V = LATTICE[0] * LATTICE[1] * LATTICE[2] * LATTICE[3]
+    n = 12 * V
+    shapes = [("restart V(QZ)", 0, 0, M, 2 * NEV), ("deflation U c", 0, 0, NBANK, 1),
+              ("deflation U^H r", 0, 1, NBANK, 1), ("batched U C fp32", 1, 0, NBANK, 12),
+              ("batched U^H R fp32", 1, 1, NBANK, 12)]
+    kmax = max(k for _, _, _, k, _ in shapes)
+    out = []
+    for name, prec, kind, K, N in shapes:
+        dt = torch.complex128 if prec == 0 else torch.complex64
+        eb = 16 if prec == 0 else 8
+        a = torch.randn((K, n), dtype=dt, device="cuda:0")
+        r = torch.randn((N, n), dtype=dt, device="cuda:0") if kind == 1 else None
+        o = torch.empty((N, n) if kind == 0 else (N, K), dtype=torch.complex128 if kind == 1 else dt,
+                        device="cuda:0")
+        sm = torch.randn((N, K), dtype=torch.complex128, device="cuda:0")  # S column-major K x N
+        scratch = torch.empty(2 * 1024 * K * 24, dtype=torch.float64, device="cuda:0")
+
+        def call():
+            rc = B.LIB.eigcg_debug_gemm(prec, kind, n, K, N, B._ptr(a),
+                                        B._ptr(r) if r is not None else None, B._ptr(sm),
+                                        B._ptr(o), B._ptr(scratch), scratch.numel())
+            if rc != 0:
+                raise RuntimeError(f"eigcg_debug_gemm {name}: {rc}")
+        call()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            call()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / reps * 1e3
+        nbytes = (K + N) * n * eb
+        flops = 8.0 * n * K * N
+        peak = FP64_MFMA_PEAK_TF if prec == 0 else FP32_MFMA_PEAK_TF
+        out.append({"shape": name, "prec": "f64" if prec == 0 else "f32", "K": K, "N": N, "n": n,
+                    "ms": ms, "GBs": nbytes / ms / 1e6, "hbm_frac": nbytes / ms / 1e6 / HBM_PEAK_GBS,
+                    "TFLOPs": flops / ms / 1e9, "mfma_frac": flops / ms / 1e9 / peak,
+                    "algorithmic_bytes": nbytes, "flops": flops,
+                    "arith_intensity": flops / nbytes})
+        log(f"{name}: {ms:.3f} ms, {nbytes / ms / 1e6:.0f} GB/s, {flops / ms / 1e9:.1f} TFLOP/s")
+        del a, r, o, sm, scratch
+        torch.cuda.empty_cache()
+    return out
+
+
 def source_hash():
     import hashlib
     h = hashlib.sha256()
@@ -622,6 +678,9 @@ def main():
     ap.add_argument("--stencil-variant", type=int, default=0,
                     help="with --roofline-only: force this stencil variant (counter runs "
                          "use the variant the full bench run picked)")
+    ap.add_argument("--gemm-only", action="store_true",
+                    help="only time the window and deflation contractions (MFMA) at the bench "
+                         "lattice's vector length")
     ap.add_argument("--roofline-only", choices=("bench", "hbm"),
                     help="only time the stencil, copy and CG iteration on the bench lattice "
                          "or the 24^3x48 lattice (short runs for counter collection)")
@@ -636,6 +695,10 @@ def main():
     from synthetic import gauge_field, gaussian_rhs
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.gemm_only:
+        log("window and deflation contractions only")
+        print(json.dumps({"gemm": gemm_roofline(B, torch)}))
+        return
     if args.roofline_only:
         dims, seed = (LATTICE, SEED) if args.roofline_only == "bench" else (HBM_LATTICE, HBM_SEED)
         log(f"stencil timings only ({dims})")

@@ -153,13 +153,21 @@ __global__ __launch_bounds__(256) void k_gemm_tall(size_t n, int K, int N, const
 }
 
 // Reduction product partials: wave handles (row chunk, 16 input columns).
+// The workgroup stages tiles of kTileRows rows through LDS with coalesced
+// loads (each input column's rows are contiguous; a half-wave reads 32 of
+// them at once) and shares the R tile between its four waves; the products
+// then run over the tile's rows in pairs, in the same order as a direct
+// row-pair sweep of the chunk.
 template <typename VS, int NT>
 __global__ __launch_bounds__(256) void k_gemm_reduce(size_t n, int K, int N, size_t chunk,
                                                      TallArgs cols, double* partial) {
   using R = typename Storage<VS>::real;
   using M = Mfma<R>;
+  constexpr int kTileRows = 32;
   __shared__ const VS* sin[kMaxK];
   __shared__ const VS* sr[kMaxN];
+  __shared__ cpx<R> tU[4][16][kTileRows];  // [wave][input column][row]
+  __shared__ cpx<R> tR[16][kTileRows];     // [output column][row], N <= 16
   for (int i = threadIdx.x; i < K; i += blockDim.x) sin[i] = reinterpret_cast<const VS*>(cols.in[i]);
   for (int i = threadIdx.x; i < N; i += blockDim.x) sr[i] = reinterpret_cast<const VS*>(cols.out[i]);
   __syncthreads();
@@ -167,13 +175,13 @@ __global__ __launch_bounds__(256) void k_gemm_reduce(size_t n, int K, int N, siz
   const int wave = threadIdx.x >> 6;
   const int mtile = blockIdx.y * 4 + wave;
   const int mtiles = (K + 15) / 16;
-  if (mtile >= mtiles) return;
+  const bool mact = mtile < mtiles;  // every wave takes part in the loads and barriers
   const int li = lane & 15;
   const int lk = lane >> 4;
   const int kpart = lk & 1;
   const int krow = lk >> 1;
-  const int icol = mtile * 16 + li;
-  const VS* a = icol < K ? sin[icol] : nullptr;
+  const int half = lane >> 5;       // loads: half-wave per column
+  const int lrow = lane & 31;       // loads: row within the tile
   const size_t r0 = (size_t)blockIdx.x * chunk;
   size_t r1 = r0 + chunk;
   if (r1 > n) r1 = n;
@@ -182,49 +190,60 @@ __global__ __launch_bounds__(256) void k_gemm_reduce(size_t n, int K, int N, siz
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = typename M::acc_t{};
 
-  // operands of the rows r + krow (two rows per step)
-  struct Frag {
-    R a;
-    R b[NT];
-  };
-  auto load = [&](size_t r, Frag& f) {
-    const size_t row = r + krow;
+  // the next tile's entries are loaded into registers while the current
+  // tile's products run
+  cpx<R> pu[8], pr[2];
+  auto fetch = [&](size_t rb) {
+    const size_t row = rb + lrow;
     const bool rv = row < r1;
-    f.a = R(0);
-    if (a && rv) {
-      cpx<R> z = Storage<VS>::ld(a, row);
-      f.a = kpart ? z.im : z.re;
+#pragma unroll
+    for (int c2 = 0; c2 < 8; ++c2) {
+      const int col = mtile * 16 + 2 * c2 + half;
+      pu[c2] = {R(0), R(0)};
+      if (mact && col < K && rv) pu[c2] = Storage<VS>::ld(sin[col], row);
     }
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const int j = 8 * t + (li >> 1);
-      R bv = R(0);
-      if (rv && j < N) {
-        cpx<R> z = Storage<VS>::ld(sr[j], row);
-        // [[Re R, Im R], [Im R, -Re R]] with rows (Re-in, Im-in), cols (Re-out, Im-out)
-        if (kpart == 0) bv = (li & 1) ? z.im : z.re;
-        else bv = (li & 1) ? -z.re : z.im;
-      }
-      f.b[t] = bv;
+    for (int q = 0; q < 2; ++q) {
+      const int j = 2 * wave + half + 8 * q;
+      pr[q] = {R(0), R(0)};
+      if (j < N && rv) pr[q] = Storage<VS>::ld(sr[j], row);
     }
   };
-  // software pipeline: the operands of the next kPre steps are in flight while
-  // the current step's products run (same product order as unpipelined)
-  constexpr int kPre = 4;
-  Frag fr[kPre];
+  if (r0 < r1) fetch(r0);
+  for (size_t rb = r0; rb < r1; rb += kTileRows) {
 #pragma unroll
-  for (int q = 0; q < kPre; ++q) load(r0 + 2 * q, fr[q]);
-  for (size_t r = r0; r < r1; r += 2 * kPre) {
+    for (int c2 = 0; c2 < 8; ++c2) tU[wave][2 * c2 + half][lrow] = pu[c2];
 #pragma unroll
-    for (int q = 0; q < kPre; ++q) {
-      const size_t rq = r + 2 * q;
-      if (rq >= r1) break;
-      const Frag cur = fr[q];
-      load(rq + 2 * kPre, fr[q]);
-#pragma unroll
-      for (int t = 0; t < NT; ++t) acc[t] = M::op(cur.a, cur.b[t], acc[t]);
+    for (int q = 0; q < 2; ++q) {
+      const int j = 2 * wave + half + 8 * q;
+      if (j < N) tR[j][lrow] = pr[q];
     }
+    __syncthreads();
+    if (rb + kTileRows < r1) fetch(rb + kTileRows);
+    if (mact) {
+      const int nr = (int)((r1 - rb) < (size_t)kTileRows ? (r1 - rb) : (size_t)kTileRows);
+      for (int s = 0; s < nr; s += 2) {
+        const int tr = s + krow;  // rows beyond the chunk are zero in the tile
+        const bool trv = rb + tr < r1;
+        const cpx<R> z = tU[wave][li][tr];
+        const R a = kpart ? z.im : z.re;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const int j = 8 * t + (li >> 1);
+          R bv = R(0);
+          if (trv && j < N) {
+            const cpx<R> y = tR[j][tr];
+            // [[Re R, Im R], [Im R, -Re R]] with rows (Re-in, Im-in), cols (Re-out, Im-out)
+            if (kpart == 0) bv = (li & 1) ? y.im : y.re;
+            else bv = (li & 1) ? -y.re : y.im;
+          }
+          acc[t] = M::op(a, bv, acc[t]);
+        }
+      }
+    }
+    __syncthreads();
   }
+  if (!mact) return;
   // partial layout: [chunk][i in 0..K)][jj in 0..2N) doubles
   double* dst = partial + (size_t)blockIdx.x * K * 2 * N;
 #pragma unroll
