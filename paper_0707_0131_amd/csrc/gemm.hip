@@ -153,21 +153,28 @@ __global__ __launch_bounds__(256) void k_gemm_tall(size_t n, int K, int N, const
 }
 
 // Reduction product partials: wave handles (row chunk, 16 input columns).
-// The workgroup stages tiles of kTileRows rows through LDS with coalesced
-// loads (each input column's rows are contiguous; a half-wave reads 32 of
-// them at once) and shares the R tile between its four waves; the products
+// The workgroup stages tiles of TR rows through LDS with coalesced loads
+// (each input column's rows are contiguous; one wave load reads TR rows of
+// 64 / TR columns, or 64 rows of one) and shares the R tile between its four waves; the products
 // then run over the tile's rows in pairs, in the same order as a direct
-// row-pair sweep of the chunk.
-template <typename VS, int NT>
+// row-pair sweep of the chunk (so TR does not change any result).  Dynamic
+// LDS: 4 x 16 columns of input entries, then 16 columns of R, each column
+// TR + 1 entries long (the pad spreads the 16 lanes that read one row of 16
+// columns over the LDS banks).
+template <typename VS, int NT, int TR>
 __global__ __launch_bounds__(256) void k_gemm_reduce(size_t n, int K, int N, size_t chunk,
                                                      TallArgs cols, double* partial) {
   using R = typename Storage<VS>::real;
   using M = Mfma<R>;
-  constexpr int kTileRows = 32;
+  constexpr int kLanesPerCol = TR < 64 ? TR : 64;  // lanes loading one column's tile rows
+  constexpr int kColsPerLoad = 64 / kLanesPerCol;  // columns one wave load covers
+  constexpr int kLoads = 16 / kColsPerLoad * (TR / kLanesPerCol);
   __shared__ const VS* sin[kMaxK];
   __shared__ const VS* sr[kMaxN];
-  __shared__ cpx<R> tU[4][16][kTileRows];  // [wave][input column][row]
-  __shared__ cpx<R> tR[16][kTileRows];     // [output column][row], N <= 16
+  extern __shared__ double2 lds_dyn[];
+  constexpr int CS = TR + 1;                          // column stride in LDS
+  cpx<R>* tU = reinterpret_cast<cpx<R>*>(lds_dyn);  // [wave][input column][row]
+  cpx<R>* tR = tU + 4 * 16 * CS;                     // [output column][row], N <= 16
   for (int i = threadIdx.x; i < K; i += blockDim.x) sin[i] = reinterpret_cast<const VS*>(cols.in[i]);
   for (int i = threadIdx.x; i < N; i += blockDim.x) sr[i] = reinterpret_cast<const VS*>(cols.out[i]);
   __syncthreads();
@@ -180,59 +187,71 @@ __global__ __launch_bounds__(256) void k_gemm_reduce(size_t n, int K, int N, siz
   const int lk = lane >> 4;
   const int kpart = lk & 1;
   const int krow = lk >> 1;
-  const int half = lane >> 5;       // loads: half-wave per column
-  const int lrow = lane & 31;       // loads: row within the tile
+  const int lsub = lane / kLanesPerCol;  // loads: column within a load
+  const int lrow = lane % kLanesPerCol;  // loads: row within a load
   const size_t r0 = (size_t)blockIdx.x * chunk;
   size_t r1 = r0 + chunk;
   if (r1 > n) r1 = n;
+  cpx<R>* tUw = tU + (size_t)wave * 16 * CS;
 
   typename M::acc_t acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = typename M::acc_t{};
 
+  // load q covers columns (q % (16 / kColsPerLoad)) * kColsPerLoad + lsub and
+  // rows (q / (16 / kColsPerLoad)) * kLanesPerCol + lrow of the tile
+  constexpr int kColGroups = 16 / kColsPerLoad;
   // the next tile's entries are loaded into registers while the current
   // tile's products run
-  cpx<R> pu[8], pr[2];
+  cpx<R> pu[kLoads];
+  constexpr int kRLoads = (16 * TR) / 256;  // R tile entries per thread
+  cpx<R> pr[kRLoads];
   auto fetch = [&](size_t rb) {
-    const size_t row = rb + lrow;
-    const bool rv = row < r1;
 #pragma unroll
-    for (int c2 = 0; c2 < 8; ++c2) {
-      const int col = mtile * 16 + 2 * c2 + half;
-      pu[c2] = {R(0), R(0)};
-      if (mact && col < K && rv) pu[c2] = Storage<VS>::ld(sin[col], row);
+    for (int q = 0; q < kLoads; ++q) {
+      const int c = (q % kColGroups) * kColsPerLoad + lsub;
+      const size_t row = rb + (size_t)(q / kColGroups) * kLanesPerCol + lrow;
+      const int col = mtile * 16 + c;
+      pu[q] = {R(0), R(0)};
+      if (mact && col < K && row < r1) pu[q] = Storage<VS>::ld(sin[col], row);
     }
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int j = 2 * wave + half + 8 * q;
+    for (int q = 0; q < kRLoads; ++q) {
+      const int e = q * 256 + (int)threadIdx.x;  // entry of the 16 x TR tile
+      const int j = e / TR, tr = e % TR;
+      const size_t row = rb + tr;
       pr[q] = {R(0), R(0)};
-      if (j < N && rv) pr[q] = Storage<VS>::ld(sr[j], row);
+      if (j < N && row < r1) pr[q] = Storage<VS>::ld(sr[j], row);
     }
   };
   if (r0 < r1) fetch(r0);
-  for (size_t rb = r0; rb < r1; rb += kTileRows) {
+  for (size_t rb = r0; rb < r1; rb += TR) {
 #pragma unroll
-    for (int c2 = 0; c2 < 8; ++c2) tU[wave][2 * c2 + half][lrow] = pu[c2];
+    for (int q = 0; q < kLoads; ++q) {
+      const int c = (q % kColGroups) * kColsPerLoad + lsub;
+      const int tr = (q / kColGroups) * kLanesPerCol + lrow;
+      tUw[c * CS + tr] = pu[q];
+    }
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int j = 2 * wave + half + 8 * q;
-      if (j < N) tR[j][lrow] = pr[q];
+    for (int q = 0; q < kRLoads; ++q) {
+      const int e = q * 256 + (int)threadIdx.x;  // entry e = j * TR + row
+      tR[(e / TR) * CS + e % TR] = pr[q];
     }
     __syncthreads();
-    if (rb + kTileRows < r1) fetch(rb + kTileRows);
+    if (rb + TR < r1) fetch(rb + TR);
     if (mact) {
-      const int nr = (int)((r1 - rb) < (size_t)kTileRows ? (r1 - rb) : (size_t)kTileRows);
+      const int nr = (int)((r1 - rb) < (size_t)TR ? (r1 - rb) : (size_t)TR);
       for (int s = 0; s < nr; s += 2) {
         const int tr = s + krow;  // rows beyond the chunk are zero in the tile
         const bool trv = rb + tr < r1;
-        const cpx<R> z = tU[wave][li][tr];
+        const cpx<R> z = tUw[li * CS + tr];
         const R a = kpart ? z.im : z.re;
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
           const int j = 8 * t + (li >> 1);
           R bv = R(0);
           if (trv && j < N) {
-            const cpx<R> y = tR[j][tr];
+            const cpx<R> y = tR[j * CS + tr];
             // [[Re R, Im R], [Im R, -Re R]] with rows (Re-in, Im-in), cols (Re-out, Im-out)
             if (kpart == 0) bv = (li & 1) ? y.im : y.re;
             else bv = (li & 1) ? -y.re : y.im;
@@ -330,10 +349,14 @@ hipError_t reduce_typed(size_t n, int K, int N, const void* const* in_cols,
   const int nt = (N + 7) / 8;
   dim3 grid(nchunk, ((K + 15) / 16 + 3) / 4), block(256);
   double* part = reinterpret_cast<double*>(partial);
+  // 32-row tiles: 512 B (FP64) or 256 B (FP32) contiguous per column, 42 KB /
+  // 21 KB of LDS, so three / seven workgroups share a CU
+  constexpr int kTR = 32;
+  const size_t lds = (4 * 16 + 16) * (kTR + 1) * sizeof(cpx<typename Storage<VS>::real>);
   if (nt == 1)
-    hipLaunchKernelGGL((k_gemm_reduce<VS, 1>), grid, block, 0, s, n, K, N, chunk, a, part);
+    hipLaunchKernelGGL((k_gemm_reduce<VS, 1, kTR>), grid, block, lds, s, n, K, N, chunk, a, part);
   else
-    hipLaunchKernelGGL((k_gemm_reduce<VS, 2>), grid, block, 0, s, n, K, N, chunk, a, part);
+    hipLaunchKernelGGL((k_gemm_reduce<VS, 2, kTR>), grid, block, lds, s, n, K, N, chunk, a, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int outs = K * N;
