@@ -254,3 +254,28 @@ def test_inner_precision_operator(B, schur, precision, tol):
                 assert np.max(np.abs(got[c] - ref)) <= tol * np.max(np.abs(ref)), code
     finally:
         B.eigcg_destroy(ctx)
+
+
+def test_schur_auto_mode_fp32(B):
+    """EIGCG_MODE_AUTO on the even-site system with FP32 iterations (eigCG
+    groups with FP64 reliable updates, then init-CG with FP64 refinement):
+    a prefix of eigCG solves, every right-hand side to 1e-10 in FP64 with the
+    oracle's Ahat."""
+    dims = (8, 8, 4, 8)
+    U = gauge_field(dims, 0.5, 7)
+    op = SchurOperator(U, -0.3)
+    ctx, _ = make_ctx(U, -0.3, precision=1, nev=4, m=24, max_bank=32, max_iter=20000,
+                      reliable_every=50, schur=1)
+    try:
+        b = gaussian_rhs_block(dims, [71 + i for i in range(6)])
+        rc, st, xe, _ = _solve_full(B, ctx, b, 1e-10, B.EIGCG_MODE_AUTO)
+        assert rc == B.EIGCG_OK, B.eigcg_last_error(ctx)
+        modes = [s["mode_used"] for s in st]
+        keig = modes.count(B.EIGCG_MODE_EIGCG)
+        assert keig >= 3 and modes == [B.EIGCG_MODE_EIGCG] * keig + [B.EIGCG_MODE_INITCG] * (6 - keig)
+        assert len(B.eigcg_bank_info(ctx)[0]) > 0
+        for c in range(6):
+            rhs = op.rhs(b[c].reshape(-1))
+            assert np.linalg.norm(rhs - op.A(xe[c].reshape(-1))) <= 1.01e-10 * np.linalg.norm(rhs)
+    finally:
+        B.eigcg_destroy(ctx)
