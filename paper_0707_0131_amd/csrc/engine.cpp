@@ -358,6 +358,13 @@ static int seg_len_eig(const eigcg_params& P) {
   return std::max(1, d);
 }
 
+// Restart products V <- V (QZ) run in column groups whose m x group
+// coefficients fit the tall kernel's 64 KB of LDS; with more than one group
+// the restarted block cannot be overwritten in place (every output column
+// reads all of the old block), so it alternates between two halves.
+static int restart_group(const eigcg_params& P) { return std::max(1, std::min(24, 4096 / P.m)); }
+static bool restart_pingpong(const eigcg_params& P) { return 2 * P.nev > restart_group(P); }
+
 static void ws_ensure(Ctx& c, Workspace& w, int prec, bool eig) {
   const int K = c.P.max_batch;
   const size_t vb = c.cs * elem_bytes(prec);
@@ -375,7 +382,7 @@ static void ws_ensure(Ctx& c, Workspace& w, int prec, bool eig) {
     w.nev = c.P.nev;
     w.ring_len = c.P.m + seg_len_eig(c.P) + 2;
     w.ring = c.dalloc(vb * (size_t)K * w.ring_len);
-    w.vr = c.dalloc(vb * (size_t)K * 2 * c.P.nev);
+    w.vr = c.dalloc(vb * (size_t)K * 2 * c.P.nev * (restart_pingpong(c.P) ? 2 : 1));
     w.tbuf = c.dalloc(vb * (size_t)K * 2);
     w.w = c.dalloc(vb * (size_t)K);
     w.ritz = c.dalloc(vb * (size_t)K * c.P.nev);
@@ -579,8 +586,10 @@ static void tall_from_host(Ctx& c, int prec, int K, int N, const std::vector<con
                            int negate) {
   for (int k0 = 0; k0 < K; k0 += 256) {
     const int kk = std::min(256, K - k0);
-    for (int n0 = 0; n0 < N; n0 += 24) {
-      const int nn = std::min(24, N - n0);
+    // the kernel holds the kk x nn coefficients in 64 KB of LDS
+    const int nmax = std::max(1, std::min(24, 4096 / kk));
+    for (int n0 = 0; n0 < N; n0 += nmax) {
+      const int nn = std::min(nmax, N - n0);
       c.check(hipStreamSynchronize(c.stream), "sync");
       double2* dg = c.d_small + kGenericOff;
       double2* hg = c.h_small + kGenericOff;
@@ -641,6 +650,7 @@ static void deflate_columns(Ctx& c, int prec, int ncols, uint32_t mask, void* x,
 struct EigCol {
   int k_lo = 1;            // first residual index in the window
   bool has_vr = false;     // restarted block present (2 nev columns)
+  int vr_half = 0;         // which half of the column's restart area holds it
   std::vector<double> Mv;  // its Ritz values (diagonal of T)
   std::vector<cplx> arrow; // arrow row, T(2nev, 0:2nev)
   int arrow_J = 0;         // iteration whose residual carries the arrow row
@@ -698,7 +708,13 @@ struct Run {
     const int slot = k % w.ring_len;
     return col_ptr(w.ring, prec, c.cs, (size_t)col * w.ring_len + slot);
   }
-  void* vrcol(int col, int i) const { return col_ptr(w.vr, prec, c.cs, (size_t)col * 2 * nev + i); }
+  // column i of the restarted block of column col (half: of the two
+  // alternating areas when restart_pingpong)
+  void* vrcol_half(int col, int half, int i) const {
+    const size_t per = (size_t)2 * nev * (restart_pingpong(c.P) ? 2 : 1);
+    return col_ptr(w.vr, prec, c.cs, (size_t)col * per + (size_t)half * 2 * nev + i);
+  }
+  void* vrcol(int col, int i) const { return vrcol_half(col, ec[col].vr_half, i); }
 
   // alpha_k, beta_k, rho_k from the host history copy (k is 1-based)
   double alpha(int col, int k) const { return c.h_hist[(size_t)col * c.hist_stride + 3 * (k - 1)]; }
@@ -910,11 +926,19 @@ struct Run {
             "qz upload");
     std::vector<const void*> in;
     window_cols(col, E, in);
+    const bool pp = restart_pingpong(c.P);
+    const int nh = pp ? 1 - e.vr_half : e.vr_half;  // output half
     std::vector<void*> out(2 * nev);
-    for (int q = 0; q < 2 * nev; ++q) out[q] = vrcol(col, q);
-    c.check(launch_gemm_tall(prec, c.cs, m, 2 * nev, in.data(), out.data(), dq, 0, 0, c.stream),
-            "restart gemm");
+    for (int q = 0; q < 2 * nev; ++q) out[q] = vrcol_half(col, nh, q);
+    const int nmax = restart_group(c.P);
+    for (int n0 = 0; n0 < 2 * nev; n0 += nmax) {
+      const int nn = std::min(nmax, 2 * nev - n0);
+      c.check(launch_gemm_tall(prec, c.cs, m, nn, in.data(), out.data() + n0, dq + (size_t)n0 * m,
+                               0, 0, c.stream),
+              "restart gemm");
+    }
     c.check(hipEventRecord(ev, c.stream), "event");
+    e.vr_half = nh;
     e.has_vr = true;
     e.Mv = Mv;
     e.k_lo = E + 1;

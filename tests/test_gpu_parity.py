@@ -108,7 +108,7 @@ def test_cg_parity_cfg0(B, cfg0, variant):
         B.eigcg_destroy(ctx)
 
 
-@pytest.mark.parametrize("nev,m,iters", [(4, 12, 40), (10, 40, 90), (2, 20, 60)])
+@pytest.mark.parametrize("nev,m,iters", [(4, 12, 40), (10, 40, 90), (2, 20, 60), (16, 40, 70)])
 def test_eigcg_same_trajectory(B, cfg0, nev, m, iters):
     """Forced iteration count (max_iter) before loss of orthogonality: Ritz
     values to 1e-8 and x to 1e-10 against the oracle's eigCG."""
@@ -532,3 +532,29 @@ def test_bank_truncate_and_restore(B, cfg0):
     finally:
         B.eigcg_destroy(ctx)
         B.eigcg_destroy(ctx2)
+
+
+def test_bank_truncate_large(B, cfg0):
+    """Truncation of a full 240-vector bank to 200 and 30 (the product U Y_k
+    then runs in several column groups): the lowest Ritz values of H are
+    kept, U stays orthonormal and H = U^H A U is the diagonal of them."""
+    U, op, _ = cfg0
+    ctx, _ = make_ctx(U, -0.2, nev=10, m=40, max_bank=240, max_iter=5000)
+    try:
+        vecs = gaussian_rhs_block((4, 4, 4, 4), [5000 + i for i in range(240)])
+        added = B.eigcg_bank_load(ctx, dev(vecs))
+        assert added == 240
+        vals, _ = B.eigcg_bank_info(ctx)
+        for k in (200, 30):
+            B.eigcg_bank_truncate(ctx, k)
+            tv, _ = B.eigcg_bank_info(ctx)
+            assert len(tv) == k
+            assert np.max(np.abs(tv - vals[:k]) / vals[:k]) <= 1e-10
+            Ut = dev(np.zeros((k,) + vecs.shape[1:], dtype=np.complex128))
+            B.eigcg_bank_vectors(ctx, 0, k, Ut)
+            Um = host(Ut).reshape(k, -1).T
+            assert np.max(np.abs(Um.conj().T @ Um - np.eye(k))) < 1e-11
+            G = Um.conj().T @ np.stack([op.A(Um[:, j]) for j in range(k)], axis=1)
+            assert np.max(np.abs(G - np.diag(tv))) <= 1e-10 * tv[-1]
+    finally:
+        B.eigcg_destroy(ctx)
