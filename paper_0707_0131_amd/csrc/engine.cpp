@@ -1623,9 +1623,9 @@ bool auto_continue(int done, int left, const double* iters, const double* secs, 
 int solve(Ctx& c, int nrhs, const void* b_aos, void* x_aos, double tol, int mode,
           eigcg_stats* stats) {
   const bool mixed = c.P.precision != EIGCG_FP64;
-  const bool automatic = mode == EIGCG_MODE_AUTO;
   // 16-bit inner solves cannot run eigCG: the automatic mode is init-CG there
-  if (automatic && c.P.precision == EIGCG_MIXED_HALF) mode = EIGCG_MODE_INITCG;
+  if (mode == EIGCG_MODE_AUTO && c.P.precision == EIGCG_MIXED_HALF) mode = EIGCG_MODE_INITCG;
+  const bool automatic = mode == EIGCG_MODE_AUTO;
   if (mode == EIGCG_MODE_EIGCG && c.P.precision == EIGCG_MIXED_HALF)
     throw ApiError{EIGCG_EINVAL, "eigCG mode needs FP64 or FP32 iterations (16-bit inner solves "
                                  "restart at every refinement step)"};

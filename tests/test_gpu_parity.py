@@ -558,3 +558,23 @@ def test_bank_truncate_large(B, cfg0):
             assert np.max(np.abs(G - np.diag(tv))) <= 1e-10 * tv[-1]
     finally:
         B.eigcg_destroy(ctx)
+
+
+def test_auto_mode_with_16bit_inner_solves_is_initcg(B, cfg0):
+    """16-bit inner solves cannot run eigCG: EIGCG_MODE_AUTO solves every
+    right-hand side with init-CG (FP64 refinement) and leaves the bank alone."""
+    U, op, _ = cfg0
+    ctx, _ = make_ctx(U, -0.2, precision=2, nev=4, m=20, max_bank=40, max_iter=20000)
+    try:
+        bs = gaussian_rhs_block((4, 4, 4, 4), [4200, 4201, 4202, 4203])
+        x = dev(np.zeros_like(bs))
+        rc, st = B.eigcg_solve(ctx, dev(bs), x, 1e-10, B.EIGCG_MODE_AUTO)
+        assert rc == B.EIGCG_OK
+        assert all(s["mode_used"] == B.EIGCG_MODE_INITCG for s in st)
+        assert len(B.eigcg_bank_info(ctx)[0]) == 0
+        xa = host(x)
+        for j in range(4):
+            r = bs[j].reshape(-1) - op.A(xa[j].reshape(-1))
+            assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(bs[j])
+    finally:
+        B.eigcg_destroy(ctx)
