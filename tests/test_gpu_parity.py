@@ -578,3 +578,25 @@ def test_auto_mode_with_16bit_inner_solves_is_initcg(B, cfg0):
             assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(bs[j])
     finally:
         B.eigcg_destroy(ctx)
+
+
+@pytest.mark.parametrize("precision,tol", [(1, 1e-6), (2, 1e-6)])
+def test_deflate_init_mixed_bank(B, cfg0, precision, tol):
+    """eq. (2.1) with the FP32 bank of a mixed context (FP32 or 16-bit inner
+    solves): the deflated guess matches the oracle's Galerkin guess to FP32
+    accuracy, for two right-hand sides in one call."""
+    U, op, b = cfg0
+    A, lam, X = _dense_lowest(op, 20)
+    H = X.conj().T @ A @ X
+    bs = gaussian_rhs_block((4, 4, 4, 4), [4300, 4301])
+    ctx, _ = make_ctx(U, -0.2, precision=precision, nev=10, m=40, max_bank=40, max_batch=2)
+    try:
+        vecs = dev(X.T.reshape((20, 4, 4, 4, 4, 4, 3)).copy())
+        assert B.eigcg_bank_load(ctx, vecs) == 20
+        x0 = dev(np.zeros_like(bs))
+        B.eigcg_deflate_init(ctx, dev(bs), x0)
+        for j in range(2):
+            x0o = galerkin_guess(op.A, X, H, bs[j].reshape(-1))
+            assert rel(host(x0)[j].reshape(-1), x0o) <= tol
+    finally:
+        B.eigcg_destroy(ctx)
