@@ -91,7 +91,8 @@ typedef struct {
                              refinement in init-CG mode); EIGCG_MIXED_HALF
                              (16-bit links and vectors with FP32 arithmetic and
                              an FP32 iterate, each inner solve rescaled, FP64
-                             refinement; CG and init-CG modes only) */
+                             refinement; CG and init-CG modes only; needs
+                             compress_links and SU(3) links, else EINVAL) */
   int32_t max_batch;      /* right-hand sides per batched launch, 1..12 */
   int32_t reliable_every; /* mixed precision: FP64 reliable update period */
   int32_t max_iter;       /* per right-hand side */

@@ -250,6 +250,9 @@ void ctx_init(Ctx& c, const eigcg_params& p, const void* gauge_dev, hipStream_t 
   if (p.precision != EIGCG_FP64) {  // inner links: FP32, or 16-bit for the half mode
     c.iprec = p.precision == EIGCG_MIXED_HALF ? kF16 : kF32;
     c.comp32 = (p.compress_links && h2[0] < 1e-6 && h2[1] < 1e-6) ? 1 : 0;
+    if (c.iprec == kF16 && !c.comp32)
+      throw ApiError{EIGCG_EINVAL, "16-bit storage needs two-row links: compress_links = 1 and "
+                                   "links unitary with determinant 1 to 1e-6"};
     c.u32 = c.dalloc(link_blocks * 4 * (c.comp32 ? 6 : 9) * g.vs * elem_bytes(c.iprec));
     c.check(launch_gauge_to_soa((const double2*)gauge_dev, c.u32, c.iprec, c.comp32, &g, s),
             "gauge to soa inner");

@@ -231,8 +231,8 @@ def test_schur_errors(B, cfg0_field):
 
 
 @pytest.mark.parametrize("schur", [0, 1])
-@pytest.mark.parametrize("precision,tol", [(1, 5e-6), (2, 4e-3)])
-def test_inner_precision_operator(B, schur, precision, tol):
+@pytest.mark.parametrize("precision,tol,compress", [(1, 5e-6, 1), (1, 5e-6, 0), (2, 4e-3, 1)])
+def test_inner_precision_operator(B, schur, precision, tol, compress):
     """The inner-precision stencil kernels (FP32, 16-bit storage) applied
     alone (EIGCG_OP_INNER + op) against the FP64 oracle: entries within the
     storage precision's rounding (FP32: 5e-6, 16-bit: 4e-3 of the largest
@@ -241,7 +241,8 @@ def test_inner_precision_operator(B, schur, precision, tol):
     U = gauge_field(dims, 0.5, 7)
     op = SchurOperator(U, -0.3) if schur else WilsonOperator(U, -0.3)
     fns = [op.Mhat, op.Mhat_dag, op.A] if schur else [op.M, op.Mdag, op.A]
-    ctx, _ = make_ctx(U, -0.3, precision=precision, max_batch=2, schur=schur)
+    ctx, _ = make_ctx(U, -0.3, precision=precision, max_batch=2, schur=schur,
+                      compress_links=compress)
     try:
         psi = _half_block(dims, [61, 62]) if schur else gaussian_rhs_block(dims, [61, 62])
         inp = dev(psi)
@@ -279,3 +280,11 @@ def test_schur_auto_mode_fp32(B):
             assert np.linalg.norm(rhs - op.A(xe[c].reshape(-1))) <= 1.01e-10 * np.linalg.norm(rhs)
     finally:
         B.eigcg_destroy(ctx)
+
+
+def test_half_precision_needs_two_row_links(B):
+    dims = (4, 4, 4, 4)
+    U = gauge_field(dims, 0.3, 0)
+    with pytest.raises(B.EigcgError) as e:
+        make_ctx(U, -0.2, precision=2, compress_links=0)
+    assert e.value.code == B.EIGCG_EINVAL
