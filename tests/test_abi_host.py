@@ -47,13 +47,23 @@ def test_default_params_and_validation(B):
     fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
     for bad in [dict(nev=10, m=20), dict(dims=(1, 4, 4, 4)), dict(max_batch=13),
                 dict(max_bank=300), dict(precision=7), dict(max_iter=0),
-                dict(mass=float("nan")), dict(nev=0)]:
+                dict(mass=float("nan")), dict(nev=0), dict(schur=2),
+                dict(schur=1, dims=(4, 4, 3, 4)), dict(stencil_variant=12),
+                dict(sample_every=-1), dict(nev=16, m=257)]:
         q = B.eigcg_default_params(**bad)
         rc = B.LIB.eigcg_create(ctypes.byref(q), fake, None, ctypes.byref(ctx))
         assert rc == B.EIGCG_EINVAL, bad
+        assert B.eigcg_last_error(None), bad  # the thread's create error says why
     assert B.LIB.eigcg_create(ctypes.byref(p), None, None, ctypes.byref(ctx)) == B.EIGCG_EINVAL
     assert B.LIB.eigcg_solve(None, 1, None, None, 1e-10, 0, None) == B.EIGCG_EINVAL
     assert B.LIB.eigcg_destroy(None) == B.EIGCG_EINVAL
+    for fn, args in [("eigcg_schur_rhs", (None, 1, None, None)),
+                     ("eigcg_schur_reconstruct", (None, 1, None, None, None)),
+                     ("eigcg_bank_truncate", (None, 1)),
+                     ("eigcg_bank_restore", (None, 1, None, None))]:
+        assert getattr(B.LIB, fn)(*args) == B.EIGCG_EINVAL, fn
+    with pytest.raises(KeyError):
+        B.eigcg_default_params(no_such_field=1)
 
 
 def test_server_validation_without_gpu(B):
