@@ -26,10 +26,13 @@ Modules:
 * ``schur``        - odd-even (Schur complement) preconditioned operator on
                      the even sites, with the maps to and from the full
                      system (the operator of the paper's lattice runs).
+* ``bicgstab``     - BiCGSTAB on gamma5 M (or M) with a deflated initial
+                     guess from the bank (Section 1's use of the eigCG
+                     vectors for a nonsymmetric solver).
 
 Parity status: every function here is pinned by a test under ``tests/``
 (closed forms, invariants, dense linear algebra or brute force); nothing is
 "parity unpinned".
 """
 
-from . import dirac, cg, eigcg, initcg, incremental, dense, schur  # noqa: F401
+from . import dirac, cg, eigcg, initcg, incremental, dense, schur, bicgstab  # noqa: F401
