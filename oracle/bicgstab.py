@@ -15,10 +15,15 @@ sides.  The paper does not spell out either part.  Readings taken here:
   method restarts from the current iterate (a new ``r_0`` and ``rh``).
 * BiCGSTAB runs on ``Q x = gamma5 b`` (reading of "BiCGSTAB on gamma5 M"; the
   bank approximates eigenvectors of ``Q``, not of ``M``), or on ``M x = b``.
-* The deflated initial guess is the Galerkin projection of
-  ``Q x = gamma5 b`` onto ``span(U)``, the analogue for ``Q`` of eq. (2.1):
-  ``x_0 = xt + U (U^H Q U)^{-1} U^H gamma5 (b - M xt)``.  ``U^H Q U`` is Hermitian
-  but indefinite, so it is solved through its eigendecomposition.
+* The deflated starting guess minimises ``||b - M x||`` over
+  ``x in xt + span(U)``.  Its normal equations have the matrix
+  ``(M U)^H (M U) = U^H A U = H``, the bank's own matrix, so the guess is
+  init-CG's eq. (2.1) applied to ``A x = M^H b``:
+  ``x_0 = xt + U H^{-1} U^H M^H (b - M xt)``.  For exact eigenvectors of ``A``
+  (hence of ``gamma5 M``, eigenvalues ``mu``, ``mu^2 = lambda``) it equals the
+  Galerkin projection of ``gamma5 M x = gamma5 b`` onto ``span(U)``; unlike that
+  projection it never raises the residual when ``U`` is approximate (the
+  Galerkin matrix ``U^H gamma5 M U`` is indefinite and can be nearly singular).
 
 Only tests/, the smoke check and the bench's CPU baseline use this module.
 """
@@ -26,6 +31,8 @@ Only tests/, the smoke check and the bench's CPU baseline use this module.
 from __future__ import annotations
 
 import numpy as np
+
+from .initcg import galerkin_guess
 
 
 def _dot(a, b):
@@ -108,30 +115,20 @@ def bicgstab(apply_M, b, x0=None, tol=1e-10, max_iter=10000, max_restarts=8):
     return x, info
 
 
-def gamma5_projection_matrix(apply_M, gamma5, U):
-    """``U^H gamma5 M U`` (Hermitian for a gamma5-Hermitian M), column by column."""
-    l = U.shape[1]
-    QU = np.empty_like(U)
-    for j in range(l):
-        QU[:, j] = gamma5(apply_M(U[:, j]))
-    return U.conj().T @ QU
-
-
-def gamma5_galerkin_guess(apply_M, gamma5, U, HQ, b, x_tilde=None):
-    """Galerkin guess for ``Q x = gamma5 b`` on ``span(U)``:
-    ``x0 = xt + U HQ^{-1} U^H gamma5 (b - M xt)`` with ``HQ = U^H Q U``."""
+def deflated_guess(apply_M, apply_Mdag, U, b, x_tilde=None):
+    """``x0 = xt + U H^{-1} U^H M^H (b - M xt)``, ``H = U^H M^H M U`` formed
+    here column by column (``xt = 0`` if omitted)."""
     b = np.asarray(b, dtype=np.complex128).reshape(-1)
     base = np.zeros_like(b) if x_tilde is None else np.array(x_tilde, dtype=np.complex128)
     if U is None or U.shape[1] == 0:
         return base
-    res = b if x_tilde is None else b - apply_M(base)
-    c = U.conj().T @ gamma5(res)
-    theta, Z = np.linalg.eigh(HQ)
-    y = Z @ ((Z.conj().T @ c) / theta)
-    return base + U @ y
+    apply_A = lambda v: apply_Mdag(apply_M(v))
+    AU = np.stack([apply_A(U[:, j]) for j in range(U.shape[1])], axis=1)
+    H = U.conj().T @ AU
+    return galerkin_guess(apply_A, U, H, apply_Mdag(b), x_tilde=x_tilde)
 
 
-def deflated_bicgstab(apply_M, gamma5, U, b, x0=None, tol=1e-10, max_iter=10000,
+def deflated_bicgstab(apply_M, apply_Mdag, gamma5, U, b, x0=None, tol=1e-10, max_iter=10000,
                       on_gamma5=True):
     """Deflated guess from the bank ``U``, then BiCGSTAB.
 
@@ -141,9 +138,7 @@ def deflated_bicgstab(apply_M, gamma5, U, b, x0=None, tol=1e-10, max_iter=10000,
     residual norm (gamma5 is unitary).
     """
     b = np.asarray(b, dtype=np.complex128).reshape(-1)
-    have_u = U is not None and U.shape[1] > 0
-    HQ = gamma5_projection_matrix(apply_M, gamma5, U) if have_u else None
-    xg = gamma5_galerkin_guess(apply_M, gamma5, U, HQ, b, x_tilde=x0)
+    xg = deflated_guess(apply_M, apply_Mdag, U, b, x_tilde=x0)
     if on_gamma5:
         x, info = bicgstab(lambda v: gamma5(apply_M(v)), gamma5(b), x0=xg, tol=tol,
                            max_iter=max_iter)

@@ -10,9 +10,10 @@ What fixes it independently of its own code:
 * the Wilson solve equals the dense solve of M;
 * the paper's premise that eigenvectors of A = M^H M are eigenvectors of
   gamma5 M, with eigenvalue +-sqrt(lambda), on the dense 4^4 operator;
-* with exact eigenvectors the Galerkin guess is the orthogonal projection of
-  the exact solution, and the projected matrix is diagonal with the
-  eigenvalues of gamma5 M;
+* the deflated guess is the dense least-squares solution of M (U y) = b
+  (minimal residual over span(U)) for an approximate U; with exact
+  eigenvectors it equals the dense Galerkin projection of gamma5 M and the
+  orthogonal projection of the exact solution;
 * deflation with the lowest eigenvectors of A cuts BiCGSTAB's iterations on
   gamma5 M by more than half.
 """
@@ -21,8 +22,7 @@ import numpy as np
 import pytest
 import scipy.sparse.linalg as sla
 
-from oracle.bicgstab import bicgstab, deflated_bicgstab, gamma5_galerkin_guess, \
-    gamma5_projection_matrix
+from oracle.bicgstab import bicgstab, deflated_bicgstab, deflated_guess
 from oracle.dirac import apply_gamma5
 
 
@@ -109,21 +109,33 @@ def test_eigenvectors_of_A_are_eigenvectors_of_gamma5_M(cfg0_op, cfg0_dense):
         assert np.linalg.norm(Q @ u - mu * u) < 1e-9
 
 
-def test_galerkin_guess_with_exact_eigenvectors(cfg0_op, cfg0_dense, cfg0_rhs):
+def test_guess_is_least_squares_and_galerkin_for_exact_eigenvectors(cfg0_op, cfg0_dense,
+                                                                     cfg0_rhs):
     b = cfg0_rhs
+    Md = cfg0_dense["M"]
     X = cfg0_dense["X"][:, :16]
-    HQ = gamma5_projection_matrix(cfg0_op.M, cfg0_op.gamma5, X)
-    mu = np.array([np.vdot(X[:, j], cfg0_op.gamma5(cfg0_op.M(X[:, j]))).real for j in range(16)])
-    assert np.max(np.abs(HQ - np.diag(mu))) < 1e-9
-    x_star = np.linalg.solve(cfg0_dense["M"], b)
-    x0 = gamma5_galerkin_guess(cfg0_op.M, cfg0_op.gamma5, X, HQ, b)
-    proj = X @ (X.conj().T @ x_star)
-    assert np.linalg.norm(x0 - proj) <= 1e-9 * np.linalg.norm(proj)
-    # from a non-zero starting point the guess adds the projected correction
+    # approximate basis: least squares over span(U), from the dense matrix
+    rng = np.random.default_rng(3)
+    Un, _ = np.linalg.qr(X + 1e-2 * (rng.standard_normal(X.shape) + 1j * rng.standard_normal(X.shape)))
+    y, *_ = np.linalg.lstsq(Md @ Un, b, rcond=None)
+    xg = deflated_guess(cfg0_op.M, cfg0_op.Mdag, Un, b)
+    assert np.linalg.norm(xg - Un @ y) <= 1e-9 * np.linalg.norm(Un @ y)
+    assert np.linalg.norm(b - cfg0_op.M(xg)) < np.linalg.norm(b)
+    # from a starting point: least squares for the correction
     xt = 0.1 * b
-    x1 = gamma5_galerkin_guess(cfg0_op.M, cfg0_op.gamma5, X, HQ, b, x_tilde=xt)
-    corr = X @ (X.conj().T @ (x_star - xt))
-    assert np.linalg.norm(x1 - xt - corr) <= 1e-9 * np.linalg.norm(corr)
+    y, *_ = np.linalg.lstsq(Md @ Un, b - Md @ xt, rcond=None)
+    x1 = deflated_guess(cfg0_op.M, cfg0_op.Mdag, Un, b, x_tilde=xt)
+    assert np.linalg.norm(x1 - xt - Un @ y) <= 1e-9 * np.linalg.norm(Un @ y)
+    # exact eigenvectors: the Galerkin projection of Q = gamma5 M on span(X) ...
+    Q = _q_matrix(cfg0_op, Md)
+    HQ = X.conj().T @ Q @ X
+    x_gal = X @ np.linalg.solve(HQ, X.conj().T @ cfg0_op.gamma5(b))
+    xg = deflated_guess(cfg0_op.M, cfg0_op.Mdag, X, b)
+    assert np.linalg.norm(xg - x_gal) <= 1e-9 * np.linalg.norm(x_gal)
+    # ... which is the orthogonal projection of the exact solution
+    x_star = np.linalg.solve(Md, b)
+    proj = X @ (X.conj().T @ x_star)
+    assert np.linalg.norm(xg - proj) <= 1e-9 * np.linalg.norm(proj)
     # the boundary gamma5 agrees with the dense one
     assert np.allclose(cfg0_op.gamma5(b), apply_gamma5(b.reshape(4, 4, 4, 4, 4, 3)).reshape(-1))
 
@@ -133,8 +145,8 @@ def test_deflation_cuts_iterations_on_gamma5_M(cfg0_op, cfg0_dense, cfg0_rhs):
     small-magnitude part of Q's indefinite spectrum out of the initial residual."""
     b = cfg0_rhs
     U = cfg0_dense["X"][:, :24]
-    _, plain = deflated_bicgstab(cfg0_op.M, cfg0_op.gamma5, None, b, tol=1e-10)
-    x, defl = deflated_bicgstab(cfg0_op.M, cfg0_op.gamma5, U, b, tol=1e-10)
+    _, plain = deflated_bicgstab(cfg0_op.M, cfg0_op.Mdag, cfg0_op.gamma5, None, b, tol=1e-10)
+    x, defl = deflated_bicgstab(cfg0_op.M, cfg0_op.Mdag, cfg0_op.gamma5, U, b, tol=1e-10)
     assert plain["status"] == "ok" and defl["status"] == "ok"
     assert plain["guess_rel_res"] == 1.0 and defl["guess_rel_res"] < 1.0
     assert 2 * defl["iterations"] < plain["iterations"]
@@ -143,4 +155,4 @@ def test_deflation_cuts_iterations_on_gamma5_M(cfg0_op, cfg0_dense, cfg0_rhs):
     # the iteration on gamma5 M is BiCGSTAB on the matrix Q itself
     xq, q = bicgstab(lambda v: cfg0_op.gamma5(cfg0_op.M(v)), cfg0_op.gamma5(b), tol=1e-10)
     assert q["iterations"] == plain["iterations"] and np.array_equal(xq, np.asarray(
-        deflated_bicgstab(cfg0_op.M, cfg0_op.gamma5, None, b, tol=1e-10)[0]))
+        deflated_bicgstab(cfg0_op.M, cfg0_op.Mdag, cfg0_op.gamma5, None, b, tol=1e-10)[0]))
