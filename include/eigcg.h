@@ -156,6 +156,41 @@ int eigcg_deflate_init(eigcg_ctx* ctx, int32_t nrhs, const void* b_dev, void* x_
 /* Free everything the context owns. */
 int eigcg_destroy(eigcg_ctx* ctx);
 
+/* ---- deflated BiCGSTAB on the Dirac system ------------------------------------
+ * Section 1: the eigenvectors of A = M^H M are eigenvectors of the Hermitian
+ * Q = gamma5 M (Q^2 = A), so the bank built by eigCG can deflate a
+ * nonsymmetric solver for further right-hand sides.  eigcg_solve_bicgstab
+ * solves M x_i = b_i (in an odd-even context Mhat x_e = b_e on even-site
+ * fields) for nrhs columns, one after the other, in FP64 on the context's FP64
+ * operator, with BiCGSTAB (van der Vorst 1992; shadow residual r_0, half step
+ * taken when ||s|| meets the tolerance, restart from the current iterate when
+ * the recursive residual converged but the true one did not).
+ * flags: EIGCG_BICG_GAMMA5 iterates on Q x = gamma5 b instead of M x = b (same
+ * solution and residual norm; the form whose spectrum the bank deflates);
+ * EIGCG_BICG_DEFLATE first moves x to the minimiser of ||b - M x|| over
+ * x + span(U): since (M U)^H (M U) = U^H A U = H, this is the init-CG step of
+ * eq. (2.1) for A x = M^H b, x <- x + U H^{-1} U^H M^H (b - M x), with the bank's
+ * H and Cholesky factor (for exact eigenvectors it is the Galerkin projection
+ * of Q x = gamma5 b onto span(U)).  An empty bank leaves x unchanged.
+ * b_dev, x_dev: boundary spinor layout, x holds the starting guess on entry.
+ * max_iter <= 0: the context's max_iter.  Success means the FP64 true residual
+ * ||b - M x|| / ||b|| <= tol.  stats: nrhs entries or NULL.  Returns the worst
+ * per-column status (ENOTCONV at max_iter, EBREAKDOWN on a zero rho, r^_0^H v or
+ * t^H t, on non-finite scalars, or when H is not positive definite). */
+enum { EIGCG_BICG_GAMMA5 = 1, EIGCG_BICG_DEFLATE = 2 };
+typedef struct {
+  int32_t iters;          /* BiCGSTAB iterations (two applications of M each) */
+  int32_t restarts;       /* restarts after a true-residual check */
+  int32_t status;         /* EIGCG_OK, EIGCG_ENOTCONV or EIGCG_EBREAKDOWN */
+  int32_t bank_used;      /* bank columns in the deflated guess (0: none) */
+  double true_rel_res;    /* ||b - M x|| / ||b|| in FP64 */
+  double guess_rel_res;   /* the same for the starting guess after deflation */
+  double seconds;         /* wall time of this column */
+} eigcg_bicgstab_stats;
+int eigcg_solve_bicgstab(eigcg_ctx* ctx, int32_t nrhs, const void* b_dev, void* x_dev,
+                         double tol, int32_t flags, int32_t max_iter,
+                         eigcg_bicgstab_stats* stats);
+
 /* out = op(in) for op = M, M^H or A = M^H M in FP64 (test support); in an
  * odd-even context Mhat, Mhat^H and Mhat^H Mhat on even-site fields.
  * op + 3 (EIGCG_OP_INNER): the same with the inner-precision kernels of a

@@ -24,6 +24,7 @@ EIGCG_EBREAKDOWN, EIGCG_EHIP, EIGCG_EBUSY = -4, -5, -6
 EIGCG_FP64, EIGCG_MIXED_FP32, EIGCG_MIXED_HALF = 0, 1, 2
 EIGCG_MODE_CG, EIGCG_MODE_EIGCG, EIGCG_MODE_INITCG, EIGCG_MODE_AUTO = 0, 1, 2, 3
 EIGCG_OP_M, EIGCG_OP_MDAG, EIGCG_OP_A, EIGCG_OP_INNER = 0, 1, 2, 3
+EIGCG_BICG_GAMMA5, EIGCG_BICG_DEFLATE = 1, 2
 
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "ENOTCONV", -4: "EBREAKDOWN",
                 -5: "EHIP", -6: "EBUSY"}
@@ -69,6 +70,21 @@ class Stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class BicgstabStats(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int32),
+        ("restarts", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+        ("bank_used", ctypes.c_int32),
+        ("true_rel_res", ctypes.c_double),
+        ("guess_rel_res", ctypes.c_double),
+        ("seconds", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _VP = ctypes.c_void_p
 _I32 = ctypes.c_int32
 _DP = ctypes.POINTER(ctypes.c_double)
@@ -80,6 +96,8 @@ SIGNATURES = {
     "eigcg_solve": (_I32, [_VP, _I32, _VP, _VP, ctypes.c_double, _I32, ctypes.POINTER(Stats)]),
     "eigcg_deflate_init": (_I32, [_VP, _I32, _VP, _VP]),
     "eigcg_destroy": (_I32, [_VP]),
+    "eigcg_solve_bicgstab": (_I32, [_VP, _I32, _VP, _VP, ctypes.c_double, _I32, _I32,
+                                    ctypes.POINTER(BicgstabStats)]),
     "eigcg_apply": (_I32, [_VP, _I32, _I32, _VP, _VP]),
     "eigcg_schur_rhs": (_I32, [_VP, _I32, _VP, _VP]),
     "eigcg_schur_reconstruct": (_I32, [_VP, _I32, _VP, _VP, _VP]),
@@ -215,6 +233,22 @@ def eigcg_deflate_init(ctx, b, x):
     rc = LIB.eigcg_deflate_init(ctx, b.shape[0], _ptr(b), _ptr(x))
     if rc != EIGCG_OK:
         raise EigcgError(rc, eigcg_last_error(ctx))
+
+
+def eigcg_solve_bicgstab(ctx, b, x, tol, gamma5=True, deflate=True, max_iter=0):
+    """BiCGSTAB on M x = b (gamma5=False) or gamma5 M x = gamma5 b, from the
+    guess in x, after the bank's Galerkin guess when deflate is set.
+    Returns (status, [stats dict per right-hand side])."""
+    _check_field(b, "b")
+    _check_field(x, "x")
+    nrhs = b.shape[0]
+    flags = (EIGCG_BICG_GAMMA5 if gamma5 else 0) | (EIGCG_BICG_DEFLATE if deflate else 0)
+    st = (BicgstabStats * max(1, nrhs))()
+    rc = LIB.eigcg_solve_bicgstab(ctx, nrhs, _ptr(b), _ptr(x), float(tol), flags,
+                                  int(max_iter), st)
+    if rc in (EIGCG_EINVAL, EIGCG_ENOMEM, EIGCG_EHIP):
+        raise EigcgError(rc, eigcg_last_error(ctx))
+    return rc, [st[i].as_dict() for i in range(nrhs)]
 
 
 def eigcg_apply(ctx, op, inp, out):

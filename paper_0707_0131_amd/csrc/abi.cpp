@@ -162,6 +162,20 @@ int eigcg_deflate_init(eigcg_ctx* ctx, int32_t nrhs, const void* b_dev, void* x_
   });
 }
 
+int eigcg_solve_bicgstab(eigcg_ctx* ctx, int32_t nrhs, const void* b_dev, void* x_dev,
+                         double tol, int32_t flags, int32_t max_iter,
+                         eigcg_bicgstab_stats* stats) {
+  if (!ctx) return EIGCG_EINVAL;
+  if (nrhs < 0 || (nrhs > 0 && (!b_dev || !x_dev)))
+    return fail(ctx, EIGCG_EINVAL, "bad right-hand side arguments");
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(ctx, EIGCG_EINVAL, "tol must be > 0");
+  if (flags & ~(EIGCG_BICG_GAMMA5 | EIGCG_BICG_DEFLATE)) return fail(ctx, EIGCG_EINVAL, "bad flags");
+  if (nrhs == 0) return EIGCG_OK;
+  return guarded(ctx, [&] {
+    return eigcg::solve_bicgstab(ctx->c, nrhs, b_dev, x_dev, tol, flags, max_iter, stats);
+  });
+}
+
 int eigcg_apply(eigcg_ctx* ctx, int32_t op, int32_t nrhs, const void* in_dev, void* out_dev) {
   if (!ctx) return EIGCG_EINVAL;
   if (op < EIGCG_OP_M || op > EIGCG_OP_A + 3) return fail(ctx, EIGCG_EINVAL, "bad op");

@@ -1,0 +1,244 @@
+// BiCGSTAB on the Dirac system with a deflated starting guess from the eigCG
+// bank.  Section 1 of the paper: the eigenvectors of A = M^H M are also
+// eigenvectors of the Hermitian Q = gamma5 M (Q^2 = A), so the vectors eigCG
+// accumulates can deflate a nonsymmetric solver for later right-hand sides.
+//
+// The iteration is van der Vorst's BiCGSTAB (1992) with shadow residual r_0,
+// on M x = b or on Q x = gamma5 b.  The guess minimises ||b - M x|| over
+// x + span(U): the normal equations of that least-squares problem have the
+// matrix (M U)^H (M U) = U^H A U = H, the bank's own, so the guess is the
+// init-CG step of eq. (2.1) applied to A x = M^H b and reuses its Cholesky
+// factor.  For exact eigenvectors it equals the Galerkin projection of
+// Q x = gamma5 b onto span(U).
+//
+// Every vector operation runs in the library's kernels: the two-tile stencil,
+// BLAS1 (axpy, copy), the MFMA reduction product for inner products and the
+// MFMA tall products of the deflation.  The host holds only the recurrence's
+// scalars.
+
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <utility>
+#include <vector>
+
+#include "engine.h"
+
+namespace eigcg {
+namespace {
+
+constexpr int kMaxRestarts = 8;
+
+enum { kX, kB, kR, kRh, kP, kV, kS, kT, kFields };
+
+size_t prec_bytes(int prec) { return prec == kF64 ? 16 : (prec == kF32 ? 8 : 4); }
+
+double wall_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+bool finite(cplx z) { return std::isfinite(z.real()) && std::isfinite(z.imag()); }
+
+struct Bicg {
+  Ctx& c;
+  bool g5;               // iterate on gamma5 M
+  void* f[kFields];
+
+  Bicg(Ctx& c_, bool g5_) : c(c_), g5(g5_) {
+    const size_t fb = c.cs * prec_bytes(kF64);
+    if (!c.bs) {
+      c.bs = c.dalloc(fb * kFields);
+      // plane padding stays zero: kernels below never write it
+      c.check(hipMemsetAsync(c.bs, 0, fb * kFields, c.stream), "clear");
+    }
+    for (int i = 0; i < kFields; ++i) f[i] = col_ptr(c.bs, kF64, c.cs, i);
+  }
+
+  // y <- gamma5 y: in the chiral basis gamma5 = diag(1, 1, -1, -1), so the
+  // planes of spins 2 and 3 (the second half of the field) change sign
+  void gamma5(void* y) {
+    const size_t half = c.cs / 2;
+    void* lo = (char*)y + half * prec_bytes(kF64);
+    c.check(launch_axpy(kF64, 1, half, nullptr, -2.0, 0.0, lo, half, lo, half, c.stream),
+            "gamma5");
+  }
+  // out = M in, or gamma5 M in
+  void op(const void* in, void* out, bool with_g5) {
+    stencil_store(c, kF64, kOpM, 1, in, out);
+    if (with_g5) gamma5(out);
+  }
+  void axpy(cplx a, const void* x, void* y) {
+    c.check(launch_axpy(kF64, 1, c.cs, nullptr, a.real(), a.imag(), x, c.cs, y, c.cs, c.stream),
+            "axpy");
+  }
+  void copy(const void* x, void* y) {
+    c.check(launch_copy(kF64, kF64, 1, c.cs, x, c.cs, y, c.cs, c.stream), "copy");
+  }
+  void zero(void* y) {
+    c.check(hipMemsetAsync(y, 0, c.cs * prec_bytes(kF64), c.stream), "zero");
+  }
+  // G (K x N, ld K) = [in]^H [rc]
+  std::vector<cplx> dots(std::vector<const void*> in, std::vector<const void*> rc) {
+    std::vector<cplx> G;
+    reduce_to_host(c, kF64, (int)in.size(), (int)rc.size(), in, rc, G);
+    return G;
+  }
+  // r = rhs - Op x (rhs = f[kB]: b, or gamma5 b on the gamma5 system)
+  void residual(void* r) {
+    op(f[kX], f[kT], g5);
+    copy(f[kB], r);
+    axpy(-1.0, f[kT], r);
+  }
+};
+
+// x <- x + U H^{-1} U^H M^H (b - M x)
+void deflated_guess(Ctx& c, Bicg& B) {
+  B.residual(B.f[kR]);            // rhs - Op x
+  if (B.g5) B.gamma5(B.f[kR]);    // b - M x either way
+  stencil_store(c, kF64, kOpMdag, 1, B.f[kR], B.f[kT]);  // M^H (b - M x)
+  if (c.bank_prec == kF64) {
+    deflate_columns(c, kF64, 1, 1u, B.f[kX], B.f[kT]);
+  } else {  // FP32 bank: the products run in FP32, the correction is added in FP64
+    void* r32 = B.f[kR];
+    void* e32 = B.f[kV];
+    c.check(launch_copy(kF64, kF32, 1, c.cs, B.f[kT], c.cs, r32, c.cs, c.stream), "narrow");
+    c.check(hipMemsetAsync(e32, 0, c.cs * prec_bytes(kF32), c.stream), "zero");
+    deflate_columns(c, kF32, 1, 1u, e32, r32);
+    c.check(launch_accum_f32_into_f64(1, c.cs, B.f[kX], c.cs, e32, c.cs, c.stream), "accum");
+  }
+}
+
+int solve_column(Ctx& c, Bicg& B, double tol, int max_iter, bool defl,
+                 eigcg_bicgstab_stats& st) {
+  std::vector<cplx> G = B.dots({B.f[kB]}, {B.f[kB]});
+  const double bb = G[0].real();
+  if (!std::isfinite(bb)) throw ApiError{EIGCG_EINVAL, "right-hand side is not finite"};
+  if (bb == 0.0) {  // b = 0: x = 0
+    B.zero(B.f[kX]);
+    return EIGCG_OK;
+  }
+  const double bnorm = std::sqrt(bb);
+  const double stop = tol * bnorm;
+  if (B.g5) B.gamma5(B.f[kB]);
+  if (defl) {
+    deflated_guess(c, B);
+    st.bank_used = c.l;
+  }
+  int status = EIGCG_OK;
+  int it = 0;
+  bool first = true;
+  void* R = B.f[kR];
+  void* S = B.f[kS];
+  void* P = B.f[kP];
+  void* V = B.f[kV];
+  while (true) {
+    B.residual(R);
+    B.copy(R, B.f[kRh]);
+    G = B.dots({B.f[kRh], R}, {R});
+    cplx rho = G[0];
+    const double rr = G[1].real();
+    if (first) st.guess_rel_res = std::sqrt(rr) / bnorm;
+    first = false;
+    if (std::sqrt(rr) <= stop) break;
+    if (st.restarts > kMaxRestarts) break;
+    cplx rho_old(1.0, 0.0), alpha(1.0, 0.0), omega(1.0, 0.0);
+    B.zero(V);
+    B.zero(P);
+    bool conv = false;
+    while (it < max_iter) {
+      if (rho == 0.0 || omega == 0.0 || !finite(rho)) {
+        status = EIGCG_EBREAKDOWN;
+        break;
+      }
+      const cplx beta = (rho / rho_old) * (alpha / omega);
+      // p = r + beta (p - omega v), built in v's storage
+      B.axpy(-omega, V, P);
+      B.copy(R, V);
+      B.axpy(beta, P, V);
+      std::swap(P, V);
+      B.op(P, V, B.g5);
+      G = B.dots({B.f[kRh]}, {V});
+      const cplx rv = G[0];
+      if (rv == 0.0 || !finite(rv)) {
+        status = EIGCG_EBREAKDOWN;
+        break;
+      }
+      alpha = rho / rv;
+      B.copy(R, S);
+      B.axpy(-alpha, V, S);  // s = r - alpha v
+      ++it;
+      B.op(S, B.f[kT], B.g5);
+      G = B.dots({B.f[kT], S}, {S, B.f[kT]});  // t^H s, s^H s, t^H t, s^H t
+      const cplx ts = G[0], tt = G[2];
+      const double ss = G[1].real();
+      if (std::sqrt(ss) <= stop) {  // half step
+        B.axpy(alpha, P, B.f[kX]);
+        std::swap(R, S);
+        conv = true;
+        break;
+      }
+      if (tt == 0.0 || !finite(tt) || !finite(ts)) {
+        status = EIGCG_EBREAKDOWN;
+        break;
+      }
+      omega = ts / tt;
+      B.axpy(alpha, P, B.f[kX]);
+      B.axpy(omega, S, B.f[kX]);
+      B.axpy(-omega, B.f[kT], S);  // r = s - omega t
+      std::swap(R, S);
+      rho_old = rho;
+      G = B.dots({B.f[kRh], R}, {R});
+      rho = G[0];
+      if (std::sqrt(G[1].real()) <= stop) {
+        conv = true;
+        break;
+      }
+    }
+    if (!conv) {
+      if (status == EIGCG_OK) status = EIGCG_ENOTCONV;
+      break;
+    }
+    // the recursion met the tolerance: the true residual decides
+    B.residual(R);
+    G = B.dots({R}, {R});
+    if (std::sqrt(G[0].real()) <= stop) break;
+    ++st.restarts;
+  }
+  st.iters = it;
+  B.residual(R);
+  G = B.dots({R}, {R});
+  st.true_rel_res = std::sqrt(G[0].real()) / bnorm;
+  if (status == EIGCG_OK && !(st.true_rel_res <= tol)) status = EIGCG_ENOTCONV;
+  return status;
+}
+
+}  // namespace
+
+int solve_bicgstab(Ctx& c, int nrhs, const void* b_aos, void* x_aos, double tol, int flags,
+                   int max_iter, eigcg_bicgstab_stats* stats) {
+  const bool g5 = (flags & EIGCG_BICG_GAMMA5) != 0;
+  const bool defl = (flags & EIGCG_BICG_DEFLATE) != 0 && c.l > 0;
+  if (max_iter <= 0) max_iter = c.P.max_iter;
+  Bicg B(c, g5);
+  int worst = EIGCG_OK;
+  const size_t col_elems = (size_t)12 * c.g.V;
+  for (int j = 0; j < nrhs; ++j) {
+    const double t0 = wall_s();
+    eigcg_bicgstab_stats st{};
+    const double2* bsrc = (const double2*)b_aos + (size_t)j * col_elems;
+    double2* xdst = (double2*)x_aos + (size_t)j * col_elems;
+    c.check(launch_spinor_to_soa(bsrc, B.f[kB], kF64, &c.g, 1, c.cs, c.stream), "to soa");
+    c.check(launch_spinor_to_soa(xdst, B.f[kX], kF64, &c.g, 1, c.cs, c.stream), "to soa");
+    st.status = solve_column(c, B, tol, max_iter, defl, st);
+    c.check(launch_spinor_from_soa(B.f[kX], xdst, kF64, &c.g, 1, c.cs, c.stream), "from soa");
+    c.check(hipStreamSynchronize(c.stream), "sync");
+    st.seconds = wall_s() - t0;
+    if (stats) stats[j] = st;
+    if (st.status != EIGCG_OK && (worst == EIGCG_OK || st.status < worst)) worst = st.status;
+  }
+  return worst;
+}
+
+}  // namespace eigcg

@@ -290,6 +290,7 @@ void ctx_release(Ctx& c) {
   c.dfree(c.u32);
   c.dfree(c.eo_tmp64);
   c.dfree(c.eo_tmp32);
+  c.dfree(c.bs);
   void* v;
   v = c.d_st; c.dfree(v);
   v = c.d_hist; c.dfree(v);
@@ -393,7 +394,7 @@ static void ws_ensure(Ctx& c, Workspace& w, int prec, bool eig) {
   }
 }
 
-static void* col_ptr(void* base, int prec, size_t cs, size_t idx) {
+void* col_ptr(void* base, int prec, size_t cs, size_t idx) {
   return (char*)base + idx * cs * elem_bytes(prec);
 }
 
@@ -421,7 +422,7 @@ static StencilLaunch stencil_base(Ctx& c, int prec) {
 }
 
 // out = op(in) (op = M or M^H) on ncols internal fields
-static void stencil_store(Ctx& c, int prec, int op, int ncols, const void* in, void* out) {
+void stencil_store(Ctx& c, int prec, int op, int ncols, const void* in, void* out) {
   StencilLaunch L = stencil_base(c, prec);
   L.op = op;
   L.epi = kEpiStore;
@@ -558,8 +559,8 @@ void schur_reconstruct(Ctx& c, int nrhs, const void* b_full, const void* x_even,
 // ---------------------------------------------------------------------------
 
 // G (K x N) = In^H R on the device, copied to host (synchronous)
-static void reduce_to_host(Ctx& c, int prec, int K, int N, const std::vector<const void*>& in,
-                           const std::vector<const void*>& rc, std::vector<cplx>& G) {
+void reduce_to_host(Ctx& c, int prec, int K, int N, const std::vector<const void*>& in,
+                    const std::vector<const void*>& rc, std::vector<cplx>& G) {
   G.assign((size_t)K * N, cplx(0.0, 0.0));
   for (int k0 = 0; k0 < K; k0 += 256) {
     const int kk = std::min(256, K - k0);
@@ -584,9 +585,8 @@ static void reduce_to_host(Ctx& c, int prec, int K, int N, const std::vector<con
 
 // Out (+)= In * S with host S (K x N, ld K); uses the staging area at
 // element offset `slot` of d_small / h_small.  Synchronous staging.
-static void tall_from_host(Ctx& c, int prec, int K, int N, const std::vector<const void*>& in,
-                           const std::vector<void*>& out, const cplx* S, int beta_one,
-                           int negate) {
+void tall_from_host(Ctx& c, int prec, int K, int N, const std::vector<const void*>& in,
+                    const std::vector<void*>& out, const cplx* S, int beta_one, int negate) {
   for (int k0 = 0; k0 < K; k0 += 256) {
     const int kk = std::min(256, K - k0);
     // the kernel holds the kk x nn coefficients in 64 KB of LDS
@@ -626,7 +626,7 @@ static void ensure_chol(Ctx& c) {
 }
 
 // columns of ws (prec) given by mask; r holds b - A x on entry (prec storage)
-static void deflate_columns(Ctx& c, int prec, int ncols, uint32_t mask, void* x, const void* r) {
+void deflate_columns(Ctx& c, int prec, int ncols, uint32_t mask, void* x, const void* r) {
   if (c.l == 0) return;
   ensure_chol(c);
   const int l = c.l;

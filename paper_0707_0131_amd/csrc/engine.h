@@ -71,6 +71,7 @@ struct Ctx {
   std::vector<cplx> L;    // Cholesky factor of H(0:l, 0:l)
   bool chol_ok = false;
   double amax = 0.0;      // largest Ritz value seen (norm of A estimate)
+  void* bs = nullptr;      // BiCGSTAB on M or gamma5 M: eight FP64 work fields
   // scratch
   ColState* d_st = nullptr;
   ColState* h_st = nullptr;        // pinned: 2 x kMaxCols polls, kMaxCols upload slots
@@ -128,10 +129,26 @@ void bank_vectors(Ctx& c, int first, int count, void* out_aos);
 int bank_load(Ctx& c, int count, const void* vecs_aos);
 void bank_truncate(Ctx& c, int k);
 void bank_restore(Ctx& c, int l, const void* vecs_aos, const double* h_host);
+int solve_bicgstab(Ctx& c, int nrhs, const void* b_aos, void* x_aos, double tol, int flags,
+                   int max_iter, eigcg_bicgstab_stats* stats);
 double bench_kernels(Ctx& c, int what, int reps);
 bool auto_continue(int done, int left, const double* iters, const double* secs, double iter_ms,
                    int bank_room);
 void kernel_samples(Ctx& c, bool reset, double* out);
+
+// Engine helpers shared by the solver files (engine.cpp, bicgstab.cpp).
+void* col_ptr(void* base, int prec, size_t cs, size_t idx);
+// out = op(in) (op = kOpM or kOpMdag) on ncols internal fields
+void stencil_store(Ctx& c, int prec, int op, int ncols, const void* in, void* out);
+// G (K x N, ld K) = In^H R on the device, copied to the host (synchronous)
+void reduce_to_host(Ctx& c, int prec, int K, int N, const std::vector<const void*>& in,
+                    const std::vector<const void*>& rc, std::vector<cplx>& G);
+// init-CG deflation of the masked columns, eq. (2.1): x += U H^{-1} U^H r with
+// r = b - A x given (storage precision prec = the bank's)
+void deflate_columns(Ctx& c, int prec, int ncols, uint32_t mask, void* x, const void* r);
+// Out (+)= In * S with the host matrix S (K x N, ld K)
+void tall_from_host(Ctx& c, int prec, int K, int N, const std::vector<const void*>& in,
+                    const std::vector<void*>& out, const cplx* S, int beta_one, int negate);
 
 // Serving sessions (continuous batching over max_batch slots of one context).
 struct Session;
