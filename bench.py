@@ -223,6 +223,58 @@ def auto_leg(B, torch, g, bt, xt, mass=-0.58):
     return out
 
 
+def bicgstab_leg(B, torch, g, bt, xt, mass=-0.58, n_eig=N_EIG, n_rhs=4, max_iter=20000):
+    """Section 1's use of the bank for a nonsymmetric solver: after 24
+    Incremental eigCG solves, the next right-hand sides are solved for M x = b
+    by BiCGSTAB on M and on gamma5 M, with and without the bank's
+    least-squares guess, beside init-CG on A x = M^H b with the same bank."""
+    log(f"deflated BiCGSTAB (mass {mass})")
+    p = B.eigcg_default_params(dims=LATTICE, mass=mass, nev=NEV, m=M, max_bank=NBANK,
+                               max_iter=40000, check_every=16)
+    ctx = B.eigcg_create(p, g)
+    out = {"mass": mass, "rhs": n_rhs, "max_iter": max_iter, "runs": []}
+    try:
+        xt.zero_()
+        B.eigcg_solve(ctx, bt[:n_eig], xt[:n_eig], TOL, B.EIGCG_MODE_EIGCG)
+        out["bank"] = len(B.eigcg_bank_info(ctx)[0])
+        b = bt[n_eig:n_eig + n_rhs]
+        x = xt[n_eig:n_eig + n_rhs]
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = B.eigcg_solve(ctx, b, x, TOL, B.EIGCG_MODE_INITCG)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out["runs"].append({
+            "solver": "init-CG on A x = M^H b (reference)", "s_per_rhs": dt / n_rhs,
+            "mean_iters": sum(s["iters"] for s in st) / n_rhs,
+            "mean_matvecs": 2.0 * sum(s["iters"] for s in st) / n_rhs,
+            "max_true_rel_res": max(s["true_rel_res"] for s in st),
+            "failed": sum(1 for s in st if s["status"] != 0)})
+        for gamma5, deflate in ((False, False), (False, True), (True, True), (True, False)):
+            x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, st = B.eigcg_solve_bicgstab(ctx, b, x, TOL, gamma5=gamma5, deflate=deflate,
+                                           max_iter=max_iter)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            name = ("BiCGSTAB on gamma5 M" if gamma5 else "BiCGSTAB on M") + \
+                (", deflated" if deflate else "")
+            run = {"solver": name, "s_per_rhs": dt / n_rhs,
+                   "mean_iters": sum(s["iters"] for s in st) / n_rhs,
+                   "mean_matvecs": 2.0 * sum(s["iters"] for s in st) / n_rhs,
+                   "mean_guess_rel_res": sum(s["guess_rel_res"] for s in st) / n_rhs,
+                   "max_true_rel_res": max(s["true_rel_res"] for s in st),
+                   "failed": sum(1 for s in st if s["status"] != 0)}
+            out["runs"].append(run)
+            log(f"{name}: {run['s_per_rhs']:.3f} s/RHS, {run['mean_iters']:.0f} iterations, "
+                f"failed {run['failed']}")
+    finally:
+        B.eigcg_destroy(ctx)
+    return out
+
+
 FP64_MFMA_PEAK_TF = 78.6
 FP32_MFMA_PEAK_TF = 157.3
 
@@ -673,6 +725,9 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the 32^3x64 half-precision leg")
     ap.add_argument("--no-schur", action="store_true", help="skip the odd-even preconditioning leg")
     ap.add_argument("--no-auto", action="store_true", help="skip the automatic eigCG/init-CG leg")
+    ap.add_argument("--no-bicgstab", action="store_true", help="skip the deflated BiCGSTAB leg")
+    ap.add_argument("--bicgstab-only", action="store_true",
+                    help="only the deflated BiCGSTAB leg (no timed steps)")
     ap.add_argument("--serve-bank-rhs", type=int, default=N_EIG)
     ap.add_argument("--serve-requests", type=int, default=120)
     ap.add_argument("--stencil-variant", type=int, default=0,
@@ -717,6 +772,10 @@ def main():
         bt[i].copy_(torch.from_numpy(gaussian_rhs(LATTICE, 1000 + i)))
     xt = torch.zeros_like(bt)
     torch.cuda.synchronize()
+
+    if args.bicgstab_only:
+        print(json.dumps({"bicgstab": bicgstab_leg(B, torch, g, bt, xt)}))
+        return
 
     for w in range(args.warmup):
         log(f"warmup step {w}")
@@ -768,6 +827,10 @@ def main():
         fixed = [s for s in steps if s["mass"] == auto["mass"]]
         if fixed:
             auto["fixed_plan_rhs_per_s"] = nrhs / (fixed[0]["phase1_s"] + fixed[0]["phase2_s"])
+
+    bicg = None
+    if not args.no_bicgstab:
+        bicg = bicgstab_leg(B, torch, g, bt, xt)
 
     odd_even = None
     if not args.no_schur:
@@ -858,6 +921,7 @@ def main():
         "batching": batching,
         "odd_even": odd_even,
         "auto_switch": auto,
+        "bicgstab": bicg,
         "serving": serving,
         "large_lattice": large,
         "stencil_bench_lattice": roof_small,

@@ -12,9 +12,10 @@
 // Q x = gamma5 b onto span(U).
 //
 // Every vector operation runs in the library's kernels: the two-tile stencil,
-// BLAS1 (axpy, copy), the MFMA reduction product for inner products and the
-// MFMA tall products of the deflation.  The host holds only the recurrence's
-// scalars.
+// the fused BiCGSTAB updates and inner products (bicgstab_blas.hip), BLAS1 and
+// the MFMA products of the deflation.  The host holds only the recurrence's
+// scalars: three read-backs per iteration (r^_0^H v; t^H s, s^H s, t^H t;
+// r^_0^H r, r^H r).
 
 #include <hip/hip_runtime.h>
 
@@ -41,19 +42,28 @@ double wall_s() {
 
 bool finite(cplx z) { return std::isfinite(z.real()) && std::isfinite(z.imag()); }
 
+double2 d2(cplx z) { return make_double2(z.real(), z.imag()); }
+
+constexpr size_t kPartialBytes = sizeof(double2) * kBicgMaxDots * kBicgDotBlocks;
+
 struct Bicg {
   Ctx& c;
   bool g5;               // iterate on gamma5 M
   void* f[kFields];
+  double2* partial;      // inner-product partials
+  double2* out;          // inner products (kBicgMaxDots)
 
   Bicg(Ctx& c_, bool g5_) : c(c_), g5(g5_) {
     const size_t fb = c.cs * prec_bytes(kF64);
+    const size_t bytes = fb * kFields + kPartialBytes + sizeof(double2) * kBicgMaxDots;
     if (!c.bs) {
-      c.bs = c.dalloc(fb * kFields);
+      c.bs = c.dalloc(bytes);
       // plane padding stays zero: kernels below never write it
-      c.check(hipMemsetAsync(c.bs, 0, fb * kFields, c.stream), "clear");
+      c.check(hipMemsetAsync(c.bs, 0, bytes, c.stream), "clear");
     }
     for (int i = 0; i < kFields; ++i) f[i] = col_ptr(c.bs, kF64, c.cs, i);
+    partial = (double2*)((char*)c.bs + fb * kFields);
+    out = partial + kBicgMaxDots * kBicgDotBlocks;
   }
 
   // y <- gamma5 y: in the chiral basis gamma5 = diag(1, 1, -1, -1), so the
@@ -79,11 +89,20 @@ struct Bicg {
   void zero(void* y) {
     c.check(hipMemsetAsync(y, 0, c.cs * prec_bytes(kF64), c.stream), "zero");
   }
-  // G (K x N, ld K) = [in]^H [rc]
-  std::vector<cplx> dots(std::vector<const void*> in, std::vector<const void*> rc) {
-    std::vector<cplx> G;
-    reduce_to_host(c, kF64, (int)in.size(), (int)rc.size(), in, rc, G);
+  // the np inner products in `out`, read back (synchronous)
+  std::vector<cplx> fetch(int np) {
+    c.check(hipMemcpyAsync(c.h_norm, out, sizeof(double2) * np, hipMemcpyDeviceToHost, c.stream),
+            "memcpy");
+    c.check(hipStreamSynchronize(c.stream), "sync");
+    std::vector<cplx> G(np);
+    for (int i = 0; i < np; ++i) G[i] = cplx(c.h_norm[2 * i], c.h_norm[2 * i + 1]);
     return G;
+  }
+  // a_i^H b_i
+  std::vector<cplx> dots(std::vector<const void*> a, std::vector<const void*> b) {
+    c.check(launch_bicg_dots((int)a.size(), c.cs, a.data(), b.data(), partial, out, c.stream),
+            "dots");
+    return fetch((int)a.size());
   }
   // r = rhs - Op x (rhs = f[kB]: b, or gamma5 b on the gamma5 system)
   void residual(void* r) {
@@ -136,7 +155,7 @@ int solve_column(Ctx& c, Bicg& B, double tol, int max_iter, bool defl,
   while (true) {
     B.residual(R);
     B.copy(R, B.f[kRh]);
-    G = B.dots({B.f[kRh], R}, {R});
+    G = B.dots({B.f[kRh], R}, {R, R});
     cplx rho = G[0];
     const double rr = G[1].real();
     if (first) st.guess_rel_res = std::sqrt(rr) / bnorm;
@@ -153,11 +172,7 @@ int solve_column(Ctx& c, Bicg& B, double tol, int max_iter, bool defl,
         break;
       }
       const cplx beta = (rho / rho_old) * (alpha / omega);
-      // p = r + beta (p - omega v), built in v's storage
-      B.axpy(-omega, V, P);
-      B.copy(R, V);
-      B.axpy(beta, P, V);
-      std::swap(P, V);
+      c.check(launch_bicg_p(c.cs, P, R, V, d2(beta), d2(omega), c.stream), "p");
       B.op(P, V, B.g5);
       G = B.dots({B.f[kRh]}, {V});
       const cplx rv = G[0];
@@ -166,11 +181,10 @@ int solve_column(Ctx& c, Bicg& B, double tol, int max_iter, bool defl,
         break;
       }
       alpha = rho / rv;
-      B.copy(R, S);
-      B.axpy(-alpha, V, S);  // s = r - alpha v
+      c.check(launch_bicg_s(c.cs, S, R, V, d2(alpha), c.stream), "s");
       ++it;
       B.op(S, B.f[kT], B.g5);
-      G = B.dots({B.f[kT], S}, {S, B.f[kT]});  // t^H s, s^H s, t^H t, s^H t
+      G = B.dots({B.f[kT], S, B.f[kT]}, {S, S, B.f[kT]});  // t^H s, s^H s, t^H t
       const cplx ts = G[0], tt = G[2];
       const double ss = G[1].real();
       if (std::sqrt(ss) <= stop) {  // half step
@@ -184,12 +198,12 @@ int solve_column(Ctx& c, Bicg& B, double tol, int max_iter, bool defl,
         break;
       }
       omega = ts / tt;
-      B.axpy(alpha, P, B.f[kX]);
-      B.axpy(omega, S, B.f[kX]);
-      B.axpy(-omega, B.f[kT], S);  // r = s - omega t
-      std::swap(R, S);
+      // x += alpha p + omega s; r = s - omega t; rh^H r and r^H r
+      c.check(launch_bicg_xr(c.cs, B.f[kX], R, P, S, B.f[kT], B.f[kRh], d2(alpha), d2(omega),
+                             B.partial, B.out, c.stream),
+              "x, r");
+      G = B.fetch(2);
       rho_old = rho;
-      G = B.dots({B.f[kRh], R}, {R});
       rho = G[0];
       if (std::sqrt(G[1].real()) <= stop) {
         conv = true;

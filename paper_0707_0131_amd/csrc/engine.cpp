@@ -559,8 +559,8 @@ void schur_reconstruct(Ctx& c, int nrhs, const void* b_full, const void* x_even,
 // ---------------------------------------------------------------------------
 
 // G (K x N) = In^H R on the device, copied to host (synchronous)
-void reduce_to_host(Ctx& c, int prec, int K, int N, const std::vector<const void*>& in,
-                    const std::vector<const void*>& rc, std::vector<cplx>& G) {
+static void reduce_to_host(Ctx& c, int prec, int K, int N, const std::vector<const void*>& in,
+                           const std::vector<const void*>& rc, std::vector<cplx>& G) {
   G.assign((size_t)K * N, cplx(0.0, 0.0));
   for (int k0 = 0; k0 < K; k0 += 256) {
     const int kk = std::min(256, K - k0);
@@ -585,8 +585,9 @@ void reduce_to_host(Ctx& c, int prec, int K, int N, const std::vector<const void
 
 // Out (+)= In * S with host S (K x N, ld K); uses the staging area at
 // element offset `slot` of d_small / h_small.  Synchronous staging.
-void tall_from_host(Ctx& c, int prec, int K, int N, const std::vector<const void*>& in,
-                    const std::vector<void*>& out, const cplx* S, int beta_one, int negate) {
+static void tall_from_host(Ctx& c, int prec, int K, int N, const std::vector<const void*>& in,
+                           const std::vector<void*>& out, const cplx* S, int beta_one,
+                           int negate) {
   for (int k0 = 0; k0 < K; k0 += 256) {
     const int kk = std::min(256, K - k0);
     // the kernel holds the kk x nn coefficients in 64 KB of LDS

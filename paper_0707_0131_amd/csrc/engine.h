@@ -140,15 +140,9 @@ void kernel_samples(Ctx& c, bool reset, double* out);
 void* col_ptr(void* base, int prec, size_t cs, size_t idx);
 // out = op(in) (op = kOpM or kOpMdag) on ncols internal fields
 void stencil_store(Ctx& c, int prec, int op, int ncols, const void* in, void* out);
-// G (K x N, ld K) = In^H R on the device, copied to the host (synchronous)
-void reduce_to_host(Ctx& c, int prec, int K, int N, const std::vector<const void*>& in,
-                    const std::vector<const void*>& rc, std::vector<cplx>& G);
 // init-CG deflation of the masked columns, eq. (2.1): x += U H^{-1} U^H r with
 // r = b - A x given (storage precision prec = the bank's)
 void deflate_columns(Ctx& c, int prec, int ncols, uint32_t mask, void* x, const void* r);
-// Out (+)= In * S with the host matrix S (K x N, ld K)
-void tall_from_host(Ctx& c, int prec, int K, int N, const std::vector<const void*>& in,
-                    const std::vector<void*>& out, const cplx* S, int beta_one, int negate);
 
 // Serving sessions (continuous batching over max_batch slots of one context).
 struct Session;

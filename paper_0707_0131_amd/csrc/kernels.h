@@ -184,6 +184,25 @@ hipError_t launch_gemm_reduce(int prec, size_t n, int K, int N, const void* cons
                               const void* const* r_cols, double2* partial, size_t partial_elems,
                               double2* G, hipStream_t s);
 
+// BiCGSTAB vectors (FP64, n complex entries; bicgstab_blas.hip).
+// launch_bicg_dots: out[i] = a_i^H b_i for np <= kBicgMaxDots pairs, deterministic
+// (workgroup partials in `partial`, kBicgMaxDots * kBicgDotBlocks entries, then a
+// fixed-order sum).
+constexpr int kBicgMaxDots = 4;
+constexpr int kBicgDotBlocks = 1024;
+hipError_t launch_bicg_dots(int np, size_t n, const void* const* a, const void* const* b,
+                            double2* partial, double2* out, hipStream_t s);
+// p = r + beta (p - omega v)
+hipError_t launch_bicg_p(size_t n, void* p, const void* r, const void* v, double2 beta,
+                         double2 omega, hipStream_t s);
+// s = r - alpha v
+hipError_t launch_bicg_s(size_t n, void* sv, const void* r, const void* v, double2 alpha,
+                         hipStream_t s);
+// x += alpha p + omega s; r = s - omega t; out[0] = rh^H r, out[1] = r^H r
+hipError_t launch_bicg_xr(size_t n, void* x, void* r, const void* p, const void* sv,
+                          const void* t, const void* rh, double2 alpha, double2 omega,
+                          double2* partial, double2* out, hipStream_t s);
+
 // Test support: MFMA lane-layout probe (1024 doubles written to out_dev).
 hipError_t launch_mfma_probe(double* out_dev, hipStream_t s);
 

@@ -8,11 +8,12 @@ residual norm agrees to 1e-9 relative.
 
 On M the iterates are stable (a 1e-15 relative change of b moves the 25th
 iterate by 1e-11), so trajectories are compared over 25 iterations and the
-iteration counts to within five.  On the indefinite gamma5 M the method meets
+iteration counts to within eight.  On the indefinite gamma5 M the method meets
 near-breakdowns (r_0^H gamma5 M p close to zero) that amplify rounding: the same
 1e-15 change of b moves the third iterate by 4e-6 and the sixth by O(1) in the
-oracle itself.  There trajectories are compared over the first two iterations,
-and converged runs by their solution and their iteration count within 30 %.
+oracle itself, and its iteration count ranges over 966..1555.  There
+trajectories are compared over the first two iterations, and converged runs by
+their solution and their iteration count within 50 %.
 """
 
 import numpy as np
@@ -88,7 +89,9 @@ def test_converged_solution(B, cfg0_field, cfg0_op, cfg0_dense, gamma5):
 
 
 def _iters_band(n, gamma5):
-    return int(0.3 * n) + 5 if gamma5 else 5
+    # spread of the oracle's own counts under 1e-15 relative changes of b (six
+    # draws, 4^4 lattice): 186..194 on M, 966..1555 on gamma5 M
+    return int(0.5 * n) + 5 if gamma5 else 8
 
 
 def _bank(X, l):
