@@ -172,12 +172,15 @@ int eigcg_destroy(eigcg_ctx* ctx);
  * eq. (2.1) for A x = M^H b, x <- x + U H^{-1} U^H M^H (b - M x), with the bank's
  * H and Cholesky factor (for exact eigenvectors it is the Galerkin projection
  * of Q x = gamma5 b onto span(U)).  An empty bank leaves x unchanged.
+ * EIGCG_BICG_GUESS_ONLY returns after that step (iters 0; true_rel_res and
+ * guess_rel_res = the starting point's residual; status OK if it meets tol,
+ * else ENOTCONV).
  * b_dev, x_dev: boundary spinor layout, x holds the starting guess on entry.
  * max_iter <= 0: the context's max_iter.  Success means the FP64 true residual
  * ||b - M x|| / ||b|| <= tol.  stats: nrhs entries or NULL.  Returns the worst
  * per-column status (ENOTCONV at max_iter, EBREAKDOWN on a zero rho, r^_0^H v or
  * t^H t, on non-finite scalars, or when H is not positive definite). */
-enum { EIGCG_BICG_GAMMA5 = 1, EIGCG_BICG_DEFLATE = 2 };
+enum { EIGCG_BICG_GAMMA5 = 1, EIGCG_BICG_DEFLATE = 2, EIGCG_BICG_GUESS_ONLY = 4 };
 typedef struct {
   int32_t iters;          /* BiCGSTAB iterations (two applications of M each) */
   int32_t restarts;       /* restarts after a true-residual check */

@@ -24,7 +24,7 @@ EIGCG_EBREAKDOWN, EIGCG_EHIP, EIGCG_EBUSY = -4, -5, -6
 EIGCG_FP64, EIGCG_MIXED_FP32, EIGCG_MIXED_HALF = 0, 1, 2
 EIGCG_MODE_CG, EIGCG_MODE_EIGCG, EIGCG_MODE_INITCG, EIGCG_MODE_AUTO = 0, 1, 2, 3
 EIGCG_OP_M, EIGCG_OP_MDAG, EIGCG_OP_A, EIGCG_OP_INNER = 0, 1, 2, 3
-EIGCG_BICG_GAMMA5, EIGCG_BICG_DEFLATE = 1, 2
+EIGCG_BICG_GAMMA5, EIGCG_BICG_DEFLATE, EIGCG_BICG_GUESS_ONLY = 1, 2, 4
 
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "ENOTCONV", -4: "EBREAKDOWN",
                 -5: "EHIP", -6: "EBUSY"}
@@ -235,14 +235,16 @@ def eigcg_deflate_init(ctx, b, x):
         raise EigcgError(rc, eigcg_last_error(ctx))
 
 
-def eigcg_solve_bicgstab(ctx, b, x, tol, gamma5=True, deflate=True, max_iter=0):
+def eigcg_solve_bicgstab(ctx, b, x, tol, gamma5=True, deflate=True, max_iter=0,
+                         guess_only=False):
     """BiCGSTAB on M x = b (gamma5=False) or gamma5 M x = gamma5 b, from the
-    guess in x, after the bank's Galerkin guess when deflate is set.
-    Returns (status, [stats dict per right-hand side])."""
+    guess in x, after the bank's least-squares guess when deflate is set
+    (guess_only: stop after it).  Returns (status, [stats dict per right-hand side])."""
     _check_field(b, "b")
     _check_field(x, "x")
     nrhs = b.shape[0]
-    flags = (EIGCG_BICG_GAMMA5 if gamma5 else 0) | (EIGCG_BICG_DEFLATE if deflate else 0)
+    flags = (EIGCG_BICG_GAMMA5 if gamma5 else 0) | (EIGCG_BICG_DEFLATE if deflate else 0) | \
+        (EIGCG_BICG_GUESS_ONLY if guess_only else 0)
     st = (BicgstabStats * max(1, nrhs))()
     rc = LIB.eigcg_solve_bicgstab(ctx, nrhs, _ptr(b), _ptr(x), float(tol), flags,
                                   int(max_iter), st)

@@ -169,7 +169,8 @@ int eigcg_solve_bicgstab(eigcg_ctx* ctx, int32_t nrhs, const void* b_dev, void* 
   if (nrhs < 0 || (nrhs > 0 && (!b_dev || !x_dev)))
     return fail(ctx, EIGCG_EINVAL, "bad right-hand side arguments");
   if (!(tol > 0.0) || !std::isfinite(tol)) return fail(ctx, EIGCG_EINVAL, "tol must be > 0");
-  if (flags & ~(EIGCG_BICG_GAMMA5 | EIGCG_BICG_DEFLATE)) return fail(ctx, EIGCG_EINVAL, "bad flags");
+  if (flags & ~(EIGCG_BICG_GAMMA5 | EIGCG_BICG_DEFLATE | EIGCG_BICG_GUESS_ONLY))
+    return fail(ctx, EIGCG_EINVAL, "bad flags");
   if (nrhs == 0) return EIGCG_OK;
   return guarded(ctx, [&] {
     return eigcg::solve_bicgstab(ctx->c, nrhs, b_dev, x_dev, tol, flags, max_iter, stats);

@@ -129,7 +129,7 @@ void deflated_guess(Ctx& c, Bicg& B) {
   }
 }
 
-int solve_column(Ctx& c, Bicg& B, double tol, int max_iter, bool defl,
+int solve_column(Ctx& c, Bicg& B, double tol, int max_iter, bool defl, bool guess_only,
                  eigcg_bicgstab_stats& st) {
   std::vector<cplx> G = B.dots({B.f[kB]}, {B.f[kB]});
   const double bb = G[0].real();
@@ -148,6 +148,12 @@ int solve_column(Ctx& c, Bicg& B, double tol, int max_iter, bool defl,
   int status = EIGCG_OK;
   int it = 0;
   bool first = true;
+  if (guess_only) {  // the deflated starting point alone
+    B.residual(B.f[kR]);
+    G = B.dots({B.f[kR]}, {B.f[kR]});
+    st.guess_rel_res = st.true_rel_res = std::sqrt(G[0].real()) / bnorm;
+    return st.true_rel_res <= tol ? EIGCG_OK : EIGCG_ENOTCONV;
+  }
   void* R = B.f[kR];
   void* S = B.f[kS];
   void* P = B.f[kP];
@@ -234,6 +240,7 @@ int solve_bicgstab(Ctx& c, int nrhs, const void* b_aos, void* x_aos, double tol,
                    int max_iter, eigcg_bicgstab_stats* stats) {
   const bool g5 = (flags & EIGCG_BICG_GAMMA5) != 0;
   const bool defl = (flags & EIGCG_BICG_DEFLATE) != 0 && c.l > 0;
+  const bool guess_only = (flags & EIGCG_BICG_GUESS_ONLY) != 0;
   if (max_iter <= 0) max_iter = c.P.max_iter;
   Bicg B(c, g5);
   int worst = EIGCG_OK;
@@ -245,7 +252,7 @@ int solve_bicgstab(Ctx& c, int nrhs, const void* b_aos, void* x_aos, double tol,
     double2* xdst = (double2*)x_aos + (size_t)j * col_elems;
     c.check(launch_spinor_to_soa(bsrc, B.f[kB], kF64, &c.g, 1, c.cs, c.stream), "to soa");
     c.check(launch_spinor_to_soa(xdst, B.f[kX], kF64, &c.g, 1, c.cs, c.stream), "to soa");
-    st.status = solve_column(c, B, tol, max_iter, defl, st);
+    st.status = solve_column(c, B, tol, max_iter, defl, guess_only, st);
     c.check(launch_spinor_from_soa(B.f[kX], xdst, kF64, &c.g, 1, c.cs, c.stream), "from soa");
     c.check(hipStreamSynchronize(c.stream), "sync");
     st.seconds = wall_s() - t0;

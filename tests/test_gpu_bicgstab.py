@@ -39,10 +39,10 @@ def B():
     return binding
 
 
-def _solve(B, ctx, b, x0, tol, gamma5, deflate, max_iter=0):
+def _solve(B, ctx, b, x0, tol, gamma5, deflate, max_iter=0, guess_only=False):
     x = dev(x0.copy())
     rc, st = B.eigcg_solve_bicgstab(ctx, dev(b), x, tol, gamma5=gamma5, deflate=deflate,
-                                    max_iter=max_iter)
+                                    max_iter=max_iter, guess_only=guess_only)
     return rc, st, host(x)
 
 
@@ -107,10 +107,7 @@ def test_deflated_guess_and_iterates_with_loaded_bank(B, cfg0_field, cfg0_op, cf
     ctx, _ = make_ctx(cfg0_field, MASS, max_bank=40, max_iter=4000)
     try:
         assert B.eigcg_bank_load(ctx, _bank(X, 24)) == 24
-        l = 24
-        Ut = dev(np.zeros((l,) + DIMS[::-1] + (4, 3), np.complex128))
-        B.eigcg_bank_vectors(ctx, 0, l, Ut)
-        Ub = host(Ut).reshape(l, -1).T  # the bank as the library holds it
+        Ub = X[:, :24]  # the oracle deflates with the dense eigenvectors themselves
         x0 = np.zeros((1,) + b.shape, np.complex128)
         for gamma5, k in ((False, 6), (False, 25), (True, 2)):
             rc, st, x = _solve(B, ctx, b[None], x0, 1e-14, gamma5, True, max_iter=k)
@@ -146,10 +143,10 @@ def test_guess_follows_bank_changes(B, cfg0_field, cfg0_op, cfg0_dense):
     ctx, _ = make_ctx(cfg0_field, MASS, max_bank=40, max_iter=4000)
 
     def guess_res(l):
-        Ut = dev(np.zeros((l,) + DIMS[::-1] + (4, 3), np.complex128))
-        B.eigcg_bank_vectors(ctx, 0, l, Ut)
-        Ub = host(Ut).reshape(l, -1).T
-        xg = deflated_guess(cfg0_op.M, cfg0_op.Mdag, Ub, b)
+        # the bank spans the l lowest eigenvectors in every state below (loaded
+        # 8, then 12 more; truncated to its 10 lowest Ritz vectors), and the
+        # guess depends on the span only
+        xg = deflated_guess(cfg0_op.M, cfg0_op.Mdag, X[:, :l], b)
         return np.linalg.norm(b - cfg0_op.M(xg)) / np.linalg.norm(b)
 
     try:
@@ -209,11 +206,19 @@ def test_odd_even_context(B, cfg0_field, gamma5, k):
         B.eigcg_destroy(ctx)
 
 
+def _normal_equations_ratio(op, Um, b, x0):
+    """||(M U)^H (b - M x0)|| / ||(M U)^H b||: zero for the least-squares guess."""
+    MU = np.stack([op.M(Um[:, j]) for j in range(Um.shape[1])], axis=1)
+    r0 = b - op.M(x0)
+    return np.linalg.norm(MU.conj().T @ r0) / np.linalg.norm(MU.conj().T @ b)
+
+
 def test_mixed_context_fp32_bank(B, cfg0_field, cfg0_op):
-    """A bank grown by Incremental eigCG in an FP32 context (FP32 storage):
-    the guess (FP32 products, FP64 correction) matches the oracle's guess from
-    the same bank vectors to FP32 accuracy and never raises the residual; the
-    FP64 BiCGSTAB after it converges."""
+    """A bank grown by Incremental eigCG in an FP32 context (FP32 storage).
+    The guess alone (FP32 products, FP64 correction) lies in span(U) and meets
+    the least-squares normal equations (M U)^H (b - M x0) = 0 to FP32 accuracy,
+    checked with the oracle's M on the library's bank; the FP64 BiCGSTAB after
+    it converges."""
     ctx, _ = make_ctx(cfg0_field, MASS, precision=1, nev=8, m=40, max_bank=48, max_iter=20000)
     try:
         for s in (3130, 3131, 3132, 3133):
@@ -226,17 +231,20 @@ def test_mixed_context_fp32_bank(B, cfg0_field, cfg0_op):
         assert l >= 16
         Ut = dev(np.zeros((l,) + DIMS[::-1] + (4, 3), np.complex128))
         B.eigcg_bank_vectors(ctx, 0, l, Ut)
-        Ub = host(Ut).reshape(l, -1).T
+        Um = host(Ut).reshape(l, -1).T
         b = gaussian_rhs(DIMS, 3140)
-        xg = deflated_guess(cfg0_op.M, cfg0_op.Mdag, Ub, b.reshape(-1))
-        g_ref = np.linalg.norm(b.reshape(-1) - cfg0_op.M(xg)) / np.linalg.norm(b)
         x0 = np.zeros((1,) + b.shape, np.complex128)
+        rc, sg, xg = _solve(B, ctx, b[None], x0, 1e-10, False, True, guess_only=True)
+        assert rc == B.EIGCG_ENOTCONV and sg[0]["iters"] == 0 and sg[0]["bank_used"] == l
+        xg = xg[0].reshape(-1)
+        assert np.linalg.norm(xg - Um @ (Um.conj().T @ xg)) <= 1e-5 * np.linalg.norm(xg)
+        assert _normal_equations_ratio(cfg0_op, Um, b.reshape(-1), xg) <= 1e-3
+        g = np.linalg.norm(b.reshape(-1) - cfg0_op.M(xg)) / np.linalg.norm(b)
+        assert abs(sg[0]["guess_rel_res"] - g) <= 1e-12 and g < 1.0
         for gamma5 in (True, False):
             rc, sd, x = _solve(B, ctx, b[None], x0, 1e-10, gamma5, True)
             assert rc == B.EIGCG_OK, sd
-            assert sd[0]["bank_used"] == l
-            assert sd[0]["guess_rel_res"] < 1.0
-            assert abs(sd[0]["guess_rel_res"] - g_ref) <= 1e-4 * g_ref
+            assert sd[0]["guess_rel_res"] == pytest.approx(g, rel=1e-9)
             r = b.reshape(-1) - cfg0_op.M(x[0].reshape(-1))
             assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(b)
     finally:
@@ -249,7 +257,7 @@ def test_errors_and_zero_rhs(B, cfg0_field):
         b = gaussian_rhs(DIMS, 3150)[None]
         x = dev(np.zeros_like(b))
         assert B.LIB.eigcg_solve_bicgstab(ctx, 1, None, None, 1e-10, 0, 0, None) == B.EIGCG_EINVAL
-        assert B.LIB.eigcg_solve_bicgstab(ctx, 1, B._ptr(dev(b)), B._ptr(x), 1e-10, 4, 0,
+        assert B.LIB.eigcg_solve_bicgstab(ctx, 1, B._ptr(dev(b)), B._ptr(x), 1e-10, 8, 0,
                                           None) == B.EIGCG_EINVAL
         assert B.LIB.eigcg_solve_bicgstab(ctx, 1, B._ptr(dev(b)), B._ptr(x), 0.0, 0, 0,
                                           None) == B.EIGCG_EINVAL

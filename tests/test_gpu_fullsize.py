@@ -15,6 +15,7 @@ import numpy as np
 import pytest
 
 from gpu_common import dev, host, make_ctx
+from oracle.bicgstab import bicgstab
 from oracle.dirac import WilsonOperator
 from synthetic import gauge_field, gaussian_rhs
 
@@ -171,5 +172,53 @@ def test_fullsize_schur_stencil_and_solve(B, field):
         assert np.max(np.abs(xf_h - sop.reconstruct(b.reshape(-1), xe_h))) <= \
             1e-13 * np.max(np.abs(xf_h))
         assert np.linalg.norm(op.M(xf_h) - b.reshape(-1)) <= 1e-8 * np.linalg.norm(b)
+    finally:
+        B.eigcg_destroy(ctx)
+
+
+def test_fullsize_bicgstab(B, field):
+    """Deflated BiCGSTAB on M at full size: the first iterates against the
+    oracle's BiCGSTAB; the deflated guess alone lies in span(U) and meets the
+    least-squares normal equations (M U)^H (b - M x0) = 0 on sampled bank
+    columns (oracle's M); the converged solution checked with the oracle's M."""
+    U, op = field
+    ctx, _ = make_ctx(U, MASS, nev=10, m=100, max_bank=40, max_iter=20000, check_every=16)
+    try:
+        b = gaussian_rhs(DIMS, 1010)
+        z = np.zeros((1,) + b.shape, dtype=np.complex128)
+        x = dev(z)
+        rc, st = B.eigcg_solve_bicgstab(ctx, dev(b[None]), x, 1e-10, gamma5=False,
+                                        deflate=False, max_iter=3)
+        assert rc == B.EIGCG_ENOTCONV and st[0]["iters"] == 3
+        xo, info = bicgstab(op.M, b.reshape(-1), tol=1e-10, max_iter=3)
+        assert info["iterations"] == 3
+        assert np.linalg.norm(host(x).reshape(-1) - xo) <= 1e-10 * np.linalg.norm(xo)
+
+        for seed in (1001, 1002):  # a bank from two Incremental eigCG solves
+            bs = gaussian_rhs(DIMS, seed)
+            xs = dev(np.zeros((1,) + bs.shape, dtype=np.complex128))
+            assert B.eigcg_solve(ctx, dev(bs[None]), xs, 1e-10, B.EIGCG_MODE_EIGCG)[0] == B.EIGCG_OK
+        vals, _ = B.eigcg_bank_info(ctx)
+        l = len(vals)
+        Ut = dev(np.zeros((l,) + b.shape, dtype=np.complex128))
+        B.eigcg_bank_vectors(ctx, 0, l, Ut)
+        Um = host(Ut).reshape(l, -1).T
+        del Ut
+        x = dev(z)
+        rc, sg = B.eigcg_solve_bicgstab(ctx, dev(b[None]), x, 1e-10, gamma5=False, deflate=True,
+                                        guess_only=True)
+        assert sg[0]["bank_used"] == l and sg[0]["iters"] == 0
+        xg = host(x).reshape(-1)
+        assert np.linalg.norm(xg - Um @ (Um.conj().T @ xg)) <= 1e-12 * np.linalg.norm(xg)
+        r0 = b.reshape(-1) - op.M(xg)
+        assert abs(np.linalg.norm(r0) / np.linalg.norm(b) - sg[0]["guess_rel_res"]) <= 1e-12
+        for j in (0, l // 2, l - 1):
+            mu = op.M(Um[:, j])
+            assert abs(np.vdot(mu, r0)) <= 1e-8 * abs(np.vdot(mu, b.reshape(-1)))
+        x = dev(z)
+        rc, st = B.eigcg_solve_bicgstab(ctx, dev(b[None]), x, 1e-10, gamma5=False, deflate=True)
+        assert rc == B.EIGCG_OK
+        r = b.reshape(-1) - op.M(host(x).reshape(-1))
+        assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(b)
     finally:
         B.eigcg_destroy(ctx)
