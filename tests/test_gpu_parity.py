@@ -139,15 +139,18 @@ def test_eigcg_full_run_cfg0(B, cfg0):
     from oracle.dense import dense_A
     U, op, b = cfg0
     xo, _, _, io = eigcg(op.A, b.reshape(-1), 10, 40, tol=1e-8)
+    # the oracle's iterates one step either side of its own stop
+    k = io["iterations"]
+    cands = {k: xo}
+    for kk in (k - 1, k + 1):
+        cands[kk] = eigcg(op.A, b.reshape(-1), 10, 40, tol=0.0, max_iter=kk)[0]
     ctx, _ = make_ctx(U, -0.2, nev=10, m=40, max_bank=40)
     try:
         x = dev(np.zeros((1,) + b.shape, dtype=np.complex128))
         rc, st = B.eigcg_solve(ctx, dev(b[None]), x, 1e-8, B.EIGCG_MODE_EIGCG)
         assert rc == B.EIGCG_OK
-        assert abs(st[0]["iters"] - io["iterations"]) <= 1
-        if st[0]["iters"] != io["iterations"]:
-            xo, _, _, io = eigcg(op.A, b.reshape(-1), 10, 40, tol=0.0, max_iter=st[0]["iters"])
-        assert rel(host(x)[0].reshape(-1), xo) <= 1e-10
+        assert st[0]["iters"] in cands
+        assert rel(host(x)[0].reshape(-1), cands[st[0]["iters"]]) <= 1e-10
         vals, res = B.eigcg_bank_info(ctx, residuals=True)
         A, _ = dense_A(op)
         lam = np.linalg.eigvalsh(A)
@@ -222,6 +225,11 @@ def test_incremental_eigcg_bank(B, cfg0):
     U, op, _ = cfg0
     bs = gaussian_rhs_block((4, 4, 4, 4), [1000, 1001, 1002])
     xs, Uo, Ho, infos = incremental_eigcg(op.A, list(bs.reshape(3, -1)), 4, 30, tol=1e-8)
+    # the oracle's first-solve iterates one step either side of its own stop
+    k0 = infos[0]["iterations"]
+    first = {k0: xs[0]}
+    for kk in (k0 - 1, k0 + 1):
+        first[kk] = eigcg(op.A, bs[0].reshape(-1), 4, 30, tol=0.0, max_iter=kk)[0]
     ctx, _ = make_ctx(U, -0.2, nev=4, m=30, max_bank=12)
     try:
         its = []
@@ -239,9 +247,8 @@ def test_incremental_eigcg_bank(B, cfg0):
             # their 1e-8 residuals fix
             ref = xs[i]
             if i == 0:
-                assert abs(its[0] - infos[0]["iterations"]) <= 1
-                if its[0] != infos[0]["iterations"]:
-                    ref = eigcg(op.A, bs[0].reshape(-1), 4, 30, tol=0.0, max_iter=its[0])[0]
+                assert its[0] in first
+                ref = first[its[0]]
             assert rel(host(x)[0].reshape(-1), ref) <= (1e-10 if i == 0 else 1e-6)
         assert its[2] < its[0]
         vals, _ = B.eigcg_bank_info(ctx)
