@@ -60,7 +60,8 @@ def test_default_params_and_validation(B):
     for fn, args in [("eigcg_schur_rhs", (None, 1, None, None)),
                      ("eigcg_schur_reconstruct", (None, 1, None, None, None)),
                      ("eigcg_bank_truncate", (None, 1)),
-                     ("eigcg_bank_restore", (None, 1, None, None))]:
+                     ("eigcg_bank_restore", (None, 1, None, None)),
+                     ("eigcg_solve_bicgstab", (None, 1, None, None, 1e-10, 0, 0, None))]:
         assert getattr(B.LIB, fn)(*args) == B.EIGCG_EINVAL, fn
     with pytest.raises(KeyError):
         B.eigcg_default_params(no_such_field=1)
