@@ -223,7 +223,11 @@ def auto_leg(B, torch, g, bt, xt, mass=-0.58):
     return out
 
 
-def bicgstab_leg(B, torch, g, bt, xt, mass=-0.58, n_eig=N_EIG, n_rhs=4, max_iter=20000):
+BICG_SOLVERS = ((False, False), (False, True), (True, True), (True, False))
+
+
+def bicgstab_leg(B, torch, g, bt, xt, mass=-0.58, n_eig=N_EIG, n_rhs=4, max_iter=20000,
+                 solvers=BICG_SOLVERS):
     """Section 1's use of the bank for a nonsymmetric solver: after 24
     Incremental eigCG solves, the next right-hand sides are solved for M x = b
     by BiCGSTAB on M and on gamma5 M, with and without the bank's
@@ -251,7 +255,7 @@ def bicgstab_leg(B, torch, g, bt, xt, mass=-0.58, n_eig=N_EIG, n_rhs=4, max_iter
             "mean_matvecs": 2.0 * sum(s["iters"] for s in st) / n_rhs,
             "max_true_rel_res": max(s["true_rel_res"] for s in st),
             "failed": sum(1 for s in st if s["status"] != 0)})
-        for gamma5, deflate in ((False, False), (False, True), (True, True), (True, False)):
+        for gamma5, deflate in solvers:
             x.zero_()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -728,6 +732,9 @@ def main():
     ap.add_argument("--no-bicgstab", action="store_true", help="skip the deflated BiCGSTAB leg")
     ap.add_argument("--bicgstab-only", action="store_true",
                     help="only the deflated BiCGSTAB leg (no timed steps)")
+    ap.add_argument("--bicgstab-short", action="store_true",
+                    help="with --bicgstab-only: one right-hand side, a bank from 4 eigCG "
+                         "solves, BiCGSTAB on M only (short runs for counter collection)")
     ap.add_argument("--serve-bank-rhs", type=int, default=N_EIG)
     ap.add_argument("--serve-requests", type=int, default=120)
     ap.add_argument("--stencil-variant", type=int, default=0,
@@ -774,7 +781,8 @@ def main():
     torch.cuda.synchronize()
 
     if args.bicgstab_only:
-        print(json.dumps({"bicgstab": bicgstab_leg(B, torch, g, bt, xt)}))
+        kw = dict(n_eig=4, n_rhs=1, solvers=BICG_SOLVERS[:2]) if args.bicgstab_short else {}
+        print(json.dumps({"bicgstab": bicgstab_leg(B, torch, g, bt, xt, **kw)}))
         return
 
     for w in range(args.warmup):
