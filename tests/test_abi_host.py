@@ -200,3 +200,15 @@ def test_auto_switch_grows_with_the_number_of_rhs(B):
                 iters.append(n)
                 secs.append((1.3 * n + 20.0 * k) * iter_ms * 1e-3)
             assert total(s, len(iters)) <= 1.05 * best, (s, len(iters))
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus N > 1 exits with a message before
+    touching a device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
