@@ -97,7 +97,9 @@ typedef struct {
   int32_t reliable_every; /* mixed precision: FP64 reliable update period */
   int32_t max_iter;       /* per right-hand side */
   double restart_tol;     /* init-CG restart threshold on ||r||/||b||:
-                             0 -> 10 eps ||A|| (Section 5.3), < 0 -> never */
+                             0 -> 10 u ||A|| with u = 2^-24, single precision as
+                             in the paper's runs (Sections 5.1, 5.3; ||A|| = the
+                             largest Ritz value seen), < 0 -> never */
   uint64_t hbm_budget;    /* bytes this context may allocate, 0 = no cap */
   int32_t compress_links; /* 1: store links as two rows when they are SU(3) */
   int32_t check_every;    /* iterations between host convergence polls */

@@ -13,8 +13,9 @@ Section 5.3 restarts init-CG once, when the residual norm comes within an
 order of magnitude of machine precision scaled by the norm of the matrix,
 deflating the current iterate again (the deflation cost is paid twice,
 Section 5.5).  Reading: the restart fires when ``||r|| / ||b||`` first falls
-to ``restart_tol``; the caller chooses ``restart_tol`` (``10 eps ||A||`` with
-``||A||`` estimated by the largest known Ritz value, or 0 for no restart).
+to ``restart_tol``; the caller chooses ``restart_tol`` (``10 u ||A||`` with the
+single-precision unit roundoff ``u = 2^-24`` of the paper's runs, Section 5.1, and
+``||A||`` estimated by the largest known Ritz value; or 0 for no restart).
 """
 
 from __future__ import annotations

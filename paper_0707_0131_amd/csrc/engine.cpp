@@ -1384,10 +1384,13 @@ double restart_tol_for(const Ctx& c, int mode, int scheme) {
   if (mode != EIGCG_MODE_INITCG || c.P.restart_tol < 0) return 0.0;
   if (c.P.restart_tol > 0) return c.P.restart_tol;
   // Section 5.3: within an order of magnitude of machine precision scaled by
-  // the norm of A, estimated by the largest Ritz value seen (or (8+|m|)^2)
+  // the norm of A.  The paper's runs are in single precision (Section 5.1) and
+  // its convergence figure restarts close to single machine precision, which is
+  // where a bank of Ritz vectors of that accuracy stops deflating: 10 u ||A||
+  // with u = 2^-24, ||A|| estimated by the largest Ritz value seen (or (8+|m|)^2)
   const double am = std::fabs(c.P.mass);
   const double anorm = c.amax > 0 ? c.amax : (8.0 + am) * (8.0 + am);
-  return 10.0 * 2.220446049250313e-16 * anorm;
+  return 10.0 * 5.9604644775390625e-8 * anorm;
 }
 
 }  // namespace

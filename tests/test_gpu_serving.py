@@ -39,8 +39,10 @@ def _setup(B, precision, max_batch, nbank=12):
         op = WilsonOperator(U, mass)
         A, _ = dense_A(op)
         lam, X = np.linalg.eigh(A)
+        # no init-CG restart: the comparison below is with the oracle's init-CG
+        # without one (mixed contexts refine instead and ignore it)
         ctx, g = make_ctx(U, mass, precision=precision, max_batch=max_batch, max_bank=nbank,
-                          nev=6, m=20, max_iter=4000)
+                          nev=6, m=20, max_iter=4000, restart_tol=-1.0)
         shape = (dims[3], dims[2], dims[1], dims[0], 4, 3)
         B.eigcg_bank_load(ctx, dev(X[:, :nbank].T.reshape((nbank,) + shape).copy()))
         ctxs.append(ctx)
