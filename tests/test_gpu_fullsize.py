@@ -222,3 +222,36 @@ def test_fullsize_bicgstab(B, field):
         assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(b)
     finally:
         B.eigcg_destroy(ctx)
+
+
+LARGE = (32, 32, 32, 64)
+
+
+def test_fullsize_largest_lattice_operators(B):
+    """32^3 x 64 (the largest configuration, eps 0.5, seed 4): the FP64 stencil
+    M and M^H of the autotuned launch element-wise against the oracle
+    (<= 1e-13), and the 16-bit inner operator that its deflated solves iterate
+    with (half-precision context, two-row SU(3) links, 12 columns per launch)
+    within 4e-3 of the largest entry of the oracle's M."""
+    U = gauge_field(LARGE, 0.5, 4)
+    op = WilsonOperator(U, MASS)
+    psi = gaussian_rhs(LARGE, 4242)[None]
+    ref_m = op.M(psi.reshape(-1)).reshape(psi.shape)
+    ctx, g = make_ctx(U, MASS)
+    try:
+        inp = dev(psi)
+        out = dev(np.zeros_like(psi))
+        B.eigcg_apply(ctx, B.EIGCG_OP_M, inp, out)
+        assert np.max(np.abs(host(out) - ref_m)) <= 1e-13 * np.max(np.abs(ref_m))
+        ref_d = op.Mdag(psi.reshape(-1)).reshape(psi.shape)
+        B.eigcg_apply(ctx, B.EIGCG_OP_MDAG, inp, out)
+        assert np.max(np.abs(host(out) - ref_d)) <= 1e-13 * np.max(np.abs(ref_d))
+    finally:
+        B.eigcg_destroy(ctx)
+    del g
+    ctx, g = make_ctx(U, MASS, precision=2, compress_links=1, max_batch=12)
+    try:
+        B.eigcg_apply(ctx, B.EIGCG_OP_INNER + B.EIGCG_OP_M, inp, out)
+        assert np.max(np.abs(host(out) - ref_m)) <= 4e-3 * np.max(np.abs(ref_m))
+    finally:
+        B.eigcg_destroy(ctx)
