@@ -224,18 +224,19 @@ def test_fullsize_bicgstab(B, field):
         B.eigcg_destroy(ctx)
 
 
-LARGE = (32, 32, 32, 64)
-
-
-def test_fullsize_largest_lattice_operators(B):
-    """32^3 x 64 (the largest configuration, eps 0.5, seed 4): the FP64 stencil
-    M and M^H of the autotuned launch element-wise against the oracle
-    (<= 1e-13), and the 16-bit inner operator that its deflated solves iterate
-    with (half-precision context, two-row SU(3) links, 12 columns per launch)
-    within 4e-3 of the largest entry of the oracle's M."""
-    U = gauge_field(LARGE, 0.5, 4)
+@pytest.mark.parametrize("dims,seed,precision,tol", [
+    ((32, 32, 32, 64), 4, 2, 4e-3),   # the largest configuration: 16-bit inner storage
+    ((24, 24, 24, 48), 3, 1, 5e-6),   # the serving field above the MALL: FP32 inner
+])
+def test_fullsize_largest_lattice_operators(B, dims, seed, precision, tol):
+    """Lattices of the larger configurations (eps 0.5): the FP64 stencil M and
+    M^H of the autotuned launch element-wise against the oracle (<= 1e-13), and
+    the inner operator that their deflated solves iterate with (16-bit or FP32
+    storage, two-row SU(3) links, 12 columns per launch) within its storage
+    rounding of the largest entry of the oracle's M."""
+    U = gauge_field(dims, 0.5, seed)
     op = WilsonOperator(U, MASS)
-    psi = gaussian_rhs(LARGE, 4242)[None]
+    psi = gaussian_rhs(dims, 4242)[None]
     ref_m = op.M(psi.reshape(-1)).reshape(psi.shape)
     ctx, g = make_ctx(U, MASS)
     try:
@@ -249,9 +250,9 @@ def test_fullsize_largest_lattice_operators(B):
     finally:
         B.eigcg_destroy(ctx)
     del g
-    ctx, g = make_ctx(U, MASS, precision=2, compress_links=1, max_batch=12)
+    ctx, g = make_ctx(U, MASS, precision=precision, compress_links=1, max_batch=12)
     try:
         B.eigcg_apply(ctx, B.EIGCG_OP_INNER + B.EIGCG_OP_M, inp, out)
-        assert np.max(np.abs(host(out) - ref_m)) <= 4e-3 * np.max(np.abs(ref_m))
+        assert np.max(np.abs(host(out) - ref_m)) <= tol * np.max(np.abs(ref_m))
     finally:
         B.eigcg_destroy(ctx)
