@@ -212,3 +212,31 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_auto_switch_against_the_papers_table(B):
+    """Section 5.5 tabulates the best number of Incremental eigCG solves for
+    6 to 48 right-hand sides (tests/golden).  The rule, run on the model of the
+    paper's iteration decay used above, picks counts within a factor of two of
+    the table's and growing with the number of right-hand sides like it."""
+    import json
+    here = os.path.dirname(os.path.abspath(__file__))
+    with open(os.path.join(here, "golden", "optimal_incremental_eigcg_rhs.json")) as f:
+        table = json.load(f)
+    iter_ms = 1.0
+
+    def eig_secs(k):
+        return (1.3 * _model(k) + 20.0 * k) * iter_ms * 1e-3
+
+    chosen = []
+    for s in table["total_rhs"]:
+        iters, secs = [], []
+        for k in range(1, s + 1):
+            if not B.eigcg_host_auto_continue(iters, secs, s - k + 1, iter_ms, 100):
+                break
+            iters.append(_model(k))
+            secs.append(eig_secs(k))
+        chosen.append(len(iters))
+    for got, paper in zip(chosen, table["optimal_incremental_rhs"]):
+        assert paper / 2 <= got <= 2 * paper, (chosen, table)
+    assert chosen == sorted(chosen) and chosen[-1] > chosen[0]
