@@ -32,7 +32,8 @@
  *                      inner solves.
  *
  * Odd-even preconditioning (params.schur = 1; the operator of the paper's
- * lattice runs, Sections 6 and 7, which halves the system): sites split by the
+ * lattice runs, compared in Section 3.1 and used in the QCD tests of Section
+ * 5.1, which halves the system): sites split by the
  * parity of x + y + z + t, D couples opposite parities only, and with
  * d = 4 + m_q the context's operator becomes A = Mhat^H Mhat on the even
  * sites, where Mhat = d - D_eo D_oe / (4 d) is the Schur complement of the
@@ -131,6 +132,9 @@ typedef struct {
   int32_t nritz;          /* Ritz pairs produced by eigCG (EIGCG mode) */
   int32_t mode_used;      /* mode this right-hand side was solved in (EIGCG_MODE_AUTO
                              resolves to EIGCG or INITCG) */
+  int32_t first_leg_iters;/* FP64 init-CG: iterations completed when the restart of
+                             Section 5.3 re-deflated the iterate (= iters when it did
+                             not restart); other schemes: iters */
 } eigcg_stats;
 
 /* Fill *p with defaults (nev 10, m 100, bank 240, FP64, batch 1, ...). */
@@ -341,6 +345,15 @@ int eigcg_server_destroy(eigcg_server* srv);
  * scratch_dev (scratch_elems doubles) for chunk partials.  K <= 256,
  * N <= 24 (kind 0) or 16 (kind 1).  Both synchronise the device. */
 int eigcg_debug_mfma_probe(double* out_dev);
+/* eigcg_debug_span: the host-side bounds layer (no GPU needed).  The library
+ * registers each of its device allocations with its size and refuses, with
+ * EINVAL before any launch, a column pointer or a launch whose fields would
+ * reach past the end of the allocation they start in.  op 0 registers
+ * [addr, addr + bytes) as an allocation, op 1 removes the allocation at addr,
+ * op 2 checks an access of bytes at addr: EIGCG_OK when it ends inside the
+ * allocation containing addr (or addr lies in none), EIGCG_EINVAL when it
+ * reaches past that allocation's end.  Addresses are never dereferenced. */
+int eigcg_debug_span(int32_t op, uint64_t addr, uint64_t bytes);
 int eigcg_debug_gemm(int32_t prec, int32_t kind, uint64_t n, int32_t K, int32_t N,
                      const void* in_dev, const void* r_dev, const double* s_dev, void* out_dev,
                      double* scratch_dev, uint64_t scratch_elems);

@@ -43,24 +43,44 @@ def galerkin_guess(apply_A, U, H, b, x_tilde=None):
     return base + U @ y
 
 
-def init_cg(apply_A, U, H, b, tol=1e-10, restart_tol=0.0, max_iter=100000):
+def init_cg(apply_A, U, H, b, tol=1e-10, restart_tol=0.0, max_iter=100000,
+            first_leg_iters=None, second_leg_iters=None):
     """Deflated solve: Galerkin guess, CG, optionally one restart (Section 5.3).
 
     Returns ``(x, info)`` with ``iterations`` summed over both CG runs and
     ``restarted`` telling whether the restart happened.
+
+    ``first_leg_iters`` / ``second_leg_iters`` (test support) run exactly that
+    many iterations in the leg before / after the restart instead of stopping
+    at its tolerance.  Stop tests compare a recursively updated residual with a
+    tolerance, so an implementation with different rounding may stop one
+    iteration apart; these give the oracle's own iterates either side of its
+    stop without changing any arithmetic.
     """
     x0 = galerkin_guess(apply_A, U, H, b)
-    if restart_tol > tol:
-        x1, info1 = cg(apply_A, b, x0=x0, tol=restart_tol, max_iter=max_iter)
+    if restart_tol > tol or first_leg_iters is not None:
+        if first_leg_iters is None:
+            x1, info1 = cg(apply_A, b, x0=x0, tol=restart_tol, max_iter=max_iter)
+        else:
+            x1, info1 = cg(apply_A, b, x0=x0, tol=0.0, max_iter=first_leg_iters,
+                           true_residual_restarts=0)
         x0 = galerkin_guess(apply_A, U, H, b, x_tilde=x1)
-        x, info2 = cg(apply_A, b, x0=x0, tol=tol,
-                      max_iter=max(0, max_iter - info1["iterations"]))
+        if second_leg_iters is None:
+            x, info2 = cg(apply_A, b, x0=x0, tol=tol,
+                          max_iter=max(0, max_iter - info1["iterations"]))
+        else:
+            x, info2 = cg(apply_A, b, x0=x0, tol=0.0, max_iter=second_leg_iters,
+                          true_residual_restarts=0)
         info = dict(info2)
         info["iterations"] = info1["iterations"] + info2["iterations"]
         info["first_leg_iterations"] = info1["iterations"]
         info["restarted"] = True
         return x, info
-    x, info = cg(apply_A, b, x0=x0, tol=tol, max_iter=max_iter)
+    if second_leg_iters is None:
+        x, info = cg(apply_A, b, x0=x0, tol=tol, max_iter=max_iter)
+    else:
+        x, info = cg(apply_A, b, x0=x0, tol=0.0, max_iter=second_leg_iters,
+                     true_residual_restarts=0)
     info["restarted"] = False
     info["first_leg_iterations"] = info["iterations"]
     return x, info

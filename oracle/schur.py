@@ -1,8 +1,8 @@
 """Odd-even (Schur complement) preconditioned Wilson operator, plain NumPy FP64
 (test infrastructure only).
 
-The paper's lattice runs (the Section 6 comparisons and the Section 7
-production ensembles) solve the odd-even preconditioned normal equations, a
+The paper's lattice runs (the comparisons of Section 3.1 and the QCD tests of
+Section 5.1) solve the odd-even preconditioned normal equations, a
 system of half the size; the paper does not write the preconditioned operator
 out.  The reading used here is the exact Schur complement of the even-site
 block of M.

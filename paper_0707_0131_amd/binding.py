@@ -64,6 +64,7 @@ class Stats(ctypes.Structure):
         ("bank_added", ctypes.c_int32),
         ("nritz", ctypes.c_int32),
         ("mode_used", ctypes.c_int32),
+        ("first_leg_iters", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -122,6 +123,7 @@ SIGNATURES = {
     "eigcg_server_drain": (_I32, [_VP]),
     "eigcg_server_destroy": (_I32, [_VP]),
     "eigcg_debug_mfma_probe": (_I32, [_VP]),
+    "eigcg_debug_span": (_I32, [_I32, ctypes.c_uint64, ctypes.c_uint64]),
     "eigcg_debug_gemm": (_I32, [_I32, _I32, ctypes.c_uint64, _I32, _I32, _VP, _VP, _VP, _VP, _VP,
                                 ctypes.c_uint64]),
     "eigcg_host_eig_lowest": (_I32, [_I32, _DP, _I32, _DP, _DP]),
@@ -180,6 +182,42 @@ def _check_field(t, what):
         raise ValueError(f"{what} must be a contiguous complex128 device tensor")
 
 
+# Sites of a solver vector and of the lattice, per live context handle (the
+# two differ in odd-even contexts, whose vectors hold the even sites only).
+# The C ABI takes raw device pointers; sizes are checked here before any call,
+# so a mis-sized tensor is refused instead of being read or written past its end.
+_GEOM: dict = {}
+_SERVERS: dict = {}  # server handle -> {field id: (V, Vfull)}
+
+
+def _key(h):
+    return h.value if isinstance(h, ctypes.c_void_p) else h
+
+
+def _geom(ctx):
+    g = _GEOM.get(_key(ctx))
+    if g is None:
+        raise ValueError("unknown context: not created by eigcg_create or already destroyed")
+    return g
+
+
+def _check_fields(t, what, sites, count=None):
+    """t: a contiguous complex128 device tensor of `count` (default: its
+    leading extent) fields of `sites` sites x 12 complex entries."""
+    _check_field(t, what)
+    if t.dim() < 2:
+        raise ValueError(f"{what} needs a leading right-hand-side axis")
+    n = t.shape[0] if count is None else count
+    if t.numel() != n * 12 * sites:
+        raise ValueError(f"{what} holds {t.numel()} complex entries, expected {n} x 12 x {sites}")
+    return n
+
+
+def _same_shape(a, b, what):
+    if tuple(a.shape) != tuple(b.shape):
+        raise ValueError(f"{what}: shapes {tuple(a.shape)} and {tuple(b.shape)} differ")
+
+
 _PARAM_NAMES = {name for name, _ in Params._fields_}
 
 
@@ -199,10 +237,17 @@ def eigcg_default_params(**overrides) -> Params:
 
 def eigcg_create(params: Params, gauge, stream=None):
     _check_field(gauge, "gauge")
+    vfull = 1
+    for i in range(4):
+        vfull *= max(0, int(params.dims[i]))
+    if gauge.numel() != vfull * 4 * 9:
+        raise ValueError(f"gauge holds {gauge.numel()} complex entries, expected "
+                         f"{vfull} sites x 4 x 3 x 3")
     ctx = ctypes.c_void_p()
     rc = LIB.eigcg_create(ctypes.byref(params), _ptr(gauge), _stream(stream), ctypes.byref(ctx))
     if rc != EIGCG_OK:
         raise EigcgError(rc, "eigcg_create failed: " + eigcg_last_error(None))
+    _GEOM[ctx.value] = (vfull // 2 if params.schur else vfull, vfull)
     return ctx
 
 
@@ -212,14 +257,16 @@ def eigcg_last_error(ctx) -> str:
 
 
 def eigcg_destroy(ctx):
+    _GEOM.pop(_key(ctx), None)
     return LIB.eigcg_destroy(ctx)
 
 
 def eigcg_solve(ctx, b, x, tol, mode=EIGCG_MODE_CG):
     """Returns (status, [stats dict per right-hand side])."""
-    _check_field(b, "b")
-    _check_field(x, "x")
-    nrhs = b.shape[0]
+    V, _ = _geom(ctx)
+    nrhs = _check_fields(b, "b", V)
+    _check_fields(x, "x", V)
+    _same_shape(b, x, "b and x")
     st = (Stats * max(1, nrhs))()
     rc = LIB.eigcg_solve(ctx, nrhs, _ptr(b), _ptr(x), float(tol), int(mode), st)
     if rc in (EIGCG_EINVAL, EIGCG_ENOMEM, EIGCG_EHIP):
@@ -228,8 +275,10 @@ def eigcg_solve(ctx, b, x, tol, mode=EIGCG_MODE_CG):
 
 
 def eigcg_deflate_init(ctx, b, x):
-    _check_field(b, "b")
-    _check_field(x, "x")
+    V, _ = _geom(ctx)
+    _check_fields(b, "b", V)
+    _check_fields(x, "x", V)
+    _same_shape(b, x, "b and x")
     rc = LIB.eigcg_deflate_init(ctx, b.shape[0], _ptr(b), _ptr(x))
     if rc != EIGCG_OK:
         raise EigcgError(rc, eigcg_last_error(ctx))
@@ -240,9 +289,10 @@ def eigcg_solve_bicgstab(ctx, b, x, tol, gamma5=True, deflate=True, max_iter=0,
     """BiCGSTAB on M x = b (gamma5=False) or gamma5 M x = gamma5 b, from the
     guess in x, after the bank's least-squares guess when deflate is set
     (guess_only: stop after it).  Returns (status, [stats dict per right-hand side])."""
-    _check_field(b, "b")
-    _check_field(x, "x")
-    nrhs = b.shape[0]
+    V, _ = _geom(ctx)
+    nrhs = _check_fields(b, "b", V)
+    _check_fields(x, "x", V)
+    _same_shape(b, x, "b and x")
     flags = (EIGCG_BICG_GAMMA5 if gamma5 else 0) | (EIGCG_BICG_DEFLATE if deflate else 0) | \
         (EIGCG_BICG_GUESS_ONLY if guess_only else 0)
     st = (BicgstabStats * max(1, nrhs))()
@@ -254,8 +304,10 @@ def eigcg_solve_bicgstab(ctx, b, x, tol, gamma5=True, deflate=True, max_iter=0,
 
 
 def eigcg_apply(ctx, op, inp, out):
-    _check_field(inp, "in")
-    _check_field(out, "out")
+    V, _ = _geom(ctx)
+    _check_fields(inp, "in", V)
+    _check_fields(out, "out", V)
+    _same_shape(inp, out, "in and out")
     rc = LIB.eigcg_apply(ctx, int(op), inp.shape[0], _ptr(inp), _ptr(out))
     if rc != EIGCG_OK:
         raise EigcgError(rc, eigcg_last_error(ctx))
@@ -263,8 +315,11 @@ def eigcg_apply(ctx, op, inp, out):
 
 def eigcg_schur_rhs(ctx, b_full, rhs):
     """rhs (even sites) = Mhat^H (b_e + D_eo b_o / (2 d)) for full-lattice fields b_full."""
-    _check_field(b_full, "b_full")
-    _check_field(rhs, "rhs")
+    V, Vfull = _geom(ctx)
+    if V == Vfull:
+        raise EigcgError(EIGCG_EINVAL, "context is not odd-even preconditioned")
+    n = _check_fields(b_full, "b_full", Vfull)
+    _check_fields(rhs, "rhs", V, n)
     rc = LIB.eigcg_schur_rhs(ctx, b_full.shape[0], _ptr(b_full), _ptr(rhs))
     if rc != EIGCG_OK:
         raise EigcgError(rc, eigcg_last_error(ctx))
@@ -272,9 +327,12 @@ def eigcg_schur_rhs(ctx, b_full, rhs):
 
 def eigcg_schur_reconstruct(ctx, b_full, x_even, x_full):
     """x_full = (x_even, (b_o + D_oe x_even / 2) / d) on the full lattice."""
-    _check_field(b_full, "b_full")
-    _check_field(x_even, "x_even")
-    _check_field(x_full, "x_full")
+    V, Vfull = _geom(ctx)
+    if V == Vfull:
+        raise EigcgError(EIGCG_EINVAL, "context is not odd-even preconditioned")
+    n = _check_fields(b_full, "b_full", Vfull)
+    _check_fields(x_even, "x_even", V, n)
+    _check_fields(x_full, "x_full", Vfull, n)
     rc = LIB.eigcg_schur_reconstruct(ctx, b_full.shape[0], _ptr(b_full), _ptr(x_even),
                                      _ptr(x_full))
     if rc != EIGCG_OK:
@@ -294,14 +352,19 @@ def eigcg_bank_info(ctx, residuals=False, cap=256):
 
 
 def eigcg_bank_vectors(ctx, first, count, out):
+    V, _ = _geom(ctx)
     _check_field(out, "out")
+    if out.numel() < int(count) * 12 * V:
+        raise ValueError(f"out holds {out.numel()} complex entries, {count} fields need "
+                         f"{int(count) * 12 * V}")
     rc = LIB.eigcg_bank_vectors(ctx, int(first), int(count), _ptr(out))
     if rc != EIGCG_OK:
         raise EigcgError(rc, eigcg_last_error(ctx))
 
 
 def eigcg_bank_load(ctx, vecs):
-    _check_field(vecs, "vectors")
+    V, _ = _geom(ctx)
+    _check_fields(vecs, "vectors", V)
     added = _I32()
     rc = LIB.eigcg_bank_load(ctx, vecs.shape[0], _ptr(vecs), ctypes.byref(added))
     if rc != EIGCG_OK:
@@ -336,9 +399,12 @@ def eigcg_bank_truncate(ctx, k):
 
 def eigcg_bank_restore(ctx, vecs, h):
     """Restore U from l device fields and H (l x l complex, [row, col]) on the host."""
-    _check_field(vecs, "vectors")
-    l = vecs.shape[0]
-    hf = np.ascontiguousarray(np.asarray(h, dtype=np.complex128).T)  # column-major
+    V, _ = _geom(ctx)
+    l = _check_fields(vecs, "vectors", V)
+    h = np.asarray(h, dtype=np.complex128)
+    if h.shape != (l, l):
+        raise ValueError(f"h must be {l} x {l}, got {h.shape}")
+    hf = np.ascontiguousarray(h.T)  # column-major
     rc = LIB.eigcg_bank_restore(ctx, l, _ptr(vecs), hf.ctypes.data_as(_DP))
     if rc != EIGCG_OK:
         raise EigcgError(rc, eigcg_last_error(ctx))
@@ -391,16 +457,21 @@ def eigcg_server_create(hbm_budget=0):
 
 
 def eigcg_server_add(srv, ctx):
+    geom = _geom(ctx)
     fid = _I32()
     rc = LIB.eigcg_server_add(srv, ctx, ctypes.byref(fid))
     if rc != EIGCG_OK:
         raise EigcgError(rc, "eigcg_server_add failed")
+    _SERVERS.setdefault(_key(srv), {})[fid.value] = geom
     return fid.value
 
 
 def eigcg_submit(srv, field_id, b, x, tol):
-    _check_field(b, "b")
-    _check_field(x, "x")
+    geom = _SERVERS.get(_key(srv), {}).get(int(field_id))
+    if geom is None:
+        raise ValueError(f"field {field_id} is not registered with this server")
+    _check_fields(b, "b", geom[0], 1)
+    _check_fields(x, "x", geom[0], 1)
     t = ctypes.c_uint64()
     rc = LIB.eigcg_submit(srv, int(field_id), _ptr(b), _ptr(x), float(tol), ctypes.byref(t))
     if rc != EIGCG_OK:
@@ -419,6 +490,7 @@ def eigcg_server_drain(srv):
 
 
 def eigcg_server_destroy(srv):
+    _SERVERS.pop(_key(srv), None)
     return LIB.eigcg_server_destroy(srv)
 
 
@@ -453,6 +525,12 @@ def eigcg_debug_gemm(kind, inp, s=None, r=None):
     if rc != EIGCG_OK:
         raise EigcgError(rc, "debug gemm failed")
     return out.cpu().numpy() if kind == 0 else out.cpu().numpy().T
+
+
+def eigcg_debug_span(op, addr, nbytes=0):
+    """The host-side bounds layer: op 0 registers [addr, addr + nbytes) as an
+    allocation, 1 removes it, 2 checks an access (EIGCG_OK or EIGCG_EINVAL)."""
+    return LIB.eigcg_debug_span(int(op), ctypes.c_uint64(addr), ctypes.c_uint64(nbytes))
 
 
 # ---- host linear algebra (no GPU) --------------------------------------------

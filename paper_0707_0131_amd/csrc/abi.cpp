@@ -292,6 +292,18 @@ int eigcg_memory(eigcg_ctx* ctx, uint64_t* bytes) {
   return EIGCG_OK;
 }
 
+int eigcg_debug_span(int32_t op, uint64_t addr, uint64_t bytes) {
+  const void* p = reinterpret_cast<const void*>((uintptr_t)addr);
+  if (op == 0) {
+    if (!addr || !bytes) return EIGCG_EINVAL;
+    eigcg::register_span(p, (size_t)bytes);
+    return EIGCG_OK;
+  }
+  if (op == 1) return eigcg::unregister_span(p) ? EIGCG_OK : EIGCG_EINVAL;
+  if (op == 2) return eigcg::span_fits(p, (size_t)bytes) ? EIGCG_OK : EIGCG_EINVAL;
+  return EIGCG_EINVAL;
+}
+
 int eigcg_layout_info(eigcg_ctx* ctx, int32_t* info) {
   if (!ctx || !info) return EIGCG_EINVAL;
   info[0] = ctx->c.g.V;

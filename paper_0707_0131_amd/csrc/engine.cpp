@@ -29,9 +29,16 @@ namespace eigcg {
 
 namespace {
 
-std::unordered_map<void*, size_t>& alloc_sizes() {
-  static thread_local std::unordered_map<void*, size_t> m;
-  return m;
+// Registry of the library's device allocations (base address -> bytes),
+// shared by every thread and context: the byte accounting of dfree and the
+// host-side bounds checks below read it.
+struct AllocRegistry {
+  std::mutex mu;
+  std::map<uintptr_t, size_t> m;
+};
+AllocRegistry& allocs() {
+  static AllocRegistry r;
+  return r;
 }
 
 size_t round_up(size_t a, size_t b) { return (a + b - 1) / b * b; }
@@ -67,19 +74,53 @@ void* Ctx::dalloc(size_t n) {
   }
   check(hipMemsetAsync(p, 0, n, stream), "hipMemsetAsync");
   bytes += n;
-  alloc_sizes()[p] = n;
+  register_span(p, n);
   return p;
 }
 
 void Ctx::dfree(void*& p) {
   if (!p) return;
-  auto it = alloc_sizes().find(p);
-  if (it != alloc_sizes().end()) {
-    bytes -= it->second;
-    alloc_sizes().erase(it);
-  }
+  const size_t n = unregister_span(p);
+  bytes -= std::min(bytes, n);
   (void)hipFree(p);
   p = nullptr;
+}
+
+void register_span(const void* base, size_t bytes) {
+  AllocRegistry& r = allocs();
+  std::lock_guard<std::mutex> lk(r.mu);
+  r.m[(uintptr_t)base] = bytes;
+}
+
+size_t unregister_span(const void* base) {
+  AllocRegistry& r = allocs();
+  std::lock_guard<std::mutex> lk(r.mu);
+  auto it = r.m.find((uintptr_t)base);
+  if (it == r.m.end()) return 0;
+  const size_t n = it->second;
+  r.m.erase(it);
+  return n;
+}
+
+// Host-side bounds check of a device access: when p lies inside one of the
+// library's allocations, [p, p + bytes) must end inside it.  Pointers outside
+// every allocation (the caller's tensors) are not the library's to check.
+bool span_fits(const void* p, size_t bytes) {
+  AllocRegistry& r = allocs();
+  std::lock_guard<std::mutex> lk(r.mu);
+  const uintptr_t a = (uintptr_t)p;
+  auto it = r.m.upper_bound(a);
+  if (it == r.m.begin()) return true;
+  --it;
+  const uintptr_t end = it->first + it->second;
+  if (a >= end) return true;
+  return bytes <= end - a;
+}
+
+void check_span(const void* p, size_t bytes, const char* what) {
+  if (!span_fits(p, bytes))
+    throw ApiError{EIGCG_EINVAL, std::string("internal: ") + what +
+                                     " reaches past the end of its device allocation"};
 }
 
 static size_t elem_bytes(int prec) { return prec == kF64 ? 16 : (prec == kF32 ? 8 : 4); }
@@ -394,8 +435,16 @@ static void ws_ensure(Ctx& c, Workspace& w, int prec, bool eig) {
   }
 }
 
+// Field idx of a run of fields starting at base; the field must end inside
+// base's allocation.
 void* col_ptr(void* base, int prec, size_t cs, size_t idx) {
+  check_span(base, (idx + 1) * cs * elem_bytes(prec), "column");
   return (char*)base + idx * cs * elem_bytes(prec);
+}
+
+// ncols whole fields of precision prec start at p (inside p's allocation)
+void check_fields(const Ctx& c, const void* p, int prec, int ncols, const char* what) {
+  if (p && ncols > 0) check_span(p, (size_t)ncols * c.cs * elem_bytes(prec), what);
 }
 
 // ---------------------------------------------------------------------------
@@ -423,6 +472,8 @@ static StencilLaunch stencil_base(Ctx& c, int prec) {
 
 // out = op(in) (op = M or M^H) on ncols internal fields
 void stencil_store(Ctx& c, int prec, int op, int ncols, const void* in, void* out) {
+  check_fields(c, in, prec, ncols, "stencil input");
+  check_fields(c, out, prec, ncols, "stencil output");
   StencilLaunch L = stencil_base(c, prec);
   L.op = op;
   L.epi = kEpiStore;
@@ -436,6 +487,8 @@ void stencil_store(Ctx& c, int prec, int op, int ncols, const void* in, void* ou
 // r = b - A x for masked columns, rho = ||r||^2 into the column states
 static void true_residual(Ctx& c, int prec, int ncols, uint32_t mask, const void* x,
                           const void* b, void* r, void* tmp) {
+  for (const void* f : {x, b, (const void*)r, (const void*)tmp})
+    check_fields(c, f, prec, ncols, "true-residual field");
   StencilLaunch L = stencil_base(c, prec);
   L.op = kOpM;
   L.epi = kEpiStore;
@@ -485,6 +538,7 @@ void apply_op(Ctx& c, int op, int nrhs, const void* in_aos, void* out_aos) {
     const int k = std::min(w.K, nrhs - c0);
     const double2* src = (const double2*)in_aos + (size_t)c0 * 12 * c.g.V;
     double2* dst = (double2*)out_aos + (size_t)c0 * 12 * c.g.V;
+    check_fields(c, w.x, kF64, k, "operator input");
     c.check(launch_spinor_to_soa(src, w.x, kF64, &c.g, k, c.cs, c.stream), "to soa");
     if (op == EIGCG_OP_A) {
       stencil_store(c, kF64, kOpM, k, w.x, w.tmp);
@@ -680,6 +734,7 @@ struct Run {
   std::vector<int> reason;
   std::vector<int> iters;
   std::vector<int> outer;        // host-driven restarts
+  std::vector<int> first_leg;    // iterations before the first init-CG restart (-1: none)
   std::vector<int> stale_until;  // snapshots of segments <= this id predate a host restart
   int enq_iter = 0;              // iterations enqueued (all columns in lockstep)
   int seg_id = 0;                // id of the last enqueued segment
@@ -699,8 +754,14 @@ struct Run {
     reason.assign(K, 0);
     iters.assign(K, 0);
     outer.assign(K, 0);
+    first_leg.assign(K, -1);
     stale_until.assign(K, -1);
     for (int j = 0; j < K; ++j) ec[j].next_full = m;
+    // every launch of the run covers K columns of the workspace
+    if (K > w.K) throw ApiError{EIGCG_EINVAL, "internal: run wider than its workspace"};
+    for (const void* f : {w.b, w.r, w.p, w.tmp}) check_fields(c, f, prec, K, "run field");
+    check_fields(c, w.x, prec == kF16 ? kF32 : prec, K, "run iterate");
+    if (eig) check_fields(c, w.ring, prec, K * w.ring_len, "window ring");
   }
   ~Run() {
     for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
@@ -1136,6 +1197,7 @@ struct Driver {
       R.reason[j] = 0;
       R.iters[j] = 0;
       R.outer[j] = 0;
+      R.first_leg[j] = -1;
       R.ec[j] = EigCol();
       R.ec[j].next_full = R.m;
       R.hist_read[j] = 0;
@@ -1266,6 +1328,7 @@ struct Driver {
       if (S.reason == ReasonRestart) {
         if (scheme == kSchemeF64) {
           cx.check(hipStreamSynchronize(cx.stream), "sync");
+          if (R.first_leg[j] < 0) R.first_leg[j] = S.iter;
           host_restart(j);
           continue;
         }
@@ -1665,6 +1728,8 @@ int solve(Ctx& c, int nrhs, const void* b_aos, void* x_aos, double tol, int mode
     const double t0 = now_s();
     const double2* bsrc = (const double2*)b_aos + (size_t)c0 * 12 * c.g.V;
     double2* xdst = (double2*)x_aos + (size_t)c0 * 12 * c.g.V;
+    check_fields(c, w64.b, kF64, K, "right-hand sides");
+    check_fields(c, w64.x, kF64, K, "iterates");
     c.check(launch_spinor_to_soa(bsrc, w64.b, kF64, &c.g, K, c.cs, c.stream), "to soa");
     c.check(launch_spinor_to_soa(xdst, w64.x, kF64, &c.g, K, c.cs, c.stream), "to soa");
     std::vector<double> bn2 = col_norms(c, kF64, K, w64.b);
@@ -1737,6 +1802,7 @@ int solve(Ctx& c, int nrhs, const void* b_aos, void* x_aos, double tol, int mode
         s.bank_added = added[j];
         s.nritz = eig ? D.R.ec[j].nritz : 0;
         s.mode_used = gmode;
+        s.first_leg_iters = D.R.first_leg[j] >= 0 ? D.R.first_leg[j] : D.R.iters[j];
       }
     }
   }
@@ -1869,6 +1935,7 @@ void session_step(Session* s, std::vector<SessionDone>& done) {
     d.status = stt;
     d.iters = s->D.R.iters[j];
     d.outer = s->D.R.outer[j];
+    d.first_leg = s->D.R.first_leg[j] >= 0 ? s->D.R.first_leg[j] : s->D.R.iters[j];
     d.true_rel_res = res[j];
     done.push_back(d);
     s->active[j] = 0;
@@ -1891,6 +1958,8 @@ void deflate_init(Ctx& c, int nrhs, const void* b_aos, void* x_aos) {
     const uint32_t mask = (K >= 32) ? 0xffffffffu : ((1u << K) - 1);
     const double2* bsrc = (const double2*)b_aos + (size_t)c0 * 12 * c.g.V;
     double2* xdst = (double2*)x_aos + (size_t)c0 * 12 * c.g.V;
+    check_fields(c, w64.b, kF64, K, "right-hand sides");
+    check_fields(c, w64.x, kF64, K, "iterates");
     c.check(launch_spinor_to_soa(bsrc, w64.b, kF64, &c.g, K, c.cs, c.stream), "to soa");
     c.check(launch_spinor_to_soa(xdst, w64.x, kF64, &c.g, K, c.cs, c.stream), "to soa");
     if (c.l > 0) {

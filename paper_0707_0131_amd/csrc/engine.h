@@ -137,6 +137,15 @@ bool auto_continue(int done, int left, const double* iters, const double* secs, 
 void kernel_samples(Ctx& c, bool reset, double* out);
 
 // Engine helpers shared by the solver files (engine.cpp, bicgstab.cpp).
+// Host-side bounds layer over the library's device allocations: every
+// allocation is registered with its size, column pointers and the fields a
+// launch touches are checked against it (ApiError EINVAL when they would
+// reach past the end).
+void register_span(const void* base, size_t bytes);
+size_t unregister_span(const void* base);  // returns the registered size (0: unknown)
+bool span_fits(const void* p, size_t bytes);
+void check_span(const void* p, size_t bytes, const char* what);
+void check_fields(const Ctx& c, const void* p, int prec, int ncols, const char* what);
 void* col_ptr(void* base, int prec, size_t cs, size_t idx);
 // out = op(in) (op = kOpM or kOpMdag) on ncols internal fields
 void stencil_store(Ctx& c, int prec, int op, int ncols, const void* in, void* out);
@@ -151,6 +160,7 @@ struct SessionDone {
   int status;
   int iters;
   int outer;
+  int first_leg;  // iterations before the first init-CG restart (= iters when none)
   double true_rel_res;
 };
 Session* session_open(Ctx& c);

@@ -139,6 +139,7 @@ struct eigcg_server {
           r.st.status = d.status;
           r.st.iters = d.iters;
           r.st.outer_steps = d.outer;
+          r.st.first_leg_iters = d.first_leg;
           r.st.true_rel_res = d.true_rel_res;
           r.st.seconds = t - r.t_submit;
           --outstanding;

@@ -240,3 +240,104 @@ def test_auto_switch_against_the_papers_table(B):
     for got, paper in zip(chosen, table["optimal_incremental_rhs"]):
         assert paper / 2 <= got <= 2 * paper, (chosen, table)
     assert chosen == sorted(chosen) and chosen[-1] > chosen[0]
+
+
+class _FakeDeviceTensor:
+    """Stands in for a complex128 device tensor in the binding's argument
+    checks; the checks must refuse it before any library call reads its
+    (invalid) data pointer."""
+
+    def __init__(self, *shape):
+        import torch
+        self.shape = tuple(shape)
+        self.is_cuda = True
+        self.dtype = torch.complex128
+
+    def is_contiguous(self):
+        return True
+
+    def dim(self):
+        return len(self.shape)
+
+    def numel(self):
+        return int(np.prod(self.shape))
+
+    def data_ptr(self):
+        raise AssertionError("a mis-sized tensor reached the library")
+
+
+def test_binding_refuses_mis_sized_tensors(B):
+    """Every entry point taking device fields checks their sizes against the
+    context's lattice before calling the C ABI (which takes raw pointers)."""
+    F = _FakeDeviceTensor
+    full = ctypes.c_void_p(0x7e57)      # 4^4 lattice, full geometry
+    eo = ctypes.c_void_p(0x7e58)        # 4^4 lattice, odd-even (128 even sites)
+    B._GEOM[full.value] = (256, 256)
+    B._GEOM[eo.value] = (128, 256)
+    try:
+        good = (1, 4, 4, 4, 4, 4, 3)
+        bad_cases = [
+            (B.eigcg_solve, (full, F(*good), F(1, 4, 4, 4, 4, 4, 2), 1e-10)),   # x too small
+            (B.eigcg_solve, (full, F(2, 4, 4, 4, 4, 4, 3), F(*good), 1e-10)),   # x misses a column
+            (B.eigcg_solve, (full, F(1, 4, 4, 4, 2, 4, 3), F(1, 4, 4, 4, 2, 4, 3), 1e-10)),
+            (B.eigcg_solve, (eo, F(*good), F(*good), 1e-10)),                   # full fields, even system
+            (B.eigcg_deflate_init, (full, F(*good), F(1, 3072 - 1))),
+            (B.eigcg_solve_bicgstab, (full, F(*good), F(1, 4, 4, 4, 4, 4, 4), 1e-10)),
+            (B.eigcg_apply, (full, 0, F(*good), F(1, 4, 4, 4, 4, 3, 3))),
+            (B.eigcg_schur_rhs, (eo, F(*good), F(*good))),                      # rhs is half size
+            (B.eigcg_schur_rhs, (eo, F(1, 128, 4, 3), F(1, 128, 4, 3))),        # b_full is full size
+            (B.eigcg_schur_reconstruct, (eo, F(*good), F(1, 128, 4, 3), F(1, 128, 4, 3))),
+            (B.eigcg_bank_load, (full, F(3, 255, 4, 3))),
+            (B.eigcg_bank_vectors, (full, 0, 2, F(*good))),
+            (B.eigcg_bank_restore, (full, F(2, 256, 4, 3), np.eye(3))),
+            (B.eigcg_solve, (ctypes.c_void_p(0x7e59), F(*good), F(*good), 1e-10)),  # unknown ctx
+        ]
+        for fn, args in bad_cases:
+            with pytest.raises(ValueError):
+                fn(*args)
+        # a gauge field of the wrong lattice is refused before create
+        p = B.eigcg_default_params(dims=(4, 4, 4, 4))
+        with pytest.raises(ValueError):
+            B.eigcg_create(p, F(4, 4, 4, 4, 4, 3, 2))
+        # a server request for a field it does not hold, or of the wrong size
+        srv = B.eigcg_server_create(0)
+        try:
+            B._SERVERS[srv.value] = {0: (256, 256)}
+            with pytest.raises(ValueError):
+                B.eigcg_submit(srv, 1, F(*good), F(*good), 1e-10)
+            with pytest.raises(ValueError):
+                B.eigcg_submit(srv, 0, F(1, 4, 4, 4, 4, 4, 2), F(*good), 1e-10)
+        finally:
+            B.eigcg_server_destroy(srv)
+    finally:
+        B._GEOM.pop(full.value, None)
+        B._GEOM.pop(eo.value, None)
+
+
+def test_bounds_layer_refuses_accesses_past_an_allocation(B):
+    """The library's host-side bounds layer (every device allocation
+    registered with its size; column pointers and the fields of a launch
+    checked before enqueueing): an access must end inside the allocation it
+    starts in.  Fake addresses, never dereferenced."""
+    base, size = 0x5e0000000000, 12 * 4096
+    nxt = base + size + 256                      # the next allocation
+    assert B.eigcg_debug_span(0, base, size) == B.EIGCG_OK
+    assert B.eigcg_debug_span(0, nxt, size) == B.EIGCG_OK
+    try:
+        field = 4096
+        for k in range(1, 13):                   # fields 0..11 of 12 fit
+            assert B.eigcg_debug_span(2, base, k * field) == B.EIGCG_OK
+        assert B.eigcg_debug_span(2, base, 13 * field) == B.EIGCG_EINVAL
+        # a column pointer inside the allocation, checked from where it starts
+        assert B.eigcg_debug_span(2, base + 11 * field, field) == B.EIGCG_OK
+        assert B.eigcg_debug_span(2, base + 11 * field, field + 1) == B.EIGCG_EINVAL
+        # 16 columns in a 1-column workspace: refused, although the overrun
+        # would land in the next allocation
+        assert B.eigcg_debug_span(2, nxt, 16 * size) == B.EIGCG_EINVAL
+        # memory the library did not allocate (the caller's tensors) is not checked
+        assert B.eigcg_debug_span(2, nxt + 2 * size, 1 << 40) == B.EIGCG_OK
+        assert B.eigcg_debug_span(2, base - 64, 128) == B.EIGCG_OK
+    finally:
+        assert B.eigcg_debug_span(1, base) == B.EIGCG_OK
+        assert B.eigcg_debug_span(1, nxt) == B.EIGCG_OK
+    assert B.eigcg_debug_span(1, base) == B.EIGCG_EINVAL  # already removed

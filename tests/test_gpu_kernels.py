@@ -3,7 +3,10 @@
 The complex tall-skinny products of the library (restart V (QZ), Ritz vectors,
 U C, U^H R) run on the 16x16x4 matrix-core instructions; the lane-layout probe
 pins the register layout they rely on, the products are then compared element
-by element with numpy in FP64 (1e-13) and FP32 (1e-5, relative to the norms).
+by element with numpy in FP64 (1e-13) and FP32 (1e-5, relative to the norms),
+including the shapes of the bench's eigCG(10, 100) restart (K = 100 inputs,
+2 nev = 20 outputs) and of deflation with a 240-vector bank (the tall product
+splits its outputs into groups whose K x N coefficients fit 64 KB of LDS).
 """
 
 import numpy as np
@@ -39,7 +42,8 @@ def test_mfma_lane_layout(B):
 
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
-@pytest.mark.parametrize("n,K,N", [(1000, 1, 1), (3072, 7, 5), (1024, 40, 20), (777, 33, 24)])
+@pytest.mark.parametrize("n,K,N", [(1000, 1, 1), (3072, 7, 5), (1024, 40, 20), (777, 33, 24),
+                                   (6144, 100, 20), (5000, 240, 17), (4099, 240, 1)])
 def test_gemm_tall(B, dt, n, K, N):
     import torch
     rng = np.random.default_rng(K * 100 + N)
@@ -54,7 +58,8 @@ def test_gemm_tall(B, dt, n, K, N):
 
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
-@pytest.mark.parametrize("n,K,N", [(1000, 1, 1), (3072, 20, 1), (1024, 40, 12), (4097, 17, 16)])
+@pytest.mark.parametrize("n,K,N", [(1000, 1, 1), (3072, 20, 1), (1024, 40, 12), (4097, 17, 16),
+                                   (6144, 100, 1), (5000, 240, 16), (4099, 240, 1)])
 def test_gemm_reduce(B, dt, n, K, N):
     import torch
     rng = np.random.default_rng(K * 7 + N)

@@ -102,19 +102,29 @@ def _solve_full(B, ctx, b_full, tol, mode):
 
 @pytest.mark.parametrize("variant", [3, 6, 10])
 def test_schur_cg_parity(B, cfg0_field, variant):
+    """CG on the even-site system: the GPU stops within one iteration of the
+    oracle's CG on Ahat (both test a recursive residual), x_e equals the
+    oracle's iterate after the same number of iterations to 1e-10, and so
+    does the reconstructed full solution."""
     U = cfg0_field
     op = SchurOperator(U, -0.2)
     full = WilsonOperator(U, -0.2)
     b = gaussian_rhs((4, 4, 4, 4), 1000)
-    xo_e, io = cg(op.A, op.rhs(b.reshape(-1)), tol=1e-10)
-    xo = op.reconstruct(b.reshape(-1), xo_e)
+    rhs = op.rhs(b.reshape(-1))
+    xo_e, io = cg(op.A, rhs, tol=1e-10)
+    k = io["iterations"]
+    cands = {k: xo_e}
+    for kk in (k - 1, k + 1):
+        cands[kk] = cg(op.A, rhs, tol=0.0, max_iter=kk, true_residual_restarts=0)[0]
     ctx, _ = make_ctx(U, -0.2, max_iter=5000, stencil_variant=variant, schur=1)
     try:
         rc, st, xe, xf = _solve_full(B, ctx, b[None], 1e-10, B.EIGCG_MODE_CG)
         assert rc == B.EIGCG_OK, B.eigcg_last_error(ctx)
-        assert abs(st[0]["iters"] - io["iterations"]) <= 1
+        assert st[0]["iters"] in cands, (st[0]["iters"], k)
         assert st[0]["true_rel_res"] <= 1e-10
-        assert rel(xf[0].reshape(-1), xo) <= 1e-9
+        ref_e = cands[st[0]["iters"]]
+        assert rel(xe[0].reshape(-1), ref_e) <= 1e-10
+        assert rel(xf[0].reshape(-1), op.reconstruct(b.reshape(-1), ref_e)) <= 1e-10
         # the reconstructed field solves the full system M x = b
         r = full.M(xf[0].reshape(-1)) - b.reshape(-1)
         assert np.linalg.norm(r) <= 1e-8 * np.linalg.norm(b)

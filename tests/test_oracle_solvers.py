@@ -203,6 +203,16 @@ def test_initcg_restart(cfg0_op, cfg0_dense, cfg0_rhs):
     assert 0 < info["first_leg_iterations"] < info["iterations"]
     xs = np.linalg.solve(cfg0_dense["A"], cfg0_rhs)
     assert np.linalg.norm(x - xs) / np.linalg.norm(xs) < 1e-6
+    # forcing each leg to the oracle's own counts replays the same arithmetic
+    k1 = info["first_leg_iterations"]
+    k2 = info["iterations"] - k1
+    xf, infof = init_cg(cfg0_op.A, X, H, cfg0_rhs, tol=1e-10, restart_tol=1e-6,
+                        first_leg_iters=k1, second_leg_iters=k2)
+    assert np.array_equal(xf, x) and infof["iterations"] == info["iterations"]
+    # one iteration more in the second leg moves x by less than the residual allows
+    x1, _ = init_cg(cfg0_op.A, X, H, cfg0_rhs, tol=1e-10, restart_tol=1e-6,
+                    first_leg_iters=k1, second_leg_iters=k2 + 1)
+    assert 0 < np.linalg.norm(x1 - x) / np.linalg.norm(x) < 1e-6
 
 
 def test_incremental_bank_invariants(cfg0_op, cfg0_dense):
