@@ -207,6 +207,22 @@ int eigcg_solve_bicgstab(eigcg_ctx* ctx, int32_t nrhs, const void* b_dev, void* 
  * EINVAL in an FP64 context. */
 int eigcg_apply(eigcg_ctx* ctx, int32_t op, int32_t nrhs, const void* in_dev, void* out_dev);
 
+/* eigcg_apply without allocating: for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  out = op(in) for op = EIGCG_OP_M, EIGCG_OP_MDAG or
+ * EIGCG_OP_A in FP64 (not EIGCG_OP_INNER), the same kernels and results as
+ * eigcg_apply, one column at a time through two staging fields held in a
+ * fixed device array of the library (one per GPU, kept until the process
+ * ends; its size from eigcg_noalloc_scratch_bytes, 64 MiB: lattices up to
+ * 2 x 12 x 16 B x (padded sites) within it, e.g. 16^3 x 32).  EINVAL for a
+ * larger lattice, another op, or when the context's device is not current.
+ * Calls on one GPU share its array: calls that overlap on one GPU (several
+ * threads or streams) race and must be serialised by the caller.
+ * Synchronises the context's stream. */
+int eigcg_apply_noalloc(eigcg_ctx* ctx, int32_t op, int32_t nrhs, const void* in_dev,
+                        void* out_dev);
+int eigcg_noalloc_scratch_bytes(uint64_t* bytes);
+
 /* Odd-even contexts only (EINVAL otherwise), for nrhs full-lattice fields
  * b_full_dev (boundary layout [nrhs][Lt][Lz][Ly][Lx][4][3]):
  * eigcg_schur_rhs writes rhs_dev (even-site layout) = Mhat^H (b_e + D_eo b_o / (2 d)),

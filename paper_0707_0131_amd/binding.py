@@ -100,6 +100,8 @@ SIGNATURES = {
     "eigcg_solve_bicgstab": (_I32, [_VP, _I32, _VP, _VP, ctypes.c_double, _I32, _I32,
                                     ctypes.POINTER(BicgstabStats)]),
     "eigcg_apply": (_I32, [_VP, _I32, _I32, _VP, _VP]),
+    "eigcg_apply_noalloc": (_I32, [_VP, _I32, _I32, _VP, _VP]),
+    "eigcg_noalloc_scratch_bytes": (_I32, [ctypes.POINTER(ctypes.c_uint64)]),
     "eigcg_schur_rhs": (_I32, [_VP, _I32, _VP, _VP]),
     "eigcg_schur_reconstruct": (_I32, [_VP, _I32, _VP, _VP, _VP]),
     "eigcg_bank_info": (_I32, [_VP, ctypes.POINTER(_I32), _DP, _DP]),
@@ -311,6 +313,24 @@ def eigcg_apply(ctx, op, inp, out):
     rc = LIB.eigcg_apply(ctx, int(op), inp.shape[0], _ptr(inp), _ptr(out))
     if rc != EIGCG_OK:
         raise EigcgError(rc, eigcg_last_error(ctx))
+
+
+def eigcg_apply_noalloc(ctx, op, inp, out):
+    """eigcg_apply (FP64 M, M^H or A) without any device allocation: staging
+    in the library's fixed scratch array (calls overlapping on one GPU race)."""
+    V, _ = _geom(ctx)
+    _check_fields(inp, "in", V)
+    _check_fields(out, "out", V)
+    _same_shape(inp, out, "in and out")
+    rc = LIB.eigcg_apply_noalloc(ctx, int(op), inp.shape[0], _ptr(inp), _ptr(out))
+    if rc != EIGCG_OK:
+        raise EigcgError(rc, eigcg_last_error(ctx))
+
+
+def eigcg_noalloc_scratch_bytes():
+    b = ctypes.c_uint64()
+    LIB.eigcg_noalloc_scratch_bytes(ctypes.byref(b))
+    return b.value
 
 
 def eigcg_schur_rhs(ctx, b_full, rhs):

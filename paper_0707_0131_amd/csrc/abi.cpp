@@ -188,6 +188,24 @@ int eigcg_apply(eigcg_ctx* ctx, int32_t op, int32_t nrhs, const void* in_dev, vo
   });
 }
 
+int eigcg_apply_noalloc(eigcg_ctx* ctx, int32_t op, int32_t nrhs, const void* in_dev,
+                        void* out_dev) {
+  if (!ctx) return EIGCG_EINVAL;
+  if (op < EIGCG_OP_M || op > EIGCG_OP_A) return fail(ctx, EIGCG_EINVAL, "bad op");
+  if (nrhs < 0 || (nrhs > 0 && (!in_dev || !out_dev))) return fail(ctx, EIGCG_EINVAL, "bad arguments");
+  if (nrhs == 0) return EIGCG_OK;
+  return guarded(ctx, [&] {
+    eigcg::apply_op_noalloc(ctx->c, op, nrhs, in_dev, out_dev);
+    return EIGCG_OK;
+  });
+}
+
+int eigcg_noalloc_scratch_bytes(uint64_t* bytes) {
+  if (!bytes) return EIGCG_EINVAL;
+  *bytes = eigcg::noalloc_scratch_bytes();
+  return EIGCG_OK;
+}
+
 int eigcg_schur_rhs(eigcg_ctx* ctx, int32_t nrhs, const void* b_full_dev, void* rhs_dev) {
   if (!ctx) return EIGCG_EINVAL;
   if (!ctx->c.g.eo) return fail(ctx, EIGCG_EINVAL, "context is not odd-even preconditioned");

@@ -119,6 +119,10 @@ struct Ctx {
 void ctx_init(Ctx& c, const eigcg_params& p, const void* gauge_dev, hipStream_t s);
 void ctx_release(Ctx& c);
 void apply_op(Ctx& c, int op, int nrhs, const void* in_aos, void* out_aos);
+// as apply_op for M, M^H, A in FP64, through a static device scratch array
+// (no allocation); noalloc_scratch_bytes() is the array's size
+void apply_op_noalloc(Ctx& c, int op, int nrhs, const void* in_aos, void* out_aos);
+size_t noalloc_scratch_bytes();
 void schur_rhs(Ctx& c, int nrhs, const void* b_full, void* rhs);
 void schur_reconstruct(Ctx& c, int nrhs, const void* b_full, const void* x_even, void* x_full);
 int solve(Ctx& c, int nrhs, const void* b_aos, void* x_aos, double tol, int mode,
