@@ -293,14 +293,29 @@ int eigcg_memory(eigcg_ctx* ctx, uint64_t* bytes);
  *   8  as 5, each XCD sweeping its t-slab in (z, t, xy) tile order
  *   9  as 8 with at most two workgroups per compute unit
  *  10  as 9 with cached (not streaming) epilogue loads and stores
- * (8-10 need Lx Ly divisible by 64 and Lt by 8, else they run as 5 / 6 / 6;
- * 16-bit storage runs 1-4 as 5 and 10 as 9).
- * eigcg_tune_report: tune_ms (20 doubles) receives the ms that variants 1..10
+ *  11  z-march: each lane marches the z-planes of one (x, y, t) column, so
+ *      the z-hops reuse spinors and links from registers; XCD x owns a t-slab
+ *  12  as 11 with the z-range in 2 chunks; 13: in 4 chunks (more waves)
+ * (8-13 need Lx Ly divisible by 64 and Lt by 8, else they run as 5 / 6 / 6;
+ * 16-bit storage runs 1-4 as 5 and 10 as 9; odd-even contexts run 1-2 as 3
+ * and 11-13 as 6).
+ * eigcg_tune_report: tune_ms (26 doubles) receives the ms that variants 1..13
  * took (best over columns per workgroup) for one CG-shaped pair of stencil
  * passes over a full batch at create, FP64 then FP32 (0 where not timed, e.g.
  * a forced variant). */
 int eigcg_layout_info(eigcg_ctx* ctx, int32_t* info);
 int eigcg_tune_report(eigcg_ctx* ctx, double* tune_ms);
+
+/* The stencil tuner's choices per (lattice, plane stride, geometry,
+ * precision, link storage, batch width) are kept for the process and
+ * persisted in a text file (one line per choice: device and library build,
+ * the key, the variant, columns per workgroup and the timings), so that
+ * later processes skip the timing: the file is the environment variable
+ * EIGCG_TUNE_CACHE (empty or "off": no file), else
+ * $XDG_CACHE_HOME/eigcg/stencil_tune.txt or ~/.cache/eigcg/stencil_tune.txt.
+ * eigcg_tune_cache_reset drops the process's choices (the file stays), so the
+ * next create reads the file again or re-tunes. */
+int eigcg_tune_cache_reset(void);
 
 /* Average device time (ms) of one launch, from HIP events on the context's
  * stream around reps back-to-back launches: what 0 = FP64 stencil M, 1 = plain

@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libeigcg.so")
 
 EIGCG_OK, EIGCG_EINVAL, EIGCG_ENOMEM, EIGCG_ENOTCONV = 0, -1, -2, -3
-STENCIL_VARIANTS = 10
+STENCIL_VARIANTS = 13
 EIGCG_EBREAKDOWN, EIGCG_EHIP, EIGCG_EBUSY = -4, -5, -6
 EIGCG_FP64, EIGCG_MIXED_FP32, EIGCG_MIXED_HALF = 0, 1, 2
 EIGCG_MODE_CG, EIGCG_MODE_EIGCG, EIGCG_MODE_INITCG, EIGCG_MODE_AUTO = 0, 1, 2, 3
@@ -116,6 +116,7 @@ SIGNATURES = {
     "eigcg_last_error": (ctypes.c_char_p, [_VP]),
     "eigcg_layout_info": (_I32, [_VP, ctypes.POINTER(_I32)]),
     "eigcg_tune_report": (_I32, [_VP, _DP]),
+    "eigcg_tune_cache_reset": (_I32, []),
     "eigcg_time_kernel": (_I32, [_VP, _I32, _I32, _DP]),
     "eigcg_kernel_samples": (_I32, [_VP, _I32, _DP]),
     "eigcg_server_create": (_I32, [ctypes.c_uint64, ctypes.POINTER(_VP)]),
@@ -445,6 +446,10 @@ def eigcg_layout_info(ctx):
             "links32_two_rows": bool(info[3]), "variant64": info[4], "variant32": info[5],
             "cols_per_group64": info[6], "cols_per_group32": info[7],
             "tune_ms64": ms[:STENCIL_VARIANTS].tolist(), "tune_ms32": ms[STENCIL_VARIANTS:].tolist()}
+
+
+def eigcg_tune_cache_reset():
+    return LIB.eigcg_tune_cache_reset()
 
 
 def eigcg_time_kernel(ctx, what, reps):

@@ -322,6 +322,11 @@ int eigcg_debug_span(int32_t op, uint64_t addr, uint64_t bytes) {
   return EIGCG_EINVAL;
 }
 
+int eigcg_tune_cache_reset(void) {
+  eigcg::tune_cache_reset();
+  return EIGCG_OK;
+}
+
 int eigcg_layout_info(eigcg_ctx* ctx, int32_t* info) {
   if (!ctx || !info) return EIGCG_EINVAL;
   info[0] = ctx->c.g.V;

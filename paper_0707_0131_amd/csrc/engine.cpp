@@ -15,9 +15,13 @@
 // row w^H V uses t saved by the device on a schedule it advances itself.
 #include "engine.h"
 
+#include <sys/stat.h>
+
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -132,20 +136,124 @@ static size_t elem_bytes(int prec) { return prec == kF64 ? 16 : (prec == kF32 ? 
 static void ws_ensure(Ctx& c, Workspace& w, int prec, bool eig);
 static StencilLaunch stencil_base(Ctx& c, int prec);
 
-// Stencil autotuner: times every kernel variant, and for the two-tile
-// variants every number of columns per workgroup, on this lattice at the
-// context's batch width, and keeps the fastest.  The choice is cached per
-// (lattice shape, precision, link storage, batch width) for the process.
-// Variants differ in summation order at the rounding level; columns per
-// workgroup do not change any column's arithmetic.  A forced variant in the
-// parameters wins (with the widest column grouping).
+// Stencil autotuner: times every kernel variant (the search space: site
+// mapping and sweep order, workgroups per CU, z-march chunking) and, for the
+// two-tile variants, every number of columns per workgroup, on this lattice
+// at the context's batch width, and keeps the fastest.  The choice is cached
+// per (lattice shape, plane stride, geometry, precision, link storage, batch
+// width) for the process and persisted in a file keyed by the device and the
+// library build, so later processes skip the timing.  Variants differ in
+// summation order at the rounding level; columns per workgroup do not change
+// any column's arithmetic.  A forced variant in the parameters wins (with
+// the widest column grouping).
+namespace {
+
+struct TunePick {
+  std::vector<double> ms;  // best time per variant
+  int var, nc;
+};
+
+std::mutex g_tune_mu;
+std::map<std::vector<int>, TunePick> g_tune;  // this process's choices
+
+// File of persisted choices: EIGCG_TUNE_CACHE (empty or "off": none), else
+// $XDG_CACHE_HOME/eigcg/stencil_tune.txt or ~/.cache/eigcg/stencil_tune.txt.
+std::string tune_cache_path() {
+  const char* e = std::getenv("EIGCG_TUNE_CACHE");
+  if (e) return (*e == 0 || std::strcmp(e, "off") == 0) ? std::string() : std::string(e);
+  const char* x = std::getenv("XDG_CACHE_HOME");
+  const char* h = std::getenv("HOME");
+  std::string dir;
+  if (x && *x) dir = std::string(x);
+  else if (h && *h) dir = std::string(h) + "/.cache";
+  else return std::string();
+  (void)mkdir(dir.c_str(), 0755);
+  dir += "/eigcg";
+  (void)mkdir(dir.c_str(), 0755);
+  return dir + "/stencil_tune.txt";
+}
+
+// The device and this build of the kernels: a persisted choice is used only
+// by the same library build on the same kind of device.
+std::string tune_tag(int device) {
+  hipDeviceProp_t prop{};
+  std::string arch = "unknown";
+  int cus = 0;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+    arch = prop.gcnArchName;
+    cus = prop.multiProcessorCount;
+  }
+  for (char& ch : arch)
+    if (ch == ' ' || ch == ':') ch = '_';
+  std::string build = __DATE__ "_" __TIME__;
+  for (char& ch : build)
+    if (ch == ' ' || ch == ':') ch = '_';
+  return arch + "/" + std::to_string(cus) + "cu/v" + std::to_string(kStencilVariants) + "/" + build;
+}
+
+std::string tune_line_key(const std::string& tag, const std::vector<int>& key) {
+  std::string k = tag;
+  for (int v : key) k += " " + std::to_string(v);
+  return k;
+}
+
+bool tune_file_lookup(const std::string& path, const std::string& lk, TunePick& pk) {
+  if (path.empty()) return false;
+  std::FILE* f = std::fopen(path.c_str(), "r");
+  if (!f) return false;
+  char buf[2048];
+  bool found = false;
+  while (std::fgets(buf, sizeof(buf), f)) {  // the last matching line wins
+    std::string line(buf);
+    const size_t sep = line.find(" : ");
+    if (sep == std::string::npos || line.substr(0, sep) != lk) continue;
+    std::vector<double> vals;
+    const char* q = line.c_str() + sep + 3;
+    char* end = nullptr;
+    for (;;) {
+      const double v = std::strtod(q, &end);
+      if (end == q) break;
+      vals.push_back(v);
+      q = end;
+    }
+    if ((int)vals.size() != 2 + kStencilVariants) continue;
+    const int var = (int)vals[0];
+    if (var < 1 || var > kStencilVariants) continue;
+    pk.var = var;
+    pk.nc = (int)vals[1];
+    pk.ms.assign(vals.begin() + 2, vals.end());
+    found = true;
+  }
+  std::fclose(f);
+  return found;
+}
+
+void tune_file_append(const std::string& path, const std::string& lk, const TunePick& pk) {
+  if (path.empty()) return;
+  std::string line = lk + " : " + std::to_string(pk.var) + " " + std::to_string(pk.nc);
+  char num[64];
+  for (double v : pk.ms) {
+    std::snprintf(num, sizeof(num), " %.6g", v);
+    line += num;
+  }
+  line += "\n";
+  std::FILE* f = std::fopen(path.c_str(), "a");  // one short append per choice
+  if (!f) return;
+  std::fputs(line.c_str(), f);
+  std::fclose(f);
+}
+
+}  // namespace
+
+void tune_cache_reset() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.clear();
+}
+
 static void autotune_stencil(Ctx& c, int prec) {
-  struct Pick {
-    std::vector<double> ms;  // best time per variant
-    int var, nc;
-  };
-  static std::mutex mu;
-  static std::map<std::vector<int>, Pick> cache;
+  using Pick = TunePick;
+  std::mutex& mu = g_tune_mu;
+  auto& cache = g_tune;
   int& var = prec == kF64 ? c.var64 : c.var32;
   int& ncs = prec == kF64 ? c.nc64 : c.nc32;
   double* tms = c.tune_ms + (prec == kF64 ? 0 : kStencilVariants);
@@ -161,9 +269,15 @@ static void autotune_stencil(Ctx& c, int prec) {
     var = pk.var;
     ncs = pk.nc;
   };
+  const std::string path = tune_cache_path();
+  const std::string lkey = tune_line_key(tune_tag(c.device), key);
   {
     std::lock_guard<std::mutex> lk(mu);
     auto it = cache.find(key);
+    if (it == cache.end()) {
+      Pick pf;
+      if (tune_file_lookup(path, lkey, pf)) it = cache.emplace(key, pf).first;
+    }
     if (it != cache.end()) {
       apply(it->second);
       return;
@@ -186,8 +300,9 @@ static void autotune_stencil(Ctx& c, int prec) {
   double best = 1e300;
   const int ncmax = (w.K >= 4 && prec != kF64) ? 4 : (w.K >= 2 ? 2 : 1);
   for (int v = c.g.eo ? 3 : 1; v <= kStencilVariants; ++v) {  // odd-even runs 1, 2 as 3
+    if (c.g.eo && v >= 11) break;  // the z-march needs the full geometry
     for (int nc = 1; nc <= ncmax; nc *= 2) {
-      if (v < 3 && nc > 1) break;
+      if ((v < 3 || v >= 11) && nc > 1) break;
       StencilLaunch L1 = stencil_base(c, prec);
       L1.variant = v;
       L1.nc = nc;
@@ -230,7 +345,10 @@ static void autotune_stencil(Ctx& c, int prec) {
   c.check(hipStreamSynchronize(c.stream), "sync");
   std::lock_guard<std::mutex> lk(mu);
   auto it = cache.find(key);
-  if (it == cache.end()) it = cache.emplace(key, pk).first;
+  if (it == cache.end()) {
+    it = cache.emplace(key, pk).first;
+    tune_file_append(path, lkey, pk);
+  }
   apply(it->second);
 }
 
@@ -268,6 +386,7 @@ void ctx_init(Ctx& c, const eigcg_params& p, const void* gauge_dev, hipStream_t 
           "hipHostMalloc");
   c.d_partial = (double*)c.dalloc(sizeof(double) * (size_t)(kMaxCols + 2) * kMaxGrid * 2);
   c.d_counter = (unsigned int*)c.dalloc(256);
+  c.d_ucount = (unsigned int*)c.dalloc(sizeof(unsigned int) * kMaxCols);
   c.gpart_elems = (size_t)1 << 21;  // 32 MiB of double2 chunk partials
   c.d_gpart = (double2*)c.dalloc(sizeof(double2) * c.gpart_elems);
   c.small_elems = kSmallElems;
@@ -337,6 +456,7 @@ void ctx_release(Ctx& c) {
   v = c.d_hist; c.dfree(v);
   v = c.d_partial; c.dfree(v);
   v = c.d_counter; c.dfree(v);
+  v = c.d_ucount; c.dfree(v);
   v = c.d_gpart; c.dfree(v);
   v = c.d_small; c.dfree(v);
   v = c.d_norm; c.dfree(v);
@@ -835,6 +955,14 @@ struct Run {
     L3.ring_cs = c.cs;
     L3.ring_len = w.ring_len;
     L3.ring_col_cs = (size_t)w.ring_len * c.cs;
+    // the update kernel forms the CG scalars from both passes' partials
+    int nb2 = 0;
+    L2.grid_out = &nb2;
+    L3.part_a = c.d_partial;
+    L3.part_b = c.d_partial + (size_t)kMaxCols * kMaxGrid;
+    L3.hist = c.d_hist;
+    L3.hist_stride = c.hist_stride;
+    L3.counter = c.d_ucount;
     if (c.P.use_graphs && c.P.sample_every <= 0 && n > 0) {
       auto it = graphs.find(n);
       if (it == graphs.end()) {
@@ -848,6 +976,7 @@ struct Run {
         for (int i = 0; i < n && e == hipSuccess; ++i) {
           e = launch_stencil(L1, c.gstream);
           if (e == hipSuccess) e = launch_stencil(L2, c.gstream);
+          L3.nb = nb2;
           if (e == hipSuccess) e = launch_cg_update(L3, c.gstream);
         }
         const hipError_t e2 = hipStreamEndCapture(c.gstream, &gr);
@@ -872,6 +1001,7 @@ struct Run {
       L2.ev_stop = ks ? ks->e[3] : nullptr;
       c.check(launch_stencil(L1, c.stream), "K1");
       c.check(launch_stencil(L2, c.stream), "K2");
+      L3.nb = nb2;
       c.check(launch_cg_update(L3, c.stream), "K3");
     }
     enq_iter += n;

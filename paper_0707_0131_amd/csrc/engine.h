@@ -80,6 +80,7 @@ struct Ctx {
   int hist_stride = 0;             // doubles per column
   double* d_partial = nullptr;
   unsigned int* d_counter = nullptr;
+  unsigned int* d_ucount = nullptr;  // per-column arrival counters of the CG update kernel
   double2* d_gpart = nullptr;
   size_t gpart_elems = 0;
   double2* d_small = nullptr;      // small matrices (S, G) for GEMMs
@@ -139,6 +140,8 @@ double bench_kernels(Ctx& c, int what, int reps);
 bool auto_continue(int done, int left, const double* iters, const double* secs, double iter_ms,
                    int bank_room);
 void kernel_samples(Ctx& c, bool reset, double* out);
+// drop this process's stencil tuning choices (the persisted file stays)
+void tune_cache_reset();
 
 // Engine helpers shared by the solver files (engine.cpp, bicgstab.cpp).
 // Host-side bounds layer over the library's device allocations: every

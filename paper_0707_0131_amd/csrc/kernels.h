@@ -16,8 +16,8 @@ enum StencilOp { kOpM = 0, kOpMdag = 1 };
 enum StencilEpi {
   kEpiStore = 0,   // out = op(in)
   kEpiNorm = 1,    // out = op(in); partials of ||out||^2 = p^H A p (first CG pass)
-  kEpiCGR = 2,     // alpha from the first pass; t = op(in); r -= alpha t; r^H r; then a
-                   // finalize kernel updates alpha, beta and the stop tests
+  kEpiCGR = 2,     // alpha from the first pass; t = op(in); r -= alpha t; r^H r (the
+                   // update kernel that follows forms beta and the stop tests)
   kEpiRes = 3,     // r = b - op(in); r^H r -> rho (true residual, with finalize)
 };
 
@@ -32,16 +32,20 @@ enum StencilEpi {
 //  8: as 5, each XCD sweeping a t-slab in (z, t, xy) tile order
 //  9: as 8 with at most two workgroups per CU
 // 10: as 9 with cached (not streaming) epilogue loads and stores
-// 8-10 need whole 64-site tiles per xy-plane and Lt divisible by 8; other
-// lattices run 5 and 6 (10 as 6) instead.
-constexpr int kStencilVariants = 10;
+// 11: z-march: each lane marches the z-planes of one (x, y, t) column, the
+//     z-hops from registers, XCD x owning a t-slab (stencil_impl.h)
+// 12, 13: as 11 with the z-range split in 2 or 4 chunks (more waves)
+// 8-13 need whole 64-site tiles per xy-plane and Lt divisible by 8; other
+// lattices run 5 and 6 (10-13 as 6) instead; the odd-even geometry runs
+// 11-13 as 6.
+constexpr int kStencilVariants = 13;
 
 struct StencilLaunch {
   int prec;                 // kF64 / kF32 (vectors and links)
   int op;                   // kOpM / kOpMdag
   int epi;                  // StencilEpi
   int compressed;           // links stored as two rows
-  int variant;              // stencil kernel variant 1..3 (0 = 1)
+  int variant;              // stencil kernel variant 1..kStencilVariants (0 = 1)
   const void* in; size_t in_cs;     // column stride in complex elements
   void* out; size_t out_cs;         // kEpiStore / kEpiNorm target
   const void* u;
@@ -58,6 +62,8 @@ struct StencilLaunch {
   double* hist; int hist_stride;    // kEpiCGR: per column 3 doubles per iteration
   hipEvent_t ev_start = nullptr;    // when set: timestamps of the stencil kernel's own
   hipEvent_t ev_stop = nullptr;     // start and end, taken by its dispatch
+  int* grid_out = nullptr;          // when set: receives the grid's x extent (the number
+                                    // of partials per column the pass writes)
   int nc = 0;                       // variants 3..10: columns per workgroup (1, 2, or 4
                                     // for FP32); 0 = widest that ncols allows
   // Odd-even geometry (g->eo): op is the even-site Schur complement
@@ -83,8 +89,14 @@ hipError_t launch_stencil_eo_f64(const StencilLaunch& L, hipStream_t s);
 hipError_t launch_stencil_eo_f32(const StencilLaunch& L, hipStream_t s);
 hipError_t launch_stencil_eo_f16(const StencilLaunch& L, hipStream_t s);
 
-// End of a CG iteration: x += alpha p; (running) p = r + beta p; optional window append
-// V_ring[(iter + 1) % ring] = r / sqrt(rho).
+// End of a CG iteration: the iteration's scalars from the two stencil passes'
+// partials (alpha = rho / p^H A p, beta = rho_new / rho, history, stop tests,
+// eigCG t-save schedule), then x += alpha p; (running) p = r + beta p;
+// optional window append V_ring[(iter + 1) % ring] = r / sqrt(rho).  Every
+// workgroup forms the scalars itself from the column state as it was before
+// the iteration; the last workgroup of a column to finish (counted by an
+// atomic counter per column, which it resets) stores the new state, so no
+// workgroup reads a state another one has already replaced.
 struct UpdateLaunch {
   int prec;
   int ncols;
@@ -95,6 +107,11 @@ struct UpdateLaunch {
   void* p; size_t p_cs;
   const void* r; size_t r_cs;
   void* ring; size_t ring_cs; int ring_len; size_t ring_col_cs;  // slot stride, column stride
+  const double* part_a;     // first pass (||M p||^2) partials, nb per column
+  const double* part_b;     // second pass (r^H r) partials, nb per column
+  int nb;
+  double* hist; int hist_stride;  // alpha, beta, rho_new per iteration (or null)
+  unsigned int* counter;    // kMaxCols counters, zero between launches
 };
 hipError_t launch_cg_update(const UpdateLaunch& L, hipStream_t s);
 

@@ -10,8 +10,8 @@
 // (||M p||^2 and r^H r) are deterministic and fence-free: fixed-order
 // wave/workgroup sums into one partial slot per workgroup; the second pass
 // sums the first pass's partials itself (same order in every workgroup) to
-// get alpha, and a one-workgroup finalize kernel, ordered by the stream,
-// updates the CG scalars of every column.
+// get alpha, and the update kernel that follows sums both passes' partials
+// the same way to form the CG scalars of every column.
 #include <algorithm>
 #include <type_traits>
 
@@ -42,6 +42,7 @@ struct DevArgs {
   void* tbuf; size_t t_cs;
   double* hist; int hist_stride;
   uint32_t ord_P, ord_Ls;   // slab sweep: 64-site tiles per xy-plane, t-slices per XCD
+  uint32_t zc_n, zc_len;    // z-march: z-chunks per (xy tile, t) column and their length
   // odd-even geometry: output parity, the other parity's link block, and
   // out = dg in2 + ch (hopping sum of in) at the centre (in2 may be null)
   uint32_t par;
@@ -130,7 +131,7 @@ __device__ __forceinline__ bool column_setup(const DevArgs& a, int col, double* 
   save_slot = 0;
   if (EPI == kEpiCGR) {
     // alpha = rho / ||M p||^2 from the first pass's partials, summed in the
-    // same fixed order by every workgroup (and by the finalize kernel)
+    // same fixed order by every workgroup (and by the update kernel)
     const double pap = reduce_partials(a.partial_in + (size_t)col * gridDim.x, gridDim.x, lds4);
     if (active) {
       if (pap > 0.0 && pap < INFINITY) {
@@ -139,7 +140,7 @@ __device__ __forceinline__ bool column_setup(const DevArgs& a, int col, double* 
         save_t = a.tbuf != nullptr && (j == a.st[col].save_t0 || j == a.st[col].save_t1);
         save_slot = j & 1;
       } else {
-        active = false;  // breakdown: the finalize kernel stops the column
+        active = false;  // breakdown: the update kernel stops the column
       }
     }
   }
@@ -334,62 +335,129 @@ __global__ __launch_bounds__(kBlock) void k_wilson_pair(DevArgs a) {
   }
 }
 
-// CG scalars after the second stencil pass (one workgroup): p^H A p from the
-// first pass's partials (alpha, or breakdown), r^H r from the second pass's
-// partials (beta, history, stop tests, eigCG t-save schedule).
-__global__ __launch_bounds__(kBlock) void k_finalize_cg(ColState* st, int ncols, uint32_t mask,
-                                                        const double* part_a, const double* part_b,
-                                                        int nb, double* hist, int hist_stride) {
+// Variants 11..13: z-march.  Lane l of a wave owns the sites (xy = 64 tile +
+// l, z, t) of one t-slice and marches z through a chunk of zc_len planes.
+// The z-hops come from registers: the forward hop's link U_z(s) also forms
+// the backward hop of site s + z, U_z(s)^+ (1 -+ g_z) psi(s), which is carried
+// to the next plane, so along z every spinor and link is loaded once by its
+// own lane.  The x, y and t neighbours of a plane are the sites the other
+// lanes and waves march over at the same time (all waves start at the first
+// plane of their chunk together), so they are L2 hits.  XCD x owns the
+// t-slab [x Ls, (x + 1) Ls) (workgroup b runs on XCD b mod 8), so the working
+// set of one plane step on an XCD is one z-plane of its slab.  Per site the
+// hops are accumulated in the order of variant 1 (x, y, z forward then
+// backward, t) with the same expressions: a site's output equals variant 1's
+// bit for bit; only the order of the partial sums of the reductions differs.
+template <typename VS, typename LS, bool COMP, bool DAG, int EPI>
+__global__ __launch_bounds__(kBlock) void k_wilson_zmarch(DevArgs a) {
+  using R = typename Storage<VS>::real;
+  constexpr int SF = DAG ? 1 : -1;
   __shared__ double lds4[kBlock / 64];
-  {
-    const int c = blockIdx.x;  // one workgroup per column
-    if (c >= ncols || !((mask >> c) & 1u)) return;
-    const double pap = reduce_partials(part_a + (size_t)c * nb, nb, lds4);
-    const double rho_new = reduce_partials(part_b + (size_t)c * nb, nb, lds4);
-    if (threadIdx.x != 0) return;
-    ColState& S = st[c];
-    if (S.state == ColRun) {
-      S.pap = pap;
-      if (!(pap > 0.0 && pap < INFINITY)) {
-        S.alpha = 0.0;
-        S.state = ColStopPending;
-        S.reason = ReasonBreakdown;
-        return;
+  __shared__ R ldsr[kBlock / 64];
+  const int col = blockIdx.y;
+  R alpha;
+  bool save_t;
+  int save_slot;
+  const bool active = column_setup<VS, EPI>(a, col, lds4, alpha, save_t, save_slot);
+  const VS* in = reinterpret_cast<const VS*>(a.in) + (size_t)col * a.in_cs;
+  const LS* u = reinterpret_cast<const LS*>(a.u);
+  const size_t vs = (size_t)a.g.vs;
+  R acc2 = R(0);
+  const uint32_t P = a.ord_P, Ls = a.ord_Ls;
+  const uint32_t wv = (blockIdx.x >> 3) * (kBlock / 64) + (threadIdx.x >> 6);  // wave of the XCD
+  if (active && wv < P * Ls * a.zc_n) {
+    const uint32_t tile = wv % P, rest = wv / P;
+    const uint32_t t = (blockIdx.x & 7u) * Ls + rest % Ls;
+    const uint32_t zc = rest / Ls;
+    const uint32_t xy = tile * 64u + (threadIdx.x & 63u);
+    const uint32_t Lz = (uint32_t)a.g.L[2];
+    const uint32_t plane = (uint32_t)a.g.stride[2];  // Lx Ly
+    const uint32_t z0 = zc * a.zc_len;
+    const uint32_t z1 = min(z0 + a.zc_len, Lz);
+    uint32_t coord[4];
+    coord[1] = a.g.dx.div(xy);
+    coord[0] = xy - coord[1] * (uint32_t)a.g.L[0];
+    coord[3] = t;
+    const uint32_t base = t * Lz * plane + xy;  // site at z = 0
+    // carried backward z-hop: g = U_z(s - z)^+ h(psi(s - z)), two spin rows x 3 colours
+    cpx<R> cg[6];
+    auto carry = [&](uint32_t sb, const cpx<R>* U) {
+      cpx<R> h[6];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        cpx<R> u0 = Storage<VS>::ld(in, (size_t)(0 + c) * vs + sb);
+        cpx<R> u1 = Storage<VS>::ld(in, (size_t)(3 + c) * vs + sb);
+        cpx<R> l0 = Storage<VS>::ld(in, (size_t)(6 + c) * vs + sb);
+        cpx<R> l1 = Storage<VS>::ld(in, (size_t)(9 + c) * vs + sb);
+        project<2, -SF>(u0, u1, l0, l1, h[c], h[3 + c]);
       }
-      S.alpha = S.rho / pap;
-      const int j = S.iter + 1;
-      const double beta = rho_new / S.rho;
-      if (hist) {
-        double* h = hist + (size_t)c * hist_stride + (size_t)3 * (j - 1);
-        h[0] = S.alpha;
-        h[1] = beta;
-        h[2] = rho_new;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        cpx<R> g0 = cmulc(U[0 * 3 + c], h[0]);
+        cpx<R> g1 = cmulc(U[0 * 3 + c], h[3]);
+        g0 = cadd(g0, cmulc(U[1 * 3 + c], h[1]));
+        g1 = cadd(g1, cmulc(U[1 * 3 + c], h[4]));
+        g0 = cadd(g0, cmulc(U[2 * 3 + c], h[2]));
+        g1 = cadd(g1, cmulc(U[2 * 3 + c], h[5]));
+        cg[c] = g0;
+        cg[3 + c] = g1;
       }
-      S.iter = j;
-      if (j == S.save_t1 && S.tperiod > 0) {
-        S.save_t0 += S.tperiod;
-        S.save_t1 += S.tperiod;
+    };
+    if (z0 < z1) {  // prologue: the backward hop into the chunk's first plane
+      const uint32_t sb = base + ((z0 > 0 ? z0 : Lz) - 1u) * plane;
+      cpx<R> U[9];
+      load_link<LS, COMP>(u, 2, vs, sb, U);
+      carry(sb, U);
+    }
+    for (uint32_t z = z0; z < z1; ++z) {
+      const uint32_t s = base + z * plane;
+      coord[2] = z;
+      cpx<R> acc[12];
+#pragma unroll
+      for (int e = 0; e < 12; ++e) acc[e] = {R(0), R(0)};
+      hop_dir<0, VS, LS, COMP, SF>(in, u, a.g, s, coord, acc);
+      hop_dir<1, VS, LS, COMP, SF>(in, u, a.g, s, coord, acc);
+      {
+        cpx<R> U[9];
+        load_link<LS, COMP>(u, 2, vs, s, U);
+        const uint32_t sf = z + 1u < Lz ? s + plane : base;
+        cpx<R> h[6];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          cpx<R> u0 = Storage<VS>::ld(in, (size_t)(0 + c) * vs + sf);
+          cpx<R> u1 = Storage<VS>::ld(in, (size_t)(3 + c) * vs + sf);
+          cpx<R> l0 = Storage<VS>::ld(in, (size_t)(6 + c) * vs + sf);
+          cpx<R> l1 = Storage<VS>::ld(in, (size_t)(9 + c) * vs + sf);
+          project<2, SF>(u0, u1, l0, l1, h[c], h[3 + c]);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          cpx<R> g0 = cmul(U[c * 3 + 0], h[0]);
+          cpx<R> g1 = cmul(U[c * 3 + 0], h[3]);
+          g0 = cadd(g0, cmul(U[c * 3 + 1], h[1]));
+          g1 = cadd(g1, cmul(U[c * 3 + 1], h[4]));
+          g0 = cadd(g0, cmul(U[c * 3 + 2], h[2]));
+          g1 = cadd(g1, cmul(U[c * 3 + 2], h[5]));
+          accumulate<2, SF>(acc, c, g0, g1);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) accumulate<2, -SF>(acc, c, cg[c], cg[3 + c]);
+        carry(s, U);  // the backward hop into plane z + 1
       }
-      S.rho_prev = S.rho;
-      S.rho = rho_new;
-      S.beta = beta;
-      if (!(rho_new < INFINITY)) {
-        S.state = ColStopPending;
-        S.reason = ReasonBreakdown;
-      } else if (rho_new <= S.stop2) {
-        S.state = ColStopPending;
-        S.reason = ReasonConverged;
-      } else if (rho_new <= S.restart2) {
-        S.state = ColStopPending;
-        S.reason = ReasonRestart;
-      } else if (j >= S.max_iter) {
-        S.state = ColStopPending;
-        S.reason = ReasonMaxIter;
+      hop_dir<3, VS, LS, COMP, SF>(in, u, a.g, s, coord, acc);
+      const R d = (R)a.diag;
+      cpx<R> o[12];
+#pragma unroll
+      for (int e = 0; e < 12; ++e) {
+        cpx<R> v = Storage<VS>::ld(in, (size_t)e * vs + s);
+        o[e] = {d * v.re - R(0.5) * acc[e].re, d * v.im - R(0.5) * acc[e].im};
       }
-    } else if (S.state == ColStopPending) {
-      S.state = ColStopped;
+      epilogue<VS, EPI, 0, 12, true>(a, col, s, o, alpha, save_t, save_slot, acc2);
     }
   }
+  if (EPI == kEpiStore) return;
+  R bs = block_sum(acc2, ldsr);
+  if (threadIdx.x == 0) a.partial[(size_t)col * gridDim.x + blockIdx.x] = (double)bs;
 }
 
 // rho = ||b - A x||^2 of a true-residual pass
@@ -481,15 +549,31 @@ hipError_t launch_typed(const StencilLaunch& L, hipStream_t s) {
     if (variant == 10) variant = 9;
   }
   const uint32_t plane = (uint32_t)(L.g->L[0] * L.g->L[1]) >> (EO ? 1 : 0);
-  if (variant >= 8 && (plane % 64u != 0 || L.g->L[3] % 8 != 0))
-    variant = variant == 8 ? 5 : 6;  // the slab sweep needs whole tiles per plane, 8 slabs
   a.ord_P = plane / 64u;
   a.ord_Ls = (uint32_t)L.g->L[3] / 8u;
+  a.zc_n = 1;
+  a.zc_len = (uint32_t)L.g->L[2];
+  int gx = 0;
+  if (variant >= 11) {
+    // z-march: 1, 2 or 4 z-chunks per column; needs the full geometry, whole
+    // 64-site tiles per xy-plane, a t-slab per XCD and a grid within kMaxGrid
+    const uint32_t n = variant == 11 ? 1u : variant == 12 ? 2u : 4u;
+    const uint32_t Lz = (uint32_t)L.g->L[2];
+    a.zc_n = std::min(n, Lz);
+    a.zc_len = (Lz + a.zc_n - 1) / a.zc_n;
+    a.zc_n = (Lz + a.zc_len - 1) / a.zc_len;  // no empty chunk
+    const uint32_t waves = a.ord_P * a.ord_Ls * a.zc_n;
+    gx = (int)(8u * ((waves + kBlock / 64 - 1) / (kBlock / 64)));
+    if (EO || plane % 64u != 0 || L.g->L[3] % 8 != 0 || gx > kMaxGrid) variant = 6;
+  }
+  if (variant >= 8 && variant <= 10 && (plane % 64u != 0 || L.g->L[3] % 8 != 0))
+    variant = variant == 8 ? 5 : 6;  // the slab sweep needs whole tiles per plane, 8 slabs
   const uint32_t unit = variant >= 3 ? 128u : (uint32_t)kBlock;
   const uint32_t T = ((uint32_t)L.g->V + unit - 1) / unit;
-  int gx;
   size_t dyn_lds = 0;
-  if (variant == 1) {
+  if (variant >= 11) {
+    // grid set above
+  } else if (variant == 1) {
     gx = (int)std::min<uint32_t>(T, kMaxGrid);
   } else if (variant >= 5) {
     // as many workgroups as are resident at once (multiple of 8), so each
@@ -506,7 +590,7 @@ hipError_t launch_typed(const StencilLaunch& L, hipStream_t s) {
   // do not depend on it, so every column's reductions are the same for any
   // batch width.  FP64 takes at most 2 (LDS of the exchange buffer).
   int nc = 1;
-  if (variant >= 3 && L.compressed && L.ncols >= 2) {
+  if (variant >= 3 && variant <= 10 && L.compressed && L.ncols >= 2) {
     const int widest = (L.ncols >= 4 && sizeof(typename Storage<VS>::real) == 4) ? 4 : 2;
     nc = L.nc > 0 ? std::min(L.nc, widest) : widest;
     if (nc == 3) nc = 2;
@@ -524,7 +608,11 @@ hipError_t launch_typed(const StencilLaunch& L, hipStream_t s) {
     EIGCG_LAUNCH((k_wilson_pair<VS, LS, COMP, DAG, EPI, NT, ORD, 1, EO>), dyn_lds)   \
   }
 #define EIGCG_K(COMP, DAG, EPI)                                                      \
-  if (variant == 10) {                                                               \
+  if (variant >= 11) {                                                               \
+    if constexpr (!EO) {                                                             \
+      EIGCG_LAUNCH((k_wilson_zmarch<VS, LS, COMP, DAG, EPI>), 0)                     \
+    }                                                                                \
+  } else if (variant == 10) {                                                        \
     EIGCG_PAIR(COMP, DAG, EPI, false, 1)                                             \
   } else if (variant >= 8) {                                                         \
     EIGCG_PAIR(COMP, DAG, EPI, true, 1)                                              \
@@ -548,7 +636,11 @@ hipError_t launch_typed(const StencilLaunch& L, hipStream_t s) {
   }
   if constexpr (kHalf) {
 #define EIGCG_KH(COMP, DAG, EPI)                                                     \
-  if (variant >= 8) {                                                                \
+  if (variant >= 11) {                                                               \
+    if constexpr (!EO) {                                                             \
+      EIGCG_LAUNCH((k_wilson_zmarch<VS, LS, COMP, DAG, EPI>), 0)                     \
+    }                                                                                \
+  } else if (variant >= 8) {                                                         \
     EIGCG_PAIR(COMP, DAG, EPI, true, 1)                                              \
   } else {                                                                           \
     EIGCG_PAIR(COMP, DAG, EPI, true, 0)                                              \
@@ -577,10 +669,10 @@ hipError_t launch_typed(const StencilLaunch& L, hipStream_t s) {
 #undef EIGCG_LAUNCH
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (L.epi == kEpiCGR)
-    hipLaunchKernelGGL(k_finalize_cg, dim3(L.ncols), dim3(kBlock), 0, s, L.st, L.ncols, L.mask, part_a,
-                       part_b, gx, L.hist, L.hist_stride);
-  else if (L.epi == kEpiRes)
+  if (L.grid_out) *L.grid_out = gx;
+  // kEpiCGR: the update kernel that follows forms the CG scalars from both
+  // passes' partials (launch_cg_update)
+  if (L.epi == kEpiRes)
     hipLaunchKernelGGL(k_finalize_res, dim3(L.ncols), dim3(kBlock), 0, s, L.st, L.ncols, L.mask, part_b,
                        gx);
   return hipGetLastError();

@@ -71,3 +71,40 @@ def test_gemm_reduce(B, dt, n, K, N):
     ref = A.astype(np.complex128).conj() @ R.astype(np.complex128).T
     tol = 1e-13 if dt == "c128" else 2e-6
     assert np.max(np.abs(out - ref)) <= tol * np.sqrt(n) * 2
+
+
+def test_tuning_choices_are_persisted(B, tmp_path, monkeypatch):
+    """The stencil tuner writes its choice to the file named by
+    EIGCG_TUNE_CACHE; a later process (here: after dropping this process's
+    choices) takes the choice from the file instead of timing again."""
+    import torch
+    from synthetic import gauge_field
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("EIGCG_TUNE_CACHE", str(path))
+    B.eigcg_tune_cache_reset()
+    dims = (8, 8, 4, 8)
+    U = torch.from_numpy(gauge_field(dims, 0.5, 11)).to("cuda:0")
+    try:
+        p = B.eigcg_default_params(dims=dims, mass=-0.2, max_bank=0, max_batch=3)
+        ctx = B.eigcg_create(p, U)
+        info = B.eigcg_layout_info(ctx)
+        B.eigcg_destroy(ctx)
+        lines = path.read_text().splitlines()
+        assert len(lines) == 1
+        key, val = lines[0].split(" : ")
+        fields = val.split()
+        assert int(fields[0]) == info["variant64"]
+        assert len(fields) == 2 + B.STENCIL_VARIANTS
+        # another choice in the file (variant 3, one column per workgroup) is
+        # what a fresh process takes
+        forced = [3, 1] + [float(v) for v in fields[2:]]
+        path.write_text(key + " : " + " ".join(str(v) for v in forced) + "\n")
+        B.eigcg_tune_cache_reset()
+        ctx = B.eigcg_create(p, U)
+        info2 = B.eigcg_layout_info(ctx)
+        B.eigcg_destroy(ctx)
+        assert info2["variant64"] == 3 and info2["cols_per_group64"] == 1
+        assert info2["tune_ms64"] == pytest.approx([float(v) for v in fields[2:]], rel=1e-5)
+        assert len(path.read_text().splitlines()) == 1  # nothing re-timed
+    finally:
+        B.eigcg_tune_cache_reset()

@@ -40,7 +40,7 @@ CASES = [
 @pytest.mark.parametrize("name,dims,eps,seed,mass", CASES)
 @pytest.mark.parametrize("compress,variant", [(0, 1), (1, 1), (1, 2), (1, 3), (0, 3), (1, 4),
                                               (1, 5), (1, 6), (1, 7), (1, 8), (1, 9), (0, 9),
-                                              (1, 10)])
+                                              (1, 10), (1, 11), (0, 11), (1, 12), (1, 13)])
 def test_apply_matches_oracle(B, name, dims, eps, seed, mass, compress, variant):
     U = gauge_field(dims, eps, seed)
     op = WilsonOperator(U, mass)
@@ -105,7 +105,7 @@ def _cg_candidates(apply_A, b, tol, x0=None):
     return cands, io
 
 
-@pytest.mark.parametrize("variant", list(range(1, 11)))
+@pytest.mark.parametrize("variant", list(range(1, 14)))
 def test_cg_parity_cfg0(B, cfg0, variant):
     """Single-column FP64 CG with every stencil variant: x matches the
     oracle's iterate after the same number of iterations to 1e-10."""
@@ -118,6 +118,57 @@ def test_cg_parity_cfg0(B, cfg0, variant):
         assert rc == B.EIGCG_OK, B.eigcg_last_error(ctx)
         assert st[0]["iters"] in cands, (st[0]["iters"], io["iterations"])
         assert st[0]["true_rel_res"] <= 1e-10
+        assert rel(host(x)[0].reshape(-1), cands[st[0]["iters"]]) <= 1e-10
+    finally:
+        B.eigcg_destroy(ctx)
+
+
+ZMARCH_LATTICES = [((8, 8, 3, 16), 0.5, 4, -0.15), ((8, 8, 8, 8), 0.5, 2, -0.3)]
+
+
+@pytest.mark.parametrize("dims,eps,seed,mass", ZMARCH_LATTICES)
+@pytest.mark.parametrize("compress", [0, 1])
+def test_zmarch_equals_variant1_bitwise(B, dims, eps, seed, mass, compress):
+    """The z-march kernels (variants 11-13: z-hops carried in registers, the
+    z-range in 1, 2 or 4 chunks; Lz = 3 gives chunks of one plane) form every
+    site's output with variant 1's operations in variant 1's order: M and
+    M^H agree bit for bit."""
+    U = gauge_field(dims, eps, seed)
+    psi = gaussian_rhs_block(dims, [31, 32])
+    outs = {}
+    for v in (1, 11, 12, 13):
+        ctx, _ = make_ctx(U, mass, compress_links=compress, max_batch=2, stencil_variant=v)
+        try:
+            assert B.eigcg_layout_info(ctx)["variant64"] == v
+            res = []
+            for code in (B.EIGCG_OP_M, B.EIGCG_OP_MDAG, B.EIGCG_OP_A):
+                out = dev(np.zeros_like(psi))
+                B.eigcg_apply(ctx, code, dev(psi), out)
+                res.append(host(out))
+            outs[v] = res
+        finally:
+            B.eigcg_destroy(ctx)
+    for v in (11, 12, 13):
+        for k in range(3):
+            assert np.array_equal(outs[v][k], outs[1][k]), (v, k)
+
+
+@pytest.mark.parametrize("variant", [11, 12, 13])
+def test_zmarch_cg_parity(B, variant):
+    """FP64 CG with the z-march stencil on a lattice it runs on (whole 64-site
+    tiles per xy-plane, Lt divisible by 8): x equals the oracle's iterate
+    after the same number of iterations to 1e-10."""
+    dims, eps, seed, mass = ZMARCH_LATTICES[0]
+    U = gauge_field(dims, eps, seed)
+    op = WilsonOperator(U, mass)
+    b = gaussian_rhs(dims, 1000)
+    cands, io = _cg_candidates(op.A, b.reshape(-1), 1e-10)
+    ctx, _ = make_ctx(U, mass, max_iter=5000, stencil_variant=variant)
+    try:
+        x = dev(np.zeros((1,) + b.shape, dtype=np.complex128))
+        rc, st = B.eigcg_solve(ctx, dev(b[None]), x, 1e-10, B.EIGCG_MODE_CG)
+        assert rc == B.EIGCG_OK, B.eigcg_last_error(ctx)
+        assert st[0]["iters"] in cands, (st[0]["iters"], io["iterations"])
         assert rel(host(x)[0].reshape(-1), cands[st[0]["iters"]]) <= 1e-10
     finally:
         B.eigcg_destroy(ctx)
