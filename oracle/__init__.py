@@ -17,8 +17,10 @@ Modules:
 
 * ``dirac``        - Wilson-Dirac operator M, its adjoint and A = M^H M
                      (Section 1; operator written out in the module).
-* ``cg``           - CG, left box of Figure 3.1, with P = I.
-* ``eigcg``        - eigCG(nev, m), right box of Figure 3.1.
+* ``cg``           - CG, left box of Figure 3.1 (P = I, or an SPD
+                     preconditioner given as P^{-1}).
+* ``eigcg``        - eigCG(nev, m), right box of Figure 3.1, also in the
+                     preconditioned form of Section 3 (V = P^{-1} R).
 * ``initcg``       - init-CG Galerkin guess, eq. (2.1), and the restarted
                      init-CG of Section 5.3.
 * ``incremental``  - Incremental eigCG outer loop (Section 4 algorithm box).
@@ -29,10 +31,12 @@ Modules:
 * ``bicgstab``     - BiCGSTAB on gamma5 M (or M) with a deflated initial
                      guess from the bank (Section 1's use of the eigCG
                      vectors for a nonsymmetric solver).
+* ``spectral``     - the bank used as a spectral preconditioner (Section
+                     2.1's alternative to init-CG; Section 4's example).
 
 Parity status: every function here is pinned by a test under ``tests/``
 (closed forms, invariants, dense linear algebra or brute force); nothing is
 "parity unpinned".
 """
 
-from . import dirac, cg, eigcg, initcg, incremental, dense, schur, bicgstab  # noqa: F401
+from . import dirac, cg, eigcg, initcg, incremental, dense, schur, bicgstab, spectral  # noqa: F401

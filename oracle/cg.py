@@ -1,13 +1,15 @@
 """Conjugate Gradient, plain FP64 (test infrastructure only).
 
-Follows the CG algorithm in the left box of Figure 3.1 of the paper with the
-preconditioner ``P = I`` (so ``z = r`` and ``rho = r^H r`` is real):
+Follows the CG algorithm in the left box of Figure 3.1 of the paper.  With
+the preconditioner ``P = I`` (the default) ``z = r`` and ``rho = r^H r``;
+with an SPD preconditioner given as ``apply_Pinv`` (``z = P^{-1} r``) the
+same box reads
 
     r = b - A x;  j = 0
     while not converged:
-        j += 1;  rho_prev = rho;  rho = r^H r
-        p = r                      (j == 1)
-        p = r + beta_j p,  beta_j = rho / rho_prev   (j > 1)
+        j += 1;  rho_prev = rho;  z = P^{-1} r;  rho = r^H z
+        p = z                      (j == 1)
+        p = z + beta_j p,  beta_j = rho / rho_prev   (j > 1)
         t = A p;  alpha_j = rho / (p^H t)
         x += alpha_j p;  r -= alpha_j t
 
@@ -35,11 +37,13 @@ def _real_positive(val, what):
     return float(val.real)
 
 
-def cg(apply_A, b, x0=None, tol=1e-10, max_iter=100000, true_residual_restarts=3):
+def cg(apply_A, b, x0=None, tol=1e-10, max_iter=100000, true_residual_restarts=3,
+       apply_Pinv=None):
     """Solve ``A x = b``; returns ``(x, info)``.
 
     ``info`` holds ``iterations``, ``alpha`` and ``beta`` (per iteration,
-    ``beta[0] = 0``), ``rho`` (``||r_{j-1}||^2`` seen at iteration j),
+    ``beta[0] = 0``), ``rho`` (``r_{j-1}^H z_{j-1}`` seen at iteration j,
+    ``||r_{j-1}||^2`` without a preconditioner),
     ``true_rel_res`` and ``converged``.
     """
     b = np.asarray(b, dtype=np.complex128).reshape(-1)
@@ -61,14 +65,15 @@ def cg(apply_A, b, x0=None, tol=1e-10, max_iter=100000, true_residual_restarts=3
         while np.linalg.norm(r) / bnorm > tol and j < max_iter:
             j += 1
             rho_prev = rho
-            rho = _real_positive(_dot(r, r), "r^H r")
+            z = r if apply_Pinv is None else apply_Pinv(r)
+            rho = _real_positive(_dot(r, z), "r^H z")
             if first:
                 beta = 0.0
-                p = r.copy()
+                p = z.copy()
                 first = False
             else:
                 beta = rho / rho_prev
-                p = r + beta * p
+                p = z + beta * p
             t = apply_A(p)
             pt = _real_positive(_dot(p, t), "p^H A p")
             if pt <= 0.0:

@@ -64,9 +64,21 @@ def restart_coefficients(Tm, nev):
     return Q @ Z, Mvals, Q, Z, Y, Ybar
 
 
-def eigcg(apply_A, b, nev, m, x0=None, tol=1e-10, max_iter=100000, record=False):
+def eigcg(apply_A, b, nev, m, x0=None, tol=1e-10, max_iter=100000, record=False,
+          apply_Pinv=None):
     """Solve ``A x = b`` while computing ``nev`` Ritz pairs; returns
     ``(x, ritz_vectors (n, k), ritz_values (k,), info)``.
+
+    ``apply_Pinv`` (``z = P^{-1} r`` for an SPD preconditioner P; default
+    P = I): the preconditioned form of Section 3.  CG then runs with
+    ``z = P^{-1} r``, ``rho = r^H z`` and ``p = z + beta p``, and the window
+    holds ``V = P^{-1} R`` normalised, ``v = z / sqrt(rho)``, so that
+    ``V^H P V = I`` and ``T = V^H A V`` is the Lanczos matrix of
+    ``P^{-1/2} A P^{-1/2}`` built from the same CG scalars.  The Ritz pairs
+    approximate the pencil ``A y = lambda P y``; their vectors ``V Y`` deflate
+    later systems through eq. (2.1) unchanged (the derivation of Section 3
+    with a general P).  The arrow row of a restart uses
+    ``w = t - beta t_prev = A z``.
 
     ``info`` holds ``iterations``, ``alpha``, ``beta``, ``rho``,
     ``restart_iterations`` (the CG iteration j at which each restart ran) and
@@ -100,13 +112,14 @@ def eigcg(apply_A, b, nev, m, x0=None, tol=1e-10, max_iter=100000, record=False)
     while np.linalg.norm(r) / bnorm > tol and j < max_iter:
         j += 1
         rho_prev = rho
-        rho = _real_positive(_dot(r, r), "r^H r")          # z = r (P = I)
+        z = r if apply_Pinv is None else apply_Pinv(r)     # z = P^{-1} r (z = r for P = I)
+        rho = _real_positive(_dot(r, z), "r^H z")
         if j == 1:
             beta = 0.0
-            p = r.copy()
+            p = z.copy()
         else:
             beta = rho / rho_prev
-            p = r + beta * p
+            p = z + beta * p
         if i == m:
             t_prev = t                                     # A p of the previous iteration
         t = apply_A(p)
@@ -120,7 +133,7 @@ def eigcg(apply_A, b, nev, m, x0=None, tol=1e-10, max_iter=100000, record=False)
             T[:, :] = 0.0
             T[: 2 * nev, : 2 * nev] = np.diag(Mvals)
             i = 2 * nev
-            w = t - beta * t_prev                          # w = A r
+            w = t - beta * t_prev                          # w = A z
             arrow = (w.conj() @ V[:, :i]) / np.sqrt(rho)   # z^H A V / sqrt(rho)
             T[i, :i] = arrow
             T[:i, i] = np.conj(arrow)
@@ -130,8 +143,8 @@ def eigcg(apply_A, b, nev, m, x0=None, tol=1e-10, max_iter=100000, record=False)
                                          "arrow": arrow, "Q": Q, "Z": Z, "j": j})
         elif i >= 1:                                       # off-diagonal of T
             T[i, i - 1] = T[i - 1, i] = -np.sqrt(beta) / alpha_1
-        i += 1                                             # append r / sqrt(rho) to V
-        V[:, i - 1] = r / np.sqrt(rho)
+        i += 1                                             # append z / sqrt(rho) to V
+        V[:, i - 1] = z / np.sqrt(rho)
         pt = _real_positive(_dot(p, t), "p^H A p")
         if pt <= 0.0:
             raise FloatingPointError("p^H A p <= 0: A is not positive definite")
