@@ -419,6 +419,7 @@ void ctx_init(Ctx& c, const eigcg_params& p, const void* gauge_dev, hipStream_t 
   }
   if (g.eo) {  // odd-site intermediate of the two-pass Schur operator, per batch column
     c.eo_tmp64 = c.dalloc((size_t)p.max_batch * c.cs * 16);
+    c.eo_cols64 = (size_t)p.max_batch;
     if (p.precision != EIGCG_FP64)
       c.eo_tmp32 = c.dalloc((size_t)p.max_batch * c.cs * elem_bytes(c.iprec));
   }
@@ -443,6 +444,7 @@ void ctx_release(Ctx& c) {
   if (c.stream) (void)hipStreamSynchronize(c.stream);
   ws_release(c, c.ws64);
   ws_release(c, c.ws32);
+  ws_release(c, c.wsg);
   c.dfree(c.U);
   c.dfree(c.bwork);
   c.dfree(c.bwork64);
@@ -591,9 +593,16 @@ static StencilLaunch stencil_base(Ctx& c, int prec) {
 }
 
 // out = op(in) (op = M or M^H) on ncols internal fields
+// The odd-even operator's two passes keep ncols odd-site intermediates.
+static void check_eo_tmp(const Ctx& c, int prec, int ncols) {
+  if (c.g.eo) check_fields(c, prec == kF64 ? c.eo_tmp64 : c.eo_tmp32, prec, ncols,
+                           "odd-even intermediate");
+}
+
 void stencil_store(Ctx& c, int prec, int op, int ncols, const void* in, void* out) {
   check_fields(c, in, prec, ncols, "stencil input");
   check_fields(c, out, prec, ncols, "stencil output");
+  check_eo_tmp(c, prec, ncols);
   StencilLaunch L = stencil_base(c, prec);
   L.op = op;
   L.epi = kEpiStore;
@@ -609,6 +618,7 @@ static void true_residual(Ctx& c, int prec, int ncols, uint32_t mask, const void
                           const void* b, void* r, void* tmp) {
   for (const void* f : {x, b, (const void*)r, (const void*)tmp})
     check_fields(c, f, prec, ncols, "true-residual field");
+  check_eo_tmp(c, prec, ncols);
   StencilLaunch L = stencil_base(c, prec);
   L.op = kOpM;
   L.epi = kEpiStore;
@@ -881,6 +891,7 @@ struct Run {
     if (K > w.K) throw ApiError{EIGCG_EINVAL, "internal: run wider than its workspace"};
     for (const void* f : {w.b, w.r, w.p, w.tmp}) check_fields(c, f, prec, K, "run field");
     check_fields(c, w.x, prec == kF16 ? kF32 : prec, K, "run iterate");
+    check_eo_tmp(c, prec, K);
     if (eig) check_fields(c, w.ring, prec, K * w.ring_len, "window ring");
   }
   ~Run() {
@@ -1820,6 +1831,68 @@ bool auto_continue(int done, int left, const double* iters, const double* secs, 
   return over_s < gain_s;
 }
 
+// FP64 init-CG guesses, eq. (2.1), of right-hand sides [first, first +
+// count) in groups of up to kMaxCols columns: x <- x + U H^-1 U^H (b - A x)
+// in the caller's x, so that one pass over the bank U serves a group instead
+// of one right-hand side.  Each column's arithmetic is that of its own
+// deflation (the stencil and both products treat columns independently).
+// Returns false, having changed nothing, when the group workspace cannot be
+// allocated.
+static bool batched_guess(Ctx& c, int first, int count, const void* b_aos, void* x_aos) {
+  Workspace& g = c.wsg;
+  if (g.K == 0) {
+    const size_t vb = c.cs * 16;
+    for (int k = kMaxCols; k >= 2 && g.K == 0; k /= 2) {
+      try {
+        g.b = c.dalloc(vb * k);
+        g.x = c.dalloc(vb * k);
+        g.r = c.dalloc(vb * k);
+        g.tmp = c.dalloc(vb * k);
+        g.K = k;
+        g.prec = kF64;
+      } catch (const ApiError&) {  // budget or device memory: try fewer columns
+        c.dfree(g.b); c.dfree(g.x); c.dfree(g.r); c.dfree(g.tmp);
+      }
+    }
+    if (g.K == 0) return false;
+  }
+  // the odd-even operator's intermediate holds max_batch columns; the
+  // group's residual pass needs g.K of them
+  if (c.g.eo && (size_t)g.K > c.eo_cols64) {
+    void* t = nullptr;
+    try {
+      t = c.dalloc((size_t)g.K * c.cs * 16);
+    } catch (const ApiError&) {
+      return false;
+    }
+    c.dfree(c.eo_tmp64);
+    c.eo_tmp64 = t;
+    c.eo_cols64 = (size_t)g.K;
+  }
+  std::vector<ColState> st(kMaxCols);
+  std::memset(st.data(), 0, sizeof(ColState) * kMaxCols);
+  for (auto& s : st) s.state = ColStopped;
+  for (int c0 = first; c0 < first + count; c0 += g.K) {
+    const int k = std::min(g.K, first + count - c0);
+    const uint32_t mask = k >= 32 ? 0xffffffffu : ((1u << k) - 1u);
+    const double2* bsrc = (const double2*)b_aos + (size_t)c0 * 12 * c.g.V;
+    double2* xdst = (double2*)x_aos + (size_t)c0 * 12 * c.g.V;
+    check_fields(c, g.b, kF64, k, "guess right-hand sides");
+    check_fields(c, g.x, kF64, k, "guess iterates");
+    // the residual pass leaves its norms in the column states: keep them idle
+    std::memcpy(c.h_st, st.data(), sizeof(ColState) * k);
+    c.check(hipMemcpyAsync(c.d_st, c.h_st, sizeof(ColState) * k, hipMemcpyHostToDevice, c.stream),
+            "states");
+    c.check(launch_spinor_to_soa(bsrc, g.b, kF64, &c.g, k, c.cs, c.stream), "to soa");
+    c.check(launch_spinor_to_soa(xdst, g.x, kF64, &c.g, k, c.cs, c.stream), "to soa");
+    true_residual(c, kF64, k, mask, g.x, g.b, g.r, g.tmp);
+    deflate_columns(c, kF64, k, mask, g.x, g.r);
+    c.check(launch_spinor_from_soa(g.x, xdst, kF64, &c.g, k, c.cs, c.stream), "from soa");
+    c.check(hipStreamSynchronize(c.stream), "sync");
+  }
+  return true;
+}
+
 int solve(Ctx& c, int nrhs, const void* b_aos, void* x_aos, double tol, int mode,
           eigcg_stats* stats) {
   const bool mixed = c.P.precision != EIGCG_FP64;
@@ -1839,6 +1912,7 @@ int solve(Ctx& c, int nrhs, const void* b_aos, void* x_aos, double tol, int mode
   c.last_ritz.clear();
   std::vector<double> auto_iters, auto_secs;  // eigCG groups of the automatic mode
   bool auto_eig = true;
+  int guessed_from = nrhs;  // right-hand sides from here on carry their deflated guess
   for (int c0 = 0; c0 < nrhs; c0 += w.K) {
     const int K = std::min(w.K, nrhs - c0);
     int gmode = mode;
@@ -1854,6 +1928,11 @@ int solve(Ctx& c, int nrhs, const void* b_aos, void* x_aos, double tol, int mode
     }
     const bool eig = gmode == EIGCG_MODE_EIGCG;
     const int scheme = scheme_for(c, gmode);
+    // FP64 init-CG over more than one batch: the bank is fixed from here on,
+    // so the guesses of all remaining right-hand sides are formed in groups
+    if (gmode == EIGCG_MODE_INITCG && scheme == kSchemeF64 && c.l > 0 && c0 < guessed_from &&
+        nrhs - c0 > w.K && batched_guess(c, c0, nrhs - c0, b_aos, x_aos))
+      guessed_from = c0;
     const double rtol = restart_tol_for(c, gmode, scheme);
     const double t0 = now_s();
     const double2* bsrc = (const double2*)b_aos + (size_t)c0 * 12 * c.g.V;
@@ -1884,7 +1963,7 @@ int solve(Ctx& c, int nrhs, const void* b_aos, void* x_aos, double tol, int mode
     }
     std::vector<double> res(K, 0.0);
     if (mask) {
-      D.start_columns(mask, bn2, tol, rtol, gmode != EIGCG_MODE_CG);
+      D.start_columns(mask, bn2, tol, rtol, gmode != EIGCG_MODE_CG && c0 < guessed_from);
       const int hard_cap = c.P.max_iter + 4 * D.seg + 8;
       while (!D.all_done(mask) && D.R.enq_iter <= hard_cap) D.step();
       D.finish();

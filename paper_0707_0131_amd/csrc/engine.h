@@ -59,7 +59,8 @@ struct Ctx {
   double tune_ms[2 * kStencilVariants] = {};  // FP64 then FP32, per variant
   void* u64 = nullptr;
   void* u32 = nullptr;
-  void* eo_tmp64 = nullptr;        // odd-even: odd-site intermediates (max_batch fields)
+  void* eo_tmp64 = nullptr;        // odd-even: odd-site intermediates (max_batch fields,
+  size_t eo_cols64 = 0;            // or more for the batched init-CG guesses: eo_cols64)
   void* eo_tmp32 = nullptr;
   // bank (Section 4): U columns, H = U^H A U and its Cholesky factor
   int bank_prec = kF64;
@@ -89,6 +90,7 @@ struct Ctx {
   double* d_norm = nullptr;        // kMaxCols norms
   double* h_norm = nullptr;
   Workspace ws64, ws32;
+  Workspace wsg;                   // FP64 init-CG guesses of several right-hand sides at once
   size_t bytes = 0;
   std::string err;
   int sticky = 0;

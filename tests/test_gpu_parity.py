@@ -358,6 +358,36 @@ def test_eigcg_same_trajectory_10_100(B):
         B.eigcg_destroy(ctx)
 
 
+def test_batched_initcg_guesses_match_single_solves(B, cfg0):
+    """FP64 init-CG over many right-hand sides forms the deflated guesses
+    (eq. (2.1)) in groups of up to 16 columns, one pass over the bank per
+    group; each solve is bitwise the one of a single-right-hand-side call
+    (18 right-hand sides: groups of 16 and 2; with the init-CG restart)."""
+    U, op, _ = cfg0
+    A, lam, X = _dense_lowest(op, 12)
+    rng = np.random.default_rng(23)
+    Xn, _ = np.linalg.qr(X + 1e-6 * (rng.standard_normal(X.shape) + 1j * rng.standard_normal(X.shape)))
+    bs = gaussian_rhs_block((4, 4, 4, 4), [2400 + i for i in range(18)])
+    x0 = 0.01 * gaussian_rhs_block((4, 4, 4, 4), [2500 + i for i in range(18)])
+    ctx, _ = make_ctx(U, -0.2, nev=6, m=20, max_bank=12, restart_tol=1e-6)
+    try:
+        assert B.eigcg_bank_load(ctx, dev(Xn.T.reshape((12, 4, 4, 4, 4, 4, 3)).copy())) == 12
+        xall = dev(x0)
+        rc, st_all = B.eigcg_solve(ctx, dev(bs), xall, 1e-10, B.EIGCG_MODE_INITCG)
+        assert rc == B.EIGCG_OK
+        got = host(xall)
+        for i in range(18):
+            x1 = dev(x0[i:i + 1].copy())
+            rc, st1 = B.eigcg_solve(ctx, dev(bs[i:i + 1]), x1, 1e-10, B.EIGCG_MODE_INITCG)
+            assert rc == B.EIGCG_OK
+            assert st1[0]["iters"] == st_all[i]["iters"]
+            assert st1[0]["first_leg_iters"] == st_all[i]["first_leg_iters"]
+            assert np.array_equal(host(x1)[0], got[i]), i
+            assert st_all[i]["true_rel_res"] <= 1e-10
+    finally:
+        B.eigcg_destroy(ctx)
+
+
 def test_incremental_eigcg_bank(B, cfg0):
     """Three Incremental eigCG steps: bank orthonormal, H = U^H A U, later
     right-hand sides converge faster, x matches the oracle's incremental run."""

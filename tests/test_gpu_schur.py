@@ -225,6 +225,40 @@ def test_schur_batched_columns_match_single(B):
     assert np.array_equal(out[0][0], out[1][0])
 
 
+def test_schur_batched_initcg_guesses_match_single_solves(B, cfg0_field):
+    """FP64 init-CG in a one-column odd-even context forms the deflated guesses
+    of 18 right-hand sides in groups of 16 and 2 (the odd-even operator's
+    intermediate then needs 16 odd-site fields, not one); each solve is
+    bitwise the one of a single-right-hand-side call, with the restart."""
+    U = cfg0_field
+    op = SchurOperator(U, -0.2)
+    ctx, _ = make_ctx(U, -0.2, nev=6, m=30, max_bank=12, max_iter=5000, schur=1,
+                      restart_tol=1e-6)
+    try:
+        for seed in (2100, 2101):  # a bank of two Incremental eigCG solves
+            b = gaussian_rhs((4, 4, 4, 4), seed)
+            rc, _, _, _ = _solve_full(B, ctx, b[None], 1e-10, B.EIGCG_MODE_EIGCG)
+            assert rc == B.EIGCG_OK
+        assert len(B.eigcg_bank_info(ctx)[0]) >= 6
+        nh = op.n // 12
+        rhs = np.stack([gaussian_half_rhs((4, 4, 4, 4), 2200 + i) for i in range(18)])
+        xall = dev(np.zeros_like(rhs))
+        rc, st_all = B.eigcg_solve(ctx, dev(rhs), xall, 1e-10, B.EIGCG_MODE_INITCG)
+        assert rc == B.EIGCG_OK
+        got = host(xall)
+        for i in range(18):
+            x1 = dev(np.zeros((1, nh, 4, 3), dtype=np.complex128))
+            rc, st1 = B.eigcg_solve(ctx, dev(rhs[i:i + 1].copy()), x1, 1e-10,
+                                    B.EIGCG_MODE_INITCG)
+            assert rc == B.EIGCG_OK
+            assert st1[0]["iters"] == st_all[i]["iters"]
+            assert np.array_equal(host(x1)[0], got[i]), i
+            r = rhs[i].reshape(-1) - op.A(got[i].reshape(-1))
+            assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(rhs[i])
+    finally:
+        B.eigcg_destroy(ctx)
+
+
 def test_schur_errors(B, cfg0_field):
     U = gauge_field((4, 4, 3, 4), 0.3, 1)
     lt, lz, ly, lx = U.shape[:4]
