@@ -53,6 +53,9 @@ STENCIL_SOURCES = ("paper_0707_0131_amd/csrc/stencil_impl.h",
                    "paper_0707_0131_amd/csrc/dslash_f64.hip", "paper_0707_0131_amd/csrc/wilson.h",
                    "paper_0707_0131_amd/csrc/common.h")
 TRAFFIC_SUMMARY = "profiles/k_wilson_pair_cgr_f64_16x16x16x32.md"
+TRAFFIC_SUMMARY_HBM = "profiles/k_wilson_pair_cgr_f64_24x24x24x48.md"
+HBM_CG_MASS = -0.58
+HBM_CG_ITERS = 240  # FP64 CG iterations sampled on the 24^3x48 lattice
 
 
 def run_step(B, torch, g, mass, bt, xt, n_eig=N_EIG):
@@ -76,6 +79,8 @@ def run_step(B, torch, g, mass, bt, xt, n_eig=N_EIG):
     bad = [s for s in st1 + st2 if s["status"] != 0 or s["true_rel_res"] > TOL]
     return {
         "mass": mass,
+        "phase1_restarts": sum(s["restarts"] for s in st1),
+        "phase2_restarts": sum(s["outer_steps"] for s in st2),
         "phase1_s": t1 - t0,
         "phase2_s": t2 - t1,
         "phase1_iters": [s["iters"] for s in st1],
@@ -344,11 +349,11 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(summary=TRAFFIC_SUMMARY):
     """HBM bytes per launch of the dominant kernel from the committed counter
     summary, or None when the stencil sources changed since it was taken."""
     import re
-    path = os.path.join(ROOT, TRAFFIC_SUMMARY)
+    path = os.path.join(ROOT, summary)
     if not os.path.exists(path):
         return None
     txt = open(path).read()
@@ -359,11 +364,32 @@ def measured_traffic():
     return float(t.group(1))
 
 
-def stencil_roofline(B, torch, dims, seed, reps, variant=0):
-    from synthetic import gauge_field
-    U = gauge_field(dims, EPS, seed)
-    g = torch.from_numpy(U).to("cuda:0")
-    del U
+def cg_pass_samples(B, torch, g, dims, mass, n_iter, variant=0):
+    """FP64 CG (one Gaussian right-hand side, seed 1000) for n_iter iterations
+    on the given links; the two stencil passes of every SAMPLE_EVERY-th
+    iteration are timed by their own dispatch start/stop events on the
+    solver's stream.  Returns the sampled mean durations and the variant."""
+    from synthetic import gaussian_rhs
+    b = torch.from_numpy(gaussian_rhs(dims, 1000)[None].copy()).to("cuda:0")
+    x = torch.zeros_like(b)
+    p = B.eigcg_default_params(dims=dims, mass=mass, max_bank=0, max_iter=n_iter, check_every=16,
+                               sample_every=SAMPLE_EVERY, stencil_variant=variant)
+    ctx = B.eigcg_create(p, g)
+    try:
+        B.eigcg_solve(ctx, b, x, TOL, B.EIGCG_MODE_CG)  # stops at n_iter (ENOTCONV)
+        s = B.eigcg_kernel_samples(ctx)["f64"]
+        s["stencil_variant"] = B.eigcg_layout_info(ctx)["variant64"]
+    finally:
+        B.eigcg_destroy(ctx)
+    return s
+
+
+def stencil_roofline(B, torch, dims, seed, reps, variant=0, g=None):
+    if g is None:
+        from synthetic import gauge_field
+        U = gauge_field(dims, EPS, seed)
+        g = torch.from_numpy(U).to("cuda:0")
+        del U
     p = B.eigcg_default_params(dims=dims, mass=-0.5, max_bank=0, stencil_variant=variant)
     ctx = B.eigcg_create(p, g)
     try:
@@ -674,28 +700,78 @@ def large_leg(B, torch, n_bank_rhs=6, n_rhs=12):
     return out
 
 
-def cpu_baseline(total_rhs, total_iters, budget_s=20.0):
-    """Oracle CG on the bench lattice for a bounded number of iterations."""
+def cpu_baseline(total_rhs, total_iters, total_restarts, total_deflations, budget_s=10.0):
+    """The NumPy oracle timed on this host: the 4^4 workload in full (plain CG
+    and eigCG(10, 40) to 1e-8), and bounded segments on the bench lattice: CG
+    iterations, one eigCG(10, 100) restart (the oracle's restart coefficients
+    and its V (QZ) product) and one init-CG deflation with 240 vectors (stand-in
+    vectors for timing only).  RHS/s for the bench workload is extrapolated
+    from the GPU run's counts of iterations, restarts and deflations."""
+    import platform
+
     import numpy as np
+    from oracle.cg import cg
     from oracle.dirac import WilsonOperator
+    from oracle.eigcg import eigcg, restart_coefficients
+    from oracle.initcg import galerkin_guess
     from synthetic import gauge_field, gaussian_rhs
+
+    blas_threads = None
+    try:
+        from threadpoolctl import threadpool_info
+        blas_threads = max((d.get("num_threads", 0) for d in threadpool_info()
+                            if d.get("user_api") == "blas"), default=None)
+    except Exception:  # threadpoolctl missing or no BLAS found
+        pass
+    out = {"kind": "oracle", "unit": "RHS/s", "blas_threads": blas_threads,
+           "host_cores_available": len(os.sched_getaffinity(0))}
+    # 4^4 (the small configuration) in full
+    U0 = gauge_field((4, 4, 4, 4), 0.3, 0)
+    op0 = WilsonOperator(U0, -0.2)
+    b0 = gaussian_rhs((4, 4, 4, 4), 1000).reshape(-1)
+    t0 = time.perf_counter()
+    _, i_cg = cg(op0.A, b0, tol=1e-10)
+    t1 = time.perf_counter()
+    _, _, _, i_eig = eigcg(op0.A, b0, 10, 40, tol=1e-8)
+    t2 = time.perf_counter()
+    out["small_4x4x4x4"] = {"cg_s": t1 - t0, "cg_iters": i_cg["iterations"],
+                            "eigcg_10_40_s": t2 - t1, "eigcg_iters": i_eig["iterations"]}
+    # bench lattice: CG iterations
     U = gauge_field(LATTICE, EPS, SEED)
     op = WilsonOperator(U, MASSES[0])
     b = gaussian_rhs(LATTICE, 1000).reshape(-1)
-    from oracle.cg import cg
+    n = b.shape[0]
     t0 = time.perf_counter()
-    n = 0
-    # one iteration first to size the sample to the budget
     cg(op.A, b, tol=0.0, max_iter=1, true_residual_restarts=0)
     one = time.perf_counter() - t0
     n_it = max(2, min(40, int(budget_s / max(one, 1e-3))))
     t0 = time.perf_counter()
     cg(op.A, b, tol=0.0, max_iter=n_it, true_residual_restarts=0)
-    dt = time.perf_counter() - t0
-    # cg() also applies A once for r0 and once for the final true residual
-    per_iter = dt / (n_it + 2)
-    rhs_per_s = total_rhs / (total_iters * per_iter)
-    import platform
+    per_iter = (time.perf_counter() - t0) / (n_it + 2)  # + r0 and the final true residual
+    # one eigCG(10, 100) restart: coefficients from a 100 x 100 window matrix
+    # (built from the 4^4 run's CG scalars: the small eigenproblems cost the
+    # same for any lattice), then V <- V (QZ) over 100 window columns of this
+    # lattice
+    al, be = np.array(i_cg["alpha"][:M]), np.array(i_cg["beta"][:M])
+    d = 1.0 / al
+    d[1:] += be[1:] / al[:-1]
+    off = -np.sqrt(be[1:]) / al[:-1]
+    Tm = (np.diag(d) + np.diag(off, 1) + np.diag(off, -1)).astype(np.complex128)
+    V = np.empty((n, M), dtype=np.complex128)
+    V[:] = (1.0 + 0.5j) / np.sqrt(n)
+    t0 = time.perf_counter()
+    QZ = restart_coefficients(Tm, NEV)[0]
+    V[:, :2 * NEV] = V[:, :M] @ QZ
+    t_restart = time.perf_counter() - t0
+    del V
+    # one init-CG deflation with 240 vectors (eq. (2.1)); the oracle's Galerkin guess
+    Ub = np.empty((n, NBANK), dtype=np.complex128)
+    Ub[:] = (1.0 - 0.25j) / np.sqrt(n)
+    H = np.eye(NBANK, dtype=np.complex128)
+    t0 = time.perf_counter()
+    galerkin_guess(op.A, Ub, H, b, x_tilde=np.zeros_like(b))
+    t_defl = time.perf_counter() - t0
+    del Ub
     cpu_model = platform.processor() or ""
     try:
         with open("/proc/cpuinfo") as f:
@@ -705,13 +781,23 @@ def cpu_baseline(total_rhs, total_iters, budget_s=20.0):
                     break
     except OSError:
         pass
-    return {"value": rhs_per_s, "unit": "RHS/s", "cores": 1, "kind": "oracle",
-            "host_cores_available": len(os.sched_getaffinity(0)), "cpu_model": cpu_model,
-            "seconds_per_cg_iteration": per_iter, "extrapolated": True,
-            "sample": f"{n_it} FP64 CG iterations of the NumPy oracle on the 16^3x32 lattice "
-                      f"({per_iter:.3f} s per iteration incl. A = M^H M; the NumPy stencil runs "
-                      f"on one core); RHS/s extrapolated with the GPU run's {total_iters} "
-                      f"iterations for {total_rhs} RHS"}
+    total_s = total_iters * per_iter + total_restarts * t_restart + total_deflations * t_defl
+    out.update({
+        "value": total_rhs / total_s,
+        "cores": blas_threads or 1,
+        "cpu_model": cpu_model,
+        "seconds_per_cg_iteration": per_iter,
+        "seconds_per_eigcg_restart": t_restart,
+        "seconds_per_deflation_240": t_defl,
+        "extrapolated": True,
+        "sample": f"4^4 CG + eigCG(10,40) in full; on 16^3x32: {n_it} FP64 CG iterations "
+                  f"({per_iter:.3f} s each, A = M^H M; the NumPy stencil runs on one core), one "
+                  f"eigCG(10,100) restart ({t_restart:.2f} s) and one 240-vector deflation "
+                  f"({t_defl:.2f} s, BLAS threads {blas_threads}); RHS/s extrapolated with the "
+                  f"GPU run's {total_iters} iterations, {total_restarts} restarts and "
+                  f"{total_deflations} deflations for {total_rhs} RHS (bank updates not included)",
+    })
+    return out
 
 
 def main():
@@ -764,8 +850,14 @@ def main():
     if args.roofline_only:
         dims, seed = (LATTICE, SEED) if args.roofline_only == "bench" else (HBM_LATTICE, HBM_SEED)
         log(f"stencil timings only ({dims})")
-        print(json.dumps({"stencil": stencil_roofline(B, torch, dims, seed, 100,
-                                                      args.stencil_variant)}))
+        U = gauge_field(dims, EPS, seed)
+        g = torch.from_numpy(U).to("cuda:0")
+        del U
+        out = {"stencil": stencil_roofline(B, torch, dims, seed, 100, args.stencil_variant, g=g)}
+        if args.roofline_only == "hbm":
+            out["cg_samples"] = cg_pass_samples(B, torch, g, dims, HBM_CG_MASS, HBM_CG_ITERS,
+                                                args.stencil_variant)
+        print(json.dumps(out))
         return
     log(f"generating {LATTICE} links and {args.n_eig + args.n_defl} right-hand sides")
     U = gauge_field(LATTICE, EPS, SEED)
@@ -844,14 +936,21 @@ def main():
     if not args.no_schur:
         odd_even = schur_leg(B, torch, g, bt, n_eig=n_eig, n_defl=n_defl)
 
-    roof_small = roof_hbm = None
+    roof_small = roof_hbm = hbm_samples = None
     if not args.no_roofline:
         log("stencil roofline (bench lattice, MALL-resident)")
-        roof_small = stencil_roofline(B, torch, LATTICE, SEED, 200)
+        roof_small = stencil_roofline(B, torch, LATTICE, SEED, 200, g=g)
         del g
         torch.cuda.empty_cache()
         log(f"stencil roofline ({HBM_LATTICE}, working set above the 256 MB MALL)")
-        roof_hbm = stencil_roofline(B, torch, HBM_LATTICE, HBM_SEED, 100)
+        U = gauge_field(HBM_LATTICE, EPS, HBM_SEED)
+        g_hbm = torch.from_numpy(U).to("cuda:0")
+        del U
+        roof_hbm = stencil_roofline(B, torch, HBM_LATTICE, HBM_SEED, 100, g=g_hbm)
+        log(f"FP64 CG passes sampled on {HBM_LATTICE} ({HBM_CG_ITERS} iterations)")
+        hbm_samples = cg_pass_samples(B, torch, g_hbm, HBM_LATTICE, HBM_CG_MASS, HBM_CG_ITERS)
+        del g_hbm
+        torch.cuda.empty_cache()
 
     serving = None
     if not args.no_serving:
@@ -864,10 +963,15 @@ def main():
         large = large_leg(B, torch)
 
     total_iters = sum(sum(s["phase1_iters"]) + sum(s["phase2_iters"]) for s in steps)
+    total_restarts = sum(s["phase1_restarts"] for s in steps)
+    # a deflation per init-CG solve and per init-CG restart, and one per eigCG solve
+    # after the first (the bank is empty before it)
+    total_deflations = sum(len(s["phase1_iters"]) - 1 + len(s["phase2_iters"])
+                           + s["phase2_restarts"] for s in steps)
     cpu = None
     if not args.no_cpu:
         log("CPU oracle baseline (bounded sample)")
-        cpu = cpu_baseline(total_rhs, total_iters)
+        cpu = cpu_baseline(total_rhs, total_iters, total_restarts, total_deflations)
 
     # dominant kernel: the second stencil pass of every CG iteration (M^H fused
     # with r -= alpha t and ||r||^2), timed live with events on the solver's
@@ -881,6 +985,46 @@ def main():
     pass1_bytes = V * site_bytes_stencil(True)  # p in, links, t out
     achieved = pass2_bytes / pass2_ms / 1e6 if n_s else None
     traffic = measured_traffic()
+    roof_mall = {
+        "bound": "hbm",
+        "mall_resident": True,
+        "kernel": "k_wilson_pair FP64 M^H pass fused with the CG residual update "
+                  "(960 algorithmic B/site, 16^3x32: links, p, t, r and x fit the 256 MB MALL)",
+        "achieved": achieved,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS if achieved else None,
+        "traffic": traffic,
+        "launch_ms": pass2_ms,
+        "stencil_variant": steps[0]["samples"]["stencil_variant"] if steps else None,
+        "sampled_launches": n_s,
+        "algorithmic_bytes_per_launch": pass2_bytes,
+        "timed_region": True,
+    }
+    roof = roof_mall
+    if hbm_samples and hbm_samples["n"] > 0:
+        V_h = HBM_LATTICE[0] * HBM_LATTICE[1] * HBM_LATTICE[2] * HBM_LATTICE[3]
+        b2 = V_h * (192 + 384 + 192 + 192)
+        a_h = b2 / hbm_samples["pass2_ms"] / 1e6
+        roof = {
+            "bound": "hbm",
+            "mall_resident": False,
+            "kernel": "k_wilson_pair FP64 M^H pass fused with the CG residual update "
+                      "(960 algorithmic B/site) on 24^3x48: working set (links 255 MB + "
+                      "4 fields of 127 MB) above the 256 MB MALL",
+            "achieved": a_h,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": a_h / HBM_PEAK_GBS,
+            "traffic": measured_traffic(TRAFFIC_SUMMARY_HBM),
+            "launch_ms": hbm_samples["pass2_ms"],
+            "stencil_variant": hbm_samples["stencil_variant"],
+            "sampled_launches": int(hbm_samples["n"]),
+            "algorithmic_bytes_per_launch": b2,
+            "timed_region": False,
+            "pass1_ms": hbm_samples["pass1_ms"],
+            "pass1_GBs": V_h * site_bytes_stencil(True) / hbm_samples["pass1_ms"] / 1e6,
+        }
     out = {
         "metric": "deflated RHS solves/sec at 1e-10 rel. residual vs plain CG; stencil HBM GB/s; p99",
         "value": value,
@@ -909,20 +1053,8 @@ def main():
                             "phase2_mean_iters": sum(s["phase2_iters"]) / len(s["phase2_iters"])}
                          for s in steps],
         "plain_cg": base,
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "k_wilson_pair FP64 M^H pass fused with the CG residual update "
-                      "(960 algorithmic B/site, 16^3x32)",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS if achieved else None,
-            "traffic": traffic,
-            "launch_ms": pass2_ms,
-            "stencil_variant": steps[0]["samples"]["stencil_variant"] if steps else None,
-            "sampled_launches": n_s,
-            "algorithmic_bytes_per_launch": pass2_bytes,
-        },
+        "roofline": roof,
+        "roofline_mall_resident": roof_mall,
         "timed_window_monotonic_ns": [win0, win1],
         "stencil_pass1": {"launch_ms": pass1_ms, "GBs": pass1_bytes / pass1_ms / 1e6 if n_s else None,
                           "algorithmic_bytes_per_launch": pass1_bytes},
