@@ -284,6 +284,66 @@ def bicgstab_leg(B, torch, g, bt, xt, mass=-0.58, n_eig=N_EIG, n_rhs=4, max_iter
     return out
 
 
+def spectral_leg(B, torch, g, bt, xt, mass=-0.58, n_rhs=4):
+    """Section 2.1's alternative to init-CG and Section 4's example: after one
+    eigCG(10, 100) solve (10 Ritz vectors) and after 24 Incremental eigCG
+    solves (240), the next right-hand sides are solved by plain CG, by init-CG
+    with the bank, and by CG with the same bank as a spectral preconditioner
+    (P^{-1} = I + U_R (sigma Theta^{-1} - I) U_R^H, two passes over the bank
+    per iteration; the bank is copied into a preconditioned context), FP64,
+    tol 1e-10."""
+    log(f"spectral preconditioning (mass {mass})")
+    out = {"mass": mass, "rhs": n_rhs, "banks": []}
+    b = bt[N_EIG:N_EIG + n_rhs]
+    x = xt[N_EIG:N_EIG + n_rhs]
+    shape = tuple(bt.shape[1:])
+
+    def timed(ctx, mode):
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = B.eigcg_solve(ctx, b, x, TOL, mode)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        return {"s_per_rhs": dt / n_rhs, "mean_iters": sum(s["iters"] for s in st) / n_rhs,
+                "max_true_rel_res": max(s["true_rel_res"] for s in st),
+                "failed": sum(1 for s in st if s["status"] != 0 or s["true_rel_res"] > TOL)}
+
+    kw = dict(dims=LATTICE, mass=mass, nev=NEV, m=M, max_bank=NBANK, max_iter=40000,
+              check_every=16, restart_tol=-1.0)
+    for n_bank_rhs in (1, N_EIG):
+        ctx = B.eigcg_create(B.eigcg_default_params(**kw), g)
+        spec = None
+        try:
+            xt[:n_bank_rhs].zero_()
+            B.eigcg_solve(ctx, bt[:n_bank_rhs], xt[:n_bank_rhs], TOL, B.EIGCG_MODE_EIGCG)
+            l = len(B.eigcg_bank_info(ctx)[0])
+            entry = {"bank_rhs": n_bank_rhs, "bank": l, "runs": []}
+            runs = [("init-CG (no restart)", ctx, B.EIGCG_MODE_INITCG)]
+            if n_bank_rhs == 1:
+                runs.insert(0, ("plain CG", ctx, B.EIGCG_MODE_CG))
+            vecs = torch.empty((l,) + shape, dtype=torch.complex128, device="cuda:0")
+            B.eigcg_bank_vectors(ctx, 0, l, vecs)
+            h = B.eigcg_bank_matrix(ctx, l)
+            spec = B.eigcg_create(B.eigcg_default_params(precond=1, **kw), g)
+            B.eigcg_bank_restore(spec, vecs, h)
+            del vecs
+            runs.append(("spectral preconditioned CG", spec, B.EIGCG_MODE_CG))
+            for name, c, mode in runs:
+                run = timed(c, mode)
+                run["solver"] = name
+                entry["runs"].append(run)
+                log(f"bank of {l}: {name}: {run['s_per_rhs']:.3f} s/RHS, "
+                    f"{run['mean_iters']:.0f} iterations, failed {run['failed']}")
+            out["banks"].append(entry)
+        finally:
+            B.eigcg_destroy(ctx)
+            if spec is not None:
+                B.eigcg_destroy(spec)
+        torch.cuda.empty_cache()
+    return out
+
+
 FP64_MFMA_PEAK_TF = 78.6
 FP32_MFMA_PEAK_TF = 157.3
 
@@ -614,6 +674,7 @@ def serving_leg(B, torch, n_bank_rhs, n_requests, seed=7):
     for k, pf in enumerate(per_field):
         pf["plain_fp64_cg_s"] = plain_s[[list(F["dims"]) for F in fields].index(pf["dims"])]
     plain_mix = float(sum(plain_s[f] for f in which))
+    growth = serving_from_empty_banks(B, torch, fields, which, reqs, plain_mix)
     out = {"requests": n_requests, "rhs_per_s": n_requests / (t1 - t0), "wall_s": t1 - t0,
            "plain_fp64_cg_same_mix_s": plain_mix, "speedup_vs_plain_fp64_cg": plain_mix / (t1 - t0),
            "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
@@ -621,9 +682,75 @@ def serving_leg(B, torch, n_bank_rhs, n_requests, seed=7):
            "loads": loads,
            "isolated_request_s": {str(list(fields[k]["dims"])): v for k, v in iso.items()},
            "failed": int(len(ok) - sum(ok)),
-           "max_true_rel_res": max(st["true_rel_res"] for _, st in res), "per_field": per_field}
+           "max_true_rel_res": max(st["true_rel_res"] for _, st in res), "per_field": per_field,
+           "from_empty_banks": growth}
     log(f"serving: {out['rhs_per_s']:.1f} RHS/s p50 {out['p50_s'] * 1e3:.0f} ms "
         f"p99 {out['p99_s'] * 1e3:.0f} ms failed {out['failed']}, "
+        f"{out['speedup_vs_plain_fp64_cg']:.2f}x plain FP64 CG on the same mix")
+    return out
+
+
+SERVE_GROW_EIG = 8  # eigCG requests per field that grow its bank inside the server
+
+
+def serving_from_empty_banks(B, torch, fields, which, reqs, plain_mix):
+    """The same request mix served from empty banks: FP64 contexts, each
+    field's first SERVE_GROW_EIG requests are eigCG requests (one step of
+    Incremental eigCG each, growing the bank inside the server), the rest
+    init-CG with the grown bank; all requests submitted at once, so RHS/s and
+    p50/p99 include the bank building."""
+    import numpy as np
+    ctxs = []
+    try:
+        for F in fields:
+            p = B.eigcg_default_params(dims=F["dims"], mass=SERVE_MASS, nev=NEV, m=M,
+                                       max_bank=NBANK, max_batch=12, max_iter=SERVE_MAX_ITER,
+                                       check_every=16, use_graphs=1)
+            ctxs.append(B.eigcg_create(p, F["g"]))
+        seen = [0] * len(fields)
+        modes = []
+        for f in which:
+            modes.append(B.EIGCG_MODE_EIGCG if seen[f] < SERVE_GROW_EIG else B.EIGCG_MODE_INITCG)
+            seen[f] += 1
+        for _, _, x in reqs:
+            x.zero_()
+        torch.cuda.synchronize()
+        srv = B.eigcg_server_create(0)
+        try:
+            fids = [B.eigcg_server_add(srv, c) for c in ctxs]
+            t0 = t_log = time.perf_counter()
+            tickets = [B.eigcg_submit_mode(srv, fids[f], b, x, TOL, modes[i])
+                       for i, (f, b, x) in enumerate(reqs)]
+            while True:
+                ndone = sum(1 for t in tickets if B.eigcg_poll(srv, t)[0] != B.EIGCG_EBUSY)
+                if ndone == len(tickets):
+                    break
+                if time.perf_counter() - t_log > 5.0:
+                    t_log = time.perf_counter()
+                    log(f"serving from empty banks: {ndone} of {len(tickets)} done")
+                time.sleep(2e-3)
+            wall = time.perf_counter() - t0
+            res = [B.eigcg_poll(srv, t) for t in tickets]
+        finally:
+            B.eigcg_server_destroy(srv)
+        banks = [len(B.eigcg_bank_info(c)[0]) for c in ctxs]
+    finally:
+        for c in ctxs:
+            B.eigcg_destroy(c)
+    lat = np.array([st["seconds"] for _, st in res])
+    eig = np.array([m == B.EIGCG_MODE_EIGCG for m in modes])
+    out = {"requests": len(reqs), "eigcg_requests_per_field": SERVE_GROW_EIG, "precision": "fp64",
+           "rhs_per_s": len(reqs) / wall, "wall_s": wall, "banks": banks,
+           "speedup_vs_plain_fp64_cg": plain_mix / wall,
+           "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+           "eigcg_p50_s": float(np.percentile(lat[eig], 50)),
+           "initcg_p50_s": float(np.percentile(lat[~eig], 50)),
+           "mean_iters_eigcg": float(np.mean([res[i][1]["iters"] for i in np.nonzero(eig)[0]])),
+           "mean_iters_initcg": float(np.mean([res[i][1]["iters"] for i in np.nonzero(~eig)[0]])),
+           "failed": int(sum(1 for rc, st in res if rc != 0 or st["true_rel_res"] > TOL)),
+           "max_true_rel_res": max(st["true_rel_res"] for _, st in res)}
+    log(f"serving from empty banks: {out['rhs_per_s']:.1f} RHS/s (banks {banks}) p50 "
+        f"{out['p50_s'] * 1e3:.0f} ms p99 {out['p99_s'] * 1e3:.0f} ms failed {out['failed']}, "
         f"{out['speedup_vs_plain_fp64_cg']:.2f}x plain FP64 CG on the same mix")
     return out
 
@@ -821,6 +948,12 @@ def main():
     ap.add_argument("--bicgstab-short", action="store_true",
                     help="with --bicgstab-only: one right-hand side, a bank from 4 eigCG "
                          "solves, BiCGSTAB on M only (short runs for counter collection)")
+    ap.add_argument("--no-spectral", action="store_true",
+                    help="skip the spectral preconditioning leg")
+    ap.add_argument("--spectral-only", action="store_true",
+                    help="only the spectral preconditioning leg (no timed steps)")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="only the serving leg (no timed steps)")
     ap.add_argument("--serve-bank-rhs", type=int, default=N_EIG)
     ap.add_argument("--serve-requests", type=int, default=120)
     ap.add_argument("--stencil-variant", type=int, default=0,
@@ -871,6 +1004,17 @@ def main():
         bt[i].copy_(torch.from_numpy(gaussian_rhs(LATTICE, 1000 + i)))
     xt = torch.zeros_like(bt)
     torch.cuda.synchronize()
+
+    if args.serving_only:
+        del bt, xt, g
+        torch.cuda.empty_cache()
+        print(json.dumps({"serving": serving_leg(B, torch, args.serve_bank_rhs,
+                                                 args.serve_requests)}))
+        return
+
+    if args.spectral_only:
+        print(json.dumps({"spectral": spectral_leg(B, torch, g, bt, xt)}))
+        return
 
     if args.bicgstab_only:
         kw = dict(n_eig=4, n_rhs=1, solvers=BICG_SOLVERS[:2]) if args.bicgstab_short else {}
@@ -927,6 +1071,10 @@ def main():
         fixed = [s for s in steps if s["mass"] == auto["mass"]]
         if fixed:
             auto["fixed_plan_rhs_per_s"] = nrhs / (fixed[0]["phase1_s"] + fixed[0]["phase2_s"])
+
+    spectral = None
+    if not args.no_spectral:
+        spectral = spectral_leg(B, torch, g, bt, xt)
 
     bicg = None
     if not args.no_bicgstab:
@@ -1062,6 +1210,7 @@ def main():
         "odd_even": odd_even,
         "auto_switch": auto,
         "bicgstab": bicg,
+        "spectral_preconditioning": spectral,
         "serving": serving,
         "large_lattice": large,
         "stencil_bench_lattice": roof_small,

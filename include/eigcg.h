@@ -81,6 +81,7 @@ enum {
 enum { EIGCG_FP64 = 0, EIGCG_MIXED_FP32 = 1, EIGCG_MIXED_HALF = 2 };
 enum { EIGCG_MODE_CG = 0, EIGCG_MODE_EIGCG = 1, EIGCG_MODE_INITCG = 2, EIGCG_MODE_AUTO = 3 };
 enum { EIGCG_OP_M = 0, EIGCG_OP_MDAG = 1, EIGCG_OP_A = 2, EIGCG_OP_INNER = 3 };
+enum { EIGCG_PRECOND_NONE = 0, EIGCG_PRECOND_SPECTRAL = 1 };
 
 typedef struct {
   int32_t dims[4];        /* Lx, Ly, Lz, Lt; each >= 2, periodic */
@@ -110,7 +111,7 @@ typedef struct {
                              ignored while sample_every > 0 */
   int32_t stencil_variant;/* 0: pick the fastest stencil kernel by timing at create
                              (cached per lattice shape and precision in the process);
-                             1..10: force a variant (see eigcg_layout_info) */
+                             1..13: force a variant (see eigcg_layout_info) */
   int32_t plane_pad;      /* extra sites (in units of 64) after each SoA plane so
                              that planes do not start on the same memory channel:
                              0 = library default, < 0 = none */
@@ -119,6 +120,20 @@ typedef struct {
                              (read with eigcg_kernel_samples); 0 = off */
   int32_t schur;          /* 1: odd-even preconditioned operator on the even
                              sites (every extent even); 0: A = M^H M */
+  int32_t precond;        /* EIGCG_PRECOND_NONE, or EIGCG_PRECOND_SPECTRAL: CG and
+                             eigCG iterations use z = P^{-1} r with the bank as a
+                             spectral preconditioner (Section 2.1's alternative to
+                             init-CG; Section 4's example), P^{-1} = I + U_R
+                             (sigma Theta^{-1} - I) U_R^H with U_R, Theta the bank's
+                             Ritz vectors and values (U_R^H A U_R = Theta), rebuilt
+                             when the bank changes; eigCG then runs in the
+                             preconditioned form of Section 3 (window V = P^{-1} R,
+                             Ritz pairs of the pencil A y = lambda P y).  Costs two
+                             passes over U per iteration.  FP64 contexts only
+                             (EINVAL otherwise); an empty bank means P = I */
+  double precond_sigma;   /* sigma of the spectral preconditioner (the value the
+                             Ritz directions are mapped to); <= 0: the largest
+                             Ritz value seen, else (8 + |m_q|)^2 */
 } eigcg_params;
 
 typedef struct {
@@ -339,14 +354,21 @@ int eigcg_kernel_samples(eigcg_ctx* ctx, int32_t reset, double* out);
 const char* eigcg_last_error(const eigcg_ctx* ctx);
 
 /* ---- serving: continuous batching over several contexts --------------------
- * A server admits solve requests for any registered context (gauge field) as
- * long as the per-request working set fits the HBM budget, runs all admitted
- * requests of one context as columns of a shared batched iteration (new
- * requests join and finished ones leave between iteration segments), deflates
- * each request with the context's resident bank (init-CG, eq. (2.1)) and
- * reports completion per ticket.  Requests that arrive while others run are
- * admitted as slots free up; the server thread owns the device work.
- * Results do not depend on which other requests share a batch. */
+ * A server admits solve requests for any registered context (gauge field).
+ * Every field has a worker thread and a HIP stream of its own, so the work of
+ * different fields overlaps on the device.  A field's requests are served in
+ * submission order: init-CG requests run as columns of a shared batched
+ * iteration (new requests join and finished ones leave between iteration
+ * segments) deflated with the field's resident bank (eq. (2.1)); eigCG
+ * requests (eigcg_submit_mode with EIGCG_MODE_EIGCG: one step of Incremental
+ * eigCG, Section 4) wait for the running slots to finish, then grow the
+ * field's bank by their Ritz vectors, so later requests are deflated with
+ * the grown bank.  Admission is subject to the HBM budget: each context's
+ * resident memory is charged once, every active init-CG request its working
+ * set, an eigCG request the field's eigCG window while it is not allocated
+ * (it waits for other fields' requests to finish, and fails with
+ * EIGCG_ENOMEM when the window cannot fit even then).  Results do not depend
+ * on which other requests share a batch or run at the same time. */
 typedef struct eigcg_server eigcg_server;
 
 int eigcg_server_create(uint64_t hbm_budget, eigcg_server** out);
@@ -357,6 +379,10 @@ int eigcg_server_add(eigcg_server* srv, eigcg_ctx* ctx, int32_t* field_id);
  * x_dev (one field each, boundary layout) must stay valid until done. */
 int eigcg_submit(eigcg_server* srv, int32_t field_id, const void* b_dev, void* x_dev, double tol,
                  uint64_t* ticket);
+/* As eigcg_submit with mode EIGCG_MODE_INITCG or EIGCG_MODE_EIGCG (the latter
+ * grows the field's bank; EINVAL in a 16-bit context). */
+int eigcg_submit_mode(eigcg_server* srv, int32_t field_id, const void* b_dev, void* x_dev,
+                      double tol, int32_t mode, uint64_t* ticket);
 /* EIGCG_EBUSY while running; otherwise the solve status with *st filled
  * (st->seconds = submit-to-completion latency). */
 int eigcg_poll(eigcg_server* srv, uint64_t ticket, eigcg_stats* st);

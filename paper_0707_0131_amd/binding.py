@@ -24,6 +24,7 @@ EIGCG_EBREAKDOWN, EIGCG_EHIP, EIGCG_EBUSY = -4, -5, -6
 EIGCG_FP64, EIGCG_MIXED_FP32, EIGCG_MIXED_HALF = 0, 1, 2
 EIGCG_MODE_CG, EIGCG_MODE_EIGCG, EIGCG_MODE_INITCG, EIGCG_MODE_AUTO = 0, 1, 2, 3
 EIGCG_OP_M, EIGCG_OP_MDAG, EIGCG_OP_A, EIGCG_OP_INNER = 0, 1, 2, 3
+EIGCG_PRECOND_NONE, EIGCG_PRECOND_SPECTRAL = 0, 1
 EIGCG_BICG_GAMMA5, EIGCG_BICG_DEFLATE, EIGCG_BICG_GUESS_ONLY = 1, 2, 4
 
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "ENOTCONV", -4: "EBREAKDOWN",
@@ -50,6 +51,8 @@ class Params(ctypes.Structure):
         ("plane_pad", ctypes.c_int32),
         ("sample_every", ctypes.c_int32),
         ("schur", ctypes.c_int32),
+        ("precond", ctypes.c_int32),
+        ("precond_sigma", ctypes.c_double),
     ]
 
 
@@ -122,6 +125,8 @@ SIGNATURES = {
     "eigcg_server_create": (_I32, [ctypes.c_uint64, ctypes.POINTER(_VP)]),
     "eigcg_server_add": (_I32, [_VP, _VP, ctypes.POINTER(_I32)]),
     "eigcg_submit": (_I32, [_VP, _I32, _VP, _VP, ctypes.c_double, ctypes.POINTER(ctypes.c_uint64)]),
+    "eigcg_submit_mode": (_I32, [_VP, _I32, _VP, _VP, ctypes.c_double, _I32,
+                                 ctypes.POINTER(ctypes.c_uint64)]),
     "eigcg_poll": (_I32, [_VP, ctypes.c_uint64, ctypes.POINTER(Stats)]),
     "eigcg_server_drain": (_I32, [_VP]),
     "eigcg_server_destroy": (_I32, [_VP]),
@@ -501,6 +506,22 @@ def eigcg_submit(srv, field_id, b, x, tol):
     rc = LIB.eigcg_submit(srv, int(field_id), _ptr(b), _ptr(x), float(tol), ctypes.byref(t))
     if rc != EIGCG_OK:
         raise EigcgError(rc, "eigcg_submit failed")
+    return t.value
+
+
+def eigcg_submit_mode(srv, field_id, b, x, tol, mode=EIGCG_MODE_INITCG):
+    """Enqueue an init-CG (EIGCG_MODE_INITCG) or bank-growing eigCG
+    (EIGCG_MODE_EIGCG) request; returns its ticket."""
+    geom = _SERVERS.get(_key(srv), {}).get(int(field_id))
+    if geom is None:
+        raise ValueError(f"field {field_id} is not registered with this server")
+    _check_fields(b, "b", geom[0], 1)
+    _check_fields(x, "x", geom[0], 1)
+    t = ctypes.c_uint64()
+    rc = LIB.eigcg_submit_mode(srv, int(field_id), _ptr(b), _ptr(x), float(tol), int(mode),
+                               ctypes.byref(t))
+    if rc != EIGCG_OK:
+        raise EigcgError(rc, "eigcg_submit_mode failed")
     return t.value
 
 

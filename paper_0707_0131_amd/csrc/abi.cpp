@@ -74,6 +74,12 @@ int validate(const eigcg_params* p, std::string& why) {
     return EIGCG_EINVAL;
   }
   if (p->precision == EIGCG_MIXED_FP32 && p->reliable_every < 1) { why = "reliable_every must be >= 1"; return EIGCG_EINVAL; }
+  if (p->precond != EIGCG_PRECOND_NONE && p->precond != EIGCG_PRECOND_SPECTRAL) { why = "bad precond"; return EIGCG_EINVAL; }
+  if (p->precond == EIGCG_PRECOND_SPECTRAL && p->precision != EIGCG_FP64) {
+    why = "the spectral preconditioner runs in FP64 contexts only";
+    return EIGCG_EINVAL;
+  }
+  if (!std::isfinite(p->precond_sigma)) { why = "precond_sigma not finite"; return EIGCG_EINVAL; }
   return EIGCG_OK;
 }
 
@@ -301,6 +307,7 @@ int eigcg_bank_reset(eigcg_ctx* ctx) {
   if (!ctx) return EIGCG_EINVAL;
   ctx->c.l = 0;
   ctx->c.chol_ok = false;
+  ctx->c.spec_ok = false;
   return EIGCG_OK;
 }
 

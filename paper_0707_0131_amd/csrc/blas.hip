@@ -17,109 +17,41 @@ inline int grid_for(size_t n) {
   return (int)g;
 }
 
-// The CG scalars of one iteration (Figure 3.1) from the state before it and
-// the two passes' sums: p^H A p (alpha, or breakdown) and r^H r of the new
-// residual (beta, stop tests, the eigCG t-save schedule).  Returns the
-// iteration completed (0: none, no history entry).
-__device__ __forceinline__ int finalize_state(ColState& S, double pap, double rho_new) {
-  if (S.state == ColRun) {
-    S.pap = pap;
-    if (!(pap > 0.0 && pap < INFINITY)) {
-      S.alpha = 0.0;
-      S.state = ColStopPending;
-      S.reason = ReasonBreakdown;
-      return 0;
-    }
-    S.alpha = S.rho / pap;
-    const int j = S.iter + 1;
-    const double beta = rho_new / S.rho;
-    S.iter = j;
-    if (j == S.save_t1 && S.tperiod > 0) {
-      S.save_t0 += S.tperiod;
-      S.save_t1 += S.tperiod;
-    }
-    S.rho_prev = S.rho;
-    S.rho = rho_new;
-    S.beta = beta;
-    if (!(rho_new < INFINITY)) {
-      S.state = ColStopPending;
-      S.reason = ReasonBreakdown;
-    } else if (rho_new <= S.stop2) {
-      S.state = ColStopPending;
-      S.reason = ReasonConverged;
-    } else if (rho_new <= S.restart2) {
-      S.state = ColStopPending;
-      S.reason = ReasonRestart;
-    } else if (j >= S.max_iter) {
-      S.state = ColStopPending;
-      S.reason = ReasonMaxIter;
-    }
-    return j;
-  }
-  if (S.state == ColStopPending) S.state = ColStopped;
-  return 0;
-}
-
-// End of a CG iteration (Figure 3.1) and the start of the next: the scalars
-// (finalize_state, every workgroup alike from the partials summed in one
-// fixed order), then x += alpha p; p = r + beta p; window slot (iter+1) % ring
-// = r / sqrt(rho).  The last workgroup of the column stores the new state.
+// End of a CG iteration (Figure 3.1) and the start of the next: x += alpha p;
+// p = r + beta p; window slot (iter+1) % ring = r / sqrt(rho).
 template <typename VS, typename XS>
 __global__ __launch_bounds__(kBlock) void k_cg_update(UpdateLaunch a, Geom g) {
   using R = typename Storage<VS>::real;
-  __shared__ double lds4[kBlock / 64];
   const int col = blockIdx.y;
   if (!((a.mask >> col) & 1u)) return;
-  ColState S = a.st[col];
-  if (S.state == ColStopped) return;  // (uniform over the column's workgroups)
-  const double pap = reduce_partials(a.part_a + (size_t)col * a.nb, a.nb, lds4);
-  const double rho_new = reduce_partials(a.part_b + (size_t)col * a.nb, a.nb, lds4);
-  const int j = finalize_state(S, pap, rho_new);
-  if (S.state != ColStopped) {
-    const bool run = S.state == ColRun;
-    const R alpha = (R)S.alpha, beta = (R)S.beta;
-    const R inv = run ? (R)(1.0 / sqrt(S.rho)) : R(0);
-    XS* x = reinterpret_cast<XS*>(a.x) + (size_t)col * a.x_cs;
-    VS* p = reinterpret_cast<VS*>(a.p) + (size_t)col * a.p_cs;
-    const VS* r = reinterpret_cast<const VS*>(a.r) + (size_t)col * a.r_cs;
-    VS* v = nullptr;
-    if (run && a.ring) {
-      const int slot = (S.iter + 1) % a.ring_len;
-      v = reinterpret_cast<VS*>(a.ring) + (size_t)col * a.ring_col_cs + (size_t)slot * a.ring_cs;
-    }
-    const size_t vs = (size_t)g.vs;
-    for (uint32_t s = blockIdx.x * kBlock + threadIdx.x; s < (uint32_t)g.V;
-         s += gridDim.x * kBlock) {
-#pragma unroll
-      for (int e = 0; e < 12; ++e) {
-        const size_t i = (size_t)e * vs + s;
-        cpx<R> pv = Storage<VS>::ld(p, i);
-        cpx<R> xv = Storage<XS>::ld(x, i);
-        xv.re += alpha * pv.re;
-        xv.im += alpha * pv.im;
-        Storage<XS>::st(x, i, xv);
-        if (run) {
-          cpx<R> rv = Storage<VS>::ld(r, i);
-          Storage<VS>::st(p, i, {rv.re + beta * pv.re, rv.im + beta * pv.im});
-          if (v) Storage<VS>::st(v, i, {rv.re * inv, rv.im * inv});
-        }
-      }
-    }
+  const ColState S = a.st[col];
+  if (S.state == ColStopped) return;
+  const bool run = S.state == ColRun;
+  const R alpha = (R)S.alpha, beta = (R)S.beta;
+  const R inv = run ? (R)(1.0 / sqrt(S.rho)) : R(0);
+  XS* x = reinterpret_cast<XS*>(a.x) + (size_t)col * a.x_cs;
+  VS* p = reinterpret_cast<VS*>(a.p) + (size_t)col * a.p_cs;
+  const VS* r = reinterpret_cast<const VS*>(a.r) + (size_t)col * a.r_cs;
+  VS* v = nullptr;
+  if (run && a.ring) {
+    const int slot = (S.iter + 1) % a.ring_len;
+    v = reinterpret_cast<VS*>(a.ring) + (size_t)col * a.ring_col_cs + (size_t)slot * a.ring_cs;
   }
-  // every workgroup read the old state above; the last one to arrive stores
-  // the new state (no workgroup of this launch reads it afterwards)
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned int before = atomicAdd(a.counter + col, 1u);
-    if (before == gridDim.x - 1) {
-      a.st[col] = S;
-      if (j > 0 && a.hist) {
-        double* h = a.hist + (size_t)col * a.hist_stride + (size_t)3 * (j - 1);
-        h[0] = S.alpha;
-        h[1] = S.beta;
-        h[2] = S.rho;
+  const size_t vs = (size_t)g.vs;
+  for (uint32_t s = blockIdx.x * kBlock + threadIdx.x; s < (uint32_t)g.V; s += gridDim.x * kBlock) {
+#pragma unroll
+    for (int e = 0; e < 12; ++e) {
+      const size_t i = (size_t)e * vs + s;
+      cpx<R> pv = Storage<VS>::ld(p, i);
+      cpx<R> xv = Storage<XS>::ld(x, i);
+      xv.re += alpha * pv.re;
+      xv.im += alpha * pv.im;
+      Storage<XS>::st(x, i, xv);
+      if (run) {
+        cpx<R> rv = Storage<VS>::ld(r, i);
+        Storage<VS>::st(p, i, {rv.re + beta * pv.re, rv.im + beta * pv.im});
+        if (v) Storage<VS>::st(v, i, {rv.re * inv, rv.im * inv});
       }
-      a.counter[col] = 0u;
     }
   }
 }
@@ -547,6 +479,50 @@ hipError_t launch_set_state(ColState* st, int ncols, uint32_t mask, int state, i
                             int clear_restart, hipStream_t s) {
   hipLaunchKernelGGL(k_set_state, dim3(1), dim3(64), 0, s, st, ncols, mask, state, reason,
                      clear_restart);
+  return hipGetLastError();
+}
+
+namespace {
+
+// Spectral preconditioner, middle step: S = D G and s = G^H D G per column
+// (G = U_R^H r, l x ncols complex column-major; D = sigma / theta - 1).  One
+// workgroup; column j's sum runs over i in a fixed order in thread j.
+__global__ __launch_bounds__(kBlock) void k_spec_scale(const double2* G, const double* D, int l,
+                                                       int ncols, double2* S, double* s_out) {
+  for (int e = threadIdx.x; e < l * ncols; e += kBlock) {
+    const double2 g = G[e];
+    const double d = D[e % l];
+    S[e] = make_double2(d * g.x, d * g.y);
+  }
+  if (threadIdx.x < ncols) {
+    const int j = threadIdx.x;
+    double acc = 0.0;
+    for (int i = 0; i < l; ++i) {
+      const double2 g = G[(size_t)j * l + i];
+      acc += D[i] * (g.x * g.x + g.y * g.y);
+    }
+    s_out[j] = acc;
+  }
+}
+
+__global__ void k_spec_rho(ColState* st, int ncols, uint32_t mask, const double* s_in) {
+  const int c = threadIdx.x;
+  if (c >= ncols || !((mask >> c) & 1u)) return;
+  if (st[c].state == ColRun) st[c].rho += s_in[c];
+}
+
+}  // namespace
+
+hipError_t launch_spec_scale(const double2* G, const double* D, int l, int ncols, double2* S,
+                             double* s_out, hipStream_t s) {
+  if (l <= 0 || ncols <= 0 || ncols > kBlock) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_spec_scale, dim3(1), dim3(kBlock), 0, s, G, D, l, ncols, S, s_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_spec_rho(ColState* st, int ncols, uint32_t mask, const double* s_in,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_spec_rho, dim3(1), dim3(64), 0, s, st, ncols, mask, s_in);
   return hipGetLastError();
 }
 

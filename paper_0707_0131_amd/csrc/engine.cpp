@@ -133,7 +133,7 @@ static size_t elem_bytes(int prec) { return prec == kF64 ? 16 : (prec == kF32 ? 
 // context
 // ---------------------------------------------------------------------------
 
-static void ws_ensure(Ctx& c, Workspace& w, int prec, bool eig);
+static void ws_ensure(Ctx& c, Workspace& w, int prec, bool eig, int keig = 0);
 static StencilLaunch stencil_base(Ctx& c, int prec);
 
 // Stencil autotuner: times every kernel variant (the search space: site
@@ -386,7 +386,6 @@ void ctx_init(Ctx& c, const eigcg_params& p, const void* gauge_dev, hipStream_t 
           "hipHostMalloc");
   c.d_partial = (double*)c.dalloc(sizeof(double) * (size_t)(kMaxCols + 2) * kMaxGrid * 2);
   c.d_counter = (unsigned int*)c.dalloc(256);
-  c.d_ucount = (unsigned int*)c.dalloc(sizeof(unsigned int) * kMaxCols);
   c.gpart_elems = (size_t)1 << 21;  // 32 MiB of double2 chunk partials
   c.d_gpart = (double2*)c.dalloc(sizeof(double2) * c.gpart_elems);
   c.small_elems = kSmallElems;
@@ -435,7 +434,7 @@ void ctx_init(Ctx& c, const eigcg_params& p, const void* gauge_dev, hipStream_t 
 
 static void ws_release(Ctx& c, Workspace& w) {
   c.dfree(w.b); c.dfree(w.x); c.dfree(w.r); c.dfree(w.p); c.dfree(w.tmp);
-  c.dfree(w.ring); c.dfree(w.vr); c.dfree(w.tbuf); c.dfree(w.w); c.dfree(w.ritz);
+  c.dfree(w.ring); c.dfree(w.vr); c.dfree(w.tbuf); c.dfree(w.w); c.dfree(w.ritz); c.dfree(w.z);
   w.K = 0;
   w.eig = false;
 }
@@ -446,6 +445,14 @@ void ctx_release(Ctx& c) {
   ws_release(c, c.ws32);
   ws_release(c, c.wsg);
   c.dfree(c.U);
+  c.dfree(c.UR);
+  {
+    void* v2;
+    v2 = c.d_specD; c.dfree(v2);
+    v2 = c.d_specG; c.dfree(v2);
+    v2 = c.d_specS; c.dfree(v2);
+    v2 = c.d_specs; c.dfree(v2);
+  }
   c.dfree(c.bwork);
   c.dfree(c.bwork64);
   c.dfree(c.u64);
@@ -458,7 +465,6 @@ void ctx_release(Ctx& c) {
   v = c.d_hist; c.dfree(v);
   v = c.d_partial; c.dfree(v);
   v = c.d_counter; c.dfree(v);
-  v = c.d_ucount; c.dfree(v);
   v = c.d_gpart; c.dfree(v);
   v = c.d_small; c.dfree(v);
   v = c.d_norm; c.dfree(v);
@@ -532,8 +538,32 @@ static int seg_len_eig(const eigcg_params& P) {
 static int restart_group(const eigcg_params& P) { return std::max(1, std::min(24, 4096 / P.m)); }
 static bool restart_pingpong(const eigcg_params& P) { return 2 * P.nev > restart_group(P); }
 
-static void ws_ensure(Ctx& c, Workspace& w, int prec, bool eig) {
+// Device bytes of the eigCG window arrays (residual ring, restarted block,
+// saved A p, arrow vector, Ritz vectors) for keig columns in precision prec.
+static size_t window_bytes(const Ctx& c, int prec, int keig) {
+  const size_t vb = c.cs * elem_bytes(prec);
+  const size_t ring_len = (size_t)(c.P.m + seg_len_eig(c.P) + 2);
+  const size_t per = ring_len + (size_t)2 * c.P.nev * (restart_pingpong(c.P) ? 2 : 1) + 2 + 1 +
+                     (size_t)c.P.nev;
+  return vb * per * (size_t)keig;
+}
+
+size_t eig_window_bytes(const Ctx& c, int keig) {
+  if (c.P.precision == EIGCG_MIXED_HALF) return 0;  // no eigCG iterations
+  size_t b = 0;
+  if (c.P.precision == EIGCG_FP64) {
+    if (!c.ws64.eig || c.ws64.Keig < keig) b += window_bytes(c, kF64, keig);
+  } else if (!c.ws32.eig || c.ws32.Keig < keig) {
+    b += window_bytes(c, c.iprec, keig);
+  }
+  return b;
+}
+
+// Work vectors of max_batch columns; with eig, the eigCG window arrays for
+// keig columns (default max_batch), reallocated when a wider run needs them.
+static void ws_ensure(Ctx& c, Workspace& w, int prec, bool eig, int keig) {
   const int K = c.P.max_batch;
+  if (keig <= 0 || keig > K) keig = K;
   const size_t vb = c.cs * elem_bytes(prec);
   if (w.K == 0) {
     w.prec = prec;
@@ -544,15 +574,21 @@ static void ws_ensure(Ctx& c, Workspace& w, int prec, bool eig) {
     w.r = c.dalloc(vb * K);
     w.p = c.dalloc(vb * K);
     w.tmp = c.dalloc(vb * K);
+    if (c.P.precond == EIGCG_PRECOND_SPECTRAL && prec == kF64) w.z = c.dalloc(vb * K);
+  }
+  if (eig && w.eig && w.Keig < keig) {  // a wider eigCG run than the window holds
+    c.dfree(w.ring); c.dfree(w.vr); c.dfree(w.tbuf); c.dfree(w.w); c.dfree(w.ritz);
+    w.eig = false;
   }
   if (eig && !w.eig) {
     w.nev = c.P.nev;
+    w.Keig = keig;
     w.ring_len = c.P.m + seg_len_eig(c.P) + 2;
-    w.ring = c.dalloc(vb * (size_t)K * w.ring_len);
-    w.vr = c.dalloc(vb * (size_t)K * 2 * c.P.nev * (restart_pingpong(c.P) ? 2 : 1));
-    w.tbuf = c.dalloc(vb * (size_t)K * 2);
-    w.w = c.dalloc(vb * (size_t)K);
-    w.ritz = c.dalloc(vb * (size_t)K * c.P.nev);
+    w.ring = c.dalloc(vb * (size_t)keig * w.ring_len);
+    w.vr = c.dalloc(vb * (size_t)keig * 2 * c.P.nev * (restart_pingpong(c.P) ? 2 : 1));
+    w.tbuf = c.dalloc(vb * (size_t)keig * 2);
+    w.w = c.dalloc(vb * (size_t)keig);
+    w.ritz = c.dalloc(vb * (size_t)keig * c.P.nev);
     w.eig = true;
   }
 }
@@ -832,6 +868,78 @@ void deflate_columns(Ctx& c, int prec, int ncols, uint32_t mask, void* x, const 
 }
 
 // ---------------------------------------------------------------------------
+// spectral preconditioner (params.precond): P^{-1} = I + U_R D U_R^H
+// ---------------------------------------------------------------------------
+
+// From the current bank: Rayleigh-Ritz on H (host FP64, H Y = Y Theta), the
+// Ritz basis U_R = U Y on the device, D = sigma / theta - 1 (Section 2.1's
+// spectral preconditioner; sigma from the parameters, else the largest Ritz
+// value seen, else (8 + |m|)^2).  An empty bank leaves P = I.
+static void ensure_spectral(Ctx& c) {
+  if (c.P.precond != EIGCG_PRECOND_SPECTRAL || c.spec_ok) return;
+  const int l = c.l, ld = c.P.max_bank;
+  c.lR = 0;
+  if (l > 0) {
+    std::vector<double> th(l);
+    std::vector<cplx> Y((size_t)l * l);
+    if (hostla::herm_eig_lowest(l, c.H.data(), ld, l, th.data(), Y.data(), l) != 0)
+      throw ApiError{EIGCG_EBREAKDOWN, "bank eigensolver failed"};
+    if (!(th[0] > 0.0))
+      throw ApiError{EIGCG_EBREAKDOWN, "the spectral preconditioner needs positive Ritz values"};
+    const double am = std::fabs(c.P.mass);
+    const double sigma = c.P.precond_sigma > 0 ? c.P.precond_sigma
+                                               : (c.amax > 0 ? c.amax : (8.0 + am) * (8.0 + am));
+    const size_t nb = (size_t)c.P.max_bank;
+    if (!c.UR) c.UR = c.dalloc(c.cs * 16 * nb);
+    if (!c.d_specD) {
+      c.d_specD = (double*)c.dalloc(sizeof(double) * nb);
+      c.d_specG = (double2*)c.dalloc(sizeof(double2) * nb * kMaxCols);
+      c.d_specS = (double2*)c.dalloc(sizeof(double2) * nb * kMaxCols);
+      c.d_specs = (double*)c.dalloc(sizeof(double) * kMaxCols);
+    }
+    std::vector<const void*> in(l);
+    std::vector<void*> out(l);
+    for (int i = 0; i < l; ++i) {
+      in[i] = col_ptr(c.U, kF64, c.cs, i);
+      out[i] = col_ptr(c.UR, kF64, c.cs, i);
+    }
+    tall_from_host(c, kF64, l, l, in, out, Y.data(), 0, 0);
+    std::vector<double> D(l);
+    for (int i = 0; i < l; ++i) D[i] = sigma / th[i] - 1.0;
+    c.check(hipMemcpy(c.d_specD, D.data(), sizeof(double) * l, hipMemcpyHostToDevice), "D");
+    c.spec_sigma = sigma;
+    c.lR = l;
+  }
+  c.spec_ok = true;
+}
+
+// z = P^{-1} r = r + U_R (D (U_R^H r)) for K columns (enqueued on stream s;
+// capturable); also leaves s_j = r_j^H U_R D U_R^H r_j in d_specs, so that
+// r^H z = ||r||^2 + s_j.
+static hipError_t apply_spectral(Ctx& c, hipStream_t s, int K, uint32_t mask, const void* r,
+                                 void* z) {
+  const int l = c.lR;
+  std::vector<const void*> in(l), rc(K);
+  std::vector<void*> zc(K);
+  for (int i = 0; i < l; ++i) in[i] = col_ptr(c.UR, kF64, c.cs, i);
+  for (int j = 0; j < K; ++j) {
+    rc[j] = col_ptr(const_cast<void*>(r), kF64, c.cs, j);
+    zc[j] = col_ptr(z, kF64, c.cs, j);
+  }
+  hipError_t e = launch_gemm_reduce(kF64, c.cs, l, K, in.data(), rc.data(), c.d_gpart,
+                                    c.gpart_elems, c.d_specG, s);
+  if (e == hipSuccess) e = launch_spec_scale(c.d_specG, c.d_specD, l, K, c.d_specS, c.d_specs, s);
+  if (e == hipSuccess) e = launch_copy(kF64, kF64, K, c.cs, r, c.cs, z, c.cs, s, mask);
+  const int nmax = std::max(1, std::min(24, 4096 / l));
+  for (int n0 = 0; n0 < K && e == hipSuccess; n0 += nmax) {
+    const int nn = std::min(nmax, K - n0);
+    e = launch_gemm_tall(kF64, c.cs, l, nn, in.data(), zc.data() + n0, c.d_specS + (size_t)n0 * l,
+                         1, 0, s);
+  }
+  return e;
+}
+
+// ---------------------------------------------------------------------------
 // eigCG window bookkeeping (host side, one per column)
 // ---------------------------------------------------------------------------
 
@@ -867,6 +975,7 @@ struct Run {
   std::vector<int> first_leg;    // iterations before the first init-CG restart (-1: none)
   std::vector<int> stale_until;  // snapshots of segments <= this id predate a host restart
   int enq_iter = 0;              // iterations enqueued (all columns in lockstep)
+  bool spec = false;             // iterations preconditioned with z = P^{-1} r
   int seg_id = 0;                // id of the last enqueued segment
   // captured segments of n iterations (params.use_graphs): the kernels of a
   // segment only depend on this run's buffers, mask and width, so one graph
@@ -887,12 +996,17 @@ struct Run {
     first_leg.assign(K, -1);
     stale_until.assign(K, -1);
     for (int j = 0; j < K; ++j) ec[j].next_full = m;
+    spec = c.P.precond == EIGCG_PRECOND_SPECTRAL && prec == kF64 && c.spec_ok && c.lR > 0;
+    if (spec) check_fields(c, w.z, kF64, K, "preconditioned residuals");
     // every launch of the run covers K columns of the workspace
     if (K > w.K) throw ApiError{EIGCG_EINVAL, "internal: run wider than its workspace"};
     for (const void* f : {w.b, w.r, w.p, w.tmp}) check_fields(c, f, prec, K, "run field");
     check_fields(c, w.x, prec == kF16 ? kF32 : prec, K, "run iterate");
     check_eo_tmp(c, prec, K);
-    if (eig) check_fields(c, w.ring, prec, K * w.ring_len, "window ring");
+    if (eig) {
+      if (K > w.Keig) throw ApiError{EIGCG_EINVAL, "internal: eigCG run wider than its window"};
+      check_fields(c, w.ring, prec, K * w.ring_len, "window ring");
+    }
   }
   ~Run() {
     for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
@@ -966,14 +1080,23 @@ struct Run {
     L3.ring_cs = c.cs;
     L3.ring_len = w.ring_len;
     L3.ring_col_cs = (size_t)w.ring_len * c.cs;
-    // the update kernel forms the CG scalars from both passes' partials
+    // preconditioned iterations: after the second pass z = P^{-1} r, then the
+    // CG scalars with rho = r^H z, then p = z + beta p and the window from z
     int nb2 = 0;
-    L2.grid_out = &nb2;
-    L3.part_a = c.d_partial;
-    L3.part_b = c.d_partial + (size_t)kMaxCols * kMaxGrid;
-    L3.hist = c.d_hist;
-    L3.hist_stride = c.hist_stride;
-    L3.counter = c.d_ucount;
+    double* part_a = c.d_partial;
+    double* part_b = c.d_partial + (size_t)kMaxCols * kMaxGrid;
+    if (spec) {
+      L2.defer_finalize = 1;
+      L2.grid_out = &nb2;
+      L3.r = w.z;
+    }
+    auto precond_step = [&](hipStream_t st) -> hipError_t {
+      hipError_t e = apply_spectral(c, st, K, mask, w.r, w.z);
+      if (e == hipSuccess)
+        e = launch_finalize_cg(c.d_st, K, mask, part_a, part_b, nb2, c.d_hist, c.hist_stride,
+                               c.d_specs, st);
+      return e;
+    };
     if (c.P.use_graphs && c.P.sample_every <= 0 && n > 0) {
       auto it = graphs.find(n);
       if (it == graphs.end()) {
@@ -987,7 +1110,7 @@ struct Run {
         for (int i = 0; i < n && e == hipSuccess; ++i) {
           e = launch_stencil(L1, c.gstream);
           if (e == hipSuccess) e = launch_stencil(L2, c.gstream);
-          L3.nb = nb2;
+          if (e == hipSuccess && spec) e = precond_step(c.gstream);
           if (e == hipSuccess) e = launch_cg_update(L3, c.gstream);
         }
         const hipError_t e2 = hipStreamEndCapture(c.gstream, &gr);
@@ -1012,7 +1135,7 @@ struct Run {
       L2.ev_stop = ks ? ks->e[3] : nullptr;
       c.check(launch_stencil(L1, c.stream), "K1");
       c.check(launch_stencil(L2, c.stream), "K2");
-      L3.nb = nb2;
+      if (spec) c.check(precond_step(c.stream), "preconditioner");
       c.check(launch_cg_update(L3, c.stream), "K3");
     }
     enq_iter += n;
@@ -1224,6 +1347,10 @@ constexpr double kRefineRel = 1e-4;
 constexpr double kRefineRelHalf = 1e-2;
 
 static void cg_start(Run& R, uint32_t mask) {
+  if (R.spec) {  // z = P^{-1} r and rho = r^H z = ||r||^2 + s for the first direction
+    R.c.check(apply_spectral(R.c, R.c.stream, R.K, mask, R.w.r, R.w.z), "preconditioner");
+    R.c.check(launch_spec_rho(R.c.d_st, R.K, mask, R.c.d_specs, R.c.stream), "rho");
+  }
   UpdateLaunch L{};
   L.prec = R.prec;
   L.ncols = R.K;
@@ -1231,7 +1358,7 @@ static void cg_start(Run& R, uint32_t mask) {
   L.st = R.c.d_st;
   L.g = &R.c.g;
   L.p = R.w.p; L.p_cs = R.c.cs;
-  L.r = R.w.r; L.r_cs = R.c.cs;
+  L.r = R.spec ? R.w.z : R.w.r; L.r_cs = R.c.cs;
   L.ring = R.eig ? R.w.ring : nullptr;
   L.ring_cs = R.c.cs;
   L.ring_len = R.w.ring_len;
@@ -1760,6 +1887,7 @@ int bank_append_from(Ctx& c, const void* src, int nsrc) {
   if (good < l + kept) kept = std::max(0, good - l);
   c.l = l + kept;
   c.chol_ok = false;
+  c.spec_ok = false;
   return kept;
 }
 
@@ -1789,6 +1917,7 @@ static double cg_iteration_ms(Ctx& c, int prec, int K) {
   std::memcpy(c.h_st, st.data(), sizeof(ColState) * K);
   c.check(hipMemcpy(c.d_st, c.h_st, sizeof(ColState) * K, hipMemcpyHostToDevice), "st");
   const int reps = 10;
+  ensure_spectral(c);
   Run R(c, w, prec, K, K >= 32 ? 0xffffffffu : ((1u << K) - 1), false);
   hipEvent_t e0, e1;
   c.check(hipEventCreate(&e0), "ev");
@@ -1904,8 +2033,10 @@ int solve(Ctx& c, int nrhs, const void* b_aos, void* x_aos, double tol, int mode
                                  "restart at every refinement step)"};
   const bool any_eig = mode == EIGCG_MODE_EIGCG || mode == EIGCG_MODE_AUTO;
   const int prec = mixed ? c.iprec : kF64;
-  ws_ensure(c, c.ws64, kF64, any_eig && !mixed);
-  if (mixed) ws_ensure(c, c.ws32, c.iprec, any_eig);
+  // eigCG groups run min(max_batch, nrhs) columns: the window holds that many
+  const int keig = std::min(c.P.max_batch, nrhs);
+  ws_ensure(c, c.ws64, kF64, any_eig && !mixed, keig);
+  if (mixed) ws_ensure(c, c.ws32, c.iprec, any_eig, keig);
   Workspace& w = mixed ? c.ws32 : c.ws64;
   Workspace& w64 = c.ws64;
   int worst = EIGCG_OK;
@@ -1951,6 +2082,7 @@ int solve(Ctx& c, int nrhs, const void* b_aos, void* x_aos, double tol, int mode
         c.check(hipMemsetAsync(col_ptr(w64.x, kF64, c.cs, j), 0, c.cs * 16, c.stream), "zero");
       }
     }
+    ensure_spectral(c);  // the bank may have grown since the last group
     Driver D(c, w, w64, prec, K, eig, scheme);
     {  // columns with b = 0 never run
       std::vector<ColState> idle(K);
@@ -2046,6 +2178,7 @@ Session* session_open(Ctx& c) {
   const int prec = mixed ? c.iprec : kF64;
   ws_ensure(c, c.ws64, kF64, false);
   if (mixed) ws_ensure(c, c.ws32, c.iprec, false);
+  ensure_spectral(c);
   Session* s = new Session(c, mixed ? c.ws32 : c.ws64, c.ws64, prec,
                            scheme_for(c, EIGCG_MODE_INITCG));
   std::vector<ColState> idle(s->K);
@@ -2246,6 +2379,7 @@ void bank_truncate(Ctx& c, int k) {
   if (k == 0) {
     c.l = 0;
     c.chol_ok = false;
+    c.spec_ok = false;
     return;
   }
   const int l = c.l, ld = c.P.max_bank, prec = c.bank_prec;
@@ -2271,6 +2405,7 @@ void bank_truncate(Ctx& c, int k) {
   for (int i = 0; i < k; ++i) c.H[(size_t)i * ld + i] = cplx(th[i], 0.0);
   c.l = k;
   c.chol_ok = false;
+  c.spec_ok = false;
 }
 
 // Restore a saved bank: U <- the given fields (in the bank's precision) and
@@ -2298,6 +2433,7 @@ void bank_restore(Ctx& c, int l, const void* vecs_aos, const double* h_host) {
   c.H = Hn;
   c.l = l;
   c.chol_ok = false;
+  c.spec_ok = false;
 }
 
 void bank_vectors(Ctx& c, int first, int count, void* out_aos) {
@@ -2336,6 +2472,7 @@ double bench_kernels(Ctx& c, int what, int reps) {
   st[0].max_iter = 0x3fffffff;
   std::memcpy(c.h_st, st.data(), sizeof(ColState));
   c.check(hipMemcpy(c.d_st, c.h_st, sizeof(ColState), hipMemcpyHostToDevice), "st");
+  ensure_spectral(c);
   Run R(c, w, prec, 1, 1u, false);
   hipEvent_t e0, e1;
   c.check(hipEventCreate(&e0), "ev");

@@ -29,6 +29,7 @@ struct ApiError {
 // Device vectors of one batched solve (K columns, one precision).
 struct Workspace {
   int K = 0;
+  int Keig = 0;          // columns of the eigCG window arrays
   int prec = kF64;
   bool eig = false;
   int ring_len = 0;
@@ -43,6 +44,7 @@ struct Workspace {
   void* tbuf = nullptr;  // K * 2 saved A p
   void* w = nullptr;     // K arrow-row vectors
   void* ritz = nullptr;  // K * nev Ritz vectors
+  void* z = nullptr;     // K preconditioned residuals z = P^{-1} r (spectral preconditioner)
 };
 
 struct Ctx {
@@ -72,6 +74,17 @@ struct Ctx {
   std::vector<cplx> L;    // Cholesky factor of H(0:l, 0:l)
   bool chol_ok = false;
   double amax = 0.0;      // largest Ritz value seen (norm of A estimate)
+  // spectral preconditioner P^{-1} = I + U_R D U_R^H (params.precond): the
+  // bank in its Ritz basis, D = sigma / theta - 1, device staging of U_R^H r,
+  // D U_R^H r and r^H U_R D U_R^H r per column
+  void* UR = nullptr;
+  int lR = 0;             // columns of U_R (0: P = I)
+  bool spec_ok = false;   // U_R, D built for the current bank
+  double spec_sigma = 0.0;
+  double* d_specD = nullptr;
+  double2* d_specG = nullptr;
+  double2* d_specS = nullptr;
+  double* d_specs = nullptr;
   void* bs = nullptr;      // BiCGSTAB on M or gamma5 M: eight FP64 work fields
   // scratch
   ColState* d_st = nullptr;
@@ -81,7 +94,6 @@ struct Ctx {
   int hist_stride = 0;             // doubles per column
   double* d_partial = nullptr;
   unsigned int* d_counter = nullptr;
-  unsigned int* d_ucount = nullptr;  // per-column arrival counters of the CG update kernel
   double2* d_gpart = nullptr;
   size_t gpart_elems = 0;
   double2* d_small = nullptr;      // small matrices (S, G) for GEMMs
@@ -142,6 +154,8 @@ double bench_kernels(Ctx& c, int what, int reps);
 bool auto_continue(int done, int left, const double* iters, const double* secs, double iter_ms,
                    int bank_room);
 void kernel_samples(Ctx& c, bool reset, double* out);
+// device bytes an eigCG run of keig columns would still allocate for its window
+size_t eig_window_bytes(const Ctx& c, int keig);
 // drop this process's stencil tuning choices (the persisted file stays)
 void tune_cache_reset();
 

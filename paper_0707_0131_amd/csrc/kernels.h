@@ -16,8 +16,8 @@ enum StencilOp { kOpM = 0, kOpMdag = 1 };
 enum StencilEpi {
   kEpiStore = 0,   // out = op(in)
   kEpiNorm = 1,    // out = op(in); partials of ||out||^2 = p^H A p (first CG pass)
-  kEpiCGR = 2,     // alpha from the first pass; t = op(in); r -= alpha t; r^H r (the
-                   // update kernel that follows forms beta and the stop tests)
+  kEpiCGR = 2,     // alpha from the first pass; t = op(in); r -= alpha t; r^H r; then a
+                   // finalize kernel updates alpha, beta and the stop tests
   kEpiRes = 3,     // r = b - op(in); r^H r -> rho (true residual, with finalize)
 };
 
@@ -64,6 +64,8 @@ struct StencilLaunch {
   hipEvent_t ev_stop = nullptr;     // start and end, taken by its dispatch
   int* grid_out = nullptr;          // when set: receives the grid's x extent (the number
                                     // of partials per column the pass writes)
+  int defer_finalize = 0;           // kEpiCGR: leave the finalize kernel to the caller
+                                    // (launch_finalize_cg), e.g. after a preconditioner
   int nc = 0;                       // variants 3..10: columns per workgroup (1, 2, or 4
                                     // for FP32); 0 = widest that ncols allows
   // Odd-even geometry (g->eo): op is the even-site Schur complement
@@ -89,14 +91,8 @@ hipError_t launch_stencil_eo_f64(const StencilLaunch& L, hipStream_t s);
 hipError_t launch_stencil_eo_f32(const StencilLaunch& L, hipStream_t s);
 hipError_t launch_stencil_eo_f16(const StencilLaunch& L, hipStream_t s);
 
-// End of a CG iteration: the iteration's scalars from the two stencil passes'
-// partials (alpha = rho / p^H A p, beta = rho_new / rho, history, stop tests,
-// eigCG t-save schedule), then x += alpha p; (running) p = r + beta p;
-// optional window append V_ring[(iter + 1) % ring] = r / sqrt(rho).  Every
-// workgroup forms the scalars itself from the column state as it was before
-// the iteration; the last workgroup of a column to finish (counted by an
-// atomic counter per column, which it resets) stores the new state, so no
-// workgroup reads a state another one has already replaced.
+// End of a CG iteration: x += alpha p; (running) p = r + beta p; optional window append
+// V_ring[(iter + 1) % ring] = r / sqrt(rho).
 struct UpdateLaunch {
   int prec;
   int ncols;
@@ -107,13 +103,26 @@ struct UpdateLaunch {
   void* p; size_t p_cs;
   const void* r; size_t r_cs;
   void* ring; size_t ring_cs; int ring_len; size_t ring_col_cs;  // slot stride, column stride
-  const double* part_a;     // first pass (||M p||^2) partials, nb per column
-  const double* part_b;     // second pass (r^H r) partials, nb per column
-  int nb;
-  double* hist; int hist_stride;  // alpha, beta, rho_new per iteration (or null)
-  unsigned int* counter;    // kMaxCols counters, zero between launches
 };
 hipError_t launch_cg_update(const UpdateLaunch& L, hipStream_t s);
+
+// The CG scalars after the second stencil pass (what a kEpiCGR launch does
+// itself unless defer_finalize): p^H A p from part_a (alpha or breakdown),
+// ||r||^2 from part_b (stop tests); with spec_s the preconditioned rho_new =
+// r^H z = ||r||^2 + spec_s[col] sets beta, rho and the history.  nb partials
+// per column (the passes' grid extent).
+hipError_t launch_finalize_cg(ColState* st, int ncols, uint32_t mask, const double* part_a,
+                              const double* part_b, int nb, double* hist, int hist_stride,
+                              const double* spec_s, hipStream_t s);
+// Spectral preconditioner z = r + U_R (D (U_R^H r)) (blas.hip): from G =
+// U_R^H r (l x ncols, complex, column-major), S = D G and s = G^H D G per
+// column (fixed order); then z = r and the caller adds U_R S.
+hipError_t launch_spec_scale(const double2* G, const double* D, int l, int ncols, double2* S,
+                             double* s_out, hipStream_t s);
+// rho += s[col] for running masked columns (the start of a preconditioned CG:
+// rho = r^H z after the true residual's ||r||^2)
+hipError_t launch_spec_rho(ColState* st, int ncols, uint32_t mask, const double* s_in,
+                           hipStream_t s);
 
 // Initial CG state: p = r (rho already in st), optional ring slot 1 write;
 // per column: rho = r^H r given by kEpiRes.

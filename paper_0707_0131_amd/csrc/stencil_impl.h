@@ -10,8 +10,8 @@
 // (||M p||^2 and r^H r) are deterministic and fence-free: fixed-order
 // wave/workgroup sums into one partial slot per workgroup; the second pass
 // sums the first pass's partials itself (same order in every workgroup) to
-// get alpha, and the update kernel that follows sums both passes' partials
-// the same way to form the CG scalars of every column.
+// get alpha, and a one-workgroup finalize kernel, ordered by the stream,
+// updates the CG scalars of every column.
 #include <algorithm>
 #include <type_traits>
 
@@ -131,7 +131,7 @@ __device__ __forceinline__ bool column_setup(const DevArgs& a, int col, double* 
   save_slot = 0;
   if (EPI == kEpiCGR) {
     // alpha = rho / ||M p||^2 from the first pass's partials, summed in the
-    // same fixed order by every workgroup (and by the update kernel)
+    // same fixed order by every workgroup (and by the finalize kernel)
     const double pap = reduce_partials(a.partial_in + (size_t)col * gridDim.x, gridDim.x, lds4);
     if (active) {
       if (pap > 0.0 && pap < INFINITY) {
@@ -140,7 +140,7 @@ __device__ __forceinline__ bool column_setup(const DevArgs& a, int col, double* 
         save_t = a.tbuf != nullptr && (j == a.st[col].save_t0 || j == a.st[col].save_t1);
         save_slot = j & 1;
       } else {
-        active = false;  // breakdown: the update kernel stops the column
+        active = false;  // breakdown: the finalize kernel stops the column
       }
     }
   }
@@ -460,6 +460,68 @@ __global__ __launch_bounds__(kBlock) void k_wilson_zmarch(DevArgs a) {
   if (threadIdx.x == 0) a.partial[(size_t)col * gridDim.x + blockIdx.x] = (double)bs;
 }
 
+// CG scalars after the second stencil pass (one workgroup): p^H A p from the
+// first pass's partials (alpha, or breakdown), r^H r from the second pass's
+// partials (beta, history, stop tests, eigCG t-save schedule).  With a
+// preconditioner (spec_s): the stop tests keep ||r||^2 and the CG scalar
+// becomes r^H z = ||r||^2 + spec_s[c].
+__global__ __launch_bounds__(kBlock) void k_finalize_cg(ColState* st, int ncols, uint32_t mask,
+                                                        const double* part_a, const double* part_b,
+                                                        int nb, double* hist, int hist_stride,
+                                                        const double* spec_s) {
+  __shared__ double lds4[kBlock / 64];
+  {
+    const int c = blockIdx.x;  // one workgroup per column
+    if (c >= ncols || !((mask >> c) & 1u)) return;
+    const double pap = reduce_partials(part_a + (size_t)c * nb, nb, lds4);
+    const double rr_new = reduce_partials(part_b + (size_t)c * nb, nb, lds4);
+    const double rho_new = spec_s ? rr_new + spec_s[c] : rr_new;
+    if (threadIdx.x != 0) return;
+    ColState& S = st[c];
+    if (S.state == ColRun) {
+      S.pap = pap;
+      if (!(pap > 0.0 && pap < INFINITY)) {
+        S.alpha = 0.0;
+        S.state = ColStopPending;
+        S.reason = ReasonBreakdown;
+        return;
+      }
+      S.alpha = S.rho / pap;
+      const int j = S.iter + 1;
+      const double beta = rho_new / S.rho;
+      if (hist) {
+        double* h = hist + (size_t)c * hist_stride + (size_t)3 * (j - 1);
+        h[0] = S.alpha;
+        h[1] = beta;
+        h[2] = rho_new;
+      }
+      S.iter = j;
+      if (j == S.save_t1 && S.tperiod > 0) {
+        S.save_t0 += S.tperiod;
+        S.save_t1 += S.tperiod;
+      }
+      S.rho_prev = S.rho;
+      S.rho = rho_new;
+      S.beta = beta;
+      if (!(rho_new < INFINITY)) {
+        S.state = ColStopPending;
+        S.reason = ReasonBreakdown;
+      } else if (rr_new <= S.stop2) {
+        S.state = ColStopPending;
+        S.reason = ReasonConverged;
+      } else if (rr_new <= S.restart2) {
+        S.state = ColStopPending;
+        S.reason = ReasonRestart;
+      } else if (j >= S.max_iter) {
+        S.state = ColStopPending;
+        S.reason = ReasonMaxIter;
+      }
+    } else if (S.state == ColStopPending) {
+      S.state = ColStopped;
+    }
+  }
+}
+
 // rho = ||b - A x||^2 of a true-residual pass
 __global__ __launch_bounds__(kBlock) void k_finalize_res(ColState* st, int ncols, uint32_t mask,
                                                          const double* part, int nb) {
@@ -670,9 +732,11 @@ hipError_t launch_typed(const StencilLaunch& L, hipStream_t s) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (L.grid_out) *L.grid_out = gx;
-  // kEpiCGR: the update kernel that follows forms the CG scalars from both
-  // passes' partials (launch_cg_update)
-  if (L.epi == kEpiRes)
+  if (L.epi == kEpiCGR) {
+    if (!L.defer_finalize)
+      hipLaunchKernelGGL(k_finalize_cg, dim3(L.ncols), dim3(kBlock), 0, s, L.st, L.ncols, L.mask,
+                         part_a, part_b, gx, L.hist, L.hist_stride, (const double*)nullptr);
+  } else if (L.epi == kEpiRes)
     hipLaunchKernelGGL(k_finalize_res, dim3(L.ncols), dim3(kBlock), 0, s, L.st, L.ncols, L.mask, part_b,
                        gx);
   return hipGetLastError();

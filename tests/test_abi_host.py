@@ -49,7 +49,8 @@ def test_default_params_and_validation(B):
                 dict(max_bank=300), dict(precision=7), dict(max_iter=0),
                 dict(mass=float("nan")), dict(nev=0), dict(schur=2),
                 dict(schur=1, dims=(4, 4, 3, 4)), dict(stencil_variant=14),
-                dict(sample_every=-1), dict(nev=16, m=257)]:
+                dict(sample_every=-1), dict(nev=16, m=257), dict(precond=2),
+                dict(precond=1, precision=1), dict(precond_sigma=float("inf"))]:
         q = B.eigcg_default_params(**bad)
         rc = B.LIB.eigcg_create(ctypes.byref(q), fake, None, ctypes.byref(ctx))
         assert rc == B.EIGCG_EINVAL, bad

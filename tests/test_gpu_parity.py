@@ -14,6 +14,7 @@ from oracle.cg import cg
 from oracle.dirac import WilsonOperator
 from oracle.eigcg import eigcg
 from oracle.initcg import galerkin_guess, init_cg
+from oracle.spectral import ritz_basis, spectral_preconditioner
 from synthetic import gauge_field, gaussian_rhs, gaussian_rhs_block, unit_gauge_field
 
 pytestmark = pytest.mark.gpu
@@ -386,6 +387,113 @@ def test_batched_initcg_guesses_match_single_solves(B, cfg0):
             assert st_all[i]["true_rel_res"] <= 1e-10
     finally:
         B.eigcg_destroy(ctx)
+
+
+def _spectral_setup(op, nbank=12, sigma=40.0):
+    """The lowest nbank eigenvectors of the 4^4 A (dense) as the bank, and the
+    oracle's spectral preconditioner built from them (Ritz basis of H = X^H A X)."""
+    A, lam, X = _dense_lowest(op, nbank)
+    H = X.conj().T @ A @ X
+    UR, th = ritz_basis(X, H)
+    return A, X, H, spectral_preconditioner(UR, th, sigma)
+
+
+def test_spectral_preconditioned_cg_parity(B, cfg0):
+    """CG preconditioned by the bank as a spectral preconditioner (sigma = 40;
+    the 12 near-zero modes of this field move to 40, CG needs ~5x fewer
+    iterations): same stop within one iteration of the oracle's
+    preconditioned CG, x equal to its iterate at the GPU's count to 1e-10."""
+    U, op, b = cfg0
+    A, X, H, Pinv = _spectral_setup(op)
+    bf = b.reshape(-1)
+    xo, io = cg(op.A, bf, tol=1e-10, apply_Pinv=Pinv)
+    k = io["iterations"]
+    cands = {k: xo}
+    for kk in (k - 1, k + 1):
+        cands[kk] = cg(op.A, bf, tol=0.0, max_iter=kk, true_residual_restarts=0, apply_Pinv=Pinv)[0]
+    _, iplain = cg(op.A, bf, tol=1e-10)
+    assert k < 0.3 * iplain["iterations"]
+    ctx, _ = make_ctx(U, -0.2, nev=6, m=20, max_bank=12, max_iter=5000, precond=1,
+                      precond_sigma=40.0)
+    try:
+        assert B.eigcg_bank_load(ctx, dev(X.T.reshape((12, 4, 4, 4, 4, 4, 3)).copy())) == 12
+        x = dev(np.zeros((1,) + b.shape, dtype=np.complex128))
+        rc, st = B.eigcg_solve(ctx, dev(b[None]), x, 1e-10, B.EIGCG_MODE_CG)
+        assert rc == B.EIGCG_OK, B.eigcg_last_error(ctx)
+        assert st[0]["iters"] in cands, (st[0]["iters"], k)
+        assert st[0]["true_rel_res"] <= 1e-10
+        assert rel(host(x)[0].reshape(-1), cands[st[0]["iters"]]) <= 1e-10
+    finally:
+        B.eigcg_destroy(ctx)
+
+
+@pytest.mark.parametrize("nev,m,iters", [(4, 12, 40), (10, 40, 80)])
+def test_spectral_preconditioned_eigcg_same_trajectory(B, cfg0, nev, m, iters):
+    """eigCG in the preconditioned form of Section 3 (window V = P^{-1} R,
+    Ritz pairs of the pencil A y = lambda P y) with the spectral
+    preconditioner, after the init-CG guess from the same bank, forced to a
+    fixed iteration count: same restarts, Ritz values to 1e-8, x to 1e-10."""
+    U, op, b = cfg0
+    A, X, H, Pinv = _spectral_setup(op)
+    bf = b.reshape(-1)
+    x0 = galerkin_guess(op.A, X, H, bf)
+    xo, _, tho, io = eigcg(op.A, bf, nev, m, x0=x0, tol=1e-14, max_iter=iters, apply_Pinv=Pinv)
+    ctx, _ = make_ctx(U, -0.2, nev=nev, m=m, max_bank=64, max_iter=iters, precond=1,
+                      precond_sigma=40.0)
+    try:
+        assert B.eigcg_bank_load(ctx, dev(X.T.reshape((12, 4, 4, 4, 4, 4, 3)).copy())) == 12
+        x = dev(np.zeros((1,) + b.shape, dtype=np.complex128))
+        rc, st = B.eigcg_solve(ctx, dev(b[None]), x, 1e-14, B.EIGCG_MODE_EIGCG)
+        assert rc == B.EIGCG_ENOTCONV
+        assert st[0]["iters"] == iters
+        assert st[0]["restarts"] == len(io["restart_iterations"])
+        th = B.eigcg_last_ritz(ctx)
+        assert len(th) == len(tho)
+        assert np.max(np.abs(th - tho) / np.abs(tho)) <= 1e-8
+        assert rel(host(x)[0].reshape(-1), xo) <= 1e-10
+        # the bank grew by the preconditioned Ritz vectors and stays orthonormal
+        l = len(B.eigcg_bank_info(ctx)[0])
+        assert l > 12
+        Uv = dev(np.zeros((l, 4, 4, 4, 4, 4, 3), dtype=np.complex128))
+        B.eigcg_bank_vectors(ctx, 0, l, Uv)
+        Um = host(Uv).reshape(l, -1).T
+        assert np.max(np.abs(Um.conj().T @ Um - np.eye(l))) < 1e-12
+    finally:
+        B.eigcg_destroy(ctx)
+
+
+def test_spectral_preconditioner_with_batches_and_empty_bank(B, cfg0):
+    """Preconditioned CG over a batch of 3 columns equals single-column solves
+    bitwise; with an empty bank the preconditioner is the identity (the same
+    bits as plain CG)."""
+    U, op, _ = cfg0
+    A, X, H, Pinv = _spectral_setup(op)
+    bs = gaussian_rhs_block((4, 4, 4, 4), [2600, 2601, 2602])
+    kw = dict(nev=6, m=20, max_bank=12, max_iter=5000, precond=1, precond_sigma=40.0)
+    ctx3, _ = make_ctx(U, -0.2, max_batch=3, stencil_variant=3, **kw)
+    ctx1, _ = make_ctx(U, -0.2, max_batch=1, stencil_variant=3, **kw)
+    plain, _ = make_ctx(U, -0.2, max_batch=1, stencil_variant=3, max_iter=5000)
+    try:
+        # empty bank: P = I
+        x_e = dev(np.zeros_like(bs[:1]))
+        x_p = dev(np.zeros_like(bs[:1]))
+        rc, st_e = B.eigcg_solve(ctx1, dev(bs[:1]), x_e, 1e-10, B.EIGCG_MODE_CG)
+        rc, st_p = B.eigcg_solve(plain, dev(bs[:1]), x_p, 1e-10, B.EIGCG_MODE_CG)
+        assert st_e[0]["iters"] == st_p[0]["iters"] and np.array_equal(host(x_e), host(x_p))
+        vecs = dev(X.T.reshape((12, 4, 4, 4, 4, 4, 3)).copy())
+        B.eigcg_bank_load(ctx1, vecs)
+        B.eigcg_bank_load(ctx3, vecs)
+        x3 = dev(np.zeros_like(bs))
+        rc, st3 = B.eigcg_solve(ctx3, dev(bs), x3, 1e-10, B.EIGCG_MODE_CG)
+        assert rc == B.EIGCG_OK
+        for i in range(3):
+            x1 = dev(np.zeros_like(bs[i:i + 1]))
+            rc, st1 = B.eigcg_solve(ctx1, dev(bs[i:i + 1]), x1, 1e-10, B.EIGCG_MODE_CG)
+            assert st1[0]["iters"] == st3[i]["iters"]
+            assert np.array_equal(host(x1)[0], host(x3)[i])
+    finally:
+        for c in (ctx3, ctx1, plain):
+            B.eigcg_destroy(c)
 
 
 def test_incremental_eigcg_bank(B, cfg0):

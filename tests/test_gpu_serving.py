@@ -186,3 +186,116 @@ def test_schur_field_alone_equals_mixed(B):
         B.eigcg_destroy(sctx)
         for c in ctxs:
             B.eigcg_destroy(c)
+
+
+def _grow_ctxs(B, precision):
+    """Two fields with empty banks (they grow inside the server)."""
+    ctxs, keep = [], []
+    for dims, eps, seed, mass in FIELDS:
+        U = gauge_field(dims, eps, seed)
+        ctx, g = make_ctx(U, mass, precision=precision, max_batch=3, max_bank=24, nev=4, m=20,
+                          max_iter=4000, restart_tol=-1.0)
+        ctxs.append(ctx)
+        keep.append(g)
+    return ctxs, keep
+
+
+# per field: eigCG requests grow the bank, init-CG requests use it
+GROW_PLAN = [1, 1, 2, 2, 1, 2, 2]  # modes: 1 = EIGCG, 2 = INITCG
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_bank_growing_requests_alone_equal_mixed_and_direct(B, precision):
+    """eigCG-mode requests (one step of Incremental eigCG each) grow their
+    field's bank inside the server; later init-CG requests are deflated with
+    the grown bank.  Every request's result is bitwise the same when the
+    requests are served one by one, when both fields' requests are submitted
+    at once (interleaved), and when the same sequence of calls runs directly on
+    a fresh context; the final banks agree too."""
+    import torch
+    shapes = [(d[3], d[2], d[1], d[0], 4, 3) for d, _, _, _ in FIELDS]
+    rhs = [gaussian_rhs_block(tuple(reversed(s[:4])), [3500 + 10 * f + i
+                                                         for i in range(len(GROW_PLAN))])
+           for f, s in enumerate(shapes)]
+    results = []
+    for how in ("alone", "mixed", "direct"):
+        ctxs, keep = _grow_ctxs(B, precision)
+        xs = [[torch.zeros((1,) + shapes[f], dtype=torch.complex128, device="cuda:0")
+               for _ in GROW_PLAN] for f in range(2)]
+        # the right-hand sides stay alive until their requests complete
+        bs = [[dev(rhs[f][i][None].copy()) for i in range(len(GROW_PLAN))] for f in range(2)]
+        its = {}
+        try:
+            if how == "direct":
+                for f in range(2):
+                    for i, mode in enumerate(GROW_PLAN):
+                        rc, st = B.eigcg_solve(ctxs[f], bs[f][i], xs[f][i], 1e-10, mode)
+                        assert rc == B.EIGCG_OK
+                        its[(f, i)] = st[0]["iters"]
+            else:
+                srv = B.eigcg_server_create(0)
+                fids = [B.eigcg_server_add(srv, c) for c in ctxs]
+                try:
+                    order = [(f, i) for i in range(len(GROW_PLAN)) for f in range(2)]
+                    tickets = {}
+                    for f, i in order:
+                        tickets[(f, i)] = B.eigcg_submit_mode(srv, fids[f], bs[f][i], xs[f][i],
+                                                              1e-10, GROW_PLAN[i])
+                        if how == "alone":
+                            B.eigcg_server_drain(srv)
+                    B.eigcg_server_drain(srv)
+                    for k, t in tickets.items():
+                        rc, st = B.eigcg_poll(srv, t)
+                        assert rc == B.EIGCG_OK, (k, rc)
+                        assert st["true_rel_res"] <= 1e-10
+                        its[k] = st["iters"]
+                finally:
+                    B.eigcg_server_destroy(srv)
+            banks = [B.eigcg_bank_info(c)[0] for c in ctxs]
+            results.append(({k: host(xs[k[0]][k[1]]) for k in its}, its, banks))
+        finally:
+            for c in ctxs:
+                B.eigcg_destroy(c)
+    ref_x, ref_it, ref_banks = results[2]
+    for xsd, itd, banks in results[:2]:
+        assert itd == ref_it
+        for k in ref_x:
+            assert np.array_equal(xsd[k], ref_x[k]), k
+        for a, b in zip(banks, ref_banks):
+            assert np.array_equal(a, b)
+    assert all(len(b) >= 8 for b in ref_banks)
+    # the grown bank pays: the last init-CG request needs fewer iterations
+    # than the first (eigCG) request on each field
+    for f in range(2):
+        assert ref_it[(f, len(GROW_PLAN) - 1)] < ref_it[(f, 0)]
+
+
+def test_eigcg_request_window_is_charged_against_the_budget(B):
+    """An eigCG request needs the field's eigCG window; with a budget that
+    holds only the contexts' resident memory it fails with ENOMEM (no device
+    allocation is attempted), while init-CG requests of the same field still
+    complete."""
+    import torch
+    ctxs, keep = _grow_ctxs(B, 0)
+    try:
+        mem = sum(B.eigcg_memory(c) for c in ctxs)
+        srv = B.eigcg_server_create(mem + 1)
+        fids = [B.eigcg_server_add(srv, c) for c in ctxs]
+        try:
+            shape = (4, 4, 4, 4, 4, 3)
+            b = dev(gaussian_rhs_block((4, 4, 4, 4), [3600])[:1].copy())
+            x1 = torch.zeros_like(b)
+            x2 = torch.zeros_like(b)
+            t1 = B.eigcg_submit_mode(srv, fids[0], b, x1, 1e-10, B.EIGCG_MODE_EIGCG)
+            t2 = B.eigcg_submit_mode(srv, fids[0], b, x2, 1e-10, B.EIGCG_MODE_INITCG)
+            B.eigcg_server_drain(srv)
+            rc1, _ = B.eigcg_poll(srv, t1)
+            rc2, st2 = B.eigcg_poll(srv, t2)
+            assert rc1 == B.EIGCG_ENOMEM
+            assert rc2 == B.EIGCG_OK and st2["true_rel_res"] <= 1e-10
+        finally:
+            B.eigcg_server_destroy(srv)
+        assert len(B.eigcg_bank_info(ctxs[0])[0]) == 0
+    finally:
+        for c in ctxs:
+            B.eigcg_destroy(c)
