@@ -33,6 +33,9 @@ Modules:
                      vectors for a nonsymmetric solver).
 * ``spectral``     - the bank used as a spectral preconditioner (Section
                      2.1's alternative to init-CG; Section 4's example).
+* ``restart_model`` - a dynamic init-CG restart threshold from the bank's
+                     Ritz values and residual norms (the open choice at the
+                     end of Section 5.3), as a stated cost model.
 
 Parity status: every function here is pinned by a test under ``tests/``
 (closed forms, invariants, dense linear algebra or brute force); nothing is
