@@ -9,7 +9,7 @@ Section 4 algorithm box: for each of the first ``s1`` right-hand sides
     H = [[H, U^H W], [W^H U, Vbar^H W]]         (nev new rows and columns)
     U = [U, Vbar]
 
-Readings: the paper calls the orthonormalisation "not strictly necessary";
+Readings: the paper treats the orthonormalisation as optional;
 here it is always done, by classical Gram-Schmidt applied twice against ``U``
 and then inside ``Vbar`` (column by column, again twice).  A column whose norm
 after projection falls below ``drop_tol`` times its norm before is dropped, so

@@ -8,18 +8,23 @@ the paper leaves the rule open.  This module writes out the rule the library
 takes, as a cost model in four steps.
 
 1. Contamination.  For the ``k`` lowest Ritz pairs ``(theta_j, u_j)`` of the
-   bank, the Davis-Kahan sin-Theta theorem bounds the angle between
-   ``span(u_1..u_k)`` and the true invariant subspace of the ``k`` lowest
-   eigenvalues by ``||R_k||_F / gap_k``, with ``R_k = [A u_j - theta_j u_j]``
-   and the gap to the rest of the spectrum estimated by
-   ``theta_{k+1} - theta_k``.  After a Galerkin projection (eq. (2.1)) the
-   residual components along those eigenvectors are at most that fraction of
-   the projected residual, so they reappear once CG has reduced the residual
-   by that factor: ``s_k = min(1, ||R_k||_F / gap_k)`` for ``k = 1..l-1`` and
-   ``s_0 = 0``.
-2. Bulk.  The bank separates its lowest ``b-1`` Ritz values from the rest,
-   ``b = 1 + max{k : s_k < 1}`` (``b = 1`` if none), so deflation leaves the
-   condition number ``kappa = lambda_max / theta_b``.
+   bank, with residuals ``R_k = [A u_j - theta_j u_j]``, the sine of the angle
+   between ``span(u_1..u_k)`` and the true invariant subspace lies between
+   ``||R_k|| / lambda_max`` and ``||R_k|| / gap_k`` (the second is the
+   Davis-Kahan sin-Theta bound, the gap to the rest of the spectrum estimated
+   by ``theta_{k+1} - theta_k``).  After a Galerkin projection (eq. (2.1))
+   the residual keeps components along those eigenvectors of at most that
+   angle relative to the projected residual, usually far less because the
+   error of a Ritz vector spreads over the whole spectrum; they reappear once
+   CG has reduced the residual that far.  Reading: the model takes the lower
+   end, ``s_k = ||R_k||_F / lambda_max`` (``s_0 = 0``), which is also Section
+   5.3's observation that Ritz vectors keep deflating until the linear
+   residual reaches their own residual norm scaled by the norm of A.
+2. Bulk.  The span of the ``k`` lowest is resolved when its Davis-Kahan
+   bound ``d_k = ||R_k||_F / gap_k`` is below one; the bank separates its
+   lowest ``b-1`` Ritz values from the rest, ``b = 1 + max{k : d_k < 1}``
+   (``b = 1`` if none), so deflation leaves the condition number
+   ``kappa = lambda_max / theta_b``.
 3. Leg cost.  A CG leg that starts right after a projection and reduces the
    residual by ``f`` keeps the lowest ``k'(f) = max{k < b : s_k <= f}``
    directions deflated; the others, ``O(f) = {k'+1 .. b-1}``, are outlying
@@ -49,18 +54,28 @@ import math
 import numpy as np
 
 
-def contamination_levels(theta, res):
-    """Step 1: ``s_0 .. s_{l-1}`` from ascending Ritz values and residual
-    norms (``s_0 = 0``; ``s_k`` for the span of the ``k`` lowest)."""
-    theta = np.asarray(theta, dtype=np.float64)
-    res = np.asarray(res, dtype=np.float64)
-    l = theta.size
+def _frobenius(res, k):
+    return math.sqrt(sum(float(r) * float(r) for r in res[:k]))
+
+
+def contamination_levels(theta, res, lam_max):
+    """Step 1: ``s_0 .. s_{l-1}`` (``s_0 = 0``; ``s_k`` for the span of the
+    ``k`` lowest of the ascending Ritz values)."""
+    l = len(theta)
     s = np.zeros(max(l, 1))
     for k in range(1, l):
-        rk = math.sqrt(float(np.sum(res[:k] ** 2)))
-        gap = theta[k] - theta[k - 1]
-        s[k] = 1.0 if gap <= 0.0 else min(1.0, rk / gap)
+        s[k] = _frobenius(res, k) / lam_max
     return s
+
+
+def bulk_start(theta, res):
+    """Step 2: ``b``, the 1-based index of the first Ritz value of the bulk."""
+    b = 1
+    for k in range(1, len(theta)):
+        gap = theta[k] - theta[k - 1]
+        if gap > 0.0 and _frobenius(res, k) / gap < 1.0:
+            b = k + 1
+    return b
 
 
 def outlier_bound(f, lam_max, lam_bulk, outliers):
@@ -73,10 +88,8 @@ def outlier_bound(f, lam_max, lam_bulk, outliers):
     return len(outliers) + 0.5 * math.sqrt(kappa) * (math.log(2.0 / f) + extra)
 
 
-def leg_cost(f, theta, s, lam_max):
+def leg_cost(f, theta, s, b, lam_max):
     """Step 3: predicted iterations of a leg that reduces the residual by ``f``."""
-    l = len(theta)
-    b = 1 + max([k for k in range(1, l) if s[k] < 1.0], default=0)
     kp = max([k for k in range(0, b) if s[k] <= f], default=0)
     return outlier_bound(f, lam_max, theta[b - 1], [theta[j - 1] for j in range(kp + 1, b)])
 
@@ -91,8 +104,9 @@ def choose_restart(theta, res, lam_max, tol, restart_cost):
         return 0.0, 0.0, 0.0
     if res.shape != theta.shape or np.any(np.diff(theta) < 0) or theta[0] <= 0.0:
         raise ValueError("need ascending positive Ritz values and one residual each")
-    s = contamination_levels(theta, res)
-    none = leg_cost(tol, theta, s, lam_max)
+    s = contamination_levels(theta, res, lam_max)
+    b = bulk_start(theta, res)
+    none = leg_cost(tol, theta, s, b, lam_max)
     pts = {tol, 1.0}
     for k in range(1, theta.size):
         for p in (s[k], tol / s[k] if s[k] > 0 else 0.0):
@@ -102,7 +116,8 @@ def choose_restart(theta, res, lam_max, tol, restart_cost):
     merged = []  # [lo, hi, cost]
     for lo, hi in zip(pts[:-1], pts[1:]):
         mid = math.sqrt(lo * hi)
-        c = leg_cost(mid, theta, s, lam_max) + restart_cost + leg_cost(tol / mid, theta, s, lam_max)
+        c = (leg_cost(mid, theta, s, b, lam_max) + restart_cost
+             + leg_cost(tol / mid, theta, s, b, lam_max))
         if merged and abs(merged[-1][2] - c) <= 1e-12 * max(1.0, abs(c)):
             merged[-1][1] = hi
         else:

@@ -16,7 +16,7 @@ from oracle.cg import cg
 from oracle.dirac import WilsonOperator
 from oracle.incremental import bank_ritz, incremental_eigcg
 from oracle.initcg import init_cg
-from oracle.restart_model import (choose_restart, contamination_levels, leg_cost,
+from oracle.restart_model import (bulk_start, choose_restart, contamination_levels, leg_cost,
                                   outlier_bound)
 from synthetic import gaussian_rhs
 
@@ -60,12 +60,15 @@ def _cluster(res_low):
 
 def test_contamination_levels_closed_form():
     theta, res = _cluster(1e-7)
-    s = contamination_levels(theta, res)
+    s = contamination_levels(theta, res, 60.0)
     assert s[0] == 0.0
-    assert s[1] == pytest.approx(1e-7 / 1e-3, rel=1e-14)
-    assert s[2] == pytest.approx(math.sqrt(2) * 1e-7 / 1e-3, rel=1e-14)
-    assert s[3] == pytest.approx(math.sqrt(3) * 1e-7 / (1.0 - 3e-3), rel=1e-14)
-    assert s[4] == 1.0 and s[5] == 1.0
+    assert s[1] == pytest.approx(1e-7 / 60.0, rel=1e-14)
+    assert s[3] == pytest.approx(math.sqrt(3) * 1e-7 / 60.0, rel=1e-14)
+    assert s[5] == pytest.approx(math.sqrt(3 * 1e-14 + 2 * 0.09) / 60.0, rel=1e-14)
+    # the three low pairs are resolved (Davis-Kahan bound below one), the
+    # bulk pairs with residual 0.3 and gaps 0.1 are not
+    assert bulk_start(theta, res) == 4
+    assert bulk_start(theta, np.full(6, 0.9)) == 1
 
 
 def test_exact_eigenvectors_never_restart():
@@ -109,10 +112,11 @@ def test_choice_minimises_the_stated_cost(seed):
     res = 10.0 ** rng.uniform(-9, -2, l)
     lam_max, tol, R = 60.0, 1e-10, float(rng.uniform(0, 40))
     tau, c0, c1 = choose_restart(theta, res, lam_max, tol, R)
-    s = contamination_levels(theta, res)
+    s = contamination_levels(theta, res, lam_max)
+    b = bulk_start(theta, res)
 
     def cost(t):
-        return leg_cost(t, theta, s, lam_max) + R + leg_cost(tol / t, theta, s, lam_max)
+        return leg_cost(t, theta, s, b, lam_max) + R + leg_cost(tol / t, theta, s, b, lam_max)
 
     grid = np.exp(np.linspace(math.log(tol), 0.0, 2001))[1:-1]
     best = min(min(cost(t) for t in grid), c0)
