@@ -58,9 +58,14 @@ HBM_CG_MASS = -0.58
 HBM_CG_ITERS = 240  # FP64 CG iterations sampled on the 24^3x48 lattice
 
 
+RESTART_RULE = {"fixed": 0, "dynamic": 1}
+restart_rule = 0  # init-CG restart threshold of the timed steps (--restart-rule)
+
+
 def run_step(B, torch, g, mass, bt, xt, n_eig=N_EIG):
     p = B.eigcg_default_params(dims=LATTICE, mass=mass, nev=NEV, m=M, max_bank=NBANK,
-                               max_iter=40000, check_every=16, sample_every=SAMPLE_EVERY)
+                               max_iter=40000, check_every=16, sample_every=SAMPLE_EVERY,
+                               restart_rule=restart_rule)
     ctx = B.eigcg_create(p, g)
     try:
         xt.zero_()
@@ -85,6 +90,8 @@ def run_step(B, torch, g, mass, bt, xt, n_eig=N_EIG):
         "phase2_s": t2 - t1,
         "phase1_iters": [s["iters"] for s in st1],
         "phase2_iters": [s["iters"] for s in st2],
+        "phase2_first_leg_iters": [s["first_leg_iters"] for s in st2],
+        "phase2_restart_tau": sorted({s["restart_tau"] for s in st2}),
         "max_true_rel_res": max(s["true_rel_res"] for s in st1 + st2),
         "failed": len(bad),
         "bank_lambda_min": float(vals[0]) if len(vals) else None,
@@ -106,6 +113,56 @@ def plain_cg(B, torch, g, mass, bt, xt, n):
     finally:
         B.eigcg_destroy(ctx)
     return dt, [s["iters"] for s in st], max(s["true_rel_res"] for s in st)
+
+
+def lambda_max_est(B, torch, g, mass, dims=None, iters=60, seed=4242):
+    """Largest eigenvalue of A = M^H M by power iteration through the library's
+    FP64 operator (Rayleigh quotient of the last iterate; a lower bound that
+    converges from below)."""
+    from synthetic import gaussian_rhs
+    dims = dims or LATTICE
+    p = B.eigcg_default_params(dims=dims, mass=mass, max_bank=0)
+    ctx = B.eigcg_create(p, g)
+    try:
+        v = torch.from_numpy(gaussian_rhs(dims, seed)).to("cuda:0")[None]
+        w = torch.empty_like(v)
+        lam = 0.0
+        for _ in range(iters):
+            v /= torch.linalg.vector_norm(v)
+            B.eigcg_apply(ctx, B.EIGCG_OP_A, v, w)
+            lam = float(torch.vdot(v.reshape(-1), w.reshape(-1)).real)
+            v, w = w, v
+    finally:
+        B.eigcg_destroy(ctx)
+    return lam
+
+
+CRIT_MASS = -0.61
+
+
+def critical_leg(B, torch, g, bt, xt, n_eig=N_EIG, n_defl=24, n_plain=2):
+    """The deflated workload closer to the critical mass (Section 5.4's claim
+    that deflation removes the critical slowdown): plain FP64 CG on n_plain
+    right-hand sides, then Incremental eigCG(10,100) on n_eig and init-CG on
+    n_defl at m_q = CRIT_MASS, with kappa = lambda_max / lambda_min from power
+    iteration and the bank's lowest Ritz value."""
+    log(f"critical-mass leg (mass {CRIT_MASS})")
+    dt, its, res = plain_cg(B, torch, g, CRIT_MASS, bt[n_eig:], xt[n_eig:], n_plain)
+    r = run_step(B, torch, g, CRIT_MASS, bt[:n_eig + n_defl], xt[:n_eig + n_defl], n_eig)
+    lam_max = lambda_max_est(B, torch, g, CRIT_MASS)
+    out = {"mass": CRIT_MASS, "plain_cg_iters": its, "plain_cg_s_per_rhs": dt / n_plain,
+           "plain_max_true_rel_res": res, "lambda_max": lam_max,
+           "bank_lambda_min": r["bank_lambda_min"],
+           "kappa": lam_max / r["bank_lambda_min"] if r["bank_lambda_min"] else None,
+           "phase1_iters": r["phase1_iters"],
+           "phase2_mean_iters": sum(r["phase2_iters"]) / len(r["phase2_iters"]),
+           "phase2_s_per_rhs": r["phase2_s"] / n_defl,
+           "phase2_speedup": (dt / n_plain) / (r["phase2_s"] / n_defl),
+           "max_true_rel_res": r["max_true_rel_res"], "failed": r["failed"]}
+    log(f"critical mass {CRIT_MASS}: kappa {out['kappa']:.2e}, plain CG {its} iterations, "
+        f"init-CG {out['phase2_mean_iters']:.0f} iterations, phase 2 "
+        f"{out['phase2_speedup']:.1f}x plain CG")
+    return out
 
 
 SCHUR_MASS = -0.58
@@ -948,10 +1005,15 @@ def main():
     ap.add_argument("--bicgstab-short", action="store_true",
                     help="with --bicgstab-only: one right-hand side, a bank from 4 eigCG "
                          "solves, BiCGSTAB on M only (short runs for counter collection)")
+    ap.add_argument("--no-critical", action="store_true",
+                    help="skip the critical-mass leg (m_q = -0.61)")
     ap.add_argument("--no-spectral", action="store_true",
                     help="skip the spectral preconditioning leg")
     ap.add_argument("--spectral-only", action="store_true",
                     help="only the spectral preconditioning leg (no timed steps)")
+    ap.add_argument("--restart-rule", choices=tuple(RESTART_RULE), default="fixed",
+                    help="init-CG restart threshold of the timed steps: the fixed "
+                         "10 u ||A|| or the dynamic cost model")
     ap.add_argument("--serving-only", action="store_true",
                     help="only the serving leg (no timed steps)")
     ap.add_argument("--serve-bank-rhs", type=int, default=N_EIG)
@@ -966,6 +1028,8 @@ def main():
                     help="only time the stencil, copy and CG iteration on the bench lattice "
                          "or the 24^3x48 lattice (short runs for counter collection)")
     args = ap.parse_args()
+    global restart_rule
+    restart_rule = RESTART_RULE[args.restart_rule]
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               f"(this build runs on a single MI355X)", file=sys.stderr)
@@ -1048,7 +1112,8 @@ def main():
         mass = MASSES[k]
         dt, its, res = plain_cg(B, torch, g, mass, bt[n_eig:], xt[n_eig:], args.baseline_rhs)
         base.append({"mass": mass, "s_per_rhs": dt / args.baseline_rhs, "iters": its,
-                     "max_true_rel_res": res})
+                     "max_true_rel_res": res,
+                     "lambda_max": lambda_max_est(B, torch, g, mass)})
         log(f"plain CG mass {mass}: {dt / args.baseline_rhs:.3f} s/RHS, iters {its}")
     # per-mass RHS/s of the deflated workload vs plain CG
     per_mass = []
@@ -1058,7 +1123,11 @@ def main():
         per_mass.append({"mass": s["mass"], "deflated_rhs_per_s": defl, "plain_cg_rhs_per_s": plain,
                          "speedup": defl / plain,
                          "phase2_rhs_per_s": n_defl / s["phase2_s"],
-                         "phase2_speedup": (n_defl / s["phase2_s"]) / plain})
+                         "phase2_speedup": (n_defl / s["phase2_s"]) / plain,
+                         "lambda_max": base[k]["lambda_max"],
+                         "bank_lambda_min": s["bank_lambda_min"],
+                         "kappa": (base[k]["lambda_max"] / s["bank_lambda_min"]
+                                   if s["bank_lambda_min"] else None)})
     plain_all = len(base) / sum(b["s_per_rhs"] for b in base)
 
     batching = None
@@ -1071,6 +1140,10 @@ def main():
         fixed = [s for s in steps if s["mass"] == auto["mass"]]
         if fixed:
             auto["fixed_plan_rhs_per_s"] = nrhs / (fixed[0]["phase1_s"] + fixed[0]["phase2_s"])
+
+    critical = None
+    if not args.no_critical:
+        critical = critical_leg(B, torch, g, bt, xt, n_eig=n_eig)
 
     spectral = None
     if not args.no_spectral:
@@ -1192,13 +1265,17 @@ def main():
             "lattice": list(LATTICE),
             "masses": list(MASSES),
             "rhs_per_step": nrhs,
+            "init_cg_restart": args.restart_rule,
         },
         "plain_cg_rhs_per_s": plain_all,
         "speedup_vs_plain_cg": value / plain_all,
         "per_mass": per_mass,
-        "steps_detail": [{k: v for k, v in s.items() if k not in ("phase1_iters", "phase2_iters")}
+        "steps_detail": [{k: v for k, v in s.items()
+                          if k not in ("phase1_iters", "phase2_iters", "phase2_first_leg_iters")}
                          | {"phase1_iters": s["phase1_iters"],
-                            "phase2_mean_iters": sum(s["phase2_iters"]) / len(s["phase2_iters"])}
+                            "phase2_mean_iters": sum(s["phase2_iters"]) / len(s["phase2_iters"]),
+                            "phase2_mean_first_leg_iters":
+                                sum(s["phase2_first_leg_iters"]) / len(s["phase2_first_leg_iters"])}
                          for s in steps],
         "plain_cg": base,
         "roofline": roof,
@@ -1210,6 +1287,7 @@ def main():
         "odd_even": odd_even,
         "auto_switch": auto,
         "bicgstab": bicg,
+        "critical_mass": critical,
         "spectral_preconditioning": spectral,
         "serving": serving,
         "large_lattice": large,

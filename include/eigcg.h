@@ -82,6 +82,7 @@ enum { EIGCG_FP64 = 0, EIGCG_MIXED_FP32 = 1, EIGCG_MIXED_HALF = 2 };
 enum { EIGCG_MODE_CG = 0, EIGCG_MODE_EIGCG = 1, EIGCG_MODE_INITCG = 2, EIGCG_MODE_AUTO = 3 };
 enum { EIGCG_OP_M = 0, EIGCG_OP_MDAG = 1, EIGCG_OP_A = 2, EIGCG_OP_INNER = 3 };
 enum { EIGCG_PRECOND_NONE = 0, EIGCG_PRECOND_SPECTRAL = 1 };
+enum { EIGCG_RESTART_FIXED = 0, EIGCG_RESTART_DYNAMIC = 1 };
 
 typedef struct {
   int32_t dims[4];        /* Lx, Ly, Lz, Lt; each >= 2, periodic */
@@ -134,6 +135,19 @@ typedef struct {
   double precond_sigma;   /* sigma of the spectral preconditioner (the value the
                              Ritz directions are mapped to); <= 0: the largest
                              Ritz value seen, else (8 + |m_q|)^2 */
+  int32_t restart_rule;   /* EIGCG_RESTART_FIXED: the init-CG restart threshold is
+                             restart_tol as above; EIGCG_RESTART_DYNAMIC: FP64
+                             init-CG chooses it per solve from the bank's Ritz
+                             values and residual norms (the open choice at the end
+                             of Section 5.3) with the cost model of
+                             eigcg_restart_model, lambda_max the largest Ritz value
+                             seen (else (8 + |m|)^2); the inputs are recomputed
+                             after the bank changes (l applications of A);
+                             restart_tol < 0 still disables the restart */
+  double restart_cost;    /* iterations the dynamic rule charges for one restart;
+                             <= 0: the library's estimate from algorithmic bytes
+                             (an application of A plus two passes over the l bank
+                             vectors, against one FP64 CG iteration) */
 } eigcg_params;
 
 typedef struct {
@@ -150,6 +164,9 @@ typedef struct {
   int32_t first_leg_iters;/* FP64 init-CG: iterations completed when the restart of
                              Section 5.3 re-deflated the iterate (= iters when it did
                              not restart); other schemes: iters */
+  double restart_tau;     /* FP64 init-CG: the restart threshold on ||r||/||b|| this
+                             right-hand side was given (0: no restart planned);
+                             other schemes: 0 */
 } eigcg_stats;
 
 /* Fill *p with defaults (nev 10, m 100, bank 240, FP64, batch 1, ...). */
@@ -280,6 +297,24 @@ int eigcg_bank_reset(eigcg_ctx* ctx);
  * (k >= l leaves the bank unchanged, k = 0 empties it).  Needs k fields of
  * device memory for the duration of the call.  EINVAL for k < 0. */
 int eigcg_bank_truncate(eigcg_ctx* ctx, int32_t k);
+
+/* Lock accurate eigenvectors out of U (the Section 4 discussion of lowering
+ * the cost of growing U): Rayleigh-Ritz on the unlocked columns, U_u <- U_u Y
+ * with H_u Y = Y Theta (H_u the block of H on the unlocked columns; its
+ * coupling with the locked block is zero by construction), and every Ritz
+ * vector with ||A u - theta u|| <= tol (absolute, in the bank precision) is
+ * locked.  Locked columns come first (the earlier ones, then the new ones in
+ * ascending Ritz value), the unlocked Ritz vectors follow in ascending order,
+ * and H becomes diag(Theta) on the rotated columns.  Later bank updates leave
+ * the locked rows of U^H A Vbar at zero instead of forming them (each skipped
+ * entry is r^H v, at most tol in modulus) while still orthonormalising new
+ * vectors against every column.  Needs l - nlocked fields of device memory
+ * during the call and one application of A per unlocked column.  *nlocked
+ * (may be null) receives the number of locked columns.  Truncation,
+ * restore and reset unlock everything.  EINVAL for tol < 0 or non-finite. */
+int eigcg_bank_lock(eigcg_ctx* ctx, double tol, int32_t* nlocked);
+/* Number of locked leading columns of U (>= 0), or EINVAL. */
+int eigcg_bank_locked(eigcg_ctx* ctx);
 
 /* Restore a saved bank (checkpoint / resume): U <- l fields from vecs_dev
  * (boundary layout, as eigcg_bank_vectors wrote them; stored in the bank's
@@ -436,6 +471,28 @@ int eigcg_host_chol_solve(int32_t n, const double* h, int32_t nrhs, double* b);
  * (with left > 1 and room), always 0 for left <= 1 or no room. */
 int eigcg_host_auto_continue(int32_t done, int32_t left, const double* iters, const double* secs,
                              double iter_ms, int32_t bank_room);
+/* The dynamic init-CG restart threshold (EIGCG_RESTART_DYNAMIC), the open
+ * choice at the end of Section 5.3, on given inputs: l Ritz values theta
+ * (ascending, positive) with residual norms res = ||A u - theta u||, the norm
+ * estimate lambda_max, the solve tolerance tol and the cost of one restart in
+ * iterations.  Model: with R_k the residuals of the k lowest pairs, the
+ * residual left by a Galerkin projection (eq. (2.1)) regains components along
+ * their true eigenvectors once CG has reduced it by s_k = ||R_k||_F / lambda_max
+ * (the lower end of the angle bracket [||R_k|| / lambda_max, ||R_k|| / gap_k];
+ * s_0 = 0); the bulk starts at theta_b, b = 1 + max{k : ||R_k||_F /
+ * (theta_{k+1} - theta_k) < 1}; a CG leg reducing the residual by f costs
+ * |O| + sqrt(lambda_max/theta_b)/2 (ln(2/f) + sum over the outliers
+ * O = {k'+1 .. b-1}, k' = max{k < b : s_k <= f}, of ln(lambda_max/theta_j - 1))
+ * iterations (the CG bound with outlying eigenvalues); one restart at tau
+ * costs leg(tau) + restart_cost + leg(tol/tau), constant between the break
+ * points {s_k, tol/s_k}: equal neighbouring intervals merge, the cheapest wins
+ * (then the wider in ln tau, then the larger tau), and tau is its geometric
+ * midpoint, planned only when strictly cheaper than no restart.  out[0] = tau
+ * (0: no restart), out[1] = predicted iterations without a restart, out[2] =
+ * with the planned one (= out[1] if none).  Host only; EINVAL for l < 0,
+ * unsorted or non-positive theta, or non-finite inputs. */
+int eigcg_restart_model(int32_t l, const double* theta, const double* res, double lambda_max,
+                        double tol, double restart_cost, double* out);
 
 #ifdef __cplusplus
 }

@@ -25,6 +25,7 @@ EIGCG_FP64, EIGCG_MIXED_FP32, EIGCG_MIXED_HALF = 0, 1, 2
 EIGCG_MODE_CG, EIGCG_MODE_EIGCG, EIGCG_MODE_INITCG, EIGCG_MODE_AUTO = 0, 1, 2, 3
 EIGCG_OP_M, EIGCG_OP_MDAG, EIGCG_OP_A, EIGCG_OP_INNER = 0, 1, 2, 3
 EIGCG_PRECOND_NONE, EIGCG_PRECOND_SPECTRAL = 0, 1
+EIGCG_RESTART_FIXED, EIGCG_RESTART_DYNAMIC = 0, 1
 EIGCG_BICG_GAMMA5, EIGCG_BICG_DEFLATE, EIGCG_BICG_GUESS_ONLY = 1, 2, 4
 
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "ENOTCONV", -4: "EBREAKDOWN",
@@ -53,6 +54,8 @@ class Params(ctypes.Structure):
         ("schur", ctypes.c_int32),
         ("precond", ctypes.c_int32),
         ("precond_sigma", ctypes.c_double),
+        ("restart_rule", ctypes.c_int32),
+        ("restart_cost", ctypes.c_double),
     ]
 
 
@@ -68,6 +71,7 @@ class Stats(ctypes.Structure):
         ("nritz", ctypes.c_int32),
         ("mode_used", ctypes.c_int32),
         ("first_leg_iters", ctypes.c_int32),
+        ("restart_tau", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -114,6 +118,8 @@ SIGNATURES = {
     "eigcg_last_ritz": (_I32, [_VP, _DP, _I32, ctypes.POINTER(_I32)]),
     "eigcg_bank_reset": (_I32, [_VP]),
     "eigcg_bank_truncate": (_I32, [_VP, _I32]),
+    "eigcg_bank_lock": (_I32, [_VP, ctypes.c_double, ctypes.POINTER(_I32)]),
+    "eigcg_bank_locked": (_I32, [_VP]),
     "eigcg_bank_restore": (_I32, [_VP, _I32, _VP, _DP]),
     "eigcg_memory": (_I32, [_VP, ctypes.POINTER(ctypes.c_uint64)]),
     "eigcg_last_error": (ctypes.c_char_p, [_VP]),
@@ -138,6 +144,8 @@ SIGNATURES = {
     "eigcg_host_qr": (_I32, [_I32, _I32, _DP, _DP, _DP]),
     "eigcg_host_chol_solve": (_I32, [_I32, _DP, _I32, _DP]),
     "eigcg_host_auto_continue": (_I32, [_I32, _I32, _DP, _DP, ctypes.c_double, _I32]),
+    "eigcg_restart_model": (_I32, [_I32, _DP, _DP, ctypes.c_double, ctypes.c_double,
+                                   ctypes.c_double, _DP]),
 }
 
 
@@ -423,6 +431,23 @@ def eigcg_bank_truncate(ctx, k):
         raise EigcgError(rc, eigcg_last_error(ctx))
 
 
+def eigcg_bank_lock(ctx, tol):
+    """Lock the bank's Ritz vectors with ||A u - theta u|| <= tol out of
+    building H (Section 4); returns the number of locked columns."""
+    n = _I32()
+    rc = LIB.eigcg_bank_lock(ctx, float(tol), ctypes.byref(n))
+    if rc != EIGCG_OK:
+        raise EigcgError(rc, eigcg_last_error(ctx))
+    return n.value
+
+
+def eigcg_bank_locked(ctx):
+    rc = LIB.eigcg_bank_locked(ctx)
+    if rc < 0:
+        raise EigcgError(rc, "bad context")
+    return rc
+
+
 def eigcg_bank_restore(ctx, vecs, h):
     """Restore U from l device fields and H (l x l complex, [row, col]) on the host."""
     V, _ = _geom(ctx)
@@ -625,3 +650,20 @@ def eigcg_host_auto_continue(iters, secs, left, iter_ms, bank_room):
     if rc < 0:
         raise EigcgError(rc, "bad arguments")
     return rc == 1
+
+
+def eigcg_restart_model(theta, res, lambda_max, tol, restart_cost):
+    """The dynamic init-CG restart threshold on given Ritz values (ascending)
+    and residual norms: ``(tau, iterations without, iterations with)``, tau = 0
+    for no restart."""
+    th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))
+    rs = np.ascontiguousarray(np.asarray(res, dtype=np.float64))
+    if th.shape != rs.shape or th.ndim != 1:
+        raise ValueError("theta and res must be 1-D of one length")
+    out = np.zeros(3)
+    rc = LIB.eigcg_restart_model(th.size, th.ctypes.data_as(_DP), rs.ctypes.data_as(_DP),
+                                 float(lambda_max), float(tol), float(restart_cost),
+                                 out.ctypes.data_as(_DP))
+    if rc != EIGCG_OK:
+        raise EigcgError(rc, "bad restart-model inputs")
+    return float(out[0]), float(out[1]), float(out[2])

@@ -80,6 +80,12 @@ int validate(const eigcg_params* p, std::string& why) {
     return EIGCG_EINVAL;
   }
   if (!std::isfinite(p->precond_sigma)) { why = "precond_sigma not finite"; return EIGCG_EINVAL; }
+  if (p->restart_rule != EIGCG_RESTART_FIXED && p->restart_rule != EIGCG_RESTART_DYNAMIC) {
+    why = "bad restart_rule";
+    return EIGCG_EINVAL;
+  }
+  if (!std::isfinite(p->restart_cost)) { why = "restart_cost not finite"; return EIGCG_EINVAL; }
+  if (!std::isfinite(p->restart_tol)) { why = "restart_tol not finite"; return EIGCG_EINVAL; }
   return EIGCG_OK;
 }
 
@@ -294,6 +300,22 @@ int eigcg_bank_truncate(eigcg_ctx* ctx, int32_t k) {
   });
 }
 
+int eigcg_bank_lock(eigcg_ctx* ctx, double tol, int32_t* nlocked) {
+  if (!ctx) return EIGCG_EINVAL;
+  if (!(tol >= 0.0) || !std::isfinite(tol))
+    return fail(ctx, EIGCG_EINVAL, "lock tolerance must be finite and >= 0");
+  return guarded(ctx, [&] {
+    const int n = eigcg::bank_lock(ctx->c, tol);
+    if (nlocked) *nlocked = n;
+    return EIGCG_OK;
+  });
+}
+
+int eigcg_bank_locked(eigcg_ctx* ctx) {
+  if (!ctx) return EIGCG_EINVAL;
+  return ctx->c.nlock;
+}
+
 int eigcg_bank_restore(eigcg_ctx* ctx, int32_t l, const void* vecs_dev, const double* h_host) {
   if (!ctx) return EIGCG_EINVAL;
   if (l < 0 || (l > 0 && (!vecs_dev || !h_host))) return fail(ctx, EIGCG_EINVAL, "bad arguments");
@@ -306,8 +328,10 @@ int eigcg_bank_restore(eigcg_ctx* ctx, int32_t l, const void* vecs_dev, const do
 int eigcg_bank_reset(eigcg_ctx* ctx) {
   if (!ctx) return EIGCG_EINVAL;
   ctx->c.l = 0;
+  ctx->c.nlock = 0;
   ctx->c.chol_ok = false;
   ctx->c.spec_ok = false;
+  ++ctx->c.bank_gen;
   return EIGCG_OK;
 }
 
@@ -438,6 +462,23 @@ int eigcg_host_auto_continue(int32_t done, int32_t left, const double* iters, co
                              double iter_ms, int32_t bank_room) {
   if (done < 0 || (done > 0 && (!iters || !secs))) return EIGCG_EINVAL;
   return eigcg::auto_continue(done, left, iters, secs, iter_ms, bank_room) ? 1 : 0;
+}
+
+int eigcg_restart_model(int32_t l, const double* theta, const double* res, double lambda_max,
+                        double tol, double restart_cost, double* out) {
+  if (l < 0 || !out || (l > 0 && (!theta || !res))) return EIGCG_EINVAL;
+  if (!(lambda_max > 0.0) || !std::isfinite(lambda_max) || !(tol > 0.0) || !(tol < 1.0) ||
+      !std::isfinite(restart_cost))
+    return EIGCG_EINVAL;
+  for (int i = 0; i < l; ++i) {
+    if (!std::isfinite(theta[i]) || !std::isfinite(res[i]) || res[i] < 0.0) return EIGCG_EINVAL;
+    if (!(theta[i] > 0.0) || (i > 0 && theta[i] < theta[i - 1])) return EIGCG_EINVAL;
+  }
+  const eigcg::RestartPick r = eigcg::restart_model(l, theta, res, lambda_max, tol, restart_cost);
+  out[0] = r.tau;
+  out[1] = r.cost_none;
+  out[2] = r.cost_with;
+  return EIGCG_OK;
 }
 
 }  // extern "C"

@@ -135,6 +135,8 @@ static size_t elem_bytes(int prec) { return prec == kF64 ? 16 : (prec == kF32 ? 
 
 static void ws_ensure(Ctx& c, Workspace& w, int prec, bool eig, int keig = 0);
 static StencilLaunch stencil_base(Ctx& c, int prec);
+static void bank_ritz_residuals(Ctx& c, int j0, int n, const std::vector<double>& th,
+                                const std::vector<cplx>& Y, double* res);
 
 // Stencil autotuner: times every kernel variant (the search space: site
 // mapping and sweep order, workgroups per CU, z-march chunking) and, for the
@@ -1686,6 +1688,105 @@ struct Driver {
   }
 };
 
+// ---------------------------------------------------------------------------
+// Dynamic init-CG restart threshold.  Section 5.3 restarts once near machine
+// precision and leaves open a threshold chosen from the bank's Ritz values and
+// residual norms, trading the condition number that re-deflation restores
+// against the cost of restarting.  The rule taken here is a cost model:
+//  * contamination: with R_k the residuals of the k lowest Ritz pairs, the sine
+//    of the angle between their span and the true invariant subspace lies
+//    between ||R_k|| / lambda_max and the Davis-Kahan bound ||R_k|| / gap_k;
+//    after a Galerkin projection, eq. (2.1), the residual's components along
+//    those eigenvectors are at most that fraction of it, usually far less since
+//    a Ritz vector's error spreads over the spectrum.  The model takes the
+//    lower end, s_k = ||R_k||_F / lambda_max (s_0 = 0): those directions
+//    reappear once CG has reduced the residual by s_k, which is also Section
+//    5.3's observation that Ritz vectors keep deflating down to their own
+//    residual norm scaled by the norm of A;
+//  * bulk: the span is resolved while ||R_k||_F / (theta_{k+1} - theta_k) < 1;
+//    b = 1 + the largest such k, kappa = lambda_max / theta_b;
+//  * a leg that reduces the residual by f keeps the lowest
+//    k'(f) = max{k < b : s_k <= f} directions deflated; the others are outlying
+//    eigenvalues in the CG bound:
+//    n(f) = |O| + sqrt(kappa)/2 (ln(2/f) + sum_O ln(lambda_max/theta_j - 1));
+//  * one restart at tau costs n(tau) + R + n(tol/tau), which is constant
+//    between the break points {s_k, tol/s_k}; equal neighbours merge, the
+//    cheapest interval wins (then the wider in ln tau, then the larger tau),
+//    tau is its geometric midpoint, and the restart is planned only when it is
+//    strictly cheaper than n(tol).
+// ---------------------------------------------------------------------------
+namespace {
+
+struct LegModel {
+  const double* th = nullptr;
+  std::vector<double> s;
+  int b = 1;
+  double lam_max = 0.0;
+  double cost(double f) const {
+    int kp = 0;
+    for (int k = 0; k < b; ++k)
+      if (s[k] <= f) kp = k;
+    const double kappa = lam_max / th[b - 1];
+    double extra = 0.0;
+    for (int j = kp + 1; j < b; ++j) extra += std::log(std::max(lam_max / th[j - 1] - 1.0, 1.0));
+    return (double)(b - 1 - kp) + 0.5 * std::sqrt(kappa) * (std::log(2.0 / f) + extra);
+  }
+};
+
+}  // namespace
+
+RestartPick restart_model(int l, const double* theta, const double* res, double lam_max,
+                          double tol, double restart_cost) {
+  RestartPick out{0.0, 0.0, 0.0};
+  if (l <= 0) return out;
+  LegModel m;
+  m.th = theta;
+  m.lam_max = lam_max;
+  m.s.assign(l, 0.0);
+  for (int k = 1; k < l; ++k) {
+    double acc = 0.0;
+    for (int j = 0; j < k; ++j) acc += res[j] * res[j];
+    const double rk = std::sqrt(acc);
+    m.s[k] = rk / lam_max;
+    const double gap = theta[k] - theta[k - 1];
+    if (gap > 0.0 && rk / gap < 1.0) m.b = k + 1;
+  }
+  const double none = m.cost(tol);
+  std::vector<double> pts{tol, 1.0};
+  for (int k = 1; k < l; ++k) {
+    const double cand[2] = {m.s[k], m.s[k] > 0.0 ? tol / m.s[k] : 0.0};
+    for (double p : cand)
+      if (tol < p && p < 1.0) pts.push_back(p);
+  }
+  std::sort(pts.begin(), pts.end());
+  pts.erase(std::unique(pts.begin(), pts.end()), pts.end());
+  struct Iv { double lo, hi, c; };
+  std::vector<Iv> merged;
+  for (size_t i = 0; i + 1 < pts.size(); ++i) {
+    const double lo = pts[i], hi = pts[i + 1];
+    const double mid = std::sqrt(lo * hi);
+    const double c = m.cost(mid) + restart_cost + m.cost(tol / mid);
+    if (!merged.empty() && std::fabs(merged.back().c - c) <= 1e-12 * std::max(1.0, std::fabs(c)))
+      merged.back().hi = hi;
+    else
+      merged.push_back({lo, hi, c});
+  }
+  const Iv* best = nullptr;
+  for (const Iv& v : merged) {
+    if (!best) { best = &v; continue; }
+    const double wv = -std::log(v.hi / v.lo), wb = -std::log(best->hi / best->lo);
+    if (v.c < best->c || (v.c == best->c && (wv < wb || (wv == wb && -v.hi < -best->hi))))
+      best = &v;
+  }
+  out.cost_none = none;
+  out.cost_with = none;
+  if (best && best->c < none) {
+    out.tau = std::sqrt(best->lo * best->hi);
+    out.cost_with = best->c;
+  }
+  return out;
+}
+
 namespace {
 
 void check_finite(const std::vector<double>& v) {
@@ -1708,20 +1809,70 @@ int scheme_for(const Ctx& c, int mode) {
   return mode == EIGCG_MODE_INITCG ? kSchemeRefine : kSchemeReliable;
 }
 
-double restart_tol_for(const Ctx& c, int mode, int scheme) {
+// Section 5.3's fixed threshold: within an order of magnitude of machine
+// precision scaled by the norm of A.  The paper's runs are in single precision
+// (Section 5.1) and its convergence figure restarts close to single machine
+// precision, which is where a bank of Ritz vectors of that accuracy stops
+// deflating: 10 u ||A|| with u = 2^-24, ||A|| estimated by the largest Ritz
+// value seen (or (8+|m|)^2)
+double anorm_estimate(const Ctx& c) {
+  const double am = std::fabs(c.P.mass);
+  return c.amax > 0 ? c.amax : (8.0 + am) * (8.0 + am);
+}
+
+double fixed_restart_tol(const Ctx& c) { return 10.0 * 5.9604644775390625e-8 * anorm_estimate(c); }
+
+// Iterations one init-CG restart costs, from algorithmic bytes per site: the
+// restart recomputes r = b - A x (one application of A), forms U^H r and
+// x += U y (two passes over the l bank columns) and touches x, r and b; one
+// FP64 CG iteration is an application of A (two stencil passes: spinor in and
+// out, four links) plus its BLAS passes (nine spinors).
+double restart_cost_estimate(const Ctx& c) {
+  const double vec = 192.0;
+  const double vbank = c.bank_prec == kF64 ? 192.0 : 96.0;
+  const double links = c.comp64 ? 4.0 * 96.0 : 4.0 * 144.0;
+  const double apply_a = 2.0 * (2.0 * vec + links);
+  const double iteration = apply_a + 9.0 * vec;
+  const double restart = apply_a + 2.0 * c.l * vbank + 4.0 * vec;
+  return restart / iteration;
+}
+
+// Ritz values and residual norms of the bank, recomputed when U or H changed
+// (l applications of A).  Uses the bank-precision workspace: call only while no
+// solve holds live columns in it.
+void ensure_restart_inputs(Ctx& c) {
+  if (c.rm_gen == c.bank_gen) return;
+  const int l = c.l, ld = c.P.max_bank;
+  c.rm_theta.assign(l, 0.0);
+  c.rm_res.assign(l, 0.0);
+  if (l > 0) {
+    std::vector<cplx> Y((size_t)l * l);
+    if (hostla::herm_eig_lowest(l, c.H.data(), ld, l, c.rm_theta.data(), Y.data(), l) != 0)
+      throw ApiError{EIGCG_EBREAKDOWN, "bank eigensolver failed"};
+    bank_ritz_residuals(c, 0, l, c.rm_theta, Y, c.rm_res.data());
+  }
+  c.rm_gen = c.bank_gen;
+}
+
+double restart_tol_for(Ctx& c, int mode, int scheme, double tol, bool may_compute) {
   if (scheme == kSchemeRefine)
     return c.P.restart_tol > 0 ? c.P.restart_tol
                                : (c.P.precision == EIGCG_MIXED_HALF ? kRefineRelHalf : kRefineRel);
   if (mode != EIGCG_MODE_INITCG || c.P.restart_tol < 0) return 0.0;
+  if (c.P.restart_rule == EIGCG_RESTART_DYNAMIC) {
+    if (c.l < 2) return 0.0;
+    if (c.rm_gen != c.bank_gen) {
+      if (!may_compute)
+        throw ApiError{EIGCG_EINVAL, "internal: restart-model inputs are stale inside a session"};
+      ensure_restart_inputs(c);
+    }
+    if (!(c.rm_theta[0] > 0.0)) return fixed_restart_tol(c);  // H not numerically SPD
+    const double cost = c.P.restart_cost > 0 ? c.P.restart_cost : restart_cost_estimate(c);
+    return restart_model(c.l, c.rm_theta.data(), c.rm_res.data(), anorm_estimate(c), tol, cost)
+        .tau;
+  }
   if (c.P.restart_tol > 0) return c.P.restart_tol;
-  // Section 5.3: within an order of magnitude of machine precision scaled by
-  // the norm of A.  The paper's runs are in single precision (Section 5.1) and
-  // its convergence figure restarts close to single machine precision, which is
-  // where a bank of Ritz vectors of that accuracy stops deflating: 10 u ||A||
-  // with u = 2^-24, ||A|| estimated by the largest Ritz value seen (or (8+|m|)^2)
-  const double am = std::fabs(c.P.mass);
-  const double anorm = c.amax > 0 ? c.amax : (8.0 + am) * (8.0 + am);
-  return 10.0 * 5.9604644775390625e-8 * anorm;
+  return fixed_restart_tol(c);
 }
 
 }  // namespace
@@ -1855,15 +2006,19 @@ int bank_append_from(Ctx& c, const void* src, int nsrc) {
               "to f32");
     }
   }
-  std::vector<const void*> all(l + kept), wc(kept);
-  for (int i = 0; i < l + kept; ++i) all[i] = col_ptr(c.U, prec, c.cs, i);
+  // locked columns (Section 4) take no part: their rows of U^H W stay zero
+  const int nl = std::min(c.nlock, l);
+  const int na = l + kept - nl;
+  std::vector<const void*> all(na), wc(kept);
+  for (int i = 0; i < na; ++i) all[i] = col_ptr(c.U, prec, c.cs, nl + i);
   for (int q = 0; q < kept; ++q) wc[q] = col_ptr(W, prec, c.cs, q);
   std::vector<cplx> G2;
-  reduce_to_host(c, prec, l + kept, kept, all, wc, G2);
+  reduce_to_host(c, prec, na, kept, all, wc, G2);
   const int ld = c.P.max_bank;
   for (int q = 0; q < kept; ++q) {
     for (int i = 0; i < l + kept; ++i) {
-      const cplx v = G2[(size_t)q * (l + kept) + i];  // (U Vbar)_i^H A vbar_q
+      // (U Vbar)_i^H A vbar_q
+      const cplx v = i < nl ? cplx(0.0, 0.0) : G2[(size_t)q * na + (i - nl)];
       c.H[(size_t)(l + q) * ld + i] = v;
       if (i < l) c.H[(size_t)i * ld + (l + q)] = std::conj(v);
     }
@@ -1888,6 +2043,7 @@ int bank_append_from(Ctx& c, const void* src, int nsrc) {
   c.l = l + kept;
   c.chol_ok = false;
   c.spec_ok = false;
+  ++c.bank_gen;
   return kept;
 }
 
@@ -1967,7 +2123,11 @@ bool auto_continue(int done, int left, const double* iters, const double* secs, 
 // deflation (the stencil and both products treat columns independently).
 // Returns false, having changed nothing, when the group workspace cannot be
 // allocated.
-static bool batched_guess(Ctx& c, int first, int count, const void* b_aos, void* x_aos) {
+// The FP64 workspace of several columns at once (b, x, r, tmp; up to kMaxCols
+// columns, fewer when memory is short), allocated on first use; in an odd-even
+// context the operator's intermediate grows to its width.  False when not even
+// two columns fit.
+static bool ensure_wsg(Ctx& c) {
   Workspace& g = c.wsg;
   if (g.K == 0) {
     const size_t vb = c.cs * 16;
@@ -1998,6 +2158,14 @@ static bool batched_guess(Ctx& c, int first, int count, const void* b_aos, void*
     c.eo_tmp64 = t;
     c.eo_cols64 = (size_t)g.K;
   }
+  return true;
+}
+
+// FP64 init-CG guesses, eq. (2.1), for count right-hand sides from first, a
+// group of workspace columns per pass over U
+static bool batched_guess(Ctx& c, int first, int count, const void* b_aos, void* x_aos) {
+  if (!ensure_wsg(c)) return false;
+  Workspace& g = c.wsg;
   std::vector<ColState> st(kMaxCols);
   std::memset(st.data(), 0, sizeof(ColState) * kMaxCols);
   for (auto& s : st) s.state = ColStopped;
@@ -2064,7 +2232,7 @@ int solve(Ctx& c, int nrhs, const void* b_aos, void* x_aos, double tol, int mode
     if (gmode == EIGCG_MODE_INITCG && scheme == kSchemeF64 && c.l > 0 && c0 < guessed_from &&
         nrhs - c0 > w.K && batched_guess(c, c0, nrhs - c0, b_aos, x_aos))
       guessed_from = c0;
-    const double rtol = restart_tol_for(c, gmode, scheme);
+    const double rtol = restart_tol_for(c, gmode, scheme, tol, true);
     const double t0 = now_s();
     const double2* bsrc = (const double2*)b_aos + (size_t)c0 * 12 * c.g.V;
     double2* xdst = (double2*)x_aos + (size_t)c0 * 12 * c.g.V;
@@ -2144,6 +2312,7 @@ int solve(Ctx& c, int nrhs, const void* b_aos, void* x_aos, double tol, int mode
         s.nritz = eig ? D.R.ec[j].nritz : 0;
         s.mode_used = gmode;
         s.first_leg_iters = D.R.first_leg[j] >= 0 ? D.R.first_leg[j] : D.R.iters[j];
+        s.restart_tau = scheme == kSchemeF64 && gmode == EIGCG_MODE_INITCG ? rtol : 0.0;
       }
     }
   }
@@ -2160,7 +2329,7 @@ struct Session {
   int K;
   std::vector<int> active;
   std::vector<uint64_t> tag;
-  std::vector<double> tol, bn2, t_admit;
+  std::vector<double> tol, bn2, t_admit, rtau;
   std::vector<void*> xdst;
   Session(Ctx& c_, Workspace& w, Workspace& w64, int prec, int scheme)
       : c(c_), D(c_, w, w64, prec, c_.P.max_batch, false, scheme), K(c_.P.max_batch) {
@@ -2169,6 +2338,7 @@ struct Session {
     tol.assign(K, 0.0);
     bn2.assign(K, 0.0);
     t_admit.assign(K, 0.0);
+    rtau.assign(K, 0.0);
     xdst.assign(K, nullptr);
   }
 };
@@ -2179,6 +2349,11 @@ Session* session_open(Ctx& c) {
   ws_ensure(c, c.ws64, kF64, false);
   if (mixed) ws_ensure(c, c.ws32, c.iprec, false);
   ensure_spectral(c);
+  // the dynamic restart rule reads the bank's Ritz pairs, computed here while
+  // no request holds workspace columns (the bank is fixed while the session lives)
+  if (c.P.restart_rule == EIGCG_RESTART_DYNAMIC && c.P.restart_tol >= 0 &&
+      scheme_for(c, EIGCG_MODE_INITCG) == kSchemeF64 && c.l >= 2)
+    ensure_restart_inputs(c);
   Session* s = new Session(c, mixed ? c.ws32 : c.ws64, c.ws64, prec,
                            scheme_for(c, EIGCG_MODE_INITCG));
   std::vector<ColState> idle(s->K);
@@ -2236,7 +2411,9 @@ int session_admit(Session* s, const void* b_aos, void* x_aos, double tol, uint64
   s->xdst[j] = x_aos;
   s->t_admit[j] = now_s();
   try {
-    s->D.start_columns(1u << j, bn2, tol, restart_tol_for(c, EIGCG_MODE_INITCG, s->D.scheme), true);
+    const double rtol = restart_tol_for(c, EIGCG_MODE_INITCG, s->D.scheme, tol, false);
+    s->rtau[j] = s->D.scheme == kSchemeF64 ? rtol : 0.0;
+    s->D.start_columns(1u << j, bn2, tol, rtol, true);
   } catch (...) {
     // the slot stays free and idle; the caller reports the request as failed
     std::vector<ColState> idle(s->K);
@@ -2278,6 +2455,7 @@ void session_step(Session* s, std::vector<SessionDone>& done) {
     d.iters = s->D.R.iters[j];
     d.outer = s->D.R.outer[j];
     d.first_leg = s->D.R.first_leg[j] >= 0 ? s->D.R.first_leg[j] : s->D.R.iters[j];
+    d.restart_tau = s->rtau[j];
     d.true_rel_res = res[j];
     done.push_back(d);
     s->active[j] = 0;
@@ -2327,6 +2505,46 @@ void deflate_init(Ctx& c, int nrhs, const void* b_aos, void* x_aos) {
   c.check(hipStreamSynchronize(c.stream), "sync");
 }
 
+// Residual norms ||A u_q - theta_q u_q|| of the Ritz vectors u_q = U_n y_q of
+// the n bank columns U_n = U[:, j0 : j0 + n] (Y column-major, n x n), in the
+// bank precision, a workspace-width block of Ritz vectors per pass over U_n.
+static void bank_ritz_residuals(Ctx& c, int j0, int n, const std::vector<double>& th,
+                                const std::vector<cplx>& Y, double* res) {
+  const int prec = c.bank_prec;
+  // an FP64 bank uses the wide FP64 workspace (up to kMaxCols Ritz vectors per
+  // pass over U_n) when it exists or the context's own is narrower than four
+  // columns; otherwise the bank-precision workspace, where a 16-bit inner
+  // workspace holds half as many FP32 fields per buffer
+  Workspace* wp = nullptr;
+  int wide = 0;
+  if (prec == kF64 && (c.wsg.K > 0 || c.P.max_batch < 4) && ensure_wsg(c)) {
+    wp = &c.wsg;
+    wide = c.wsg.K;
+  } else {
+    wp = prec == kF64 ? &c.ws64 : &c.ws32;
+    ws_ensure(c, *wp, prec, false);
+    wide = wp->prec == prec ? wp->K : wp->K / 2;
+  }
+  Workspace& w = *wp;
+  const int kb = std::max(1, std::min(wide, n));
+  std::vector<const void*> in(n);
+  for (int i = 0; i < n; ++i) in[i] = col_ptr(c.U, prec, c.cs, j0 + i);
+  for (int q0 = 0; q0 < n; q0 += kb) {
+    const int nq = std::min(kb, n - q0);
+    std::vector<void*> out(nq);
+    for (int j = 0; j < nq; ++j) out[j] = col_ptr(w.x, prec, c.cs, j);
+    tall_from_host(c, prec, n, nq, in, out, Y.data() + (size_t)q0 * n, 0, 0);
+    stencil_store(c, prec, kOpM, nq, w.x, w.tmp);
+    stencil_store(c, prec, kOpMdag, nq, w.tmp, w.r);
+    for (int j = 0; j < nq; ++j)
+      c.check(launch_axpy(prec, 1, c.cs, nullptr, -th[q0 + j], 0.0, col_ptr(w.x, prec, c.cs, j),
+                          c.cs, col_ptr(w.r, prec, c.cs, j), c.cs, c.stream),
+              "axpy");
+    std::vector<double> nn = col_norms(c, prec, nq, w.r);
+    for (int j = 0; j < nq; ++j) res[q0 + j] = std::sqrt(nn[j]);
+  }
+}
+
 void bank_info(Ctx& c, int* l_out, double* vals, double* res) {
   const int l = c.l, ld = c.P.max_bank;
   *l_out = l;
@@ -2337,23 +2555,7 @@ void bank_info(Ctx& c, int* l_out, double* vals, double* res) {
                               l) != 0)
     throw ApiError{EIGCG_EBREAKDOWN, "bank eigensolver failed"};
   for (int i = 0; i < l; ++i) vals[i] = th[i];
-  if (!res) return;
-  // residuals ||A U y - theta U y|| in the bank precision
-  const int prec = c.bank_prec;
-  Workspace& w = prec == kF64 ? c.ws64 : c.ws32;
-  ws_ensure(c, w, prec, false);
-  std::vector<const void*> in(l);
-  for (int i = 0; i < l; ++i) in[i] = col_ptr(c.U, prec, c.cs, i);
-  for (int q = 0; q < l; ++q) {
-    std::vector<void*> out(1, w.x);
-    tall_from_host(c, prec, l, 1, in, out, Y.data() + (size_t)q * l, 0, 0);
-    stencil_store(c, prec, kOpM, 1, w.x, w.tmp);
-    stencil_store(c, prec, kOpMdag, 1, w.tmp, w.r);
-    c.check(launch_axpy(prec, 1, c.cs, nullptr, -th[q], 0.0, w.x, c.cs, w.r, c.cs, c.stream),
-            "axpy");
-    std::vector<double> n = col_norms(c, prec, 1, w.r);
-    res[q] = std::sqrt(n[0]);
-  }
+  if (res) bank_ritz_residuals(c, 0, l, th, Y, res);
 }
 
 int bank_load(Ctx& c, int count, const void* vecs_aos) {
@@ -2378,8 +2580,10 @@ void bank_truncate(Ctx& c, int k) {
   if (k >= c.l) return;
   if (k == 0) {
     c.l = 0;
+    c.nlock = 0;
     c.chol_ok = false;
     c.spec_ok = false;
+    ++c.bank_gen;
     return;
   }
   const int l = c.l, ld = c.P.max_bank, prec = c.bank_prec;
@@ -2404,8 +2608,72 @@ void bank_truncate(Ctx& c, int k) {
   std::fill(c.H.begin(), c.H.end(), cplx(0.0, 0.0));
   for (int i = 0; i < k; ++i) c.H[(size_t)i * ld + i] = cplx(th[i], 0.0);
   c.l = k;
+  c.nlock = 0;
   c.chol_ok = false;
   c.spec_ok = false;
+  ++c.bank_gen;
+}
+
+// Section 4: lock accurate eigenvectors out of U so that they take no part in
+// building H.  Rayleigh-Ritz on the unlocked columns (their coupling with the
+// locked block is zero by construction), H_u Y = Y Theta and U_u <- U_u Y; the
+// Ritz vectors with ||A u - theta u|| <= tol are locked.  Locked columns come
+// first (the earlier ones, then the new ones in ascending Ritz value), the
+// unlocked Ritz vectors follow in ascending order, and H becomes diag(theta)
+// on every rotated column.  Bank updates then leave the locked rows of
+// U^H A Vbar at zero: each skipped entry is r^H v for a locked residual r and
+// a new v orthogonal to it, at most tol in modulus.
+int bank_lock(Ctx& c, double tol) {
+  if (!(tol >= 0.0) || !std::isfinite(tol))
+    throw ApiError{EIGCG_EINVAL, "lock tolerance must be finite and >= 0"};
+  const int l = c.l, nl = c.nlock, n = l - nl, ld = c.P.max_bank, prec = c.bank_prec;
+  if (n <= 0) return nl;
+  std::vector<cplx> Hu((size_t)n * n);
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) Hu[(size_t)j * n + i] = c.H[(size_t)(nl + j) * ld + nl + i];
+  std::vector<double> th(n);
+  std::vector<cplx> Y((size_t)n * n);
+  if (hostla::herm_eig_lowest(n, Hu.data(), n, n, th.data(), Y.data(), n) != 0)
+    throw ApiError{EIGCG_EBREAKDOWN, "bank eigensolver failed"};
+  std::vector<double> res(n);
+  bank_ritz_residuals(c, nl, n, th, Y, res.data());
+  std::vector<int> order;
+  for (int j = 0; j < n; ++j)
+    if (res[j] <= tol) order.push_back(j);
+  const int nnew = (int)order.size();
+  for (int j = 0; j < n; ++j)
+    if (!(res[j] <= tol)) order.push_back(j);
+  std::vector<cplx> Yp((size_t)n * n);
+  for (int q = 0; q < n; ++q)
+    std::copy(Y.begin() + (size_t)order[q] * n, Y.begin() + (size_t)(order[q] + 1) * n,
+              Yp.begin() + (size_t)q * n);
+  void* tmp = c.dalloc(c.cs * elem_bytes(prec) * (size_t)n);
+  try {
+    std::vector<const void*> in(n);
+    for (int i = 0; i < n; ++i) in[i] = col_ptr(c.U, prec, c.cs, nl + i);
+    std::vector<void*> out(n);
+    for (int j = 0; j < n; ++j) out[j] = col_ptr(tmp, prec, c.cs, j);
+    tall_from_host(c, prec, n, n, in, out, Yp.data(), 0, 0);
+    c.check(launch_copy(prec, prec, n, c.cs, tmp, c.cs, col_ptr(c.U, prec, c.cs, nl), c.cs,
+                        c.stream),
+            "copy");
+    c.check(hipStreamSynchronize(c.stream), "sync");
+  } catch (...) {
+    c.dfree(tmp);
+    throw;
+  }
+  c.dfree(tmp);
+  for (int j = nl; j < l; ++j)
+    for (int i = 0; i < l; ++i) {
+      c.H[(size_t)j * ld + i] = cplx(0.0, 0.0);
+      c.H[(size_t)i * ld + j] = cplx(0.0, 0.0);
+    }
+  for (int q = 0; q < n; ++q) c.H[(size_t)(nl + q) * ld + nl + q] = cplx(th[order[q]], 0.0);
+  c.nlock = nl + nnew;
+  c.chol_ok = false;
+  c.spec_ok = false;
+  ++c.bank_gen;
+  return c.nlock;
 }
 
 // Restore a saved bank: U <- the given fields (in the bank's precision) and
@@ -2432,8 +2700,10 @@ void bank_restore(Ctx& c, int l, const void* vecs_aos, const double* h_host) {
   c.check(hipStreamSynchronize(c.stream), "sync");
   c.H = Hn;
   c.l = l;
+  c.nlock = 0;
   c.chol_ok = false;
   c.spec_ok = false;
+  ++c.bank_gen;
 }
 
 void bank_vectors(Ctx& c, int first, int count, void* out_aos) {

@@ -74,6 +74,12 @@ struct Ctx {
   std::vector<cplx> L;    // Cholesky factor of H(0:l, 0:l)
   bool chol_ok = false;
   double amax = 0.0;      // largest Ritz value seen (norm of A estimate)
+  int nlock = 0;          // leading columns of U locked out of building H (Section 4)
+  uint64_t bank_gen = 0;  // bumped whenever U or H changes
+  // Ritz values of the bank and their residual norms ||A u - theta u|| for the
+  // dynamic init-CG restart threshold, valid while rm_gen == bank_gen
+  uint64_t rm_gen = ~0ull;
+  std::vector<double> rm_theta, rm_res;
   // spectral preconditioner P^{-1} = I + U_R D U_R^H (params.precond): the
   // bank in its Ritz basis, D = sigma / theta - 1, device staging of U_R^H r,
   // D U_R^H r and r^H U_R D U_R^H r per column
@@ -143,7 +149,15 @@ void schur_reconstruct(Ctx& c, int nrhs, const void* b_full, const void* x_even,
 int solve(Ctx& c, int nrhs, const void* b_aos, void* x_aos, double tol, int mode,
           eigcg_stats* stats);
 void deflate_init(Ctx& c, int nrhs, const void* b_aos, void* x_aos);
+// Dynamic init-CG restart threshold from ascending Ritz values and their
+// residual norms (host only): tau = 0 means no restart.
+struct RestartPick {
+  double tau, cost_none, cost_with;
+};
+RestartPick restart_model(int l, const double* theta, const double* res, double lam_max,
+                          double tol, double restart_cost);
 void bank_info(Ctx& c, int* l, double* vals, double* res);
+int bank_lock(Ctx& c, double tol);
 void bank_vectors(Ctx& c, int first, int count, void* out_aos);
 int bank_load(Ctx& c, int count, const void* vecs_aos);
 void bank_truncate(Ctx& c, int k);
@@ -184,6 +198,7 @@ struct SessionDone {
   int iters;
   int outer;
   int first_leg;  // iterations before the first init-CG restart (= iters when none)
+  double restart_tau;  // the FP64 init-CG restart threshold it was given (0: none)
   double true_rel_res;
 };
 Session* session_open(Ctx& c);

@@ -108,6 +108,7 @@ struct eigcg_server {
       r.st.iters = d.iters;
       r.st.outer_steps = d.outer;
       r.st.first_leg_iters = d.first_leg;
+      r.st.restart_tau = d.restart_tau;
       r.st.true_rel_res = d.true_rel_res;
       r.st.seconds = t - r.t_submit;
       --outstanding;
@@ -162,6 +163,7 @@ struct eigcg_server {
     d.iters = st.iters;
     d.outer = st.outer_steps;
     d.first_leg = st.first_leg_iters;
+    d.restart_tau = st.restart_tau;
     d.true_rel_res = st.true_rel_res;
     complete({d});
   }

@@ -50,7 +50,8 @@ def test_default_params_and_validation(B):
                 dict(mass=float("nan")), dict(nev=0), dict(schur=2),
                 dict(schur=1, dims=(4, 4, 3, 4)), dict(stencil_variant=14),
                 dict(sample_every=-1), dict(nev=16, m=257), dict(precond=2),
-                dict(precond=1, precision=1), dict(precond_sigma=float("inf"))]:
+                dict(precond=1, precision=1), dict(precond_sigma=float("inf")),
+                dict(restart_rule=2), dict(restart_cost=float("nan"))]:
         q = B.eigcg_default_params(**bad)
         rc = B.LIB.eigcg_create(ctypes.byref(q), fake, None, ctypes.byref(ctx))
         assert rc == B.EIGCG_EINVAL, bad
@@ -61,6 +62,8 @@ def test_default_params_and_validation(B):
     for fn, args in [("eigcg_schur_rhs", (None, 1, None, None)),
                      ("eigcg_schur_reconstruct", (None, 1, None, None, None)),
                      ("eigcg_bank_truncate", (None, 1)),
+                     ("eigcg_bank_lock", (None, 1e-6, None)),
+                     ("eigcg_bank_locked", (None,)),
                      ("eigcg_bank_restore", (None, 1, None, None)),
                      ("eigcg_solve_bicgstab", (None, 1, None, None, 1e-10, 0, 0, None))]:
         assert getattr(B.LIB, fn)(*args) == B.EIGCG_EINVAL, fn
@@ -342,3 +345,43 @@ def test_bounds_layer_refuses_accesses_past_an_allocation(B):
         assert B.eigcg_debug_span(1, base) == B.EIGCG_OK
         assert B.eigcg_debug_span(1, nxt) == B.EIGCG_OK
     assert B.eigcg_debug_span(1, base) == B.EIGCG_EINVAL  # already removed
+
+
+def _restart_inputs(seed):
+    rng = np.random.default_rng(seed)
+    l = int(rng.integers(2, 40))
+    theta = np.sort(np.concatenate([10.0 ** rng.uniform(-4, -2, l // 3),
+                                    10.0 ** rng.uniform(-1, 0.5, l - l // 3)]))
+    res = 10.0 ** rng.uniform(-10, -1, l)
+    return theta, res, float(rng.uniform(20, 80)), 10.0 ** -rng.uniform(6, 12), float(rng.uniform(0, 60))
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_restart_model_matches_oracle(B, seed):
+    """The library's dynamic restart threshold (host logic) against the
+    oracle's cost model on seeded inputs: same threshold and predicted
+    iteration counts to rounding."""
+    from oracle.restart_model import choose_restart
+    theta, res, lam_max, tol, cost = _restart_inputs(seed)
+    want = choose_restart(theta, res, lam_max, tol, cost)
+    got = B.eigcg_restart_model(theta, res, lam_max, tol, cost)
+    assert (got[0] == 0.0) == (want[0] == 0.0)
+    np.testing.assert_allclose(got, want, rtol=1e-12, atol=0.0)
+
+
+def test_restart_model_closed_forms_and_errors(B):
+    """One separated cluster of three accurate Ritz pairs: tau = sqrt(tol);
+    exact eigenvectors or a prohibitive restart cost: no restart; unsorted,
+    non-positive or non-finite inputs: EINVAL."""
+    theta = np.array([1e-3, 2e-3, 3e-3, 1.0, 1.1, 1.2])
+    res = np.array([1e-7] * 3 + [0.3] * 3)
+    tau, c0, c1 = B.eigcg_restart_model(theta, res, 60.0, 1e-10, 7.0)
+    assert tau == pytest.approx(1e-5, rel=1e-12) and c1 < c0
+    assert B.eigcg_restart_model(theta, np.zeros(6), 60.0, 1e-10, 7.0)[0] == 0.0
+    assert B.eigcg_restart_model(theta, res, 60.0, 1e-10, 1e6)[0] == 0.0
+    assert B.eigcg_restart_model(theta[:0], res[:0], 60.0, 1e-10, 7.0) == (0.0, 0.0, 0.0)
+    for th, rs, lm, tl in [(theta[::-1], res, 60.0, 1e-10), (theta - 1.0, res, 60.0, 1e-10),
+                           (theta, -res, 60.0, 1e-10), (theta, res, float("nan"), 1e-10),
+                           (theta, res, 60.0, 0.0), (theta, res, 60.0, 1.0)]:
+        with pytest.raises(B.EigcgError):
+            B.eigcg_restart_model(th, rs, lm, tl, 7.0)

@@ -13,7 +13,9 @@ from gpu_common import dev, host, make_ctx, rel
 from oracle.cg import cg
 from oracle.dirac import WilsonOperator
 from oracle.eigcg import eigcg
+from oracle.incremental import bank_ritz
 from oracle.initcg import galerkin_guess, init_cg
+from oracle.restart_model import choose_restart
 from oracle.spectral import ritz_basis, spectral_preconditioner
 from synthetic import gauge_field, gaussian_rhs, gaussian_rhs_block, unit_gauge_field
 
@@ -300,6 +302,73 @@ def test_initcg_restart_parity(B, cfg0):
     try:
         B.eigcg_bank_load(ctx, dev(X.T.reshape((12, 4, 4, 4, 4, 4, 3)).copy()))
         _restart_parity(B, ctx, op, X, H, b, 1e-6)
+    finally:
+        B.eigcg_destroy(ctx)
+
+
+def _noisy_bank(op, noise_low=(-9.0, -7.0), seed=23):
+    """The 20 lowest eigenvectors of the 4^4 operator, the lowest 12 with
+    complex Gaussian noise of 10^-9 .. 10^-7 per entry (Ritz residuals of
+    1e-6 .. 1e-4) and the next 8 with 1e-3, orthonormalised."""
+    A, lam, Z = _dense_lowest(op, 20)
+    rng = np.random.default_rng(seed)
+    scale = np.concatenate([10.0 ** np.linspace(*noise_low, 12), np.full(8, 1e-3)])
+    Xn = Z + scale * (rng.standard_normal(Z.shape) + 1j * rng.standard_normal(Z.shape))
+    Xn, _ = np.linalg.qr(Xn)
+    return A, lam, Xn, Xn.conj().T @ A @ Xn
+
+
+def test_initcg_dynamic_restart_parity(B, cfg0):
+    """The dynamic init-CG restart threshold (the open choice at the end of
+    Section 5.3) on a loaded bank of approximate eigenvectors.  The context
+    computes the bank's Ritz values and residual norms (blocks of 8 Ritz
+    vectors per pass, a ragged last block of 4) and picks tau with the cost
+    model; the oracle does the same from its own bank.  Ritz pairs, tau and
+    the restarted solve agree (x to 1e-10 on the same trajectory)."""
+    U, op, b = cfg0
+    A, lam, Xn, H = _noisy_bank(op)
+    theta, res = bank_ritz(op.A, Xn, H)
+    tau_o, c0, c1 = choose_restart(theta, res, (8 + 0.2) ** 2, 1e-10, 6.0)
+    assert tau_o > 0 and c1 < c0
+    ctx, _ = make_ctx(U, -0.2, nev=10, m=40, max_bank=20, max_batch=8,
+                      restart_rule=B.EIGCG_RESTART_DYNAMIC, restart_cost=6.0)
+    try:
+        assert B.eigcg_bank_load(ctx, dev(Xn.T.reshape((20, 4, 4, 4, 4, 4, 3)).copy())) == 20
+        assert np.max(np.abs(B.eigcg_bank_matrix(ctx, 20) - H)) <= 1e-12 * lam[-1]
+        vals, resg = B.eigcg_bank_info(ctx, residuals=True)
+        np.testing.assert_allclose(vals, theta, rtol=1e-10)
+        np.testing.assert_allclose(resg, res, rtol=1e-6, atol=1e-12 * lam[-1])
+        st = _restart_parity(B, ctx, op, Xn, H, b, tau_o)
+        assert st["restart_tau"] == pytest.approx(tau_o, rel=1e-9)
+        # a second solve reuses the cached Ritz pairs: the same threshold
+        x = dev(np.zeros((1,) + b.shape, dtype=np.complex128))
+        rc, st2 = B.eigcg_solve(ctx, dev(b[None]), x, 1e-10, B.EIGCG_MODE_INITCG)
+        assert rc == B.EIGCG_OK and st2[0]["restart_tau"] == st["restart_tau"]
+    finally:
+        B.eigcg_destroy(ctx)
+
+
+def test_initcg_dynamic_restart_declines_when_exact(B, cfg0):
+    """With the exact eigenvectors (residuals at rounding level) nothing comes
+    back after the projection: the dynamic rule plans no restart, and the
+    solve is the oracle's unrestarted init-CG."""
+    U, op, b = cfg0
+    A, lam, X = _dense_lowest(op, 12)
+    H = X.conj().T @ A @ X
+    bf = b.reshape(-1)
+    _, io = init_cg(op.A, X, H, bf, tol=1e-10)
+    ctx, _ = make_ctx(U, -0.2, nev=6, m=20, max_bank=12,
+                      restart_rule=B.EIGCG_RESTART_DYNAMIC)
+    try:
+        B.eigcg_bank_load(ctx, dev(X.T.reshape((12, 4, 4, 4, 4, 4, 3)).copy()))
+        x = dev(np.zeros((1,) + b.shape, dtype=np.complex128))
+        rc, st = B.eigcg_solve(ctx, dev(b[None]), x, 1e-10, B.EIGCG_MODE_INITCG)
+        assert rc == B.EIGCG_OK
+        assert st[0]["restart_tau"] == 0.0 and st[0]["first_leg_iters"] == st[0]["iters"]
+        its = st[0]["iters"]
+        assert abs(its - io["iterations"]) <= 1
+        ref = init_cg(op.A, X, H, bf, tol=1e-10, second_leg_iters=its)[0]
+        assert rel(host(x)[0].reshape(-1), ref) <= 1e-10
     finally:
         B.eigcg_destroy(ctx)
 

@@ -299,3 +299,53 @@ def test_eigcg_request_window_is_charged_against_the_budget(B):
     finally:
         for c in ctxs:
             B.eigcg_destroy(c)
+
+
+def test_dynamic_restart_threshold_in_serving(B):
+    """FP64 serving with the dynamic init-CG restart threshold: the session
+    computes the bank's Ritz pairs when it opens, every request is given the
+    oracle's threshold for the same bank (the 20 lowest eigenvectors of the
+    4^4 operator, the lowest 12 with noise 1e-9 .. 1e-7) and restarts once;
+    x equals the oracle's restarted init-CG after the same two legs (1e-10)."""
+    import torch
+    from oracle.incremental import bank_ritz
+    from oracle.restart_model import choose_restart
+    dims, eps, seed, mass = FIELDS[0]
+    U = gauge_field(dims, eps, seed)
+    op = WilsonOperator(U, mass)
+    A, _ = dense_A(op)
+    lam, Z = np.linalg.eigh(A)
+    rng = np.random.default_rng(23)
+    scale = np.concatenate([10.0 ** np.linspace(-9.0, -7.0, 12), np.full(8, 1e-3)])
+    X = Z[:, :20] + scale * (rng.standard_normal((Z.shape[0], 20))
+                             + 1j * rng.standard_normal((Z.shape[0], 20)))
+    X, _ = np.linalg.qr(X)
+    H = X.conj().T @ A @ X
+    theta, res = bank_ritz(op.A, X, H)
+    tau, _, _ = choose_restart(theta, res, (8.0 + abs(mass)) ** 2, 1e-10, 6.0)
+    assert tau > 0
+    ctx, g = make_ctx(U, mass, max_batch=3, max_bank=20, nev=10, m=40, max_iter=4000,
+                      restart_rule=B.EIGCG_RESTART_DYNAMIC, restart_cost=6.0)
+    try:
+        shape = (dims[3], dims[2], dims[1], dims[0], 4, 3)
+        B.eigcg_bank_load(ctx, dev(X.T.reshape((20,) + shape).copy()))
+        bs = gaussian_rhs_block(dims, [3700 + i for i in range(4)])
+        jobs = []
+        for i in range(4):
+            b = dev(bs[i][None].copy())
+            jobs.append((0, b, torch.zeros_like(b)))
+        out = _serve(B, [ctx], jobs)
+        for (f, b, x), (rc, st) in zip(jobs, out):
+            assert rc == B.EIGCG_OK and st["true_rel_res"] <= 1e-10
+            assert st["restart_tau"] == pytest.approx(tau, rel=1e-9)
+            g1 = st["first_leg_iters"]
+            g2 = st["iters"] - g1
+            assert 0 < g1 < st["iters"]
+            bf = host(b).reshape(-1)
+            _, io = init_cg(op.A, X, H, bf, tol=1e-10, restart_tol=tau)
+            assert abs(g1 - io["first_leg_iterations"]) <= 1
+            ref = init_cg(op.A, X, H, bf, tol=1e-10, restart_tol=tau, first_leg_iters=g1,
+                          second_leg_iters=g2)[0]
+            assert rel(host(x).reshape(-1), ref) <= 1e-10
+    finally:
+        B.eigcg_destroy(ctx)
