@@ -884,6 +884,106 @@ def large_leg(B, torch, n_bank_rhs=6, n_rhs=12):
     return out
 
 
+LARGE_FULL_MASSES = (-0.55, -0.58, -0.60)
+
+
+def large_full_leg(B, torch, masses=LARGE_FULL_MASSES, n_bank_rhs=24, n_rhs=12, chunk=24):
+    """The largest configuration at its full shape: 32^3 x 64, for each of three
+    masses a 240-vector bank grown by FP64 Incremental eigCG(10,100) on 24
+    right-hand sides and held in FP32 (about 48 GB), then 12 deflated solves
+    to 1e-10 in one batch of 12 columns with 16-bit (half) inner storage and
+    with FP32 inner iterations, against plain FP64 CG.  The bank moves chunk
+    vectors at a time (each re-projected by the Section 4 update) from the
+    FP64 context to the half context and from there to the FP32 one, each
+    source released after the move, so at most the FP64 bank with its window
+    and one FP32 bank are resident together."""
+    from synthetic import gauge_field, gaussian_rhs
+    dims = LARGE_LATTICE
+    U = gauge_field(dims, EPS, LARGE_SEED)
+    g = torch.from_numpy(U).to("cuda:0")
+    del U
+    shape = (dims[3], dims[2], dims[1], dims[0], 4, 3)
+    bt = torch.stack([torch.from_numpy(gaussian_rhs(dims, 9500 + i)) for i in range(n_rhs)]).to("cuda:0")
+    out = {"lattice": list(dims), "rhs_per_mass": n_rhs, "masses": []}
+    for mass in masses:
+        t0 = time.perf_counter()
+        p64 = B.eigcg_default_params(dims=dims, mass=mass, nev=NEV, m=M, max_bank=NBANK,
+                                     max_iter=20000, check_every=16)
+        ctx64 = B.eigcg_create(p64, g)
+        src = None
+        try:
+            its = []
+            for i in range(n_bank_rhs):
+                b = torch.from_numpy(gaussian_rhs(dims, 7500 + i)).to("cuda:0")[None]
+                rc, st = B.eigcg_solve(ctx64, b, torch.zeros_like(b), TOL, B.EIGCG_MODE_EIGCG)
+                its.append(st[0]["iters"])
+            vals, _ = B.eigcg_bank_info(ctx64)
+            l = len(vals)
+            t_bank = time.perf_counter() - t0
+            log(f"large lattice (full shape) mass {mass}: bank {l} vectors in {t_bank:.0f}s "
+                f"(eigCG iterations {its[0]}..{its[-1]})")
+            x = torch.zeros_like(bt[:1])
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            rc, stp = B.eigcg_solve(ctx64, bt[:1], x, TOL, B.EIGCG_MODE_CG)
+            torch.cuda.synchronize()
+            plain_s = time.perf_counter() - t1
+            src = ctx64
+            entry = {"mass": mass, "bank": l, "bank_lambda_min": float(vals[0]),
+                     "bank_build_s": t_bank, "eigcg_iters": its,
+                     "plain_fp64_cg_s_per_rhs": plain_s, "plain_fp64_cg_iters": stp[0]["iters"],
+                     "runs": []}
+            for prec, name in ((2, "half storage, FP32 arithmetic"), (1, "FP32")):
+                p = B.eigcg_default_params(dims=dims, mass=mass, precision=prec, max_batch=12,
+                                           max_bank=NBANK, reliable_every=50, max_iter=20000,
+                                           check_every=16, use_graphs=1)
+                ctx = B.eigcg_create(p, g)
+                try:
+                    # the bank in chunks from the previous context (FP64 eigCG, then
+                    # the half context's FP32 bank), each chunk re-projected by the
+                    # Section 4 update; the previous context is then released
+                    buf = torch.empty((min(chunk, l),) + shape, dtype=torch.complex128,
+                                      device="cuda:0")
+                    for q0 in range(0, l, chunk):
+                        k = min(chunk, l - q0)
+                        B.eigcg_bank_vectors(src, q0, k, buf[:k])
+                        B.eigcg_bank_load(ctx, buf[:k])
+                    del buf
+                    B.eigcg_destroy(src)
+                    src = ctx
+                    torch.cuda.empty_cache()
+                    x = torch.zeros_like(bt)
+                    torch.cuda.synchronize()
+                    t1 = time.perf_counter()
+                    rc, st = B.eigcg_solve(ctx, bt, x, TOL, B.EIGCG_MODE_INITCG)
+                    torch.cuda.synchronize()
+                    dt = time.perf_counter() - t1
+                except BaseException:
+                    if src is not ctx:
+                        B.eigcg_destroy(ctx)
+                    raise
+                r = {"inner": name, "bank": len(B.eigcg_bank_info(ctx)[0]), "rhs_per_s": n_rhs / dt,
+                     "wall_s": dt, "speedup_vs_plain_fp64_cg": (n_rhs / dt) * plain_s,
+                     "mean_iters": sum(q["iters"] for q in st) / n_rhs,
+                     "mean_outer_steps": sum(q["outer_steps"] for q in st) / n_rhs,
+                     "max_true_rel_res": max(q["true_rel_res"] for q in st),
+                     "failed": sum(1 for q in st if q["status"] != 0 or q["true_rel_res"] > TOL)}
+                log(f"large lattice (full shape) mass {mass}, {name}: {r['rhs_per_s']:.2f} RHS/s "
+                    f"({r['speedup_vs_plain_fp64_cg']:.1f}x plain FP64 CG, {stp[0]['iters']} "
+                    f"iterations), mean iters {r['mean_iters']:.0f}, max res {r['max_true_rel_res']:.1e}")
+                entry["runs"].append(r)
+        finally:
+            if src is not None:
+                B.eigcg_destroy(src)
+            elif ctx64 is not None:
+                B.eigcg_destroy(ctx64)
+            torch.cuda.empty_cache()
+        out["masses"].append(entry)
+    del bt, g
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(total_rhs, total_iters, total_restarts, total_deflations, budget_s=10.0):
     """The NumPy oracle timed on this host: the 4^4 workload in full (plain CG
     and eigCG(10, 40) to 1e-8), and bounded segments on the bench lattice: CG
@@ -997,6 +1097,9 @@ def main():
     ap.add_argument("--no-batching", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-large", action="store_true", help="skip the 32^3x64 half-precision leg")
+    ap.add_argument("--large-full-only", action="store_true",
+                    help="only the 32^3x64 leg at its full shape (240-vector FP32 bank, three "
+                         "masses; several minutes)")
     ap.add_argument("--no-schur", action="store_true", help="skip the odd-even preconditioning leg")
     ap.add_argument("--no-auto", action="store_true", help="skip the automatic eigCG/init-CG leg")
     ap.add_argument("--no-bicgstab", action="store_true", help="skip the deflated BiCGSTAB leg")
@@ -1043,6 +1146,9 @@ def main():
     if args.gemm_only:
         log("window and deflation contractions only")
         print(json.dumps({"gemm": gemm_roofline(B, torch)}))
+        return
+    if args.large_full_only:
+        print(json.dumps({"large_lattice_full": large_full_leg(B, torch)}))
         return
     if args.roofline_only:
         dims, seed = (LATTICE, SEED) if args.roofline_only == "bench" else (HBM_LATTICE, HBM_SEED)

@@ -112,7 +112,7 @@ typedef struct {
                              ignored while sample_every > 0 */
   int32_t stencil_variant;/* 0: pick the fastest stencil kernel by timing at create
                              (cached per lattice shape and precision in the process);
-                             1..13: force a variant (see eigcg_layout_info) */
+                             1..15: force a variant (see eigcg_layout_info) */
   int32_t plane_pad;      /* extra sites (in units of 64) after each SoA plane so
                              that planes do not start on the same memory channel:
                              0 = library default, < 0 = none */
@@ -346,10 +346,13 @@ int eigcg_memory(eigcg_ctx* ctx, uint64_t* bytes);
  *  11  z-march: each lane marches the z-planes of one (x, y, t) column, so
  *      the z-hops reuse spinors and links from registers; XCD x owns a t-slab
  *  12  as 11 with the z-range in 2 chunks; 13: in 4 chunks (more waves)
- * (8-13 need Lx Ly divisible by 64 and Lt by 8, else they run as 5 / 6 / 6;
- * 16-bit storage runs 1-4 as 5 and 10 as 9; odd-even contexts run 1-2 as 3
- * and 11-13 as 6).
- * eigcg_tune_report: tune_ms (26 doubles) receives the ms that variants 1..13
+ *  14  as 9, the t-slab swept in blocks of 4, 3 or 2 z-planes (dividing Lz):
+ *      (z-block, t, z, xy) order, z-neighbours one xy-plane apart in the sweep
+ *  15  as 14 with cached (not streaming) epilogue loads and stores
+ * (8-15 need Lx Ly divisible by 64 and Lt by 8, else they run as 5 / 6 / 6;
+ * 16-bit storage runs 1-4 as 5, 10 as 9 and 15 as 14; odd-even contexts run
+ * 1-2 as 3 and 11-13 as 6).
+ * eigcg_tune_report: tune_ms (30 doubles) receives the ms that variants 1..15
  * took (best over columns per workgroup) for one CG-shaped pair of stencil
  * passes over a full batch at create, FP64 then FP32 (0 where not timed, e.g.
  * a forced variant). */

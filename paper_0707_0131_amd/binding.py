@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libeigcg.so")
 
 EIGCG_OK, EIGCG_EINVAL, EIGCG_ENOMEM, EIGCG_ENOTCONV = 0, -1, -2, -3
-STENCIL_VARIANTS = 13
+STENCIL_VARIANTS = 15
 EIGCG_EBREAKDOWN, EIGCG_EHIP, EIGCG_EBUSY = -4, -5, -6
 EIGCG_FP64, EIGCG_MIXED_FP32, EIGCG_MIXED_HALF = 0, 1, 2
 EIGCG_MODE_CG, EIGCG_MODE_EIGCG, EIGCG_MODE_INITCG, EIGCG_MODE_AUTO = 0, 1, 2, 3

@@ -302,9 +302,9 @@ static void autotune_stencil(Ctx& c, int prec) {
   double best = 1e300;
   const int ncmax = (w.K >= 4 && prec != kF64) ? 4 : (w.K >= 2 ? 2 : 1);
   for (int v = c.g.eo ? 3 : 1; v <= kStencilVariants; ++v) {  // odd-even runs 1, 2 as 3
-    if (c.g.eo && v >= 11) break;  // the z-march needs the full geometry
+    if (c.g.eo && v >= 11 && v <= 13) continue;  // the z-march needs the full geometry
     for (int nc = 1; nc <= ncmax; nc *= 2) {
-      if ((v < 3 || v >= 11) && nc > 1) break;
+      if ((v < 3 || (v >= 11 && v <= 13)) && nc > 1) break;
       StencilLaunch L1 = stencil_base(c, prec);
       L1.variant = v;
       L1.nc = nc;
@@ -1337,8 +1337,9 @@ struct Run {
 // Precision schemes of a run.  FP64: the whole iteration in FP64 (init-CG
 // restart of Section 5.3 host-driven).  Reliable: FP32 inner CG, every
 // reliable_every iterations of the run x64 += x32 and r is replaced by the
-// FP64 true residual (all columns in lockstep, no column ever pauses, so a
-// column's arithmetic does not depend on the others).  Refine: FP32 inner CG
+// FP64 true residual (all columns in lockstep); a column whose recursive
+// residual reaches the target waits and is updated alone at the next segment
+// boundary, so a column's arithmetic does not depend on the others.  Refine: FP32 inner CG
 // per column until its residual falls by inner_rel, then an FP64 outer step
 // x64 += e, r = b - A x64, deflation re-applied (each column on its own
 // schedule, which keeps results independent of the batch composition).
@@ -1379,7 +1380,7 @@ struct Driver {
   int scheme;
   Workspace& w64;
   int seg, relf;
-  bool want_rel = false;  // a column waits for a reliable update
+  uint32_t rel_wait = 0;  // columns waiting for a reliable update
   bool pending = false;
   int pslot = 0, pend = 0, pid = 0, slot = 0;
 
@@ -1511,10 +1512,10 @@ struct Driver {
              "accum");
   }
 
-  // lockstep FP64 reliable update of every column of the run
-  void reliable_update() {
+  // FP64 reliable update of the masked columns (every column of the run in
+  // lockstep at the periodic updates; a waiting column alone otherwise)
+  void reliable_update(uint32_t m) {
     Ctx& cx = c();
-    const uint32_t m = R.mask;
     for (int j = 0; j < R.K; ++j)
       if (((m >> j) & 1u) && !R.done[j]) R.outer[j]++;
     cx.check(launch_accum_f32_into_f64(R.K, cx.cs, w64.x, cx.cs, R.w.x, cx.cs, cx.stream, m), "accum");
@@ -1606,7 +1607,7 @@ struct Driver {
           mref |= 1u << j;
           continue;
         }
-        want_rel = true;  // kSchemeReliable
+        rel_wait |= 1u << j;  // kSchemeReliable
         continue;
       }
       R.done[j] = 1;
@@ -1626,9 +1627,9 @@ struct Driver {
 
   // plan, enqueue and poll one segment; process the previous one
   void step() {
-    if (want_rel) {  // between segments: every column's update is at an iteration boundary
-      reliable_update();
-      want_rel = false;
+    if (rel_wait) {  // between segments: every column's update is at an iteration boundary
+      reliable_update(rel_wait & R.mask);
+      rel_wait = 0;
     }
     int end = R.enq_iter + seg;
     if (R.eig)
@@ -1637,7 +1638,7 @@ struct Driver {
           end = std::min(end, R.ec[j].next_full);
     if (relf) end = std::min(end, (R.enq_iter / relf + 1) * relf);
     R.enqueue_iters(end - R.enq_iter);
-    if (relf && end % relf == 0) reliable_update();
+    if (relf && end % relf == 0) reliable_update(R.mask);
     R.enqueue_poll(slot, end);
     const int id = ++R.seg_id;
     if (pending) process(pslot, pend, pid);

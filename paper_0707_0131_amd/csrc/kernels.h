@@ -35,10 +35,14 @@ enum StencilEpi {
 // 11: z-march: each lane marches the z-planes of one (x, y, t) column, the
 //     z-hops from registers, XCD x owning a t-slab (stencil_impl.h)
 // 12, 13: as 11 with the z-range split in 2 or 4 chunks (more waves)
-// 8-13 need whole 64-site tiles per xy-plane and Lt divisible by 8; other
-// lattices run 5 and 6 (10-13 as 6) instead; the odd-even geometry runs
+// 14: as 9 with the slab swept in blocks of z-planes (4, 3 or 2 dividing Lz):
+//     (z-block, t, z, xy) order, so z-neighbours inside a block are one
+//     xy-plane apart in the sweep and t-neighbours one block of planes
+// 15: as 14 with cached (not streaming) epilogue loads and stores
+// 8-15 need whole 64-site tiles per xy-plane and Lt divisible by 8; other
+// lattices run 5 and 6 (10-15 as 6) instead; the odd-even geometry runs
 // 11-13 as 6.
-constexpr int kStencilVariants = 13;
+constexpr int kStencilVariants = 15;
 
 struct StencilLaunch {
   int prec;                 // kF64 / kF32 (vectors and links)

@@ -42,6 +42,7 @@ struct DevArgs {
   void* tbuf; size_t t_cs;
   double* hist; int hist_stride;
   uint32_t ord_P, ord_Ls;   // slab sweep: 64-site tiles per xy-plane, t-slices per XCD
+  uint32_t ord_Bz;          // slab sweep: z-planes per block (divides Lz; 1 = no blocks)
   uint32_t zc_n, zc_len;    // z-march: z-chunks per (xy tile, t) column and their length
   // odd-even geometry: output parity, the other parity's link block, and
   // out = dg in2 + ch (hopping sum of in) at the centre (in2 may be null)
@@ -306,11 +307,13 @@ __global__ __launch_bounds__(kBlock) void k_wilson_pair(DevArgs a) {
       }
     } else {
       // XCD x owns the t-slab [x Ls, (x + 1) Ls) and visits its 64-site tiles
-      // (P per xy-plane) in (z, t, xy) order: t-neighbours are P tiles apart
-      // and z-neighbours Ls P tiles apart in the sweep, so both are still in
-      // the XCD's L2 when the sweeping front reaches them
+      // (P per xy-plane) in (z-block, t, z, xy) order with blocks of Bz
+      // z-planes: t-neighbours are Bz P tiles apart in the sweep and
+      // z-neighbours inside a block P tiles apart, so they are still in the
+      // XCD's L2 when the sweeping front reaches them.  With Bz = 1 the order
+      // is (z, t, xy) and z-neighbours are Ls P tiles apart.
       const uint32_t x = blockIdx.x & 7u, step = gridDim.x >> 3;
-      const uint32_t P = a.ord_P, Ls = a.ord_Ls;
+      const uint32_t P = a.ord_P, Ls = a.ord_Ls, Bz = a.ord_Bz;
       const uint32_t ntx = P * Ls * (uint32_t)a.g.L[2];
       const uint32_t units = (ntx + 1u) >> 1;
       for (uint32_t un = blockIdx.x >> 3; un < units; un += step) {
@@ -319,7 +322,8 @@ __global__ __launch_bounds__(kBlock) void k_wilson_pair(DevArgs a) {
         uint32_t s = 0;
         if (valid) {
           const uint32_t xyt = pos % P, rest = pos / P;
-          const uint32_t t = x * Ls + rest % Ls, z = rest / Ls;
+          const uint32_t zi = rest % Bz, r2 = rest / Bz;
+          const uint32_t t = x * Ls + r2 % Ls, z = (r2 / Ls) * Bz + zi;
           s = ((t * (uint32_t)a.g.L[2] + z) * P + xyt) * 64u + (uint32_t)lane;
         }
         unit(s, valid);
@@ -609,14 +613,20 @@ hipError_t launch_typed(const StencilLaunch& L, hipStream_t s) {
     if (!L.compressed) return hipErrorInvalidValue;
     if (variant < 5) variant = 5;
     if (variant == 10) variant = 9;
+    if (variant == 15) variant = 14;
   }
   const uint32_t plane = (uint32_t)(L.g->L[0] * L.g->L[1]) >> (EO ? 1 : 0);
   a.ord_P = plane / 64u;
   a.ord_Ls = (uint32_t)L.g->L[3] / 8u;
+  a.ord_Bz = 1;
+  if (variant == 14 || variant == 15) {  // z-blocked slab sweep: the largest of 4, 3, 2 dividing Lz
+    const uint32_t Lz = (uint32_t)L.g->L[2];
+    a.ord_Bz = Lz % 4u == 0 ? 4u : Lz % 3u == 0 ? 3u : Lz % 2u == 0 ? 2u : 1u;
+  }
   a.zc_n = 1;
   a.zc_len = (uint32_t)L.g->L[2];
   int gx = 0;
-  if (variant >= 11) {
+  if (variant >= 11 && variant <= 13) {
     // z-march: 1, 2 or 4 z-chunks per column; needs the full geometry, whole
     // 64-site tiles per xy-plane, a t-slab per XCD and a grid within kMaxGrid
     const uint32_t n = variant == 11 ? 1u : variant == 12 ? 2u : 4u;
@@ -628,12 +638,13 @@ hipError_t launch_typed(const StencilLaunch& L, hipStream_t s) {
     gx = (int)(8u * ((waves + kBlock / 64 - 1) / (kBlock / 64)));
     if (EO || plane % 64u != 0 || L.g->L[3] % 8 != 0 || gx > kMaxGrid) variant = 6;
   }
-  if (variant >= 8 && variant <= 10 && (plane % 64u != 0 || L.g->L[3] % 8 != 0))
+  if ((variant >= 8 && variant <= 10 || variant >= 14) &&
+      (plane % 64u != 0 || L.g->L[3] % 8 != 0))
     variant = variant == 8 ? 5 : 6;  // the slab sweep needs whole tiles per plane, 8 slabs
   const uint32_t unit = variant >= 3 ? 128u : (uint32_t)kBlock;
   const uint32_t T = ((uint32_t)L.g->V + unit - 1) / unit;
   size_t dyn_lds = 0;
-  if (variant >= 11) {
+  if (variant >= 11 && variant <= 13) {
     // grid set above
   } else if (variant == 1) {
     gx = (int)std::min<uint32_t>(T, kMaxGrid);
@@ -652,7 +663,7 @@ hipError_t launch_typed(const StencilLaunch& L, hipStream_t s) {
   // do not depend on it, so every column's reductions are the same for any
   // batch width.  FP64 takes at most 2 (LDS of the exchange buffer).
   int nc = 1;
-  if (variant >= 3 && variant <= 10 && L.compressed && L.ncols >= 2) {
+  if (variant >= 3 && (variant <= 10 || variant >= 14) && L.compressed && L.ncols >= 2) {
     const int widest = (L.ncols >= 4 && sizeof(typename Storage<VS>::real) == 4) ? 4 : 2;
     nc = L.nc > 0 ? std::min(L.nc, widest) : widest;
     if (nc == 3) nc = 2;
@@ -670,11 +681,11 @@ hipError_t launch_typed(const StencilLaunch& L, hipStream_t s) {
     EIGCG_LAUNCH((k_wilson_pair<VS, LS, COMP, DAG, EPI, NT, ORD, 1, EO>), dyn_lds)   \
   }
 #define EIGCG_K(COMP, DAG, EPI)                                                      \
-  if (variant >= 11) {                                                               \
+  if (variant >= 11 && variant <= 13) {                                              \
     if constexpr (!EO) {                                                             \
       EIGCG_LAUNCH((k_wilson_zmarch<VS, LS, COMP, DAG, EPI>), 0)                     \
     }                                                                                \
-  } else if (variant == 10) {                                                        \
+  } else if (variant == 10 || variant == 15) {                                       \
     EIGCG_PAIR(COMP, DAG, EPI, false, 1)                                             \
   } else if (variant >= 8) {                                                         \
     EIGCG_PAIR(COMP, DAG, EPI, true, 1)                                              \
@@ -698,7 +709,7 @@ hipError_t launch_typed(const StencilLaunch& L, hipStream_t s) {
   }
   if constexpr (kHalf) {
 #define EIGCG_KH(COMP, DAG, EPI)                                                     \
-  if (variant >= 11) {                                                               \
+  if (variant >= 11 && variant <= 13) {                                              \
     if constexpr (!EO) {                                                             \
       EIGCG_LAUNCH((k_wilson_zmarch<VS, LS, COMP, DAG, EPI>), 0)                     \
     }                                                                                \

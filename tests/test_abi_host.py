@@ -48,7 +48,7 @@ def test_default_params_and_validation(B):
     for bad in [dict(nev=10, m=20), dict(dims=(1, 4, 4, 4)), dict(max_batch=13),
                 dict(max_bank=300), dict(precision=7), dict(max_iter=0),
                 dict(mass=float("nan")), dict(nev=0), dict(schur=2),
-                dict(schur=1, dims=(4, 4, 3, 4)), dict(stencil_variant=14),
+                dict(schur=1, dims=(4, 4, 3, 4)), dict(stencil_variant=16),
                 dict(sample_every=-1), dict(nev=16, m=257), dict(precond=2),
                 dict(precond=1, precision=1), dict(precond_sigma=float("inf")),
                 dict(restart_rule=2), dict(restart_cost=float("nan"))]:

@@ -43,7 +43,8 @@ CASES = [
 @pytest.mark.parametrize("name,dims,eps,seed,mass", CASES)
 @pytest.mark.parametrize("compress,variant", [(0, 1), (1, 1), (1, 2), (1, 3), (0, 3), (1, 4),
                                               (1, 5), (1, 6), (1, 7), (1, 8), (1, 9), (0, 9),
-                                              (1, 10), (1, 11), (0, 11), (1, 12), (1, 13)])
+                                              (1, 10), (1, 11), (0, 11), (1, 12), (1, 13),
+                                              (1, 14), (0, 14), (1, 15)])
 def test_apply_matches_oracle(B, name, dims, eps, seed, mass, compress, variant):
     U = gauge_field(dims, eps, seed)
     op = WilsonOperator(U, mass)
@@ -108,7 +109,7 @@ def _cg_candidates(apply_A, b, tol, x0=None):
     return cands, io
 
 
-@pytest.mark.parametrize("variant", list(range(1, 14)))
+@pytest.mark.parametrize("variant", list(range(1, 16)))
 def test_cg_parity_cfg0(B, cfg0, variant):
     """Single-column FP64 CG with every stencil variant: x matches the
     oracle's iterate after the same number of iterations to 1e-10."""
@@ -631,7 +632,8 @@ def test_batched_columns_match_single(B, cfg0):
 
 
 @pytest.mark.parametrize("dims,variant", [((4, 4, 4, 4), 9), ((4, 4, 4, 4), 3),
-                                          ((8, 8, 2, 8), 9), ((8, 8, 2, 8), 5), ((8, 8, 2, 8), 10)])
+                                          ((8, 8, 2, 8), 9), ((8, 8, 2, 8), 5), ((8, 8, 2, 8), 10),
+                                          ((8, 8, 4, 8), 14), ((8, 8, 4, 8), 15)])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_batched_multicolumn_kernels_match_single(B, dims, variant, precision):
     """Batches of 5 columns run the stencil with several right-hand sides per

@@ -44,7 +44,8 @@ def _half_block(dims, seeds):
 
 @pytest.mark.parametrize("name,dims,eps,seed,mass", CASES)
 @pytest.mark.parametrize("compress,variant", [(0, 3), (1, 1), (1, 3), (1, 4), (1, 5), (1, 6),
-                                              (1, 7), (1, 8), (1, 9), (0, 9), (1, 10)])
+                                              (1, 7), (1, 8), (1, 9), (0, 9), (1, 10),
+                                              (1, 14), (1, 15)])
 def test_schur_apply_matches_oracle(B, name, dims, eps, seed, mass, compress, variant):
     U = gauge_field(dims, eps, seed)
     op = SchurOperator(U, mass)
