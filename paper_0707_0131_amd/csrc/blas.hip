@@ -39,18 +39,29 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(UpdateLaunch a, Geom g) {
   }
   const size_t vs = (size_t)g.vs;
   for (uint32_t s = blockIdx.x * kBlock + threadIdx.x; s < (uint32_t)g.V; s += gridDim.x * kBlock) {
+    // four components at a time, every load of a group before its first
+    // store (a store could alias a later load for all the compiler knows,
+    // which would serialise the memory round trips component by component)
 #pragma unroll
-    for (int e = 0; e < 12; ++e) {
-      const size_t i = (size_t)e * vs + s;
-      cpx<R> pv = Storage<VS>::ld(p, i);
-      cpx<R> xv = Storage<XS>::ld(x, i);
-      xv.re += alpha * pv.re;
-      xv.im += alpha * pv.im;
-      Storage<XS>::st(x, i, xv);
-      if (run) {
-        cpx<R> rv = Storage<VS>::ld(r, i);
-        Storage<VS>::st(p, i, {rv.re + beta * pv.re, rv.im + beta * pv.im});
-        if (v) Storage<VS>::st(v, i, {rv.re * inv, rv.im * inv});
+    for (int e0 = 0; e0 < 12; e0 += 4) {
+      cpx<R> pv[4], xv[4], rv[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const size_t i = (size_t)(e0 + k) * vs + s;
+        pv[k] = Storage<VS>::ld(p, i);
+        xv[k] = Storage<XS>::ld(x, i);
+        if (run) rv[k] = Storage<VS>::ld(r, i);
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const size_t i = (size_t)(e0 + k) * vs + s;
+        xv[k].re += alpha * pv[k].re;
+        xv[k].im += alpha * pv[k].im;
+        Storage<XS>::st(x, i, xv[k]);
+        if (run) {
+          Storage<VS>::st(p, i, {rv[k].re + beta * pv[k].re, rv[k].im + beta * pv[k].im});
+          if (v) Storage<VS>::st(v, i, {rv[k].re * inv, rv[k].im * inv});
+        }
       }
     }
   }

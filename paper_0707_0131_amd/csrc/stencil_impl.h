@@ -96,22 +96,32 @@ __device__ __forceinline__ void epilogue(const DevArgs& a, int col, uint32_t s,
 #pragma unroll
       for (int e = C0; e < C0 + NC; ++e) Storage<VS>::st(t, (size_t)e * vs + s, o[e]);
     }
+    // every component of r is loaded before the first store: a store to r
+    // could alias a later load for all the compiler knows, which would
+    // otherwise serialise one memory round trip per component
+    cpx<R> rv[NC];
+#pragma unroll
+    for (int e = C0; e < C0 + NC; ++e)
+      rv[e - C0] = NT ? Storage<VS>::ld_nt(r, (size_t)e * vs + s) : Storage<VS>::ld(r, (size_t)e * vs + s);
 #pragma unroll
     for (int e = C0; e < C0 + NC; ++e) {
-      cpx<R> rv = NT ? Storage<VS>::ld_nt(r, (size_t)e * vs + s) : Storage<VS>::ld(r, (size_t)e * vs + s);
-      rv.re -= alpha * o[e].re;
-      rv.im -= alpha * o[e].im;
-      if (NT) Storage<VS>::st_nt(r, (size_t)e * vs + s, rv);
-      else Storage<VS>::st(r, (size_t)e * vs + s, rv);
-      acc2 += rv.re * rv.re + rv.im * rv.im;
+      cpx<R> v = rv[e - C0];
+      v.re -= alpha * o[e].re;
+      v.im -= alpha * o[e].im;
+      if (NT) Storage<VS>::st_nt(r, (size_t)e * vs + s, v);
+      else Storage<VS>::st(r, (size_t)e * vs + s, v);
+      acc2 += v.re * v.re + v.im * v.im;
     }
   } else {  // kEpiRes: r = b - op(in)
     VS* r = reinterpret_cast<VS*>(a.r) + (size_t)col * a.r_cs;
     const VS* b = reinterpret_cast<const VS*>(a.b) + (size_t)col * a.b_cs;
+    cpx<R> bv[NC];  // loaded before the first store to r (see above)
+#pragma unroll
+    for (int e = C0; e < C0 + NC; ++e)
+      bv[e - C0] = NT ? Storage<VS>::ld_nt(b, (size_t)e * vs + s) : Storage<VS>::ld(b, (size_t)e * vs + s);
 #pragma unroll
     for (int e = C0; e < C0 + NC; ++e) {
-      cpx<R> bv = NT ? Storage<VS>::ld_nt(b, (size_t)e * vs + s) : Storage<VS>::ld(b, (size_t)e * vs + s);
-      cpx<R> rv = {bv.re - o[e].re, bv.im - o[e].im};
+      cpx<R> rv = {bv[e - C0].re - o[e].re, bv[e - C0].im - o[e].im};
       if (NT) Storage<VS>::st_nt(r, (size_t)e * vs + s, rv);
       else Storage<VS>::st(r, (size_t)e * vs + s, rv);
       acc2 += rv.re * rv.re + rv.im * rv.im;

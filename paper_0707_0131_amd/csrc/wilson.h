@@ -157,6 +157,74 @@ __device__ __forceinline__ void hop_dir(const VS* __restrict__ in, const LS* __r
   }
 }
 
+// Rebuild the third row of a two-row link: conj(row0 x row1) for SU(3).
+template <typename R>
+__device__ __forceinline__ void link_third_row(cpx<R>* U) {
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    const int b1 = (b + 1) % 3, b2 = (b + 2) % 3;
+    cpx<R> t = csub(cmul(U[b1], U[3 + b2]), cmul(U[b2], U[3 + b1]));
+    U[6 + b] = {t.re, -t.im};
+  }
+}
+
+// One hop of hop_dir_n.  The link at link_site and a column's neighbour spinor
+// at nb are loaded before either is used, so a wave keeps every load of the
+// hop in flight at once (one memory round trip per hop and column); the
+// scheduling barriers stop the compiler from interleaving the loads with the
+// arithmetic.  Further columns (NC > 1) load their spinor after the previous
+// column's arithmetic, which bounds the live registers to one spinor.
+// BWD: backward hop (U^+ and the opposite projector).  The arithmetic and its
+// order are those of hop_dir.
+template <int MU, typename VS, typename LS, bool COMP, int SF, int NC, bool BWD>
+__device__ __forceinline__ void hop_one_n(const VS* __restrict__ in, size_t in_cs, uint32_t act,
+                                          const LS* __restrict__ u, size_t vs,
+                                          uint32_t link_site, uint32_t nb,
+                                          cpx<typename Storage<VS>::real> (*acc)[12]) {
+  using R = typename Storage<VS>::real;
+  constexpr int NL = COMP ? 6 : 9;
+  cpx<R> U[9];
+#pragma unroll
+  for (int e = 0; e < NL; ++e) U[e] = Storage<LS>::ld(u, (size_t)(MU * NL + e) * vs + link_site);
+  bool first = true;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    if (!((act >> c) & 1u)) continue;
+    const VS* ic = in + (size_t)c * in_cs;
+    cpx<R> v[12];
+#pragma unroll
+    for (int e = 0; e < 12; ++e) v[e] = Storage<VS>::ld(ic, (size_t)e * vs + nb);
+    __builtin_amdgcn_sched_barrier(0);
+    if (COMP && first) link_third_row(U);
+    first = false;
+    cpx<R> h[6];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      project<MU, BWD ? -SF : SF>(v[0 + a], v[3 + a], v[6 + a], v[9 + a], h[a], h[3 + a]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      cpx<R> g0, g1;
+      if (!BWD) {
+        g0 = cmul(U[a * 3 + 0], h[0]);
+        g1 = cmul(U[a * 3 + 0], h[3]);
+        g0 = cadd(g0, cmul(U[a * 3 + 1], h[1]));
+        g1 = cadd(g1, cmul(U[a * 3 + 1], h[4]));
+        g0 = cadd(g0, cmul(U[a * 3 + 2], h[2]));
+        g1 = cadd(g1, cmul(U[a * 3 + 2], h[5]));
+      } else {
+        g0 = cmulc(U[0 * 3 + a], h[0]);
+        g1 = cmulc(U[0 * 3 + a], h[3]);
+        g0 = cadd(g0, cmulc(U[1 * 3 + a], h[1]));
+        g1 = cadd(g1, cmulc(U[1 * 3 + a], h[4]));
+        g0 = cadd(g0, cmulc(U[2 * 3 + a], h[2]));
+        g1 = cadd(g1, cmulc(U[2 * 3 + a], h[5]));
+      }
+      accumulate<MU, BWD ? -SF : SF>(acc[c], a, g0, g1);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
 // hop_dir for NC right-hand sides at once: each link is loaded (and its third
 // row rebuilt) once and applied to the NC columns in == in0 + c in_cs whose
 // bit is set in act.  Per column the arithmetic is exactly hop_dir's.
@@ -167,7 +235,6 @@ __device__ __forceinline__ void hop_dir_n(const VS* __restrict__ in, size_t in_c
                                           const LS* __restrict__ u, const LS* __restrict__ u2,
                                           const Geom& g, uint32_t s, const uint32_t* coord,
                                           cpx<typename Storage<VS>::real> (*acc)[12]) {
-  using R = typename Storage<VS>::real;
   const size_t vs = (size_t)g.vs;
   const uint32_t c_ = coord[MU];
   const uint32_t st_ = (uint32_t)g.stride[MU];
@@ -176,62 +243,8 @@ __device__ __forceinline__ void hop_dir_n(const VS* __restrict__ in, size_t in_c
                           : ((c_ + 1 < (uint32_t)g.L[MU]) ? s + st_ : s - span_);
   const uint32_t sb_ = EO ? ((c_ > 0) ? s - st_ : s + span_) >> 1
                           : ((c_ > 0) ? s - st_ : s + span_);
-  {
-    cpx<R> U[9];
-    load_link<LS, COMP>(u, MU, vs, EO ? s >> 1 : s, U);
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      if (!((act >> c) & 1u)) continue;
-      const VS* ic = in + (size_t)c * in_cs;
-      cpx<R> h[6];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        cpx<R> u0 = Storage<VS>::ld(ic, (size_t)(0 + a) * vs + sf_);
-        cpx<R> u1 = Storage<VS>::ld(ic, (size_t)(3 + a) * vs + sf_);
-        cpx<R> l0 = Storage<VS>::ld(ic, (size_t)(6 + a) * vs + sf_);
-        cpx<R> l1 = Storage<VS>::ld(ic, (size_t)(9 + a) * vs + sf_);
-        project<MU, SF>(u0, u1, l0, l1, h[a], h[3 + a]);
-      }
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        cpx<R> g0 = cmul(U[a * 3 + 0], h[0]);
-        cpx<R> g1 = cmul(U[a * 3 + 0], h[3]);
-        g0 = cadd(g0, cmul(U[a * 3 + 1], h[1]));
-        g1 = cadd(g1, cmul(U[a * 3 + 1], h[4]));
-        g0 = cadd(g0, cmul(U[a * 3 + 2], h[2]));
-        g1 = cadd(g1, cmul(U[a * 3 + 2], h[5]));
-        accumulate<MU, SF>(acc[c], a, g0, g1);
-      }
-    }
-  }
-  {
-    cpx<R> U[9];
-    load_link<LS, COMP>(EO ? u2 : u, MU, vs, sb_, U);
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      if (!((act >> c) & 1u)) continue;
-      const VS* ic = in + (size_t)c * in_cs;
-      cpx<R> h[6];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        cpx<R> u0 = Storage<VS>::ld(ic, (size_t)(0 + a) * vs + sb_);
-        cpx<R> u1 = Storage<VS>::ld(ic, (size_t)(3 + a) * vs + sb_);
-        cpx<R> l0 = Storage<VS>::ld(ic, (size_t)(6 + a) * vs + sb_);
-        cpx<R> l1 = Storage<VS>::ld(ic, (size_t)(9 + a) * vs + sb_);
-        project<MU, -SF>(u0, u1, l0, l1, h[a], h[3 + a]);
-      }
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        cpx<R> g0 = cmulc(U[0 * 3 + a], h[0]);
-        cpx<R> g1 = cmulc(U[0 * 3 + a], h[3]);
-        g0 = cadd(g0, cmulc(U[1 * 3 + a], h[1]));
-        g1 = cadd(g1, cmulc(U[1 * 3 + a], h[4]));
-        g0 = cadd(g0, cmulc(U[2 * 3 + a], h[2]));
-        g1 = cadd(g1, cmulc(U[2 * 3 + a], h[5]));
-        accumulate<MU, -SF>(acc[c], a, g0, g1);
-      }
-    }
-  }
+  hop_one_n<MU, VS, LS, COMP, SF, NC, false>(in, in_cs, act, u, vs, EO ? s >> 1 : s, sf_, acc);
+  hop_one_n<MU, VS, LS, COMP, SF, NC, true>(in, in_cs, act, EO ? u2 : u, vs, sb_, sb_, acc);
 }
 
 // Hopping sum over all four directions for one site.
