@@ -917,6 +917,9 @@ def large_full_leg(B, torch, masses=LARGE_FULL_MASSES, n_bank_rhs=24, n_rhs=12, 
                 b = torch.from_numpy(gaussian_rhs(dims, 7500 + i)).to("cuda:0")[None]
                 rc, st = B.eigcg_solve(ctx64, b, torch.zeros_like(b), TOL, B.EIGCG_MODE_EIGCG)
                 its.append(st[0]["iters"])
+                if i % 6 == 5:
+                    log(f"large lattice (full shape) mass {mass}: {i + 1} eigCG solves, "
+                        f"{time.perf_counter() - t0:.0f}s")
             vals, _ = B.eigcg_bank_info(ctx64)
             l = len(vals)
             t_bank = time.perf_counter() - t0
