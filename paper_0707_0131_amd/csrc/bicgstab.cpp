@@ -13,9 +13,12 @@
 //
 // Every vector operation runs in the library's kernels: the two-tile stencil,
 // the fused BiCGSTAB updates and inner products (bicgstab_blas.hip), BLAS1 and
-// the MFMA products of the deflation.  The host holds only the recurrence's
-// scalars: three read-backs per iteration (r^_0^H v; t^H s, s^H s, t^H t;
-// r^_0^H r, r^H r).
+// the MFMA products of the deflation.  The recurrence's scalars (rho, alpha,
+// omega, beta), its stop tests and the iteration count live in a BicgState on
+// the device, updated by one-workgroup kernels after each inner product; the
+// host reads the state once per segment of iterations (kernels of a stopped
+// recurrence do nothing), and itself only starts and restarts the iteration
+// and checks the true residual.
 
 #include <hip/hip_runtime.h>
 
@@ -45,6 +48,7 @@ bool finite(cplx z) { return std::isfinite(z.real()) && std::isfinite(z.imag());
 double2 d2(cplx z) { return make_double2(z.real(), z.imag()); }
 
 constexpr size_t kPartialBytes = sizeof(double2) * kBicgMaxDots * kBicgDotBlocks;
+constexpr int kSegment = 8;  // iterations enqueued between reads of the device state
 
 struct Bicg {
   Ctx& c;
@@ -52,10 +56,12 @@ struct Bicg {
   void* f[kFields];
   double2* partial;      // inner-product partials
   double2* out;          // inner products (kBicgMaxDots)
+  BicgState* dst;        // the recurrence's device state
 
   Bicg(Ctx& c_, bool g5_) : c(c_), g5(g5_) {
     const size_t fb = c.cs * prec_bytes(kF64);
-    const size_t bytes = fb * kFields + kPartialBytes + sizeof(double2) * kBicgMaxDots;
+    const size_t bytes = fb * kFields + kPartialBytes + sizeof(double2) * kBicgMaxDots +
+                         sizeof(BicgState);
     if (!c.bs) {
       c.bs = c.dalloc(bytes);
       // plane padding stays zero: kernels below never write it
@@ -64,6 +70,17 @@ struct Bicg {
     for (int i = 0; i < kFields; ++i) f[i] = col_ptr(c.bs, kF64, c.cs, i);
     partial = (double2*)((char*)c.bs + fb * kFields);
     out = partial + kBicgMaxDots * kBicgDotBlocks;
+    dst = (BicgState*)(out + kBicgMaxDots);
+  }
+  void put_state(const BicgState& h) {
+    c.check(hipMemcpyAsync(dst, &h, sizeof(BicgState), hipMemcpyHostToDevice, c.stream), "state");
+    c.check(hipStreamSynchronize(c.stream), "sync");
+  }
+  BicgState get_state() {
+    BicgState h;
+    c.check(hipMemcpyAsync(&h, dst, sizeof(BicgState), hipMemcpyDeviceToHost, c.stream), "state");
+    c.check(hipStreamSynchronize(c.stream), "sync");
+    return h;
   }
 
   // y <- gamma5 y: in the chiral basis gamma5 = diag(1, 1, -1, -1), so the
@@ -168,59 +185,52 @@ int solve_column(Ctx& c, Bicg& B, double tol, int max_iter, bool defl, bool gues
     first = false;
     if (std::sqrt(rr) <= stop) break;
     if (st.restarts > kMaxRestarts) break;
-    cplx rho_old(1.0, 0.0), alpha(1.0, 0.0), omega(1.0, 0.0);
-    B.zero(V);
-    B.zero(P);
-    bool conv = false;
-    while (it < max_iter) {
-      if (rho == 0.0 || omega == 0.0 || !finite(rho)) {
-        status = EIGCG_EBREAKDOWN;
-        break;
-      }
-      const cplx beta = (rho / rho_old) * (alpha / omega);
-      c.check(launch_bicg_p(c.cs, P, R, V, d2(beta), d2(omega), c.stream), "p");
-      B.op(P, V, B.g5);
-      G = B.dots({B.f[kRh]}, {V});
-      const cplx rv = G[0];
-      if (rv == 0.0 || !finite(rv)) {
-        status = EIGCG_EBREAKDOWN;
-        break;
-      }
-      alpha = rho / rv;
-      c.check(launch_bicg_s(c.cs, S, R, V, d2(alpha), c.stream), "s");
-      ++it;
-      B.op(S, B.f[kT], B.g5);
-      G = B.dots({B.f[kT], S, B.f[kT]}, {S, S, B.f[kT]});  // t^H s, s^H s, t^H t
-      const cplx ts = G[0], tt = G[2];
-      const double ss = G[1].real();
-      if (std::sqrt(ss) <= stop) {  // half step
-        B.axpy(alpha, P, B.f[kX]);
-        std::swap(R, S);
-        conv = true;
-        break;
-      }
-      if (tt == 0.0 || !finite(tt) || !finite(ts)) {
-        status = EIGCG_EBREAKDOWN;
-        break;
-      }
-      omega = ts / tt;
-      // x += alpha p + omega s; r = s - omega t; rh^H r and r^H r
-      c.check(launch_bicg_xr(c.cs, B.f[kX], R, P, S, B.f[kT], B.f[kRh], d2(alpha), d2(omega),
-                             B.partial, B.out, c.stream),
-              "x, r");
-      G = B.fetch(2);
-      rho_old = rho;
-      rho = G[0];
-      if (std::sqrt(G[1].real()) <= stop) {
-        conv = true;
-        break;
-      }
-    }
-    if (!conv) {
-      if (status == EIGCG_OK) status = EIGCG_ENOTCONV;
+    if (it >= max_iter) {
+      status = EIGCG_ENOTCONV;
       break;
     }
-    // the recursion met the tolerance: the true residual decides
+    if (rho == 0.0 || !finite(rho)) {
+      status = EIGCG_EBREAKDOWN;
+      break;
+    }
+    B.zero(V);
+    B.zero(P);
+    // rho_old = alpha = omega = 1, so beta = rho (p = r in the first step)
+    BicgState h{};
+    h.rho = d2(rho);
+    h.rho_old = h.alpha = h.omega = make_double2(1.0, 0.0);
+    h.beta = d2(rho);
+    h.stop2 = stop * stop;
+    h.it = it;
+    h.max_iter = max_iter;
+    h.state = kBicgRun;
+    h.half = 0;
+    B.put_state(h);
+    while (h.state == kBicgRun) {
+      for (int k = 0; k < kSegment; ++k) {
+        c.check(launch_bicg_p_dev(c.cs, P, R, V, B.dst, c.stream), "p");
+        B.op(P, V, B.g5);
+        c.check(launch_bicg_alpha(c.cs, B.f[kRh], V, B.partial, B.dst, c.stream), "alpha");
+        c.check(launch_bicg_s_dev(c.cs, S, R, V, B.dst, c.stream), "s");
+        B.op(S, B.f[kT], B.g5);
+        c.check(launch_bicg_omega(c.cs, B.f[kT], S, B.partial, B.dst, c.stream), "omega");
+        c.check(launch_bicg_xr_dev(c.cs, B.f[kX], R, P, S, B.f[kT], B.f[kRh], B.partial, B.dst,
+                                   c.stream),
+                "x, r");
+      }
+      h = B.get_state();
+    }
+    it = h.it;
+    if (h.state == kBicgBreak) {
+      status = EIGCG_EBREAKDOWN;
+      break;
+    }
+    if (h.state == kBicgMaxIt) {
+      status = EIGCG_ENOTCONV;
+      break;
+    }
+    // the recursion met the tolerance (after a full or a half step): the
+    // true residual decides
     B.residual(R);
     G = B.dots({R}, {R});
     if (std::sqrt(G[0].real()) <= stop) break;

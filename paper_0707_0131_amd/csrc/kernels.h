@@ -222,16 +222,36 @@ constexpr int kBicgMaxDots = 4;
 constexpr int kBicgDotBlocks = 1024;
 hipError_t launch_bicg_dots(int np, size_t n, const void* const* a, const void* const* b,
                             double2* partial, double2* out, hipStream_t s);
+
+// Device-resident BiCGSTAB recurrence (one right-hand side): the scalars live
+// in a BicgState on the device and every kernel of an iteration reads them
+// there, so the host polls only between segments of iterations.  A kernel does
+// nothing once state != kBicgRun.
+enum BicgRun { kBicgRun = 0, kBicgConv = 1, kBicgHalf = 2, kBicgBreak = 3, kBicgMaxIt = 4 };
+struct BicgState {
+  double2 rho, rho_old, alpha, omega, beta;
+  double stop2;      // (tol ||b||)^2
+  int it, max_iter;  // iterations completed, cap
+  int state;         // BicgRun
+  int half;          // the current iteration ends with the half step
+};
 // p = r + beta (p - omega v)
-hipError_t launch_bicg_p(size_t n, void* p, const void* r, const void* v, double2 beta,
-                         double2 omega, hipStream_t s);
+hipError_t launch_bicg_p_dev(size_t n, void* p, const void* r, const void* v,
+                             const BicgState* st, hipStream_t s);
+// alpha = rho / (rh^H v)
+hipError_t launch_bicg_alpha(size_t n, const void* rh, const void* v, double2* partial,
+                             BicgState* st, hipStream_t s);
 // s = r - alpha v
-hipError_t launch_bicg_s(size_t n, void* sv, const void* r, const void* v, double2 alpha,
-                         hipStream_t s);
-// x += alpha p + omega s; r = s - omega t; out[0] = rh^H r, out[1] = r^H r
-hipError_t launch_bicg_xr(size_t n, void* x, void* r, const void* p, const void* sv,
-                          const void* t, const void* rh, double2 alpha, double2 omega,
-                          double2* partial, double2* out, hipStream_t s);
+hipError_t launch_bicg_s_dev(size_t n, void* sv, const void* r, const void* v,
+                             const BicgState* st, hipStream_t s);
+// t^H s, s^H s, t^H t: the half-step test on ||s||, else omega = t^H s / t^H t
+hipError_t launch_bicg_omega(size_t n, const void* t, const void* sv, double2* partial,
+                             BicgState* st, hipStream_t s);
+// x += alpha p + omega s, r = s - omega t (half step: x += alpha p, r = s),
+// then rho, the convergence test on ||r||, the iteration cap and beta
+hipError_t launch_bicg_xr_dev(size_t n, void* x, void* r, const void* p, const void* sv,
+                              const void* t, const void* rh, double2* partial, BicgState* st,
+                              hipStream_t s);
 
 // Test support: MFMA lane-layout probe (1024 doubles written to out_dev).
 hipError_t launch_mfma_probe(double* out_dev, hipStream_t s);
