@@ -436,9 +436,10 @@ int eigcg_server_destroy(eigcg_server* srv);
  * eigcg_debug_gemm: the library's complex tall-skinny products on contiguous
  * device columns of n complex entries (prec 0: complex128, 1: complex64):
  * kind 0: out (n x N) = in (n x K) s (K x N, complex128 column-major);
+ * kind 2: out += in s; kind 3: out -= in s (out holds its old values);
  * kind 1: out (K x N, complex128 column-major) = in^H r (r: n x N), using
  * scratch_dev (scratch_elems doubles) for chunk partials.  K <= 256,
- * N <= 24 (kind 0) or 16 (kind 1).  Both synchronise the device. */
+ * N <= 24 (kinds 0, 2, 3) or 16 (kind 1).  All synchronise the device. */
 int eigcg_debug_mfma_probe(double* out_dev);
 /* eigcg_debug_span: the host-side bounds layer (no GPU needed).  The library
  * registers each of its device allocations with its size and refuses, with

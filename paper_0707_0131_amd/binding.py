@@ -576,17 +576,24 @@ def eigcg_debug_mfma_probe():
     return out.cpu().numpy()
 
 
-def eigcg_debug_gemm(kind, inp, s=None, r=None):
-    """kind 0: inp (K, n) columns times s (K, N) -> (N, n); kind 1: inp^H r ->
-    (K, N).  Tensors are complex128 or complex64 device tensors."""
+def eigcg_debug_gemm(kind, inp, s=None, r=None, out=None):
+    """kind 0: inp (K, n) columns times s (K, N) -> (N, n); kinds 2 / 3: out
+    (N, n, device, updated in place and returned) plus / minus that product;
+    kind 1: inp^H r -> (K, N).  Tensors are complex128 or complex64 device
+    tensors."""
     import torch
     K, n = inp.shape
     prec = 0 if inp.dtype == torch.complex128 else 1
-    if kind == 0:
+    if kind in (0, 2, 3):
         N = s.shape[1]
         sd = s.to(torch.complex128).t().contiguous()  # column-major (K x N)
-        out = torch.zeros((N, n), dtype=inp.dtype, device=inp.device)
-        rc = LIB.eigcg_debug_gemm(prec, 0, n, K, N, _ptr(inp), None, _ptr(sd), _ptr(out), None, 0)
+        if kind == 0:
+            out = torch.zeros((N, n), dtype=inp.dtype, device=inp.device)
+        elif (out is None or tuple(out.shape) != (N, n) or out.dtype != inp.dtype
+              or not out.is_contiguous() or out.device != inp.device):
+            raise ValueError("out must be a contiguous (N, n) tensor like inp")
+        rc = LIB.eigcg_debug_gemm(prec, kind, n, K, N, _ptr(inp), None, _ptr(sd), _ptr(out),
+                                  None, 0)
     else:
         N = r.shape[0]
         out = torch.zeros((N, K), dtype=torch.complex128, device=inp.device)
@@ -595,7 +602,7 @@ def eigcg_debug_gemm(kind, inp, s=None, r=None):
                                   _ptr(scratch), scratch.numel())
     if rc != EIGCG_OK:
         raise EigcgError(rc, "debug gemm failed")
-    return out.cpu().numpy() if kind == 0 else out.cpu().numpy().T
+    return out.cpu().numpy() if kind != 1 else out.cpu().numpy().T
 
 
 def eigcg_debug_span(op, addr, nbytes=0):

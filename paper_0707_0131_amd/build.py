@@ -32,6 +32,11 @@ COMMON = [
 # result then does not depend on how many columns share its workgroup.
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics", "-ffp-contract=on"]
+# Per-source device flags.  gemm.hip keeps its MFMA accumulators in ordinary
+# VGPRs (gfx950 accepts them there as well as in AGPRs): with AGPR
+# accumulators the compiler copied every accumulator to VGPRs and back on each
+# iteration of the tall product's loop and drained its loads there.
+EXTRA = {"gemm.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
 
 
 def _sources():
@@ -44,7 +49,7 @@ def _sources():
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *COMMON, *DEVICE, "-c", src, "-o", obj]
+    cmd = [HIPCC, *COMMON, *DEVICE, *EXTRA.get(os.path.basename(src), []), "-c", src, "-o", obj]
     if src.endswith(".cpp"):
         cmd = [HIPCC, *COMMON, *DEVICE, "-x", "hip", "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -414,19 +414,21 @@ int eigcg_debug_gemm(int32_t prec, int32_t kind, uint64_t n, int32_t K, int32_t 
   std::vector<const void*> in(K);
   for (int i = 0; i < K; ++i) in[i] = (const char*)in_dev + (size_t)i * n * eb;
   hipError_t e;
-  if (kind == 0) {  // out (n x N) = in (n x K) * S (K x N)
+  if (kind == 0 || kind == 2 || kind == 3) {  // out (n x N) (+-)= in (n x K) * S (K x N)
     if (!s_dev) return EIGCG_EINVAL;
     std::vector<void*> out(N);
     for (int j = 0; j < N; ++j) out[j] = (char*)out_dev + (size_t)j * n * eb;
     e = eigcg::launch_gemm_tall(prec == 0 ? eigcg::kF64 : eigcg::kF32, n, K, N, in.data(),
-                                out.data(), (const double2*)s_dev, 0, 0, nullptr);
-  } else {  // out (K x N complex FP64) = in^H r
+                                out.data(), (const double2*)s_dev, kind != 0, kind == 3, nullptr);
+  } else if (kind == 1) {  // out (K x N complex FP64) = in^H r
     if (!r_dev || N > 16 || !scratch_dev) return EIGCG_EINVAL;
     std::vector<const void*> rc(N);
     for (int j = 0; j < N; ++j) rc[j] = (const char*)r_dev + (size_t)j * n * eb;
     e = eigcg::launch_gemm_reduce(prec == 0 ? eigcg::kF64 : eigcg::kF32, n, K, N, in.data(),
                                   rc.data(), (double2*)scratch_dev, scratch_elems / 2,
                                   (double2*)out_dev, nullptr);
+  } else {
+    return EIGCG_EINVAL;
   }
   if (e != hipSuccess) return EIGCG_EHIP;
   return hipDeviceSynchronize() == hipSuccess ? EIGCG_OK : EIGCG_EHIP;

@@ -51,6 +51,22 @@ template <> struct Mfma<float> {
   __device__ static __forceinline__ int row(int g, int r) { return 4 * g + r; }
 };
 
+// The column pointers are staged in LDS, which loses their address space:
+// loads and stores through a generic pointer become flat instructions, whose
+// completion every LDS wait must also wait for, so the products read and write
+// device memory through global pointers.
+template <typename T> using gptr = __attribute__((address_space(1))) T*;
+template <typename T> __device__ __forceinline__ gptr<T> as_global(T* p) { return (gptr<T>)p; }
+template <typename R> struct Vec2;
+template <> struct Vec2<double> { using t = nt_d2; };
+template <> struct Vec2<float> { using t = nt_f2; };
+template <typename VS>
+__device__ __forceinline__ cpx<typename Storage<VS>::real> ldg(const VS* p, size_t i) {
+  using V = typename Vec2<typename Storage<VS>::real>::t;
+  const V v = as_global(reinterpret_cast<const V*>(p))[i];
+  return {v.x, v.y};
+}
+
 // Out rows [row0, row0 + 64) per wave; 4 waves per workgroup.
 template <typename VS, int NT>
 __global__ __launch_bounds__(256) void k_gemm_tall(size_t n, int K, int N, const double2* S,
@@ -84,15 +100,21 @@ __global__ __launch_bounds__(256) void k_gemm_tall(size_t n, int K, int N, const
     for (int t = 0; t < NT; ++t) acc[m][t] = typename M::acc_t{};
 
   // A fragments of input columns k0 + kcol: one real part per lane (lanes of
-  // the two parts of a complex entry read adjacent words)
+  // the two parts of a complex entry read adjacent words).  Lanes past column
+  // K - 1 read that column and lanes past row n - 1 read that row: the B
+  // entries of a column past K - 1 are zero and an output row past n - 1 is
+  // not stored, so the loop body is free of branches and the loaded values
+  // are first used by the products.
   const R* const* sinr = reinterpret_cast<const R* const*>(sin);
+  const bool full = row0 + 64 <= n;  // wave-uniform
   auto load_a = [&](int k0, R* af) {
     const int kc = k0 + kcol;
-    const R* src = kc < K ? sinr[kc] : nullptr;
+    const gptr<const R> src = as_global(sinr[kc < K ? kc : K - 1]);
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      const size_t row = row0 + m * 16 + li;
-      af[m] = (src && row < n) ? src[2 * row + kpart] : R(0);
+      size_t row = row0 + m * 16 + li;
+      if (!full && row >= n) row = n - 1;
+      af[m] = src[2 * row + kpart];
     }
   };
   auto step = [&](int k0, const R* af) {
@@ -101,20 +123,19 @@ __global__ __launch_bounds__(256) void k_gemm_tall(size_t n, int K, int N, const
     // B fragments: real column jj = 16 t + li -> output column j = 8 t + li/2, part li&1
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
+      // lanes past column N - 1 or K - 1 read an entry in range and take zero
       const int j = 8 * t + (li >> 1);
-      R bv = R(0);
-      if (kvalid && j < N) {
-        const double2 s = sS[(size_t)j * K + kc];
-        // [[a, b], [-b, a]] with rows (Re-in, Im-in), cols (Re-out, Im-out)
-        if (kpart == 0) bv = (li & 1) ? (R)s.y : (R)s.x;
-        else bv = (li & 1) ? (R)s.x : (R)(-s.y);
-      }
+      const double2 s = sS[(size_t)(j < N ? j : N - 1) * K + (kvalid ? kc : K - 1)];
+      // [[a, b], [-b, a]] with rows (Re-in, Im-in), cols (Re-out, Im-out)
+      R bv = kpart == 0 ? ((li & 1) ? (R)s.y : (R)s.x) : ((li & 1) ? (R)s.x : (R)(-s.y));
+      bv = (kvalid && j < N) ? bv : R(0);
 #pragma unroll
       for (int m = 0; m < 4; ++m) acc[m][t] = M::op(af[m], bv, acc[m][t]);
     }
   };
   // software pipeline: the A fragments of the next kPre steps are in flight
-  // while the current step's products run (same product order as unpipelined)
+  // while the current step's products run.  The steps run in groups of kPre;
+  // steps of the last group past column K - 1 multiply by zero B entries.
   constexpr int kPre = 4;
   R af[kPre][4];
 #pragma unroll
@@ -123,32 +144,46 @@ __global__ __launch_bounds__(256) void k_gemm_tall(size_t n, int K, int N, const
 #pragma unroll
     for (int q = 0; q < kPre; ++q) {
       const int kq = k0 + 2 * q;
-      if (kq >= K) break;
-      R cur[4];
-#pragma unroll
-      for (int m = 0; m < 4; ++m) cur[m] = af[q][m];
+      step(kq, af[q]);
+      // the step's registers take the fragments kPre steps ahead (a copy of
+      // them would make every iteration wait for its own loads); the barrier
+      // keeps the scheduler from sinking the loads towards their use
       load_a(kq + 2 * kPre, af[q]);
-      step(kq, cur);
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
-  // epilogue: register r of the lane holds D[M::row(lane/16, r)][li] of each tile
+  // epilogue: register r of the lane holds D[M::row(lane/16, r)][li] of each
+  // tile.  With beta = 1 a tile's old output values are all loaded before its
+  // first store.  Lanes past column N - 1 (and, in the last wave, past row
+  // n - 1) address column N - 1 (row n - 1) and store nothing.
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const int j = 8 * t + (li >> 1);
-    if (j >= N) continue;
-    R* dst = sout[j];
+    const bool jv = j < N;
+    const gptr<R> dst = as_global(sout[jv ? j : N - 1]) + (li & 1);
+    if (beta_one) {
+      R old[4][4];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          size_t row = row0 + m * 16 + M::row(lk, r);
+          if (!full && row >= n) row = n - 1;
+          old[m][r] = dst[2 * row];
+        }
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[m][t][r] += old[m][r];
+    }
+    if (!jv) continue;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const size_t row = row0 + m * 16 + M::row(lk, r);
-        if (row >= n) continue;
-        R v = acc[m][t][r];
-        R* p = dst + 2 * row + (li & 1);
-        if (beta_one) v += *p;
-        *p = v;
+        if (full || row < n) dst[2 * row] = acc[m][t][r];
       }
-    }
   }
 }
 
@@ -213,7 +248,7 @@ __global__ __launch_bounds__(256) void k_gemm_reduce(size_t n, int K, int N, siz
       const size_t row = rb + (size_t)(q / kColGroups) * kLanesPerCol + lrow;
       const int col = mtile * 16 + c;
       pu[q] = {R(0), R(0)};
-      if (mact && col < K && row < r1) pu[q] = Storage<VS>::ld(sin[col], row);
+      if (mact && col < K && row < r1) pu[q] = ldg(sin[col], row);
     }
 #pragma unroll
     for (int q = 0; q < kRLoads; ++q) {
@@ -221,7 +256,7 @@ __global__ __launch_bounds__(256) void k_gemm_reduce(size_t n, int K, int N, siz
       const int j = e / TR, tr = e % TR;
       const size_t row = rb + tr;
       pr[q] = {R(0), R(0)};
-      if (j < N && row < r1) pr[q] = Storage<VS>::ld(sr[j], row);
+      if (j < N && row < r1) pr[q] = ldg(sr[j], row);
     }
   };
   if (r0 < r1) fetch(r0);

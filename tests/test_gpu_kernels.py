@@ -58,6 +58,29 @@ def test_gemm_tall(B, dt, n, K, N):
 
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("kind", [2, 3])
+@pytest.mark.parametrize("n,K,N", [(1000, 1, 1), (777, 33, 24), (6144, 100, 20), (4099, 240, 1),
+                                   (5000, 9, 17)])
+def test_gemm_tall_accumulate(B, dt, kind, n, K, N):
+    """The beta = 1 epilogue: out += in S (kind 2, the init-CG lift of
+    eq. (2.1)) and out -= in S (kind 3, the Gram-Schmidt update of Section 4),
+    every old output value read before the tile's stores."""
+    import torch
+    rng = np.random.default_rng(K * 31 + N + kind)
+    cdt = np.complex128 if dt == "c128" else np.complex64
+    A = (rng.standard_normal((K, n)) + 1j * rng.standard_normal((K, n))).astype(cdt)
+    S = rng.standard_normal((K, N)) + 1j * rng.standard_normal((K, N))
+    O = (rng.standard_normal((N, n)) + 1j * rng.standard_normal((N, n))).astype(cdt)
+    out = torch.from_numpy(O.copy()).to("cuda:0")
+    got = B.eigcg_debug_gemm(kind, torch.from_numpy(A).to("cuda:0"),
+                             s=torch.from_numpy(S).to("cuda:0"), out=out)
+    prod = (A.astype(np.complex128).T @ S).T
+    ref = O.astype(np.complex128) + (prod if kind == 2 else -prod)
+    tol = 1e-13 if dt == "c128" else 2e-6
+    assert np.max(np.abs(got - ref)) <= tol * np.max(np.abs(ref)) * np.sqrt(K)
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
 @pytest.mark.parametrize("n,K,N", [(1000, 1, 1), (3072, 20, 1), (1024, 40, 12), (4097, 17, 16),
                                    (6144, 100, 1), (5000, 240, 16), (4099, 240, 1)])
 def test_gemm_reduce(B, dt, n, K, N):
