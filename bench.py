@@ -48,7 +48,12 @@ def site_bytes_stencil(two_row_links: bool, elem=16):
     return 12 * elem + links + 12 * elem
 
 
-SAMPLE_EVERY = 4  # stencil passes of every 4th CG iteration are timed with events
+# Stencil passes of every SAMPLE_EVERY-th CG iteration of the timed steps are
+# timed with events (each timed pass costs a few microseconds of dispatch gap,
+# so sampling every iteration or every 4th would slow the measured workload);
+# the 24^3x48 CG sample, outside the timed steps, times every HBM_SAMPLE_EVERY-th.
+SAMPLE_EVERY = 32
+HBM_SAMPLE_EVERY = 4
 STENCIL_SOURCES = ("paper_0707_0131_amd/csrc/stencil_impl.h",
                    "paper_0707_0131_amd/csrc/dslash_f64.hip", "paper_0707_0131_amd/csrc/wilson.h",
                    "paper_0707_0131_amd/csrc/common.h")
@@ -60,11 +65,14 @@ HBM_CG_ITERS = 240  # FP64 CG iterations sampled on the 24^3x48 lattice
 
 RESTART_RULE = {"fixed": 0, "dynamic": 1}
 restart_rule = 0  # init-CG restart threshold of the timed steps (--restart-rule)
+sample_every = SAMPLE_EVERY  # event-timed CG iterations of the timed steps (--sample-every)
+use_graphs = 0  # timed steps replay captured CG segments (--graphs)
 
 
 def run_step(B, torch, g, mass, bt, xt, n_eig=N_EIG):
     p = B.eigcg_default_params(dims=LATTICE, mass=mass, nev=NEV, m=M, max_bank=NBANK,
-                               max_iter=40000, check_every=16, sample_every=SAMPLE_EVERY,
+                               max_iter=40000, check_every=16, sample_every=sample_every,
+                               use_graphs=use_graphs,
                                restart_rule=restart_rule)
     ctx = B.eigcg_create(p, g)
     try:
@@ -483,14 +491,14 @@ def measured_traffic(summary=TRAFFIC_SUMMARY):
 
 def cg_pass_samples(B, torch, g, dims, mass, n_iter, variant=0):
     """FP64 CG (one Gaussian right-hand side, seed 1000) for n_iter iterations
-    on the given links; the two stencil passes of every SAMPLE_EVERY-th
+    on the given links; the two stencil passes of every HBM_SAMPLE_EVERY-th
     iteration are timed by their own dispatch start/stop events on the
     solver's stream.  Returns the sampled mean durations and the variant."""
     from synthetic import gaussian_rhs
     b = torch.from_numpy(gaussian_rhs(dims, 1000)[None].copy()).to("cuda:0")
     x = torch.zeros_like(b)
     p = B.eigcg_default_params(dims=dims, mass=mass, max_bank=0, max_iter=n_iter, check_every=16,
-                               sample_every=SAMPLE_EVERY, stencil_variant=variant)
+                               sample_every=HBM_SAMPLE_EVERY, stencil_variant=variant)
     ctx = B.eigcg_create(p, g)
     try:
         B.eigcg_solve(ctx, b, x, TOL, B.EIGCG_MODE_CG)  # stops at n_iter (ENOTCONV)
@@ -1124,6 +1132,10 @@ def main():
                     help="only the serving leg (no timed steps)")
     ap.add_argument("--serve-bank-rhs", type=int, default=N_EIG)
     ap.add_argument("--serve-requests", type=int, default=120)
+    ap.add_argument("--sample-every", type=int, default=SAMPLE_EVERY,
+                    help="time the stencil passes of every n-th CG iteration of the timed steps")
+    ap.add_argument("--graphs", action="store_true",
+                    help="timed steps replay captured CG segments (iterations not event-timed)")
     ap.add_argument("--stencil-variant", type=int, default=0,
                     help="with --roofline-only: force this stencil variant (counter runs "
                          "use the variant the full bench run picked)")
@@ -1134,8 +1146,10 @@ def main():
                     help="only time the stencil, copy and CG iteration on the bench lattice "
                          "or the 24^3x48 lattice (short runs for counter collection)")
     args = ap.parse_args()
-    global restart_rule
+    global restart_rule, sample_every, use_graphs
     restart_rule = RESTART_RULE[args.restart_rule]
+    sample_every = args.sample_every
+    use_graphs = 1 if args.graphs else 0
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               f"(this build runs on a single MI355X)", file=sys.stderr)

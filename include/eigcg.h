@@ -106,10 +106,10 @@ typedef struct {
   uint64_t hbm_budget;    /* bytes this context may allocate, 0 = no cap */
   int32_t compress_links; /* 1: store links as two rows when they are SU(3) */
   int32_t check_every;    /* iterations between host convergence polls */
-  int32_t use_graphs;     /* 1: each segment of CG iterations (stencil passes,
-                             finalize and update kernels) is captured once per
-                             segment length and replayed as a HIP graph;
-                             ignored while sample_every > 0 */
+  int32_t use_graphs;     /* 1: segments of CG iterations (stencil passes,
+                             finalize and update kernels) are replayed from HIP
+                             graphs captured once per context and segment shape;
+                             iterations that sample_every times run on their own */
   int32_t stencil_variant;/* 0: pick the fastest stencil kernel by timing at create
                              (cached per lattice shape and precision in the process);
                              1..15: force a variant (see eigcg_layout_info) */
@@ -380,11 +380,14 @@ int eigcg_time_kernel(eigcg_ctx* ctx, int32_t what, int32_t reps, double* ms);
 
 /* Sampled stencil timings (params.sample_every; each sampled kernel carries
  * start/stop events filled by its own dispatch).  out[0..3] for FP64 and
- * out[4..7] for FP32 iterations: number of sampled iterations, mean duration in
- * ms of the first pass (M p with the p^H A p partials), mean duration of the
- * second pass (M^H fused with the residual update and its norm, without the
- * per-column finalize kernel), mean batch width.  Waits for the context's
- * stream; reset != 0 clears the accumulated samples. */
+ * out[4..7] for FP32 iterations: number of sampled iterations in which the
+ * kernels ran, mean duration in ms of the first pass (M p with the p^H A p
+ * partials), mean duration of the second pass (M^H fused with the residual
+ * update and its norm, without the per-column finalize kernel), mean batch
+ * width.  A sample whose second pass took under half the median of all
+ * samples is a launch after every column of it had stopped (the kernels exit
+ * at once) and is left out of all four.  Waits for the context's stream;
+ * reset != 0 clears the accumulated samples. */
 int eigcg_kernel_samples(eigcg_ctx* ctx, int32_t reset, double* out);
 
 /* Text of the context's last error; with ctx == NULL, of this thread's last

@@ -479,6 +479,8 @@ void ctx_release(Ctx& c) {
   for (auto& k : c.ks_pool)
     for (auto& e : k.e) (void)hipEventDestroy(e);
   c.ks_pool.clear();
+  for (auto& kv : c.graphs) (void)hipGraphExecDestroy(kv.second);
+  c.graphs.clear();
   if (c.gstream) (void)hipStreamDestroy(c.gstream);
   c.gstream = nullptr;
 }
@@ -501,29 +503,40 @@ bool Ctx::ks_harvest(bool wait) {
     check(hipEventElapsedTime(&a, k.e[0], k.e[1]), "sample time");
     check(hipEventElapsedTime(&b, k.e[2], k.e[3]), "sample time");
     const int p = k.prec == kF64 ? 0 : 1;
-    ks_sum[p][0] += a;
-    ks_sum[p][1] += b;
-    ks_n[p] += 1;
-    ks_cols[p] += k.ncols;
+    ks_done[p].push_back({a, b, (float)k.ncols});
   }
   ks_used = 0;
   return true;
 }
 
+// Means over the sampled iterations whose kernels ran: a sample whose second
+// pass took under half the median of all samples is a launch whose columns had
+// all stopped (the kernel exits at once) and is left out.
 void kernel_samples(Ctx& c, bool reset, double* out) {
   c.ks_harvest(true);
   for (int p = 0; p < 2; ++p) {
-    const double n = (double)c.ks_n[p];
+    const auto& v = c.ks_done[p];
+    double n = 0.0, s1 = 0.0, s2 = 0.0, sc = 0.0;
+    if (!v.empty()) {
+      std::vector<float> b2(v.size());
+      for (size_t i = 0; i < v.size(); ++i) b2[i] = v[i][1];
+      std::nth_element(b2.begin(), b2.begin() + b2.size() / 2, b2.end());
+      const float cut = 0.5f * b2[b2.size() / 2];
+      for (const auto& k : v) {
+        if (k[1] < cut) continue;
+        n += 1.0;
+        s1 += k[0];
+        s2 += k[1];
+        sc += k[2];
+      }
+    }
     out[4 * p + 0] = n;
-    out[4 * p + 1] = n > 0 ? c.ks_sum[p][0] / n : 0.0;
-    out[4 * p + 2] = n > 0 ? c.ks_sum[p][1] / n : 0.0;
-    out[4 * p + 3] = n > 0 ? (double)c.ks_cols[p] / n : 0.0;
+    out[4 * p + 1] = n > 0 ? s1 / n : 0.0;
+    out[4 * p + 2] = n > 0 ? s2 / n : 0.0;
+    out[4 * p + 3] = n > 0 ? sc / n : 0.0;
   }
   if (reset) {
-    for (int p = 0; p < 2; ++p) {
-      c.ks_sum[p][0] = c.ks_sum[p][1] = 0.0;
-      c.ks_n[p] = c.ks_cols[p] = 0;
-    }
+    for (int p = 0; p < 2; ++p) c.ks_done[p].clear();
   }
 }
 
@@ -979,10 +992,6 @@ struct Run {
   int enq_iter = 0;              // iterations enqueued (all columns in lockstep)
   bool spec = false;             // iterations preconditioned with z = P^{-1} r
   int seg_id = 0;                // id of the last enqueued segment
-  // captured segments of n iterations (params.use_graphs): the kernels of a
-  // segment only depend on this run's buffers, mask and width, so one graph
-  // per segment length serves the whole run
-  std::map<int, hipGraphExec_t> graphs;
 
   Run(Ctx& c_, Workspace& w_, int prec_, int K_, uint32_t mask_, bool eig_)
       : c(c_), w(w_), prec(prec_), K(K_), mask(mask_), eig(eig_) {
@@ -1009,9 +1018,6 @@ struct Run {
       if (K > w.Keig) throw ApiError{EIGCG_EINVAL, "internal: eigCG run wider than its window"};
       check_fields(c, w.ring, prec, K * w.ring_len, "window ring");
     }
-  }
-  ~Run() {
-    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
   }
   Run(const Run&) = delete;
   Run& operator=(const Run&) = delete;
@@ -1099,9 +1105,36 @@ struct Run {
                                c.d_specs, st);
       return e;
     };
-    if (c.P.use_graphs && c.P.sample_every <= 0 && n > 0) {
-      auto it = graphs.find(n);
-      if (it == graphs.end()) {
+    // one iteration on its own; a sampled one times each stencil kernel by its
+    // own dispatch timestamps (no extra packets between the kernels)
+    auto eager = [&]() {
+      Ctx::KSample* ks = sample_slot();
+      L1.ev_start = ks ? ks->e[0] : nullptr;
+      L1.ev_stop = ks ? ks->e[1] : nullptr;
+      L2.ev_start = ks ? ks->e[2] : nullptr;
+      L2.ev_stop = ks ? ks->e[3] : nullptr;
+      c.check(launch_stencil(L1, c.stream), "K1");
+      c.check(launch_stencil(L2, c.stream), "K2");
+      if (spec) c.check(precond_step(c.stream), "preconditioner");
+      c.check(launch_cg_update(L3, c.stream), "K3");
+      L1.ev_start = L1.ev_stop = L2.ev_start = L2.ev_stop = nullptr;
+    };
+    // len iterations replayed from a graph captured once per context
+    auto replay = [&](int len) {
+      const std::array<uint64_t, 14> key = {
+          (uint64_t)len, (uint64_t)prec, (uint64_t)K, (uint64_t)mask, (uint64_t)eig,
+          (uint64_t)spec, spec ? (uint64_t)c.bank_gen : 0u, (uint64_t)(uintptr_t)w.p,
+          (uint64_t)(uintptr_t)w.r, (uint64_t)(uintptr_t)w.x, (uint64_t)(uintptr_t)w.tmp,
+          (uint64_t)(uintptr_t)w.ring, (uint64_t)(uintptr_t)w.tbuf,
+          (uint64_t)(uintptr_t)w.z ^ ((uint64_t)w.ring_len << 48)};
+      auto it = c.graphs.find(key);
+      if (it == c.graphs.end()) {
+        // bounded: graphs of earlier workspaces, banks or masks are dropped
+        if (c.graphs.size() >= 64) {
+          c.check(hipStreamSynchronize(c.stream), "sync");
+          for (auto& kv : c.graphs) (void)hipGraphExecDestroy(kv.second);
+          c.graphs.clear();
+        }
         // captured on a private stream (the context's stream may be the null
         // stream, which cannot be captured); replayed on the context's stream
         if (!c.gstream) c.check(hipStreamCreateWithFlags(&c.gstream, hipStreamNonBlocking), "stream");
@@ -1109,7 +1142,7 @@ struct Run {
         hipGraphExec_t ex = nullptr;
         c.check(hipStreamBeginCapture(c.gstream, hipStreamCaptureModeThreadLocal), "capture");
         hipError_t e = hipSuccess;
-        for (int i = 0; i < n && e == hipSuccess; ++i) {
+        for (int i = 0; i < len && e == hipSuccess; ++i) {
           e = launch_stencil(L1, c.gstream);
           if (e == hipSuccess) e = launch_stencil(L2, c.gstream);
           if (e == hipSuccess && spec) e = precond_step(c.gstream);
@@ -1121,25 +1154,31 @@ struct Run {
         const hipError_t e3 = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
         (void)hipGraphDestroy(gr);
         c.check(e3, "graph instantiate");
-        it = graphs.emplace(n, ex).first;
+        it = c.graphs.emplace(key, ex).first;
       }
       c.check(hipGraphLaunch(it->second, c.stream), "graph launch");
+    };
+    if (c.P.use_graphs && n > 0) {
+      // runs of unsampled iterations from graphs, sampled ones on their own
+      for (int i = 0; i < n;) {
+        int run = n - i;
+        if (c.P.sample_every > 0) {
+          const long every = c.P.sample_every;
+          run = (int)std::min<long>(run, (every - c.ks_tick % every) % every);
+        }
+        if (run > 0) {
+          replay(run);
+          c.ks_tick += run;
+          i += run;
+        } else {
+          eager();
+          ++i;
+        }
+      }
       enq_iter += n;
       return;
     }
-    for (int i = 0; i < n; ++i) {
-      // sampled iterations time each stencil kernel by its own dispatch
-      // timestamps (no extra packets between the kernels)
-      Ctx::KSample* ks = sample_slot();
-      L1.ev_start = ks ? ks->e[0] : nullptr;
-      L1.ev_stop = ks ? ks->e[1] : nullptr;
-      L2.ev_start = ks ? ks->e[2] : nullptr;
-      L2.ev_stop = ks ? ks->e[3] : nullptr;
-      c.check(launch_stencil(L1, c.stream), "K1");
-      c.check(launch_stencil(L2, c.stream), "K2");
-      if (spec) c.check(precond_step(c.stream), "preconditioner");
-      c.check(launch_cg_update(L3, c.stream), "K3");
-    }
+    for (int i = 0; i < n; ++i) eager();
     enq_iter += n;
   }
 

@@ -7,6 +7,7 @@
 #include <complex>
 #include <map>
 #include <string>
+#include <array>
 #include <vector>
 
 #include "common.h"
@@ -53,6 +54,11 @@ struct Ctx {
   size_t cs = 0;         // complex elements per field (12 * vs)
   hipStream_t stream = nullptr;
   hipStream_t gstream = nullptr;  // capture-only stream for HIP graphs
+  // captured CG segments (params.use_graphs), kept across solves; the key
+  // holds what the captured kernels' arguments depend on beyond the context's
+  // fixed buffers: iterations, precision, width, mask, eigCG and
+  // preconditioner state and the workspace fields
+  std::map<std::array<uint64_t, 14>, hipGraphExec_t> graphs;
   int device = 0;
   int comp64 = 0, comp32 = 0;
   int iprec = kF32;                // inner precision of mixed contexts (kF32 or kF16)
@@ -125,9 +131,8 @@ struct Ctx {
   std::vector<KSample> ks_pool;
   int ks_used = 0;
   long ks_tick = 0;
-  double ks_sum[2][2] = {{0, 0}, {0, 0}};  // [prec][pass] ms
-  long ks_n[2] = {0, 0};
-  long ks_cols[2] = {0, 0};
+  // harvested samples per precision: (pass 1 ms, pass 2 ms, columns)
+  std::vector<std::array<float, 3>> ks_done[2];
   bool ks_harvest(bool wait);
 
   // memory

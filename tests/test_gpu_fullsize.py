@@ -60,6 +60,30 @@ def test_fullsize_stencil_matches_oracle(B, field):
         B.eigcg_destroy(ctx)
 
 
+def test_kernel_samples_count_the_launches_that_ran(B, field):
+    """Every 4th CG iteration timed, segments of 64 iterations: the segment in
+    which the column converges runs on with launches that exit at once, and
+    the samples count exactly the timed iterations that ran (iterations 1, 5,
+    9, ... of the solve, the context's first)."""
+    U, op = field
+    ctx, _ = make_ctx(U, MASS, max_iter=20000, check_every=64, sample_every=4)
+    try:
+        b = gaussian_rhs(DIMS, 4243)[None]
+        x = dev(np.zeros_like(b))
+        rc, st = B.eigcg_solve(ctx, dev(b), x, 1e-10, B.EIGCG_MODE_CG)
+        assert rc == B.EIGCG_OK
+        iters = st[0]["iters"]
+        # timed launches after the stop: iterations iters + 1 .. the segment's end
+        seg_end = -(-iters // 64) * 64
+        assert len(range(((iters + 3) // 4) * 4 + 1, seg_end + 1, 4)) >= 2
+        s = B.eigcg_kernel_samples(ctx, reset=True)["f64"]
+        assert s["n"] == (iters + 3) // 4
+        assert 0.0 < s["pass1_ms"] < 1.0 and 0.0 < s["pass2_ms"] < 1.0 and s["cols"] == 1.0
+        assert B.eigcg_kernel_samples(ctx)["f64"]["n"] == 0
+    finally:
+        B.eigcg_destroy(ctx)
+
+
 def test_fullsize_cg_and_eigcg_bank(B, field):
     """Plain CG, then two Incremental eigCG(10, 100) solves and a deflated
     solve, as in the bench's phases; every solution and the bank are checked

@@ -751,6 +751,38 @@ def test_graph_replay_matches_eager(B, cfg0, precision):
         B.eigcg_destroy(ctx_g)
 
 
+def test_graph_replay_with_sampling_matches_eager(B, cfg0):
+    """The bench's launch path: Incremental eigCG then init-CG in one context,
+    segments replayed from graphs kept across solves while every 7th
+    iteration is launched on its own with timing events.  Bitwise the eager
+    result and the same iterations; the graph path still times launches."""
+    U, op, _ = cfg0
+    bs = gaussian_rhs_block((4, 4, 4, 4), [2400 + i for i in range(5)])
+    kw = dict(nev=4, m=16, max_bank=16, max_iter=3000, check_every=8, sample_every=7)
+    ctx_e, _ = make_ctx(U, -0.2, **kw)
+    ctx_g, _ = make_ctx(U, -0.2, use_graphs=1, **kw)
+    try:
+        out = []
+        for ctx in (ctx_e, ctx_g):
+            x = dev(np.zeros_like(bs))
+            its = []
+            for i in range(2):  # one right-hand side per call: the bank grows in between
+                rc, st = B.eigcg_solve(ctx, dev(bs[i:i + 1]), x[i:i + 1], 1e-10, B.EIGCG_MODE_EIGCG)
+                assert rc == B.EIGCG_OK
+                its.append(st[0]["iters"])
+            rc, st = B.eigcg_solve(ctx, dev(bs[2:]), x[2:], 1e-10, B.EIGCG_MODE_INITCG)
+            assert rc == B.EIGCG_OK
+            its += [s["iters"] for s in st]
+            out.append((host(x), its, B.eigcg_kernel_samples(ctx)["f64"]["n"]))
+        (xe, ie, ne), (xg, ig, ng) = out
+        assert ie == ig
+        assert np.array_equal(xe, xg)
+        assert ne > 0 and ng > 0
+    finally:
+        B.eigcg_destroy(ctx_e)
+        B.eigcg_destroy(ctx_g)
+
+
 def test_half_precision_cg_and_initcg(B, cfg0):
     """16-bit links and vectors with FP32 arithmetic (FP32 iterate), each inner
     solve rescaled, FP64 refinement: CG and init-CG reach the FP64 tolerance;
