@@ -538,7 +538,11 @@ hipError_t launch_spec_rho(ColState* st, int ncols, uint32_t mask, const double*
 }
 
 hipError_t launch_cg_update(const UpdateLaunch& L, hipStream_t s) {
-  dim3 grid(grid_for(L.g->V), L.ncols);
+  // one site per thread (the kernel writes no per-workgroup partials, so the
+  // grid is not held to kMaxGrid): a capped grid left a fraction of the
+  // threads a second site each, a tail the rest of the GPU waited for
+  const size_t wgs = ((size_t)L.g->V + kBlock - 1) / kBlock;
+  dim3 grid((unsigned)std::min<size_t>(wgs, 1u << 20), L.ncols);
   if (L.prec == kF64)
     hipLaunchKernelGGL((k_cg_update<double2, double2>), grid, dim3(kBlock), 0, s, L, *L.g);
   else if (L.prec == kF32)
