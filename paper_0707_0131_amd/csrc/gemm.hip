@@ -241,22 +241,33 @@ __global__ __launch_bounds__(256) void k_gemm_reduce(size_t n, int K, int N, siz
   cpx<R> pu[kLoads];
   constexpr int kRLoads = (16 * TR) / 256;  // R tile entries per thread
   cpx<R> pr[kRLoads];
+  // each thread's load columns are the same for every tile: their pointers
+  // are read from LDS once (null for a column past K - 1 or N - 1)
+  const VS* ucol[kLoads];
+  const VS* rcol[kRLoads];
+#pragma unroll
+  for (int q = 0; q < kLoads; ++q) {
+    const int col = mtile * 16 + (q % kColGroups) * kColsPerLoad + lsub;
+    ucol[q] = (mact && col < K) ? sin[col] : nullptr;
+  }
+#pragma unroll
+  for (int q = 0; q < kRLoads; ++q) {
+    const int j = (q * 256 + (int)threadIdx.x) / TR;
+    rcol[q] = j < N ? sr[j] : nullptr;
+  }
   auto fetch = [&](size_t rb) {
 #pragma unroll
     for (int q = 0; q < kLoads; ++q) {
-      const int c = (q % kColGroups) * kColsPerLoad + lsub;
       const size_t row = rb + (size_t)(q / kColGroups) * kLanesPerCol + lrow;
-      const int col = mtile * 16 + c;
       pu[q] = {R(0), R(0)};
-      if (mact && col < K && row < r1) pu[q] = ldg(sin[col], row);
+      if (ucol[q] && row < r1) pu[q] = ldg(ucol[q], row);
     }
 #pragma unroll
     for (int q = 0; q < kRLoads; ++q) {
       const int e = q * 256 + (int)threadIdx.x;  // entry of the 16 x TR tile
-      const int j = e / TR, tr = e % TR;
-      const size_t row = rb + tr;
+      const size_t row = rb + e % TR;
       pr[q] = {R(0), R(0)};
-      if (j < N && row < r1) pr[q] = ldg(sr[j], row);
+      if (rcol[q] && row < r1) pr[q] = ldg(rcol[q], row);
     }
   };
   if (r0 < r1) fetch(r0);
@@ -275,22 +286,21 @@ __global__ __launch_bounds__(256) void k_gemm_reduce(size_t n, int K, int N, siz
     __syncthreads();
     if (rb + TR < r1) fetch(rb + TR);
     if (mact) {
-      const int nr = (int)((r1 - rb) < (size_t)TR ? (r1 - rb) : (size_t)TR);
-      for (int s = 0; s < nr; s += 2) {
-        const int tr = s + krow;  // rows beyond the chunk are zero in the tile
-        const bool trv = rb + tr < r1;
+      // every row pair of the tile: rows beyond the chunk are zero in both
+      // staged tiles, so their products add nothing, and the fixed trip count
+      // lets the LDS reads of several pairs be in flight together
+#pragma unroll 4
+      for (int s = 0; s < TR; s += 2) {
+        const int tr = s + krow;
         const cpx<R> z = tUw[li * CS + tr];
         const R a = kpart ? z.im : z.re;
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-          const int j = 8 * t + (li >> 1);
-          R bv = R(0);
-          if (trv && j < N) {
-            const cpx<R> y = tR[j * CS + tr];
-            // [[Re R, Im R], [Im R, -Re R]] with rows (Re-in, Im-in), cols (Re-out, Im-out)
-            if (kpart == 0) bv = (li & 1) ? y.im : y.re;
-            else bv = (li & 1) ? -y.re : y.im;
-          }
+          const int j = 8 * t + (li >> 1);  // < 16: inside the staged R tile
+          const cpx<R> y = tR[j * CS + tr];
+          // [[Re R, Im R], [Im R, -Re R]] with rows (Re-in, Im-in), cols (Re-out, Im-out)
+          R bv = kpart == 0 ? ((li & 1) ? y.im : y.re) : ((li & 1) ? -y.re : y.im);
+          bv = j < N ? bv : R(0);
           acc[t] = M::op(a, bv, acc[t]);
         }
       }
