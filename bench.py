@@ -67,25 +67,38 @@ RESTART_RULE = {"fixed": 0, "dynamic": 1}
 restart_rule = 0  # init-CG restart threshold of the timed steps (--restart-rule)
 sample_every = SAMPLE_EVERY  # event-timed CG iterations of the timed steps (--sample-every)
 use_graphs = 0  # timed steps replay captured CG segments (--graphs)
+DEFL_BATCH = 4  # phase-2 init-CG right-hand sides solved together in lockstep
+defl_batch = DEFL_BATCH  # (--defl-batch; plain CG runs the same batches)
 
 
 def run_step(B, torch, g, mass, bt, xt, n_eig=N_EIG):
     p = B.eigcg_default_params(dims=LATTICE, mass=mass, nev=NEV, m=M, max_bank=NBANK,
                                max_iter=40000, check_every=16, sample_every=sample_every,
-                               use_graphs=use_graphs,
+                               use_graphs=use_graphs, max_batch=defl_batch,
                                restart_rule=restart_rule)
     ctx = B.eigcg_create(p, g)
     try:
         xt.zero_()
         t0 = time.perf_counter()
-        rc1, st1 = B.eigcg_solve(ctx, bt[:n_eig], xt[:n_eig], TOL, B.EIGCG_MODE_EIGCG)
+        samples = None
+        if defl_batch == 1:
+            rc1, st1 = B.eigcg_solve(ctx, bt[:n_eig], xt[:n_eig], TOL, B.EIGCG_MODE_EIGCG)
+        else:  # Incremental eigCG stays sequential: one right-hand side per call
+            st1 = []
+            for i in range(n_eig):
+                _, st = B.eigcg_solve(ctx, bt[i:i + 1], xt[i:i + 1], TOL, B.EIGCG_MODE_EIGCG)
+                st1 += st
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+        if defl_batch > 1:  # the single-column launches of phase 1 for the roofline
+            samples = B.eigcg_kernel_samples(ctx, reset=True)["f64"]
+            t1 = time.perf_counter()
         rc2, st2 = B.eigcg_solve(ctx, bt[n_eig:], xt[n_eig:], TOL, B.EIGCG_MODE_INITCG)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         vals, _ = B.eigcg_bank_info(ctx)
-        samples = B.eigcg_kernel_samples(ctx)["f64"]
+        if samples is None:
+            samples = B.eigcg_kernel_samples(ctx)["f64"]
         samples["stencil_variant"] = B.eigcg_layout_info(ctx)["variant64"]
     finally:
         B.eigcg_destroy(ctx)
@@ -109,7 +122,8 @@ def run_step(B, torch, g, mass, bt, xt, n_eig=N_EIG):
 
 
 def plain_cg(B, torch, g, mass, bt, xt, n):
-    p = B.eigcg_default_params(dims=LATTICE, mass=mass, max_iter=40000, check_every=32)
+    p = B.eigcg_default_params(dims=LATTICE, mass=mass, max_iter=40000, check_every=32,
+                               max_batch=defl_batch)
     ctx = B.eigcg_create(p, g)
     try:
         xt[:n].zero_()
@@ -474,9 +488,10 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(summary=TRAFFIC_SUMMARY):
+def measured_traffic(summary=TRAFFIC_SUMMARY, variant=None):
     """HBM bytes per launch of the dominant kernel from the committed counter
-    summary, or None when the stencil sources changed since it was taken."""
+    summary, or None when the stencil sources changed since it was taken or
+    the sampled launches ran another stencil variant than the counted ones."""
     import re
     path = os.path.join(ROOT, summary)
     if not os.path.exists(path):
@@ -485,6 +500,9 @@ def measured_traffic(summary=TRAFFIC_SUMMARY):
     m = re.search(r"source_sha256_16:\s*([0-9a-f]{16})", txt)
     t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
     if not m or not t or m.group(1) != source_hash():
+        return None
+    v = re.search(r"stencil_variant:\s*(\d+)", txt)
+    if variant is not None and (not v or int(v.group(1)) != int(variant)):
         return None
     return float(t.group(1))
 
@@ -1134,6 +1152,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=120)
     ap.add_argument("--sample-every", type=int, default=SAMPLE_EVERY,
                     help="time the stencil passes of every n-th CG iteration of the timed steps")
+    ap.add_argument("--defl-batch", type=int, default=DEFL_BATCH,
+                    help="phase-2 init-CG right-hand sides solved together in lockstep "
+                         "(phase 1 stays one right-hand side at a time)")
     ap.add_argument("--graphs", action="store_true",
                     help="timed steps replay captured CG segments (iterations not event-timed)")
     ap.add_argument("--stencil-variant", type=int, default=0,
@@ -1146,10 +1167,11 @@ def main():
                     help="only time the stencil, copy and CG iteration on the bench lattice "
                          "or the 24^3x48 lattice (short runs for counter collection)")
     args = ap.parse_args()
-    global restart_rule, sample_every, use_graphs
+    global restart_rule, sample_every, use_graphs, defl_batch
     restart_rule = RESTART_RULE[args.restart_rule]
     sample_every = args.sample_every
     use_graphs = 1 if args.graphs else 0
+    defl_batch = args.defl_batch
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               f"(this build runs on a single MI355X)", file=sys.stderr)
@@ -1328,7 +1350,7 @@ def main():
     pass2_bytes = V * (192 + 384 + 192 + 192)
     pass1_bytes = V * site_bytes_stencil(True)  # p in, links, t out
     achieved = pass2_bytes / pass2_ms / 1e6 if n_s else None
-    traffic = measured_traffic()
+    traffic = measured_traffic(variant=steps[0]["samples"]["stencil_variant"] if steps else None)
     roof_mall = {
         "bound": "hbm",
         "mall_resident": True,
@@ -1360,7 +1382,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": a_h / HBM_PEAK_GBS,
-            "traffic": measured_traffic(TRAFFIC_SUMMARY_HBM),
+            "traffic": measured_traffic(TRAFFIC_SUMMARY_HBM, hbm_samples["stencil_variant"]),
             "launch_ms": hbm_samples["pass2_ms"],
             "stencil_variant": hbm_samples["stencil_variant"],
             "sampled_launches": int(hbm_samples["n"]),
@@ -1384,7 +1406,10 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "Incremental eigCG(10,100) on 24 RHS + init-CG (240 vectors) on 100 RHS, "
-                        "16^3x32 Wilson, synthetic SU(3) links eps 0.5, FP64 single-RHS, tol 1e-10",
+                        "16^3x32 Wilson, synthetic SU(3) links eps 0.5, FP64, tol 1e-10; eigCG one "
+                        f"RHS at a time, init-CG (and the plain-CG baseline) in lockstep batches "
+                        f"of {defl_batch}",
+            "lockstep_batch": defl_batch,
             "lattice": list(LATTICE),
             "masses": list(MASSES),
             "rhs_per_step": nrhs,

@@ -459,6 +459,43 @@ def test_batched_initcg_guesses_match_single_solves(B, cfg0):
         B.eigcg_destroy(ctx)
 
 
+def test_lockstep_initcg_batches_match_single_solves(B, cfg0):
+    """init-CG over a fixed bank (eq. (2.1), with the Section 5.3 restart) in
+    lockstep batches of 4 right-hand sides: each column restarts on its own
+    at its own iteration, and every solve is bitwise the single-right-hand-side
+    solve run with the same stencil variant (6 right-hand sides: batches of 4
+    and 2, guesses formed for all of them in one group)."""
+    U, op, _ = cfg0
+    A, lam, X = _dense_lowest(op, 12)
+    rng = np.random.default_rng(29)
+    Xn, _ = np.linalg.qr(X + 1e-6 * (rng.standard_normal(X.shape) + 1j * rng.standard_normal(X.shape)))
+    bank = Xn.T.reshape((12, 4, 4, 4, 4, 4, 3)).copy()
+    bs = gaussian_rhs_block((4, 4, 4, 4), [2600 + i for i in range(6)])
+    kw = dict(nev=6, m=20, max_bank=12, restart_tol=1e-6)
+    ctx4, _ = make_ctx(U, -0.2, max_batch=4, **kw)
+    ctx1, _ = make_ctx(U, -0.2, max_batch=1, stencil_variant=B.eigcg_layout_info(ctx4)["variant64"],
+                       **kw)
+    try:
+        assert B.eigcg_bank_load(ctx4, dev(bank)) == 12
+        assert B.eigcg_bank_load(ctx1, dev(bank)) == 12
+        x4 = dev(np.zeros_like(bs))
+        rc, st4 = B.eigcg_solve(ctx4, dev(bs), x4, 1e-10, B.EIGCG_MODE_INITCG)
+        assert rc == B.EIGCG_OK
+        got = host(x4)
+        assert sum(s["outer_steps"] for s in st4) >= 6  # every column restarted
+        for i in range(6):
+            x1 = dev(np.zeros_like(bs[i:i + 1]))
+            rc, st1 = B.eigcg_solve(ctx1, dev(bs[i:i + 1]), x1, 1e-10, B.EIGCG_MODE_INITCG)
+            assert rc == B.EIGCG_OK
+            assert st1[0]["iters"] == st4[i]["iters"]
+            assert st1[0]["first_leg_iters"] == st4[i]["first_leg_iters"]
+            assert np.array_equal(host(x1)[0], got[i]), i
+            assert st4[i]["true_rel_res"] <= 1e-10
+    finally:
+        B.eigcg_destroy(ctx1)
+        B.eigcg_destroy(ctx4)
+
+
 def _spectral_setup(op, nbank=12, sigma=40.0):
     """The lowest nbank eigenvectors of the 4^4 A (dense) as the bank, and the
     oracle's spectral preconditioner built from them (Ritz basis of H = X^H A X)."""
