@@ -1420,6 +1420,8 @@ struct Driver {
   Workspace& w64;
   int seg, relf;
   uint32_t rel_wait = 0;  // columns waiting for a reliable update
+  uint32_t f64_wait = 0;  // FP64 columns stopped at their restart point, waiting for the batch
+  bool wait_restarts = false;  // a fixed batch (a solve call): restarts wait for each other
   bool pending = false;
   int pslot = 0, pend = 0, pid = 0, slot = 0;
 
@@ -1566,20 +1568,35 @@ struct Driver {
              "fix p");
   }
 
-  // init-CG restart (Section 5.3) of one FP64 column: deflate the current
-  // iterate again and restart CG from it
-  void host_restart(int col) {
+  // init-CG restart (Section 5.3) of the masked FP64 columns: deflate their
+  // current iterates again (one pass over the bank for all of them; each
+  // column's arithmetic is that of its own deflation) and restart CG from them
+  void host_restart(uint32_t m) {
     Ctx& cx = c();
-    const uint32_t m1 = 1u << col;
     Workspace& w = R.w;
-    true_residual(cx, kF64, R.K, m1, w.x, w.b, w.r, w.tmp);
-    deflate_columns(cx, kF64, R.K, m1, w.x, w.r);
-    true_residual(cx, kF64, R.K, m1, w.x, w.b, w.r, w.tmp);
-    cx.check(launch_set_state(cx.d_st, R.K, m1, ColRun, ReasonNone, 1, cx.stream), "state");
-    cx.check(launch_post_residual(cx.d_st, R.K, m1, cx.stream), "post");
-    cg_start(R, m1);
-    R.outer[col]++;
-    R.stale_until[col] = R.seg_id;
+    true_residual(cx, kF64, R.K, m, w.x, w.b, w.r, w.tmp);
+    deflate_columns(cx, kF64, R.K, m, w.x, w.r);
+    true_residual(cx, kF64, R.K, m, w.x, w.b, w.r, w.tmp);
+    cx.check(launch_set_state(cx.d_st, R.K, m, ColRun, ReasonNone, 1, cx.stream), "state");
+    cx.check(launch_post_residual(cx.d_st, R.K, m, cx.stream), "post");
+    cg_start(R, m);
+    for (int j = 0; j < R.K; ++j) {
+      if (!((m >> j) & 1u)) continue;
+      R.outer[j]++;
+      R.stale_until[j] = R.seg_id;
+    }
+  }
+
+  // FP64 restarts wait for the batch: a column stopped at its restart point
+  // keeps its iterate until no other column can still reach its own, then all
+  // of them restart together.  A waiting column's restart is the one it would
+  // have had at once (its x and r do not change while it waits).
+  bool restarts_ready() const {
+    for (int j = 0; j < R.K; ++j) {
+      if (!((R.mask >> j) & 1u) || R.done[j] || ((f64_wait >> j) & 1u)) continue;
+      if (R.outer[j] == 0) return false;  // running, restart still ahead
+    }
+    return true;
   }
 
   // FP64 outer step of iterative refinement for the masked mixed-precision
@@ -1637,9 +1654,13 @@ struct Driver {
       if (S.state == ColRun) continue;
       if (S.reason == ReasonRestart) {
         if (scheme == kSchemeF64) {
-          cx.check(hipStreamSynchronize(cx.stream), "sync");
           if (R.first_leg[j] < 0) R.first_leg[j] = S.iter;
-          host_restart(j);
+          f64_wait |= 1u << j;
+          if (!wait_restarts) {  // serving slots: other requests keep arriving
+            cx.check(hipStreamSynchronize(cx.stream), "sync");
+            host_restart(f64_wait);
+            f64_wait = 0;
+          }
           continue;
         }
         if (scheme == kSchemeRefine) {
@@ -1652,6 +1673,11 @@ struct Driver {
       R.done[j] = 1;
       R.reason[j] = S.reason;
       if (R.eig) R.finalize_eig(j, S.iter);
+    }
+    if (f64_wait && restarts_ready()) {
+      cx.check(hipStreamSynchronize(cx.stream), "sync");
+      host_restart(f64_wait);
+      f64_wait = 0;
     }
     if (mref) {
       cx.check(hipStreamSynchronize(cx.stream), "sync");
@@ -2292,6 +2318,7 @@ int solve(Ctx& c, int nrhs, const void* b_aos, void* x_aos, double tol, int mode
     }
     ensure_spectral(c);  // the bank may have grown since the last group
     Driver D(c, w, w64, prec, K, eig, scheme);
+    D.wait_restarts = true;
     {  // columns with b = 0 never run
       std::vector<ColState> idle(K);
       std::memset(idle.data(), 0, sizeof(ColState) * K);
